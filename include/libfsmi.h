@@ -1,0 +1,182 @@
+/*
+ * libfsmi.h -- C-ABI of libfsmi, an MI355X (gfx950) implementation of FSMI:
+ * fast Shannon mutual information between an occupancy map and range beams
+ * (Zhang, Henderson, Tzoumas, Karaman, Sze; arXiv 1905.02238).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Array arguments are DEVICE pointers owned by the caller.  The library
+ *   never frees them and never keeps them past the call.  Scalars and the
+ *   small structs below are passed on the host.
+ * - Calls are asynchronous: they enqueue kernels on the context's stream and
+ *   return.  Results are ready after fsmi_sync() or any later operation on
+ *   that stream.
+ * - Map coordinates are in cell units.  2D cell (x, y) covers
+ *   [x, x+1) x [y, y+1); 3D voxel (x, y, z) likewise.  A map is stored x
+ *   fastest: linear index = x + X*(y + Y*z), held in int32, so a map has
+ *   fewer than 2^31 cells.
+ * - Occupancy o is P(M_i = 1) in [0, 1] (Sec. 2.1).  The inverse sensor
+ *   model uses delta_occ > 1 and delta_emp = 1/delta_occ (Sec. 3.3).
+ * - Mutual information is returned in nats (natural log).
+ * - Errors: every call returns fsmi_status.  Bad scalars, shapes and sizes are
+ *   reported at once and nothing is launched.  Bad data seen on the device
+ *   (an occupancy outside [0,1] or NaN, a run length <= 0, decreasing
+ *   boundaries, a pose outside the map) makes that result NaN and latches an
+ *   error that the next fsmi_sync() returns (FSMI_E_NUMERIC) and clears.
+ * - A context is not thread-safe; separate contexts are independent.
+ *
+ * Readings of the paper used throughout: the event "no cell is hit" carries
+ * its reading beyond the last cell, outside the integration range
+ * [0, l_{n+1}), so it contributes nothing (Alg 1 loops j from 0, but no cell
+ * centre mu_0 exists); sigma is one constant per beam (Sec. 2.1, Sec. 3.3).
+ */
+#ifndef LIBFSMI_H
+#define LIBFSMI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fsmi_ctx_s* fsmi_ctx;
+
+typedef enum {
+  FSMI_OK = 0,
+  FSMI_E_INVAL = 1,       /* bad argument (NULL pointer, sigma <= 0, ...) */
+  FSMI_E_DEVICE = 2,      /* HIP runtime error */
+  FSMI_E_NOMEM = 3,       /* device allocation failed */
+  FSMI_E_CAPACITY = 4,    /* an output buffer or a beam is larger than allowed */
+  FSMI_E_NUMERIC = 5,     /* latched device data error (see above) */
+  FSMI_E_UNSUPPORTED = 6  /* valid request this build does not implement */
+} fsmi_status;
+
+/* Variants (Table 1 of the paper). */
+enum {
+  FSMI_EXACT = 0,   /* Thm 1, Eq. fast_exact_mi: full double sum over (j, k) */
+  FSMI_APPROX = 1,  /* Eq. fsmi_approx: k restricted to |k - j| <= Delta, no renormalisation */
+  FSMI_UNIFORM = 2  /* Thm 4 / Alg 4: uniform noise of half-width H cells */
+};
+/* Weight between hit cell j and reading cell k on equal-width cells. */
+enum {
+  FSMI_KERNEL_ERF = 0,    /* Phi((d+1/2)/sigma') - Phi((d-1/2)/sigma') (Eq. G_jk) */
+  FSMI_KERNEL_DENSITY = 1 /* exp(-d^2/(2 sigma'^2))/(sqrt(2 pi) sigma') (proof of Thm 5) */
+};
+enum { FSMI_FP32 = 0, FSMI_FP64 = 1 };
+enum {
+  /* Skip (row, boundary) pairs whose FP32 weight underflows to exactly zero
+     (|l - mu| > 13.5 sigma).  A separate mode: the result equals the dense FP32
+     sum up to rounding order, and its work count is reported separately. */
+  FSMI_F_SKIP_ZERO = 1u
+};
+
+typedef struct {
+  double delta_occ;   /* > 1; the paper uses 1.5 (Sec. 5.1) */
+  int32_t variant;    /* FSMI_EXACT | FSMI_APPROX | FSMI_UNIFORM */
+  int32_t trunc_delta;/* Delta >= 0, cells (APPROX) */
+  int32_t uniform_h;  /* H >= 0, cells (UNIFORM) */
+  int32_t kernel;     /* FSMI_KERNEL_* (equal-width cells and RLE only) */
+  int32_t precision;  /* FSMI_FP32 (default) | FSMI_FP64 */
+  uint32_t flags;     /* FSMI_F_* */
+} fsmi_params;
+
+typedef struct {
+  const float* occ;   /* device, o per cell, x fastest */
+  int32_t ndim;       /* 2 or 3 */
+  int64_t dims[3];    /* X, Y, Z (Z ignored for 2D) */
+} fsmi_map;
+
+/* ---- context ---- */
+/* Opens a context on HIP device `device`.  hip_stream is the hipStream_t to
+   enqueue on (NULL: the device's default stream).  The context allocates a
+   status word, queue counters and a grow-only work area on the device. */
+fsmi_status fsmi_create(fsmi_ctx* out, int device, void* hip_stream);
+void fsmi_destroy(fsmi_ctx ctx);
+/* Changes the stream later calls enqueue on (NULL: the default stream). */
+fsmi_status fsmi_set_stream(fsmi_ctx ctx, void* hip_stream);
+/* Waits for the stream; returns the latched device error (and clears it). */
+fsmi_status fsmi_sync(fsmi_ctx ctx);
+/* Text of the last error on this context (never NULL). */
+const char* fsmi_last_error(fsmi_ctx ctx);
+const char* fsmi_status_string(fsmi_status s);
+/* Defaults: delta_occ 1.5, EXACT, Delta 3, H 0, ERF kernel, FP32, no flags. */
+void fsmi_default_params(fsmi_params* p);
+
+/* ---- a1 / a2: ray traversal ----
+   The beam's cells in ascending distance (Sec. 2.2, Sec. 3.1), per ray.
+   mode FSMI_RAY_DDA (2D map): every grid cell the ray crosses.  Face distance
+     t = (face - p)*(1/d) with two roundings and no FMA, recomputed from the
+     integer face after each step; an exact tie of axes is one diagonal step;
+     a cell is listed only if its [entry, exit) is non-empty; the last cell is
+     cut at max_range; the walk ends where the ray leaves the map.
+     Outputs per ray r: count[r] = n, cell[r*max_cells + i] (linear index),
+     entry[r*(max_cells+1) + i] = l_{i+1} for i = 0..n (l_1 = 0, l_{n+1} the end),
+     occ_out[r*max_cells + i] = o of the cell (may be NULL).  cell and entry
+     may both be NULL: then only count[] is written.
+     max_cells >= floor(sqrt(2)*max_range) + 3, else FSMI_E_CAPACITY.
+   mode FSMI_RAY_VIRTUAL (3D map): the beam projected onto equal virtual cells
+     of width w (Sec. 4): cell i = 1..floor(R/w) takes the voxel holding its
+     midpoint p + (i - 1/2) w d (per axis, no FMA); the beam ends at the first
+     midpoint outside the map.  cell/occ_out as above; entry unused (NULL).
+     max_cells >= floor(max_range/w), else FSMI_E_CAPACITY.
+   mode FSMI_RAY_RLE (3D map): as VIRTUAL, then maximal runs of bit-identical
+     o (Eq. occup_rle): count[r] = n_r, occ_out = run value, run_len = L_u.
+   origin [n_rays][ndim] must lie inside the map (else that ray reports
+   count -1 and the call latches FSMI_E_NUMERIC); dir [n_rays][ndim] FP64,
+   not both zero (directions come from host libm, so both sides agree). */
+enum { FSMI_RAY_DDA = 0, FSMI_RAY_VIRTUAL = 1, FSMI_RAY_RLE = 2 };
+fsmi_status fsmi_raycast(fsmi_ctx ctx, const fsmi_map* map, int32_t mode, int64_t n_rays,
+                         const double* origin, const double* dir, double max_range, double w,
+                         int32_t max_cells, int32_t* count, int32_t* cell, double* entry,
+                         float* occ_out, int32_t* run_len);
+
+/* ---- a3..a9, a13, a14: batches of beams in CSR form ----
+   Beam b has cells off[b] .. off[b+1]-1 of occ (float, [0,1]) and, when bound
+   is not NULL, boundaries bound[off[b] + b + i] = l_{i+1}, i = 0..n_b
+   (n_b + 1 increasing values per beam); bound == NULL means unit cells
+   l_i = i - 1.  sigma[b] > 0 is the beam's range noise in the same length
+   unit as the boundaries.  mi[b] receives I(M'; Z) (FP64) per the variant:
+   EXACT (Thm 1), APPROX with Delta (Eq. fsmi_approx), UNIFORM with H (Alg 4 on
+   cell-index windows).  Computation in FP32 with compensated sums and an
+   FP64 prefix product, or entirely in FP64 with precision = FSMI_FP64.
+   Beams of uneven length are scheduled longest-first on persistent workers:
+   a beam longer than the wave threshold is shared by a whole workgroup. */
+fsmi_status fsmi_eval_beams(fsmi_ctx ctx, const fsmi_params* params, int64_t n_beams,
+                            const int64_t* off, const float* occ, const double* bound,
+                            const float* sigma, double* mi);
+
+/* ---- a10, a11: run-length-encoded beams on equal-width virtual cells ----
+   Beam b has runs run_off[b] .. run_off[b+1]-1 with value run_occ[u] and
+   length run_len[u] >= 1 (Eq. occup_rle); sigma_prime[b] = sigma / w in
+   virtual cells.  EXACT gives FSMI-RLE (Thm 5), APPROX gives Approx-FSMI-RLE
+   (Thm 6) with the kernel truncated at |d| <= Delta; the value equals the
+   plain algorithm on the expanded beam with the chosen kernel. */
+fsmi_status fsmi_rle_eval_beams(fsmi_ctx ctx, const fsmi_params* params, int64_t n_beams,
+                                const int64_t* run_off, const float* run_occ,
+                                const int32_t* run_len, const float* sigma_prime, double* mi);
+
+/* ---- a12 + fused a1..a11: many poses x many beams ----
+   2D map: poses [n_poses][4] = {x, y, cos(yaw), sin(yaw)}; beam_dir [n_beams][2]
+   sensor-frame unit vectors.  World direction (c*bx - s*by, s*bx + c*by), each
+   product rounded on its own.  Each beam is walked as FSMI_RAY_DDA to
+   max_range and evaluated with sigma and the variant.
+   3D map: poses [n_poses][5] = {x, y, z, cos(yaw), sin(yaw)}; beam_dir
+   [n_beams][3]; world direction (c*bx - s*by, s*bx + c*by, bz).  Each beam is
+   sampled as FSMI_RAY_RLE with cell width w and evaluated by the run engine
+   with sigma' = sigma / w (EXACT: FSMI-RLE, APPROX: Approx-FSMI-RLE).
+   mi_pose[p] = sum over the pose's beams (Sec. 2.4; FP64, fixed order).
+   mi_beam [n_poses][n_beams] (FP64) may be NULL. */
+fsmi_status fsmi_eval_poses(fsmi_ctx ctx, const fsmi_params* params, const fsmi_map* map,
+                            int64_t n_poses, const double* poses, int64_t n_beams,
+                            const double* beam_dir, double sigma, double max_range, double w,
+                            double* mi_pose, double* mi_beam);
+
+/* ---- diagnostics ----
+   out[i] = the library's FP32 erfc at z[i] >= 0 (the function every Gaussian
+   weight G_{k,j} is built from), so its error can be measured against FP64. */
+fsmi_status fsmi_probe_erfc(fsmi_ctx ctx, int64_t n, const float* z, float* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LIBFSMI_H */

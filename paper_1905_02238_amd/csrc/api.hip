@@ -1,0 +1,353 @@
+// api.hip -- the C-ABI of libfsmi (include/libfsmi.h): contexts, argument
+// validation, error latching, and dispatch to the kernel launchers.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+
+#include "fsmi_dev.h"
+#include "fsmi_internal.h"
+
+namespace fsmi {
+hipError_t launch_max_len(fsmi_ctx ctx, const int64_t* off, int64_t n_beams, int* host_out);
+}
+
+using namespace fsmi;
+
+namespace {
+
+fsmi_status fail(fsmi_ctx ctx, fsmi_status s, const std::string& msg) {
+  if (ctx) ctx->last_error = msg;
+  return s;
+}
+
+fsmi_status from_hip(fsmi_ctx ctx, hipError_t e, const char* where) {
+  if (e == hipSuccess) return FSMI_OK;
+  std::string m = std::string(where) + ": " + hipGetErrorString(e);
+  if (e == hipErrorOutOfMemory) return fail(ctx, FSMI_E_NOMEM, m);
+  if (e == hipErrorInvalidValue) return fail(ctx, FSMI_E_CAPACITY, m + " (launch does not fit)");
+  return fail(ctx, FSMI_E_DEVICE, m);
+}
+
+bool check_params(fsmi_ctx ctx, const fsmi_params* p, fsmi_status* st) {
+  if (!p) {
+    *st = fail(ctx, FSMI_E_INVAL, "params is NULL");
+    return false;
+  }
+  if (!(p->delta_occ > 1.0) || !std::isfinite(p->delta_occ)) {
+    *st = fail(ctx, FSMI_E_INVAL, "delta_occ must be finite and > 1");
+    return false;
+  }
+  if (p->variant < FSMI_EXACT || p->variant > FSMI_UNIFORM) {
+    *st = fail(ctx, FSMI_E_INVAL, "unknown variant");
+    return false;
+  }
+  if (p->variant == FSMI_APPROX && p->trunc_delta < 0) {
+    *st = fail(ctx, FSMI_E_INVAL, "trunc_delta must be >= 0");
+    return false;
+  }
+  if (p->variant == FSMI_UNIFORM && p->uniform_h < 0) {
+    *st = fail(ctx, FSMI_E_INVAL, "uniform_h must be >= 0");
+    return false;
+  }
+  if (p->kernel != FSMI_KERNEL_ERF && p->kernel != FSMI_KERNEL_DENSITY) {
+    *st = fail(ctx, FSMI_E_INVAL, "unknown kernel");
+    return false;
+  }
+  if (p->precision != FSMI_FP32 && p->precision != FSMI_FP64) {
+    *st = fail(ctx, FSMI_E_INVAL, "unknown precision");
+    return false;
+  }
+  return true;
+}
+
+EvalConst to_const(const fsmi_params* p) {
+  EvalConst ec;
+  ec.variant = p->variant;
+  ec.Delta = p->trunc_delta;
+  ec.H = p->uniform_h;
+  ec.kernel = p->kernel;
+  ec.precision = p->precision;
+  ec.flags = p->flags;
+  ec.delta_occ = p->delta_occ;
+  return ec;
+}
+
+bool check_map(fsmi_ctx ctx, const fsmi_map* m, fsmi_status* st) {
+  if (!m || !m->occ) {
+    *st = fail(ctx, FSMI_E_INVAL, "map or map->occ is NULL");
+    return false;
+  }
+  if (m->ndim != 2 && m->ndim != 3) {
+    *st = fail(ctx, FSMI_E_INVAL, "map ndim must be 2 or 3");
+    return false;
+  }
+  int64_t cells = 1;
+  for (int i = 0; i < m->ndim; ++i) {
+    if (m->dims[i] <= 0) {
+      *st = fail(ctx, FSMI_E_INVAL, "map dims must be positive");
+      return false;
+    }
+    cells *= m->dims[i];
+    if (cells >= (int64_t)1 << 31) {
+      *st = fail(ctx, FSMI_E_CAPACITY, "map has 2^31 cells or more");
+      return false;
+    }
+  }
+  return true;
+}
+
+}  // namespace
+
+namespace fsmi {
+hipError_t ensure_work(fsmi_ctx ctx, size_t bytes) {
+  if (bytes <= ctx->work_bytes) return hipSuccess;
+  if (ctx->d_work) {
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return e;
+    (void)hipFree(ctx->d_work);
+    ctx->d_work = nullptr;
+    ctx->work_bytes = 0;
+  }
+  size_t want = bytes < ((size_t)1 << 20) ? ((size_t)1 << 20) : bytes + bytes / 4;
+  hipError_t e = hipMalloc(&ctx->d_work, want);
+  if (e != hipSuccess) return e;
+  ctx->work_bytes = want;
+  return hipSuccess;
+}
+}  // namespace fsmi
+
+extern "C" {
+
+const char* fsmi_status_string(fsmi_status s) {
+  switch (s) {
+    case FSMI_OK: return "ok";
+    case FSMI_E_INVAL: return "invalid argument";
+    case FSMI_E_DEVICE: return "device error";
+    case FSMI_E_NOMEM: return "out of device memory";
+    case FSMI_E_CAPACITY: return "capacity exceeded";
+    case FSMI_E_NUMERIC: return "invalid data found on the device";
+    case FSMI_E_UNSUPPORTED: return "unsupported";
+  }
+  return "unknown status";
+}
+
+void fsmi_default_params(fsmi_params* p) {
+  if (!p) return;
+  memset(p, 0, sizeof(*p));
+  p->delta_occ = 1.5;
+  p->variant = FSMI_EXACT;
+  p->trunc_delta = 3;
+  p->uniform_h = 0;
+  p->kernel = FSMI_KERNEL_ERF;
+  p->precision = FSMI_FP32;
+  p->flags = 0;
+}
+
+fsmi_status fsmi_create(fsmi_ctx* out, int device, void* hip_stream) {
+  if (!out) return FSMI_E_INVAL;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return FSMI_E_DEVICE;
+  if (device < 0 || device >= ndev) return FSMI_E_INVAL;
+  fsmi_ctx c = new (std::nothrow) fsmi_ctx_s();
+  if (!c) return FSMI_E_NOMEM;
+  c->device = device;
+  if (hipSetDevice(device) != hipSuccess) {
+    delete c;
+    return FSMI_E_DEVICE;
+  }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+    c->num_cu = prop.multiProcessorCount;
+  c->stream = (hipStream_t)hip_stream;   // NULL: the device's default stream
+  if (hipMalloc(&c->d_status, 256) != hipSuccess || hipMalloc(&c->d_counters, 64 * 4) != hipSuccess) {
+    if (c->d_status) (void)hipFree(c->d_status);
+      delete c;
+    return FSMI_E_NOMEM;
+  }
+  (void)hipMemset(c->d_status, 0, 256);
+  (void)hipMemset(c->d_counters, 0, 64 * 4);
+  (void)hipDeviceSynchronize();
+  *out = c;
+  return FSMI_OK;
+}
+
+void fsmi_destroy(fsmi_ctx ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->d_work) (void)hipFree(ctx->d_work);
+  if (ctx->d_status) (void)hipFree(ctx->d_status);
+  if (ctx->d_counters) (void)hipFree(ctx->d_counters);
+  delete ctx;
+}
+
+fsmi_status fsmi_set_stream(fsmi_ctx ctx, void* hip_stream) {
+  if (!ctx) return FSMI_E_INVAL;
+  ctx->stream = (hipStream_t)hip_stream;   // NULL: the device's default stream
+  return FSMI_OK;
+}
+
+fsmi_status fsmi_sync(fsmi_ctx ctx) {
+  if (!ctx) return FSMI_E_INVAL;
+  (void)hipSetDevice(ctx->device);
+  hipError_t e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return from_hip(ctx, e, "fsmi_sync");
+  uint32_t st = 0;
+  e = hipMemcpy(&st, ctx->d_status, 4, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return from_hip(ctx, e, "fsmi_sync status read");
+  if (st) {
+    uint32_t zero = 0;
+    (void)hipMemcpy(ctx->d_status, &zero, 4, hipMemcpyHostToDevice);
+    std::string m = "device data error:";
+    if (st & kErrOcc) m += " occupancy outside [0,1] or NaN, or bad sigma/boundaries;";
+    if (st & kErrLen) m += " bad beam/run length;";
+    if (st & kErrPose) m += " pose or origin outside the map;";
+    if (st & kErrCap) m += " beam longer than the launch capacity;";
+    if (st & kErrBound) m += " decreasing boundaries;";
+    return fail(ctx, (st & kErrCap) ? FSMI_E_CAPACITY : FSMI_E_NUMERIC, m);
+  }
+  return FSMI_OK;
+}
+
+const char* fsmi_last_error(fsmi_ctx ctx) {
+  if (!ctx) return "no context";
+  return ctx->last_error.c_str();
+}
+
+fsmi_status fsmi_raycast(fsmi_ctx ctx, const fsmi_map* map, int32_t mode, int64_t n_rays,
+                         const double* origin, const double* dir, double max_range, double w,
+                         int32_t max_cells, int32_t* count, int32_t* cell, double* entry,
+                         float* occ_out, int32_t* run_len) {
+  if (!ctx) return FSMI_E_INVAL;
+  fsmi_status st;
+  if (!check_map(ctx, map, &st)) return st;
+  if (n_rays < 0) return fail(ctx, FSMI_E_INVAL, "n_rays < 0");
+  if (n_rays == 0) return FSMI_OK;
+  if (!origin || !dir || !count) return fail(ctx, FSMI_E_INVAL, "origin, dir and count are required");
+  if (!(max_range > 0.0) || !std::isfinite(max_range))
+    return fail(ctx, FSMI_E_INVAL, "max_range must be finite and > 0");
+  (void)hipSetDevice(ctx->device);
+  if (mode == FSMI_RAY_DDA) {
+    if (map->ndim != 2) return fail(ctx, FSMI_E_INVAL, "FSMI_RAY_DDA needs a 2D map");
+    if ((cell == nullptr) != (entry == nullptr))
+      return fail(ctx, FSMI_E_INVAL, "cell and entry are both given or both NULL (count only)");
+    const double bound = floor(1.4142135623730951 * max_range) + 3;
+    if ((double)max_cells < bound)
+      return fail(ctx, FSMI_E_CAPACITY, "max_cells < floor(sqrt(2) * max_range) + 3");
+    if (max_range > 8000.0) return fail(ctx, FSMI_E_CAPACITY, "max_range above 8000 cells");
+    return from_hip(ctx,
+                    launch_raycast2d(ctx, map->occ, map->dims[0], map->dims[1], n_rays, origin, dir,
+                                     max_range, max_cells, count, cell, entry, occ_out),
+                    "raycast2d");
+  }
+  if (mode == FSMI_RAY_VIRTUAL || mode == FSMI_RAY_RLE) {
+    if (map->ndim != 3) return fail(ctx, FSMI_E_INVAL, "virtual cells need a 3D map");
+    if (!(w > 0.0) || !std::isfinite(w)) return fail(ctx, FSMI_E_INVAL, "w must be finite and > 0");
+    if ((double)max_cells < floor(max_range / w))
+      return fail(ctx, FSMI_E_CAPACITY, "max_cells < floor(max_range / w)");
+    if (max_cells > 7000) return fail(ctx, FSMI_E_CAPACITY, "more than 7000 virtual cells per ray");
+    if (mode == FSMI_RAY_RLE && !run_len) return fail(ctx, FSMI_E_INVAL, "run_len is required");
+    return from_hip(ctx,
+                    launch_virtual3d(ctx, map->occ, map->dims[0], map->dims[1], map->dims[2], n_rays,
+                                     origin, dir, max_range, w, max_cells, mode == FSMI_RAY_RLE,
+                                     count, cell, occ_out, run_len),
+                    "virtual3d");
+  }
+  return fail(ctx, FSMI_E_INVAL, "unknown ray mode");
+}
+
+fsmi_status fsmi_eval_beams(fsmi_ctx ctx, const fsmi_params* params, int64_t n_beams,
+                            const int64_t* off, const float* occ, const double* bound,
+                            const float* sigma, double* mi) {
+  if (!ctx) return FSMI_E_INVAL;
+  fsmi_status st;
+  if (!check_params(ctx, params, &st)) return st;
+  if (n_beams < 0) return fail(ctx, FSMI_E_INVAL, "n_beams < 0");
+  if (n_beams == 0) return FSMI_OK;
+  if (n_beams >= ((int64_t)1 << 31)) return fail(ctx, FSMI_E_CAPACITY, "n_beams >= 2^31");
+  if (!off || !occ || !sigma || !mi) return fail(ctx, FSMI_E_INVAL, "off, occ, sigma, mi are required");
+  (void)hipSetDevice(ctx->device);
+  int max_len = 0;
+  hipError_t e = launch_max_len(ctx, off, n_beams, &max_len);
+  if (e != hipSuccess) return from_hip(ctx, e, "eval_beams max length");
+  const int bpc = params->precision == FSMI_FP64 ? 28 : 20;
+  if ((size_t)max_len * bpc + 16 > 150 * 1024)
+    return fail(ctx, FSMI_E_CAPACITY, "a beam is longer than one workgroup's LDS holds");
+  return from_hip(ctx,
+                  launch_eval_beams(ctx, to_const(params), n_beams, off, occ, bound, sigma, mi, max_len),
+                  "eval_beams");
+}
+
+fsmi_status fsmi_rle_eval_beams(fsmi_ctx ctx, const fsmi_params* params, int64_t n_beams,
+                                const int64_t* run_off, const float* run_occ,
+                                const int32_t* run_len, const float* sigma_prime, double* mi) {
+  if (!ctx) return FSMI_E_INVAL;
+  fsmi_status st;
+  if (!check_params(ctx, params, &st)) return st;
+  if (params->variant == FSMI_UNIFORM)
+    return fail(ctx, FSMI_E_UNSUPPORTED, "Uniform-FSMI-RLE is not built");
+  if (n_beams < 0) return fail(ctx, FSMI_E_INVAL, "n_beams < 0");
+  if (n_beams == 0) return FSMI_OK;
+  if (!run_off || !run_occ || !run_len || !sigma_prime || !mi)
+    return fail(ctx, FSMI_E_INVAL, "run_off, run_occ, run_len, sigma_prime, mi are required");
+  (void)hipSetDevice(ctx->device);
+  return from_hip(ctx,
+                  launch_rle_eval_beams(ctx, to_const(params), n_beams, run_off, run_occ, run_len,
+                                        sigma_prime, mi, 0),
+                  "rle_eval_beams");
+}
+
+fsmi_status fsmi_eval_poses(fsmi_ctx ctx, const fsmi_params* params, const fsmi_map* map,
+                            int64_t n_poses, const double* poses, int64_t n_beams,
+                            const double* beam_dir, double sigma, double max_range, double w,
+                            double* mi_pose, double* mi_beam) {
+  if (!ctx) return FSMI_E_INVAL;
+  fsmi_status st;
+  if (!check_params(ctx, params, &st)) return st;
+  if (!check_map(ctx, map, &st)) return st;
+  if (n_poses < 0 || n_beams < 0) return fail(ctx, FSMI_E_INVAL, "negative count");
+  if (n_poses == 0 || n_beams == 0) {
+    if (n_poses > 0 && mi_pose) {
+      (void)hipSetDevice(ctx->device);
+      return from_hip(ctx, hipMemsetAsync(mi_pose, 0, (size_t)n_poses * 8, ctx->stream), "zero poses");
+    }
+    return FSMI_OK;
+  }
+  if (!poses || !beam_dir || !mi_pose) return fail(ctx, FSMI_E_INVAL, "poses, beam_dir, mi_pose are required");
+  if (!(sigma > 0.0) || !std::isfinite(sigma)) return fail(ctx, FSMI_E_INVAL, "sigma must be finite and > 0");
+  if (!(max_range > 0.0) || !std::isfinite(max_range))
+    return fail(ctx, FSMI_E_INVAL, "max_range must be finite and > 0");
+  if (n_poses > ((int64_t)1 << 40) / std::max<int64_t>(n_beams, 1))
+    return fail(ctx, FSMI_E_CAPACITY, "too many items");
+  (void)hipSetDevice(ctx->device);
+  if (map->ndim == 2) {
+    if (max_range > 4000.0) return fail(ctx, FSMI_E_CAPACITY, "max_range above 4000 cells");
+    return from_hip(ctx,
+                    launch_eval_poses_2d(ctx, to_const(params), map->occ, map->dims[0], map->dims[1],
+                                         n_poses, poses, n_beams, beam_dir, sigma, max_range,
+                                         mi_pose, mi_beam),
+                    "eval_poses_2d");
+  }
+  if (params->variant == FSMI_UNIFORM)
+    return fail(ctx, FSMI_E_UNSUPPORTED, "Uniform-FSMI-RLE is not built");
+  if (!(w > 0.0) || !std::isfinite(w)) return fail(ctx, FSMI_E_INVAL, "w must be finite and > 0");
+  if (floor(max_range / w) > 4000.0) return fail(ctx, FSMI_E_CAPACITY, "more than 4000 virtual cells per beam");
+  return from_hip(ctx,
+                  launch_eval_poses_3d(ctx, to_const(params), map->occ, map->dims[0], map->dims[1],
+                                       map->dims[2], n_poses, poses, n_beams, beam_dir, sigma,
+                                       max_range, w, mi_pose, mi_beam),
+                  "eval_poses_3d");
+}
+
+fsmi_status fsmi_probe_erfc(fsmi_ctx ctx, int64_t n, const float* z, float* out) {
+  if (!ctx) return FSMI_E_INVAL;
+  if (n < 0 || (n > 0 && (!z || !out))) return fail(ctx, FSMI_E_INVAL, "bad probe arguments");
+  (void)hipSetDevice(ctx->device);
+  return from_hip(ctx, launch_erfc_probe(ctx, n, z, out), "probe_erfc");
+}
+
+}  // extern "C"

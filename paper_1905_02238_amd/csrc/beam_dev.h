@@ -1,0 +1,308 @@
+// beam_dev.h -- the per-beam FSMI evaluation run by a group of lanes (one wave,
+// or a whole workgroup), on data staged in LDS.
+//
+// Steps (Sec. 3): per-cell f (Sec. 2.2) -> P(e_j) by a prefix product (Alg 2)
+// -> C_k by a prefix sum (Alg 3) -> the double sum of Thm 1 with the Gaussian
+// weights G_{k,j} (Eq. G_jk), its truncated form (Eq. fsmi_approx), or the
+// uniform-noise form (Thm 4 / Alg 4).
+//
+// Numerics (FP32 mode): the prefix product of (1 - o) and the C_k prefix are
+// scanned in FP64; the O(n^2) loop is FP32 with one erfc per (row j,
+// boundary), evaluated on the tail side of mu_j so that no digits cancel, and
+// a Kahan-compensated sum over blocks of four terms; each row's P_j S_j is
+// accumulated in FP64 and the group total is a fixed-order tree.
+#pragma once
+#include <math.h>
+
+#include "fsmi_dev.h"
+#include "fsmi_internal.h"
+
+namespace fsmi {
+
+template <int NW, bool BLOCK>
+struct Grp {
+  static constexpr int size = BLOCK ? kWave * NW : kWave;
+  FSMI_DEV static void sync() {
+    if constexpr (BLOCK) __syncthreads();
+    else wave_sync();
+  }
+};
+
+// Exclusive scan across the group in thread order, carried across chunks.
+template <int NW, bool BLOCK, typename Op>
+FSMI_DEV double group_scan_excl(double v, double& carry, double* scratch, int tid) {
+  double inc = wave_scan_incl<Op>(v);
+  double exw = wave_shift_up<Op>(inc);
+  double wtot = wave_last(inc);
+  if constexpr (BLOCK) {
+    const int w = tid >> 6;
+    if ((tid & 63) == 0) scratch[w] = wtot;
+    __syncthreads();
+    double pre = Op::template ident<double>(), tot = Op::template ident<double>();
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+      double x = scratch[i];
+      if (i < w) pre = Op::apply(pre, x);
+      tot = Op::apply(tot, x);
+    }
+    __syncthreads();
+    double r = Op::apply(Op::apply(carry, pre), exw);
+    carry = Op::apply(carry, tot);
+    return r;
+  } else {
+    double r = Op::apply(carry, exw);
+    carry = Op::apply(carry, wtot);
+    return r;
+  }
+}
+
+template <int NW, bool BLOCK>
+FSMI_DEV double group_sum(double v, double* scratch, int tid) {
+  double s = wave_sum(v);
+  if constexpr (BLOCK) {
+    const int w = tid >> 6;
+    if ((tid & 63) == 0) scratch[w] = s;
+    __syncthreads();
+    double t = 0.0;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) t += scratch[i];
+    __syncthreads();
+    return t;
+  }
+  return s;
+}
+
+template <int NW, bool BLOCK>
+FSMI_DEV bool group_any(bool b, int* flag, int tid) {
+  bool w = __any(b);
+  if constexpr (BLOCK) {
+    if (tid == 0) *flag = 0;
+    __syncthreads();
+    if (w && (tid & 63) == 0) *flag = 1;
+    __syncthreads();
+    const bool r = __builtin_amdgcn_readfirstlane(*flag) != 0;
+    __syncthreads();
+    return r;
+  }
+  return w;
+}
+
+template <typename T> FSMI_DEV T tabs(T x) { return x < T(0) ? -x : x; }
+FSMI_DEV int clampi(int x, int lo, int hi) { return x < lo ? lo : (x > hi ? hi : x); }
+
+template <typename T> FSMI_DEV T erf_t(T x);
+template <> FSMI_DEV float erf_t<float>(float x) { return erff(x); }
+template <> FSMI_DEV double erf_t<double>(double x) { return erf(x); }
+
+template <typename T> struct Acc;
+template <> struct Acc<float> {
+  Kahan k;
+  FSMI_DEV void add(float x) { k.add(x); }
+  FSMI_DEV double value() const { return (double)k.s - (double)k.c; }
+};
+template <> struct Acc<double> {
+  double s = 0.0, c = 0.0;
+  FSMI_DEV void add(double x) {
+    double y = x - c, t = s + y;
+    c = (t - s) - y;
+    s = t;
+  }
+  FSMI_DEV double value() const { return s - c; }
+};
+
+// erfc of a boundary at l, on the tail side of mu (c = 1/(sigma sqrt 2)).
+template <typename T>
+FSMI_DEV T tail_E(double l, double mu, double c) {
+  return erfc_pos((T)(tabs(l - mu) * c));
+}
+
+// ---------------------------------------------------------------------------
+// Row sums S_j = sum_k C_k G_{k,j} on explicit boundaries sL[0..n].
+// G_{k,j} = (1/2)|E(l_{k+1}) - E(l_k)| for k != j (both boundaries on one side
+// of mu_j), G_{j,j} = (1/2)(erf((l_{j+1}-mu)c) + erf((mu-l_j)c)).
+// ---------------------------------------------------------------------------
+template <typename T>
+FSMI_DEV double diag_fix(Acc<T>& acc, const double* sL, const T* sC, int j, double mu, double c) {
+  // replace the k = j term the loop took by the exact diagonal weight
+  T Ej = tail_E<T>(sL[j - 1], mu, c);
+  T Ej1 = tail_E<T>(sL[j], mu, c);
+  T Cj = sC[j - 1];
+  acc.add(-(Cj * tabs(Ej1 - Ej)));
+  T g2 = erf_t<T>((T)((sL[j] - mu) * c)) + erf_t<T>((T)((mu - sL[j - 1]) * c));
+  acc.add(Cj * g2);
+  return 0.5 * acc.value();
+}
+
+template <typename T>
+FSMI_DEV double row_exact_bound(const double* sL, const T* sC, int n, int j, double c) {
+  const double mu = 0.5 * (sL[j - 1] + sL[j]);
+  Acc<T> acc;
+  T Eprev = tail_E<T>(sL[0], mu, c);
+  int b = 1;
+  for (; b + 3 <= n; b += 4) {
+    T E0 = tail_E<T>(sL[b], mu, c);
+    T E1 = tail_E<T>(sL[b + 1], mu, c);
+    T E2 = tail_E<T>(sL[b + 2], mu, c);
+    T E3 = tail_E<T>(sL[b + 3], mu, c);
+    T p = sC[b - 1] * tabs(E0 - Eprev);
+    p = fma(sC[b], tabs(E1 - E0), p);
+    p = fma(sC[b + 1], tabs(E2 - E1), p);
+    p = fma(sC[b + 2], tabs(E3 - E2), p);
+    acc.add(p);
+    Eprev = E3;
+  }
+  for (; b <= n; ++b) {
+    T E = tail_E<T>(sL[b], mu, c);
+    acc.add(sC[b - 1] * tabs(E - Eprev));
+    Eprev = E;
+  }
+  return diag_fix<T>(acc, sL, sC, j, mu, c);
+}
+
+template <typename T>
+FSMI_DEV double row_approx_bound(const double* sL, const T* sC, int n, int j, double c, int D) {
+  const double mu = 0.5 * (sL[j - 1] + sL[j]);
+  Acc<T> acc;
+  // cells k = j-D..j+D; cell k spans [sL[k-1], sL[k]]; indices clamped to the
+  // beam so out-of-range cells see two equal boundaries and weigh zero
+  T Eprev = tail_E<T>(sL[clampi(j - D - 1, 0, n)], mu, c);
+  for (int i = 0; i <= 2 * D; ++i) {
+    const int k = j - D + i;
+    T E = tail_E<T>(sL[clampi(k, 0, n)], mu, c);
+    acc.add(sC[clampi(k - 1, 0, n - 1)] * tabs(E - Eprev));
+    Eprev = E;
+  }
+  return diag_fix<T>(acc, sL, sC, j, mu, c);
+}
+
+// Unit cells: G_{k,j} = g(|k-j|), g from the per-beam table sG[0..n-1].
+template <typename T>
+FSMI_DEV double row_exact_unit(const T* sG, const T* sC, int n, int j) {
+  Acc<T> acc;
+  int k = 1;
+  for (; k + 3 <= n; k += 4) {
+    T p = sC[k - 1] * sG[abs(k - j)];
+    p = fma(sC[k], sG[abs(k + 1 - j)], p);
+    p = fma(sC[k + 1], sG[abs(k + 2 - j)], p);
+    p = fma(sC[k + 2], sG[abs(k + 3 - j)], p);
+    acc.add(p);
+  }
+  for (; k <= n; ++k) acc.add(sC[k - 1] * sG[abs(k - j)]);
+  return acc.value();
+}
+
+template <typename T>
+FSMI_DEV double row_approx_unit(const T* sG, const T* sC, int n, int j, int D) {
+  Acc<T> acc;
+  const int k0 = max(1, j - D), k1 = min(n, j + D);
+  for (int k = k0; k <= k1; ++k) acc.add(sC[k - 1] * sG[abs(k - j)]);
+  return acc.value();
+}
+
+// LDS the core needs besides o: A = FP64 [cap+1], C and P = T [cap] each.
+template <typename T>
+__host__ __device__ constexpr int core_bytes_per_cell() { return 8 + 2 * (int)sizeof(T); }
+
+struct CoreLds {
+  double* A;   // boundaries l_1..l_{n+1} on entry (explicit bounds); D prefix; kernel table
+  void* C;     // C_k
+  void* P;     // P(e_j)
+};
+
+// The beam's mutual information, valid in every lane of the group.
+// so[0..n): occupancies; with explicit bounds A[0..n] holds l_1..l_{n+1}.
+// *bad is set (group-uniform) when an input is invalid; the result is then NaN.
+template <int NW, bool BLOCK, typename T>
+FSMI_DEV double beam_core(const EvalConst& ec, int n, const float* so, bool has_bound, double sigma,
+                          const CoreLds& L, double* scratch, int* flag, int tid, bool bad_in,
+                          bool* bad_out) {
+  constexpr int G = Grp<NW, BLOCK>::size;
+  double* sA = L.A;
+  T* sC = reinterpret_cast<T*>(L.C);
+  T* sP = reinterpret_cast<T*>(L.P);
+  const T docc = (T)ec.delta_occ, demp = (T)(1.0 / ec.delta_occ);
+  const T ldo = (T)log(ec.delta_occ), lde = -(T)log(ec.delta_occ);
+  const bool uni = ec.variant == FSMI_UNIFORM;
+  bool bad = bad_in;
+  if (!(sigma > 0.0) && !uni) bad = true;
+  if (has_bound && !uni) {
+    for (int i = tid + 1; i <= n; i += G)
+      if (!(sA[i] >= sA[i - 1])) bad = true;
+  }
+  // ---- per-cell f, Alg 2 and Alg 3 (FP64 scans) ----
+  double carryC = 0.0, carryE = 1.0, carryD = 0.0;
+  for (int base = 0; base < n; base += G) {
+    const int i = base + tid;
+    const bool v = i < n;
+    const float of = v ? so[i] : 0.0f;
+    if (v && !(of >= 0.0f && of <= 1.0f)) bad = true;
+    const T o = (T)of;
+    const T fo = v ? f_cell<T>(docc, ldo, o) : T(0);
+    const T fe = v ? f_cell<T>(demp, lde, o) : T(0);
+    const double q = group_scan_excl<NW, BLOCK, OpAdd>((double)fe, carryC, scratch, tid);
+    const double E = group_scan_excl<NW, BLOCK, OpMul>(v ? 1.0 - (double)of : 1.0, carryE, scratch, tid);
+    const double Ck = q + (double)fo;
+    if (v) {
+      sC[i] = (T)Ck;
+      sP[i] = (T)(E * (double)of);
+    }
+    if (uni) {  // D_k = sum_{i<=k} C_i in FP64 at A[k], A[0] = 0
+      const double Dk = group_scan_excl<NW, BLOCK, OpAdd>(v ? Ck : 0.0, carryD, scratch, tid) + (v ? Ck : 0.0);
+      if (v) sA[i + 1] = Dk;
+      if (tid == 0 && base == 0) sA[0] = 0.0;
+    }
+  }
+  const double c = 1.0 / (sigma * 1.4142135623730951);
+  if (!uni && !has_bound) {
+    // g(d) = Phi((d+1/2)/sigma) - Phi((d-1/2)/sigma), d = 0..n-1
+    T* sG = reinterpret_cast<T*>(sA);
+    for (int d = tid; d < n; d += G) {
+      T g;
+      if (ec.kernel == FSMI_KERNEL_DENSITY) {
+        // exp(-d^2 / (2 sigma^2)) / (sqrt(2 pi) sigma) = exp(-(d c)^2) c / sqrt(pi)
+        const double z = d * c;
+        g = (T)(exp(-z * z) * c * 0.56418958354775628695);
+      } else if (d == 0) {
+        g = erf_t<T>((T)(0.5 * c));
+      } else {
+        g = T(0.5) * (erfc_pos((T)((d - 0.5) * c)) - erfc_pos((T)((d + 0.5) * c)));
+      }
+      sG[d] = g;
+    }
+  }
+  const bool any_bad = group_any<NW, BLOCK>(bad, flag, tid);
+  *bad_out = any_bad;
+  Grp<NW, BLOCK>::sync();
+
+  // ---- the double sum ----
+  double tot = 0.0;
+  if (!any_bad) {
+    if (uni) {
+      const double inv = 1.0 / (2.0 * ec.H + 1.0);
+      for (int j = tid + 1; j <= n; j += G) {
+        const int hi = min(n, j + ec.H), lo = max(0, j - ec.H - 1);
+        tot += (double)sP[j - 1] * ((sA[hi] - sA[lo]) * inv);
+      }
+    } else if (has_bound) {
+      if (ec.variant == FSMI_EXACT) {
+        for (int j = tid + 1; j <= n; j += G) tot += (double)sP[j - 1] * row_exact_bound<T>(sA, sC, n, j, c);
+      } else {
+        for (int j = tid + 1; j <= n; j += G)
+          tot += (double)sP[j - 1] * row_approx_bound<T>(sA, sC, n, j, c, ec.Delta);
+      }
+    } else {
+      const T* sG = reinterpret_cast<const T*>(sA);
+      if (ec.variant == FSMI_EXACT) {
+        for (int j = tid + 1; j <= n; j += G) tot += (double)sP[j - 1] * row_exact_unit<T>(sG, sC, n, j);
+      } else {
+        for (int j = tid + 1; j <= n; j += G)
+          tot += (double)sP[j - 1] * row_approx_unit<T>(sG, sC, n, j, ec.Delta);
+      }
+    }
+  }
+  const double s = group_sum<NW, BLOCK>(tot, scratch, tid);
+  Grp<NW, BLOCK>::sync();
+  return any_bad ? __builtin_nan("") : s;
+}
+
+}  // namespace fsmi

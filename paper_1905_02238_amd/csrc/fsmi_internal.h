@@ -1,0 +1,71 @@
+// fsmi_internal.h -- host-side declarations shared by the C-ABI layer and the
+// kernel launchers of libfsmi.  Not installed; callers use include/libfsmi.h.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "libfsmi.h"
+
+struct fsmi_ctx_s {
+  int device = 0;
+  hipStream_t stream = nullptr;   // caller's stream; nullptr = the default stream
+  uint32_t* d_status = nullptr;   // latched device error bits
+  int32_t* d_counters = nullptr;  // work-queue heads, 64 entries
+  void* d_work = nullptr;         // grow-only scratch for schedules / partial results
+  size_t work_bytes = 0;
+  int num_cu = 256;
+  std::string last_error;
+};
+
+namespace fsmi {
+
+// Scalars of one evaluation, shared by every kernel family.
+struct EvalConst {
+  int variant;       // FSMI_EXACT / FSMI_APPROX / FSMI_UNIFORM
+  int Delta;         // truncation width (cells), APPROX
+  int H;             // uniform half-width (cells), UNIFORM
+  int kernel;        // FSMI_KERNEL_ERF / FSMI_KERNEL_DENSITY (equal-width engines)
+  int precision;     // FSMI_FP32 / FSMI_FP64
+  uint32_t flags;
+  double delta_occ;  // > 1
+};
+
+// Grow-only device scratch owned by the context.
+hipError_t ensure_work(fsmi_ctx ctx, size_t bytes);
+
+// ---- launchers (k_beam.hip) ----
+hipError_t launch_eval_beams(fsmi_ctx ctx, const EvalConst& ec, int64_t n_beams, const int64_t* off,
+                             const float* occ, const double* bound, const float* sigma,
+                             double* mi, int max_len);
+
+// ---- launchers (k_ray.hip) ----
+hipError_t launch_raycast2d(fsmi_ctx ctx, const float* map, int64_t X, int64_t Y, int64_t n_rays,
+                            const double* origin, const double* dir, double R, int max_cells,
+                            int32_t* count, int32_t* cell, double* entry, float* occ_out);
+hipError_t launch_virtual3d(fsmi_ctx ctx, const float* map, int64_t X, int64_t Y, int64_t Z,
+                            int64_t n_rays, const double* origin, const double* dir, double R,
+                            double w, int max_cells, int rle, int32_t* count, int32_t* cell,
+                            float* occ_out, int32_t* run_len);
+
+// ---- launchers (k_pose.hip) ----
+hipError_t launch_eval_poses_2d(fsmi_ctx ctx, const EvalConst& ec, const float* map, int64_t X,
+                                int64_t Y, int64_t n_poses, const double* poses, int64_t n_beams,
+                                const double* beam_dir, double sigma, double R, double* mi_pose,
+                                double* mi_beam);
+
+// ---- launchers (k_rle.hip) ----
+hipError_t launch_rle_eval_beams(fsmi_ctx ctx, const EvalConst& ec, int64_t n_beams,
+                                 const int64_t* run_off, const float* run_occ,
+                                 const int32_t* run_len, const float* sigma_p, double* mi,
+                                 int max_cells);
+hipError_t launch_eval_poses_3d(fsmi_ctx ctx, const EvalConst& ec, const float* map, int64_t X,
+                                int64_t Y, int64_t Z, int64_t n_poses, const double* poses,
+                                int64_t n_beams, const double* beam_dir, double sigma, double R,
+                                double w, double* mi_pose, double* mi_beam);
+
+// ---- diagnostics (k_beam.hip) ----
+hipError_t launch_erfc_probe(fsmi_ctx ctx, int64_t n, const float* z, float* out);
+
+}  // namespace fsmi

@@ -1,0 +1,286 @@
+// k_beam.hip -- FSMI on batches of beams in CSR form (fsmi_eval_beams).
+//
+// Schedule: one persistent launch.  A device pass sorts beam ids into
+// descending length bins, with every beam above the wave threshold ahead of
+// every beam at or below it; beams above the threshold are taken by a whole
+// workgroup (rows j split over all its lanes: tile-per-beam), the rest by
+// single waves (wave-per-beam).  Both pop items from atomic queue heads, so
+// every wave exits once the queues are drained.
+#include <math.h>
+
+#include <algorithm>
+
+#include "beam_dev.h"
+#include "fsmi_internal.h"
+
+namespace fsmi {
+
+namespace {
+
+constexpr int kNW = 4;          // waves per workgroup
+constexpr int kHalf = 16;       // length bins per class (octaves, descending)
+constexpr int kBins = 2 * kHalf;
+constexpr int kMaxGrid = 4096;  // persistent workgroups
+
+struct BeamArgs {
+  EvalConst ec;
+  int64_t n_beams;
+  const int64_t* off;
+  const float* occ;
+  const double* bound;
+  const float* sigma;
+  double* mi;
+  const int32_t* order;   // beam ids, longest first
+  int32_t* counters;      // [0] block-queue head, [1] wave-queue head, [2] n_long
+  uint32_t* status;
+  int cap_block;          // cells of a workgroup item
+  int cap_wave;           // cells of a wave item
+};
+
+template <typename T>
+constexpr int bytes_per_cell() { return core_bytes_per_cell<T>() + 4; }   // + o
+
+template <typename T>
+FSMI_DEV CoreLds carve(char* p, int cap, float** so) {
+  CoreLds L;
+  L.A = reinterpret_cast<double*>(p);
+  L.C = p + 8 * (size_t)(cap + 1);
+  L.P = reinterpret_cast<char*>(L.C) + sizeof(T) * (size_t)cap;
+  *so = reinterpret_cast<float*>(reinterpret_cast<char*>(L.P) + sizeof(T) * (size_t)cap);
+  return L;
+}
+
+template <bool BLOCK, typename T>
+FSMI_DEV void process_beam(const BeamArgs& a, int b, char* lds, int cap, double* scratch,
+                           int* flag, int tid) {
+  constexpr int G = Grp<kNW, BLOCK>::size;
+  const int64_t o0 = a.off[b];
+  // wave-uniform length, clamped to [-1, 2^31): -1 flags a negative length
+  const int n = __builtin_amdgcn_readfirstlane((int)min<int64_t>(
+      max<int64_t>(a.off[b + 1] - o0, (int64_t)-1), (int64_t)0x7fffffff));
+  double v = 0.0;
+  uint32_t err = 0;
+  if (n > 0 && n <= cap) {
+    float* so;
+    const CoreLds L = carve<T>(lds, cap, &so);
+    const bool has_bound = a.bound != nullptr && a.ec.variant != FSMI_UNIFORM;
+    for (int i = tid; i < n; i += G) so[i] = a.occ[o0 + i];
+    if (has_bound) {
+      const double* bp = a.bound + o0 + b;
+      for (int i = tid; i <= n; i += G) L.A[i] = bp[i];
+    }
+    Grp<kNW, BLOCK>::sync();
+    bool bad;
+    v = beam_core<kNW, BLOCK, T>(a.ec, n, so, has_bound, (double)a.sigma[b], L, scratch, flag, tid,
+                                 false, &bad);
+    if (bad) err = kErrOcc;
+  } else if (n != 0) {
+    v = __builtin_nan("");
+    err = n < 0 ? kErrLen : kErrCap;
+  }
+  if (tid == 0) {
+    a.mi[b] = v;
+    if (err) latch(a.status, err);
+  }
+}
+
+// Tile-per-beam: the beams above the wave threshold, one workgroup per beam.
+// Every value that steers a branch around a barrier is made wave-uniform
+// (readfirstlane), so those branches are scalar and all waves of the
+// workgroup meet the same barriers.
+template <typename T>
+__global__ __launch_bounds__(kWave* kNW) void k_eval_long(BeamArgs a) {
+  extern __shared__ __align__(16) char lds[];
+  __shared__ double scratch[kNW];
+  __shared__ int s_item, s_flag;
+  const int tid = threadIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int n_long = __builtin_amdgcn_readfirstlane(a.counters[2]);
+  for (;;) {
+    if (wave == 0) s_item = wave_pop(&a.counters[0]);   // every lane of wave 0 writes the same value
+    __syncthreads();
+    const int it = __builtin_amdgcn_readfirstlane(s_item);
+    __syncthreads();
+    if (it >= n_long) break;
+    const int b = __builtin_amdgcn_readfirstlane(a.order[it]);
+    process_beam<true, T>(a, b, lds, a.cap_block, scratch, &s_flag, tid);
+    __syncthreads();
+  }
+}
+
+// Wave-per-beam: the remaining beams, each wave on its own LDS slice; no
+// workgroup barriers.
+template <typename T>
+__global__ __launch_bounds__(kWave* kNW) void k_eval_short(BeamArgs a) {
+  extern __shared__ __align__(16) char lds[];
+  const int tid = threadIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int lane = tid & 63;
+  const int n_long = __builtin_amdgcn_readfirstlane(a.counters[2]);
+  const int n_short = (int)a.n_beams - n_long;
+  char* my = lds + (size_t)wave * ((size_t)a.cap_wave * bytes_per_cell<T>() + 16);
+  for (int it = wave_pop(&a.counters[1]); it < n_short; it = wave_pop(&a.counters[1])) {
+    const int b = __builtin_amdgcn_readfirstlane(a.order[n_long + it]);
+    process_beam<false, T>(a, b, my, a.cap_wave, nullptr, nullptr, lane);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Schedule on the device: a length histogram over bins ordered long-to-short
+// (class "above the wave threshold" first, octaves descending within a class),
+// exclusive bin offsets, and a scatter of beam ids.  counters[2] receives the
+// number of beams above the threshold.
+// ---------------------------------------------------------------------------
+FSMI_DEV int len_bin(int64_t n, int wave_max) {
+  const int cls = n > wave_max ? 0 : 1;
+  int oct = n <= 1 ? 0 : 63 - __builtin_clzll((unsigned long long)n);   // floor(log2 n)
+  oct = oct > kHalf - 1 ? kHalf - 1 : oct;
+  return cls * kHalf + (kHalf - 1 - oct);
+}
+
+__global__ void k_sched_reset(int32_t* counters, int32_t* hist) {
+  const int t = threadIdx.x;
+  if (t < 8) counters[t] = 0;
+  if (t < 2 * kBins) hist[t] = 0;
+}
+
+__global__ void k_sched_count(const int64_t* off, int64_t n_beams, int wave_max, int32_t* hist,
+                              int32_t* counters) {
+  __shared__ int32_t h[kBins];
+  __shared__ int32_t nl;
+  if (threadIdx.x < kBins) h[threadIdx.x] = 0;
+  if (threadIdx.x == 0) nl = 0;
+  __syncthreads();
+  for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < n_beams;
+       b += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t n = off[b + 1] - off[b];
+    atomicAdd(&h[len_bin(n, wave_max)], 1);
+    if (n > wave_max) atomicAdd(&nl, 1);
+  }
+  __syncthreads();
+  if (threadIdx.x < kBins && h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
+  if (threadIdx.x == 0 && nl) atomicAdd(&counters[2], nl);
+}
+
+__global__ void k_sched_scan(int32_t* hist) {
+  if (threadIdx.x == 0) {
+    int32_t s = 0;
+    for (int i = 0; i < kBins; ++i) {
+      hist[kBins + i] = s;
+      s += hist[i];
+    }
+  }
+}
+
+__global__ void k_sched_scatter(const int64_t* off, int64_t n_beams, int wave_max, int32_t* hist,
+                                int32_t* order) {
+  for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < n_beams;
+       b += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t n = off[b + 1] - off[b];
+    const int pos = atomicAdd(&hist[kBins + len_bin(n, wave_max)], 1);
+    order[pos] = (int32_t)b;
+  }
+}
+
+__global__ void k_max_len(const int64_t* off, int64_t n_beams, int32_t* out) {
+  int32_t m = 0;
+  for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < n_beams;
+       b += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t n = off[b + 1] - off[b];
+    m = max(m, (int32_t)min<int64_t>(n, 0x7fffffff));
+  }
+  atomicMax(out, m);
+}
+
+__global__ void k_zero_i32(int32_t* p) {
+  if (threadIdx.x == 0) *p = 0;
+}
+
+__global__ void k_erfc_probe(int64_t n, const float* z, float* out) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) out[i] = erfc_pos(z[i]);
+}
+
+}  // namespace
+
+hipError_t launch_erfc_probe(fsmi_ctx ctx, int64_t n, const float* z, float* out) {
+  if (n <= 0) return hipSuccess;
+  const int64_t blocks = (n + 255) / 256;
+  hipLaunchKernelGGL(k_erfc_probe, dim3((unsigned)blocks), dim3(256), 0, ctx->stream, n, z, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_max_len(fsmi_ctx ctx, const int64_t* off, int64_t n_beams, int* host_out) {
+  hipError_t e = ensure_work(ctx, 64);
+  if (e != hipSuccess) return e;
+  int32_t* d = reinterpret_cast<int32_t*>(ctx->d_work);
+  hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, ctx->stream, d);
+  const int grid = (int)std::min<int64_t>((n_beams + 255) / 256, 1024);
+  hipLaunchKernelGGL(k_max_len, dim3(std::max(grid, 1)), dim3(256), 0, ctx->stream, off, n_beams, d);
+  e = hipMemcpyAsync(host_out, d, 4, hipMemcpyDeviceToHost, ctx->stream);
+  if (e != hipSuccess) return e;
+  return hipStreamSynchronize(ctx->stream);
+}
+
+// Beams longer than the wave threshold are handled by a whole workgroup.
+static int wave_threshold(int precision) { return precision == FSMI_FP64 ? 256 : 512; }
+
+hipError_t launch_eval_beams(fsmi_ctx ctx, const EvalConst& ec, int64_t n_beams, const int64_t* off,
+                             const float* occ, const double* bound, const float* sigma,
+                             double* mi, int max_len) {
+  if (n_beams <= 0) return hipSuccess;
+  const size_t need = (size_t)n_beams * 4 + 2 * kBins * 4 + 64;
+  hipError_t e = ensure_work(ctx, need);
+  if (e != hipSuccess) return e;
+  int32_t* order = reinterpret_cast<int32_t*>(ctx->d_work);
+  int32_t* hist = order + n_beams;
+  const int wave_max = wave_threshold(ec.precision);
+
+  hipLaunchKernelGGL(k_sched_reset, dim3(1), dim3(64), 0, ctx->stream, ctx->d_counters, hist);
+  const int cb = (int)std::max<int64_t>(1, std::min<int64_t>((n_beams + 255) / 256, 1024));
+  hipLaunchKernelGGL(k_sched_count, dim3(cb), dim3(256), 0, ctx->stream, off, n_beams, wave_max,
+                     hist, ctx->d_counters);
+  hipLaunchKernelGGL(k_sched_scan, dim3(1), dim3(64), 0, ctx->stream, hist);
+  hipLaunchKernelGGL(k_sched_scatter, dim3(cb), dim3(256), 0, ctx->stream, off, n_beams, wave_max,
+                     hist, order);
+
+  BeamArgs a;
+  a.ec = ec;
+  a.n_beams = n_beams;
+  a.off = off;
+  a.occ = occ;
+  a.bound = bound;
+  a.sigma = sigma;
+  a.mi = mi;
+  a.order = order;
+  a.counters = ctx->d_counters;
+  a.status = ctx->d_status;
+  const bool fp64 = ec.precision == FSMI_FP64;
+  const int bpc = fp64 ? bytes_per_cell<double>() : bytes_per_cell<float>();
+  a.cap_wave = wave_max;
+  a.cap_block = std::max(max_len, 1);
+  const size_t lds_block = (size_t)bpc * a.cap_block + 16;
+  const size_t lds_wave = (size_t)kNW * ((size_t)bpc * a.cap_wave + 16);
+  if (lds_block > 150 * 1024 || lds_wave > 150 * 1024) return hipErrorInvalidValue;
+  const int64_t want = (n_beams + kNW - 1) / kNW;
+  const size_t lds_long = lds_block, lds_short = lds_wave;
+  const int per_cu_l = std::max<int>(1, (int)((160 * 1024) / (lds_long + 512)));
+  const int per_cu_s = std::max<int>(1, (int)((160 * 1024) / (lds_short + 512)));
+  const int grid_l = std::max(1, std::min(kMaxGrid, ctx->num_cu * std::min(per_cu_l, 8)));
+  const int grid_s = (int)std::max<int64_t>(
+      1, std::min<int64_t>(want, std::min(kMaxGrid, ctx->num_cu * std::min(per_cu_s, 8))));
+  if (fp64) {
+    (void)hipFuncSetAttribute((const void*)k_eval_long<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_long);
+    (void)hipFuncSetAttribute((const void*)k_eval_short<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_short);
+    hipLaunchKernelGGL(k_eval_long<double>, dim3(grid_l), dim3(kWave * kNW), lds_long, ctx->stream, a);
+    hipLaunchKernelGGL(k_eval_short<double>, dim3(grid_s), dim3(kWave * kNW), lds_short, ctx->stream, a);
+  } else {
+    (void)hipFuncSetAttribute((const void*)k_eval_long<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_long);
+    (void)hipFuncSetAttribute((const void*)k_eval_short<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_short);
+    hipLaunchKernelGGL(k_eval_long<float>, dim3(grid_l), dim3(kWave * kNW), lds_long, ctx->stream, a);
+    hipLaunchKernelGGL(k_eval_short<float>, dim3(grid_s), dim3(kWave * kNW), lds_short, ctx->stream, a);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace fsmi

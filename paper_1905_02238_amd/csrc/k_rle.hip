@@ -1,0 +1,275 @@
+// k_rle.hip -- FSMI on run-length-encoded beams (fsmi_rle_eval_beams) and the
+// fused 3D pose path (fsmi_eval_poses on voxel maps).
+//
+// FSMI-RLE (Thm 5) and Approx-FSMI-RLE (Thm 6) are, by their proofs, the plain
+// double sum over the expanded beam of equal-width virtual cells with the
+// weight g(k - j) (exactly so once the kernel is truncated inside the blocks
+// too).  This engine expands the runs in LDS and evaluates that sum with the
+// per-beam kernel table; the paper itself evaluates short runs this way
+// (Sec. 5.4: decompress when runs are shorter than 4).
+#include <math.h>
+
+#include <algorithm>
+
+#include "beam_dev.h"
+#include "fsmi_internal.h"
+#include "ray_dev.h"
+
+namespace fsmi {
+hipError_t launch_pose_reduce(fsmi_ctx ctx, const double* mi_beam, int64_t n_poses,
+                              int64_t n_beams, double* mi_pose);
+namespace {
+
+struct RleArgs {
+  EvalConst ec;
+  int64_t n_beams;
+  const int64_t* run_off;
+  const float* run_occ;
+  const int32_t* run_len;
+  const float* sigma_p;
+  double* mi;
+  int cap;             // expanded cells per beam
+  int32_t* counter;    // 64-bit queue head
+  uint32_t* status;
+};
+
+template <typename T>
+__host__ __device__ inline size_t rle_lds(int cap) {
+  return (size_t)core_bytes_per_cell<T>() * cap + 8 + 4 * (size_t)cap + 16;
+}
+
+template <typename T>
+FSMI_DEV CoreLds carve_rle(char* p, int cap, float** so) {
+  CoreLds L;
+  L.A = reinterpret_cast<double*>(p);
+  L.C = p + 8 * (size_t)(cap + 1);
+  L.P = reinterpret_cast<char*>(L.C) + sizeof(T) * (size_t)cap;
+  *so = reinterpret_cast<float*>(reinterpret_cast<char*>(L.P) + sizeof(T) * (size_t)cap);
+  return L;
+}
+
+// Expands runs [r0, r1) into so[0..n); returns n, or -1 on a bad run length / overflow.
+FSMI_DEV int expand_runs(const float* run_occ, const int32_t* run_len, int64_t r0, int64_t r1,
+                         int cap, float* so, int* ss, int lane) {
+  // run starts by an exclusive scan of the lengths (chunks of 64 runs)
+  int carry = 0;
+  bool bad = false;
+  const int nr = (int)(r1 - r0);
+  for (int base = 0; base < nr; base += kWave) {
+    const int u = base + lane;
+    int L = u < nr ? run_len[r0 + u] : 0;
+    if (u < nr && L <= 0) bad = true;
+    L = L > 0 ? L : 0;
+    const int inc = wave_scan_incl<OpAdd>(L);
+    const int s = carry + inc - L;
+    if (u < nr && !bad && s + L <= cap) {
+      const float o = run_occ[r0 + u];
+      for (int t = 0; t < L; ++t) so[s + t] = o;
+    }
+    carry += wave_last(inc);
+    if (carry > cap) bad = true;
+  }
+  (void)ss;
+  if (__any(bad)) return -1;
+  wave_sync();
+  return carry;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kWave) void k_rle_beams(RleArgs a) {
+  extern __shared__ __align__(16) char lds[];
+  float* so;
+  const CoreLds L = carve_rle<T>(lds, a.cap, &so);
+  const int lane = threadIdx.x;
+  for (int64_t it = wave_pop64(a.counter); it < a.n_beams; it = wave_pop64(a.counter)) {
+    const int64_t r0 = a.run_off[it], r1 = a.run_off[it + 1];
+    double v;
+    if (r1 < r0) {
+      v = __builtin_nan("");
+      if (lane == 0) latch(a.status, kErrLen);
+    } else {
+      const int n = expand_runs(a.run_occ, a.run_len, r0, r1, a.cap, so, nullptr, lane);
+      if (n < 0) {
+        v = __builtin_nan("");
+        if (lane == 0) latch(a.status, kErrLen);
+      } else if (n == 0) {
+        v = 0.0;
+      } else {
+        bool bad;
+        v = beam_core<1, false, T>(a.ec, n, so, false, (double)a.sigma_p[it], L, nullptr, nullptr,
+                                   lane, false, &bad);
+        if (bad && lane == 0) latch(a.status, kErrOcc);
+      }
+    }
+    if (lane == 0) a.mi[it] = v;
+    wave_sync();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Fused 3D: one wave per (pose, beam): yaw rotation, virtual cells (ray_dev.h),
+// evaluation on the expanded virtual cells.
+// ---------------------------------------------------------------------------
+struct Pose3dArgs {
+  EvalConst ec;
+  const float* map;
+  int64_t X, Y, Z;
+  int64_t n_poses, n_beams;
+  const double* poses;     // [n][5] x, y, z, cos, sin
+  const double* beam_dir;  // [n][3]
+  double sigma_p, R, w;
+  int cap;
+  double* mi_beam;
+  int32_t* counter;
+  uint32_t* status;
+};
+
+template <typename T>
+__global__ __launch_bounds__(kWave) void k_poses3d(Pose3dArgs a) {
+#pragma clang fp contract(off)
+  extern __shared__ __align__(16) char lds[];
+  float* so;
+  const CoreLds L = carve_rle<T>(lds, a.cap, &so);
+  const int lane = threadIdx.x;
+  const int64_t n_items = a.n_poses * a.n_beams;
+  for (int64_t it = wave_pop64(a.counter); it < n_items; it = wave_pop64(a.counter)) {
+    const int64_t p = it / a.n_beams, b = it - p * a.n_beams;
+    const double* ps = a.poses + 5 * p;
+    const double* bd = a.beam_dir + 3 * b;
+    const double m1 = ps[3] * bd[0], m2 = ps[4] * bd[1], m3 = ps[4] * bd[0], m4 = ps[3] * bd[1];
+    const double d[3] = {m1 - m2, m3 + m4, bd[2]};
+    bool ok;
+    const int n = virtual3d_wave(a.map, a.X, a.Y, a.Z, ps, d, a.R, a.w, a.cap, so, nullptr, lane, &ok);
+    double v;
+    if (!ok) {
+      v = __builtin_nan("");
+      if (lane == 0) latch(a.status, kErrPose);
+    } else if (n == 0) {
+      v = 0.0;
+    } else {
+      wave_sync();
+      bool bad;
+      v = beam_core<1, false, T>(a.ec, n, so, false, a.sigma_p, L, nullptr, nullptr, lane, false, &bad);
+      if (bad && lane == 0) latch(a.status, kErrOcc);
+    }
+    if (lane == 0) a.mi_beam[it] = v;
+    wave_sync();
+  }
+}
+
+__global__ void k_reset_counter64(int32_t* c) {
+  if (threadIdx.x < 2) c[threadIdx.x] = 0;
+}
+
+__global__ void k_rle_max_len(const int64_t* run_off, const int32_t* run_len, int64_t n_beams,
+                              int32_t* out) {
+  for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < n_beams;
+       b += (int64_t)gridDim.x * blockDim.x) {
+    int64_t s = 0;
+    for (int64_t u = run_off[b]; u < run_off[b + 1]; ++u) s += run_len[u] > 0 ? run_len[u] : 0;
+    atomicMax(out, (int32_t)min<int64_t>(s, 0x7fffffff));
+  }
+}
+
+__global__ void k_zero_i32(int32_t* p) {
+  if (threadIdx.x == 0) *p = 0;
+}
+
+}  // namespace
+
+hipError_t launch_rle_eval_beams(fsmi_ctx ctx, const EvalConst& ec, int64_t n_beams,
+                                 const int64_t* run_off, const float* run_occ,
+                                 const int32_t* run_len, const float* sigma_p, double* mi,
+                                 int max_cells) {
+  if (n_beams <= 0) return hipSuccess;
+  hipError_t e;
+  if (max_cells <= 0) {
+    e = ensure_work(ctx, 64);
+    if (e != hipSuccess) return e;
+    int32_t* d = reinterpret_cast<int32_t*>(ctx->d_work);
+    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, ctx->stream, d);
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((n_beams + 255) / 256, 1024));
+    hipLaunchKernelGGL(k_rle_max_len, dim3(grid), dim3(256), 0, ctx->stream, run_off, run_len,
+                       n_beams, d);
+    int host = 0;
+    e = hipMemcpyAsync(&host, d, 4, hipMemcpyDeviceToHost, ctx->stream);
+    if (e != hipSuccess) return e;
+    e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return e;
+    max_cells = std::max(host, 1);
+  }
+  RleArgs a;
+  a.ec = ec;
+  a.n_beams = n_beams;
+  a.run_off = run_off;
+  a.run_occ = run_occ;
+  a.run_len = run_len;
+  a.sigma_p = sigma_p;
+  a.mi = mi;
+  a.cap = max_cells;
+  a.counter = ctx->d_counters + 8;
+  a.status = ctx->d_status;
+  const bool fp64 = ec.precision == FSMI_FP64;
+  const size_t lds = fp64 ? rle_lds<double>(a.cap) : rle_lds<float>(a.cap);
+  if (lds > 150 * 1024) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_reset_counter64, dim3(1), dim3(64), 0, ctx->stream, a.counter);
+  const int per_cu = std::max<int>(1, std::min<int>(16, (int)((160 * 1024) / (lds + 256))));
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(n_beams, (int64_t)ctx->num_cu * per_cu));
+  if (fp64) {
+    (void)hipFuncSetAttribute((const void*)k_rle_beams<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k_rle_beams<double>, dim3(grid), dim3(kWave), lds, ctx->stream, a);
+  } else {
+    (void)hipFuncSetAttribute((const void*)k_rle_beams<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k_rle_beams<float>, dim3(grid), dim3(kWave), lds, ctx->stream, a);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_eval_poses_3d(fsmi_ctx ctx, const EvalConst& ec, const float* map, int64_t X,
+                                int64_t Y, int64_t Z, int64_t n_poses, const double* poses,
+                                int64_t n_beams, const double* beam_dir, double sigma, double R,
+                                double w, double* mi_pose, double* mi_beam) {
+  const int64_t n_items = n_poses * n_beams;
+  if (n_items <= 0) return hipSuccess;
+  double* mb = mi_beam;
+  if (!mb) {
+    hipError_t e = ensure_work(ctx, (size_t)n_items * 8);
+    if (e != hipSuccess) return e;
+    mb = reinterpret_cast<double*>(ctx->d_work);
+  }
+  Pose3dArgs a;
+  a.ec = ec;
+  a.map = map;
+  a.X = X;
+  a.Y = Y;
+  a.Z = Z;
+  a.n_poses = n_poses;
+  a.n_beams = n_beams;
+  a.poses = poses;
+  a.beam_dir = beam_dir;
+  a.sigma_p = sigma / w;
+  a.R = R;
+  a.w = w;
+  a.cap = std::max(1, (int)floor(R / w));
+  a.mi_beam = mb;
+  a.counter = ctx->d_counters + 8;
+  a.status = ctx->d_status;
+  const bool fp64 = ec.precision == FSMI_FP64;
+  const size_t lds = fp64 ? rle_lds<double>(a.cap) : rle_lds<float>(a.cap);
+  if (lds > 150 * 1024) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_reset_counter64, dim3(1), dim3(64), 0, ctx->stream, a.counter);
+  const int per_cu = std::max<int>(1, std::min<int>(16, (int)((160 * 1024) / (lds + 256))));
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(n_items, (int64_t)ctx->num_cu * per_cu));
+  if (fp64) {
+    (void)hipFuncSetAttribute((const void*)k_poses3d<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k_poses3d<double>, dim3(grid), dim3(kWave), lds, ctx->stream, a);
+  } else {
+    (void)hipFuncSetAttribute((const void*)k_poses3d<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k_poses3d<float>, dim3(grid), dim3(kWave), lds, ctx->stream, a);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_pose_reduce(ctx, mb, n_poses, n_beams, mi_pose);
+}
+
+}  // namespace fsmi

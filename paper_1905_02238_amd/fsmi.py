@@ -1,0 +1,239 @@
+"""ctypes binding of libfsmi (include/libfsmi.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  Tensors are torch CUDA tensors (device memory owned by the caller);
+the binding checks dtype / device / contiguity, allocates outputs with torch
+when the caller does not pass them, and enqueues on torch's current stream.
+If ``libfsmi.so`` has not been built the first call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import threading
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfsmi.so")
+
+FSMI_OK, FSMI_E_INVAL, FSMI_E_DEVICE, FSMI_E_NOMEM, FSMI_E_CAPACITY, FSMI_E_NUMERIC, \
+    FSMI_E_UNSUPPORTED = range(7)
+FSMI_EXACT, FSMI_APPROX, FSMI_UNIFORM = 0, 1, 2
+FSMI_KERNEL_ERF, FSMI_KERNEL_DENSITY = 0, 1
+FSMI_FP32, FSMI_FP64 = 0, 1
+FSMI_F_SKIP_ZERO = 1
+FSMI_RAY_DDA, FSMI_RAY_VIRTUAL, FSMI_RAY_RLE = 0, 1, 2
+
+EXPORTS = ("fsmi_create", "fsmi_destroy", "fsmi_set_stream", "fsmi_sync", "fsmi_last_error",
+           "fsmi_status_string", "fsmi_default_params", "fsmi_raycast", "fsmi_eval_beams",
+           "fsmi_rle_eval_beams", "fsmi_eval_poses", "fsmi_probe_erfc")
+
+
+class FsmiError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"libfsmi status {status}: {msg}")
+        self.status = status
+
+
+class fsmi_params(C.Structure):
+    _fields_ = [("delta_occ", C.c_double), ("variant", C.c_int32), ("trunc_delta", C.c_int32),
+                ("uniform_h", C.c_int32), ("kernel", C.c_int32), ("precision", C.c_int32),
+                ("flags", C.c_uint32)]
+
+
+class fsmi_map(C.Structure):
+    _fields_ = [("occ", C.c_void_p), ("ndim", C.c_int32), ("dims", C.c_int64 * 3)]
+
+
+_lib = None
+_lock = threading.Lock()
+
+
+def load(path: str = LIB_PATH):
+    """Loads libfsmi.so (raises if it is missing)."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(path):
+                raise RuntimeError(f"libfsmi.so not found at {path}: build it with "
+                                   "`python -m paper_1905_02238_amd.build` (or __graft_entry__.build())")
+            L = C.CDLL(path)
+            p, i32, i64, d, st = C.c_void_p, C.c_int32, C.c_int64, C.c_double, C.c_int
+            L.fsmi_create.argtypes = [C.POINTER(p), C.c_int, p]
+            L.fsmi_destroy.argtypes = [p]
+            L.fsmi_destroy.restype = None
+            L.fsmi_set_stream.argtypes = [p, p]
+            L.fsmi_sync.argtypes = [p]
+            L.fsmi_last_error.argtypes = [p]
+            L.fsmi_last_error.restype = C.c_char_p
+            L.fsmi_status_string.argtypes = [st]
+            L.fsmi_status_string.restype = C.c_char_p
+            L.fsmi_default_params.argtypes = [C.POINTER(fsmi_params)]
+            L.fsmi_default_params.restype = None
+            L.fsmi_raycast.argtypes = [p, C.POINTER(fsmi_map), i32, i64, p, p, d, d, i32, p, p, p, p, p]
+            L.fsmi_eval_beams.argtypes = [p, C.POINTER(fsmi_params), i64, p, p, p, p, p]
+            L.fsmi_rle_eval_beams.argtypes = [p, C.POINTER(fsmi_params), i64, p, p, p, p, p]
+            L.fsmi_eval_poses.argtypes = [p, C.POINTER(fsmi_params), C.POINTER(fsmi_map), i64, p,
+                                          i64, p, d, d, d, p, p]
+            L.fsmi_probe_erfc.argtypes = [p, i64, p, p]
+            for n in ("fsmi_create", "fsmi_set_stream", "fsmi_sync", "fsmi_raycast",
+                      "fsmi_eval_beams", "fsmi_rle_eval_beams", "fsmi_eval_poses",
+                      "fsmi_probe_erfc"):
+                getattr(L, n).restype = st
+            _lib = L
+    return _lib
+
+
+def params(variant=FSMI_EXACT, delta_occ=1.5, trunc_delta=3, uniform_h=0, kernel=FSMI_KERNEL_ERF,
+           precision=FSMI_FP32, flags=0) -> fsmi_params:
+    p = fsmi_params()
+    load().fsmi_default_params(C.byref(p))
+    p.delta_occ, p.variant, p.trunc_delta, p.uniform_h = delta_occ, variant, trunc_delta, uniform_h
+    p.kernel, p.precision, p.flags = kernel, precision, flags
+    return p
+
+
+def _ptr(t, dtype, name, allow_none=False):
+    if t is None:
+        if allow_none:
+            return None
+        raise ValueError(f"{name} is required")
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return C.c_void_p(t.data_ptr())
+
+
+def _map(occ: torch.Tensor) -> fsmi_map:
+    m = fsmi_map()
+    m.occ = _ptr(occ, torch.float32, "map").value
+    if occ.dim() == 2:
+        m.ndim = 2
+        m.dims[0], m.dims[1], m.dims[2] = occ.shape[1], occ.shape[0], 1
+    elif occ.dim() == 3:
+        m.ndim = 3
+        m.dims[0], m.dims[1], m.dims[2] = occ.shape[2], occ.shape[1], occ.shape[0]
+    else:
+        raise ValueError("map must be [Y][X] or [Z][Y][X]")
+    return m
+
+
+class Context:
+    """An fsmi_ctx bound to one device; calls enqueue on torch's current stream."""
+
+    def __init__(self, device: int = 0):
+        self.device = device
+        self._lib = load()
+        h = C.c_void_p()
+        with torch.cuda.device(device):
+            s = torch.cuda.current_stream(device).cuda_stream
+            self._check(self._lib.fsmi_create(C.byref(h), device, C.c_void_p(s)), None)
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self._lib.fsmi_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st, h=None):
+        if st != FSMI_OK:
+            L = self._lib
+            msg = L.fsmi_last_error(h or self.handle).decode() if (h or getattr(self, "handle", None)) \
+                else L.fsmi_status_string(st).decode()
+            raise FsmiError(st, msg or L.fsmi_status_string(st).decode())
+
+    def _stream(self):
+        s = torch.cuda.current_stream(self.device).cuda_stream
+        self._check(self._lib.fsmi_set_stream(self.handle, C.c_void_p(s)))
+
+    # --- C-ABI entry points -------------------------------------------------
+    def fsmi_sync(self):
+        self._check(self._lib.fsmi_sync(self.handle))
+
+    def fsmi_raycast(self, map_occ, mode, origin, direction, max_range, w=1.0, max_cells=None,
+                     count=None, cell=None, entry=None, occ_out=None, run_len=None):
+        n = origin.shape[0]
+        dev = map_occ.device
+        if max_cells is None:
+            if mode == FSMI_RAY_DDA:
+                max_cells = int(1.4142135623730951 * max_range) + 3
+            else:
+                max_cells = int(max_range / w)
+        count = torch.empty(n, dtype=torch.int32, device=dev) if count is None else count
+        cell = torch.empty((n, max_cells), dtype=torch.int32, device=dev) if cell is None else cell
+        if mode == FSMI_RAY_DDA and entry is None:
+            entry = torch.empty((n, max_cells + 1), dtype=torch.float64, device=dev)
+        occ_out = torch.empty((n, max_cells), dtype=torch.float32, device=dev) if occ_out is None else occ_out
+        if mode == FSMI_RAY_RLE and run_len is None:
+            run_len = torch.empty((n, max_cells), dtype=torch.int32, device=dev)
+        m = _map(map_occ)
+        self._stream()
+        self._check(self._lib.fsmi_raycast(
+            self.handle, C.byref(m), mode, n, _ptr(origin, torch.float64, "origin"),
+            _ptr(direction, torch.float64, "dir"), float(max_range), float(w), int(max_cells),
+            _ptr(count, torch.int32, "count"), _ptr(cell, torch.int32, "cell"),
+            _ptr(entry, torch.float64, "entry", True), _ptr(occ_out, torch.float32, "occ_out", True),
+            _ptr(run_len, torch.int32, "run_len", True)))
+        return dict(count=count, cell=cell, entry=entry, occ=occ_out, run_len=run_len)
+
+    def fsmi_eval_beams(self, prm: fsmi_params, off, occ, sigma, bound=None, mi=None):
+        n = off.shape[0] - 1
+        mi = torch.empty(n, dtype=torch.float64, device=occ.device) if mi is None else mi
+        self._stream()
+        self._check(self._lib.fsmi_eval_beams(
+            self.handle, C.byref(prm), n, _ptr(off, torch.int64, "off"),
+            _ptr(occ, torch.float32, "occ"), _ptr(bound, torch.float64, "bound", True),
+            _ptr(sigma, torch.float32, "sigma"), _ptr(mi, torch.float64, "mi")))
+        return mi
+
+    def fsmi_rle_eval_beams(self, prm: fsmi_params, run_off, run_occ, run_len, sigma_prime, mi=None):
+        n = run_off.shape[0] - 1
+        mi = torch.empty(n, dtype=torch.float64, device=run_occ.device) if mi is None else mi
+        self._stream()
+        self._check(self._lib.fsmi_rle_eval_beams(
+            self.handle, C.byref(prm), n, _ptr(run_off, torch.int64, "run_off"),
+            _ptr(run_occ, torch.float32, "run_occ"), _ptr(run_len, torch.int32, "run_len"),
+            _ptr(sigma_prime, torch.float32, "sigma_prime"), _ptr(mi, torch.float64, "mi")))
+        return mi
+
+    def fsmi_eval_poses(self, prm: fsmi_params, map_occ, poses, beam_dir, sigma, max_range, w=1.0,
+                        mi_pose=None, mi_beam=None, want_beams=False):
+        npo, nb = poses.shape[0], beam_dir.shape[0]
+        dev = map_occ.device
+        mi_pose = torch.empty(npo, dtype=torch.float64, device=dev) if mi_pose is None else mi_pose
+        if want_beams and mi_beam is None:
+            mi_beam = torch.empty((npo, nb), dtype=torch.float64, device=dev)
+        m = _map(map_occ)
+        self._stream()
+        self._check(self._lib.fsmi_eval_poses(
+            self.handle, C.byref(prm), C.byref(m), npo, _ptr(poses, torch.float64, "poses"), nb,
+            _ptr(beam_dir, torch.float64, "beam_dir"), float(sigma), float(max_range), float(w),
+            _ptr(mi_pose, torch.float64, "mi_pose"), _ptr(mi_beam, torch.float64, "mi_beam", True)))
+        return mi_pose, mi_beam
+
+    def fsmi_probe_erfc(self, z, out=None):
+        out = torch.empty_like(z) if out is None else out
+        self._stream()
+        self._check(self._lib.fsmi_probe_erfc(self.handle, z.numel(), _ptr(z, torch.float32, "z"),
+                                              _ptr(out, torch.float32, "out")))
+        return out
+
+
+_ctx = {}
+
+
+def context(device: int = 0) -> Context:
+    """A cached Context per device."""
+    if device not in _ctx:
+        _ctx[device] = Context(device)
+    return _ctx[device]

@@ -1,0 +1,280 @@
+"""Parity of the HIP path (through the C-ABI) against the FP64 oracle.
+
+Bars: cell lists, entry distances, counts and run encodings bit-exact; MI in
+FP32 mode within 1e-5 relative of the oracle per beam and per pose (an exact
+zero must stay zero); FP64 mode within 1e-12.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_1905_02238_amd import fsmi as F
+from paper_1905_02238_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL32 = 1e-5
+TOL64 = 1e-12
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    print("[gpu] creating libfsmi context on cuda:0", flush=True)
+    return F.context(0)
+
+
+def dev(a, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+def rel_err(got, ref):
+    got = np.asarray(got, np.float64)
+    ref = np.asarray(ref, np.float64)
+    zero = ref == 0.0
+    assert np.all(got[zero] == 0.0), "an exact zero of the oracle is not zero on the GPU"
+    nz = ~zero
+    if not np.any(nz):
+        return 0.0
+    return float(np.max(np.abs(got[nz] - ref[nz]) / np.abs(ref[nz])))
+
+
+# ---------------------------------------------------------------------------
+def test_erfc_error_bound(ctx):
+    import mpmath as mp
+    z = np.concatenate([np.linspace(0, 4, 4001), np.linspace(4, 9.0, 2001)]).astype(np.float32)
+    out = ctx.fsmi_probe_erfc(dev(z)).cpu().numpy().astype(np.float64)
+    ref = np.array([math.erfc(float(v)) for v in z])
+    e = np.abs(out - ref) / ref
+    assert e[z < 4].max() < 3e-6, e[z < 4].max()
+    assert e.max() < 2e-5, e.max()
+
+
+# ---------------------------------------------------------------------------
+def _rays_2d(seed, X, Y, n, R_lo=1, R_hi=80):
+    rng = np.random.default_rng(seed)
+    o = np.stack([rng.uniform(0, X, n), rng.uniform(0, Y, n)], 1)
+    # some origins on vertices and faces, some axis-aligned and diagonal directions
+    o[: n // 8] = np.floor(o[: n // 8])
+    o[n // 8: n // 4, 0] = np.floor(o[n // 8: n // 4, 0])
+    th = rng.uniform(0, 2 * math.pi, n)
+    th[: n // 16] = rng.integers(0, 8, n // 16) * (math.pi / 4)
+    d = np.stack([np.cos(th), np.sin(th)], 1)
+    return o, d
+
+
+@pytest.mark.parametrize("R", [7.5, 60.0, 150.0])
+def test_raycast2d_bitexact(ctx, R):
+    print(f"[gpu] raycast2d R={R}", flush=True)
+    X, Y = 64, 48
+    grid = np.random.default_rng(1).uniform(0, 1, (Y, X)).astype(np.float32)
+    o, d = _rays_2d(int(R), X, Y, 600)
+    out = ctx.fsmi_raycast(dev(grid), F.FSMI_RAY_DDA, dev(o), dev(d), R)
+    torch.cuda.synchronize()
+    ctx.fsmi_sync()
+    cnt = out["count"].cpu().numpy()
+    cells = out["cell"].cpu().numpy()
+    ent = out["entry"].cpu().numpy()
+    occ = out["occ"].cpu().numpy()
+    for r in range(len(o)):
+        c, e, oc = O.raycast2d(grid, o[r], d[r], R)
+        assert cnt[r] == len(c), r
+        assert np.array_equal(cells[r, : len(c)], c), r
+        assert np.array_equal(ent[r, : len(c) + 1], e), r
+        assert np.array_equal(occ[r, : len(c)], oc), r
+
+
+def test_raycast2d_grid_small_rays(ctx):
+    wl = W.grid_small()
+    grid = wl["grid"]
+    p = wl["poses"][0]
+    d = wl["beam_dir"]
+    o = np.repeat(p[None, :2], len(d), 0)
+    out = ctx.fsmi_raycast(dev(grid), F.FSMI_RAY_DDA, dev(o), dev(d), wl["R"])
+    torch.cuda.synchronize()
+    for r in range(len(d)):
+        c, e, _ = O.raycast2d(grid, o[r], d[r], wl["R"])
+        n = int(out["count"][r])
+        assert n == len(c)
+        assert np.array_equal(out["cell"][r, :n].cpu().numpy(), c)
+        assert np.array_equal(out["entry"][r, : n + 1].cpu().numpy(), e)
+
+
+def test_virtual3d_and_runs_bitexact(ctx):
+    print("[gpu] virtual3d", flush=True)
+    vox, lab = W.voxel_map(48, 40, 24, seed=5, n_boxes=10, n_pillars=6, block=8, unknown_frac=0.05)
+    rng = np.random.default_rng(2)
+    n = 300
+    o = np.stack([rng.uniform(0, 48, n), rng.uniform(0, 40, n), rng.uniform(0, 24, n)], 1)
+    d = rng.normal(size=(n, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    R = 70.0
+    v = ctx.fsmi_raycast(dev(vox), F.FSMI_RAY_VIRTUAL, dev(o), dev(d), R, 1.0)
+    rl = ctx.fsmi_raycast(dev(vox), F.FSMI_RAY_RLE, dev(o), dev(d), R, 1.0)
+    torch.cuda.synchronize()
+    for r in range(n):
+        c, oc = O.virtual3d(vox, o[r], d[r], R, 1.0)
+        k = int(v["count"][r])
+        assert k == len(c)
+        assert np.array_equal(v["cell"][r, :k].cpu().numpy(), c)
+        assert np.array_equal(v["occ"][r, :k].cpu().numpy(), oc)
+        ro, rlen = O.rle_runs(oc)
+        m = int(rl["count"][r])
+        assert m == len(ro)
+        assert np.array_equal(rl["occ"][r, :m].cpu().numpy(), ro)
+        assert np.array_equal(rl["run_len"][r, :m].cpu().numpy(), rlen)
+
+
+# ---------------------------------------------------------------------------
+def _beam_batch(seed, n_beams, lens, widths):
+    rng = np.random.default_rng(seed)
+    lens = np.asarray(lens, np.int64)
+    off = np.zeros(n_beams + 1, np.int64)
+    np.cumsum(lens, out=off[1:])
+    occ = rng.uniform(0.0, 1.0, int(off[-1])).astype(np.float32)
+    # sprinkle known cells (o = 0, 1) and the prior 0.5
+    k = rng.integers(0, max(1, int(off[-1])), int(off[-1]) // 20)
+    occ[k] = rng.choice(np.array([0.0, 1.0, 0.5], np.float32), len(k))
+    sigma = rng.uniform(0.3, 5.0, n_beams).astype(np.float32)
+    bound = None
+    if widths:
+        bound = np.zeros(int(off[-1]) + n_beams)
+        for b in range(n_beams):
+            n = int(lens[b])
+            w = rng.uniform(0.01, 1.5, n)
+            bound[off[b] + b: off[b] + b + n + 1] = np.concatenate([[0.0], np.cumsum(w)])
+    return off, occ, bound, sigma
+
+
+LENS = [0, 1, 2, 3, 5, 63, 64, 65, 127, 200, 511, 512, 513, 700, 33, 7]
+
+
+@pytest.mark.parametrize("variant", [F.FSMI_EXACT, F.FSMI_APPROX, F.FSMI_UNIFORM])
+@pytest.mark.parametrize("widths", [True, False])
+@pytest.mark.parametrize("prec", [F.FSMI_FP32, F.FSMI_FP64])
+def test_eval_beams_parity(ctx, variant, widths, prec):
+    print(f"[gpu] eval_beams variant={variant} widths={widths} prec={prec}", flush=True)
+    off, occ, bound, sigma = _beam_batch(10 + variant, len(LENS), LENS, widths)
+    prm = F.params(variant=variant, trunc_delta=4, uniform_h=3, precision=prec)
+    mi = ctx.fsmi_eval_beams(prm, dev(off), dev(occ), dev(sigma),
+                             None if bound is None else dev(bound))
+    torch.cuda.synchronize()
+    ctx.fsmi_sync()
+    ref = O.eval_beams(variant, off, occ, sigma, bound=bound, Delta=4, H=3)
+    got = mi.cpu().numpy()
+    assert got[0] == 0.0
+    tol = TOL32 if prec == F.FSMI_FP32 else TOL64
+    assert rel_err(got, ref) <= tol
+
+
+def test_eval_beams_uneven_batch(ctx):
+    print("[gpu] eval_beams uneven batch", flush=True)
+    off, occ, sigma = W.uneven_beams(400, seed=77, n_max=1500)
+    prm = F.params(variant=F.FSMI_EXACT)
+    mi = ctx.fsmi_eval_beams(prm, dev(off), dev(occ), dev(sigma))
+    mi2 = ctx.fsmi_eval_beams(prm, dev(off), dev(occ), dev(sigma))
+    torch.cuda.synchronize()
+    ref = O.eval_beams(O.EXACT, off, occ, sigma)
+    assert rel_err(mi.cpu().numpy(), ref) <= TOL32
+    assert torch.equal(mi, mi2)          # deterministic across runs / queue orders
+
+
+def test_eval_beams_bad_data_latches(ctx):
+    off = np.array([0, 3, 6], np.int64)
+    occ = np.array([0.2, np.nan, 0.3, 0.1, 0.2, 0.3], np.float32)
+    sigma = np.array([1.0, 1.0], np.float32)
+    mi = ctx.fsmi_eval_beams(F.params(), dev(off), dev(occ), dev(sigma))
+    torch.cuda.synchronize()
+    with pytest.raises(F.FsmiError) as e:
+        ctx.fsmi_sync()
+    assert e.value.status == F.FSMI_E_NUMERIC
+    got = mi.cpu().numpy()
+    assert np.isnan(got[0]) and np.isfinite(got[1])
+    ctx.fsmi_sync()   # cleared
+
+
+def test_eval_beams_invalid_args(ctx):
+    off = dev(np.array([0, 2], np.int64))
+    occ = dev(np.array([0.2, 0.3], np.float32))
+    sg = dev(np.array([1.0], np.float32))
+    with pytest.raises(F.FsmiError) as e:
+        ctx.fsmi_eval_beams(F.params(delta_occ=0.5), off, occ, sg)
+    assert e.value.status == F.FSMI_E_INVAL
+    with pytest.raises(F.FsmiError):
+        ctx.fsmi_eval_beams(F.params(variant=7), off, occ, sg)
+
+
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("exact", [True, False])
+@pytest.mark.parametrize("kernel", [F.FSMI_KERNEL_ERF, F.FSMI_KERNEL_DENSITY])
+def test_rle_eval_beams_parity(ctx, exact, kernel):
+    print(f"[gpu] rle exact={exact} kernel={kernel}", flush=True)
+    off, ro, rl, sp = W.rle_beams(60, seed=3, run_lo=1, run_hi=40, n_runs_lo=0, n_runs_hi=20)
+    prm = F.params(variant=F.FSMI_EXACT if exact else F.FSMI_APPROX, trunc_delta=5, kernel=kernel)
+    mi = ctx.fsmi_rle_eval_beams(prm, dev(off), dev(ro), dev(rl), dev(sp))
+    torch.cuda.synchronize()
+    ctx.fsmi_sync()
+    ref = O.rle_eval_beams(exact, off, ro, rl, sp, kind=kernel, Delta=5)
+    assert rel_err(mi.cpu().numpy(), ref) <= TOL32
+
+
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("prec,tol", [(F.FSMI_FP64, TOL64), (F.FSMI_FP32, TOL32)])
+def test_poses_grid_small_full(ctx, prec, tol):
+    """200 x 200 rooms, pose on a cell vertex at the centre, 60 beams, R = 150, sigma = 2."""
+    print(f"[gpu] grid_small prec={prec}", flush=True)
+    wl = W.grid_small()
+    mp, mb = ctx.fsmi_eval_poses(F.params(precision=prec), dev(wl["grid"]), dev(wl["poses"]),
+                                 dev(wl["beam_dir"]), wl["sigma"], wl["R"], want_beams=True)
+    torch.cuda.synchronize()
+    ctx.fsmi_sync()
+    rp, rb = O.eval_poses_2d(O.EXACT, wl["grid"], wl["poses"], wl["beam_dir"], wl["sigma"], wl["R"])
+    assert rel_err(mb.cpu().numpy(), rb) <= tol
+    assert rel_err(mp.cpu().numpy(), rp) <= tol
+
+
+@pytest.mark.parametrize("variant", [F.FSMI_EXACT, F.FSMI_APPROX, F.FSMI_UNIFORM])
+def test_poses_grid_large_sample(ctx, variant):
+    """2048 x 2048 rooms + frontier blobs, R = 400, sigma = 3 (Delta 9, H 6): 3 poses x 360 beams."""
+    print(f"[gpu] grid_large variant={variant}", flush=True)
+    wl = W.grid_large(n_poses=3)
+    prm = F.params(variant=variant, trunc_delta=wl["Delta"], uniform_h=wl["H"])
+    mp, mb = ctx.fsmi_eval_poses(prm, dev(wl["grid"]), dev(wl["poses"]), dev(wl["beam_dir"]),
+                                 wl["sigma"], wl["R"], want_beams=True)
+    torch.cuda.synchronize()
+    ctx.fsmi_sync()
+    rp, rb = O.eval_poses_2d(variant, wl["grid"], wl["poses"], wl["beam_dir"], wl["sigma"], wl["R"],
+                             Delta=wl["Delta"], H=wl["H"])
+    assert rel_err(mb.cpu().numpy(), rb) <= TOL32
+    assert rel_err(mp.cpu().numpy(), rp) <= TOL32
+
+
+@pytest.mark.parametrize("exact", [True, False])
+def test_poses_voxels_small(ctx, exact):
+    print(f"[gpu] voxels exact={exact}", flush=True)
+    vox, lab = W.voxel_map(64, 64, 32, seed=9, n_boxes=12, n_pillars=8, block=16, unknown_frac=0.1)
+    poses = W.poses_in_free_space_3d(lab, 3, seed=9)
+    bd = W.beam_dirs_3d(8, 32)
+    prm = F.params(variant=F.FSMI_EXACT if exact else F.FSMI_APPROX, trunc_delta=6)
+    mp, mb = ctx.fsmi_eval_poses(prm, dev(vox), dev(poses), dev(bd), 2.0, 80.0, 1.0, want_beams=True)
+    torch.cuda.synchronize()
+    ctx.fsmi_sync()
+    rp, rb = O.eval_poses_3d(exact, vox, poses, bd, 2.0, 80.0, 1.0, Delta=6)
+    assert rel_err(mb.cpu().numpy(), rb) <= TOL32
+    assert rel_err(mp.cpu().numpy(), rp) <= TOL32
+
+
+def test_pose_outside_map_latches(ctx):
+    grid = np.full((16, 16), 0.3, np.float32)
+    poses = np.array([[4.5, 4.5, 1.0, 0.0], [40.0, 2.0, 1.0, 0.0]])
+    mp, _ = ctx.fsmi_eval_poses(F.params(), dev(grid), dev(poses), dev(W.beam_dirs_2d(8)), 1.0, 10.0)
+    torch.cuda.synchronize()
+    with pytest.raises(F.FsmiError):
+        ctx.fsmi_sync()
+    got = mp.cpu().numpy()
+    assert np.isfinite(got[0]) and np.isnan(got[1])
