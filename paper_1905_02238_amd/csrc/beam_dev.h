@@ -87,7 +87,11 @@ FSMI_DEV bool group_any(bool b, int* flag, int tid) {
   return w;
 }
 
-template <typename T> FSMI_DEV T tabs(T x) { return x < T(0) ? -x : x; }
+// |x| as the VALU source modifier (no compare/select).
+template <typename T> FSMI_DEV T tabs(T x) {
+  if constexpr (sizeof(T) == 8) return __builtin_fabs(x);
+  else return __builtin_fabsf(x);
+}
 FSMI_DEV int clampi(int x, int lo, int hi) { return x < lo ? lo : (x > hi ? hi : x); }
 
 template <typename T> FSMI_DEV T erf_t(T x);
@@ -111,9 +115,16 @@ template <> struct Acc<double> {
 };
 
 // erfc of a boundary at l, on the tail side of mu (c = 1/(sigma sqrt 2)).
+// FP32: the argument is pre-scaled by sqrt(log2 e) so that erfc_pos_l2 needs
+// no separate multiply for the base-2 exponent.
 template <typename T>
 FSMI_DEV T tail_E(double l, double mu, double c) {
-  return erfc_pos((T)(tabs(l - mu) * c));
+  if constexpr (sizeof(T) == 8) {
+    return erfc_pos(tabs(l - mu) * c);
+  } else {
+    constexpr double kSqrtL2E = 1.2011224087864498;   // sqrt(log2(e))
+    return erfc_pos_l2((float)(tabs(l - mu) * (c * kSqrtL2E)));
+  }
 }
 
 // ---------------------------------------------------------------------------

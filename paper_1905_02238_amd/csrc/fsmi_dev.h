@@ -84,6 +84,28 @@ FSMI_DEV float erfc_pos(float z) {
   return t * __builtin_amdgcn_exp2f(arg);
 }
 
+// The same function of x = z sqrt(log2 e): erfc(z) = t 2^(P2(t) - x^2), with
+// t = 1/(1 + x / (2 sqrt(log2 e))) and P2 = log2(e) P.
+FSMI_DEV float erfc_pos_l2(float x) {
+  constexpr float L2E = 1.4426950408889634f;
+  constexpr float c0 = -1.26551223f * L2E, c1 = 1.00002368f * L2E, c2 = 0.37409196f * L2E,
+                  c3 = 0.09678418f * L2E, c4 = -0.18628806f * L2E, c5 = 0.27886807f * L2E,
+                  c6 = -1.13520398f * L2E, c7 = 1.48851587f * L2E, c8 = -0.82215223f * L2E,
+                  c9 = 0.17087277f * L2E;
+  constexpr float kHalfInvSqrtL2E = 0.41627730557884884f;   // 1 / (2 sqrt(log2 e))
+  float t = __builtin_amdgcn_rcpf(fmaf(kHalfInvSqrtL2E, x, 1.0f));
+  float p = fmaf(t, c9, c8);
+  p = fmaf(t, p, c7);
+  p = fmaf(t, p, c6);
+  p = fmaf(t, p, c5);
+  p = fmaf(t, p, c4);
+  p = fmaf(t, p, c3);
+  p = fmaf(t, p, c2);
+  p = fmaf(t, p, c1);
+  p = fmaf(t, p, c0);
+  return t * __builtin_amdgcn_exp2f(fmaf(-x, x, p));
+}
+
 // FP64 complementary error function (device libm), used by the FP64 mode.
 FSMI_DEV double erfc_pos(double z) { return erfc(z); }
 
