@@ -171,10 +171,61 @@ fsmi_status fsmi_eval_poses(fsmi_ctx ctx, const fsmi_params* params, const fsmi_
                             const double* beam_dir, double sigma, double max_range, double w,
                             double* mi_pose, double* mi_beam);
 
+/* ---- a15..a17: learned surrogate, trained on FSMI's own labels ----
+   A small conv net predicts a pose's scan MI from the 128 x 128 patch of o
+   centred on the pose's cell (cells outside the map read 0.5): five 3x3 convs,
+   stride 2, padding 1, ReLU (1-32-64-64-128-128 channels), global average pool,
+   FC 128->256, ReLU, FC 256->1, 310465 parameters.  BF16 activations and
+   weights on the matrix cores with FP32 accumulation, FP32 master weights and
+   Adam moments.  Labels are standardised with fsmi_sur_fit_label_stats and the
+   loss is the batch-mean squared error.  Surrogate calls take 2D maps and 2D
+   poses ([n][4]); they enqueue on the stream of the context the net was created
+   with.  The network is not in the paper: it ranks candidate poses cheaply, and
+   fsmi_rank_poses always re-scores its top k with exact FSMI (Thm 1). */
+typedef struct fsmi_sur_s* fsmi_sur;
+int64_t fsmi_sur_num_params(void);
+/* Allocates parameters, optimiser state and activations for batches of up to
+   max_batch poses (<= 65536); Kaiming-uniform weights from a counter-based
+   generator seeded by `seed`, zero biases. */
+fsmi_status fsmi_sur_create(fsmi_ctx ctx, fsmi_sur* out, uint64_t seed, int32_t max_batch);
+void fsmi_sur_destroy(fsmi_sur net);
+/* Mean and standard deviation of n device FP64 labels (nats), kept in the net. */
+fsmi_status fsmi_sur_fit_label_stats(fsmi_sur net, int64_t n, const double* labels);
+fsmi_status fsmi_sur_get_label_stats(fsmi_sur net, double* host_mean_scale /* [2], host */);
+/* pred[n] (device FP32) = predicted MI in nats; any n (processed in batches). */
+fsmi_status fsmi_sur_forward(fsmi_sur net, const fsmi_map* map, int64_t n, const double* poses,
+                             float* pred);
+/* Forward and backward of one batch (n <= max_batch) against labels[n] (device
+   FP64, nats): gradients are kept in the net; *loss (device FP32, or NULL) gets
+   the standardised MSE.  Deterministic (fixed-order reductions). */
+fsmi_status fsmi_sur_backward(fsmi_sur net, const fsmi_map* map, int64_t n, const double* poses,
+                              const double* labels, float* loss);
+fsmi_status fsmi_sur_adam_step(fsmi_sur net, float lr, float beta1, float beta2, float eps);
+/* Device FP32 [fsmi_sur_num_params()] copies of the master weights / gradients. */
+fsmi_status fsmi_sur_get_params(fsmi_sur net, float* dst);
+fsmi_status fsmi_sur_set_params(fsmi_sur net, const float* src);
+fsmi_status fsmi_sur_get_grads(fsmi_sur net, float* dst);
+/* Checkpoint (host file): step, label statistics, weights, Adam moments. */
+fsmi_status fsmi_sur_save(fsmi_sur net, const char* path);
+fsmi_status fsmi_sur_load(fsmi_sur net, const char* path);
+/* Ranks n_poses 2D candidates by the surrogate, keeps the top k (ties by index),
+   and re-scores them with exact FSMI (params, beams, sigma, max_range as in
+   fsmi_eval_poses).  idx_out[k] (device int32): candidate indices in the
+   surrogate's order; mi_out[k] (device FP64): their exact scan MI; pred_out
+   (device FP32 [n_poses] or NULL): the surrogate's predictions. */
+fsmi_status fsmi_rank_poses(fsmi_ctx ctx, const fsmi_params* params, fsmi_sur net,
+                            const fsmi_map* map, int64_t n_poses, const double* poses,
+                            int64_t n_beams, const double* beam_dir, double sigma,
+                            double max_range, int32_t k, int32_t* idx_out, double* mi_out,
+                            float* pred_out);
+
 /* ---- diagnostics ----
    out[i] = the library's FP32 erfc at z[i] >= 0 (the function every Gaussian
    weight G_{k,j} is built from), so its error can be measured against FP64. */
 fsmi_status fsmi_probe_erfc(fsmi_ctx ctx, int64_t n, const float* z, float* out);
+/* D (device FP32 16x16, row-major) = A (BF16 16x32) * B (BF16 32x16) through one
+   matrix-core instruction, so its operand layout can be checked. */
+fsmi_status fsmi_probe_mfma(fsmi_ctx ctx, const void* A, const void* B, float* D);
 
 #ifdef __cplusplus
 }

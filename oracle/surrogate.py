@@ -1,0 +1,141 @@
+"""FP64 reference of the learned surrogate -- TEST INFRASTRUCTURE ONLY.
+
+Only the tests and the benchmark's baseline leg use this module.  It shares no
+code with the HIP kernels.  The network (not from the paper; it ranks candidate
+poses before exact FSMI re-scores the best ones):
+
+  patch 128 x 128 of o centred on the pose's cell, 0.5 outside the map
+  -> 5 x [3x3 conv, stride 2, zero padding 1, ReLU], channels 1-32-64-64-128-128
+  -> global average pool -> FC 128->256 -> ReLU -> FC 256->1.
+
+Parameters are one flat FP64 vector in the order
+W1 b1 W2 b2 ... W5 b5 F1 c1 F2 c2, conv weights [co][tap = 3 ky + kx][ci],
+F1 [256][128].  Loss: mean over the batch of (y - (label - mean)/scale)^2.
+
+`q` (identity unless given) is applied to every tensor a reduced-precision
+implementation stores between steps: the input patch, the conv weights, each
+post-ReLU activation and each masked input-gradient.  Passing a rounding
+function lets a test hold such an implementation to the same ReLU masks; the
+arithmetic between the stored tensors stays FP64.
+"""
+import numpy as np
+
+LAYERS = [(1, 32, 128), (32, 64, 64), (64, 64, 32), (64, 128, 16), (128, 128, 8)]
+FEAT, HID, PATCH = 128, 256, 128
+
+
+def layout():
+    """[(name, offset, shape)] of the flat parameter vector."""
+    out, o = [], 0
+    for l, (ci, co, _) in enumerate(LAYERS):
+        out.append((f"W{l + 1}", o, (co, 9, ci)))
+        o += co * 9 * ci
+        out.append((f"b{l + 1}", o, (co,)))
+        o += co
+    for name, shape in (("F1", (HID, FEAT)), ("c1", (HID,)), ("F2", (HID,)), ("c2", (1,))):
+        out.append((name, o, shape))
+        o += int(np.prod(shape))
+    return out
+
+
+NUM_PARAMS = sum(int(np.prod(s)) for _, _, s in layout())
+
+
+def unpack(flat):
+    flat = np.asarray(flat, np.float64)
+    return {n: flat[o:o + int(np.prod(s))].reshape(s) for n, o, s in layout()}
+
+
+def pack(d):
+    return np.concatenate([np.asarray(d[n], np.float64).reshape(-1) for n, _, _ in layout()])
+
+
+def patches(grid, poses):
+    """[B][128][128][1] patches; patch pixel (iy, ix) reads cell
+    (floor(x) - 64 + ix, floor(y) - 64 + iy), 0.5 outside the map."""
+    grid = np.asarray(grid, np.float64)
+    Y, X = grid.shape
+    out = np.full((len(poses), PATCH, PATCH, 1), 0.5)
+    for b, p in enumerate(poses):
+        cx0 = int(np.floor(p[0])) - PATCH // 2
+        cy0 = int(np.floor(p[1])) - PATCH // 2
+        ys = np.arange(cy0, cy0 + PATCH)
+        xs = np.arange(cx0, cx0 + PATCH)
+        vy = (ys >= 0) & (ys < Y)
+        vx = (xs >= 0) & (xs < X)
+        out[b][np.ix_(vy, vx)] = grid[np.ix_(ys[vy], xs[vx])][..., None]
+    return out
+
+
+def conv_fwd(x, W, b):
+    """x [B][H][H][ci], W [co][9][ci] -> pre-activation [B][H/2][H/2][co]
+    (3x3 taps, stride 2, zero padding 1)."""
+    B, H, _, ci = x.shape
+    Ho = H // 2
+    xp = np.zeros((B, H + 2, H + 2, ci))
+    xp[:, 1:-1, 1:-1] = x
+    out = np.zeros((B, Ho, Ho, W.shape[0])) + b
+    for tap in range(9):
+        ky, kx = divmod(tap, 3)
+        xs = xp[:, ky:ky + 2 * Ho:2, kx:kx + 2 * Ho:2, :]
+        out += np.einsum("bhwc,oc->bhwo", xs, W[:, tap, :])
+    return out
+
+
+def conv_bwd(x, W, dpre):
+    """Gradients of conv_fwd: (dx, dW, db)."""
+    B, H, _, ci = x.shape
+    Ho = H // 2
+    xp = np.zeros((B, H + 2, H + 2, ci))
+    xp[:, 1:-1, 1:-1] = x
+    dxp = np.zeros_like(xp)
+    dW = np.zeros_like(W)
+    for tap in range(9):
+        ky, kx = divmod(tap, 3)
+        xs = xp[:, ky:ky + 2 * Ho:2, kx:kx + 2 * Ho:2, :]
+        dW[:, tap, :] = np.einsum("bhwo,bhwc->oc", dpre, xs)
+        dxp[:, ky:ky + 2 * Ho:2, kx:kx + 2 * Ho:2, :] += np.einsum("bhwo,oc->bhwc", dpre, W[:, tap, :])
+    return dxp[:, 1:-1, 1:-1], dW, dpre.sum(axis=(0, 1, 2))
+
+
+def _ident(a):
+    return a
+
+
+def forward(flat, x, q=_ident):
+    """x: patches [B][128][128][1].  Returns (y [B], cache)."""
+    P = unpack(flat)
+    acts = [q(x)]
+    for l in range(5):
+        pre = conv_fwd(acts[-1], q(P[f"W{l + 1}"]), P[f"b{l + 1}"])
+        acts.append(q(np.maximum(pre, 0.0)))
+    g = acts[-1].mean(axis=(1, 2))                       # [B][128]
+    h = np.maximum(g @ P["F1"].T + P["c1"], 0.0)         # [B][256]
+    y = h @ P["F2"] + P["c2"][0]
+    return y, (acts, g, h)
+
+
+def loss_and_grads(flat, x, labels, mean=0.0, scale=1.0, q=_ident):
+    """Batch-mean squared error against standardised labels and its gradient."""
+    P = unpack(flat)
+    y, (acts, g, h) = forward(flat, x, q)
+    t = (np.asarray(labels, np.float64) - mean) / scale
+    n = len(y)
+    L = float(np.mean((y - t) ** 2))
+    dy = 2.0 * (y - t) / n
+    G = {}
+    G["F2"] = h.T @ dy
+    G["c2"] = np.array([dy.sum()])
+    dh = np.outer(dy, P["F2"]) * (h > 0)
+    G["F1"] = dh.T @ g
+    G["c1"] = dh.sum(0)
+    dg = dh @ P["F1"]                                    # [B][128]
+    a5 = acts[5]
+    d = np.repeat(np.repeat(dg[:, None, None, :], a5.shape[1], 1), a5.shape[2], 2) / (a5.shape[1] * a5.shape[2])
+    d = q(d * (a5 > 0))
+    for l in range(4, -1, -1):
+        dx, dW, db = conv_bwd(acts[l], q(P[f"W{l + 1}"]), d)
+        G[f"W{l + 1}"], G[f"b{l + 1}"] = dW, db
+        if l > 0:
+            d = q(dx * (acts[l] > 0))
+    return L, pack(G)

@@ -1,0 +1,904 @@
+// k_sur.hip -- the learned surrogate: a small conv net that predicts a pose's
+// mutual information from the occupancy patch around it, trained on labels the
+// exact FSMI path produces, and a ranking path whose top-k candidates are always
+// re-scored by exact FSMI.
+//
+// Network (per pose): 128 x 128 patch of o around the pose (cells outside the
+// map read 0.5) -> five 3x3 convolutions, stride 2, padding 1, ReLU
+// (1->32->64->64->128->128 channels; 128 -> 64 -> 32 -> 16 -> 8 -> 4 pixels) ->
+// global average pool -> FC 128->256 -> ReLU -> FC 256->1.  Labels are
+// standardised ((MI - mean)/scale); the loss is the batch-mean squared error.
+//
+// Layout: activations NHWC in BF16, conv weights [co][tap][ci] (and a copy
+// [tap][ci][co] for the input-gradient pass) in BF16, FP32 master weights,
+// FP32 gradients and Adam moments.  The convolutions are implicit GEMMs on
+// the gfx950 BF16 matrix cores (v_mfma_f32_16x16x32_bf16) with FP32
+// accumulation; the first layer gathers its input straight from the map.
+// Weight-gradient reductions are split over fixed pixel ranges and summed in a
+// fixed order, so training is deterministic.
+#include <math.h>
+#include <stdio.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "fsmi_dev.h"
+#include "fsmi_internal.h"
+
+namespace fsmi {
+
+typedef __bf16 bf16;
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------------------
+// Parameter layout (FP32 master, flat)
+// ---------------------------------------------------------------------------
+struct LayerDims { int cin, cout, hin; };
+constexpr LayerDims kL[5] = {{1, 32, 128}, {32, 64, 64}, {64, 64, 32}, {64, 128, 16}, {128, 128, 8}};
+constexpr int kPatch = 128, kFeat = 128, kHid = 256;
+
+constexpr int w_size(int l) { return kL[l].cout * 9 * kL[l].cin; }
+constexpr int w_off(int l) {  // FP32 master offset of conv l's weights
+  int o = 0;
+  for (int i = 0; i < l; ++i) o += w_size(i) + kL[i].cout;
+  return o;
+}
+constexpr int b_off(int l) { return w_off(l) + w_size(l); }
+constexpr int wbf_off(int l) {  // BF16 weight offset
+  int o = 0;
+  for (int i = 0; i < l; ++i) o += w_size(i);
+  return o;
+}
+constexpr int kWbfTotal = wbf_off(5);
+constexpr int kF1 = w_off(5);             // FC1 weights [256][128]
+constexpr int kC1 = kF1 + kHid * kFeat;   // FC1 bias [256]
+constexpr int kF2 = kC1 + kHid;           // FC2 weights [256]
+constexpr int kC2 = kF2 + kHid;           // FC2 bias
+constexpr int kNumParams = kC2 + 1;
+static_assert(kNumParams == 310465, "parameter count");
+
+int64_t sur_num_params() { return kNumParams; }
+
+// ---------------------------------------------------------------------------
+// MFMA fragment helpers (v_mfma_f32_16x16x32_bf16, wave64):
+//   A (16 x 32): lane l holds A[l % 16][8 (l / 16) + 0..7]
+//   B (32 x 16): lane l holds B[8 (l / 16) + 0..7][l % 16]
+//   D (16 x 16): lane l holds D[4 (l / 16) + 0..3][l % 16]
+// ---------------------------------------------------------------------------
+FSMI_DEV floatx4 mfma(bf16x8 a, bf16x8 b, floatx4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+FSMI_DEV bf16x8 load8(const bf16* p) { return *reinterpret_cast<const bf16x8*>(p); }
+FSMI_DEV bf16x8 zero8() {
+  bf16x8 z;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) z[q] = (bf16)0.0f;
+  return z;
+}
+
+// Input of the first layer: patch pixel (iy, ix) of pose b, 0 outside the
+// padded patch, the map's o (0.5 outside the map) inside.
+struct PatchSrc {
+  const float* map;
+  int64_t X, Y;
+  const double* poses;   // [n][4]
+  FSMI_DEV float at(int64_t b, int iy, int ix) const {
+    if (iy < 0 || iy >= kPatch || ix < 0 || ix >= kPatch) return 0.0f;
+    const int64_t cx = (int64_t)floor(poses[4 * b]) - kPatch / 2 + ix;
+    const int64_t cy = (int64_t)floor(poses[4 * b + 1]) - kPatch / 2 + iy;
+    if (cx < 0 || cx >= X || cy < 0 || cy >= Y) return 0.5f;
+    return map[cx + X * cy];
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Forward convolution: out[p][co] = ReLU(b[co] + sum_{tap,ci} W[co][tap][ci] in[p+tap][ci])
+// One wave = 16 output pixels x all COUT channels; 4 waves per workgroup.
+// ---------------------------------------------------------------------------
+template <int CIN, int COUT, int HIN, bool FIRST>
+__global__ __launch_bounds__(256) void k_conv_fwd(int64_t npix, const bf16* __restrict__ in,
+                                                  PatchSrc src, const bf16* __restrict__ W,
+                                                  const float* __restrict__ bias,
+                                                  bf16* __restrict__ out) {
+  constexpr int HOUT = HIN / 2, NT = COUT / 16;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t base = ((int64_t)blockIdx.x * 4 + wave) * 16;
+  if (base >= npix) return;
+  const int i = lane & 15, g = lane >> 4;
+  const int64_t p = base + i;
+  const int64_t b = p / (HOUT * HOUT);
+  const int oy = (int)((p / HOUT) % HOUT), ox = (int)(p % HOUT);
+  floatx4 acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+  if constexpr (FIRST) {
+    // K = 9 taps padded to 32; lane group g holds taps 8g .. 8g+7
+    bf16x8 a = zero8();
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int tap = 8 * g + q;
+      if (tap < 9) a[q] = (bf16)src.at(b, 2 * oy + tap / 3 - 1, 2 * ox + tap % 3 - 1);
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      bf16x8 w = zero8();
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int tap = 8 * g + q;
+        if (tap < 9) w[q] = W[(16 * t + i) * 9 + tap];
+      }
+      acc[t] = mfma(a, w, acc[t]);
+    }
+  } else {
+#pragma unroll 1
+    for (int tap = 0; tap < 9; ++tap) {
+      const int iy = 2 * oy + tap / 3 - 1, ix = 2 * ox + tap % 3 - 1;
+      const bool ok = iy >= 0 && iy < HIN && ix >= 0 && ix < HIN;
+      // the address stays inside the image even where the tap is padding
+      const bf16* ip = in + ((b * HIN + (ok ? iy : 0)) * HIN + (ok ? ix : 0)) * CIN;
+#pragma unroll
+      for (int c0 = 0; c0 < CIN; c0 += 32) {
+        const bf16x8 a = ok ? load8(ip + c0 + 8 * g) : zero8();
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          const bf16x8 w = load8(W + ((16 * t + i) * 9 + tap) * CIN + c0 + 8 * g);
+          acc[t] = mfma(a, w, acc[t]);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int co = 16 * t + i;
+    const float bv = bias[co];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t pr = base + 4 * g + r;
+      const float v = acc[t][r] + bv;
+      out[pr * COUT + co] = (bf16)(v > 0.0f ? v : 0.0f);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Input-gradient pass: d_in[p][ci] = [act_in[p][ci] > 0] *
+//   sum_{tap, co} W[co][tap][ci] d_out[(p - tap)/2][co], only where p + 1 - tap
+//   is even in both axes and inside the output grid.  Wt is [tap][ci][co].
+// One wave = 16 input pixels x all CIN channels.
+// ---------------------------------------------------------------------------
+template <int CIN, int COUT, int HIN>
+__global__ __launch_bounds__(256) void k_conv_dgrad(int64_t npix_in, const bf16* __restrict__ dout,
+                                                    const bf16* __restrict__ Wt,
+                                                    const bf16* __restrict__ act_in,
+                                                    bf16* __restrict__ din) {
+  constexpr int HOUT = HIN / 2, NT = CIN / 16;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t base = ((int64_t)blockIdx.x * 4 + wave) * 16;
+  if (base >= npix_in) return;
+  const int i = lane & 15, g = lane >> 4;
+  const int64_t p = base + i;
+  const int64_t b = p / (HIN * HIN);
+  const int iy = (int)((p / HIN) % HIN), ix = (int)(p % HIN);
+  floatx4 acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 1
+  for (int tap = 0; tap < 9; ++tap) {
+    const int ky = tap / 3, kx = tap % 3;
+    const int ty = iy + 1 - ky, tx = ix + 1 - kx;
+    const bool ok = ty >= 0 && tx >= 0 && (ty & 1) == 0 && (tx & 1) == 0 && (ty >> 1) < HOUT &&
+                    (tx >> 1) < HOUT;
+    const bf16* dp = dout + ((b * HOUT + (ok ? ty >> 1 : 0)) * HOUT + (ok ? tx >> 1 : 0)) * COUT;
+#pragma unroll
+    for (int c0 = 0; c0 < COUT; c0 += 32) {
+      const bf16x8 a = ok ? load8(dp + c0 + 8 * g) : zero8();
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const bf16x8 w = load8(Wt + (tap * CIN + 16 * t + i) * COUT + c0 + 8 * g);
+        acc[t] = mfma(a, w, acc[t]);
+      }
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int ci = 16 * t + i;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t pr = base + 4 * g + r;
+      const float m = (float)act_in[pr * CIN + ci] > 0.0f ? 1.0f : 0.0f;
+      din[pr * CIN + ci] = (bf16)(acc[t][r] * m);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Weight-gradient pass: partial[s][co][col] = sum over pixels of split s of
+//   d_out[p][co] * B[p][col], col = tap * CIN + ci (the shifted input) or, in
+//   the extra column block, 1 for the bias.  One wave = a 16 x 16 tile.
+// ---------------------------------------------------------------------------
+template <int CIN, int COUT, int HIN, bool FIRST>
+__global__ __launch_bounds__(64) void k_conv_wgrad(int64_t npix_out, int chunk,
+                                                   const bf16* __restrict__ dout,
+                                                   const bf16* __restrict__ in, PatchSrc src,
+                                                   float* __restrict__ part) {
+  constexpr int HOUT = HIN / 2;
+  constexpr int NCOL = FIRST ? 16 : 9 * CIN + 16;
+  const int lane = threadIdx.x;
+  const int i = lane & 15, g = lane >> 4;
+  const int co_tile = blockIdx.x, col_tile = blockIdx.y, s = blockIdx.z;
+  const int co = 16 * co_tile + i;         // A row held by this lane
+  const int col = 16 * col_tile + i;       // B column held by this lane
+  int tap = 0, ci = 0;
+  bool is_bias = false, is_pad = false;
+  if constexpr (FIRST) {
+    tap = col;
+    is_bias = col == 9;
+    is_pad = col > 9;
+  } else {
+    if (col < 9 * CIN) {
+      tap = col / CIN;
+      ci = col % CIN;
+    } else {
+      is_bias = col == 9 * CIN;
+      is_pad = !is_bias;
+    }
+  }
+  const int ky = tap / 3, kx = tap % 3;
+  floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+  const int64_t p0 = (int64_t)s * chunk;
+  const int64_t p1 = min<int64_t>(p0 + chunk, npix_out);
+  for (int64_t k0 = p0; k0 < p1; k0 += 32) {
+    bf16x8 a, bb;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int64_t p = k0 + 8 * g + q;
+      const bool in_range = p < p1;
+      a[q] = in_range ? dout[(in_range ? p : p0) * COUT + co] : (bf16)0.0f;
+      float v = 0.0f;
+      if (in_range && !is_pad) {
+        if (is_bias) {
+          v = 1.0f;
+        } else {
+          const int64_t b = p / (HOUT * HOUT);
+          const int oy = (int)((p / HOUT) % HOUT), ox = (int)(p % HOUT);
+          const int iy = 2 * oy + ky - 1, ix = 2 * ox + kx - 1;
+          if constexpr (FIRST) {
+            v = (float)(bf16)src.at(b, iy, ix);
+          } else {
+            if (iy >= 0 && iy < HIN && ix >= 0 && ix < HIN)
+              v = (float)in[((b * HIN + iy) * HIN + ix) * CIN + ci];
+          }
+        }
+      }
+      bb[q] = (bf16)v;
+    }
+    acc = mfma(a, bb, acc);
+  }
+  // D[4g + r][i]: row co_tile*16 + 4g + r, column col_tile*16 + i
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int row = 16 * co_tile + 4 * g + r;
+    part[((int64_t)s * COUT + row) * NCOL + 16 * col_tile + i] = acc[r];
+  }
+}
+
+// grad[W(co, tap, ci)] and grad[b(co)] = sum_s partial[s][co][col], in split order.
+template <int CIN, int COUT, bool FIRST>
+__global__ void k_wgrad_reduce(const float* __restrict__ part, int splits, float* __restrict__ gW,
+                               float* __restrict__ gb) {
+  constexpr int NCOL = FIRST ? 16 : 9 * CIN + 16;
+  constexpr int NW = COUT * 9 * CIN;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < NW) {
+    const int co = t / (9 * CIN), rest = t % (9 * CIN);   // rest = tap * CIN + ci
+    float s = 0.0f;
+    for (int k = 0; k < splits; ++k) s += part[((int64_t)k * COUT + co) * NCOL + rest];
+    gW[t] = s;
+  } else if (t < NW + COUT) {
+    const int co = t - NW;
+    const int bc = FIRST ? 9 : 9 * CIN;
+    float s = 0.0f;
+    for (int k = 0; k < splits; ++k) s += part[((int64_t)k * COUT + co) * NCOL + bc];
+    gb[co] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Head: global average pool, FC 128->256, ReLU, FC 256->1 (FP32 VALU).
+// One workgroup (256 threads) per pose.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_head_fwd(int64_t n, const bf16* __restrict__ act5,
+                                                  const float* __restrict__ P, float* __restrict__ gsave,
+                                                  float* __restrict__ hsave, float* __restrict__ ypred) {
+  __shared__ float g[kFeat];
+  __shared__ float red[4];
+  const int t = threadIdx.x;
+  for (int64_t b = blockIdx.x; b < n; b += gridDim.x) {
+    if (t < kFeat) {
+      float s = 0.0f;
+      for (int q = 0; q < 16; ++q) s += (float)act5[(b * 16 + q) * kFeat + t];
+      g[t] = s * (1.0f / 16.0f);
+      if (gsave) gsave[b * kFeat + t] = g[t];
+    }
+    __syncthreads();
+    float h = P[kC1 + t];
+    const float* w = P + kF1 + t * kFeat;
+    for (int c = 0; c < kFeat; ++c) h = fmaf(w[c], g[c], h);
+    h = h > 0.0f ? h : 0.0f;
+    if (hsave) hsave[b * kHid + t] = h;
+    float y = P[kF2 + t] * h;
+    y = wave_sum(y);
+    if ((t & 63) == 0) red[t >> 6] = y;
+    __syncthreads();
+    if (t == 0) ypred[b] = ((red[0] + red[1]) + (red[2] + red[3])) + P[kC2];
+    __syncthreads();
+  }
+}
+
+// Head backward for one pose: dy = 2 (y - target) / n; dh = dy F2 [h > 0];
+// dg = F1^T dh; d_act5[p][c] = dg[c] / 16 [act5 > 0].
+__global__ __launch_bounds__(256) void k_head_bwd(int64_t n, const float* __restrict__ ypred,
+                                                  const double* __restrict__ labels,
+                                                  const double* __restrict__ stats,
+                                                  const float* __restrict__ P,
+                                                  const float* __restrict__ hsave,
+                                                  const bf16* __restrict__ act5,
+                                                  float* __restrict__ dysave,
+                                                  float* __restrict__ dhsave,
+                                                  bf16* __restrict__ dact5) {
+  __shared__ float dh[kHid];
+  const int t = threadIdx.x;
+  for (int64_t b = blockIdx.x; b < n; b += gridDim.x) {
+    const float target = (float)((labels[b] - stats[0]) / stats[1]);
+    const float dy = 2.0f * (ypred[b] - target) / (float)n;
+    if (t == 0) dysave[b] = dy;
+    const float h = hsave[b * kHid + t];
+    const float d = h > 0.0f ? dy * P[kF2 + t] : 0.0f;
+    dh[t] = d;
+    dhsave[b * kHid + t] = d;
+    __syncthreads();
+    if (t < kFeat) {
+      float s = 0.0f;
+      for (int k = 0; k < kHid; ++k) s = fmaf(P[kF1 + k * kFeat + t], dh[k], s);
+      const float gs = s * (1.0f / 16.0f);
+      for (int q = 0; q < 16; ++q) {
+        const int64_t idx = (b * 16 + q) * kFeat + t;
+        dact5[idx] = (bf16)((float)act5[idx] > 0.0f ? gs : 0.0f);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Head weight gradients, each a fixed-order sum over the batch; also the loss.
+__global__ void k_head_wgrad(int64_t n, const float* __restrict__ gsave,
+                             const float* __restrict__ hsave, const float* __restrict__ dysave,
+                             const float* __restrict__ dhsave, const float* __restrict__ ypred,
+                             const double* __restrict__ labels, const double* __restrict__ stats,
+                             float* __restrict__ G, float* __restrict__ loss) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < kHid * kFeat) {   // dF1[k][c] = sum_b dh[b][k] g[b][c]
+    const int k = t / kFeat, c = t % kFeat;
+    float s = 0.0f;
+    for (int64_t b = 0; b < n; ++b) s = fmaf(dhsave[b * kHid + k], gsave[b * kFeat + c], s);
+    G[kF1 + t] = s;
+  } else if (t < kHid * kFeat + kHid) {   // dc1, dF2
+    const int k = t - kHid * kFeat;
+    float s1 = 0.0f, s2 = 0.0f;
+    for (int64_t b = 0; b < n; ++b) {
+      s1 += dhsave[b * kHid + k];
+      s2 = fmaf(dysave[b], hsave[b * kHid + k], s2);
+    }
+    G[kC1 + k] = s1;
+    G[kF2 + k] = s2;
+  } else if (t == kHid * kFeat + kHid) {   // dc2 and the loss
+    float s = 0.0f, L = 0.0f;
+    for (int64_t b = 0; b < n; ++b) {
+      s += dysave[b];
+      const float target = (float)((labels[b] - stats[0]) / stats[1]);
+      const float e = ypred[b] - target;
+      L = fmaf(e, e, L);
+    }
+    G[kC2] = s;
+    if (loss) *loss = L / (float)n;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Parameters: init, BF16 copies, Adam
+// ---------------------------------------------------------------------------
+FSMI_DEV uint64_t splitmix64(uint64_t x) {
+  x += 0x9E3779B97F4A7C15ull;
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+  return x ^ (x >> 31);
+}
+
+// Kaiming-uniform weights U(-sqrt(6/fan_in), sqrt(6/fan_in)) (sqrt(3/fan_in) for the
+// output layer), zero biases, zero Adam moments.  Draws: splitmix64(seed ^ index).
+__global__ void k_sur_init(uint64_t seed, float* P, float* M, float* V) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= kNumParams) return;
+  float bound = 0.0f;
+#pragma unroll
+  for (int l = 0; l < 5; ++l)
+    if (t >= w_off(l) && t < b_off(l)) bound = sqrtf(6.0f / (9.0f * kL[l].cin));
+  if (t >= kF1 && t < kC1) bound = sqrtf(6.0f / kFeat);
+  if (t >= kF2 && t < kC2) bound = sqrtf(3.0f / kHid);
+  const uint64_t r = splitmix64(seed ^ ((uint64_t)t * 0x632BE59BD9B4E019ull));
+  const float u = (float)(r >> 40) * (1.0f / 16777216.0f);   // [0, 1)
+  P[t] = bound * (2.0f * u - 1.0f);
+  M[t] = 0.0f;
+  V[t] = 0.0f;
+}
+
+__global__ void k_sur_cast(const float* __restrict__ P, bf16* __restrict__ Wbf,
+                           bf16* __restrict__ Wt) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= kWbfTotal) return;
+  int l = 0;
+  while (l < 4 && t >= wbf_off(l + 1)) ++l;
+  const int e = t - wbf_off(l);
+  const int cin = kL[l].cin, cout = kL[l].cout;
+  const int co = e / (9 * cin), rest = e % (9 * cin), tap = rest / cin, ci = rest % cin;
+  const bf16 v = (bf16)P[w_off(l) + e];
+  Wbf[t] = v;
+  Wt[wbf_off(l) + (tap * cin + ci) * cout + co] = v;
+}
+
+__global__ void k_adam(float* P, const float* G, float* M, float* V, float lr, float b1, float b2,
+                       float eps, float c1, float c2) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= kNumParams) return;
+  const float g = G[t];
+  const float m = b1 * M[t] + (1.0f - b1) * g;
+  const float v = b2 * V[t] + (1.0f - b2) * g * g;
+  M[t] = m;
+  V[t] = v;
+  P[t] -= lr * (m / c1) / (sqrtf(v / c2) + eps);
+}
+
+// Label statistics: mean and standard deviation of n FP64 labels (two-pass, one
+// workgroup, fixed order).
+__global__ void k_label_stats(int64_t n, const double* labels, double* stats) {
+  __shared__ double red[16];
+  const int t = threadIdx.x;
+  double s = 0.0;
+  for (int64_t i = t; i < n; i += blockDim.x) s += labels[i];
+  s = wave_sum(s);
+  if ((t & 63) == 0) red[t >> 6] = s;
+  __syncthreads();
+  double mean = 0.0;
+  for (int k = 0; k < (int)(blockDim.x >> 6); ++k) mean += red[k];
+  mean /= (double)n;
+  __syncthreads();
+  double q = 0.0;
+  for (int64_t i = t; i < n; i += blockDim.x) q += (labels[i] - mean) * (labels[i] - mean);
+  q = wave_sum(q);
+  if ((t & 63) == 0) red[t >> 6] = q;
+  __syncthreads();
+  if (t == 0) {
+    double v = 0.0;
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) v += red[k];
+    v = sqrt(v / (double)n);
+    stats[0] = mean;
+    stats[1] = v > 0.0 ? v : 1.0;
+  }
+}
+
+// Predictions in nats: y * scale + mean.
+__global__ void k_destandardise(int64_t n, const float* y, const double* stats, float* out) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (float)((double)y[i] * stats[1] + stats[0]);
+}
+
+// One 16x16x32 product through the matrix core, A and B row-major (diagnostic).
+__global__ void k_mfma_probe(const bf16* A, const bf16* B, float* D) {
+  const int l = threadIdx.x, i = l & 15, g = l >> 4;
+  bf16x8 a, b;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    a[q] = A[i * 32 + 8 * g + q];
+    b[q] = B[(8 * g + q) * 16 + i];
+  }
+  floatx4 d = mfma(a, b, floatx4{0.f, 0.f, 0.f, 0.f});
+#pragma unroll
+  for (int r = 0; r < 4; ++r) D[(4 * g + r) * 16 + i] = d[r];
+}
+
+// ---------------------------------------------------------------------------
+// Top-k: bitonic sort of (key, index) pairs, keys descending, ties by index.
+// ---------------------------------------------------------------------------
+__global__ void k_topk_fill(int64_t n, int64_t npow2, const float* pred, float* key, int32_t* idx) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= npow2) return;
+  const float v = i < n ? pred[i] : -INFINITY;
+  key[i] = (v == v) ? v : -INFINITY;   // NaN sorts last
+  idx[i] = (int32_t)i;
+}
+
+__global__ void k_bitonic_step(int64_t npow2, int64_t j, int64_t k, float* key, int32_t* idx) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= npow2) return;
+  const int64_t p = i ^ j;
+  if (p <= i) return;
+  const float a = key[i], b = key[p];
+  const int32_t ia = idx[i], ib = idx[p];
+  // "a before b" in descending order with ties by ascending index
+  const bool a_first = (a > b) || (a == b && ia < ib);
+  const bool up = (i & k) == 0;
+  if (up != a_first) {
+    key[i] = b;
+    key[p] = a;
+    idx[i] = ib;
+    idx[p] = ia;
+  }
+}
+
+__global__ void k_gather_poses(int k, const int32_t* idx, const double* poses, double* out,
+                               int32_t* idx_out) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= k) return;
+  const int32_t j = idx[t];
+  for (int q = 0; q < 4; ++q) out[4 * t + q] = poses[4 * (int64_t)j + q];
+  if (idx_out) idx_out[t] = j;
+}
+
+}  // namespace fsmi
+
+// ===========================================================================
+// Host side
+// ===========================================================================
+struct fsmi_sur_s {
+  fsmi_ctx ctx = nullptr;
+  int max_batch = 0;
+  int step = 0;
+  float* P = nullptr;       // master weights [kNumParams]
+  float* G = nullptr;       // gradients
+  float* M = nullptr;       // Adam first moment
+  float* V = nullptr;       // Adam second moment
+  fsmi::bf16* Wbf = nullptr;
+  fsmi::bf16* Wt = nullptr;
+  double* stats = nullptr;  // label mean, scale
+  fsmi::bf16* act[6] = {};  // act[1..5]
+  fsmi::bf16* dact[6] = {}; // gradients of act[1..5]
+  float* gsave = nullptr;
+  float* hsave = nullptr;
+  float* dysave = nullptr;
+  float* dhsave = nullptr;
+  float* ypred = nullptr;
+  float* part = nullptr;    // weight-gradient partials
+  size_t part_floats = 0;
+  float* loss = nullptr;
+};
+
+namespace fsmi {
+
+static constexpr int kSplitChunk = 4096;   // pixels per weight-gradient split
+
+static size_t act_elems(int l, int B) {   // elements of act[l] (output of conv l-1... l = 1..5)
+  const int h = kL[l - 1].hin / 2;
+  return (size_t)B * h * h * kL[l - 1].cout;
+}
+
+static hipError_t sur_alloc(fsmi_sur net) {
+  hipError_t e;
+#define ALLOC(ptr, bytes)                                  \
+  do {                                                     \
+    e = hipMalloc((void**)&(ptr), (bytes));                \
+    if (e != hipSuccess) return e;                         \
+  } while (0)
+  ALLOC(net->P, sizeof(float) * kNumParams);
+  ALLOC(net->G, sizeof(float) * kNumParams);
+  ALLOC(net->M, sizeof(float) * kNumParams);
+  ALLOC(net->V, sizeof(float) * kNumParams);
+  ALLOC(net->Wbf, sizeof(bf16) * kWbfTotal);
+  ALLOC(net->Wt, sizeof(bf16) * kWbfTotal);
+  ALLOC(net->stats, 16 * sizeof(double));
+  const int B = net->max_batch;
+  for (int l = 1; l <= 5; ++l) {
+    ALLOC(net->act[l], sizeof(bf16) * act_elems(l, B));
+    ALLOC(net->dact[l], sizeof(bf16) * act_elems(l, B));
+  }
+  ALLOC(net->gsave, sizeof(float) * (size_t)B * kFeat);
+  ALLOC(net->hsave, sizeof(float) * (size_t)B * kHid);
+  ALLOC(net->dysave, sizeof(float) * (size_t)B);
+  ALLOC(net->dhsave, sizeof(float) * (size_t)B * kHid);
+  ALLOC(net->ypred, sizeof(float) * (size_t)B);
+  size_t mx = 0;
+  for (int l = 0; l < 5; ++l) {
+    const int hout = kL[l].hin / 2;
+    const size_t npix = (size_t)B * hout * hout;
+    const size_t splits = (npix + kSplitChunk - 1) / kSplitChunk;
+    const size_t ncol = l == 0 ? 16 : 9 * (size_t)kL[l].cin + 16;
+    mx = std::max(mx, splits * kL[l].cout * ncol);
+  }
+  net->part_floats = mx;
+  ALLOC(net->part, sizeof(float) * mx);
+  ALLOC(net->loss, sizeof(float) * 4);
+#undef ALLOC
+  return hipSuccess;
+}
+
+static void sur_free(fsmi_sur net) {
+  void* ps[] = {net->P, net->G, net->M, net->V, net->Wbf, net->Wt, net->stats, net->gsave,
+                net->hsave, net->dysave, net->dhsave, net->ypred, net->part, net->loss};
+  for (void* p : ps)
+    if (p) (void)hipFree(p);
+  for (int l = 1; l <= 5; ++l) {
+    if (net->act[l]) (void)hipFree(net->act[l]);
+    if (net->dact[l]) (void)hipFree(net->dact[l]);
+  }
+}
+
+static hipError_t cast_weights(fsmi_sur net) {
+  hipLaunchKernelGGL(k_sur_cast, dim3((kWbfTotal + 255) / 256), dim3(256), 0, net->ctx->stream,
+                     net->P, net->Wbf, net->Wt);
+  return hipGetLastError();
+}
+
+template <int L, bool FIRST>
+static void conv_fwd(fsmi_sur net, int64_t nb, PatchSrc src) {
+  constexpr LayerDims d = kL[L];
+  const int64_t npix = nb * (d.hin / 2) * (d.hin / 2);
+  const bf16* in = FIRST ? nullptr : net->act[L];
+  const int64_t blocks = (npix + 63) / 64;
+  hipLaunchKernelGGL((k_conv_fwd<d.cin, d.cout, d.hin, FIRST>), dim3((unsigned)blocks), dim3(256), 0,
+                     net->ctx->stream, npix, in, src, net->Wbf + wbf_off(L), net->P + b_off(L),
+                     net->act[L + 1]);
+}
+
+// Forward of nb (<= max_batch) poses; predictions (standardised) in ypred.
+static hipError_t sur_fwd_batch(fsmi_sur net, int64_t nb, PatchSrc src, bool save) {
+  conv_fwd<0, true>(net, nb, src);
+  conv_fwd<1, false>(net, nb, src);
+  conv_fwd<2, false>(net, nb, src);
+  conv_fwd<3, false>(net, nb, src);
+  conv_fwd<4, false>(net, nb, src);
+  const int grid = (int)std::min<int64_t>(nb, 65535);
+  hipLaunchKernelGGL(k_head_fwd, dim3(grid), dim3(256), 0, net->ctx->stream, nb, net->act[5], net->P,
+                     save ? net->gsave : nullptr, save ? net->hsave : nullptr, net->ypred);
+  return hipGetLastError();
+}
+
+template <int L>
+static void conv_dgrad(fsmi_sur net, int64_t nb) {
+  constexpr LayerDims d = kL[L];
+  const int64_t npix_in = nb * d.hin * d.hin;
+  hipLaunchKernelGGL((k_conv_dgrad<d.cin, d.cout, d.hin>), dim3((unsigned)((npix_in + 63) / 64)),
+                     dim3(256), 0, net->ctx->stream, npix_in, net->dact[L + 1], net->Wt + wbf_off(L),
+                     net->act[L], net->dact[L]);
+}
+
+template <int L, bool FIRST>
+static void conv_wgrad(fsmi_sur net, int64_t nb, PatchSrc src) {
+  constexpr LayerDims d = kL[L];
+  const int64_t npix = nb * (d.hin / 2) * (d.hin / 2);
+  const int splits = (int)((npix + kSplitChunk - 1) / kSplitChunk);
+  constexpr int ncol = FIRST ? 16 : 9 * d.cin + 16;
+  dim3 grid(d.cout / 16, ncol / 16, splits);
+  hipLaunchKernelGGL((k_conv_wgrad<d.cin, d.cout, d.hin, FIRST>), grid, dim3(64), 0, net->ctx->stream,
+                     npix, kSplitChunk, net->dact[L + 1], FIRST ? nullptr : net->act[L], src,
+                     net->part);
+  const int nt = d.cout * 9 * d.cin + d.cout;
+  hipLaunchKernelGGL((k_wgrad_reduce<d.cin, d.cout, FIRST>), dim3((nt + 255) / 256), dim3(256), 0,
+                     net->ctx->stream, net->part, splits, net->G + w_off(L), net->G + b_off(L));
+}
+
+}  // namespace fsmi
+
+using namespace fsmi;
+
+extern "C" {
+
+int64_t fsmi_sur_num_params(void) { return kNumParams; }
+
+fsmi_status fsmi_sur_create(fsmi_ctx ctx, fsmi_sur* out, uint64_t seed, int32_t max_batch) {
+  if (!ctx || !out || max_batch <= 0 || max_batch > 65536) return FSMI_E_INVAL;
+  *out = nullptr;
+  (void)hipSetDevice(ctx->device);
+  fsmi_sur net = new fsmi_sur_s();
+  net->ctx = ctx;
+  net->max_batch = max_batch;
+  if (sur_alloc(net) != hipSuccess) {
+    sur_free(net);
+    delete net;
+    return FSMI_E_NOMEM;
+  }
+  hipLaunchKernelGGL(k_sur_init, dim3((kNumParams + 255) / 256), dim3(256), 0, ctx->stream, seed,
+                     net->P, net->M, net->V);
+  const double st[2] = {0.0, 1.0};
+  (void)hipMemcpy(net->stats, st, sizeof(st), hipMemcpyHostToDevice);
+  if (cast_weights(net) != hipSuccess || hipStreamSynchronize(ctx->stream) != hipSuccess) {
+    sur_free(net);
+    delete net;
+    return FSMI_E_DEVICE;
+  }
+  *out = net;
+  return FSMI_OK;
+}
+
+void fsmi_sur_destroy(fsmi_sur net) {
+  if (!net) return;
+  (void)hipStreamSynchronize(net->ctx->stream);
+  sur_free(net);
+  delete net;
+}
+
+fsmi_status fsmi_sur_fit_label_stats(fsmi_sur net, int64_t n, const double* labels) {
+  if (!net || n <= 0 || !labels) return FSMI_E_INVAL;
+  hipLaunchKernelGGL(k_label_stats, dim3(1), dim3(1024), 0, net->ctx->stream, n, labels, net->stats);
+  return hipGetLastError() == hipSuccess ? FSMI_OK : FSMI_E_DEVICE;
+}
+
+static bool sur_map_ok(fsmi_sur net, const fsmi_map* map) {
+  return net && map && map->occ && map->ndim == 2 && map->dims[0] > 0 && map->dims[1] > 0;
+}
+
+fsmi_status fsmi_sur_forward(fsmi_sur net, const fsmi_map* map, int64_t n, const double* poses,
+                             float* pred) {
+  if (!sur_map_ok(net, map) || n < 0 || (n > 0 && (!poses || !pred))) return FSMI_E_INVAL;
+  (void)hipSetDevice(net->ctx->device);
+  for (int64_t s = 0; s < n; s += net->max_batch) {
+    const int64_t nb = std::min<int64_t>(net->max_batch, n - s);
+    PatchSrc src{map->occ, map->dims[0], map->dims[1], poses + 4 * s};
+    if (sur_fwd_batch(net, nb, src, false) != hipSuccess) return FSMI_E_DEVICE;
+    hipLaunchKernelGGL(k_destandardise, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0,
+                       net->ctx->stream, nb, net->ypred, net->stats, pred + s);
+  }
+  return hipGetLastError() == hipSuccess ? FSMI_OK : FSMI_E_DEVICE;
+}
+
+fsmi_status fsmi_sur_backward(fsmi_sur net, const fsmi_map* map, int64_t n, const double* poses,
+                              const double* labels, float* loss) {
+  if (!sur_map_ok(net, map) || n <= 0 || n > net->max_batch || !poses || !labels)
+    return FSMI_E_INVAL;
+  (void)hipSetDevice(net->ctx->device);
+  PatchSrc src{map->occ, map->dims[0], map->dims[1], poses};
+  if (sur_fwd_batch(net, n, src, true) != hipSuccess) return FSMI_E_DEVICE;
+  hipStream_t st = net->ctx->stream;
+  const int grid = (int)std::min<int64_t>(n, 65535);
+  hipLaunchKernelGGL(k_head_bwd, dim3(grid), dim3(256), 0, st, n, net->ypred, labels, net->stats,
+                     net->P, net->hsave, net->act[5], net->dysave, net->dhsave, net->dact[5]);
+  const int nt = kHid * kFeat + kHid + 1;
+  hipLaunchKernelGGL(k_head_wgrad, dim3((nt + 255) / 256), dim3(256), 0, st, n, net->gsave,
+                     net->hsave, net->dysave, net->dhsave, net->ypred, labels, net->stats, net->G,
+                     loss ? loss : net->loss);
+  conv_wgrad<4, false>(net, n, src);
+  conv_dgrad<4>(net, n);
+  conv_wgrad<3, false>(net, n, src);
+  conv_dgrad<3>(net, n);
+  conv_wgrad<2, false>(net, n, src);
+  conv_dgrad<2>(net, n);
+  conv_wgrad<1, false>(net, n, src);
+  conv_dgrad<1>(net, n);
+  conv_wgrad<0, true>(net, n, src);
+  return hipGetLastError() == hipSuccess ? FSMI_OK : FSMI_E_DEVICE;
+}
+
+fsmi_status fsmi_sur_adam_step(fsmi_sur net, float lr, float b1, float b2, float eps) {
+  if (!net || !(lr > 0.0f) || !(b1 >= 0.0f && b1 < 1.0f) || !(b2 >= 0.0f && b2 < 1.0f) || !(eps > 0.0f))
+    return FSMI_E_INVAL;
+  net->step += 1;
+  const float c1 = 1.0f - powf(b1, (float)net->step), c2 = 1.0f - powf(b2, (float)net->step);
+  hipLaunchKernelGGL(k_adam, dim3((kNumParams + 255) / 256), dim3(256), 0, net->ctx->stream, net->P,
+                     net->G, net->M, net->V, lr, b1, b2, eps, c1, c2);
+  return cast_weights(net) == hipSuccess ? FSMI_OK : FSMI_E_DEVICE;
+}
+
+fsmi_status fsmi_sur_get_params(fsmi_sur net, float* dst) {
+  if (!net || !dst) return FSMI_E_INVAL;
+  return hipMemcpyAsync(dst, net->P, sizeof(float) * kNumParams, hipMemcpyDeviceToDevice,
+                        net->ctx->stream) == hipSuccess ? FSMI_OK : FSMI_E_DEVICE;
+}
+
+fsmi_status fsmi_sur_set_params(fsmi_sur net, const float* src) {
+  if (!net || !src) return FSMI_E_INVAL;
+  if (hipMemcpyAsync(net->P, src, sizeof(float) * kNumParams, hipMemcpyDeviceToDevice,
+                     net->ctx->stream) != hipSuccess)
+    return FSMI_E_DEVICE;
+  return cast_weights(net) == hipSuccess ? FSMI_OK : FSMI_E_DEVICE;
+}
+
+fsmi_status fsmi_sur_get_grads(fsmi_sur net, float* dst) {
+  if (!net || !dst) return FSMI_E_INVAL;
+  return hipMemcpyAsync(dst, net->G, sizeof(float) * kNumParams, hipMemcpyDeviceToDevice,
+                        net->ctx->stream) == hipSuccess ? FSMI_OK : FSMI_E_DEVICE;
+}
+
+fsmi_status fsmi_sur_get_label_stats(fsmi_sur net, double* host_mean_scale) {
+  if (!net || !host_mean_scale) return FSMI_E_INVAL;
+  return hipMemcpy(host_mean_scale, net->stats, 2 * sizeof(double), hipMemcpyDeviceToHost) ==
+                 hipSuccess ? FSMI_OK : FSMI_E_DEVICE;
+}
+
+// Checkpoint: magic, step, label stats, master weights, Adam moments (all host order).
+fsmi_status fsmi_sur_save(fsmi_sur net, const char* path) {
+  if (!net || !path) return FSMI_E_INVAL;
+  if (hipStreamSynchronize(net->ctx->stream) != hipSuccess) return FSMI_E_DEVICE;
+  std::vector<float> buf(3 * (size_t)kNumParams);
+  double st[2];
+  if (hipMemcpy(buf.data(), net->P, sizeof(float) * kNumParams, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(buf.data() + kNumParams, net->M, sizeof(float) * kNumParams, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(buf.data() + 2 * kNumParams, net->V, sizeof(float) * kNumParams, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(st, net->stats, sizeof(st), hipMemcpyDeviceToHost) != hipSuccess)
+    return FSMI_E_DEVICE;
+  FILE* f = fopen(path, "wb");
+  if (!f) return FSMI_E_INVAL;
+  const uint32_t hdr[4] = {0x46534D49u, 1u, (uint32_t)net->step, (uint32_t)kNumParams};
+  bool ok = fwrite(hdr, sizeof(hdr), 1, f) == 1 && fwrite(st, sizeof(st), 1, f) == 1 &&
+            fwrite(buf.data(), sizeof(float), buf.size(), f) == buf.size();
+  ok = (fclose(f) == 0) && ok;
+  return ok ? FSMI_OK : FSMI_E_INVAL;
+}
+
+fsmi_status fsmi_sur_load(fsmi_sur net, const char* path) {
+  if (!net || !path) return FSMI_E_INVAL;
+  FILE* f = fopen(path, "rb");
+  if (!f) return FSMI_E_INVAL;
+  uint32_t hdr[4];
+  double st[2];
+  std::vector<float> buf(3 * (size_t)kNumParams);
+  bool ok = fread(hdr, sizeof(hdr), 1, f) == 1 && hdr[0] == 0x46534D49u && hdr[1] == 1u &&
+            hdr[3] == (uint32_t)kNumParams && fread(st, sizeof(st), 1, f) == 1 &&
+            fread(buf.data(), sizeof(float), buf.size(), f) == buf.size();
+  fclose(f);
+  if (!ok) return FSMI_E_INVAL;
+  net->step = (int)hdr[2];
+  if (hipMemcpy(net->P, buf.data(), sizeof(float) * kNumParams, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(net->M, buf.data() + kNumParams, sizeof(float) * kNumParams, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(net->V, buf.data() + 2 * kNumParams, sizeof(float) * kNumParams, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(net->stats, st, sizeof(st), hipMemcpyHostToDevice) != hipSuccess)
+    return FSMI_E_DEVICE;
+  return cast_weights(net) == hipSuccess ? FSMI_OK : FSMI_E_DEVICE;
+}
+
+fsmi_status fsmi_probe_mfma(fsmi_ctx ctx, const void* A, const void* B, float* D) {
+  if (!ctx || !A || !B || !D) return FSMI_E_INVAL;
+  hipLaunchKernelGGL(k_mfma_probe, dim3(1), dim3(64), 0, ctx->stream, (const bf16*)A, (const bf16*)B, D);
+  return hipGetLastError() == hipSuccess ? FSMI_OK : FSMI_E_DEVICE;
+}
+
+fsmi_status fsmi_rank_poses(fsmi_ctx ctx, const fsmi_params* params, fsmi_sur net,
+                            const fsmi_map* map, int64_t n_poses, const double* poses,
+                            int64_t n_beams, const double* beam_dir, double sigma, double max_range,
+                            int32_t k, int32_t* idx_out, double* mi_out, float* pred_out) {
+  if (!ctx || !params || !net || !sur_map_ok(net, map) || n_poses <= 0 || !poses || k <= 0 ||
+      k > n_poses || !idx_out || !mi_out || n_poses > (1ll << 30))
+    return FSMI_E_INVAL;
+  (void)hipSetDevice(ctx->device);
+  int64_t npow2 = 1;
+  while (npow2 < n_poses) npow2 <<= 1;
+  // work: pred [n] float, key [npow2] float, idx [npow2] int, top poses [k][4] double,
+  // per-beam scratch of the exact re-score [k][n_beams] double
+  const size_t need = sizeof(float) * n_poses + (sizeof(float) + sizeof(int32_t)) * npow2 +
+                      sizeof(double) * 4 * (size_t)k + sizeof(double) * (size_t)k * n_beams + 2048;
+  if (ensure_work(ctx, need) != hipSuccess) return FSMI_E_NOMEM;
+  char* w = reinterpret_cast<char*>(ctx->d_work);
+  float* pred = pred_out ? pred_out : reinterpret_cast<float*>(w);
+  float* key = reinterpret_cast<float*>(w + ((sizeof(float) * n_poses + 255) / 256) * 256);
+  int32_t* idx = reinterpret_cast<int32_t*>(key + npow2);
+  double* top = reinterpret_cast<double*>(
+      reinterpret_cast<char*>(idx) + ((sizeof(int32_t) * npow2 + 255) / 256) * 256);
+  net->ctx = ctx;
+  fsmi_status st = fsmi_sur_forward(net, map, n_poses, poses, pred);
+  if (st != FSMI_OK) return st;
+  const unsigned blocks = (unsigned)((npow2 + 255) / 256);
+  hipLaunchKernelGGL(k_topk_fill, dim3(blocks), dim3(256), 0, ctx->stream, n_poses, npow2, pred, key, idx);
+  for (int64_t kk = 2; kk <= npow2; kk <<= 1)
+    for (int64_t j = kk >> 1; j > 0; j >>= 1)
+      hipLaunchKernelGGL(k_bitonic_step, dim3(blocks), dim3(256), 0, ctx->stream, npow2, j, kk, key, idx);
+  hipLaunchKernelGGL(k_gather_poses, dim3((k + 255) / 256), dim3(256), 0, ctx->stream, k, idx, poses,
+                     top, idx_out);
+  if (hipGetLastError() != hipSuccess) return FSMI_E_DEVICE;
+  // exact re-score of the k candidates (the rank path never trusts the network alone)
+  double* mb = reinterpret_cast<double*>(
+      reinterpret_cast<char*>(top) + ((sizeof(double) * 4 * (size_t)k + 255) / 256) * 256);
+  return fsmi_eval_poses(ctx, params, map, k, top, n_beams, beam_dir, sigma, max_range, 1.0, mi_out,
+                         mb);
+}
+
+}  // extern "C"

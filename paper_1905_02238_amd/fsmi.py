@@ -27,7 +27,12 @@ FSMI_RAY_DDA, FSMI_RAY_VIRTUAL, FSMI_RAY_RLE = 0, 1, 2
 
 EXPORTS = ("fsmi_create", "fsmi_destroy", "fsmi_set_stream", "fsmi_sync", "fsmi_last_error",
            "fsmi_status_string", "fsmi_default_params", "fsmi_raycast", "fsmi_eval_beams",
-           "fsmi_rle_eval_beams", "fsmi_eval_poses", "fsmi_probe_erfc")
+           "fsmi_rle_eval_beams", "fsmi_eval_poses", "fsmi_probe_erfc", "fsmi_probe_mfma",
+           "fsmi_sur_num_params", "fsmi_sur_create", "fsmi_sur_destroy",
+           "fsmi_sur_fit_label_stats", "fsmi_sur_get_label_stats", "fsmi_sur_forward",
+           "fsmi_sur_backward", "fsmi_sur_adam_step", "fsmi_sur_get_params",
+           "fsmi_sur_set_params", "fsmi_sur_get_grads", "fsmi_sur_save", "fsmi_sur_load",
+           "fsmi_rank_poses")
 
 
 class FsmiError(RuntimeError):
@@ -77,9 +82,31 @@ def load(path: str = LIB_PATH):
             L.fsmi_eval_poses.argtypes = [p, C.POINTER(fsmi_params), C.POINTER(fsmi_map), i64, p,
                                           i64, p, d, d, d, p, p]
             L.fsmi_probe_erfc.argtypes = [p, i64, p, p]
+            L.fsmi_probe_mfma.argtypes = [p, p, p, p]
+            L.fsmi_sur_num_params.argtypes = []
+            L.fsmi_sur_num_params.restype = i64
+            L.fsmi_sur_create.argtypes = [p, C.POINTER(p), C.c_uint64, i32]
+            L.fsmi_sur_destroy.argtypes = [p]
+            L.fsmi_sur_destroy.restype = None
+            L.fsmi_sur_fit_label_stats.argtypes = [p, i64, p]
+            L.fsmi_sur_get_label_stats.argtypes = [p, p]
+            L.fsmi_sur_forward.argtypes = [p, C.POINTER(fsmi_map), i64, p, p]
+            L.fsmi_sur_backward.argtypes = [p, C.POINTER(fsmi_map), i64, p, p, p]
+            L.fsmi_sur_adam_step.argtypes = [p, C.c_float, C.c_float, C.c_float, C.c_float]
+            L.fsmi_sur_get_params.argtypes = [p, p]
+            L.fsmi_sur_set_params.argtypes = [p, p]
+            L.fsmi_sur_get_grads.argtypes = [p, p]
+            L.fsmi_sur_save.argtypes = [p, C.c_char_p]
+            L.fsmi_sur_load.argtypes = [p, C.c_char_p]
+            L.fsmi_rank_poses.argtypes = [p, C.POINTER(fsmi_params), p, C.POINTER(fsmi_map), i64, p,
+                                          i64, p, d, d, i32, p, p, p]
             for n in ("fsmi_create", "fsmi_set_stream", "fsmi_sync", "fsmi_raycast",
                       "fsmi_eval_beams", "fsmi_rle_eval_beams", "fsmi_eval_poses",
-                      "fsmi_probe_erfc"):
+                      "fsmi_probe_erfc", "fsmi_probe_mfma", "fsmi_sur_create",
+                      "fsmi_sur_fit_label_stats", "fsmi_sur_get_label_stats", "fsmi_sur_forward",
+                      "fsmi_sur_backward", "fsmi_sur_adam_step", "fsmi_sur_get_params",
+                      "fsmi_sur_set_params", "fsmi_sur_get_grads", "fsmi_sur_save",
+                      "fsmi_sur_load", "fsmi_rank_poses"):
                 getattr(L, n).restype = st
             _lib = L
     return _lib
@@ -227,6 +254,117 @@ class Context:
         self._check(self._lib.fsmi_probe_erfc(self.handle, z.numel(), _ptr(z, torch.float32, "z"),
                                               _ptr(out, torch.float32, "out")))
         return out
+
+
+    def fsmi_probe_mfma(self, A, B):
+        D = torch.empty((16, 16), dtype=torch.float32, device=A.device)
+        self._stream()
+        self._check(self._lib.fsmi_probe_mfma(self.handle, _ptr(A, torch.bfloat16, "A"),
+                                              _ptr(B, torch.bfloat16, "B"),
+                                              _ptr(D, torch.float32, "D")))
+        return D
+
+    def fsmi_rank_poses(self, prm: fsmi_params, net: "Surrogate", map_occ, poses, beam_dir, sigma,
+                        max_range, k, want_pred=False):
+        dev = map_occ.device
+        idx = torch.empty(k, dtype=torch.int32, device=dev)
+        mi = torch.empty(k, dtype=torch.float64, device=dev)
+        pred = torch.empty(poses.shape[0], dtype=torch.float32, device=dev) if want_pred else None
+        m = _map(map_occ)
+        self._stream()
+        self._check(self._lib.fsmi_rank_poses(
+            self.handle, C.byref(prm), net.handle, C.byref(m), poses.shape[0],
+            _ptr(poses, torch.float64, "poses"), beam_dir.shape[0],
+            _ptr(beam_dir, torch.float64, "beam_dir"), float(sigma), float(max_range), int(k),
+            _ptr(idx, torch.int32, "idx"), _ptr(mi, torch.float64, "mi"),
+            _ptr(pred, torch.float32, "pred", True)))
+        return idx, mi, pred
+
+
+class Surrogate:
+    """fsmi_sur: the conv-net surrogate (created on a Context's device and stream)."""
+
+    def __init__(self, ctx: Context, seed: int = 0, max_batch: int = 256):
+        self.ctx = ctx
+        self._lib = ctx._lib
+        h = C.c_void_p()
+        ctx._stream()
+        ctx._check(self._lib.fsmi_sur_create(ctx.handle, C.byref(h), C.c_uint64(seed), int(max_batch)))
+        self.handle = h
+        self.max_batch = max_batch
+        self.num_params = int(self._lib.fsmi_sur_num_params())
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self._lib.fsmi_sur_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _chk(self, st):
+        if st != FSMI_OK:
+            raise FsmiError(st, self._lib.fsmi_status_string(st).decode())
+
+    def fit_label_stats(self, labels):
+        self.ctx._stream()
+        self._chk(self._lib.fsmi_sur_fit_label_stats(self.handle, labels.numel(),
+                                                     _ptr(labels, torch.float64, "labels")))
+
+    def label_stats(self):
+        out = (C.c_double * 2)()
+        self._chk(self._lib.fsmi_sur_get_label_stats(self.handle, C.cast(out, C.c_void_p)))
+        return float(out[0]), float(out[1])
+
+    def forward(self, map_occ, poses, pred=None):
+        self.ctx._stream()
+        pred = torch.empty(poses.shape[0], dtype=torch.float32, device=poses.device) if pred is None else pred
+        m = _map(map_occ)
+        self._chk(self._lib.fsmi_sur_forward(self.handle, C.byref(m), poses.shape[0],
+                                             _ptr(poses, torch.float64, "poses"),
+                                             _ptr(pred, torch.float32, "pred")))
+        return pred
+
+    def backward(self, map_occ, poses, labels, loss=None):
+        self.ctx._stream()
+        loss = torch.empty(1, dtype=torch.float32, device=poses.device) if loss is None else loss
+        m = _map(map_occ)
+        self._chk(self._lib.fsmi_sur_backward(self.handle, C.byref(m), poses.shape[0],
+                                              _ptr(poses, torch.float64, "poses"),
+                                              _ptr(labels, torch.float64, "labels"),
+                                              _ptr(loss, torch.float32, "loss")))
+        return loss
+
+    def adam_step(self, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+        self.ctx._stream()
+        self._chk(self._lib.fsmi_sur_adam_step(self.handle, lr, b1, b2, eps))
+
+    def params(self):
+        self.ctx._stream()
+        out = torch.empty(self.num_params, dtype=torch.float32, device=f"cuda:{self.ctx.device}")
+        self._chk(self._lib.fsmi_sur_get_params(self.handle, _ptr(out, torch.float32, "params")))
+        return out
+
+    def set_params(self, p):
+        self.ctx._stream()
+        self._chk(self._lib.fsmi_sur_set_params(self.handle, _ptr(p, torch.float32, "params")))
+
+    def grads(self):
+        self.ctx._stream()
+        out = torch.empty(self.num_params, dtype=torch.float32, device=f"cuda:{self.ctx.device}")
+        self._chk(self._lib.fsmi_sur_get_grads(self.handle, _ptr(out, torch.float32, "grads")))
+        return out
+
+    def save(self, path):
+        self.ctx._stream()
+        self._chk(self._lib.fsmi_sur_save(self.handle, str(path).encode()))
+
+    def load(self, path):
+        self.ctx._stream()
+        self._chk(self._lib.fsmi_sur_load(self.handle, str(path).encode()))
 
 
 _ctx = {}
