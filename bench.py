@@ -10,8 +10,14 @@ per-pose FP64 sum).  Inputs are resident in HBM before timing starts.
 Other variants and workloads are measured once each and reported as extra
 fields (Approx-FSMI, Uniform-FSMI on the same poses; the uneven 100k-beam
 batch; 3D FSMI-RLE / Approx-FSMI-RLE on the voxel map; the 200 x 200 FP64 and
-FP32 single-pose latency).  ``--quick`` skips those extras and shrinks the
-CPU baseline sample.
+FP32 single-pose latency; the learned surrogate's rank path).  ``--quick``
+skips those extras and shrinks the CPU baseline sample.
+
+Surrogate leg: the network is trained here on exact-FSMI labels of other
+2048 x 2048 room maps (``--sur-maps`` x ``--sur-poses``, ``--sur-steps`` Adam
+steps of 128 poses), then on 65 536 candidate poses of the held-out timed map
+fsmi_rank_poses (surrogate forward, top 1 %, exact re-score) is timed against
+plain exact fsmi_eval_poses on all of them, with its ranking accuracy.
 """
 import argparse
 import json
@@ -34,6 +40,11 @@ import numpy as np  # noqa: E402
 # measured rate with them counted exceeds the single-issue figure), so they are
 # not charged.
 SLOTS_PER_PAIR = 19
+# Surrogate forward, multiply-adds x 2 per pose: five 3x3 stride-2 convolutions
+# (128^2 input, 1-32-64-64-128-128 channels) plus the 128-256-1 head.
+SUR_FLOP_PER_POSE = 2 * (64 * 64 * 32 * 9 * 1 + 32 * 32 * 64 * 9 * 32 + 16 * 16 * 64 * 9 * 64
+                         + 8 * 8 * 128 * 9 * 64 + 4 * 4 * 128 * 9 * 128 + 128 * 256 + 256)
+BF16_PEAK_TFLOPS = 2500.0
 # ALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T lane-ops/s
 # (one non-packed FP32 or FP64 VALU instruction per lane per clock).
 ALU_PEAK_TSLOT = 256 * 64 * 2.4e9 / 1e12
@@ -48,6 +59,10 @@ def parse():
     ap.add_argument("--quick", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--sur-maps", type=int, default=16)
+    ap.add_argument("--sur-poses", type=int, default=4096)
+    ap.add_argument("--sur-steps", type=int, default=3000)
+    ap.add_argument("--sur-candidates", type=int, default=65536)
     ap.add_argument("--profile-step", action="store_true",
                     help="for counter runs: one plain 256 MiB device copy (the traffic "
                          "calibration), then exactly one timed-workload step, nothing else")
@@ -158,33 +173,7 @@ def main():
                      "work": f"{SLOTS_PER_PAIR} VALU slots per (row, boundary) pair"},
     }
 
-    # ---- accuracy of the timed result on a sample of poses (oracle) ----
-    import oracle as O
-    sample = min(2, n_poses)
-    rp, _ = O.eval_poses_2d(O.EXACT, wl["grid"], wl["poses"][:sample], wl["beam_dir"], sigma, R,
-                            want_beams=False)
-    got = mp[:sample].cpu().numpy()
-    out["max_rel_err_vs_oracle"] = float(np.max(np.abs(got - rp) / np.abs(rp)))
-
-    # ---- CPU baseline: the oracle as it stands, bounded sample ----
-    if not args.no_cpu:
-        thr = O.max_threads()
-        t1 = time.perf_counter()
-        O.eval_poses_2d(O.EXACT, wl["grid"], wl["poses"][:1], wl["beam_dir"], sigma, R,
-                        threads=thr, want_beams=False)
-        one = time.perf_counter() - t1
-        budget = 3.0 if args.quick else args.cpu_seconds
-        k = int(max(1, min(64, round(budget / max(one, 1e-3)))))
-        t1 = time.perf_counter()
-        O.eval_poses_2d(O.EXACT, wl["grid"], wl["poses"][:k], wl["beam_dir"], sigma, R,
-                        threads=thr, want_beams=False)
-        cs = time.perf_counter() - t1
-        out["cpu_baseline"] = {"value": k * n_beams / cs, "unit": "beams/s", "cores": thr,
-                               "kind": "oracle",
-                               "sample": f"first {k} poses x {n_beams} beams of the timed workload, "
-                                         f"{cs:.1f} s, FP64, OpenMP over beams"}
-        log(f"[bench] cpu oracle: {k} poses in {cs:.1f} s on {thr} threads")
-
+    gpu = {"exact": mp}      # results the oracle leg checks, per workload
     # ---- extras: other variants and workloads, one timed run each ----
     if not args.quick:
         def timed(fn, reps=3):
@@ -200,10 +189,12 @@ def main():
                         ("uniform_h6", F.params(variant=F.FSMI_UNIFORM, uniform_h=6))):
             dt = timed(lambda: ctx.fsmi_eval_poses(p, grid, poses, bdir, sigma, R))
             extras[name] = {"beams_per_s": n_total / dt, "ms": dt * 1e3}
+            gpu[name] = ctx.fsmi_eval_poses(p, grid, poses, bdir, sigma, R)[0]
             log(f"[bench] {name}: {n_total/dt/1e6:.2f} M beams/s")
         off, occ, sg = W.uneven_beams(100000, seed=W.SEED_BASE + 3)
         o_, oc, s2 = t(off), t(occ), t(sg)
         dt = timed(lambda: ctx.fsmi_eval_beams(prm, o_, oc, s2))
+        gpu["uneven"] = ctx.fsmi_eval_beams(prm, o_, oc, s2)
         lens = np.diff(off).astype(np.float64)
         extras["uneven_100k_exact"] = {"beams_per_s": 1e5 / dt, "ms": dt * 1e3,
                                        "pairs": float(np.sum(lens * lens))}
@@ -214,17 +205,180 @@ def main():
             pp = F.params(precision=pr)
             dt = timed(lambda: ctx.fsmi_eval_poses(pp, gs, ps, bs, small["sigma"], small["R"]), reps=10)
             extras[name] = dt * 1e6
+            gpu[name] = ctx.fsmi_eval_poses(pp, gs, ps, bs, small["sigma"], small["R"],
+                                            want_beams=True)
         log("[bench] generating the 512x512x128 voxel map")
         vw = W.voxels_large(n_poses=256)
         vx, vp, vb = t(vw["vox"]), t(vw["poses"]), t(vw["beam_dir"])
+        gpu["voxels"] = vw
         nv = vp.shape[0] * vb.shape[0]
         for name, p in (("rle_exact_3d", F.params(variant=F.FSMI_EXACT)),
                         ("rle_approx_delta6_3d", F.params(variant=F.FSMI_APPROX, trunc_delta=6))):
             dt = timed(lambda: ctx.fsmi_eval_poses(p, vx, vp, vb, vw["sigma"], vw["R"], vw["w"]), reps=2)
             extras[name] = {"beams_per_s": nv / dt, "ms": dt * 1e3, "poses": vp.shape[0]}
+            gpu[name] = ctx.fsmi_eval_poses(p, vx, vp, vb, vw["sigma"], vw["R"], vw["w"],
+                                            want_beams=True)
             log(f"[bench] {name}: {nv/dt/1e6:.2f} M beams/s")
+        extras["surrogate_rank"] = surrogate_leg(ctx, F, W, t, timed, args)
         out["extras"] = extras
+
+    # ---- the oracle: CPU baseline and the error report, from the same runs ----
+    if not args.no_cpu:
+        oracle_leg(out, gpu, wl, W, args, ctx, F, t)
     print(json.dumps(out), flush=True)
+
+
+def _rel(got, ref):
+    """Relative error per result, |got - ref| / max(|ref|, 1e-30)."""
+    got, ref = np.asarray(got, np.float64), np.asarray(ref, np.float64)
+    return np.abs(got - ref) / np.maximum(np.abs(ref), 1e-30)
+
+
+def _err_stats(rel, bar, **kw):
+    d = dict(kw)
+    d.update({"results": int(rel.size), "max_rel": float(rel.max()),
+              "p99_rel": float(np.percentile(rel, 99)), "mean_rel": float(rel.mean()),
+              "bar": bar, "within_bar": bool(rel.max() <= bar)})
+    return d
+
+
+def oracle_leg(out, gpu, wl, W, args, ctx, F, t):
+    """The FP64 oracle timed on the host's cores on a bounded sample of the timed
+    workload (cpu_baseline), and, from the same oracle runs and a few more small
+    ones, the relative error of every GPU result it covers (error_report)."""
+    import torch
+    import oracle as O
+    thr = O.max_threads()
+    n_beams = wl["beam_dir"].shape[0]
+    sig, R = wl["sigma"], wl["R"]
+    # The oracle spreads poses over its threads: time one warm pose (one thread),
+    # then take whole rounds of `thr` poses to fill the budget.
+    for _ in range(2):
+        t1 = time.perf_counter()
+        O.eval_poses_2d(O.EXACT, wl["grid"], wl["poses"][:1], wl["beam_dir"], sig, R,
+                        threads=thr, want_beams=False)
+        one = time.perf_counter() - t1
+    budget = 3.0 if args.quick else args.cpu_seconds
+    k = int(min(len(wl["poses"]), thr * max(1, round(budget / max(one, 1e-3)))))
+    t1 = time.perf_counter()
+    ref_pose, ref_beam = O.eval_poses_2d(O.EXACT, wl["grid"], wl["poses"][:k], wl["beam_dir"],
+                                         sig, R, threads=thr, want_beams=True)
+    cs = time.perf_counter() - t1
+    out["cpu_baseline"] = {"value": k * n_beams / cs, "unit": "beams/s", "cores": thr,
+                           "kind": "oracle",
+                           "sample": f"first {k} poses x {n_beams} beams of the timed workload, "
+                                     f"{cs:.1f} s, FP64, OpenMP over poses"}
+    log(f"[bench] cpu oracle: {k} poses in {cs:.1f} s on {thr} threads")
+
+    rep = {}
+    # the timed launch's per-pose results; per-beam results of the same kernel on the sample
+    got_pose = gpu["exact"][:k].cpu().numpy()
+    grid, bdir = t(wl["grid"]), t(wl["beam_dir"])
+    _, gb = ctx.fsmi_eval_poses(F.params(), grid, t(wl["poses"][:k]), bdir, sig, R, want_beams=True)
+    gb = gb.cpu().numpy()
+    rep["exact_2d"] = _err_stats(_rel(gb, ref_beam), 1e-5, poses=k,
+                                 max_rel_pose_timed=float(_rel(got_pose, ref_pose).max()))
+    out["max_rel_err_vs_oracle"] = float(max(rep["exact_2d"]["max_rel"],
+                                             rep["exact_2d"]["max_rel_pose_timed"]))
+    if not args.quick:
+        kp = min(8, len(wl["poses"]))
+        for name, v, kw in (("approx_delta9", O.APPROX, {"Delta": wl["Delta"]}),
+                            ("uniform_h6", O.UNIFORM, {"H": wl["H"]})):
+            rp, _ = O.eval_poses_2d(v, wl["grid"], wl["poses"][:kp], wl["beam_dir"], sig, R,
+                                    threads=thr, want_beams=False, **kw)
+            rep[name] = _err_stats(_rel(gpu[name][:kp].cpu().numpy(), rp), 1e-5, poses=kp)
+        off, occ, sg = W.uneven_beams(100000, seed=W.SEED_BASE + 3)
+        nb = 2000
+        rb = O.eval_beams(O.EXACT, off[:nb + 1], occ[:off[nb]], sg[:nb], threads=thr)
+        rep["uneven_exact"] = _err_stats(_rel(gpu["uneven"][:nb].cpu().numpy(), rb), 1e-5, beams=nb)
+        small = W.grid_small()
+        rp, rb = O.eval_poses_2d(O.EXACT, small["grid"], small["poses"], small["beam_dir"],
+                                 small["sigma"], small["R"], threads=thr)
+        for name, bar in (("grid_small_fp64_us", 1e-12), ("grid_small_fp32_us", 1e-5)):
+            gp, gbm = gpu[name]
+            rep[name.replace("_us", "")] = _err_stats(
+                _rel(gbm.cpu().numpy(), rb), bar, beams=int(rb.size),
+                max_rel_pose=float(_rel(gp.cpu().numpy(), rp).max()))
+        vw = gpu["voxels"]
+        for name, exact, kw in (("rle_exact_3d", True, {}),
+                                ("rle_approx_delta6_3d", False, {"Delta": 6})):
+            rp, rb = O.eval_poses_3d(exact, vw["vox"], vw["poses"][:1], vw["beam_dir"], vw["sigma"],
+                                     vw["R"], vw["w"], threads=thr, **kw)
+            gp, gbm = gpu[name]
+            rep[name] = _err_stats(_rel(gbm[:1].cpu().numpy(), rb), 1e-5, poses=1,
+                                   max_rel_pose=float(_rel(gp[:1].cpu().numpy(), rp).max()))
+    out["error_report"] = rep
+    worst = max(v["max_rel"] / v["bar"] for v in rep.values())
+    log(f"[bench] error report: {len(rep)} workloads, worst max_rel / bar = {worst:.3f}")
+
+
+def surrogate_leg(ctx, F, W, t, timed, args):
+    """Train the surrogate on exact labels of other maps, then rank the held-out
+    map's candidates: poses/s of surrogate + top 1 % exact re-score vs plain
+    exact FSMI on every candidate, at the ranking accuracy reached."""
+    import torch
+    from scipy.stats import spearmanr
+    bd = t(W.beam_dirs_2d(360))
+    sigma, R = 3.0, 400.0
+    exact = F.params(variant=F.FSMI_EXACT)
+    log(f"[bench] surrogate: labelling {args.sur_maps} maps x {args.sur_poses} poses")
+    t1 = time.perf_counter()
+    train = []
+    for i in range(args.sur_maps):
+        occ, lab = W.room_grid(2048, W.SEED_BASE + 100 + i, split_extent=160, unknown_frac=0.30)
+        g = t(occ)
+        p = t(W.poses_in_free_space_2d(lab, args.sur_poses, W.SEED_BASE + 100 + i))
+        mi, _ = ctx.fsmi_eval_poses(exact, g, p, bd, sigma, R)
+        train.append((g, p, mi))
+    torch.cuda.synchronize()
+    label_s = time.perf_counter() - t1
+    net = F.Surrogate(ctx, seed=3, max_batch=8192)
+    net.fit_label_stats(torch.cat([d[2] for d in train]))
+    rng = np.random.default_rng(3)
+    t1 = time.perf_counter()
+    for it in range(args.sur_steps):
+        g, p, mi = train[it % len(train)]
+        sel = torch.from_numpy(rng.choice(p.shape[0], 128, replace=False)).to(g.device)
+        net.backward(g, p[sel].contiguous(), mi[sel].contiguous())
+        net.adam_step(1e-3)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t1
+    log(f"[bench] surrogate: labels {label_s:.1f} s, {args.sur_steps} steps {train_s:.1f} s")
+    wl = W.grid_large(n_poses=args.sur_candidates)      # held out: not a training map
+    g, p = t(wl["grid"]), t(wl["poses"])
+    n = p.shape[0]
+    k = max(1, math.ceil(0.01 * n))
+    plain = timed(lambda: ctx.fsmi_eval_poses(exact, g, p, bd, sigma, R), reps=2)
+    ranked = timed(lambda: ctx.fsmi_rank_poses(exact, net, g, p, bd, sigma, R, k), reps=3)
+    fwd = timed(lambda: net.forward(g, p), reps=3)
+    true, _ = ctx.fsmi_eval_poses(exact, g, p, bd, sigma, R)
+    idx, mi_top, pred = ctx.fsmi_rank_poses(exact, net, g, p, bd, sigma, R, k, want_pred=True)
+    torch.cuda.synchronize()
+    true, idx, pred = true.cpu().numpy(), idx.cpu().numpy(), pred.cpu().numpy()
+    best = true.max()
+    rr = np.random.default_rng(0)
+    rand_regret = float(np.mean([1.0 - true[rr.choice(n, k, replace=False)].max() / best
+                                 for _ in range(200)]))
+    res = {
+        "candidates": n, "k": k,
+        "rank_poses_per_s": n / ranked, "plain_exact_poses_per_s": n / plain,
+        "speedup": plain / ranked, "rank_ms": ranked * 1e3, "plain_ms": plain * 1e3,
+        "forward_poses_per_s": n / fwd,
+        "forward_tflops": n * SUR_FLOP_PER_POSE / fwd / 1e12,
+        "forward_mfma_frac": n * SUR_FLOP_PER_POSE / fwd / 1e12 / BF16_PEAK_TFLOPS,
+        "spearman": float(spearmanr(pred, true).correlation),
+        "recall_at_1pct": len(set(np.argsort(-true)[:k].tolist()) & set(idx.tolist())) / k,
+        "regret": float(1.0 - true[idx].max() / best),
+        "random_1pct_regret": rand_regret,
+        "train": f"{args.sur_maps} maps x {args.sur_poses} exact-labelled poses, "
+                 f"{args.sur_steps} Adam steps of 128 (labels {label_s:.1f} s, training {train_s:.1f} s)",
+    }
+    log(f"[bench] surrogate rank: {n/ranked:.0f} poses/s vs plain {n/plain:.0f} poses/s "
+        f"(x{plain/ranked:.1f}); forward {res['forward_tflops']:.1f} TFLOP/s; "
+        f"rho {res['spearman']:.3f} recall {res['recall_at_1pct']:.2f} regret {res['regret']:.4f} "
+        f"(random {rand_regret:.4f})")
+    net.close()
+    return res
 
 
 if __name__ == "__main__":

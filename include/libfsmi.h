@@ -212,7 +212,8 @@ fsmi_status fsmi_sur_load(fsmi_sur net, const char* path);
    and re-scores them with exact FSMI (params, beams, sigma, max_range as in
    fsmi_eval_poses).  idx_out[k] (device int32): candidate indices in the
    surrogate's order; mi_out[k] (device FP64): their exact scan MI; pred_out
-   (device FP32 [n_poses] or NULL): the surrogate's predictions. */
+   (device FP32 [n_poses] or NULL): the surrogate's predictions.  `net` must have
+   been created on `ctx` (FSMI_E_INVAL otherwise): everything runs on its stream. */
 fsmi_status fsmi_rank_poses(fsmi_ctx ctx, const fsmi_params* params, fsmi_sur net,
                             const fsmi_map* map, int64_t n_poses, const double* poses,
                             int64_t n_beams, const double* beam_dir, double sigma,

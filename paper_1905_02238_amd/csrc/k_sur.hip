@@ -866,8 +866,8 @@ fsmi_status fsmi_rank_poses(fsmi_ctx ctx, const fsmi_params* params, fsmi_sur ne
                             const fsmi_map* map, int64_t n_poses, const double* poses,
                             int64_t n_beams, const double* beam_dir, double sigma, double max_range,
                             int32_t k, int32_t* idx_out, double* mi_out, float* pred_out) {
-  if (!ctx || !params || !net || !sur_map_ok(net, map) || n_poses <= 0 || !poses || k <= 0 ||
-      k > n_poses || !idx_out || !mi_out || n_poses > (1ll << 30))
+  if (!ctx || !params || !net || net->ctx != ctx || !sur_map_ok(net, map) || n_poses <= 0 ||
+      !poses || k <= 0 || k > n_poses || !idx_out || !mi_out || n_poses > (1ll << 30))
     return FSMI_E_INVAL;
   (void)hipSetDevice(ctx->device);
   int64_t npow2 = 1;
@@ -883,7 +883,6 @@ fsmi_status fsmi_rank_poses(fsmi_ctx ctx, const fsmi_params* params, fsmi_sur ne
   int32_t* idx = reinterpret_cast<int32_t*>(key + npow2);
   double* top = reinterpret_cast<double*>(
       reinterpret_cast<char*>(idx) + ((sizeof(int32_t) * npow2 + 255) / 256) * 256);
-  net->ctx = ctx;
   fsmi_status st = fsmi_sur_forward(net, map, n_poses, poses, pred);
   if (st != FSMI_OK) return st;
   const unsigned blocks = (unsigned)((npow2 + 255) / 256);
