@@ -194,11 +194,22 @@ def main():
         off, occ, sg = W.uneven_beams(100000, seed=W.SEED_BASE + 3)
         o_, oc, s2 = t(off), t(occ), t(sg)
         dt = timed(lambda: ctx.fsmi_eval_beams(prm, o_, oc, s2))
-        gpu["uneven"] = ctx.fsmi_eval_beams(prm, o_, oc, s2)
         lens = np.diff(off).astype(np.float64)
-        extras["uneven_100k_exact"] = {"beams_per_s": 1e5 / dt, "ms": dt * 1e3,
-                                       "pairs": float(np.sum(lens * lens))}
-        log(f"[bench] uneven 100k exact: {1e5/dt/1e6:.2f} M beams/s")
+        # the same batch planned once: autotuned wave/tile threshold, HIP-graph replays
+        t1 = time.perf_counter()
+        plan = F.Plan(ctx, prm, o_, oc, s2, autotune=True, graph=True)
+        plan_s = time.perf_counter() - t1
+        dtp = timed(plan.launch, reps=5)
+        info = plan.info()
+        gpu["uneven"] = plan.launch().clone()
+        extras["uneven_100k_exact"] = {
+            "beams_per_s": 1e5 / dtp, "ms": dtp * 1e3, "pairs": float(np.sum(lens * lens)),
+            "eager_ms": dt * 1e3, "eager_wave_max": 512, "tuned_wave_max": info["wave_max"],
+            "tiles": info["n_tile"], "autotune_and_capture_s": plan_s,
+            "tried": {str(w): round(m, 4) for w, m in info["tried"]}}
+        plan.close()
+        log(f"[bench] uneven 100k exact: planned {1e5/dtp/1e6:.2f} M beams/s "
+            f"(wave_max {info['wave_max']}), eager {1e5/dt/1e6:.2f} M beams/s")
         small = W.grid_small()
         gs, ps, bs = t(small["grid"]), t(small["poses"]), t(small["beam_dir"])
         for name, pr in (("grid_small_fp64_us", F.FSMI_FP64), ("grid_small_fp32_us", F.FSMI_FP32)):

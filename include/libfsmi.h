@@ -63,12 +63,6 @@ enum {
   FSMI_KERNEL_DENSITY = 1 /* exp(-d^2/(2 sigma'^2))/(sqrt(2 pi) sigma') (proof of Thm 5) */
 };
 enum { FSMI_FP32 = 0, FSMI_FP64 = 1 };
-enum {
-  /* Skip (row, boundary) pairs whose FP32 weight underflows to exactly zero
-     (|l - mu| > 13.5 sigma).  A separate mode: the result equals the dense FP32
-     sum up to rounding order, and its work count is reported separately. */
-  FSMI_F_SKIP_ZERO = 1u
-};
 
 typedef struct {
   double delta_occ;   /* > 1; the paper uses 1.5 (Sec. 5.1) */
@@ -77,7 +71,7 @@ typedef struct {
   int32_t uniform_h;  /* H >= 0, cells (UNIFORM) */
   int32_t kernel;     /* FSMI_KERNEL_* (equal-width cells and RLE only) */
   int32_t precision;  /* FSMI_FP32 (default) | FSMI_FP64 */
-  uint32_t flags;     /* FSMI_F_* */
+  uint32_t flags;     /* reserved, must be 0 */
 } fsmi_params;
 
 typedef struct {
@@ -140,10 +134,51 @@ fsmi_status fsmi_raycast(fsmi_ctx ctx, const fsmi_map* map, int32_t mode, int64_
    cell-index windows).  Computation in FP32 with compensated sums and an
    FP64 prefix product, or entirely in FP64 with precision = FSMI_FP64.
    Beams of uneven length are scheduled longest-first on persistent workers:
-   a beam longer than the wave threshold is shared by a whole workgroup. */
+   a beam longer than the wave threshold is shared by a whole workgroup.  The
+   threshold is 512 cells (FP32) or 256 (FP64), or the one the autotuner of
+   fsmi_plan_eval_beams chose on this context for the same precision, variant
+   and boundary kind.  Waits once for the device (the longest beam sizes the
+   workgroup's LDS); fsmi_plan_eval_beams avoids that wait. */
 fsmi_status fsmi_eval_beams(fsmi_ctx ctx, const fsmi_params* params, int64_t n_beams,
                             const int64_t* off, const float* occ, const double* bound,
                             const float* sigma, double* mi);
+
+/* ---- a13: a planned beam batch, autotuned and replayed from a HIP graph ----
+   fsmi_plan_eval_beams binds the arguments of fsmi_eval_beams to a plan: it
+   finds the longest beam, sorts the beams into length bins once (its own
+   device buffers, n_beams + 48 int32), and, with FSMI_PLAN_AUTOTUNE, times the
+   launch at each candidate wave threshold on these very inputs and keeps the
+   fastest (mi is written while tuning); the choice is also kept on the context
+   for later fsmi_eval_beams calls of the same kind.  With FSMI_PLAN_GRAPH the
+   launch (queue reset, tile-per-beam and wave-per-beam kernels) is captured
+   once into a HIP graph.  wave_max > 0 fixes the threshold (cells); 0 takes the
+   context's tuned value or the default.  Synchronous.
+   fsmi_plan_launch enqueues one evaluation on the context's current stream and
+   returns at once: it re-reads occ, bound and sigma and rewrites mi, so their
+   contents may change between launches; off, n_beams and the buffer addresses
+   are fixed.  Launches of one plan must not overlap (they share the queue
+   counters).  Errors as fsmi_eval_beams; FSMI_E_CAPACITY at plan time when the
+   longest beam does not fit a workgroup's LDS. */
+typedef struct fsmi_plan_s* fsmi_plan;
+enum { FSMI_PLAN_AUTOTUNE = 1u, FSMI_PLAN_GRAPH = 2u };
+typedef struct {
+  int32_t wave_max;          /* beams longer than this many cells are tile-per-beam */
+  int32_t max_len;           /* longest beam, cells */
+  int64_t n_tile;            /* beams taken by a whole workgroup */
+  int64_t n_wave;            /* beams taken by a single wave */
+  int32_t graph;             /* 1: launches replay a captured HIP graph */
+  int32_t n_tried;           /* candidates the autotuner timed (0 without it) */
+  int32_t tried_wave_max[16];
+  float tried_ms[16];        /* mean launch time of each candidate, ms */
+} fsmi_plan_info;
+fsmi_status fsmi_plan_eval_beams(fsmi_ctx ctx, const fsmi_params* params, int64_t n_beams,
+                                 const int64_t* off, const float* occ, const double* bound,
+                                 const float* sigma, double* mi, int32_t wave_max,
+                                 uint32_t plan_flags, fsmi_plan* out);
+fsmi_status fsmi_plan_launch(fsmi_plan plan);
+fsmi_status fsmi_plan_get_info(fsmi_plan plan, fsmi_plan_info* info /* host */);
+/* Waits for the context's stream, then frees the plan's buffers and graph. */
+void fsmi_plan_destroy(fsmi_plan plan);
 
 /* ---- a10, a11: run-length-encoded beams on equal-width virtual cells ----
    Beam b has runs run_off[b] .. run_off[b+1]-1 with value run_occ[u] and

@@ -10,13 +10,9 @@
 #include "fsmi_dev.h"
 #include "fsmi_internal.h"
 
-namespace fsmi {
-hipError_t launch_max_len(fsmi_ctx ctx, const int64_t* off, int64_t n_beams, int* host_out);
-}
-
 using namespace fsmi;
 
-namespace {
+namespace fsmi {
 
 fsmi_status fail(fsmi_ctx ctx, fsmi_status s, const std::string& msg) {
   if (ctx) ctx->last_error = msg;
@@ -60,6 +56,10 @@ bool check_params(fsmi_ctx ctx, const fsmi_params* p, fsmi_status* st) {
     *st = fail(ctx, FSMI_E_INVAL, "unknown precision");
     return false;
   }
+  if (p->flags != 0) {
+    *st = fail(ctx, FSMI_E_INVAL, "flags are reserved and must be 0");
+    return false;
+  }
   return true;
 }
 
@@ -99,9 +99,11 @@ bool check_map(fsmi_ctx ctx, const fsmi_map* m, fsmi_status* st) {
   return true;
 }
 
-}  // namespace
+int ctx_wave_max(fsmi_ctx ctx, const fsmi_params* p, bool has_bound) {
+  const int t = ctx->tuned_wave_max[p->precision == FSMI_FP64][p->variant][has_bound ? 1 : 0];
+  return t > 0 ? t : beam_default_wave_max(p->precision);
+}
 
-namespace fsmi {
 hipError_t ensure_work(fsmi_ctx ctx, size_t bytes) {
   if (bytes <= ctx->work_bytes) return hipSuccess;
   if (ctx->d_work) {
@@ -274,11 +276,12 @@ fsmi_status fsmi_eval_beams(fsmi_ctx ctx, const fsmi_params* params, int64_t n_b
   int max_len = 0;
   hipError_t e = launch_max_len(ctx, off, n_beams, &max_len);
   if (e != hipSuccess) return from_hip(ctx, e, "eval_beams max length");
-  const int bpc = params->precision == FSMI_FP64 ? 28 : 20;
-  if ((size_t)max_len * bpc + 16 > 150 * 1024)
+  const int wave_max = ctx_wave_max(ctx, params, bound != nullptr);
+  if (!beam_fits(params->precision, wave_max, max_len))
     return fail(ctx, FSMI_E_CAPACITY, "a beam is longer than one workgroup's LDS holds");
   return from_hip(ctx,
-                  launch_eval_beams(ctx, to_const(params), n_beams, off, occ, bound, sigma, mi, max_len),
+                  launch_eval_beams(ctx, to_const(params), n_beams, off, occ, bound, sigma, mi,
+                                    max_len, wave_max),
                   "eval_beams");
 }
 
@@ -313,7 +316,7 @@ fsmi_status fsmi_eval_poses(fsmi_ctx ctx, const fsmi_params* params, const fsmi_
   if (n_poses == 0 || n_beams == 0) {
     if (n_poses > 0 && mi_pose) {
       (void)hipSetDevice(ctx->device);
-      return from_hip(ctx, hipMemsetAsync(mi_pose, 0, (size_t)n_poses * 8, ctx->stream), "zero poses");
+      return from_hip(ctx, launch_fill_f64(ctx->stream, n_poses, 0.0, mi_pose), "zero poses");
     }
     return FSMI_OK;
   }

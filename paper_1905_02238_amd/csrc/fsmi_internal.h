@@ -17,6 +17,9 @@ struct fsmi_ctx_s {
   size_t work_bytes = 0;
   int num_cu = 256;
   std::string last_error;
+  // Autotuned wave/tile threshold of the beam-batch schedule, per
+  // [precision][variant][explicit boundaries]; 0 = not tuned (use the default).
+  int tuned_wave_max[2][3][2] = {};
 };
 
 namespace fsmi {
@@ -35,10 +38,37 @@ struct EvalConst {
 // Grow-only device scratch owned by the context.
 hipError_t ensure_work(fsmi_ctx ctx, size_t bytes);
 
+// ---- argument checks and error reporting of the C-ABI (api.hip) ----
+fsmi_status fail(fsmi_ctx ctx, fsmi_status s, const std::string& msg);
+fsmi_status from_hip(fsmi_ctx ctx, hipError_t e, const char* where);
+bool check_params(fsmi_ctx ctx, const fsmi_params* p, fsmi_status* st);
+bool check_map(fsmi_ctx ctx, const fsmi_map* m, fsmi_status* st);
+EvalConst to_const(const fsmi_params* p);
+// The wave/tile threshold for a beam batch: the autotuned one if any, else the default.
+int ctx_wave_max(fsmi_ctx ctx, const fsmi_params* p, bool has_bound);
+
 // ---- launchers (k_beam.hip) ----
+// Beam batches: beams longer than wave_max cells are tile-per-beam (a workgroup
+// each), the rest wave-per-beam.  A schedule buffer holds beam_sched_ints(n)
+// int32: the beam order (longest bins first), the bin histogram and the queue
+// counters.
+int beam_default_wave_max(int precision);
+int beam_bytes_per_cell(int precision);
+bool beam_fits(int precision, int wave_max, int max_len);
+size_t beam_sched_ints(int64_t n_beams);
+int64_t beam_sched_n_long_index(int64_t n_beams);   // where the schedule leaves the tile-beam count
+hipError_t launch_max_len(fsmi_ctx ctx, const int64_t* off, int64_t n_beams, int* host_out);
+hipError_t launch_beam_schedule(hipStream_t st, const int64_t* off, int64_t n_beams, int wave_max,
+                                int32_t* sched);
+hipError_t launch_beam_kernels(hipStream_t st, int num_cu, const EvalConst& ec, int64_t n_beams,
+                               const int64_t* off, const float* occ, const double* bound,
+                               const float* sigma, double* mi, const int32_t* sched,
+                               uint32_t* status, int wave_max, int max_len, bool run_long,
+                               bool run_short);
 hipError_t launch_eval_beams(fsmi_ctx ctx, const EvalConst& ec, int64_t n_beams, const int64_t* off,
                              const float* occ, const double* bound, const float* sigma,
-                             double* mi, int max_len);
+                             double* mi, int max_len, int wave_max);
+hipError_t launch_fill_f64(hipStream_t st, int64_t n, double v, double* p);
 
 // ---- launchers (k_ray.hip) ----
 hipError_t launch_raycast2d(fsmi_ctx ctx, const float* map, int64_t X, int64_t Y, int64_t n_rays,

@@ -21,6 +21,7 @@ constexpr int kNW = 4;          // waves per workgroup
 constexpr int kHalf = 16;       // length bins per class (octaves, descending)
 constexpr int kBins = 2 * kHalf;
 constexpr int kMaxGrid = 4096;  // persistent workgroups
+constexpr size_t kLdsLimit = 150 * 1024;   // dynamic LDS per workgroup
 
 struct BeamArgs {
   EvalConst ec;
@@ -144,6 +145,10 @@ __global__ void k_sched_reset(int32_t* counters, int32_t* hist) {
   if (t < 2 * kBins) hist[t] = 0;
 }
 
+__global__ void k_queue_reset(int32_t* counters) {
+  if (threadIdx.x < 2) counters[threadIdx.x] = 0;
+}
+
 __global__ void k_sched_count(const int64_t* off, int64_t n_beams, int wave_max, int32_t* hist,
                               int32_t* counters) {
   __shared__ int32_t h[kBins];
@@ -222,28 +227,42 @@ hipError_t launch_max_len(fsmi_ctx ctx, const int64_t* off, int64_t n_beams, int
   return hipStreamSynchronize(ctx->stream);
 }
 
-// Beams longer than the wave threshold are handled by a whole workgroup.
-static int wave_threshold(int precision) { return precision == FSMI_FP64 ? 256 : 512; }
+int beam_default_wave_max(int precision) { return precision == FSMI_FP64 ? 256 : 512; }
 
-hipError_t launch_eval_beams(fsmi_ctx ctx, const EvalConst& ec, int64_t n_beams, const int64_t* off,
-                             const float* occ, const double* bound, const float* sigma,
-                             double* mi, int max_len) {
-  if (n_beams <= 0) return hipSuccess;
-  const size_t need = (size_t)n_beams * 4 + 2 * kBins * 4 + 64;
-  hipError_t e = ensure_work(ctx, need);
-  if (e != hipSuccess) return e;
-  int32_t* order = reinterpret_cast<int32_t*>(ctx->d_work);
-  int32_t* hist = order + n_beams;
-  const int wave_max = wave_threshold(ec.precision);
+int beam_bytes_per_cell(int precision) {
+  return precision == FSMI_FP64 ? bytes_per_cell<double>() : bytes_per_cell<float>();
+}
 
-  hipLaunchKernelGGL(k_sched_reset, dim3(1), dim3(64), 0, ctx->stream, ctx->d_counters, hist);
+bool beam_fits(int precision, int wave_max, int max_len) {
+  const size_t bpc = (size_t)beam_bytes_per_cell(precision);
+  return bpc * (size_t)std::max(max_len, 1) + 16 <= kLdsLimit &&
+         (size_t)kNW * (bpc * (size_t)std::max(wave_max, 1) + 16) <= kLdsLimit;
+}
+
+size_t beam_sched_ints(int64_t n_beams) { return (size_t)n_beams + 2 * kBins + 16; }
+
+hipError_t launch_beam_schedule(hipStream_t st, const int64_t* off, int64_t n_beams, int wave_max,
+                                int32_t* sched) {
+  int32_t* order = sched;
+  int32_t* hist = sched + n_beams;
+  int32_t* counters = hist + 2 * kBins;
+  hipLaunchKernelGGL(k_sched_reset, dim3(1), dim3(64), 0, st, counters, hist);
   const int cb = (int)std::max<int64_t>(1, std::min<int64_t>((n_beams + 255) / 256, 1024));
-  hipLaunchKernelGGL(k_sched_count, dim3(cb), dim3(256), 0, ctx->stream, off, n_beams, wave_max,
-                     hist, ctx->d_counters);
-  hipLaunchKernelGGL(k_sched_scan, dim3(1), dim3(64), 0, ctx->stream, hist);
-  hipLaunchKernelGGL(k_sched_scatter, dim3(cb), dim3(256), 0, ctx->stream, off, n_beams, wave_max,
-                     hist, order);
+  hipLaunchKernelGGL(k_sched_count, dim3(cb), dim3(256), 0, st, off, n_beams, wave_max, hist,
+                     counters);
+  hipLaunchKernelGGL(k_sched_scan, dim3(1), dim3(64), 0, st, hist);
+  hipLaunchKernelGGL(k_sched_scatter, dim3(cb), dim3(256), 0, st, off, n_beams, wave_max, hist,
+                     order);
+  return hipGetLastError();
+}
 
+int64_t beam_sched_n_long_index(int64_t n_beams) { return n_beams + 2 * kBins + 2; }
+
+hipError_t launch_beam_kernels(hipStream_t st, int num_cu, const EvalConst& ec, int64_t n_beams,
+                               const int64_t* off, const float* occ, const double* bound,
+                               const float* sigma, double* mi, const int32_t* sched,
+                               uint32_t* status, int wave_max, int max_len, bool run_long,
+                               bool run_short) {
   BeamArgs a;
   a.ec = ec;
   a.n_beams = n_beams;
@@ -252,34 +271,61 @@ hipError_t launch_eval_beams(fsmi_ctx ctx, const EvalConst& ec, int64_t n_beams,
   a.bound = bound;
   a.sigma = sigma;
   a.mi = mi;
-  a.order = order;
-  a.counters = ctx->d_counters;
-  a.status = ctx->d_status;
+  a.order = sched;
+  a.counters = const_cast<int32_t*>(sched) + n_beams + 2 * kBins;
+  a.status = status;
   const bool fp64 = ec.precision == FSMI_FP64;
-  const int bpc = fp64 ? bytes_per_cell<double>() : bytes_per_cell<float>();
+  const size_t bpc = (size_t)beam_bytes_per_cell(ec.precision);
   a.cap_wave = wave_max;
   a.cap_block = std::max(max_len, 1);
-  const size_t lds_block = (size_t)bpc * a.cap_block + 16;
-  const size_t lds_wave = (size_t)kNW * ((size_t)bpc * a.cap_wave + 16);
-  if (lds_block > 150 * 1024 || lds_wave > 150 * 1024) return hipErrorInvalidValue;
+  const size_t lds_long = bpc * a.cap_block + 16;
+  const size_t lds_short = (size_t)kNW * (bpc * a.cap_wave + 16);
+  if (lds_long > kLdsLimit || lds_short > kLdsLimit) return hipErrorInvalidValue;
   const int64_t want = (n_beams + kNW - 1) / kNW;
-  const size_t lds_long = lds_block, lds_short = lds_wave;
   const int per_cu_l = std::max<int>(1, (int)((160 * 1024) / (lds_long + 512)));
   const int per_cu_s = std::max<int>(1, (int)((160 * 1024) / (lds_short + 512)));
-  const int grid_l = std::max(1, std::min(kMaxGrid, ctx->num_cu * std::min(per_cu_l, 8)));
+  const int grid_l = std::max(1, std::min(kMaxGrid, num_cu * std::min(per_cu_l, 8)));
   const int grid_s = (int)std::max<int64_t>(
-      1, std::min<int64_t>(want, std::min(kMaxGrid, ctx->num_cu * std::min(per_cu_s, 8))));
+      1, std::min<int64_t>(want, std::min(kMaxGrid, num_cu * std::min(per_cu_s, 8))));
+  // queue heads back to zero; the long-beam count written by the schedule stays
+  hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, st, a.counters);
   if (fp64) {
     (void)hipFuncSetAttribute((const void*)k_eval_long<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_long);
     (void)hipFuncSetAttribute((const void*)k_eval_short<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_short);
-    hipLaunchKernelGGL(k_eval_long<double>, dim3(grid_l), dim3(kWave * kNW), lds_long, ctx->stream, a);
-    hipLaunchKernelGGL(k_eval_short<double>, dim3(grid_s), dim3(kWave * kNW), lds_short, ctx->stream, a);
+    if (run_long) hipLaunchKernelGGL(k_eval_long<double>, dim3(grid_l), dim3(kWave * kNW), lds_long, st, a);
+    if (run_short) hipLaunchKernelGGL(k_eval_short<double>, dim3(grid_s), dim3(kWave * kNW), lds_short, st, a);
   } else {
     (void)hipFuncSetAttribute((const void*)k_eval_long<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_long);
     (void)hipFuncSetAttribute((const void*)k_eval_short<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_short);
-    hipLaunchKernelGGL(k_eval_long<float>, dim3(grid_l), dim3(kWave * kNW), lds_long, ctx->stream, a);
-    hipLaunchKernelGGL(k_eval_short<float>, dim3(grid_s), dim3(kWave * kNW), lds_short, ctx->stream, a);
+    if (run_long) hipLaunchKernelGGL(k_eval_long<float>, dim3(grid_l), dim3(kWave * kNW), lds_long, st, a);
+    if (run_short) hipLaunchKernelGGL(k_eval_short<float>, dim3(grid_s), dim3(kWave * kNW), lds_short, st, a);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_eval_beams(fsmi_ctx ctx, const EvalConst& ec, int64_t n_beams, const int64_t* off,
+                             const float* occ, const double* bound, const float* sigma,
+                             double* mi, int max_len, int wave_max) {
+  if (n_beams <= 0) return hipSuccess;
+  hipError_t e = ensure_work(ctx, beam_sched_ints(n_beams) * 4);
+  if (e != hipSuccess) return e;
+  int32_t* sched = reinterpret_cast<int32_t*>(ctx->d_work);
+  e = launch_beam_schedule(ctx->stream, off, n_beams, wave_max, sched);
+  if (e != hipSuccess) return e;
+  return launch_beam_kernels(ctx->stream, ctx->num_cu, ec, n_beams, off, occ, bound, sigma, mi, sched,
+                             ctx->d_status, wave_max, max_len, true, true);
+}
+
+__global__ void k_fill_f64(int64_t n, double v, double* p) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+hipError_t launch_fill_f64(hipStream_t st, int64_t n, double v, double* p) {
+  if (n <= 0) return hipSuccess;
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 4096));
+  hipLaunchKernelGGL(k_fill_f64, dim3(grid), dim3(256), 0, st, n, v, p);
   return hipGetLastError();
 }
 

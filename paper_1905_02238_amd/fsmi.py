@@ -22,8 +22,8 @@ FSMI_OK, FSMI_E_INVAL, FSMI_E_DEVICE, FSMI_E_NOMEM, FSMI_E_CAPACITY, FSMI_E_NUME
 FSMI_EXACT, FSMI_APPROX, FSMI_UNIFORM = 0, 1, 2
 FSMI_KERNEL_ERF, FSMI_KERNEL_DENSITY = 0, 1
 FSMI_FP32, FSMI_FP64 = 0, 1
-FSMI_F_SKIP_ZERO = 1
 FSMI_RAY_DDA, FSMI_RAY_VIRTUAL, FSMI_RAY_RLE = 0, 1, 2
+FSMI_PLAN_AUTOTUNE, FSMI_PLAN_GRAPH = 1, 2
 
 EXPORTS = ("fsmi_create", "fsmi_destroy", "fsmi_set_stream", "fsmi_sync", "fsmi_last_error",
            "fsmi_status_string", "fsmi_default_params", "fsmi_raycast", "fsmi_eval_beams",
@@ -32,7 +32,8 @@ EXPORTS = ("fsmi_create", "fsmi_destroy", "fsmi_set_stream", "fsmi_sync", "fsmi_
            "fsmi_sur_fit_label_stats", "fsmi_sur_get_label_stats", "fsmi_sur_forward",
            "fsmi_sur_backward", "fsmi_sur_adam_step", "fsmi_sur_get_params",
            "fsmi_sur_set_params", "fsmi_sur_get_grads", "fsmi_sur_save", "fsmi_sur_load",
-           "fsmi_rank_poses")
+           "fsmi_rank_poses", "fsmi_plan_eval_beams", "fsmi_plan_launch", "fsmi_plan_get_info",
+           "fsmi_plan_destroy")
 
 
 class FsmiError(RuntimeError):
@@ -49,6 +50,12 @@ class fsmi_params(C.Structure):
 
 class fsmi_map(C.Structure):
     _fields_ = [("occ", C.c_void_p), ("ndim", C.c_int32), ("dims", C.c_int64 * 3)]
+
+
+class fsmi_plan_info(C.Structure):
+    _fields_ = [("wave_max", C.c_int32), ("max_len", C.c_int32), ("n_tile", C.c_int64),
+                ("n_wave", C.c_int64), ("graph", C.c_int32), ("n_tried", C.c_int32),
+                ("tried_wave_max", C.c_int32 * 16), ("tried_ms", C.c_float * 16)]
 
 
 _lib = None
@@ -100,13 +107,20 @@ def load(path: str = LIB_PATH):
             L.fsmi_sur_load.argtypes = [p, C.c_char_p]
             L.fsmi_rank_poses.argtypes = [p, C.POINTER(fsmi_params), p, C.POINTER(fsmi_map), i64, p,
                                           i64, p, d, d, i32, p, p, p]
+            L.fsmi_plan_eval_beams.argtypes = [p, C.POINTER(fsmi_params), i64, p, p, p, p, p, i32,
+                                               C.c_uint32, C.POINTER(p)]
+            L.fsmi_plan_launch.argtypes = [p]
+            L.fsmi_plan_get_info.argtypes = [p, C.POINTER(fsmi_plan_info)]
+            L.fsmi_plan_destroy.argtypes = [p]
+            L.fsmi_plan_destroy.restype = None
             for n in ("fsmi_create", "fsmi_set_stream", "fsmi_sync", "fsmi_raycast",
                       "fsmi_eval_beams", "fsmi_rle_eval_beams", "fsmi_eval_poses",
                       "fsmi_probe_erfc", "fsmi_probe_mfma", "fsmi_sur_create",
                       "fsmi_sur_fit_label_stats", "fsmi_sur_get_label_stats", "fsmi_sur_forward",
                       "fsmi_sur_backward", "fsmi_sur_adam_step", "fsmi_sur_get_params",
                       "fsmi_sur_set_params", "fsmi_sur_get_grads", "fsmi_sur_save",
-                      "fsmi_sur_load", "fsmi_rank_poses"):
+                      "fsmi_sur_load", "fsmi_rank_poses", "fsmi_plan_eval_beams",
+                      "fsmi_plan_launch", "fsmi_plan_get_info"):
                 getattr(L, n).restype = st
             _lib = L
     return _lib
@@ -279,6 +293,53 @@ class Context:
             _ptr(idx, torch.int32, "idx"), _ptr(mi, torch.float64, "mi"),
             _ptr(pred, torch.float32, "pred", True)))
         return idx, mi, pred
+
+
+class Plan:
+    """fsmi_plan: a beam batch bound to its buffers, scheduled once (optionally
+    autotuned and captured into a HIP graph); launch() enqueues one evaluation
+    that re-reads occ / bound / sigma and rewrites mi."""
+
+    def __init__(self, ctx: Context, prm: fsmi_params, off, occ, sigma, bound=None, mi=None,
+                 wave_max=0, autotune=False, graph=False):
+        self.ctx = ctx
+        self._lib = ctx._lib
+        n = off.shape[0] - 1
+        self.mi = torch.empty(n, dtype=torch.float64, device=occ.device) if mi is None else mi
+        # keep the bound tensors alive for the plan's lifetime
+        self._keep = (off, occ, sigma, bound, self.mi)
+        flags = (FSMI_PLAN_AUTOTUNE if autotune else 0) | (FSMI_PLAN_GRAPH if graph else 0)
+        h = C.c_void_p()
+        ctx._stream()
+        ctx._check(self._lib.fsmi_plan_eval_beams(
+            ctx.handle, C.byref(prm), n, _ptr(off, torch.int64, "off"),
+            _ptr(occ, torch.float32, "occ"), _ptr(bound, torch.float64, "bound", True),
+            _ptr(sigma, torch.float32, "sigma"), _ptr(self.mi, torch.float64, "mi"),
+            int(wave_max), flags, C.byref(h)))
+        self.handle = h
+
+    def launch(self):
+        self.ctx._stream()
+        self.ctx._check(self._lib.fsmi_plan_launch(self.handle))
+        return self.mi
+
+    def info(self) -> dict:
+        i = fsmi_plan_info()
+        self.ctx._check(self._lib.fsmi_plan_get_info(self.handle, C.byref(i)))
+        return {"wave_max": i.wave_max, "max_len": i.max_len, "n_tile": i.n_tile,
+                "n_wave": i.n_wave, "graph": bool(i.graph),
+                "tried": [(i.tried_wave_max[k], i.tried_ms[k]) for k in range(i.n_tried)]}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self._lib.fsmi_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Surrogate:
