@@ -32,14 +32,14 @@ sys.path.insert(0, ROOT)
 import numpy as np  # noqa: E402
 
 # Algorithmic main-VALU instructions per (row j, boundary) pair of the exact
-# sum, one issue slot each: l - mu (FP64 add) 1, |.| * c (FP64 mul) 1, convert 1;
-# erfc = t 2^(P2(t) - x^2), t = 1/(1 + x / (2 sqrt(log2 e))): fma 1, 9-term
-# Horner 9, exponent fma 1, product 1; |E_b - E_{b-1}| 1, C_k G fma 1; the
-# compensated sum's share (4 ops per 4 pairs) 1.  The reciprocal and 2^x run on
-# the transcendental unit, which issues alongside the main VALU on gfx950 (the
-# measured rate with them counted exceeds the single-issue figure), so they are
-# not charged.
-SLOTS_PER_PAIR = 19
+# sum, one issue slot each, on boundaries pre-scaled once per beam:
+# L_b - M_j (FP64 add) 1, convert to FP32 (|.| folded into the next FMA) 1;
+# erfc = t 2^(P(t) - y^2), t = 1/(1 + a|y|): fma 1, degree-7 Horner 7,
+# exponent fma 1, product 1; |E_b - E_{b-1}| 1, C_k G fma 1; the compensated
+# sum's share (4 ops per 8 pairs) 0.5.  The reciprocal and 2^x run on the
+# transcendental unit, which issues alongside the main VALU on gfx950, so they
+# are not charged.
+SLOTS_PER_PAIR = 14.5
 # Surrogate forward, multiply-adds x 2 per pose: five 3x3 stride-2 convolutions
 # (128^2 input, 1-32-64-64-128-128 channels) plus the 128-256-1 head.
 SUR_FLOP_PER_POSE = 2 * (64 * 64 * 32 * 9 * 1 + 32 * 32 * 64 * 9 * 32 + 16 * 16 * 64 * 9 * 64

@@ -114,76 +114,79 @@ template <> struct Acc<double> {
   FSMI_DEV double value() const { return s - c; }
 };
 
-// erfc of a boundary at l, on the tail side of mu (c = 1/(sigma sqrt 2)).
-// FP32: the argument is pre-scaled by sqrt(log2 e) so that erfc_pos_l2 needs
-// no separate multiply for the base-2 exponent.
+// Explicit boundaries are pre-scaled once per beam (beam_core):
+//   FP32: L = l c sqrt(log2 e), the argument erfc_pos_l2 takes;
+//   FP64: L = l c;
+// with c = 1/(sigma sqrt 2), so the weight argument of a boundary is |L - M|
+// (M the scaled mid-point of the hit cell) with no multiply per pair.
 template <typename T>
-FSMI_DEV T tail_E(double l, double mu, double c) {
+FSMI_DEV T tail_E(double L, double M) {
   if constexpr (sizeof(T) == 8) {
-    return erfc_pos(tabs(l - mu) * c);
+    return erfc_pos(tabs(L - M));
   } else {
-    constexpr double kSqrtL2E = 1.2011224087864498;   // sqrt(log2(e))
-    return erfc_pos_l2((float)(tabs(l - mu) * (c * kSqrtL2E)));
+    return erfc_pos_l2((float)tabs(L - M));
   }
 }
+template <typename T> constexpr double unscale() { return sizeof(T) == 8 ? 1.0 : (double)kInvSqrtL2E; }
 
 // ---------------------------------------------------------------------------
-// Row sums S_j = sum_k C_k G_{k,j} on explicit boundaries sL[0..n].
+// Row sums S_j = sum_k C_k G_{k,j} on scaled boundaries sL[0..n].
 // G_{k,j} = (1/2)|E(l_{k+1}) - E(l_k)| for k != j (both boundaries on one side
 // of mu_j), G_{j,j} = (1/2)(erf((l_{j+1}-mu)c) + erf((mu-l_j)c)).
 // ---------------------------------------------------------------------------
 template <typename T>
-FSMI_DEV double diag_fix(Acc<T>& acc, const double* sL, const T* sC, int j, double mu, double c) {
+FSMI_DEV double diag_fix(Acc<T>& acc, const double* sL, const T* sC, int j, double M) {
   // replace the k = j term the loop took by the exact diagonal weight
-  T Ej = tail_E<T>(sL[j - 1], mu, c);
-  T Ej1 = tail_E<T>(sL[j], mu, c);
+  T Ej = tail_E<T>(sL[j - 1], M);
+  T Ej1 = tail_E<T>(sL[j], M);
   T Cj = sC[j - 1];
   acc.add(-(Cj * tabs(Ej1 - Ej)));
-  T g2 = erf_t<T>((T)((sL[j] - mu) * c)) + erf_t<T>((T)((mu - sL[j - 1]) * c));
+  constexpr double u = unscale<T>();
+  T g2 = erf_t<T>((T)((sL[j] - M) * u)) + erf_t<T>((T)((M - sL[j - 1]) * u));
   acc.add(Cj * g2);
   return 0.5 * acc.value();
 }
 
+// Eight pairs per compensated add: the block of eight is an FP32 (or FP64)
+// FMA chain, the blocks are Kahan-summed.
 template <typename T>
-FSMI_DEV double row_exact_bound(const double* sL, const T* sC, int n, int j, double c) {
-  const double mu = 0.5 * (sL[j - 1] + sL[j]);
+FSMI_DEV double row_exact_bound(const double* sL, const T* sC, int n, int j) {
+  const double M = 0.5 * (sL[j - 1] + sL[j]);
   Acc<T> acc;
-  T Eprev = tail_E<T>(sL[0], mu, c);
+  T Eprev = tail_E<T>(sL[0], M);
   int b = 1;
-  for (; b + 3 <= n; b += 4) {
-    T E0 = tail_E<T>(sL[b], mu, c);
-    T E1 = tail_E<T>(sL[b + 1], mu, c);
-    T E2 = tail_E<T>(sL[b + 2], mu, c);
-    T E3 = tail_E<T>(sL[b + 3], mu, c);
-    T p = sC[b - 1] * tabs(E0 - Eprev);
-    p = fma(sC[b], tabs(E1 - E0), p);
-    p = fma(sC[b + 1], tabs(E2 - E1), p);
-    p = fma(sC[b + 2], tabs(E3 - E2), p);
+  for (; b + 7 <= n; b += 8) {
+    T E[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) E[q] = tail_E<T>(sL[b + q], M);
+    T p = sC[b - 1] * tabs(E[0] - Eprev);
+#pragma unroll
+    for (int q = 1; q < 8; ++q) p = fma(sC[b - 1 + q], tabs(E[q] - E[q - 1]), p);
     acc.add(p);
-    Eprev = E3;
+    Eprev = E[7];
   }
   for (; b <= n; ++b) {
-    T E = tail_E<T>(sL[b], mu, c);
+    T E = tail_E<T>(sL[b], M);
     acc.add(sC[b - 1] * tabs(E - Eprev));
     Eprev = E;
   }
-  return diag_fix<T>(acc, sL, sC, j, mu, c);
+  return diag_fix<T>(acc, sL, sC, j, M);
 }
 
 template <typename T>
-FSMI_DEV double row_approx_bound(const double* sL, const T* sC, int n, int j, double c, int D) {
-  const double mu = 0.5 * (sL[j - 1] + sL[j]);
+FSMI_DEV double row_approx_bound(const double* sL, const T* sC, int n, int j, int D) {
+  const double M = 0.5 * (sL[j - 1] + sL[j]);
   Acc<T> acc;
   // cells k = j-D..j+D; cell k spans [sL[k-1], sL[k]]; indices clamped to the
   // beam so out-of-range cells see two equal boundaries and weigh zero
-  T Eprev = tail_E<T>(sL[clampi(j - D - 1, 0, n)], mu, c);
+  T Eprev = tail_E<T>(sL[clampi(j - D - 1, 0, n)], M);
   for (int i = 0; i <= 2 * D; ++i) {
     const int k = j - D + i;
-    T E = tail_E<T>(sL[clampi(k, 0, n)], mu, c);
+    T E = tail_E<T>(sL[clampi(k, 0, n)], M);
     acc.add(sC[clampi(k - 1, 0, n - 1)] * tabs(E - Eprev));
     Eprev = E;
   }
-  return diag_fix<T>(acc, sL, sC, j, mu, c);
+  return diag_fix<T>(acc, sL, sC, j, M);
 }
 
 // Unit cells: G_{k,j} = g(|k-j|), g from the per-beam table sG[0..n-1].
@@ -284,6 +287,12 @@ FSMI_DEV double beam_core(const EvalConst& ec, int n, const float* so, bool has_
   const bool any_bad = group_any<NW, BLOCK>(bad, flag, tid);
   *bad_out = any_bad;
   Grp<NW, BLOCK>::sync();
+  if (has_bound && !uni && !any_bad) {
+    // scale the boundaries once: the weight argument becomes |L_b - M_j|
+    const double s = sizeof(T) == 8 ? c : c * (double)kSqrtL2E;
+    for (int i = tid; i <= n; i += G) sA[i] *= s;
+    Grp<NW, BLOCK>::sync();
+  }
 
   // ---- the double sum ----
   double tot = 0.0;
@@ -296,10 +305,10 @@ FSMI_DEV double beam_core(const EvalConst& ec, int n, const float* so, bool has_
       }
     } else if (has_bound) {
       if (ec.variant == FSMI_EXACT) {
-        for (int j = tid + 1; j <= n; j += G) tot += (double)sP[j - 1] * row_exact_bound<T>(sA, sC, n, j, c);
+        for (int j = tid + 1; j <= n; j += G) tot += (double)sP[j - 1] * row_exact_bound<T>(sA, sC, n, j);
       } else {
         for (int j = tid + 1; j <= n; j += G)
-          tot += (double)sP[j - 1] * row_approx_bound<T>(sA, sC, n, j, c, ec.Delta);
+          tot += (double)sP[j - 1] * row_approx_bound<T>(sA, sC, n, j, ec.Delta);
       }
     } else {
       const T* sG = reinterpret_cast<const T*>(sA);
