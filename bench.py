@@ -40,6 +40,34 @@ import numpy as np  # noqa: E402
 # transcendental unit, which issues alongside the main VALU on gfx950, so they
 # are not charged.
 SLOTS_PER_PAIR = 14.5
+# HBM traffic of one k_poses2d<float> launch on the timed workload, from two
+# rocprofv3 --pmc passes (profiles/k_poses2d_exact_grid2048_4096x360.md):
+# FETCH_SIZE and WRITE_SIZE in KiB per dispatch, each scaled by what the same
+# counter reads for a plain 256 MiB device copy in the same run (FETCH_SIZE
+# 131091 KiB for 262144 KiB read, WRITE_SIZE 262144 KiB for 262144 KiB written).
+# They describe the kernel built from the sources hashed here; with any other
+# sources the bench reports traffic as null.
+TRAFFIC = {"fetch_kib": 9.72271e6, "write_kib": 90297.1,
+           "fetch_scale": 262144.0 / 131091.0, "write_scale": 1.0,
+           "sources_sha256": "224468929ef7ef2277c5a3b3d0f015fdacb1d2406ba968cf8bdf3d9320aec072"}
+TRAFFIC_SOURCES = ("paper_1905_02238_amd/csrc/k_pose.hip", "paper_1905_02238_amd/csrc/beam_dev.h",
+                   "paper_1905_02238_amd/csrc/ray_dev.h", "paper_1905_02238_amd/csrc/fsmi_dev.h",
+                   "paper_1905_02238_amd/csrc/fsmi_internal.h", "paper_1905_02238_amd/build.py")
+
+
+def measured_traffic():
+    """Bytes per launch from the counters, or None if the kernel sources changed."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != TRAFFIC["sources_sha256"]:
+        return None
+    return 1024.0 * (TRAFFIC["fetch_kib"] * TRAFFIC["fetch_scale"]
+                     + TRAFFIC["write_kib"] * TRAFFIC["write_scale"])
+
+
 # Surrogate forward, multiply-adds x 2 per pose: five 3x3 stride-2 convolutions
 # (128^2 input, 1-32-64-64-128-128 channels) plus the 128-256-1 head.
 SUR_FLOP_PER_POSE = 2 * (64 * 64 * 32 * 9 * 1 + 32 * 32 * 64 * 9 * 32 + 16 * 16 * 64 * 9 * 64
@@ -168,7 +196,8 @@ def main():
                    "poses": n_poses, "beams_per_pose": n_beams, "max_range": R, "sigma": sigma,
                    "mean_cells_per_beam": mean_n, "pairs_per_step": pairs},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TSLOT,
-                     "unit": "TFLOP/s", "frac": achieved / ALU_PEAK_TSLOT, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / ALU_PEAK_TSLOT,
+                     "traffic": measured_traffic(),
                      "kernel": "k_poses2d<float>", "kernel_ms": kern_ms,
                      "work": f"{SLOTS_PER_PAIR} VALU slots per (row, boundary) pair"},
     }
