@@ -207,8 +207,12 @@ fsmi_status fsmi_eval_poses(fsmi_ctx ctx, const fsmi_params* params, const fsmi_
                             double* mi_pose, double* mi_beam);
 
 /* ---- a15..a17: learned surrogate, trained on FSMI's own labels ----
-   A small conv net predicts a pose's scan MI from the 128 x 128 patch of o
-   centred on the pose's cell (cells outside the map read 0.5): five 3x3 convs,
+   A small conv net predicts a pose's scan MI from a 128 x 128 patch of o
+   around the pose: with cell stride s, patch pixel (iy, ix) is the mean of o
+   over the s x s block (bx - 64 + ix, by - 64 + iy) of cells, where (bx, by) =
+   (floor(floor(x) / s), floor(floor(y) / s)) is the block holding the pose's
+   cell (blocks cut by the map edge average their inside cells; blocks outside
+   the map read 0.5); s = 1 is the plain local patch.  Five 3x3 convs,
    stride 2, padding 1, ReLU (1-32-64-64-128-128 channels), global average pool,
    FC 128->256, ReLU, FC 256->1, 310465 parameters.  BF16 activations and
    weights on the matrix cores with FP32 accumulation, FP32 master weights and
@@ -221,8 +225,9 @@ typedef struct fsmi_sur_s* fsmi_sur;
 int64_t fsmi_sur_num_params(void);
 /* Allocates parameters, optimiser state and activations for batches of up to
    max_batch poses (<= 65536); Kaiming-uniform weights from a counter-based
-   generator seeded by `seed`, zero biases. */
-fsmi_status fsmi_sur_create(fsmi_ctx ctx, fsmi_sur* out, uint64_t seed, int32_t max_batch);
+   generator seeded by `seed`, zero biases; patch cell stride 1..64. */
+fsmi_status fsmi_sur_create(fsmi_ctx ctx, fsmi_sur* out, uint64_t seed, int32_t max_batch,
+                            int32_t patch_stride);
 void fsmi_sur_destroy(fsmi_sur net);
 /* Mean and standard deviation of n device FP64 labels (nats), kept in the net. */
 fsmi_status fsmi_sur_fit_label_stats(fsmi_sur net, int64_t n, const double* labels);
@@ -240,7 +245,8 @@ fsmi_status fsmi_sur_adam_step(fsmi_sur net, float lr, float beta1, float beta2,
 fsmi_status fsmi_sur_get_params(fsmi_sur net, float* dst);
 fsmi_status fsmi_sur_set_params(fsmi_sur net, const float* src);
 fsmi_status fsmi_sur_get_grads(fsmi_sur net, float* dst);
-/* Checkpoint (host file): step, label statistics, weights, Adam moments. */
+/* Checkpoint (host file): step, patch stride, label statistics, weights, Adam
+   moments; load adopts the file's patch stride. */
 fsmi_status fsmi_sur_save(fsmi_sur net, const char* path);
 fsmi_status fsmi_sur_load(fsmi_sur net, const char* path);
 /* Ranks n_poses 2D candidates by the surrogate, keeps the top k (ties by index),

@@ -4,7 +4,8 @@ Only the tests and the benchmark's baseline leg use this module.  It shares no
 code with the HIP kernels.  The network (not from the paper; it ranks candidate
 poses before exact FSMI re-scores the best ones):
 
-  patch 128 x 128 of o centred on the pose's cell, 0.5 outside the map
+  patch 128 x 128 of o around the pose (cells, or s x s block means), 0.5
+  outside the map
   -> 5 x [3x3 conv, stride 2, zero padding 1, ReLU], channels 1-32-64-64-128-128
   -> global average pool -> FC 128->256 -> ReLU -> FC 256->1.
 
@@ -50,20 +51,33 @@ def pack(d):
     return np.concatenate([np.asarray(d[n], np.float64).reshape(-1) for n, _, _ in layout()])
 
 
-def patches(grid, poses):
-    """[B][128][128][1] patches; patch pixel (iy, ix) reads cell
-    (floor(x) - 64 + ix, floor(y) - 64 + iy), 0.5 outside the map."""
+def block_means(grid, s):
+    """Map of s x s block means: block (v, u) averages the cells
+    x in [s u, s u + s), y in [s v, s v + s) that lie inside the map."""
     grid = np.asarray(grid, np.float64)
     Y, X = grid.shape
+    Yc, Xc = -(-Y // s), -(-X // s)
+    pad = np.full((Yc * s, Xc * s), np.nan)
+    pad[:Y, :X] = grid
+    return np.nanmean(pad.reshape(Yc, s, Xc, s), axis=(1, 3))
+
+
+def patches(grid, poses, stride=1):
+    """[B][128][128][1] patches.  With cell stride s, pixel (iy, ix) is block
+    (bx - 64 + ix, by - 64 + iy) of the s x s block means, (bx, by) = the block
+    holding the pose's cell (floor(floor(x) / s), floor(floor(y) / s)); 0.5
+    outside the map.  s = 1 reads the cells themselves."""
+    src = np.asarray(grid, np.float64) if stride == 1 else block_means(grid, stride)
+    Y, X = src.shape
     out = np.full((len(poses), PATCH, PATCH, 1), 0.5)
     for b, p in enumerate(poses):
-        cx0 = int(np.floor(p[0])) - PATCH // 2
-        cy0 = int(np.floor(p[1])) - PATCH // 2
+        cx0 = int(np.floor(p[0])) // stride - PATCH // 2
+        cy0 = int(np.floor(p[1])) // stride - PATCH // 2
         ys = np.arange(cy0, cy0 + PATCH)
         xs = np.arange(cx0, cx0 + PATCH)
         vy = (ys >= 0) & (ys < Y)
         vx = (xs >= 0) & (xs < X)
-        out[b][np.ix_(vy, vx)] = grid[np.ix_(ys[vy], xs[vx])][..., None]
+        out[b][np.ix_(vy, vx)] = src[np.ix_(ys[vy], xs[vx])][..., None]
     return out
 
 

@@ -78,19 +78,41 @@ FSMI_DEV bf16x8 zero8() {
 }
 
 // Input of the first layer: patch pixel (iy, ix) of pose b, 0 outside the
-// padded patch, the map's o (0.5 outside the map) inside.
+// padded patch, else the map's value (0.5 outside the map).  With cell stride
+// s > 1, `map` is the map of s x s block means and the patch is centred on the
+// block holding the pose's cell; s = 1 reads the map itself.
 struct PatchSrc {
   const float* map;
-  int64_t X, Y;
+  int64_t X, Y;          // dims of `map`
   const double* poses;   // [n][4]
+  int s;                 // cell stride
+  FSMI_DEV int64_t block(double v) const {
+    const int64_t c = (int64_t)floor(v);
+    return c >= 0 ? c / s : -((-c + s - 1) / s);   // floor(c / s)
+  }
   FSMI_DEV float at(int64_t b, int iy, int ix) const {
     if (iy < 0 || iy >= kPatch || ix < 0 || ix >= kPatch) return 0.0f;
-    const int64_t cx = (int64_t)floor(poses[4 * b]) - kPatch / 2 + ix;
-    const int64_t cy = (int64_t)floor(poses[4 * b + 1]) - kPatch / 2 + iy;
+    const int64_t cx = block(poses[4 * b]) - kPatch / 2 + ix;
+    const int64_t cy = block(poses[4 * b + 1]) - kPatch / 2 + iy;
     if (cx < 0 || cx >= X || cy < 0 || cy >= Y) return 0.5f;
     return map[cx + X * cy];
   }
 };
+
+// Block means: out[v][u] = mean of the map's cells x in [s u, s u + s),
+// y in [s v, s v + s) that lie inside the map (FP64 sum, fixed order).
+__global__ void k_pool_map(const float* __restrict__ map, int64_t X, int64_t Y, int s,
+                           int64_t Xc, int64_t Yc, float* __restrict__ out) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < Xc * Yc;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t u = i % Xc, v = i / Xc;
+    const int64_t x1 = min<int64_t>(s * u + s, X), y1 = min<int64_t>(s * v + s, Y);
+    double acc = 0.0;
+    for (int64_t y = s * v; y < y1; ++y)
+      for (int64_t x = s * u; x < x1; ++x) acc += (double)map[x + X * y];
+    out[i] = (float)(acc / (double)((x1 - s * u) * (y1 - s * v)));
+  }
+}
 
 // ---------------------------------------------------------------------------
 // Forward convolution: out[p][co] = ReLU(b[co] + sum_{tap,ci} W[co][tap][ci] in[p+tap][ci])
@@ -573,6 +595,9 @@ struct fsmi_sur_s {
   float* part = nullptr;    // weight-gradient partials
   size_t part_floats = 0;
   float* loss = nullptr;
+  int stride = 1;            // cell stride of the patch
+  float* pooled = nullptr;   // block means of the last map (stride > 1)
+  size_t pooled_elems = 0;
 };
 
 namespace fsmi {
@@ -628,10 +653,40 @@ static void sur_free(fsmi_sur net) {
                 net->hsave, net->dysave, net->dhsave, net->ypred, net->part, net->loss};
   for (void* p : ps)
     if (p) (void)hipFree(p);
+  if (net->pooled) (void)hipFree(net->pooled);
   for (int l = 1; l <= 5; ++l) {
     if (net->act[l]) (void)hipFree(net->act[l]);
     if (net->dact[l]) (void)hipFree(net->dact[l]);
   }
+}
+
+// The first layer's input for `map`: the map itself, or (stride > 1) its block
+// means, recomputed on the net's stream for this call.
+static hipError_t make_src(fsmi_sur net, const fsmi_map* map, const double* poses, PatchSrc* src) {
+  const int s = net->stride;
+  if (s == 1) {
+    *src = PatchSrc{map->occ, map->dims[0], map->dims[1], poses, 1};
+    return hipSuccess;
+  }
+  const int64_t X = map->dims[0], Y = map->dims[1];
+  const int64_t Xc = (X + s - 1) / s, Yc = (Y + s - 1) / s;
+  if ((size_t)(Xc * Yc) > net->pooled_elems) {
+    if (net->pooled) {
+      hipError_t e = hipStreamSynchronize(net->ctx->stream);
+      if (e != hipSuccess) return e;
+      (void)hipFree(net->pooled);
+      net->pooled = nullptr;
+      net->pooled_elems = 0;
+    }
+    hipError_t e = hipMalloc((void**)&net->pooled, sizeof(float) * (size_t)(Xc * Yc));
+    if (e != hipSuccess) return e;
+    net->pooled_elems = (size_t)(Xc * Yc);
+  }
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((Xc * Yc + 255) / 256, 4096));
+  hipLaunchKernelGGL(k_pool_map, dim3(grid), dim3(256), 0, net->ctx->stream, map->occ, X, Y, s, Xc,
+                     Yc, net->pooled);
+  *src = PatchSrc{net->pooled, Xc, Yc, poses, s};
+  return hipGetLastError();
 }
 
 static hipError_t cast_weights(fsmi_sur net) {
@@ -696,13 +751,16 @@ extern "C" {
 
 int64_t fsmi_sur_num_params(void) { return kNumParams; }
 
-fsmi_status fsmi_sur_create(fsmi_ctx ctx, fsmi_sur* out, uint64_t seed, int32_t max_batch) {
-  if (!ctx || !out || max_batch <= 0 || max_batch > 65536) return FSMI_E_INVAL;
+fsmi_status fsmi_sur_create(fsmi_ctx ctx, fsmi_sur* out, uint64_t seed, int32_t max_batch,
+                            int32_t patch_stride) {
+  if (!ctx || !out || max_batch <= 0 || max_batch > 65536 || patch_stride < 1 || patch_stride > 64)
+    return FSMI_E_INVAL;
   *out = nullptr;
   (void)hipSetDevice(ctx->device);
   fsmi_sur net = new fsmi_sur_s();
   net->ctx = ctx;
   net->max_batch = max_batch;
+  net->stride = patch_stride;
   if (sur_alloc(net) != hipSuccess) {
     sur_free(net);
     delete net;
@@ -742,9 +800,14 @@ fsmi_status fsmi_sur_forward(fsmi_sur net, const fsmi_map* map, int64_t n, const
                              float* pred) {
   if (!sur_map_ok(net, map) || n < 0 || (n > 0 && (!poses || !pred))) return FSMI_E_INVAL;
   (void)hipSetDevice(net->ctx->device);
+  if (n == 0) return FSMI_OK;
+  PatchSrc src0;
+  const hipError_t e = make_src(net, map, poses, &src0);
+  if (e != hipSuccess) return e == hipErrorOutOfMemory ? FSMI_E_NOMEM : FSMI_E_DEVICE;
   for (int64_t s = 0; s < n; s += net->max_batch) {
     const int64_t nb = std::min<int64_t>(net->max_batch, n - s);
-    PatchSrc src{map->occ, map->dims[0], map->dims[1], poses + 4 * s};
+    PatchSrc src = src0;
+    src.poses = poses + 4 * s;
     if (sur_fwd_batch(net, nb, src, false) != hipSuccess) return FSMI_E_DEVICE;
     hipLaunchKernelGGL(k_destandardise, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0,
                        net->ctx->stream, nb, net->ypred, net->stats, pred + s);
@@ -757,7 +820,9 @@ fsmi_status fsmi_sur_backward(fsmi_sur net, const fsmi_map* map, int64_t n, cons
   if (!sur_map_ok(net, map) || n <= 0 || n > net->max_batch || !poses || !labels)
     return FSMI_E_INVAL;
   (void)hipSetDevice(net->ctx->device);
-  PatchSrc src{map->occ, map->dims[0], map->dims[1], poses};
+  PatchSrc src;
+  const hipError_t e = make_src(net, map, poses, &src);
+  if (e != hipSuccess) return e == hipErrorOutOfMemory ? FSMI_E_NOMEM : FSMI_E_DEVICE;
   if (sur_fwd_batch(net, n, src, true) != hipSuccess) return FSMI_E_DEVICE;
   hipStream_t st = net->ctx->stream;
   const int grid = (int)std::min<int64_t>(n, 65535);
@@ -828,7 +893,8 @@ fsmi_status fsmi_sur_save(fsmi_sur net, const char* path) {
     return FSMI_E_DEVICE;
   FILE* f = fopen(path, "wb");
   if (!f) return FSMI_E_INVAL;
-  const uint32_t hdr[4] = {0x46534D49u, 1u, (uint32_t)net->step, (uint32_t)kNumParams};
+  const uint32_t hdr[5] = {0x46534D49u, 2u, (uint32_t)net->step, (uint32_t)kNumParams,
+                           (uint32_t)net->stride};
   bool ok = fwrite(hdr, sizeof(hdr), 1, f) == 1 && fwrite(st, sizeof(st), 1, f) == 1 &&
             fwrite(buf.data(), sizeof(float), buf.size(), f) == buf.size();
   ok = (fclose(f) == 0) && ok;
@@ -839,15 +905,17 @@ fsmi_status fsmi_sur_load(fsmi_sur net, const char* path) {
   if (!net || !path) return FSMI_E_INVAL;
   FILE* f = fopen(path, "rb");
   if (!f) return FSMI_E_INVAL;
-  uint32_t hdr[4];
+  uint32_t hdr[5];
   double st[2];
   std::vector<float> buf(3 * (size_t)kNumParams);
-  bool ok = fread(hdr, sizeof(hdr), 1, f) == 1 && hdr[0] == 0x46534D49u && hdr[1] == 1u &&
-            hdr[3] == (uint32_t)kNumParams && fread(st, sizeof(st), 1, f) == 1 &&
+  bool ok = fread(hdr, sizeof(hdr), 1, f) == 1 && hdr[0] == 0x46534D49u && hdr[1] == 2u &&
+            hdr[3] == (uint32_t)kNumParams && hdr[4] >= 1u && hdr[4] <= 64u &&
+            fread(st, sizeof(st), 1, f) == 1 &&
             fread(buf.data(), sizeof(float), buf.size(), f) == buf.size();
   fclose(f);
   if (!ok) return FSMI_E_INVAL;
   net->step = (int)hdr[2];
+  net->stride = (int)hdr[4];
   if (hipMemcpy(net->P, buf.data(), sizeof(float) * kNumParams, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(net->M, buf.data() + kNumParams, sizeof(float) * kNumParams, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(net->V, buf.data() + 2 * kNumParams, sizeof(float) * kNumParams, hipMemcpyHostToDevice) != hipSuccess ||

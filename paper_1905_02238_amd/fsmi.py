@@ -92,7 +92,7 @@ def load(path: str = LIB_PATH):
             L.fsmi_probe_mfma.argtypes = [p, p, p, p]
             L.fsmi_sur_num_params.argtypes = []
             L.fsmi_sur_num_params.restype = i64
-            L.fsmi_sur_create.argtypes = [p, C.POINTER(p), C.c_uint64, i32]
+            L.fsmi_sur_create.argtypes = [p, C.POINTER(p), C.c_uint64, i32, i32]
             L.fsmi_sur_destroy.argtypes = [p]
             L.fsmi_sur_destroy.restype = None
             L.fsmi_sur_fit_label_stats.argtypes = [p, i64, p]
@@ -345,12 +345,13 @@ class Plan:
 class Surrogate:
     """fsmi_sur: the conv-net surrogate (created on a Context's device and stream)."""
 
-    def __init__(self, ctx: Context, seed: int = 0, max_batch: int = 256):
+    def __init__(self, ctx: Context, seed: int = 0, max_batch: int = 256, patch_stride: int = 1):
         self.ctx = ctx
         self._lib = ctx._lib
         h = C.c_void_p()
         ctx._stream()
-        ctx._check(self._lib.fsmi_sur_create(ctx.handle, C.byref(h), C.c_uint64(seed), int(max_batch)))
+        ctx._check(self._lib.fsmi_sur_create(ctx.handle, C.byref(h), C.c_uint64(seed),
+                                             int(max_batch), int(patch_stride)))
         self.handle = h
         self.max_batch = max_batch
         self.num_params = int(self._lib.fsmi_sur_num_params())

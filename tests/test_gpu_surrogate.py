@@ -55,13 +55,14 @@ def _per_tensor(g_gpu, g_ref):
     return out
 
 
-def test_forward_and_gradients_match_fp64_reference(ctx):
+@pytest.mark.parametrize("stride", [1, 4])
+def test_forward_and_gradients_match_fp64_reference(ctx, stride):
     wl = W.grid_small()
     grid, lab = wl["grid"], wl["labels"]
     poses = _poses_near_and_inside(lab, 32, 5)
-    net = F.Surrogate(ctx, seed=7, max_batch=32)
+    net = F.Surrogate(ctx, seed=7, max_batch=32, patch_stride=stride)
     flat = net.params().double().cpu().numpy()
-    x = S.patches(grid, poses)
+    x = S.patches(grid, poses, stride=stride)
     y_ref, _ = S.forward(flat, x)
     y_bf, _ = S.forward(flat, x, q=_bf16)
     pred = net.forward(dev(grid), dev(poses))

@@ -41,6 +41,33 @@ def test_patch_reads_cells_around_the_pose_and_half_outside():
     assert np.all(p[114:, 60] == 0.5)                      # y >= 200: outside
 
 
+def test_block_means_match_plain_loops_on_a_ragged_map():
+    rng = np.random.default_rng(3)
+    grid = rng.uniform(0, 1, (10, 13))
+    got = S.block_means(grid, 4)
+    assert got.shape == (3, 4)
+    for v in range(3):
+        for u in range(4):
+            cells = [grid[y, x] for y in range(4 * v, min(4 * v + 4, 10))
+                     for x in range(4 * u, min(4 * u + 4, 13))]
+            assert np.isclose(got[v, u], sum(cells) / len(cells), rtol=1e-15)
+
+
+def test_strided_patch_is_centred_on_the_block_of_the_pose():
+    grid = np.arange(42 * 38, dtype=np.float64).reshape(38, 42) / 1e3
+    bm = S.block_means(grid, 4)                                 # 10 x 11 blocks
+    assert bm.shape == (10, 11)
+    assert np.isclose(bm[9, 10], grid[36:38, 40:42].mean())     # cut by both edges
+    p = S.patches(grid, [[3.5, 13.2, 1.0, 0.0]], stride=4)[0, ..., 0]
+    # pose cell (3, 13) -> block (0, 3): pixel (64, 64) holds block (0, 3)
+    assert np.isclose(p[64, 64], bm[3, 0])
+    assert p[64, 63] == 0.5                                     # block x = -1: outside
+    assert np.isclose(p[70, 74], bm[9, 10])                     # the last block
+    assert p[71, 64] == 0.5 and p[64, 75] == 0.5                # past the last block
+    assert np.array_equal(S.patches(grid, [[3.5, 13.2, 1, 0]], stride=1),
+                          S.patches(grid, [[3.5, 13.2, 1, 0]]))
+
+
 @pytest.mark.parametrize("seed", [1, 2])
 def test_gradient_matches_central_differences(seed):
     rng = np.random.default_rng(seed)
