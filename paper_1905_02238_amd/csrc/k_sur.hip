@@ -184,6 +184,257 @@ __global__ __launch_bounds__(256) void k_conv_fwd(int64_t npix, const bf16* __re
   }
 }
 
+// Two floats as packed BF16 (round to nearest even), low half first.
+FSMI_DEV uint32_t pack2(float a, float b) {
+  const bf16 x = (bf16)a, y = (bf16)b;
+  return (uint32_t)__builtin_bit_cast(uint16_t, x) | ((uint32_t)__builtin_bit_cast(uint16_t, y) << 16);
+}
+
+// ---------------------------------------------------------------------------
+// Forward convolution, layers after the first: one wave = MT column tiles of
+// 16 output pixels x all COUT channels, so every weight fragment it loads
+// feeds MT products (MT = 4, or 2 for 128 channels to keep three waves per
+// SIMD).  Products are taken transposed (weights as the A operand), so a lane
+// ends with four consecutive channels of one pixel and stores 8 bytes at once.
+// npix is a multiple of 16.
+// ---------------------------------------------------------------------------
+template <int CIN, int COUT, int HIN>
+constexpr int conv_mt() { return COUT >= 128 ? 2 : 4; }
+
+template <int CIN, int COUT, int HIN>
+__global__ __launch_bounds__(256) void k_conv_fwd_m4(int64_t npix, const bf16* __restrict__ in,
+                                                     const bf16* __restrict__ W,
+                                                     const float* __restrict__ bias,
+                                                     bf16* __restrict__ out) {
+  constexpr int HOUT = HIN / 2, NT = COUT / 16, MT = conv_mt<CIN, COUT, HIN>();
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t base = ((int64_t)blockIdx.x * 4 + wave) * (16 * MT);
+  if (base >= npix) return;
+  const int n_mt = (int)min<int64_t>(MT, (npix - base) / 16);   // wave-uniform
+  const int i = lane & 15, g = lane >> 4;
+  int64_t pb[MT];
+  int poy[MT], pox[MT];
+#pragma unroll
+  for (int m = 0; m < MT; ++m) {
+    const int64_t p = min<int64_t>(base + 16 * m + i, npix - 1);
+    pb[m] = p / (HOUT * HOUT);
+    poy[m] = (int)((p / HOUT) % HOUT);
+    pox[m] = (int)(p % HOUT);
+  }
+  floatx4 acc[MT][NT];
+#pragma unroll
+  for (int m = 0; m < MT; ++m)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[m][t] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 1
+  for (int tap = 0; tap < 9; ++tap) {
+    const int ky = tap / 3, kx = tap % 3;
+#pragma unroll
+    for (int c0 = 0; c0 < CIN; c0 += 32) {
+      bf16x8 a[MT];
+#pragma unroll
+      for (int m = 0; m < MT; ++m) {
+        const int iy = 2 * poy[m] + ky - 1, ix = 2 * pox[m] + kx - 1;
+        const bool ok = iy >= 0 && iy < HIN && ix >= 0 && ix < HIN;
+        const bf16* ip = in + ((pb[m] * HIN + (ok ? iy : 0)) * HIN + (ok ? ix : 0)) * CIN;
+        a[m] = ok ? load8(ip + c0 + 8 * g) : zero8();
+      }
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const bf16x8 w = load8(W + ((16 * t + i) * 9 + tap) * CIN + c0 + 8 * g);
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+          if (m < n_mt) acc[m][t] = mfma(w, a[m], acc[m][t]);
+      }
+    }
+  }
+  // D[n][p]: channels 16t + 4g + r of pixel base + 16m + i
+  float bv[NT][4];
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) bv[t][r] = bias[16 * t + 4 * g + r];
+#pragma unroll
+  for (int m = 0; m < MT; ++m) {
+    if (m >= n_mt) break;
+    bf16* op = out + (base + 16 * m + i) * COUT + 4 * g;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      float o[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const float v = acc[m][t][r] + bv[t][r];
+        o[r] = v > 0.0f ? v : 0.0f;
+      }
+      uint2 w;
+      w.x = pack2(o[0], o[1]);
+      w.y = pack2(o[2], o[3]);
+      *reinterpret_cast<uint2*>(op + 16 * t) = w;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Inference: conv1 fused into conv2.  A workgroup owns 8 x 8 output pixels of
+// conv2 (all 64 channels) at a time: it gathers the 35 x 35 patch window those
+// pixels depend on, computes the 17 x 17 x 32 conv1 outputs of the window into
+// LDS (zero where conv1's 64 x 64 grid ends: conv2's zero padding), then conv2
+// from LDS, so conv1's activations never reach HBM.  The products are taken
+// transposed (weights as the A operand, activations as B), so a lane ends with
+// four consecutive channels of one pixel and stores them as one 8-byte word.
+// Persistent workgroups stage W2 in LDS once (laid out [tap][ci/8][co][8], so
+// the 16 lanes of a fragment read 16 consecutive 16-byte rows) and keep W1 in
+// registers; the next tile's patch gathers are issued before the current tile
+// is computed.
+// ---------------------------------------------------------------------------
+constexpr int kT2 = 8;                 // conv2 tile edge (output pixels)
+constexpr int kT1 = 2 * kT2 + 1;       // 17: conv1 window edge
+constexpr int kTP = 2 * kT1 + 1;       // 35: patch window edge
+constexpr int kA1Px = 40;              // bf16 per conv1 pixel in LDS (32 channels + 8 pad)
+constexpr int kW2Elems = 64 * 9 * 32;
+constexpr int kPatchPer = (kTP * kTP + 255) / 256;   // gathers per thread
+
+// Patch window of tile `tile` into registers: all gathers issue before any is
+// used (clamped addresses, selects after the loads).
+FSMI_DEV void gather_window(const PatchSrc& src, int64_t tile, int tid, float (&v)[kPatchPer]) {
+  const int64_t b = tile >> 4;
+  const int oy0 = kT2 * (int)((tile >> 2) & 3), ox0 = kT2 * (int)(tile & 3);
+  const int py0 = 4 * oy0 - 3, px0 = 4 * ox0 - 3;   // patch window origin
+  const int64_t cx0 = src.block(src.poses[4 * b]) - kPatch / 2 + px0;
+  const int64_t cy0 = src.block(src.poses[4 * b + 1]) - kPatch / 2 + py0;
+#pragma unroll
+  for (int k = 0; k < kPatchPer; ++k) {
+    const int e = tid + 256 * k;
+    const int r = e / kTP, c = e - (e / kTP) * kTP;
+    const int64_t cx = cx0 + c, cy = cy0 + r;
+    const bool on_map = cx >= 0 && cx < src.X && cy >= 0 && cy < src.Y;
+    const float m = src.map[on_map ? cx + src.X * cy : 0];
+    const bool in_patch = py0 + r >= 0 && py0 + r < kPatch && px0 + c >= 0 && px0 + c < kPatch;
+    v[k] = in_patch ? (on_map ? m : 0.5f) : 0.0f;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_conv12_fwd(int64_t n_tiles, PatchSrc src,
+                                                    const bf16* __restrict__ W1,
+                                                    const float* __restrict__ b1,
+                                                    const bf16* __restrict__ W2,
+                                                    const float* __restrict__ b2,
+                                                    bf16* __restrict__ act2) {
+  __shared__ __align__(16) bf16 sW2[kW2Elems];
+  __shared__ __align__(16) bf16 sP[kTP * kTP + 8];
+  __shared__ __align__(16) bf16 sA1[kT1 * kT1 * kA1Px];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int i = lane & 15, g = lane >> 4;
+  // W2 [co][tap][ci] -> LDS [tap][ci/8][co][8]
+  for (int e8 = tid; e8 < kW2Elems / 8; e8 += 256) {
+    const int co = e8 / 36, rem = e8 - co * 36, tap = rem >> 2, gg = rem & 3;
+    *reinterpret_cast<bf16x8*>(sW2 + ((tap * 4 + gg) * 64 + co) * 8) = load8(W2 + e8 * 8);
+  }
+  // A operand of conv1: A[n][k] = W1[16t + n][k], k = tap 8g + q (< 9)
+  bf16x8 w1[2];
+  float bias1[2][4], bias2[4][4];
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    w1[t] = zero8();
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int tap = 8 * g + q;
+      if (tap < 9) w1[t][q] = W1[(16 * t + i) * 9 + tap];
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) bias1[t][r] = b1[16 * t + 4 * g + r];
+  }
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) bias2[t][r] = b2[16 * t + 4 * g + r];
+  float v[kPatchPer];
+  if ((int64_t)blockIdx.x < n_tiles) gather_window(src, blockIdx.x, tid, v);
+  __syncthreads();
+  for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+    const int64_t b = tile >> 4;
+    const int oy0 = kT2 * (int)((tile >> 2) & 3), ox0 = kT2 * (int)(tile & 3);
+#pragma unroll
+    for (int k = 0; k < kPatchPer; ++k) {
+      const int e = tid + 256 * k;
+      if (e < kTP * kTP) sP[e] = (bf16)v[k];
+    }
+    __syncthreads();
+    if (tile + gridDim.x < n_tiles) gather_window(src, tile + gridDim.x, tid, v);
+    // conv1 on the window: 289 pixels in 19 column tiles of 16 (the last padded)
+    for (int m = wave; m < 19; m += 4) {
+      const int p = 16 * m + i;
+      const bool pv = p < kT1 * kT1;
+      const int pr = pv ? p / kT1 : 0, pc = pv ? p - (p / kT1) * kT1 : 0;
+      const int base = 2 * pr * kTP + 2 * pc;
+      bf16x8 x = zero8();   // B operand: taps 8g .. 8g + 7 of pixel p
+      if (g == 0) {
+        x[0] = sP[base];
+        x[1] = sP[base + 1];
+        x[2] = sP[base + 2];
+        x[3] = sP[base + kTP];
+        x[4] = sP[base + kTP + 1];
+        x[5] = sP[base + kTP + 2];
+        x[6] = sP[base + 2 * kTP];
+        x[7] = sP[base + 2 * kTP + 1];
+      } else if (g == 1) {
+        x[0] = sP[base + 2 * kTP + 2];
+      }
+      const int y1 = 2 * oy0 - 1 + pr, x1 = 2 * ox0 - 1 + pc;
+      const bool inside = pv && y1 >= 0 && y1 < 64 && x1 >= 0 && x1 < 64;
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        // D[n][p]: channels 16t + 4g + r of pixel p
+        const floatx4 d = mfma(w1[t], x, floatx4{0.f, 0.f, 0.f, 0.f});
+        float o[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const float val = d[r] + bias1[t][r];
+          o[r] = inside && val > 0.0f ? val : 0.0f;
+        }
+        if (pv) {
+          uint2 w;
+          w.x = pack2(o[0], o[1]);
+          w.y = pack2(o[2], o[3]);
+          *reinterpret_cast<uint2*>(sA1 + p * kA1Px + 16 * t + 4 * g) = w;
+        }
+      }
+    }
+    __syncthreads();
+    // conv2: wave w takes output pixels 16w .. 16w + 15 of the 8 x 8 tile
+    floatx4 acc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+    const int qy = (16 * wave + i) >> 3, qx = (16 * wave + i) & 7;
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+      const int ky = tap / 3, kx = tap % 3;
+      const bf16x8 x = load8(sA1 + ((2 * qy + ky) * kT1 + 2 * qx + kx) * kA1Px + 8 * g);
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        acc[t] = mfma(load8(sW2 + ((tap * 4 + g) * 64 + 16 * t + i) * 8), x, acc[t]);
+    }
+    const int oy = oy0 + qy, ox = ox0 + qx;
+    bf16* op = act2 + ((b * 32 + oy) * 32 + ox) * 64 + 4 * g;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      float o[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const float val = acc[t][r] + bias2[t][r];
+        o[r] = val > 0.0f ? val : 0.0f;
+      }
+      uint2 w;
+      w.x = pack2(o[0], o[1]);
+      w.y = pack2(o[2], o[3]);
+      *reinterpret_cast<uint2*>(op + 16 * t) = w;
+    }
+    __syncthreads();   // sP and sA1 are rewritten by the next tile
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Input-gradient pass: d_in[p][ci] = [act_in[p][ci] > 0] *
 //   sum_{tap, co} W[co][tap][ci] d_out[(p - tap)/2][co], only where p + 1 - tap
@@ -699,17 +950,34 @@ template <int L, bool FIRST>
 static void conv_fwd(fsmi_sur net, int64_t nb, PatchSrc src) {
   constexpr LayerDims d = kL[L];
   const int64_t npix = nb * (d.hin / 2) * (d.hin / 2);
-  const bf16* in = FIRST ? nullptr : net->act[L];
-  const int64_t blocks = (npix + 63) / 64;
-  hipLaunchKernelGGL((k_conv_fwd<d.cin, d.cout, d.hin, FIRST>), dim3((unsigned)blocks), dim3(256), 0,
-                     net->ctx->stream, npix, in, src, net->Wbf + wbf_off(L), net->P + b_off(L),
-                     net->act[L + 1]);
+  if constexpr (FIRST) {
+    const int64_t blocks = (npix + 63) / 64;
+    hipLaunchKernelGGL((k_conv_fwd<d.cin, d.cout, d.hin, true>), dim3((unsigned)blocks), dim3(256),
+                       0, net->ctx->stream, npix, nullptr, src, net->Wbf + wbf_off(L),
+                       net->P + b_off(L), net->act[L + 1]);
+  } else {
+    constexpr int per_block = 4 * 16 * conv_mt<d.cin, d.cout, d.hin>();   // 4 waves
+    const int64_t blocks = (npix + per_block - 1) / per_block;
+    hipLaunchKernelGGL((k_conv_fwd_m4<d.cin, d.cout, d.hin>), dim3((unsigned)blocks), dim3(256), 0,
+                       net->ctx->stream, npix, net->act[L], net->Wbf + wbf_off(L), net->P + b_off(L),
+                       net->act[L + 1]);
+  }
 }
 
 // Forward of nb (<= max_batch) poses; predictions (standardised) in ypred.
 static hipError_t sur_fwd_batch(fsmi_sur net, int64_t nb, PatchSrc src, bool save) {
-  conv_fwd<0, true>(net, nb, src);
-  conv_fwd<1, false>(net, nb, src);
+  if (save) {   // training keeps conv1's activations for the backward pass
+    conv_fwd<0, true>(net, nb, src);
+    conv_fwd<1, false>(net, nb, src);
+  } else {
+    static_assert(kL[0].cout == 32 && kL[1].cin == 32 && kL[1].cout == 64 && kL[1].hin == 64,
+                  "k_conv12_fwd is written for conv1 1->32 on 128^2 and conv2 32->64");
+    const int64_t n_tiles = nb * 16;
+    const int grid = (int)std::min<int64_t>(n_tiles, (int64_t)net->ctx->num_cu * 2);
+    hipLaunchKernelGGL(k_conv12_fwd, dim3(grid), dim3(256), 0, net->ctx->stream, n_tiles, src,
+                       net->Wbf + wbf_off(0), net->P + b_off(0), net->Wbf + wbf_off(1),
+                       net->P + b_off(1), net->act[2]);
+  }
   conv_fwd<2, false>(net, nb, src);
   conv_fwd<3, false>(net, nb, src);
   conv_fwd<4, false>(net, nb, src);
