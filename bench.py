@@ -9,7 +9,7 @@ per-pose FP64 sum).  Inputs are resident in HBM before timing starts.
 
 Other variants and workloads are measured once each and reported as extra
 fields (Approx-FSMI, Uniform-FSMI on the same poses; the uneven 100k-beam
-batch; 3D FSMI-RLE / Approx-FSMI-RLE on the voxel map; the 200 x 200 FP64 and
+batch; 3D FSMI-RLE / Approx-FSMI-RLE / Uniform-FSMI-RLE on the voxel map; the 200 x 200 FP64 and
 FP32 single-pose latency; the learned surrogate's rank path).  ``--quick``
 skips those extras and shrinks the CPU baseline sample.
 
@@ -253,7 +253,8 @@ def main():
         gpu["voxels"] = vw
         nv = vp.shape[0] * vb.shape[0]
         for name, p in (("rle_exact_3d", F.params(variant=F.FSMI_EXACT)),
-                        ("rle_approx_delta6_3d", F.params(variant=F.FSMI_APPROX, trunc_delta=6))):
+                        ("rle_approx_delta6_3d", F.params(variant=F.FSMI_APPROX, trunc_delta=6)),
+                        ("rle_uniform_h4_3d", F.params(variant=F.FSMI_UNIFORM, uniform_h=4))):
             dt = timed(lambda: ctx.fsmi_eval_poses(p, vx, vp, vb, vw["sigma"], vw["R"], vw["w"]), reps=2)
             extras[name] = {"beams_per_s": nv / dt, "ms": dt * 1e3, "poses": vp.shape[0]}
             gpu[name] = ctx.fsmi_eval_poses(p, vx, vp, vb, vw["sigma"], vw["R"], vw["w"],
@@ -341,7 +342,8 @@ def oracle_leg(out, gpu, wl, W, args, ctx, F, t):
                 max_rel_pose=float(_rel(gp.cpu().numpy(), rp).max()))
         vw = gpu["voxels"]
         for name, exact, kw in (("rle_exact_3d", True, {}),
-                                ("rle_approx_delta6_3d", False, {"Delta": 6})):
+                                ("rle_approx_delta6_3d", False, {"Delta": 6}),
+                                ("rle_uniform_h4_3d", True, {"kind": O.K_UNIFORM, "H": 4})):
             rp, rb = O.eval_poses_3d(exact, vw["vox"], vw["poses"][:1], vw["beam_dir"], vw["sigma"],
                                      vw["R"], vw["w"], threads=thr, **kw)
             gp, gbm = gpu[name]

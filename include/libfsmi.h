@@ -138,7 +138,8 @@ fsmi_status fsmi_raycast(fsmi_ctx ctx, const fsmi_map* map, int32_t mode, int64_
    threshold is 512 cells (FP32) or 256 (FP64), or the one the autotuner of
    fsmi_plan_eval_beams chose on this context for the same precision, variant
    and boundary kind.  Waits once for the device (the longest beam sizes the
-   workgroup's LDS); fsmi_plan_eval_beams avoids that wait. */
+   workgroup's LDS); fsmi_plan_eval_beams avoids that wait.  A beam holds at
+   most 7679 cells (FP32) or 5485 (FP64), else FSMI_E_CAPACITY. */
 fsmi_status fsmi_eval_beams(fsmi_ctx ctx, const fsmi_params* params, int64_t n_beams,
                             const int64_t* off, const float* occ, const double* bound,
                             const float* sigma, double* mi);
@@ -184,7 +185,9 @@ void fsmi_plan_destroy(fsmi_plan plan);
    Beam b has runs run_off[b] .. run_off[b+1]-1 with value run_occ[u] and
    length run_len[u] >= 1 (Eq. occup_rle); sigma_prime[b] = sigma / w in
    virtual cells.  EXACT gives FSMI-RLE (Thm 5), APPROX gives Approx-FSMI-RLE
-   (Thm 6) with the kernel truncated at |d| <= Delta; the value equals the
+   (Thm 6) with the kernel truncated at |d| <= Delta, UNIFORM gives
+   Uniform-FSMI-RLE (uniform noise of half-width H cells, the Thm 5 structure
+   with the uniform kernel; params.kernel is ignored); the value equals the
    plain algorithm on the expanded beam with the chosen kernel. */
 fsmi_status fsmi_rle_eval_beams(fsmi_ctx ctx, const fsmi_params* params, int64_t n_beams,
                                 const int64_t* run_off, const float* run_occ,
@@ -198,9 +201,12 @@ fsmi_status fsmi_rle_eval_beams(fsmi_ctx ctx, const fsmi_params* params, int64_t
    3D map: poses [n_poses][5] = {x, y, z, cos(yaw), sin(yaw)}; beam_dir
    [n_beams][3]; world direction (c*bx - s*by, s*bx + c*by, bz).  Each beam is
    sampled as FSMI_RAY_RLE with cell width w and evaluated by the run engine
-   with sigma' = sigma / w (EXACT: FSMI-RLE, APPROX: Approx-FSMI-RLE).
+   with sigma' = sigma / w (EXACT: FSMI-RLE, APPROX: Approx-FSMI-RLE,
+   UNIFORM: Uniform-FSMI-RLE with half-width H virtual cells).
    mi_pose[p] = sum over the pose's beams (Sec. 2.4; FP64, fixed order).
-   mi_beam [n_poses][n_beams] (FP64) may be NULL. */
+   mi_beam [n_poses][n_beams] (FP64) may be NULL.  One wave keeps a beam in
+   LDS: 2D max_range <= 4000 cells (FP32) or < 3873 (FP64), 3D
+   floor(max_range / w) <= 4000, else FSMI_E_CAPACITY. */
 fsmi_status fsmi_eval_poses(fsmi_ctx ctx, const fsmi_params* params, const fsmi_map* map,
                             int64_t n_poses, const double* poses, int64_t n_beams,
                             const double* beam_dir, double sigma, double max_range, double w,

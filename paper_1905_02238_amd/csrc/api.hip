@@ -291,8 +291,6 @@ fsmi_status fsmi_rle_eval_beams(fsmi_ctx ctx, const fsmi_params* params, int64_t
   if (!ctx) return FSMI_E_INVAL;
   fsmi_status st;
   if (!check_params(ctx, params, &st)) return st;
-  if (params->variant == FSMI_UNIFORM)
-    return fail(ctx, FSMI_E_UNSUPPORTED, "Uniform-FSMI-RLE is not built");
   if (n_beams < 0) return fail(ctx, FSMI_E_INVAL, "n_beams < 0");
   if (n_beams == 0) return FSMI_OK;
   if (!run_off || !run_occ || !run_len || !sigma_prime || !mi)
@@ -328,15 +326,16 @@ fsmi_status fsmi_eval_poses(fsmi_ctx ctx, const fsmi_params* params, const fsmi_
     return fail(ctx, FSMI_E_CAPACITY, "too many items");
   (void)hipSetDevice(ctx->device);
   if (map->ndim == 2) {
+    // one wave holds a beam's walk, boundaries and occupancies in LDS
     if (max_range > 4000.0) return fail(ctx, FSMI_E_CAPACITY, "max_range above 4000 cells");
+    if (params->precision == FSMI_FP64 && max_range >= 3873.0)
+      return fail(ctx, FSMI_E_CAPACITY, "max_range above 3872 cells in FP64");
     return from_hip(ctx,
                     launch_eval_poses_2d(ctx, to_const(params), map->occ, map->dims[0], map->dims[1],
                                          n_poses, poses, n_beams, beam_dir, sigma, max_range,
                                          mi_pose, mi_beam),
                     "eval_poses_2d");
   }
-  if (params->variant == FSMI_UNIFORM)
-    return fail(ctx, FSMI_E_UNSUPPORTED, "Uniform-FSMI-RLE is not built");
   if (!(w > 0.0) || !std::isfinite(w)) return fail(ctx, FSMI_E_INVAL, "w must be finite and > 0");
   if (floor(max_range / w) > 4000.0) return fail(ctx, FSMI_E_CAPACITY, "more than 4000 virtual cells per beam");
   return from_hip(ctx,

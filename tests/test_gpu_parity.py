@@ -210,6 +210,18 @@ def test_eval_beams_invalid_args(ctx):
 
 
 # ---------------------------------------------------------------------------
+@pytest.mark.parametrize("H", [0, 4])
+def test_uniform_rle_eval_beams_parity(ctx, H):
+    print(f"[gpu] uniform rle H={H}", flush=True)
+    off, ro, rl, sp = W.rle_beams(60, seed=4, run_lo=1, run_hi=40, n_runs_lo=0, n_runs_hi=20)
+    prm = F.params(variant=F.FSMI_UNIFORM, uniform_h=H)
+    mi = ctx.fsmi_rle_eval_beams(prm, dev(off), dev(ro), dev(rl), dev(sp))
+    torch.cuda.synchronize()
+    ctx.fsmi_sync()
+    ref = O.rle_eval_beams(True, off, ro, rl, sp, kind=O.K_UNIFORM, H=H)
+    assert rel_err(mi.cpu().numpy(), ref) <= TOL32
+
+
 @pytest.mark.parametrize("exact", [True, False])
 @pytest.mark.parametrize("kernel", [F.FSMI_KERNEL_ERF, F.FSMI_KERNEL_DENSITY])
 def test_rle_eval_beams_parity(ctx, exact, kernel):
@@ -254,17 +266,20 @@ def test_poses_grid_large_sample(ctx, variant):
     assert rel_err(mp.cpu().numpy(), rp) <= TOL32
 
 
-@pytest.mark.parametrize("exact", [True, False])
-def test_poses_voxels_small(ctx, exact):
-    print(f"[gpu] voxels exact={exact}", flush=True)
+@pytest.mark.parametrize("variant", [F.FSMI_EXACT, F.FSMI_APPROX, F.FSMI_UNIFORM])
+def test_poses_voxels_small(ctx, variant):
+    print(f"[gpu] voxels variant={variant}", flush=True)
     vox, lab = W.voxel_map(64, 64, 32, seed=9, n_boxes=12, n_pillars=8, block=16, unknown_frac=0.1)
     poses = W.poses_in_free_space_3d(lab, 3, seed=9)
     bd = W.beam_dirs_3d(8, 32)
-    prm = F.params(variant=F.FSMI_EXACT if exact else F.FSMI_APPROX, trunc_delta=6)
+    prm = F.params(variant=variant, trunc_delta=6, uniform_h=4)
     mp, mb = ctx.fsmi_eval_poses(prm, dev(vox), dev(poses), dev(bd), 2.0, 80.0, 1.0, want_beams=True)
     torch.cuda.synchronize()
     ctx.fsmi_sync()
-    rp, rb = O.eval_poses_3d(exact, vox, poses, bd, 2.0, 80.0, 1.0, Delta=6)
+    if variant == F.FSMI_UNIFORM:
+        rp, rb = O.eval_poses_3d(True, vox, poses, bd, 2.0, 80.0, 1.0, kind=O.K_UNIFORM, H=4)
+    else:
+        rp, rb = O.eval_poses_3d(variant == F.FSMI_EXACT, vox, poses, bd, 2.0, 80.0, 1.0, Delta=6)
     assert rel_err(mb.cpu().numpy(), rb) <= TOL32
     assert rel_err(mp.cpu().numpy(), rp) <= TOL32
 
@@ -278,3 +293,44 @@ def test_pose_outside_map_latches(ctx):
         ctx.fsmi_sync()
     got = mp.cpu().numpy()
     assert np.isfinite(got[0]) and np.isnan(got[1])
+
+
+# ---------------------------------------------------------------------------
+# Maximum sizes: the longest beam a workgroup holds, and the longest range a
+# pose's wave holds, against the oracle; one past each limit is refused.
+@pytest.mark.parametrize("prec,n_max,tol", [(F.FSMI_FP32, 7679, TOL32), (F.FSMI_FP64, 5485, TOL64)])
+def test_eval_beams_longest_beam(ctx, prec, n_max, tol):
+    print(f"[gpu] eval_beams longest beam {n_max} precision {prec}", flush=True)
+    lens = [n_max, 3, 0, 1]
+    off, occ, _, sigma = _beam_batch(401, len(lens), lens, False)
+    occ[:n_max] *= 0.02                 # keep P(e_j) alive along the whole beam
+    prm = F.params(precision=prec)
+    mi = ctx.fsmi_eval_beams(prm, dev(off), dev(occ), dev(sigma))
+    torch.cuda.synchronize()
+    ctx.fsmi_sync()
+    assert rel_err(mi.cpu().numpy(), O.eval_beams(O.EXACT, off, occ, sigma)) <= tol
+    off2 = np.array([0, n_max + 1], np.int64)
+    occ2 = np.full(n_max + 1, 0.01, np.float32)
+    with pytest.raises(F.FsmiError) as e:
+        ctx.fsmi_eval_beams(prm, dev(off2), dev(occ2), dev(sigma[:1]))
+    assert e.value.status == F.FSMI_E_CAPACITY
+
+
+@pytest.mark.parametrize("prec,R,tol", [(F.FSMI_FP32, 4000.0, TOL32), (F.FSMI_FP64, 3872.0, TOL64)])
+def test_poses_2d_at_max_range(ctx, prec, R, tol):
+    print(f"[gpu] poses 2D at max range {R} precision {prec}", flush=True)
+    size = 8200
+    grid = np.random.default_rng(402).uniform(0.0, 0.02, (size, size)).astype(np.float32)
+    poses = np.array([[4100.5, 4100.25, 1.0, 0.0], [4099.75, 4101.5, 1.0, 0.0]])
+    th = np.array([0.0, np.pi / 4, 1.9, 3.9])
+    bdir = np.stack([np.cos(th), np.sin(th)], axis=1)
+    prm = F.params(precision=prec)
+    mp, mb = ctx.fsmi_eval_poses(prm, dev(grid), dev(poses), dev(bdir), 3.0, R, want_beams=True)
+    torch.cuda.synchronize()
+    ctx.fsmi_sync()
+    rp, rb = O.eval_poses_2d(O.EXACT, grid, poses, bdir, 3.0, R)
+    assert rel_err(mb.cpu().numpy(), rb) <= tol
+    assert rel_err(mp.cpu().numpy(), rp) <= tol
+    with pytest.raises(F.FsmiError) as e:
+        ctx.fsmi_eval_poses(prm, dev(grid), dev(poses), dev(bdir), 3.0, R + 1.0)
+    assert e.value.status == F.FSMI_E_CAPACITY

@@ -274,13 +274,24 @@ def _runs(seed, nr=7, lmax=6):
     return rng.uniform(0.05, 0.95, nr), rng.integers(1, lmax + 1, nr)
 
 
-@pytest.mark.parametrize("kind", [O.K_ERF, O.K_DENSITY])
+@pytest.mark.parametrize("kind", [O.K_ERF, O.K_DENSITY, O.K_UNIFORM])
 @pytest.mark.parametrize("seed", range(3))
 def test_thm5_equals_expanded(kind, seed):
     ro, L = _runs(30 + seed)
-    a = O.rle_expanded(ro, L, 1.7, kind)
-    b = O.rle_thm5(ro, L, 1.7, kind)
+    a = O.rle_expanded(ro, L, 1.7, kind, H=3)
+    b = O.rle_thm5(ro, L, 1.7, kind, H=3)
     assert abs(a - b) <= 1e-14 * a
+
+
+@pytest.mark.parametrize("H", [0, 2, 5])
+def test_uniform_rle_is_alg4_on_the_expanded_beam(H):
+    """Uniform-FSMI-RLE: the uniform kernel on runs gives Alg 4 on the expanded
+    beam, which the uniform-noise integration pin fixes."""
+    ro, L = _runs(60 + H, nr=8, lmax=7)
+    expanded = np.repeat(ro, L)
+    ref = O.fsmi_uniform(expanded, H)
+    assert abs(O.rle_expanded(ro, L, 1.0, O.K_UNIFORM, H=H) - ref) <= 1e-14 * ref
+    assert abs(O.rle_thm5(ro, L, 1.0, O.K_UNIFORM, H=H) - ref) <= 1e-13 * ref
 
 
 def test_rle_runs_of_one_are_plain_fsmi():
