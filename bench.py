@@ -44,12 +44,12 @@ SLOTS_PER_PAIR = 14.5
 # rocprofv3 --pmc passes (profiles/k_poses2d_exact_grid2048_4096x360.md):
 # FETCH_SIZE and WRITE_SIZE in KiB per dispatch, each scaled by what the same
 # counter reads for a plain 256 MiB device copy in the same run (FETCH_SIZE
-# 131091 KiB for 262144 KiB read, WRITE_SIZE 262144 KiB for 262144 KiB written).
+# 131088 KiB for 262144 KiB read, WRITE_SIZE 262144 KiB for 262144 KiB written).
 # They describe the kernel built from the sources hashed here; with any other
 # sources the bench reports traffic as null.
-TRAFFIC = {"fetch_kib": 9.72271e6, "write_kib": 90297.1,
-           "fetch_scale": 262144.0 / 131091.0, "write_scale": 1.0,
-           "sources_sha256": "224468929ef7ef2277c5a3b3d0f015fdacb1d2406ba968cf8bdf3d9320aec072"}
+TRAFFIC = {"fetch_kib": 9.72664e6, "write_kib": 90446.7,
+           "fetch_scale": 262144.0 / 131088.0, "write_scale": 1.0,
+           "sources_sha256": "0ccfc424f84e6c609e176782c4b2ab56cd56991ab607e25a6836aca31346dfcf"}
 TRAFFIC_SOURCES = ("paper_1905_02238_amd/csrc/k_pose.hip", "paper_1905_02238_amd/csrc/beam_dev.h",
                    "paper_1905_02238_amd/csrc/ray_dev.h", "paper_1905_02238_amd/csrc/fsmi_dev.h",
                    "paper_1905_02238_amd/csrc/fsmi_internal.h", "paper_1905_02238_amd/build.py")
@@ -94,6 +94,12 @@ def parse():
     ap.add_argument("--profile-step", action="store_true",
                     help="for counter runs: one plain 256 MiB device copy (the traffic "
                          "calibration), then exactly one timed-workload step, nothing else")
+    ap.add_argument("--profile-surrogate", action="store_true",
+                    help="for kernel traces: surrogate forward over 65 536 candidates (3 times) "
+                         "and one fsmi_rank_poses, random-initialised weights, nothing else")
+    ap.add_argument("--profile-uneven", action="store_true",
+                    help="for kernel traces: the 100k uneven beams through an autotuned, "
+                         "graph-captured plan (5 launches), nothing else")
     return ap.parse_args()
 
 
@@ -114,6 +120,28 @@ def main():
     dev = torch.device("cuda:0")
     ctx = F.context(0)
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+    if args.profile_surrogate:
+        wl = W.grid_large(n_poses=65536)
+        g, p, bd = t(wl["grid"]), t(wl["poses"]), t(wl["beam_dir"])
+        net = F.Surrogate(ctx, seed=3, max_batch=8192)
+        for _ in range(3):
+            net.forward(g, p)
+        ctx.fsmi_rank_poses(F.params(), net, g, p, bd, wl["sigma"], wl["R"], 656)
+        torch.cuda.synchronize()
+        ctx.fsmi_sync()
+        log("[bench] surrogate profile done")
+        return
+    if args.profile_uneven:
+        off, occ, sg = W.uneven_beams(100000, seed=W.SEED_BASE + 3)
+        plan = F.Plan(ctx, F.params(), t(off), t(occ), t(sg), autotune=True, graph=True)
+        for _ in range(5):
+            plan.launch()
+        torch.cuda.synchronize()
+        ctx.fsmi_sync()
+        log(f"[bench] uneven profile done (wave_max {plan.info()['wave_max']})")
+        plan.close()
+        return
 
     log(f"[bench] generating the 2048^2 room grid and {args.poses} poses")
     wl = W.grid_large(n_poses=args.poses)

@@ -19,14 +19,18 @@
 
 namespace fsmi {
 
-// Count of entries of the increasing array A[0..N) that are < key.
-FSMI_DEV int lower_count(const double* A, int N, double key) {
-  int pos = 0;
-  int step = 1;
-  while (step * 2 <= N) step *= 2;
-  for (; step > 0; step >>= 1)
-    if (pos + step <= N && A[pos + step - 1] < key) pos += step;
-  return pos;
+// Count of entries of the non-decreasing array A[0..N) that are < key, where
+// A holds one axis's face times, A[m] ~ A[0] + m / rate (rate = |d| of that
+// axis).  The spacing gives the count to within rounding; the two loops then
+// move it to the exact boundary with the true comparisons, so the result is
+// exact for any input (and is usually reached with one or two reads).
+FSMI_DEV int count_below(const double* A, int N, double key, double rate) {
+  if (N <= 0) return 0;
+  const double e = (key - A[0]) * rate;
+  int c = !(e > 0.0) ? 0 : (e >= (double)N ? N : (int)ceil(e));
+  while (c > 0 && A[c - 1] >= key) --c;
+  while (c < N && A[c] < key) ++c;
+  return c;
 }
 
 // Per-axis capacity for max range R: at most floor(R) + 3 faces per axis.
@@ -69,6 +73,7 @@ FSMI_DEV Dda2dResult dda2d_wave(int64_t X, int64_t Y, double px, double py, doub
   const double fy0 = sy > 0 ? (double)(cy0 + 1) : (double)cy0;
   const double ix = sx ? 1.0 / dx : 0.0;
   const double iy = sy ? 1.0 / dy : 0.0;
+  const double adx = fabs(dx), ady = fabs(dy);   // events per unit of t, per axis
   const int64_t ex = sx > 0 ? X - 1 - cx0 : cx0;   // x event index that leaves the map
   const int64_t ey = sy > 0 ? Y - 1 - cy0 : cy0;
   int nx = 0, ny = 0;
@@ -100,7 +105,7 @@ FSMI_DEV Dda2dResult dda2d_wave(int64_t X, int64_t Y, double px, double py, doub
     int tie = 0;
     if (i < Nx) {
       const double t = tx[i];
-      const int c = lower_count(ty, Ny, t);
+      const int c = count_below(ty, Ny, t, ady);
       tie = (c < Ny && ty[c] == t) ? 1 : 0;
     }
     const int inc = wave_scan_incl<OpAdd>(tie);
@@ -120,7 +125,7 @@ FSMI_DEV Dda2dResult dda2d_wave(int64_t X, int64_t Y, double px, double py, doub
   // x events
   for (int i = lane; i < Nx; i += kWave) {
     const double t = tx[i];
-    const int c = lower_count(ty, Ny, t);
+    const int c = count_below(ty, Ny, t, ady);
     const int tie = (c < Ny && ty[c] == t) ? 1 : 0;
     const int r = i + c - tiep[i];
     const int64_t cx = cx0 + (int64_t)sx * (i + 1);
@@ -132,7 +137,7 @@ FSMI_DEV Dda2dResult dda2d_wave(int64_t X, int64_t Y, double px, double py, doub
   // y events that do not tie with an x event
   for (int m = lane; m < Ny; m += kWave) {
     const double t = ty[m];
-    const int c = lower_count(tx, Nx, t);
+    const int c = count_below(tx, Nx, t, adx);
     if (c < Nx && tx[c] == t) continue;
     const int r = m + c - tiep[c];
     const int64_t cy = cy0 + (int64_t)sy * (m + 1);
