@@ -13,6 +13,9 @@
 namespace fsmi {
 
 constexpr int kWave = 64;
+// Longest run of (pose, beam) items one queue ticket takes in the fused pose
+// kernels (guided self-scheduling, run_length below).
+constexpr int kMaxRun = 32;
 
 // Bits latched into the device status word.
 enum : uint32_t {
@@ -47,6 +50,33 @@ FSMI_DEV int wave_pop(int32_t* counter) {
   const int old = atomicAdd(counter, inc);
   return __builtin_amdgcn_readfirstlane(old);
 }
+// Takes the next k items (k wave-uniform) from a 64-bit queue head: returns the
+// first, the same in every lane.
+FSMI_DEV int64_t wave_take64(int32_t* counter_pair, int64_t k) {
+  unsigned long long* c = reinterpret_cast<unsigned long long*>(counter_pair);
+  const unsigned long long inc = __lane_id() == 0 ? (unsigned long long)k : 0ull;
+  const unsigned long long old = atomicAdd(c, inc);
+  const int lo = __builtin_amdgcn_readfirstlane((int)(old & 0xffffffffull));
+  const int hi = __builtin_amdgcn_readfirstlane((int)(old >> 32));
+  return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+// The same on a 32-bit queue head.
+FSMI_DEV int wave_take(int32_t* counter, int k) {
+  const int inc = __lane_id() == 0 ? k : 0;
+  const int old = atomicAdd(counter, inc);
+  return __builtin_amdgcn_readfirstlane(old);
+}
+
+// Guided self-scheduling: a quarter of the remaining items' share per wave,
+// between 1 and kMaxRun, so runs are long (few atomics on the queue head)
+// while the queue is full and single items at the end (the last, possibly
+// costly, items still spread over all waves).
+FSMI_DEV int64_t run_length(int64_t n_items, int64_t taken, int64_t n_waves) {
+  const int64_t r = (n_items - taken) / (4 * n_waves);
+  return r < 1 ? 1 : (r > kMaxRun ? kMaxRun : r);
+}
+
 FSMI_DEV int64_t wave_pop64(int32_t* counter_pair) {
   unsigned long long* c = reinterpret_cast<unsigned long long*>(counter_pair);
   const unsigned long long inc = __lane_id() == 0 ? 1ull : 0ull;

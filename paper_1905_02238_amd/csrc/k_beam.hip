@@ -120,9 +120,18 @@ __global__ __launch_bounds__(kWave* kNW) void k_eval_short(BeamArgs a) {
   const int n_long = __builtin_amdgcn_readfirstlane(a.counters[2]);
   const int n_short = (int)a.n_beams - n_long;
   char* my = lds + (size_t)wave * ((size_t)a.cap_wave * bytes_per_cell<T>() + 16);
-  for (int it = wave_pop(&a.counters[1]); it < n_short; it = wave_pop(&a.counters[1])) {
-    const int b = __builtin_amdgcn_readfirstlane(a.order[n_long + it]);
-    process_beam<false, T>(a, b, my, a.cap_wave, nullptr, nullptr, lane);
+  // runs of beams (guided self-scheduling): neighbours in the order have
+  // similar lengths, and the queue head is touched once per run
+  const int64_t n_waves = (int64_t)gridDim.x * kNW;
+  int k = (int)run_length(n_short, 0, n_waves);
+  for (int start = wave_take(&a.counters[1], k); start < n_short;
+       start = wave_take(&a.counters[1], k)) {
+    const int end = min(start + k, n_short);
+    k = (int)run_length(n_short, end, n_waves);
+    for (int it = start; it < end; ++it) {
+      const int b = __builtin_amdgcn_readfirstlane(a.order[n_long + it]);
+      process_beam<false, T>(a, b, my, a.cap_wave, nullptr, nullptr, lane);
+    }
   }
 }
 

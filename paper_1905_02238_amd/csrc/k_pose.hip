@@ -57,41 +57,71 @@ __global__ __launch_bounds__(kWave) void k_poses2d(Pose2dArgs a) {
   double* sL = reinterpret_cast<double*>(lds + pose2d_region1<T>(a.capa, a.ecap));
   float* so = reinterpret_cast<float*>(sL + a.ecap + 1);
   const int64_t n_items = a.n_poses * a.n_beams;
-  for (int64_t it = wave_pop64(a.counter); it < n_items; it = wave_pop64(a.counter)) {
-    const int64_t p = it / a.n_beams, b = it - p * a.n_beams;
-    const double* ps = a.poses + 4 * p;
-    const double bx = a.beam_dir[2 * b], by = a.beam_dir[2 * b + 1];
-    const double m1 = ps[2] * bx, m2 = ps[3] * by, m3 = ps[3] * bx, m4 = ps[2] * by;
-    const double dx = m1 - m2, dy = m3 + m4;
-    const float* map = a.map;
-    auto emit = [&](int r, double t, int c) {
-      sL[r + 1] = t > 0.0 ? t : 0.0;
-      so[r + 1] = c >= 0 ? map[c] : 0.0f;
-    };
-    const Dda2dResult res =
-        dda2d_wave(a.X, a.Y, ps[0], ps[1], dx, dy, a.R, a.capa, a.ecap, tx, ty, tie, emit, lane);
-    double v;
-    if (res.n < 0) {
-      v = __builtin_nan("");
-      if (lane == 0) latch(a.status, res.n == -1 ? kErrPose : kErrCap);
-    } else {
-      if (lane == 0) {
-        sL[0] = 0.0;
-        so[0] = map[res.cell0];
-        sL[res.skip0 + res.n] = res.lend;
+  // runs of items from the queue (guided self-scheduling); k, start and the
+  // loop bounds are wave-uniform
+  const int64_t n_waves = gridDim.x;
+  int64_t k = run_length(n_items, 0, n_waves);
+  for (int64_t start = wave_take64(a.counter, k); start < n_items;
+       start = wave_take64(a.counter, k)) {
+    const int64_t it_end = min<int64_t>(start + k, n_items);
+    k = run_length(n_items, it_end, n_waves);
+    for (int64_t it = start; it < it_end; ++it) {
+      const int64_t p = it / a.n_beams, b = it - p * a.n_beams;
+      const double* ps = a.poses + 4 * p;
+      const double bx = a.beam_dir[2 * b], by = a.beam_dir[2 * b + 1];
+      const double m1 = ps[2] * bx, m2 = ps[3] * by, m3 = ps[3] * bx, m4 = ps[2] * by;
+      const double dx = m1 - m2, dy = m3 + m4;
+      const float* map = a.map;
+      // the walk records entry distances and cell indices (in o's slots); the
+      // occupancies are gathered afterwards, several loads in flight per lane
+      int* sc = reinterpret_cast<int*>(so);
+      auto emit = [&](int r, double t, int c) {
+        sL[r + 1] = t > 0.0 ? t : 0.0;
+        sc[r + 1] = c;
+      };
+      const Dda2dResult res =
+          dda2d_wave(a.X, a.Y, ps[0], ps[1], dx, dy, a.R, a.capa, a.ecap, tx, ty, tie, emit, lane);
+      double v;
+      if (res.n < 0) {
+        v = __builtin_nan("");
+        if (lane == 0) latch(a.status, res.n == -1 ? kErrPose : kErrCap);
+      } else {
+        // cells 1 .. skip0 + n - 1 were entered by events before the walk's end
+        const int hi = res.skip0 + res.n;
+        for (int base = 1; base < hi; base += 4 * kWave) {
+          int c[4];
+          float o[4];
+  #pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int i = base + u * kWave + lane;
+            c[u] = i < hi ? sc[i] : -1;
+          }
+  #pragma unroll
+          for (int u = 0; u < 4; ++u) o[u] = map[c[u] >= 0 ? c[u] : 0];
+  #pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int i = base + u * kWave + lane;
+            if (i < hi) so[i] = c[u] >= 0 ? o[u] : 0.0f;
+          }
+        }
+        if (lane == 0) {
+          sL[0] = 0.0;
+          so[0] = map[res.cell0];
+          sL[res.skip0 + res.n] = res.lend;
+        }
+        wave_sync();
+        CoreLds L;
+        L.A = sL + res.skip0;
+        L.C = r1;
+        L.P = r1 + sizeof(T) * (size_t)a.ecap;
+        bool bad;
+        v = beam_core<1, false, T>(a.ec, res.n, so + res.skip0, true, a.sigma, L, nullptr, nullptr,
+                                   lane, false, &bad);
+        if (bad && lane == 0) latch(a.status, kErrOcc);
       }
+      if (lane == 0) a.mi_beam[it] = v;
       wave_sync();
-      CoreLds L;
-      L.A = sL + res.skip0;
-      L.C = r1;
-      L.P = r1 + sizeof(T) * (size_t)a.ecap;
-      bool bad;
-      v = beam_core<1, false, T>(a.ec, res.n, so + res.skip0, true, a.sigma, L, nullptr, nullptr,
-                                 lane, false, &bad);
-      if (bad && lane == 0) latch(a.status, kErrOcc);
     }
-    if (lane == 0) a.mi_beam[it] = v;
-    wave_sync();
   }
 }
 

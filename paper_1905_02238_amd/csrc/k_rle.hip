@@ -81,28 +81,36 @@ __global__ __launch_bounds__(kWave) void k_rle_beams(RleArgs a) {
   float* so;
   const CoreLds L = carve_rle<T>(lds, a.cap, &so);
   const int lane = threadIdx.x;
-  for (int64_t it = wave_pop64(a.counter); it < a.n_beams; it = wave_pop64(a.counter)) {
-    const int64_t r0 = a.run_off[it], r1 = a.run_off[it + 1];
-    double v;
-    if (r1 < r0) {
-      v = __builtin_nan("");
-      if (lane == 0) latch(a.status, kErrLen);
-    } else {
-      const int n = expand_runs(a.run_occ, a.run_len, r0, r1, a.cap, so, nullptr, lane);
-      if (n < 0) {
+  // runs of beams from the queue (guided self-scheduling)
+  const int64_t n_waves = gridDim.x;
+  int64_t kr = run_length(a.n_beams, 0, n_waves);
+  for (int64_t start = wave_take64(a.counter, kr); start < a.n_beams;
+       start = wave_take64(a.counter, kr)) {
+    const int64_t it_end = min<int64_t>(start + kr, a.n_beams);
+    kr = run_length(a.n_beams, it_end, n_waves);
+    for (int64_t it = start; it < it_end; ++it) {
+      const int64_t r0 = a.run_off[it], r1 = a.run_off[it + 1];
+      double v;
+      if (r1 < r0) {
         v = __builtin_nan("");
         if (lane == 0) latch(a.status, kErrLen);
-      } else if (n == 0) {
-        v = 0.0;
       } else {
-        bool bad;
-        v = beam_core<1, false, T>(a.ec, n, so, false, (double)a.sigma_p[it], L, nullptr, nullptr,
-                                   lane, false, &bad);
-        if (bad && lane == 0) latch(a.status, kErrOcc);
+        const int n = expand_runs(a.run_occ, a.run_len, r0, r1, a.cap, so, nullptr, lane);
+        if (n < 0) {
+          v = __builtin_nan("");
+          if (lane == 0) latch(a.status, kErrLen);
+        } else if (n == 0) {
+          v = 0.0;
+        } else {
+          bool bad;
+          v = beam_core<1, false, T>(a.ec, n, so, false, (double)a.sigma_p[it], L, nullptr, nullptr,
+                                     lane, false, &bad);
+          if (bad && lane == 0) latch(a.status, kErrOcc);
+        }
       }
+      if (lane == 0) a.mi[it] = v;
+      wave_sync();
     }
-    if (lane == 0) a.mi[it] = v;
-    wave_sync();
   }
 }
 
@@ -132,28 +140,37 @@ __global__ __launch_bounds__(kWave) void k_poses3d(Pose3dArgs a) {
   const CoreLds L = carve_rle<T>(lds, a.cap, &so);
   const int lane = threadIdx.x;
   const int64_t n_items = a.n_poses * a.n_beams;
-  for (int64_t it = wave_pop64(a.counter); it < n_items; it = wave_pop64(a.counter)) {
-    const int64_t p = it / a.n_beams, b = it - p * a.n_beams;
-    const double* ps = a.poses + 5 * p;
-    const double* bd = a.beam_dir + 3 * b;
-    const double m1 = ps[3] * bd[0], m2 = ps[4] * bd[1], m3 = ps[4] * bd[0], m4 = ps[3] * bd[1];
-    const double d[3] = {m1 - m2, m3 + m4, bd[2]};
-    bool ok;
-    const int n = virtual3d_wave(a.map, a.X, a.Y, a.Z, ps, d, a.R, a.w, a.cap, so, nullptr, lane, &ok);
-    double v;
-    if (!ok) {
-      v = __builtin_nan("");
-      if (lane == 0) latch(a.status, kErrPose);
-    } else if (n == 0) {
-      v = 0.0;
-    } else {
+  // runs of items from the queue (guided self-scheduling); k, start and the
+  // loop bounds are wave-uniform
+  const int64_t n_waves = gridDim.x;
+  int64_t k = run_length(n_items, 0, n_waves);
+  for (int64_t start = wave_take64(a.counter, k); start < n_items;
+       start = wave_take64(a.counter, k)) {
+    const int64_t it_end = min<int64_t>(start + k, n_items);
+    k = run_length(n_items, it_end, n_waves);
+    for (int64_t it = start; it < it_end; ++it) {
+      const int64_t p = it / a.n_beams, b = it - p * a.n_beams;
+      const double* ps = a.poses + 5 * p;
+      const double* bd = a.beam_dir + 3 * b;
+      const double m1 = ps[3] * bd[0], m2 = ps[4] * bd[1], m3 = ps[4] * bd[0], m4 = ps[3] * bd[1];
+      const double d[3] = {m1 - m2, m3 + m4, bd[2]};
+      bool ok;
+      const int n = virtual3d_wave(a.map, a.X, a.Y, a.Z, ps, d, a.R, a.w, a.cap, so, nullptr, lane, &ok);
+      double v;
+      if (!ok) {
+        v = __builtin_nan("");
+        if (lane == 0) latch(a.status, kErrPose);
+      } else if (n == 0) {
+        v = 0.0;
+      } else {
+        wave_sync();
+        bool bad;
+        v = beam_core<1, false, T>(a.ec, n, so, false, a.sigma_p, L, nullptr, nullptr, lane, false, &bad);
+        if (bad && lane == 0) latch(a.status, kErrOcc);
+      }
+      if (lane == 0) a.mi_beam[it] = v;
       wave_sync();
-      bool bad;
-      v = beam_core<1, false, T>(a.ec, n, so, false, a.sigma_p, L, nullptr, nullptr, lane, false, &bad);
-      if (bad && lane == 0) latch(a.status, kErrOcc);
     }
-    if (lane == 0) a.mi_beam[it] = v;
-    wave_sync();
   }
 }
 

@@ -183,6 +183,8 @@ FSMI_DEV int virtual3d_wave(const float* __restrict__ map, int64_t X, int64_t Y,
   const int64_t nmax = (int64_t)floor(R / w);
   int n = (int)min<int64_t>(nmax, (int64_t)cap);
   int end = n;
+  // pass 1: voxel indices (in o's slots) and the first sample outside the map
+  int* sidx = reinterpret_cast<int*>(so);
   for (int base = 0; base < n; base += kWave) {
     const int i = base + lane + 1;
     bool in = false;
@@ -198,7 +200,7 @@ FSMI_DEV int virtual3d_wave(const float* __restrict__ map, int64_t X, int64_t Y,
     }
     const uint64_t outm = __ballot(i <= n && !in);
     if (i <= n && in) {
-      so[i - 1] = map[idx];
+      sidx[i - 1] = (int)idx;
       if (scell) scell[i - 1] = (int)idx;
     }
     if (outm) {
@@ -206,6 +208,26 @@ FSMI_DEV int virtual3d_wave(const float* __restrict__ map, int64_t X, int64_t Y,
       break;
     }
   }
+  wave_sync();
+  // pass 2: the occupancies of samples 0 .. end-1 (all inside the map), four
+  // loads in flight per lane
+  for (int b0 = 0; b0 < end; b0 += 4 * kWave) {
+    int c[4];
+    float o[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = b0 + u * kWave + lane;
+      c[u] = i < end ? sidx[i] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) o[u] = map[c[u]];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = b0 + u * kWave + lane;
+      if (i < end) so[i] = o[u];
+    }
+  }
+  wave_sync();
   return end;
 }
 
