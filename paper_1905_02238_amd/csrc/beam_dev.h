@@ -190,26 +190,45 @@ FSMI_DEV double row_approx_bound(const double* sL, const T* sC, int n, int j, in
 }
 
 // Unit cells: G_{k,j} = g(|k-j|), g from the per-beam table sG[0..n-1].
+// The weight table of equal-width cells, seen from row j: w(k) = g(|k - j|).
+// FP32 keeps the table mirrored (g(|d|) at n - 1 + d, d = -(n-1)..n-1), so a
+// row reads consecutive addresses and an unrolled block needs no index
+// arithmetic; FP64 keeps g(d), d = 0..n-1 (a mirror would not fit its LDS).
+template <typename T> struct UnitRow;
+template <> struct UnitRow<float> {
+  const float* base;
+  FSMI_DEV UnitRow(const float* sG, int n, int j) : base(sG + (n - 1 - j)) {}
+  FSMI_DEV float operator()(int k) const { return base[k]; }
+};
+template <> struct UnitRow<double> {
+  const double* g;
+  int j;
+  FSMI_DEV UnitRow(const double* sG, int, int jj) : g(sG), j(jj) {}
+  FSMI_DEV double operator()(int k) const { return g[abs(k - j)]; }
+};
+
+// Eight pairs per compensated add, as on explicit boundaries.
 template <typename T>
 FSMI_DEV double row_exact_unit(const T* sG, const T* sC, int n, int j) {
+  const UnitRow<T> w(sG, n, j);
   Acc<T> acc;
   int k = 1;
-  for (; k + 3 <= n; k += 4) {
-    T p = sC[k - 1] * sG[abs(k - j)];
-    p = fma(sC[k], sG[abs(k + 1 - j)], p);
-    p = fma(sC[k + 1], sG[abs(k + 2 - j)], p);
-    p = fma(sC[k + 2], sG[abs(k + 3 - j)], p);
+  for (; k + 7 <= n; k += 8) {
+    T p = sC[k - 1] * w(k);
+#pragma unroll
+    for (int q = 1; q < 8; ++q) p = fma(sC[k - 1 + q], w(k + q), p);
     acc.add(p);
   }
-  for (; k <= n; ++k) acc.add(sC[k - 1] * sG[abs(k - j)]);
+  for (; k <= n; ++k) acc.add(sC[k - 1] * w(k));
   return acc.value();
 }
 
 template <typename T>
 FSMI_DEV double row_approx_unit(const T* sG, const T* sC, int n, int j, int D) {
+  const UnitRow<T> w(sG, n, j);
   Acc<T> acc;
   const int k0 = max(1, j - D), k1 = min(n, j + D);
-  for (int k = k0; k <= k1; ++k) acc.add(sC[k - 1] * sG[abs(k - j)]);
+  for (int k = k0; k <= k1; ++k) acc.add(sC[k - 1] * w(k));
   return acc.value();
 }
 
@@ -268,7 +287,8 @@ FSMI_DEV double beam_core(const EvalConst& ec, int n, const float* so, bool has_
   }
   const double c = 1.0 / (sigma * 1.4142135623730951);
   if (!uni && !has_bound) {
-    // g(d) = Phi((d+1/2)/sigma) - Phi((d-1/2)/sigma), d = 0..n-1
+    // g(d) = Phi((d+1/2)/sigma) - Phi((d-1/2)/sigma), d = 0..n-1; FP32 also
+    // stores the mirror image (UnitRow), in the 2(n+1) floats of A
     T* sG = reinterpret_cast<T*>(sA);
     for (int d = tid; d < n; d += G) {
       T g;
@@ -281,7 +301,12 @@ FSMI_DEV double beam_core(const EvalConst& ec, int n, const float* so, bool has_
       } else {
         g = T(0.5) * (erfc_pos((T)((d - 0.5) * c)) - erfc_pos((T)((d + 0.5) * c)));
       }
-      sG[d] = g;
+      if constexpr (sizeof(T) == 4) {
+        sG[n - 1 + d] = g;
+        sG[n - 1 - d] = g;
+      } else {
+        sG[d] = g;
+      }
     }
   }
   const bool any_bad = group_any<NW, BLOCK>(bad, flag, tid);
