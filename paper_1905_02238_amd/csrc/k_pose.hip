@@ -32,11 +32,12 @@ struct Pose2dArgs {
   uint32_t* status;
 };
 
-// LDS of one wave: region 1 = walk scratch (tx, ty, tie), reused for C and P
-// after the walk; region 2 = l (FP64 [ecap+1]) and o (FP32 [ecap]).
+// LDS of one wave: region 1 = the walk's tie counts, reused for C and P after
+// the walk; region 2 = l (FP64 [ecap+1]) and o (FP32 [ecap]).  The walk
+// recomputes face times instead of storing them.
 template <typename T>
 __host__ __device__ inline size_t pose2d_region1(int capa, int ecap) {
-  const size_t walk = (size_t)capa * 16 + (size_t)(capa + 1) * 4;
+  const size_t walk = (size_t)(capa + 1) * 4;
   const size_t cp = 2 * sizeof(T) * (size_t)ecap;
   return ((walk > cp ? walk : cp) + 15) / 16 * 16;
 }
@@ -51,9 +52,7 @@ __global__ __launch_bounds__(kWave) void k_poses2d(Pose2dArgs a) {
   extern __shared__ __align__(16) char lds[];
   const int lane = threadIdx.x;
   char* r1 = lds;
-  double* tx = reinterpret_cast<double*>(r1);
-  double* ty = tx + a.capa;
-  int* tie = reinterpret_cast<int*>(ty + a.capa);
+  int* tie = reinterpret_cast<int*>(r1);
   double* sL = reinterpret_cast<double*>(lds + pose2d_region1<T>(a.capa, a.ecap));
   float* so = reinterpret_cast<float*>(sL + a.ecap + 1);
   const int64_t n_items = a.n_poses * a.n_beams;
@@ -80,7 +79,7 @@ __global__ __launch_bounds__(kWave) void k_poses2d(Pose2dArgs a) {
         sc[r + 1] = c;
       };
       const Dda2dResult res =
-          dda2d_wave(a.X, a.Y, ps[0], ps[1], dx, dy, a.R, a.capa, a.ecap, tx, ty, tie, emit, lane);
+          dda2d_wave(a.X, a.Y, ps[0], ps[1], dx, dy, a.R, a.capa, a.ecap, tie, emit, lane);
       double v;
       if (res.n < 0) {
         v = __builtin_nan("");

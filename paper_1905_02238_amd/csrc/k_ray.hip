@@ -8,9 +8,9 @@
 namespace fsmi {
 namespace {
 
-// LDS of the walk: tx, ty [capa] FP64, tie [capa + 1] int, ev [ecap] FP64, pc [ecap] int.
+// LDS of the walk: ev [ecap] FP64, pc [ecap] int, tie [capa + 1] int.
 static inline size_t raycast2d_lds(int capa, int ecap) {
-  return (size_t)capa * 16 + (size_t)ecap * 8 + (size_t)ecap * 4 + (size_t)(capa + 1) * 4 + 16;
+  return (size_t)ecap * 8 + (size_t)ecap * 4 + (size_t)(capa + 1) * 4 + 16;
 }
 
 __global__ __launch_bounds__(kWave) void k_raycast2d(const float* __restrict__ map, int64_t X,
@@ -21,9 +21,7 @@ __global__ __launch_bounds__(kWave) void k_raycast2d(const float* __restrict__ m
                                                      int32_t* count, int32_t* cell, double* entry,
                                                      float* occ_out, uint32_t* status) {
   extern __shared__ __align__(16) char lds[];
-  double* tx = reinterpret_cast<double*>(lds);
-  double* ty = tx + capa;
-  double* ev = ty + capa;
+  double* ev = reinterpret_cast<double*>(lds);
   int* pc = reinterpret_cast<int*>(ev + ecap);
   int* tie = pc + ecap;
   const int lane = threadIdx.x;
@@ -33,7 +31,7 @@ __global__ __launch_bounds__(kWave) void k_raycast2d(const float* __restrict__ m
       pc[rank] = c;
     };
     const Dda2dResult res = dda2d_wave(X, Y, origin[2 * r], origin[2 * r + 1], dir[2 * r],
-                                       dir[2 * r + 1], R, capa, ecap, tx, ty, tie, emit, lane);
+                                       dir[2 * r + 1], R, capa, ecap, tie, emit, lane);
     if (res.n < 0 || res.n > max_cells) {
       if (lane == 0) {
         count[r] = res.n < 0 ? res.n : -2;

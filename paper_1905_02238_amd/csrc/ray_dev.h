@@ -19,17 +19,29 @@
 
 namespace fsmi {
 
-// Count of entries of the non-decreasing array A[0..N) that are < key, where
-// A holds one axis's face times, A[m] ~ A[0] + m / rate (rate = |d| of that
-// axis).  The spacing gives the count to within rounding; the two loops then
-// move it to the exact boundary with the true comparisons, so the result is
-// exact for any input (and is usually reached with one or two reads).
-FSMI_DEV int count_below(const double* A, int N, double key, double rate) {
+// The distance along the ray to face i of one axis: ((f0 + s i) - p) * inv,
+// two separately rounded operations after the exact integer face, so every
+// evaluation of the same face gives the same bits.
+struct FaceTimes {
+  double f0, p, inv;
+  int s;
+  FSMI_DEV double operator()(int i) const {
+#pragma clang fp contract(off)
+    return ((f0 + (double)(s * i)) - p) * inv;
+  }
+};
+
+// Count of faces i in [0, N) with A(i) < key, where A(i) is non-decreasing and
+// A(i) ~ A(0) + i / rate (rate = |d| of that axis).  The spacing gives the
+// count to within rounding; the two loops then move it to the exact boundary
+// with the true comparisons, so the result is exact for any input (usually
+// after one or two evaluations).
+FSMI_DEV int count_below(const FaceTimes& A, int N, double key, double rate) {
   if (N <= 0) return 0;
-  const double e = (key - A[0]) * rate;
+  const double e = (key - A(0)) * rate;
   int c = !(e > 0.0) ? 0 : (e >= (double)N ? N : (int)ceil(e));
-  while (c > 0 && A[c - 1] >= key) --c;
-  while (c < N && A[c] < key) ++c;
+  while (c > 0 && A(c - 1) >= key) --c;
+  while (c < N && A(c) < key) ++c;
   return c;
 }
 
@@ -55,8 +67,7 @@ struct Dda2dResult {
 // first exit are emitted too and must be ignored by the caller (ranks < ecap).
 template <class Emit>
 FSMI_DEV Dda2dResult dda2d_wave(int64_t X, int64_t Y, double px, double py, double dx, double dy,
-                                double R, int capa, int ecap, double* tx, double* ty, int* tiep,
-                                Emit emit, int lane) {
+                                double R, int capa, int ecap, int* tiep, Emit emit, int lane) {
 #pragma clang fp contract(off)
   Dda2dResult res;
   res.n = -1;
@@ -74,6 +85,7 @@ FSMI_DEV Dda2dResult dda2d_wave(int64_t X, int64_t Y, double px, double py, doub
   const double ix = sx ? 1.0 / dx : 0.0;
   const double iy = sy ? 1.0 / dy : 0.0;
   const double adx = fabs(dx), ady = fabs(dy);   // events per unit of t, per axis
+  const FaceTimes tx{fx0, px, ix, sx}, ty{fy0, py, iy, sy};   // face times, recomputed on use
   const int64_t ex = sx > 0 ? X - 1 - cx0 : cx0;   // x event index that leaves the map
   const int64_t ey = sy > 0 ? Y - 1 - cy0 : cy0;
   int nx = 0, ny = 0;
@@ -83,30 +95,21 @@ FSMI_DEV Dda2dResult dda2d_wave(int64_t X, int64_t Y, double px, double py, doub
     res.n = -2;
     return res;
   }
-  // event times; count those below R (the arrays increase, so they form a prefix)
+  // events before R (the times increase, so they form a prefix)
   int Nx = 0, Ny = 0;
-  for (int i = lane; i < nx; i += kWave) {
-    const double t = ((fx0 + (double)(sx * i)) - px) * ix;
-    tx[i] = t;
-    Nx += t < R ? 1 : 0;
-  }
-  for (int i = lane; i < ny; i += kWave) {
-    const double t = ((fy0 + (double)(sy * i)) - py) * iy;
-    ty[i] = t;
-    Ny += t < R ? 1 : 0;
-  }
+  for (int i = lane; i < nx; i += kWave) Nx += tx(i) < R ? 1 : 0;
+  for (int i = lane; i < ny; i += kWave) Ny += ty(i) < R ? 1 : 0;
   Nx = wave_sum(Nx);
   Ny = wave_sum(Ny);
-  wave_sync();
   // x events: ties with y events, exclusive prefix count of ties
   int carry = 0;
   for (int base = 0; base < Nx; base += kWave) {
     const int i = base + lane;
     int tie = 0;
     if (i < Nx) {
-      const double t = tx[i];
+      const double t = tx(i);
       const int c = count_below(ty, Ny, t, ady);
-      tie = (c < Ny && ty[c] == t) ? 1 : 0;
+      tie = (c < Ny && ty(c) == t) ? 1 : 0;
     }
     const int inc = wave_scan_incl<OpAdd>(tie);
     if (i < Nx) tiep[i] = carry + inc - tie;
@@ -117,16 +120,16 @@ FSMI_DEV Dda2dResult dda2d_wave(int64_t X, int64_t Y, double px, double py, doub
   const int K = Nx + Ny - carry;
   // the first event decides whether the origin cell has zero length
   double t0 = 1.0 / 0.0;
-  if (Nx > 0) t0 = tx[0];
-  if (Ny > 0 && ty[0] < t0) t0 = ty[0];
+  if (Nx > 0) t0 = tx(0);
+  if (Ny > 0 && ty(0) < t0) t0 = ty(0);
   res.skip0 = (K >= 1 && !(t0 > 0.0)) ? 1 : 0;
   int first_out = K;
   double t_out = 0.0;
   // x events
   for (int i = lane; i < Nx; i += kWave) {
-    const double t = tx[i];
+    const double t = tx(i);
     const int c = count_below(ty, Ny, t, ady);
-    const int tie = (c < Ny && ty[c] == t) ? 1 : 0;
+    const int tie = (c < Ny && ty(c) == t) ? 1 : 0;
     const int r = i + c - tiep[i];
     const int64_t cx = cx0 + (int64_t)sx * (i + 1);
     const int64_t cy = cy0 + (int64_t)sy * (c + tie);
@@ -136,9 +139,9 @@ FSMI_DEV Dda2dResult dda2d_wave(int64_t X, int64_t Y, double px, double py, doub
   }
   // y events that do not tie with an x event
   for (int m = lane; m < Ny; m += kWave) {
-    const double t = ty[m];
+    const double t = ty(m);
     const int c = count_below(tx, Nx, t, adx);
-    if (c < Nx && tx[c] == t) continue;
+    if (c < Nx && tx(c) == t) continue;
     const int r = m + c - tiep[c];
     const int64_t cy = cy0 + (int64_t)sy * (m + 1);
     const int64_t cx = cx0 + (int64_t)sx * c;
