@@ -47,9 +47,9 @@ SLOTS_PER_PAIR = 14.5
 # 131088 KiB for 262144 KiB read, WRITE_SIZE 262144 KiB for 262144 KiB written).
 # They describe the kernel built from the sources hashed here; with any other
 # sources the bench reports traffic as null.
-TRAFFIC = {"fetch_kib": 1.46012e+07, "write_kib": 48575.7,
-           "fetch_scale": 262144.0 / 131087.6, "write_scale": 1.0,
-           "sources_sha256": "9b6ce80500e6e1808d623ca44055950ef07920e890fa730417469689503b982d"}
+TRAFFIC = {"fetch_kib": 1.45935e+07, "write_kib": 48557.2,
+           "fetch_scale": 262144.0 / 131088.2, "write_scale": 1.0,
+           "sources_sha256": "c4d2d413a5af68437c341fd51c377629d8af69b01695cc5f9e6ab64c7d88f85a"}
 TRAFFIC_SOURCES = ("paper_1905_02238_amd/csrc/k_pose.hip", "paper_1905_02238_amd/csrc/beam_dev.h",
                    "paper_1905_02238_amd/csrc/ray_dev.h", "paper_1905_02238_amd/csrc/fsmi_dev.h",
                    "paper_1905_02238_amd/csrc/fsmi_internal.h", "paper_1905_02238_amd/build.py")
@@ -248,6 +248,30 @@ def main():
             extras[name] = {"beams_per_s": n_total / dt, "ms": dt * 1e3}
             gpu[name] = ctx.fsmi_eval_poses(p, grid, poses, bdir, sigma, R)[0]
             log(f"[bench] {name}: {n_total/dt/1e6:.2f} M beams/s")
+        # skip-zero exact mode: same workload, pairs whose FP32 weight is below
+        # the smallest normal float left out; its own work count from the
+        # walks of the first 16 poses
+        pz = F.params(variant=F.FSMI_EXACT, flags=F.FSMI_F_SKIP_ZERO)
+        dt = timed(lambda: ctx.fsmi_eval_poses(pz, grid, poses, bdir, sigma, R))
+        gpu["exact_skip_zero"] = ctx.fsmi_eval_poses(pz, grid, poses, bdir, sigma, R)[0]
+        ns = min(16, n_poses) * n_beams
+        rc = ctx.fsmi_raycast(grid, F.FSMI_RAY_DDA, org[:ns].contiguous(), wdir[:ns].contiguous(), R)
+        cnts, ents = rc["count"].cpu().numpy(), rc["entry"].cpu().numpy()
+        half = 13.19 * sigma     # 11.2 in the kernel's scaled units, in cells
+        band = 0.0
+        for q in range(ns):
+            nq = int(cnts[q])
+            lq = ents[q, :nq + 1]
+            mu = 0.5 * (lq[:-1] + lq[1:])
+            k0 = np.maximum(1, np.searchsorted(lq, mu - half, "left"))
+            k1 = np.minimum(nq, np.searchsorted(lq, mu + half, "right"))
+            band += float(np.sum(k1 - k0 + 2))
+        dense_s = float(np.sum(cnts.astype(np.float64) * (cnts + 1)))
+        extras["exact_skip_zero"] = {"beams_per_s": n_total / dt, "ms": dt * 1e3,
+                                     "pairs_fraction_of_dense": band / dense_s,
+                                     "pairs_per_step_est": pairs * band / dense_s}
+        log(f"[bench] exact skip-zero: {n_total/dt/1e6:.2f} M beams/s, "
+            f"{band/dense_s*100:.1f} % of the dense pairs")
         off, occ, sg = W.uneven_beams(100000, seed=W.SEED_BASE + 3)
         o_, oc, s2 = t(off), t(occ), t(sg)
         dt = timed(lambda: ctx.fsmi_eval_beams(prm, o_, oc, s2))
@@ -356,6 +380,8 @@ def oracle_leg(out, gpu, wl, W, args, ctx, F, t):
             rp, _ = O.eval_poses_2d(v, wl["grid"], wl["poses"][:kp], wl["beam_dir"], sig, R,
                                     threads=thr, want_beams=False, **kw)
             rep[name] = _err_stats(_rel(gpu[name][:kp].cpu().numpy(), rp), 1e-5, poses=kp)
+        rep["exact_skip_zero"] = _err_stats(_rel(gpu["exact_skip_zero"][:k].cpu().numpy(), ref_pose),
+                                            1e-5, poses=k)
         off, occ, sg = W.uneven_beams(100000, seed=W.SEED_BASE + 3)
         nb = 2000
         rb = O.eval_beams(O.EXACT, off[:nb + 1], occ[:off[nb]], sg[:nb], threads=thr)

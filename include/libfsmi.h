@@ -63,6 +63,16 @@ enum {
   FSMI_KERNEL_DENSITY = 1 /* exp(-d^2/(2 sigma'^2))/(sqrt(2 pi) sigma') (proof of Thm 5) */
 };
 enum { FSMI_FP32 = 0, FSMI_FP64 = 1 };
+enum {
+  /* Skip-zero exact mode (EXACT, FP32, explicit boundaries: fsmi_eval_beams
+     with bound, fsmi_plan_eval_beams with bound, 2D fsmi_eval_poses): each row
+     j keeps only the boundaries within 9.3 sigma sqrt(2) of mu_j (plus the
+     cells straddling that band's edges); every pair left out has an FP32 weight
+     below the smallest normal float, so the result is the dense sum up to
+     rounding order.  A separate mode with its own work count; any other
+     combination gives FSMI_E_INVAL. */
+  FSMI_F_SKIP_ZERO = 1u
+};
 
 typedef struct {
   double delta_occ;   /* > 1; the paper uses 1.5 (Sec. 5.1) */
@@ -71,7 +81,7 @@ typedef struct {
   int32_t uniform_h;  /* H >= 0, cells (UNIFORM) */
   int32_t kernel;     /* FSMI_KERNEL_* (equal-width cells and RLE only) */
   int32_t precision;  /* FSMI_FP32 (default) | FSMI_FP64 */
-  uint32_t flags;     /* reserved, must be 0 */
+  uint32_t flags;     /* 0 or FSMI_F_SKIP_ZERO */
 } fsmi_params;
 
 typedef struct {

@@ -56,8 +56,12 @@ bool check_params(fsmi_ctx ctx, const fsmi_params* p, fsmi_status* st) {
     *st = fail(ctx, FSMI_E_INVAL, "unknown precision");
     return false;
   }
-  if (p->flags != 0) {
-    *st = fail(ctx, FSMI_E_INVAL, "flags are reserved and must be 0");
+  if (p->flags & ~(uint32_t)FSMI_F_SKIP_ZERO) {
+    *st = fail(ctx, FSMI_E_INVAL, "unknown flags");
+    return false;
+  }
+  if ((p->flags & FSMI_F_SKIP_ZERO) && (p->variant != FSMI_EXACT || p->precision != FSMI_FP32)) {
+    *st = fail(ctx, FSMI_E_INVAL, "FSMI_F_SKIP_ZERO is an EXACT, FP32 mode");
     return false;
   }
   return true;
@@ -272,6 +276,8 @@ fsmi_status fsmi_eval_beams(fsmi_ctx ctx, const fsmi_params* params, int64_t n_b
   if (n_beams == 0) return FSMI_OK;
   if (n_beams >= ((int64_t)1 << 31)) return fail(ctx, FSMI_E_CAPACITY, "n_beams >= 2^31");
   if (!off || !occ || !sigma || !mi) return fail(ctx, FSMI_E_INVAL, "off, occ, sigma, mi are required");
+  if ((params->flags & FSMI_F_SKIP_ZERO) && !bound)
+    return fail(ctx, FSMI_E_INVAL, "FSMI_F_SKIP_ZERO needs explicit boundaries");
   (void)hipSetDevice(ctx->device);
   int max_len = 0;
   hipError_t e = launch_max_len(ctx, off, n_beams, &max_len);
@@ -295,6 +301,8 @@ fsmi_status fsmi_rle_eval_beams(fsmi_ctx ctx, const fsmi_params* params, int64_t
   if (n_beams == 0) return FSMI_OK;
   if (!run_off || !run_occ || !run_len || !sigma_prime || !mi)
     return fail(ctx, FSMI_E_INVAL, "run_off, run_occ, run_len, sigma_prime, mi are required");
+  if (params->flags & FSMI_F_SKIP_ZERO)
+    return fail(ctx, FSMI_E_INVAL, "FSMI_F_SKIP_ZERO needs explicit boundaries");
   (void)hipSetDevice(ctx->device);
   return from_hip(ctx,
                   launch_rle_eval_beams(ctx, to_const(params), n_beams, run_off, run_occ, run_len,
@@ -336,6 +344,8 @@ fsmi_status fsmi_eval_poses(fsmi_ctx ctx, const fsmi_params* params, const fsmi_
                                          mi_pose, mi_beam),
                     "eval_poses_2d");
   }
+  if (params->flags & FSMI_F_SKIP_ZERO)
+    return fail(ctx, FSMI_E_INVAL, "FSMI_F_SKIP_ZERO needs explicit boundaries (2D maps)");
   if (!(w > 0.0) || !std::isfinite(w)) return fail(ctx, FSMI_E_INVAL, "w must be finite and > 0");
   if (floor(max_range / w) > 4000.0) return fail(ctx, FSMI_E_CAPACITY, "more than 4000 virtual cells per beam");
   return from_hip(ctx,

@@ -173,6 +173,49 @@ FSMI_DEV double row_exact_bound(const double* sL, const T* sC, int n, int j) {
   return diag_fix<T>(acc, sL, sC, j, M);
 }
 
+// Skip-zero mode (FP32): only boundaries with |L_b - M_j| <= kSkipY, beyond
+// which erfc is below the smallest normal float (erfc(9.3) < 2^-126), so the
+// skipped terms add nothing at FP32 precision.  Cells kept: from the band's
+// first boundary to one past its last (the cells at the edges of the band).
+constexpr double kSkipY = 11.2;   // scaled units: 9.32 in units of sigma sqrt 2
+
+FSMI_DEV int first_at_least(const double* sL, int n, double key) {   // in [0, n + 1]
+  int lo = 0, hi = n + 1;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (sL[mid] < key) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+template <typename T>
+FSMI_DEV double row_exact_band(const double* sL, const T* sC, int n, int j) {
+  const double M = 0.5 * (sL[j - 1] + sL[j]);
+  const int b_lo = first_at_least(sL, n, M - kSkipY);
+  const int b_hi = first_at_least(sL, n, M + kSkipY + 1e-300) - 1;   // last with L_b <= M + Y
+  const int k0 = max(1, b_lo), k1 = min(n, b_hi + 1);
+  Acc<T> acc;
+  T Eprev = tail_E<T>(sL[k0 - 1], M);
+  int b = k0;
+  for (; b + 7 <= k1; b += 8) {
+    T E[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) E[q] = tail_E<T>(sL[b + q], M);
+    T p = sC[b - 1] * tabs(E[0] - Eprev);
+#pragma unroll
+    for (int q = 1; q < 8; ++q) p = fma(sC[b - 1 + q], tabs(E[q] - E[q - 1]), p);
+    acc.add(p);
+    Eprev = E[7];
+  }
+  for (; b <= k1; ++b) {
+    T E = tail_E<T>(sL[b], M);
+    acc.add(sC[b - 1] * tabs(E - Eprev));
+    Eprev = E;
+  }
+  return diag_fix<T>(acc, sL, sC, j, M);
+}
+
 template <typename T>
 FSMI_DEV double row_approx_bound(const double* sL, const T* sC, int n, int j, int D) {
   const double M = 0.5 * (sL[j - 1] + sL[j]);
@@ -329,7 +372,9 @@ FSMI_DEV double beam_core(const EvalConst& ec, int n, const float* so, bool has_
         tot += (double)sP[j - 1] * ((sA[hi] - sA[lo]) * inv);
       }
     } else if (has_bound) {
-      if (ec.variant == FSMI_EXACT) {
+      if (ec.variant == FSMI_EXACT && (ec.flags & FSMI_F_SKIP_ZERO)) {
+        for (int j = tid + 1; j <= n; j += G) tot += (double)sP[j - 1] * row_exact_band<T>(sA, sC, n, j);
+      } else if (ec.variant == FSMI_EXACT) {
         for (int j = tid + 1; j <= n; j += G) tot += (double)sP[j - 1] * row_exact_bound<T>(sA, sC, n, j);
       } else {
         for (int j = tid + 1; j <= n; j += G)

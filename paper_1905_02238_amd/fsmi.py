@@ -24,6 +24,7 @@ FSMI_KERNEL_ERF, FSMI_KERNEL_DENSITY = 0, 1
 FSMI_FP32, FSMI_FP64 = 0, 1
 FSMI_RAY_DDA, FSMI_RAY_VIRTUAL, FSMI_RAY_RLE = 0, 1, 2
 FSMI_PLAN_AUTOTUNE, FSMI_PLAN_GRAPH = 1, 2
+FSMI_F_SKIP_ZERO = 1
 
 EXPORTS = ("fsmi_create", "fsmi_destroy", "fsmi_set_stream", "fsmi_sync", "fsmi_last_error",
            "fsmi_status_string", "fsmi_default_params", "fsmi_raycast", "fsmi_eval_beams",

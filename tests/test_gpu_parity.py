@@ -334,3 +334,49 @@ def test_poses_2d_at_max_range(ctx, prec, R, tol):
     with pytest.raises(F.FsmiError) as e:
         ctx.fsmi_eval_poses(prm, dev(grid), dev(poses), dev(bdir), 3.0, R + 1.0)
     assert e.value.status == F.FSMI_E_CAPACITY
+
+
+# ---------------------------------------------------------------------------
+# Skip-zero exact mode: the dense sum up to rounding order.
+def test_skip_zero_matches_dense_and_oracle(ctx):
+    print("[gpu] skip-zero exact", flush=True)
+    wl = W.grid_large(n_poses=3)
+    args = (dev(wl["grid"]), dev(wl["poses"]), dev(wl["beam_dir"]), wl["sigma"], wl["R"])
+    mpd, mbd = ctx.fsmi_eval_poses(F.params(), *args, want_beams=True)
+    mps, mbs = ctx.fsmi_eval_poses(F.params(flags=F.FSMI_F_SKIP_ZERO), *args, want_beams=True)
+    torch.cuda.synchronize()
+    ctx.fsmi_sync()
+    rp, rb = O.eval_poses_2d(O.EXACT, wl["grid"], wl["poses"], wl["beam_dir"], wl["sigma"], wl["R"])
+    assert rel_err(mbs.cpu().numpy(), rb) <= TOL32
+    assert rel_err(mps.cpu().numpy(), rp) <= TOL32
+    assert rel_err(mbs.cpu().numpy(), mbd.cpu().numpy()) <= 2e-6
+    # explicit boundaries through fsmi_eval_beams, widths and sigma varied
+    lens = [0, 1, 2, 9, 64, 65, 300, 700, 1200]
+    off, occ, bound, sigma = _beam_batch(501, len(lens), lens, True)
+    prm = F.params(flags=F.FSMI_F_SKIP_ZERO)
+    mi = ctx.fsmi_eval_beams(prm, dev(off), dev(occ), dev(sigma), bound=dev(bound))
+    torch.cuda.synchronize()
+    ctx.fsmi_sync()
+    assert rel_err(mi.cpu().numpy(), O.eval_beams(O.EXACT, off, occ, sigma, bound=bound)) <= TOL32
+
+
+def test_skip_zero_rejects_other_modes(ctx):
+    off = dev(np.array([0, 2], np.int64))
+    occ = dev(np.array([0.2, 0.3], np.float32))
+    sg = dev(np.array([1.0], np.float32))
+    bd = dev(np.array([0.0, 1.0, 2.0]))
+    for prm in (F.params(variant=F.FSMI_APPROX, flags=F.FSMI_F_SKIP_ZERO),
+                F.params(precision=F.FSMI_FP64, flags=F.FSMI_F_SKIP_ZERO),
+                F.params(flags=2)):
+        with pytest.raises(F.FsmiError) as e:
+            ctx.fsmi_eval_beams(prm, off, occ, sg, bound=bd)
+        assert e.value.status == F.FSMI_E_INVAL
+    with pytest.raises(F.FsmiError) as e:      # unit cells: no explicit boundaries
+        ctx.fsmi_eval_beams(F.params(flags=F.FSMI_F_SKIP_ZERO), off, occ, sg)
+    assert e.value.status == F.FSMI_E_INVAL
+    vox = dev(np.full((8, 8, 8), 0.3, np.float32))
+    with pytest.raises(F.FsmiError) as e:
+        ctx.fsmi_eval_poses(F.params(flags=F.FSMI_F_SKIP_ZERO), vox, dev(np.array([[4.5, 4.5, 4.5, 1.0, 0.0]])),
+                            dev(np.array([[1.0, 0.0, 0.0]])), 1.0, 5.0, 1.0)
+    assert e.value.status == F.FSMI_E_INVAL
+    ctx.fsmi_sync()
