@@ -32,13 +32,15 @@ struct Pose2dArgs {
   uint32_t* status;
 };
 
-// LDS of one wave: region 1 = the walk's tie counts, reused for C and P after
-// the walk; region 2 = l (FP64 [ecap+1]) and o (FP32 [ecap]).  The walk
-// recomputes face times instead of storing them.
+// LDS of one wave: region 1 = the walk's tie counts, reused for C (and, in
+// FP64, P) after the walk; region 2 = l (FP64 [ecap+1]) and o (FP32 [ecap]).
+// In FP32, P(e_j) overwrites o in place (each lane reads o_i and writes P_i at
+// the same index, and o is not read again).  The walk recomputes face times
+// instead of storing them.
 template <typename T>
 __host__ __device__ inline size_t pose2d_region1(int capa, int ecap) {
   const size_t walk = (size_t)(capa + 1) * 4;
-  const size_t cp = 2 * sizeof(T) * (size_t)ecap;
+  const size_t cp = (sizeof(T) == 4 ? 1 : 2) * sizeof(T) * (size_t)ecap;
   return ((walk > cp ? walk : cp) + 15) / 16 * 16;
 }
 template <typename T>
@@ -112,7 +114,8 @@ __global__ __launch_bounds__(kWave) void k_poses2d(Pose2dArgs a) {
         CoreLds L;
         L.A = sL + res.skip0;
         L.C = r1;
-        L.P = r1 + sizeof(T) * (size_t)a.ecap;
+        L.P = sizeof(T) == 4 ? reinterpret_cast<void*>(so + res.skip0)
+                             : reinterpret_cast<void*>(r1 + sizeof(T) * (size_t)a.ecap);
         bool bad;
         v = beam_core<1, false, T>(a.ec, res.n, so + res.skip0, true, a.sigma, L, nullptr, nullptr,
                                    lane, false, &bad);
