@@ -1,0 +1,37 @@
+"""Host-side pieces of bench.py that need no GPU: the refusal of several GPUs,
+the error statistics of the error report, and the traffic guard that drops
+counter figures once the kernel's sources change."""
+import os
+import subprocess
+import sys
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+
+
+def test_relative_error_and_its_summary():
+    rel = bench._rel([1.0, 2.0, 0.0], [1.0, 1.0, 0.0])
+    assert rel.tolist() == [0.0, 1.0, 0.0]
+    st = bench._err_stats(np.array([1e-7, 3e-6]), 1e-5, poses=2)
+    assert st["results"] == 2 and st["max_rel"] == 3e-6 and st["within_bar"] and st["poses"] == 2
+
+
+def test_traffic_is_dropped_when_sources_change(monkeypatch):
+    monkeypatch.setitem(bench.TRAFFIC, "sources_sha256", "0" * 64)
+    assert bench.measured_traffic() is None
+
+
+def test_slot_accounting_is_the_documented_one():
+    assert bench.SLOTS_PER_PAIR == 14.5
+    assert abs(bench.ALU_PEAK_TSLOT - 39.3216) < 1e-9
+    assert bench.SUR_FLOP_PER_POSE == 73204224

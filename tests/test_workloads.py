@@ -1,0 +1,85 @@
+"""The seeded input recipes (CPU): value ranges per label, unknown fractions,
+pose placement, sensor geometry, uneven-batch statistics, 3D run compression,
+and determinism."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1905_02238_amd import workloads as W
+
+
+def test_room_grid_values_follow_their_labels():
+    occ, lab = W.room_grid(512, W.SEED_BASE + 50, split_extent=160, unknown_frac=0.30)
+    free, wall, unk = lab == W.FREE, lab == W.WALL, lab == W.UNKNOWN
+    assert occ.dtype == np.float32 and occ.shape == (512, 512)
+    assert occ[free].min() >= 0.05 and occ[free].max() <= 0.3
+    assert occ[wall].min() >= 0.8 and occ[wall].max() <= 0.95
+    assert np.all(occ[unk] == np.float32(0.5))
+    assert unk.mean() >= 0.30                        # blobs added until 30 % unknown
+    assert np.all(lab[:2] == W.WALL) and np.all(lab[:, -2:] == W.WALL)   # 2-cell border
+
+
+def test_grid_workloads_match_their_stated_sizes():
+    small = W.grid_small()
+    assert small["grid"].shape == (200, 200)
+    assert np.array_equal(small["poses"], [[100.0, 100.0, 1.0, 0.0]])
+    assert small["beam_dir"].shape == (60, 2) and small["R"] == 150.0 and small["sigma"] == 2.0
+    large = W.grid_large(n_poses=64)
+    assert large["grid"].shape == (2048, 2048) and large["poses"].shape == (64, 4)
+    assert (large["R"], large["sigma"], large["Delta"], large["H"]) == (400.0, 3.0, 9, 6)
+
+
+def test_poses_sit_in_free_cells_with_yaw_zero():
+    occ, lab = W.room_grid(256, W.SEED_BASE + 51, split_extent=60)
+    p = W.poses_in_free_space_2d(lab, 500, 7)
+    cells = lab[np.floor(p[:, 1]).astype(int), np.floor(p[:, 0]).astype(int)]
+    assert np.all(cells == W.FREE)
+    assert np.all(p[:, 2] == 1.0) and np.all(p[:, 3] == 0.0)
+
+
+def test_beam_directions_are_unit_vectors_at_equal_angles():
+    d = W.beam_dirs_2d(360)
+    assert np.allclose(np.hypot(d[:, 0], d[:, 1]), 1.0, atol=1e-15)
+    ang = np.mod(np.arctan2(d[:, 1], d[:, 0]), 2 * np.pi)
+    assert np.allclose(ang, 2 * np.pi * np.arange(360) / 360, atol=1e-12)
+    d3 = W.beam_dirs_3d()
+    assert d3.shape == (64 * 256, 3)
+    assert np.allclose(np.linalg.norm(d3, axis=1), 1.0, atol=1e-15)
+    az = np.degrees(np.arctan2(d3[:, 1], d3[:, 0]))
+    el = np.degrees(np.arcsin(d3[:, 2]))
+    assert az.min() > -45 and az.max() < 45 and el.min() > -30 and el.max() < 30
+
+
+def test_uneven_batch_statistics():
+    off, occ, sigma = W.uneven_beams(20000, seed=W.SEED_BASE + 3)
+    lens = np.diff(off)
+    assert lens.min() >= 8 and lens.max() <= 2000
+    # log-uniform on [8, 2000]: E[n] = (2000 - 8) / ln(250) = 360.8
+    assert abs(lens.mean() - (2000 - 8) / math.log(250)) < 15
+    near = np.min(np.abs(occ[:, None] - np.array([0.1, 0.5, 0.9], np.float32)), axis=1)
+    assert near.max() <= 0.05 + 1e-6
+    assert sigma.min() >= 1.0 and sigma.max() <= 6.0
+
+
+def test_voxel_map_compresses_into_long_runs():
+    vw = W.voxels_large(n_poses=4)
+    vox, poses, bd = vw["vox"], vw["poses"], vw["beam_dir"][::97]
+    cells = runs = 0
+    for p in poses:
+        for d in bd:
+            c, o = O.virtual3d(vox, p[:3], d, vw["R"], vw["w"])
+            ro, _ = O.rle_runs(o)
+            cells += len(o)
+            runs += len(ro)
+    assert cells / runs > 8.0          # long runs, as in an OctoMap (stated ratio about 16)
+
+
+def test_generators_are_deterministic():
+    a = W.uneven_beams(100, seed=5)
+    b = W.uneven_beams(100, seed=5)
+    assert all(np.array_equal(x, y) for x, y in zip(a, b))
+    g1, _ = W.room_grid(128, 9, split_extent=60, unknown_frac=0.1)
+    g2, _ = W.room_grid(128, 9, split_extent=60, unknown_frac=0.1)
+    assert np.array_equal(g1, g2)
