@@ -86,18 +86,30 @@ struct PatchSrc {
   int64_t X, Y;          // dims of `map`
   const double* poses;   // [n][4]
   int s;                 // cell stride
+  const bf16* patch = nullptr;   // [n][128][128] once gathered (training), else NULL
   FSMI_DEV int64_t block(double v) const {
     const int64_t c = (int64_t)floor(v);
     return c >= 0 ? c / s : -((-c + s - 1) / s);   // floor(c / s)
   }
   FSMI_DEV float at(int64_t b, int iy, int ix) const {
     if (iy < 0 || iy >= kPatch || ix < 0 || ix >= kPatch) return 0.0f;
+    if (patch) return (float)patch[(b * kPatch + iy) * kPatch + ix];
     const int64_t cx = block(poses[4 * b]) - kPatch / 2 + ix;
     const int64_t cy = block(poses[4 * b + 1]) - kPatch / 2 + iy;
     if (cx < 0 || cx >= X || cy < 0 || cy >= Y) return 0.5f;
     return map[cx + X * cy];
   }
 };
+
+// The patches of n poses as BF16 [n][128][128], the values at() returns.
+__global__ void k_patch_gather(int64_t n, PatchSrc src, bf16* __restrict__ out) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n * kPatch * kPatch;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = i / (kPatch * kPatch);
+    const int r = (int)(i % (kPatch * kPatch));
+    out[i] = (bf16)src.at(b, r / kPatch, r % kPatch);
+  }
+}
 
 // Block means: out[v][u] = mean of the map's cells x in [s u, s u + s),
 // y in [s v, s v + s) that lie inside the map (FP64 sum, fixed order).
@@ -847,6 +859,7 @@ struct fsmi_sur_s {
   size_t part_floats = 0;
   float* loss = nullptr;
   int stride = 1;            // cell stride of the patch
+  fsmi::bf16* patch = nullptr;   // the training batch's patches, allocated on first use
   float* pooled = nullptr;   // block means of the last map (stride > 1)
   size_t pooled_elems = 0;
 };
@@ -905,6 +918,7 @@ static void sur_free(fsmi_sur net) {
   for (void* p : ps)
     if (p) (void)hipFree(p);
   if (net->pooled) (void)hipFree(net->pooled);
+  if (net->patch) (void)hipFree(net->patch);
   for (int l = 1; l <= 5; ++l) {
     if (net->act[l]) (void)hipFree(net->act[l]);
     if (net->dact[l]) (void)hipFree(net->dact[l]);
@@ -1089,8 +1103,20 @@ fsmi_status fsmi_sur_backward(fsmi_sur net, const fsmi_map* map, int64_t n, cons
     return FSMI_E_INVAL;
   (void)hipSetDevice(net->ctx->device);
   PatchSrc src;
-  const hipError_t e = make_src(net, map, poses, &src);
+  hipError_t e = make_src(net, map, poses, &src);
   if (e != hipSuccess) return e == hipErrorOutOfMemory ? FSMI_E_NOMEM : FSMI_E_DEVICE;
+  // the first layer's forward and weight gradient read the patch from one
+  // gathered copy instead of the map
+  if (!net->patch) {
+    e = hipMalloc((void**)&net->patch, sizeof(bf16) * (size_t)net->max_batch * kPatch * kPatch);
+    if (e != hipSuccess) return FSMI_E_NOMEM;
+  }
+  {
+    const int64_t total = n * kPatch * kPatch;
+    const int grid = (int)std::min<int64_t>((total + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_patch_gather, dim3(grid), dim3(256), 0, net->ctx->stream, n, src, net->patch);
+    src.patch = net->patch;
+  }
   if (sur_fwd_batch(net, n, src, true) != hipSuccess) return FSMI_E_DEVICE;
   hipStream_t st = net->ctx->stream;
   const int grid = (int)std::min<int64_t>(n, 65535);
