@@ -6,11 +6,15 @@
  * Conventions shared by every entry point
  * ---------------------------------------
  * - Array arguments are DEVICE pointers owned by the caller.  The library
- *   never frees them and never keeps them past the call.  Scalars and the
- *   small structs below are passed on the host.
+ *   never frees them and keeps them past the call only where a call says so
+ *   (a plan of fsmi_plan_eval_beams keeps its batch's addresses until
+ *   fsmi_plan_destroy).  Scalars and the small structs below are passed on
+ *   the host.
  * - Calls are asynchronous: they enqueue kernels on the context's stream and
  *   return.  Results are ready after fsmi_sync() or any later operation on
- *   that stream.
+ *   that stream.  The calls that say so wait for the device (fsmi_eval_beams
+ *   once, to size its launch; plan creation; surrogate creation, checkpoint
+ *   save and load).
  * - Map coordinates are in cell units.  2D cell (x, y) covers
  *   [x, x+1) x [y, y+1); 3D voxel (x, y, z) likewise.  A map is stored x
  *   fastest: linear index = x + X*(y + Y*z), held in int32, so a map has
