@@ -15,7 +15,8 @@ skips those extras and shrinks the CPU baseline sample.
 
 Surrogate leg: the network is trained here on exact-FSMI labels of other
 2048 x 2048 room maps (``--sur-maps`` x ``--sur-poses``, ``--sur-steps`` Adam
-steps of 128 poses), then on 65 536 candidate poses of the held-out timed map
+steps of 128 poses, cosine learning-rate decay from 1e-3, patch stride
+``--sur-stride``), then on 65 536 candidate poses of the held-out timed map
 fsmi_rank_poses (surrogate forward, top 1 %, exact re-score) is timed against
 plain exact fsmi_eval_poses on all of them, with its ranking accuracy.
 """
@@ -87,9 +88,10 @@ def parse():
     ap.add_argument("--quick", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--sur-maps", type=int, default=16)
-    ap.add_argument("--sur-poses", type=int, default=4096)
-    ap.add_argument("--sur-steps", type=int, default=3000)
+    ap.add_argument("--sur-maps", type=int, default=32)
+    ap.add_argument("--sur-poses", type=int, default=8192)
+    ap.add_argument("--sur-steps", type=int, default=8000)
+    ap.add_argument("--sur-stride", type=int, default=2, help="patch cell stride")
     ap.add_argument("--sur-candidates", type=int, default=65536)
     ap.add_argument("--profile-step", action="store_true",
                     help="for counter runs: one plain 256 MiB device copy (the traffic "
@@ -428,7 +430,7 @@ def surrogate_leg(ctx, F, W, t, timed, args):
         train.append((g, p, mi))
     torch.cuda.synchronize()
     label_s = time.perf_counter() - t1
-    net = F.Surrogate(ctx, seed=3, max_batch=8192)
+    net = F.Surrogate(ctx, seed=3, max_batch=8192, patch_stride=args.sur_stride)
     net.fit_label_stats(torch.cat([d[2] for d in train]))
     rng = np.random.default_rng(3)
     t1 = time.perf_counter()
@@ -436,7 +438,7 @@ def surrogate_leg(ctx, F, W, t, timed, args):
         g, p, mi = train[it % len(train)]
         sel = torch.from_numpy(rng.choice(p.shape[0], 128, replace=False)).to(g.device)
         net.backward(g, p[sel].contiguous(), mi[sel].contiguous())
-        net.adam_step(1e-3)
+        net.adam_step(float(1e-3 * 0.5 * (1.0 + math.cos(math.pi * it / args.sur_steps))))
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t1
     log(f"[bench] surrogate: labels {label_s:.1f} s, {args.sur_steps} steps {train_s:.1f} s")
@@ -474,8 +476,10 @@ def surrogate_leg(ctx, F, W, t, timed, args):
         "recall_at_1pct": len(set(np.argsort(-true)[:k].tolist()) & set(idx.tolist())) / k,
         "regret": float(1.0 - true[idx].max() / best),
         "random_1pct_regret": rand_regret,
+        "patch_stride": args.sur_stride,
         "train": f"{args.sur_maps} maps x {args.sur_poses} exact-labelled poses, "
-                 f"{args.sur_steps} Adam steps of 128 (labels {label_s:.1f} s, training {train_s:.1f} s)",
+                 f"{args.sur_steps} Adam steps of 128, cosine lr from 1e-3 "
+                 f"(labels {label_s:.1f} s, training {train_s:.1f} s)",
     }
     log(f"[bench] surrogate rank: {n/ranked:.0f} poses/s vs plain {n/plain:.0f} poses/s "
         f"(x{plain/ranked:.1f}); forward {res['forward_tflops']:.1f} TFLOP/s; "
