@@ -222,14 +222,24 @@ FSMI_DEV double row_approx_bound(const double* sL, const T* sC, int n, int j, in
   Acc<T> acc;
   // cells k = j-D..j+D; cell k spans [sL[k-1], sL[k]]; indices clamped to the
   // beam so out-of-range cells see two equal boundaries and weigh zero
+  // The hit cell k = j is peeled out of the loop: it takes the exact weight
+  // of the two half widths, and its boundaries' tail values are not needed.
   T Eprev = tail_E<T>(sL[clampi(j - D - 1, 0, n)], M);
-  for (int i = 0; i <= 2 * D; ++i) {
-    const int k = j - D + i;
-    T E = tail_E<T>(sL[clampi(k, 0, n)], M);
+  for (int k = j - D; k < j; ++k) {
+    const T E = tail_E<T>(sL[clampi(k, 0, n)], M);
     acc.add(sC[clampi(k - 1, 0, n - 1)] * tabs(E - Eprev));
     Eprev = E;
   }
-  return diag_fix<T>(acc, sL, sC, j, M);
+  Eprev = tail_E<T>(sL[j], M);
+  for (int k = j + 1; k <= j + D; ++k) {
+    const T E = tail_E<T>(sL[clampi(k, 0, n)], M);
+    acc.add(sC[clampi(k - 1, 0, n - 1)] * tabs(E - Eprev));
+    Eprev = E;
+  }
+  constexpr double u = unscale<T>();
+  const T g2 = erf_t<T>((T)((sL[j] - M) * u)) + erf_t<T>((T)((M - sL[j - 1]) * u));
+  acc.add(sC[j - 1] * g2);
+  return 0.5 * acc.value();
 }
 
 // Unit cells: G_{k,j} = g(|k-j|), g from the per-beam table sG[0..n-1].
