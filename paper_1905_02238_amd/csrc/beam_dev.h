@@ -147,15 +147,16 @@ FSMI_DEV double diag_fix(Acc<T>& acc, const double* sL, const T* sC, int j, doub
   return 0.5 * acc.value();
 }
 
-// Eight pairs per compensated add: the block of eight is an FP32 (or FP64)
-// FMA chain, the blocks are Kahan-summed.
+// Terms b0..b1 (1 <= b0 <= b1 <= n) of row j, halved, with the exact diagonal
+// weight if the segment holds b = j.  Eight pairs per compensated add: the
+// block of eight is an FP32 (or FP64) FMA chain, the blocks are Kahan-summed.
 template <typename T>
-FSMI_DEV double row_exact_bound(const double* sL, const T* sC, int n, int j) {
+FSMI_DEV double row_exact_seg(const double* sL, const T* sC, int j, int b0, int b1) {
   const double M = 0.5 * (sL[j - 1] + sL[j]);
   Acc<T> acc;
-  T Eprev = tail_E<T>(sL[0], M);
-  int b = 1;
-  for (; b + 7 <= n; b += 8) {
+  T Eprev = tail_E<T>(sL[b0 - 1], M);
+  int b = b0;
+  for (; b + 7 <= b1; b += 8) {
     T E[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) E[q] = tail_E<T>(sL[b + q], M);
@@ -165,12 +166,36 @@ FSMI_DEV double row_exact_bound(const double* sL, const T* sC, int n, int j) {
     acc.add(p);
     Eprev = E[7];
   }
-  for (; b <= n; ++b) {
+  for (; b <= b1; ++b) {
     T E = tail_E<T>(sL[b], M);
     acc.add(sC[b - 1] * tabs(E - Eprev));
     Eprev = E;
   }
-  return diag_fix<T>(acc, sL, sC, j, M);
+  if (j >= b0 && j <= b1) return diag_fix<T>(acc, sL, sC, j, M);
+  return 0.5 * acc.value();
+}
+
+// sum_j P_j S_j over the n rows of an n x n pair grid, on the G lanes of a
+// group: whole sweeps of G rows (one row per lane), then the last R = n mod G
+// rows, each cut into S = floor(G / R) equal runs of terms, lane l taking row
+// (l mod R), run (l div R), so a partly filled sweep does not leave lanes idle.
+template <int G, typename T>
+FSMI_DEV double exact_rows(const double* sL, const T* sC, const T* sP, int n, int tid) {
+  double tot = 0.0;
+  const int full = (n / G) * G;
+  for (int j = tid + 1; j <= full; j += G) tot += (double)sP[j - 1] * row_exact_seg<T>(sL, sC, j, 1, n);
+  const int R = n - full;
+  if (R > 0) {
+    const int S = G / R;
+    const int r = tid % R, s = tid / R;
+    const int len = (n + S - 1) / S;
+    const int b0 = s * len + 1, b1 = min(n, (s + 1) * len);
+    if (s < S && b0 <= b1) {
+      const int j = full + 1 + r;
+      tot += (double)sP[j - 1] * row_exact_seg<T>(sL, sC, j, b0, b1);
+    }
+  }
+  return tot;
 }
 
 // Skip-zero mode (FP32): only boundaries with |L_b - M_j| <= kSkipY, beyond
@@ -385,7 +410,7 @@ FSMI_DEV double beam_core(const EvalConst& ec, int n, const float* so, bool has_
       if (ec.variant == FSMI_EXACT && (ec.flags & FSMI_F_SKIP_ZERO)) {
         for (int j = tid + 1; j <= n; j += G) tot += (double)sP[j - 1] * row_exact_band<T>(sA, sC, n, j);
       } else if (ec.variant == FSMI_EXACT) {
-        for (int j = tid + 1; j <= n; j += G) tot += (double)sP[j - 1] * row_exact_bound<T>(sA, sC, n, j);
+        tot = exact_rows<G, T>(sA, sC, sP, n, tid);
       } else {
         for (int j = tid + 1; j <= n; j += G)
           tot += (double)sP[j - 1] * row_approx_bound<T>(sA, sC, n, j, ec.Delta);
