@@ -100,6 +100,9 @@ def parse():
     ap.add_argument("--profile-step", action="store_true",
                     help="for counter runs: one plain 256 MiB device copy (the traffic "
                          "calibration), then exactly one timed-workload step, nothing else")
+    ap.add_argument("--profile-variant", choices=("exact", "approx", "uniform"), default="exact",
+                    help="with --profile-step: the FSMI variant of that one step (Approx "
+                         "Delta = 9, Uniform H = 6)")
     ap.add_argument("--profile-surrogate", action="store_true",
                     help="for kernel traces: surrogate forward over 65 536 candidates (3 times) "
                          "and one fsmi_rank_poses, random-initialised weights, nothing else")
@@ -163,7 +166,9 @@ def main():
         torch.cuda.synchronize()
         dst.copy_(src)                      # reads 256 MiB, writes 256 MiB
         torch.cuda.synchronize()
-        ctx.fsmi_eval_poses(prm, grid, poses, bdir, sigma, R)
+        pv = {"exact": prm, "approx": F.params(variant=F.FSMI_APPROX, trunc_delta=wl["Delta"]),
+              "uniform": F.params(variant=F.FSMI_UNIFORM, uniform_h=wl["H"])}[args.profile_variant]
+        ctx.fsmi_eval_poses(pv, grid, poses, bdir, sigma, R)
         torch.cuda.synchronize()
         ctx.fsmi_sync()
         log("[bench] profile step done")

@@ -285,6 +285,11 @@ fsmi_status fsmi_rank_poses(fsmi_ctx ctx, const fsmi_params* params, fsmi_sur ne
    out[i] = the library's FP32 erfc at z[i] >= 0 (the function every Gaussian
    weight G_{k,j} is built from), so its error can be measured against FP64. */
 fsmi_status fsmi_probe_erfc(fsmi_ctx ctx, int64_t n, const float* z, float* out);
+/* out[i] (device FP64) = f(delta, o[i]) of Sec. 2.2 (the log-odds update of a
+   cell of occupancy o[i] for the odds ratio delta), as the FP32 mode evaluates
+   it.  o (device FP32) in [0, 1]; delta > 0 and finite (the FP32 mode calls it
+   with delta_occ and with 1/delta_occ). */
+fsmi_status fsmi_probe_f(fsmi_ctx ctx, double delta, int64_t n, const float* o, double* out);
 /* D (device FP32 16x16, row-major) = A (BF16 16x32) * B (BF16 32x16) through one
    matrix-core instruction, so its operand layout can be checked. */
 fsmi_status fsmi_probe_mfma(fsmi_ctx ctx, const void* A, const void* B, float* D);

@@ -362,4 +362,12 @@ fsmi_status fsmi_probe_erfc(fsmi_ctx ctx, int64_t n, const float* z, float* out)
   return from_hip(ctx, launch_erfc_probe(ctx, n, z, out), "probe_erfc");
 }
 
+fsmi_status fsmi_probe_f(fsmi_ctx ctx, double delta, int64_t n, const float* o, double* out) {
+  if (!ctx) return FSMI_E_INVAL;
+  if (!(delta > 0.0) || !(delta < 1e300) || n < 0 || (n > 0 && (!o || !out)))
+    return fail(ctx, FSMI_E_INVAL, "bad probe arguments");
+  (void)hipSetDevice(ctx->device);
+  return from_hip(ctx, launch_f_probe(ctx, delta, n, o, out), "probe_f");
+}
+
 }  // extern "C"

@@ -6,11 +6,12 @@
 // weights G_{k,j} (Eq. G_jk), its truncated form (Eq. fsmi_approx), or the
 // uniform-noise form (Thm 4 / Alg 4).
 //
-// Numerics (FP32 mode): the prefix product of (1 - o) and the C_k prefix are
-// scanned in FP64; the O(n^2) loop is FP32 with one erfc per (row j,
-// boundary), evaluated on the tail side of mu_j so that no digits cancel, and
-// a Kahan-compensated sum over blocks of four terms; each row's P_j S_j is
-// accumulated in FP64 and the group total is a fixed-order tree.
+// Numerics (FP32 mode): f is evaluated in FP64 (f_cell_series); the prefix
+// product of (1 - o) and the C_k prefix are scanned in FP64; the O(n^2) loop
+// is FP32 with one erfc per (row j, boundary), evaluated on the tail side of
+// mu_j so that no digits cancel, and a Kahan-compensated sum over blocks of
+// eight terms; each row's P_j S_j is accumulated in FP64 and the group total
+// is a fixed-order tree.
 #pragma once
 #include <math.h>
 
@@ -331,8 +332,9 @@ FSMI_DEV double beam_core(const EvalConst& ec, int n, const float* so, bool has_
   double* sA = L.A;
   T* sC = reinterpret_cast<T*>(L.C);
   T* sP = reinterpret_cast<T*>(L.P);
-  const T docc = (T)ec.delta_occ, demp = (T)(1.0 / ec.delta_occ);
-  const T ldo = (T)log(ec.delta_occ), lde = -(T)log(ec.delta_occ);
+  const double docc = ec.delta_occ, demp = 1.0 / ec.delta_occ;
+  const double ldo = log(ec.delta_occ), lde = -ldo;
+  const FConst ko = f_const(docc), ke = f_const(demp);
   const bool uni = ec.variant == FSMI_UNIFORM;
   bool bad = bad_in;
   if (!(sigma > 0.0) && !uni) bad = true;
@@ -347,12 +349,19 @@ FSMI_DEV double beam_core(const EvalConst& ec, int n, const float* so, bool has_
     const bool v = i < n;
     const float of = v ? so[i] : 0.0f;
     if (v && !(of >= 0.0f && of <= 1.0f)) bad = true;
-    const T o = (T)of;
-    const T fo = v ? f_cell<T>(docc, ldo, o) : T(0);
-    const T fe = v ? f_cell<T>(demp, lde, o) : T(0);
-    const double q = group_scan_excl<NW, BLOCK, OpAdd>((double)fe, carryC, scratch, tid);
-    const double E = group_scan_excl<NW, BLOCK, OpMul>(v ? 1.0 - (double)of : 1.0, carryE, scratch, tid);
-    const double Ck = q + (double)fo;
+    const double o = (double)of;
+    double fo, fe;
+    if constexpr (sizeof(T) == 4) {
+      fo = f_cell_series(ko, o);
+      fe = f_cell_series(ke, o);
+    } else {
+      fo = f_cell<double>(docc, ldo, o);
+      fe = f_cell<double>(demp, lde, o);
+    }
+    if (!v) fo = fe = 0.0;
+    const double q = group_scan_excl<NW, BLOCK, OpAdd>(fe, carryC, scratch, tid);
+    const double E = group_scan_excl<NW, BLOCK, OpMul>(v ? 1.0 - o : 1.0, carryE, scratch, tid);
+    const double Ck = q + fo;
     if (v) {
       sC[i] = (T)Ck;
       sP[i] = (T)(E * (double)of);

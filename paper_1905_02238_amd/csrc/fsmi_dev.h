@@ -124,27 +124,15 @@ FSMI_DEV double erfc_pos(double z) { return erfc(z); }
 
 // ---------------------------------------------------------------------------
 // f(delta, o) of Sec. 2.2 written in the occupancy o = r/(1+r).
-// With s = 1 + o(delta-1): f = (o delta / s) ln(delta) - log1p(o (delta-1)).
+// With s = 1 + o(delta-1): f = (o delta / s) ln(delta) - ln s.
 // Near o = 1 both terms approach ln(delta) and cancel, so for o > 1/2 the
-// equivalent form in u = 1 - o is used:
-//   f = -log1p(-u a) - u ln(delta) / (delta (1 - u a)),  a = (delta-1)/delta.
+// equivalent form in u = 1 - o is used (s = delta (1 - u a)):
+//   f = -log1p(-u a) - u ln(delta) / s,  a = (delta-1)/delta.
 // ---------------------------------------------------------------------------
 template <typename T>
 FSMI_DEV T f_cell(T delta, T ln_delta, T o);
 
-template <>
-FSMI_DEV float f_cell<float>(float delta, float ln_delta, float o) {
-  if (o <= 0.5f) {
-    float dm1 = delta - 1.0f;
-    float s = fmaf(o, dm1, 1.0f);
-    return (o * delta / s) * ln_delta - log1pf(o * dm1);
-  }
-  float u = 1.0f - o;
-  float a = (delta - 1.0f) / delta;
-  float ua = u * a;
-  return -log1pf(-ua) - u * ln_delta / (delta * (1.0f - ua));
-}
-
+// FP64 mode: device libm.
 template <>
 FSMI_DEV double f_cell<double>(double delta, double ln_delta, double o) {
   if (o <= 0.5) {
@@ -156,6 +144,52 @@ FSMI_DEV double f_cell<double>(double delta, double ln_delta, double o) {
   double a = (delta - 1.0) / delta;
   double ua = u * a;
   return -log1p(-ua) - u * ln_delta / (delta * (1.0 - ua));
+}
+
+// FP32 mode: the same two forms, chosen per lane by a select (no branch),
+// in FP64 arithmetic with a short series for the logarithm, so that neither
+// form's cancellation reaches FP32 precision (relative error about 1e-12 of f
+// for delta in [1.001, 100]).
+//   ln(1 + x) = e ln 2 + 2 atanh(z),  1 + x = m 2^e,  m in [sqrt(1/2), sqrt 2),
+//   z = (m - 1)/(m + 1), or z = x/(2 + x) straight from x when e = 0, so a
+//   small x keeps every digit; 2 atanh(z) = z sum_k 2 z^(2k)/(2k+1), k <= 6,
+//   |z| <= 0.1716: truncation below 2e-12 relative.
+// The quotients take the hardware reciprocal and one Newton step.
+struct FConst {
+  double delta, dm1, a, ln_delta;   // delta, delta - 1, (delta - 1)/delta, ln delta
+};
+FSMI_DEV FConst f_const(double delta) {
+  return FConst{delta, delta - 1.0, (delta - 1.0) / delta, log(delta)};
+}
+FSMI_DEV double rcp_f64(double d) {
+  const double r = __builtin_amdgcn_rcp(d);
+  return fma(r, fma(-d, r, 1.0), r);
+}
+FSMI_DEV double ln1p_series(double x) {   // x > -1
+  const double y = 1.0 + x;
+  double m = __builtin_amdgcn_frexp_mant(y);   // [1/2, 1)
+  int e = __builtin_amdgcn_frexp_exp(y);
+  if (m < 0.70710678118654752440) m += m, e -= 1;
+  const bool e0 = e == 0;
+  const double zn = e0 ? x : m - 1.0;
+  const double zd = e0 ? 2.0 + x : m + 1.0;
+  const double z = zn * rcp_f64(zd);
+  const double w = z * z;
+  double p = fma(w, 2.0 / 13.0, 2.0 / 11.0);
+  p = fma(w, p, 2.0 / 9.0);
+  p = fma(w, p, 2.0 / 7.0);
+  p = fma(w, p, 2.0 / 5.0);
+  p = fma(w, p, 2.0 / 3.0);
+  p = fma(w, p, 2.0);
+  return fma((double)e, 0.69314718055994530942, z * p);
+}
+FSMI_DEV double f_cell_series(const FConst& k, double o) {
+  const bool lo = o <= 0.5;
+  const double u = 1.0 - o;
+  const double x = lo ? o * k.dm1 : -u * k.a;
+  const double num = lo ? o * k.delta : -u;
+  const double s = fma(o, k.dm1, 1.0);
+  return fma(num, k.ln_delta * rcp_f64(s), -ln1p_series(x));
 }
 
 // ---------------------------------------------------------------------------

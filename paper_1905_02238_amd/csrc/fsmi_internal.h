@@ -97,5 +97,6 @@ hipError_t launch_eval_poses_3d(fsmi_ctx ctx, const EvalConst& ec, const float* 
 
 // ---- diagnostics (k_beam.hip) ----
 hipError_t launch_erfc_probe(fsmi_ctx ctx, int64_t n, const float* z, float* out);
+hipError_t launch_f_probe(fsmi_ctx ctx, double delta, int64_t n, const float* o, double* out);
 
 }  // namespace fsmi

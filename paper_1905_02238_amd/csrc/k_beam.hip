@@ -215,7 +215,20 @@ __global__ void k_erfc_probe(int64_t n, const float* z, float* out) {
   if (i < n) out[i] = erfc_pos(z[i]);
 }
 
+__global__ void k_f_probe(FConst k, int64_t n, const float* o, double* out) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) out[i] = f_cell_series(k, (double)o[i]);
+}
+
 }  // namespace
+
+hipError_t launch_f_probe(fsmi_ctx ctx, double delta, int64_t n, const float* o, double* out) {
+  if (n <= 0) return hipSuccess;
+  const FConst k{delta, delta - 1.0, (delta - 1.0) / delta, log(delta)};
+  const int64_t blocks = (n + 255) / 256;
+  hipLaunchKernelGGL(k_f_probe, dim3((unsigned)blocks), dim3(256), 0, ctx->stream, k, n, o, out);
+  return hipGetLastError();
+}
 
 hipError_t launch_erfc_probe(fsmi_ctx ctx, int64_t n, const float* z, float* out) {
   if (n <= 0) return hipSuccess;

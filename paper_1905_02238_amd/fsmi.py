@@ -28,7 +28,7 @@ FSMI_F_SKIP_ZERO = 1
 
 EXPORTS = ("fsmi_create", "fsmi_destroy", "fsmi_set_stream", "fsmi_sync", "fsmi_last_error",
            "fsmi_status_string", "fsmi_default_params", "fsmi_raycast", "fsmi_eval_beams",
-           "fsmi_rle_eval_beams", "fsmi_eval_poses", "fsmi_probe_erfc", "fsmi_probe_mfma",
+           "fsmi_rle_eval_beams", "fsmi_eval_poses", "fsmi_probe_erfc", "fsmi_probe_f", "fsmi_probe_mfma",
            "fsmi_sur_num_params", "fsmi_sur_create", "fsmi_sur_destroy",
            "fsmi_sur_fit_label_stats", "fsmi_sur_get_label_stats", "fsmi_sur_forward",
            "fsmi_sur_backward", "fsmi_sur_adam_step", "fsmi_sur_get_params",
@@ -90,6 +90,7 @@ def load(path: str = LIB_PATH):
             L.fsmi_eval_poses.argtypes = [p, C.POINTER(fsmi_params), C.POINTER(fsmi_map), i64, p,
                                           i64, p, d, d, d, p, p]
             L.fsmi_probe_erfc.argtypes = [p, i64, p, p]
+            L.fsmi_probe_f.argtypes = [p, d, i64, p, p]
             L.fsmi_probe_mfma.argtypes = [p, p, p, p]
             L.fsmi_sur_num_params.argtypes = []
             L.fsmi_sur_num_params.restype = i64
@@ -116,7 +117,7 @@ def load(path: str = LIB_PATH):
             L.fsmi_plan_destroy.restype = None
             for n in ("fsmi_create", "fsmi_set_stream", "fsmi_sync", "fsmi_raycast",
                       "fsmi_eval_beams", "fsmi_rle_eval_beams", "fsmi_eval_poses",
-                      "fsmi_probe_erfc", "fsmi_probe_mfma", "fsmi_sur_create",
+                      "fsmi_probe_erfc", "fsmi_probe_f", "fsmi_probe_mfma", "fsmi_sur_create",
                       "fsmi_sur_fit_label_stats", "fsmi_sur_get_label_stats", "fsmi_sur_forward",
                       "fsmi_sur_backward", "fsmi_sur_adam_step", "fsmi_sur_get_params",
                       "fsmi_sur_set_params", "fsmi_sur_get_grads", "fsmi_sur_save",
@@ -270,6 +271,13 @@ class Context:
                                               _ptr(out, torch.float32, "out")))
         return out
 
+    def fsmi_probe_f(self, delta, o):
+        out = torch.empty(o.shape, dtype=torch.float64, device=o.device)
+        self._stream()
+        self._check(self._lib.fsmi_probe_f(self.handle, float(delta), o.numel(),
+                                           _ptr(o, torch.float32, "o"),
+                                           _ptr(out, torch.float64, "out")))
+        return out
 
     def fsmi_probe_mfma(self, A, B):
         D = torch.empty((16, 16), dtype=torch.float32, device=A.device)

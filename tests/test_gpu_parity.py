@@ -55,6 +55,33 @@ def test_erfc_error_bound(ctx):
     assert e.max() < 2e-5, e.max()
 
 
+def test_f_fp32_mode_error_bound(ctx):
+    """f(delta, o) of the FP32 mode (FP64 series, two forms split at o = 1/2)
+    against mpmath at 40 digits, for delta_occ and 1/delta_occ over a wide
+    range of delta, on o from 0 to 1 including values close to both ends,
+    where the two terms of f nearly cancel."""
+    import mpmath as mp
+    mp.mp.dps = 40
+    rng = np.random.default_rng(11)
+    o = np.concatenate([np.linspace(0, 1, 1001), rng.random(1000), 10.0 ** -rng.uniform(1, 7, 300),
+                        1 - 10.0 ** -rng.uniform(1, 7, 300),
+                        [np.nextafter(np.float32(1), np.float32(0)), np.float32(1e-30)]]).astype(np.float32)
+    for dl in (1.001, 1.5, 4.0, 100.0):
+        for d in (dl, 1.0 / dl):
+            got = ctx.fsmi_probe_f(d, dev(o)).cpu().numpy()
+            D = mp.mpf(d)
+
+            def f_ref(v):           # x = o (delta - 1) is exact at this precision
+                x = mp.mpf(float(v)) * (D - 1)
+                return float(mp.mpf(float(v)) * D * mp.log(D) / (1 + x) - mp.log1p(x))
+            ref = np.array([f_ref(v) for v in o])
+            assert got[o == 0].tolist() == [0.0] * int(np.sum(o == 0))
+            assert got[o == 1].tolist() == [0.0] * int(np.sum(o == 1))
+            nz = (o != 0) & (o != 1)
+            rel = np.abs(got[nz] - ref[nz]) / np.abs(ref[nz])
+            assert rel.max() < 1e-9, (d, float(rel.max()))
+
+
 # ---------------------------------------------------------------------------
 def _rays_2d(seed, X, Y, n, R_lo=1, R_hi=80):
     rng = np.random.default_rng(seed)
