@@ -11,7 +11,7 @@
 // strictly increasing event times, an exact x/y tie being one diagonal step.
 // Each lane produces event times independently, and an event's place in the
 // merged order is its own index plus the number of events of the other axis
-// strictly before it (a binary search), minus the ties strictly before it.
+// strictly before it (count_below), minus the ties strictly before it.
 // This reproduces, bit for bit, the sequential walk that steps whichever face
 // is nearer: same event values, same order, same cells.
 #pragma once
@@ -76,8 +76,11 @@ FSMI_DEV Dda2dResult dda2d_wave(int64_t X, int64_t Y, double px, double py, doub
   res.lend = 0.0;
   if (!(px >= 0.0 && px < (double)X && py >= 0.0 && py < (double)Y)) return res;
   if (dx == 0.0 && dy == 0.0) return res;
-  const int64_t cx0 = (int64_t)floor(px), cy0 = (int64_t)floor(py);
-  res.cell0 = cx0 + X * cy0;
+  // The map has fewer than 2^31 cells (checked at the boundary), so cell
+  // coordinates, the one-past-the-edge ones included, and indices fit int32.
+  const int Xi = (int)X, Yi = (int)Y;
+  const int cx0 = (int)floor(px), cy0 = (int)floor(py);
+  res.cell0 = cx0 + (int64_t)Xi * cy0;
   const int sx = dx > 0.0 ? 1 : (dx < 0.0 ? -1 : 0);
   const int sy = dy > 0.0 ? 1 : (dy < 0.0 ? -1 : 0);
   const double fx0 = sx > 0 ? (double)(cx0 + 1) : (double)cx0;
@@ -95,59 +98,57 @@ FSMI_DEV Dda2dResult dda2d_wave(int64_t X, int64_t Y, double px, double py, doub
     res.n = -2;
     return res;
   }
-  // events before R (the times increase, so they form a prefix)
-  int Nx = 0, Ny = 0;
-  for (int i = lane; i < nx; i += kWave) Nx += tx(i) < R ? 1 : 0;
-  for (int i = lane; i < ny; i += kWave) Ny += ty(i) < R ? 1 : 0;
-  Nx = wave_sum(Nx);
-  Ny = wave_sum(Ny);
-  // x events: ties with y events, exclusive prefix count of ties
+  // events before R (the times increase, so they form a prefix); the same
+  // count in every lane
+  const int Nx = count_below(tx, nx, R, adx);
+  const int Ny = count_below(ty, ny, R, ady);
+  // the first event decides whether the origin cell has zero length
+  double t0 = 1.0 / 0.0;
+  if (Nx > 0) t0 = tx(0);
+  if (Ny > 0 && ty(0) < t0) t0 = ty(0);
+  int first_out = 0x7fffffff;   // rank of the first event that leaves the map
+  double t_out = 0.0;
+  // x events, a chunk of 64 at a time: the y events before each, its tie (an
+  // equal y event time: one diagonal step), the exclusive prefix count of ties
+  // (kept for the y events), its rank, and the cell it enters
   int carry = 0;
   for (int base = 0; base < Nx; base += kWave) {
     const int i = base + lane;
-    int tie = 0;
+    int tie = 0, c = 0;
+    double t = 0.0;
     if (i < Nx) {
-      const double t = tx(i);
-      const int c = count_below(ty, Ny, t, ady);
+      t = tx(i);
+      c = count_below(ty, Ny, t, ady);
       tie = (c < Ny && ty(c) == t) ? 1 : 0;
     }
     const int inc = wave_scan_incl<OpAdd>(tie);
-    if (i < Nx) tiep[i] = carry + inc - tie;
+    if (i < Nx) {
+      const int before = carry + inc - tie;
+      tiep[i] = before;
+      const int r = i + c - before;
+      const int cx = cx0 + sx * (i + 1);
+      const int cy = cy0 + sy * (c + tie);
+      const bool in = cx >= 0 && cx < Xi && cy >= 0 && cy < Yi;
+      if (!in && r < first_out) first_out = r, t_out = t;
+      emit(r, t, in ? cx + Xi * cy : -1);
+    }
     carry += wave_last(inc);
   }
   if (lane == 0) tiep[Nx] = carry;
   wave_sync();
   const int K = Nx + Ny - carry;
-  // the first event decides whether the origin cell has zero length
-  double t0 = 1.0 / 0.0;
-  if (Nx > 0) t0 = tx(0);
-  if (Ny > 0 && ty(0) < t0) t0 = ty(0);
   res.skip0 = (K >= 1 && !(t0 > 0.0)) ? 1 : 0;
-  int first_out = K;
-  double t_out = 0.0;
-  // x events
-  for (int i = lane; i < Nx; i += kWave) {
-    const double t = tx(i);
-    const int c = count_below(ty, Ny, t, ady);
-    const int tie = (c < Ny && ty(c) == t) ? 1 : 0;
-    const int r = i + c - tiep[i];
-    const int64_t cx = cx0 + (int64_t)sx * (i + 1);
-    const int64_t cy = cy0 + (int64_t)sy * (c + tie);
-    const bool in = cx >= 0 && cx < X && cy >= 0 && cy < Y;
-    if (!in && r < first_out) first_out = r, t_out = t;
-    emit(r, t, in ? (int)(cx + X * cy) : -1);
-  }
   // y events that do not tie with an x event
   for (int m = lane; m < Ny; m += kWave) {
     const double t = ty(m);
     const int c = count_below(tx, Nx, t, adx);
     if (c < Nx && tx(c) == t) continue;
     const int r = m + c - tiep[c];
-    const int64_t cy = cy0 + (int64_t)sy * (m + 1);
-    const int64_t cx = cx0 + (int64_t)sx * c;
-    const bool in = cx >= 0 && cx < X && cy >= 0 && cy < Y;
+    const int cy = cy0 + sy * (m + 1);
+    const int cx = cx0 + sx * c;
+    const bool in = cx >= 0 && cx < Xi && cy >= 0 && cy < Yi;
     if (!in && r < first_out) first_out = r, t_out = t;
-    emit(r, t, in ? (int)(cx + X * cy) : -1);
+    emit(r, t, in ? cx + Xi * cy : -1);
   }
   const int mine = first_out;
   first_out = wave_min(first_out);
