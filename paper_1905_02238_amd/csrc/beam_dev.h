@@ -343,34 +343,65 @@ FSMI_DEV double beam_core(const EvalConst& ec, int n, const float* so, bool has_
       if (!(sA[i] >= sA[i - 1])) bad = true;
   }
   // ---- per-cell f, Alg 2 and Alg 3 (FP64 scans) ----
+  // Each lane takes kv consecutive cells of a chunk of kv * G (kv <= 4, as
+  // many as the cells left need, so a short tail does not evaluate f for
+  // empty slots): it scans them in order itself, and one group scan over the
+  // lanes' totals serves all kv.  A lane reads o_i and writes P_i only at its
+  // own cells (P may share o's storage).
   double carryC = 0.0, carryE = 1.0, carryD = 0.0;
-  for (int base = 0; base < n; base += G) {
-    const int i = base + tid;
-    const bool v = i < n;
-    const float of = v ? so[i] : 0.0f;
-    if (v && !(of >= 0.0f && of <= 1.0f)) bad = true;
-    const double o = (double)of;
-    double fo, fe;
-    if constexpr (sizeof(T) == 4) {
-      fo = f_cell_series(ko, o);
-      fe = f_cell_series(ke, o);
-    } else {
-      fo = f_cell<double>(docc, ldo, o);
-      fe = f_cell<double>(demp, lde, o);
+  for (int base = 0; base < n;) {
+    const int kv = min(4, (n - base + G - 1) / G);   // group-uniform
+    const int i0 = base + kv * tid;
+    float of[4];
+    double fo[4], qin[4], ein[4];
+    double qs = 0.0, es = 1.0;   // this lane's running sum of f_emp, product of 1 - o
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (u >= kv) break;
+      const bool v = i0 + u < n;
+      of[u] = v ? so[i0 + u] : 0.0f;
+      if (v && !(of[u] >= 0.0f && of[u] <= 1.0f)) bad = true;
+      const double o = (double)of[u];
+      double fe;
+      if constexpr (sizeof(T) == 4) {
+        fo[u] = f_cell_series(ko, o);
+        fe = f_cell_series(ke, o);
+      } else {
+        fo[u] = f_cell<double>(docc, ldo, o);
+        fe = f_cell<double>(demp, lde, o);
+      }
+      if (!v) fo[u] = fe = 0.0;
+      qin[u] = qs;
+      ein[u] = es;
+      qs += fe;
+      es *= v ? 1.0 - o : 1.0;
     }
-    if (!v) fo = fe = 0.0;
-    const double q = group_scan_excl<NW, BLOCK, OpAdd>(fe, carryC, scratch, tid);
-    const double E = group_scan_excl<NW, BLOCK, OpMul>(v ? 1.0 - o : 1.0, carryE, scratch, tid);
-    const double Ck = q + fo;
-    if (v) {
-      sC[i] = (T)Ck;
-      sP[i] = (T)(E * (double)of);
+    const double q = group_scan_excl<NW, BLOCK, OpAdd>(qs, carryC, scratch, tid);
+    const double E = group_scan_excl<NW, BLOCK, OpMul>(es, carryE, scratch, tid);
+    double Ck[4], ds = 0.0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (u >= kv) break;
+      Ck[u] = (q + qin[u]) + fo[u];
+      if (i0 + u < n) {
+        sC[i0 + u] = (T)Ck[u];
+        sP[i0 + u] = (T)((E * ein[u]) * (double)of[u]);
+        ds += Ck[u];
+      }
     }
     if (uni) {  // D_k = sum_{i<=k} C_i in FP64 at A[k], A[0] = 0
-      const double Dk = group_scan_excl<NW, BLOCK, OpAdd>(v ? Ck : 0.0, carryD, scratch, tid) + (v ? Ck : 0.0);
-      if (v) sA[i + 1] = Dk;
+      double d = group_scan_excl<NW, BLOCK, OpAdd>(ds, carryD, scratch, tid);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (u >= kv) break;
+        if (i0 + u < n) {
+          d += Ck[u];
+          sA[i0 + u + 1] = d;
+        }
+      }
       if (tid == 0 && base == 0) sA[0] = 0.0;
     }
+    base += kv * G;
   }
   const double c = 1.0 / (sigma * 1.4142135623730951);
   if (!uni && !has_bound) {
