@@ -93,7 +93,6 @@ template <typename T> FSMI_DEV T tabs(T x) {
   if constexpr (sizeof(T) == 8) return __builtin_fabs(x);
   else return __builtin_fabsf(x);
 }
-FSMI_DEV int clampi(int x, int lo, int hi) { return x < lo ? lo : (x > hi ? hi : x); }
 
 template <typename T> FSMI_DEV T erf_t(T x);
 template <> FSMI_DEV float erf_t<float>(float x) { return erff(x); }
@@ -242,26 +241,33 @@ FSMI_DEV double row_exact_band(const double* sL, const T* sC, int n, int j) {
   return diag_fix<T>(acc, sL, sC, j, M);
 }
 
+// Cells k in [k0, k1) of row j on the tail side given by Eprev (the tail
+// value at boundary k0 - 1): sum of C_k |E_k - E_{k-1}| in FMA chains of up
+// to eight terms, each chain Kahan-added to acc.
+template <typename T>
+FSMI_DEV void row_side(const double* sL, const T* sC, double M, int k0, int k1, T Eprev,
+                       Acc<T>& acc) {
+  for (int b = k0; b < k1; b += 8) {
+    const int e = min(b + 8, k1);
+    T p = T(0);
+    for (int k = b; k < e; ++k) {
+      const T E = tail_E<T>(sL[k], M);
+      p = fma(sC[k - 1], tabs(E - Eprev), p);
+      Eprev = E;
+    }
+    acc.add(p);
+  }
+}
+
 template <typename T>
 FSMI_DEV double row_approx_bound(const double* sL, const T* sC, int n, int j, int D) {
   const double M = 0.5 * (sL[j - 1] + sL[j]);
+  // cells k = j-D..j+D inside the beam; the hit cell k = j takes the exact
+  // weight of its two half widths, the others their tail differences
+  const int k0 = max(1, j - D), k1 = min(n, j + D);
   Acc<T> acc;
-  // cells k = j-D..j+D; cell k spans [sL[k-1], sL[k]]; indices clamped to the
-  // beam so out-of-range cells see two equal boundaries and weigh zero
-  // The hit cell k = j is peeled out of the loop: it takes the exact weight
-  // of the two half widths, and its boundaries' tail values are not needed.
-  T Eprev = tail_E<T>(sL[clampi(j - D - 1, 0, n)], M);
-  for (int k = j - D; k < j; ++k) {
-    const T E = tail_E<T>(sL[clampi(k, 0, n)], M);
-    acc.add(sC[clampi(k - 1, 0, n - 1)] * tabs(E - Eprev));
-    Eprev = E;
-  }
-  Eprev = tail_E<T>(sL[j], M);
-  for (int k = j + 1; k <= j + D; ++k) {
-    const T E = tail_E<T>(sL[clampi(k, 0, n)], M);
-    acc.add(sC[clampi(k - 1, 0, n - 1)] * tabs(E - Eprev));
-    Eprev = E;
-  }
+  row_side<T>(sL, sC, M, k0, j, tail_E<T>(sL[k0 - 1], M), acc);
+  row_side<T>(sL, sC, M, j + 1, k1 + 1, tail_E<T>(sL[j], M), acc);
   constexpr double u = unscale<T>();
   const T g2 = erf_t<T>((T)((sL[j] - M) * u)) + erf_t<T>((T)((M - sL[j - 1]) * u));
   acc.add(sC[j - 1] * g2);
@@ -307,7 +313,12 @@ FSMI_DEV double row_approx_unit(const T* sG, const T* sC, int n, int j, int D) {
   const UnitRow<T> w(sG, n, j);
   Acc<T> acc;
   const int k0 = max(1, j - D), k1 = min(n, j + D);
-  for (int k = k0; k <= k1; ++k) acc.add(sC[k - 1] * w(k));
+  for (int b = k0; b <= k1; b += 8) {
+    const int e = min(b + 7, k1);
+    T p = T(0);
+    for (int k = b; k <= e; ++k) p = fma(sC[k - 1], w(k), p);
+    acc.add(p);
+  }
   return acc.value();
 }
 
