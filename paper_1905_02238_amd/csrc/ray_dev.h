@@ -35,13 +35,30 @@ struct FaceTimes {
 // A(i) ~ A(0) + i / rate (rate = |d| of that axis).  The spacing gives the
 // count to within rounding; the two loops then move it to the exact boundary
 // with the true comparisons, so the result is exact for any input (usually
-// after one or two evaluations).
-FSMI_DEV int count_below(const FaceTimes& A, int N, double key, double rate) {
+// after one or two evaluations).  When the count c is below N, *at receives
+// A(c), the first face time at or after key (every path evaluates it).
+FSMI_DEV int count_below(const FaceTimes& A, int N, double key, double rate, double* at) {
   if (N <= 0) return 0;
   const double e = (key - A(0)) * rate;
   int c = !(e > 0.0) ? 0 : (e >= (double)N ? N : (int)ceil(e));
-  while (c > 0 && A(c - 1) >= key) --c;
-  while (c < N && A(c) < key) ++c;
+  bool down = false;
+  while (c > 0) {
+    const double v = A(c - 1);
+    if (v < key) break;
+    --c;
+    *at = v;
+    down = true;
+  }
+  if (!down) {
+    while (c < N) {
+      const double v = A(c);
+      if (v >= key) {
+        *at = v;
+        break;
+      }
+      ++c;
+    }
+  }
   return c;
 }
 
@@ -100,8 +117,9 @@ FSMI_DEV Dda2dResult dda2d_wave(int64_t X, int64_t Y, double px, double py, doub
   }
   // events before R (the times increase, so they form a prefix); the same
   // count in every lane
-  const int Nx = count_below(tx, nx, R, adx);
-  const int Ny = count_below(ty, ny, R, ady);
+  double unused;
+  const int Nx = count_below(tx, nx, R, adx, &unused);
+  const int Ny = count_below(ty, ny, R, ady, &unused);
   // the first event decides whether the origin cell has zero length
   double t0 = 1.0 / 0.0;
   if (Nx > 0) t0 = tx(0);
@@ -118,8 +136,9 @@ FSMI_DEV Dda2dResult dda2d_wave(int64_t X, int64_t Y, double px, double py, doub
     double t = 0.0;
     if (i < Nx) {
       t = tx(i);
-      c = count_below(ty, Ny, t, ady);
-      tie = (c < Ny && ty(c) == t) ? 1 : 0;
+      double at = 0.0;
+      c = count_below(ty, Ny, t, ady, &at);
+      tie = (c < Ny && at == t) ? 1 : 0;
     }
     const int inc = wave_scan_incl<OpAdd>(tie);
     if (i < Nx) {
@@ -141,8 +160,9 @@ FSMI_DEV Dda2dResult dda2d_wave(int64_t X, int64_t Y, double px, double py, doub
   // y events that do not tie with an x event
   for (int m = lane; m < Ny; m += kWave) {
     const double t = ty(m);
-    const int c = count_below(tx, Nx, t, adx);
-    if (c < Nx && tx(c) == t) continue;
+    double at = 0.0;
+    const int c = count_below(tx, Nx, t, adx, &at);
+    if (c < Nx && at == t) continue;
     const int r = m + c - tiep[c];
     const int cy = cy0 + sy * (m + 1);
     const int cx = cx0 + sx * c;
