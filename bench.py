@@ -241,6 +241,29 @@ def main():
                      "work": f"{SLOTS_PER_PAIR} VALU slots per (row, boundary) pair"},
     }
 
+    # the chip's ceilings measured by the library's own microbenchmarks, beside
+    # the published peaks (outside the timed region)
+    ceil = {}
+    for key, kind in (("hbm_copy_TBps", F.FSMI_PEAK_COPY), ("fp32_fma_TFLOPs", F.FSMI_PEAK_FMA),
+                      ("phi_pair_Tpairs_per_s", F.FSMI_PEAK_PAIR),
+                      ("bf16_mfma_TFLOPs", F.FSMI_PEAK_MFMA_BF16)):
+        rate, mhz = ctx.fsmi_peak(kind, with_clock=True)
+        ceil[key] = rate / 1e12
+        ceil[key.split("_")[0] + "_" + key.split("_")[1] + "_clock_MHz"] = mhz
+    out["measured_ceilings"] = ceil
+    roof = out["roofline"]
+    roof["measured_peak"] = ceil["fp32_fma_TFLOPs"] / 2      # one FMA per issue slot
+    roof["frac_of_measured"] = achieved / roof["measured_peak"]
+    roof["pairs_per_s"] = pairs / (kern_ms * 1e-3)
+    roof["frac_of_phi_pair_ceiling"] = roof["pairs_per_s"] / (ceil["phi_pair_Tpairs_per_s"] * 1e12)
+    log(f"[bench] measured ceilings: copy {ceil['hbm_copy_TBps']:.2f} TB/s, FP32 FMA "
+        f"{ceil['fp32_fma_TFLOPs']:.1f} TFLOP/s, erfc+FMA pairs {ceil['phi_pair_Tpairs_per_s']:.3f} "
+        f"T pairs/s, BF16 MFMA {ceil['bf16_mfma_TFLOPs']:.0f} TFLOP/s (shader clocks "
+        f"{ceil['hbm_copy_clock_MHz']:.0f}, {ceil['fp32_fma_clock_MHz']:.0f}, "
+        f"{ceil['phi_pair_clock_MHz']:.0f}, {ceil['bf16_mfma_clock_MHz']:.0f} MHz); exact at "
+        f"{roof['frac_of_measured']:.3f} of the measured slot rate, "
+        f"{roof['frac_of_phi_pair_ceiling']:.3f} of the erfc+FMA pair ceiling")
+
     gpu = {"exact": mp}      # results the oracle leg checks, per workload
     # ---- extras: other variants and workloads, one timed run each ----
     if not args.quick:
@@ -324,6 +347,8 @@ def main():
                                             want_beams=True)
             log(f"[bench] {name}: {nv/dt/1e6:.2f} M beams/s")
         extras["surrogate_rank"] = surrogate_leg(ctx, F, W, t, timed, args)
+        extras["surrogate_rank"]["forward_frac_of_measured_mfma"] = (
+            extras["surrogate_rank"]["forward_tflops"] / ceil["bf16_mfma_TFLOPs"])
         out["extras"] = extras
 
     # ---- the oracle: CPU baseline and the error report, from the same runs ----

@@ -294,6 +294,26 @@ fsmi_status fsmi_probe_f(fsmi_ctx ctx, double delta, int64_t n, const float* o, 
    matrix-core instruction, so its operand layout can be checked. */
 fsmi_status fsmi_probe_mfma(fsmi_ctx ctx, const void* A, const void* B, float* D);
 
+/* ---- machine ceilings ----
+   Runs one of the library's own microbenchmarks on ctx's device, on ctx's
+   stream, and returns the measured rate in *rate and, if clock_mhz is not
+   NULL, the shader clock its waves ran at (their cycle counts over the
+   constant-rate wall clock), in MHz.  Waits for the device.
+   Allocates and frees its own buffers: 2 GiB for the copy, a few MiB for the
+   others.  FSMI_E_INVAL for another kind.
+     FSMI_PEAK_COPY       bytes/s moved by a plain device-to-device copy of
+                          1 GiB, bytes read plus bytes written (the HBM roof);
+     FSMI_PEAK_FMA        FP32 FLOP/s of independent scalar FMA chains, 2 FLOP
+                          per FMA (this library does not use packed FP32);
+     FSMI_PEAK_PAIR       pairs/s of one FP32 erfc of the library plus one FMA
+                          per pair, operands in registers: the Phi-pair
+                          ceiling of the exact double sum (Thm 1 with the
+                          weights of Eq. G_jk, one erfc per (row, boundary));
+     FSMI_PEAK_MFMA_BF16  FLOP/s of dense BF16 matrix-core products
+                          (16x16x32, FP32 accumulate). */
+enum { FSMI_PEAK_COPY = 0, FSMI_PEAK_FMA = 1, FSMI_PEAK_PAIR = 2, FSMI_PEAK_MFMA_BF16 = 3 };
+fsmi_status fsmi_peak(fsmi_ctx ctx, int32_t kind, double* rate, double* clock_mhz);
+
 #ifdef __cplusplus
 }
 #endif

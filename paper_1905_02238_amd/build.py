@@ -23,6 +23,9 @@ FLAGS = ["-O3", f"--offload-arch={ARCH}", "-std=c++17", "-fPIC",
          # loop heads on 64-byte boundaries: keeps the hot loops' timing
          # independent of unrelated code placed before them
          "-falign-loops=64",
+         # matrix-core results in ordinary VGPRs: without it the compiler
+         # shuffles loop-carried accumulators through AGPR moves every iteration
+         "-mllvm", "-amdgpu-mfma-vgpr-form",
          "-Wno-unused-command-line-argument"]
 
 

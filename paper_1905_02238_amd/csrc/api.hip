@@ -362,6 +362,16 @@ fsmi_status fsmi_probe_erfc(fsmi_ctx ctx, int64_t n, const float* z, float* out)
   return from_hip(ctx, launch_erfc_probe(ctx, n, z, out), "probe_erfc");
 }
 
+fsmi_status fsmi_peak(fsmi_ctx ctx, int32_t kind, double* rate, double* clock_mhz) {
+  if (!ctx) return FSMI_E_INVAL;
+  if (!rate || kind < FSMI_PEAK_COPY || kind > FSMI_PEAK_MFMA_BF16)
+    return fail(ctx, FSMI_E_INVAL, "bad peak kind or NULL rate");
+  (void)hipSetDevice(ctx->device);
+  const hipError_t e = run_peak(ctx, kind, rate, clock_mhz);
+  if (e == hipErrorOutOfMemory) return fail(ctx, FSMI_E_NOMEM, "peak: out of device memory");
+  return from_hip(ctx, e, "peak");
+}
+
 fsmi_status fsmi_probe_f(fsmi_ctx ctx, double delta, int64_t n, const float* o, double* out) {
   if (!ctx) return FSMI_E_INVAL;
   if (!(delta > 0.0) || !(delta < 1e300) || n < 0 || (n > 0 && (!o || !out)))

@@ -95,6 +95,9 @@ hipError_t launch_eval_poses_3d(fsmi_ctx ctx, const EvalConst& ec, const float* 
                                 int64_t n_beams, const double* beam_dir, double sigma, double R,
                                 double w, double* mi_pose, double* mi_beam);
 
+// ---- machine ceilings (k_peak.hip) ----
+hipError_t run_peak(fsmi_ctx ctx, int kind, double* rate, double* clock_mhz);
+
 // ---- diagnostics (k_beam.hip) ----
 hipError_t launch_erfc_probe(fsmi_ctx ctx, int64_t n, const float* z, float* out);
 hipError_t launch_f_probe(fsmi_ctx ctx, double delta, int64_t n, const float* o, double* out);

@@ -25,10 +25,11 @@ FSMI_FP32, FSMI_FP64 = 0, 1
 FSMI_RAY_DDA, FSMI_RAY_VIRTUAL, FSMI_RAY_RLE = 0, 1, 2
 FSMI_PLAN_AUTOTUNE, FSMI_PLAN_GRAPH = 1, 2
 FSMI_F_SKIP_ZERO = 1
+FSMI_PEAK_COPY, FSMI_PEAK_FMA, FSMI_PEAK_PAIR, FSMI_PEAK_MFMA_BF16 = 0, 1, 2, 3
 
 EXPORTS = ("fsmi_create", "fsmi_destroy", "fsmi_set_stream", "fsmi_sync", "fsmi_last_error",
            "fsmi_status_string", "fsmi_default_params", "fsmi_raycast", "fsmi_eval_beams",
-           "fsmi_rle_eval_beams", "fsmi_eval_poses", "fsmi_probe_erfc", "fsmi_probe_f", "fsmi_probe_mfma",
+           "fsmi_rle_eval_beams", "fsmi_eval_poses", "fsmi_probe_erfc", "fsmi_probe_f", "fsmi_probe_mfma", "fsmi_peak",
            "fsmi_sur_num_params", "fsmi_sur_create", "fsmi_sur_destroy",
            "fsmi_sur_fit_label_stats", "fsmi_sur_get_label_stats", "fsmi_sur_forward",
            "fsmi_sur_backward", "fsmi_sur_adam_step", "fsmi_sur_get_params",
@@ -91,6 +92,7 @@ def load(path: str = LIB_PATH):
                                           i64, p, d, d, d, p, p]
             L.fsmi_probe_erfc.argtypes = [p, i64, p, p]
             L.fsmi_probe_f.argtypes = [p, d, i64, p, p]
+            L.fsmi_peak.argtypes = [p, i32, C.POINTER(d), C.POINTER(d)]
             L.fsmi_probe_mfma.argtypes = [p, p, p, p]
             L.fsmi_sur_num_params.argtypes = []
             L.fsmi_sur_num_params.restype = i64
@@ -117,7 +119,7 @@ def load(path: str = LIB_PATH):
             L.fsmi_plan_destroy.restype = None
             for n in ("fsmi_create", "fsmi_set_stream", "fsmi_sync", "fsmi_raycast",
                       "fsmi_eval_beams", "fsmi_rle_eval_beams", "fsmi_eval_poses",
-                      "fsmi_probe_erfc", "fsmi_probe_f", "fsmi_probe_mfma", "fsmi_sur_create",
+                      "fsmi_probe_erfc", "fsmi_probe_f", "fsmi_probe_mfma", "fsmi_peak", "fsmi_sur_create",
                       "fsmi_sur_fit_label_stats", "fsmi_sur_get_label_stats", "fsmi_sur_forward",
                       "fsmi_sur_backward", "fsmi_sur_adam_step", "fsmi_sur_get_params",
                       "fsmi_sur_set_params", "fsmi_sur_get_grads", "fsmi_sur_save",
@@ -278,6 +280,12 @@ class Context:
                                            _ptr(o, torch.float32, "o"),
                                            _ptr(out, torch.float64, "out")))
         return out
+
+    def fsmi_peak(self, kind, with_clock=False):
+        r, mhz = C.c_double(0.0), C.c_double(0.0)
+        self._stream()
+        self._check(self._lib.fsmi_peak(self.handle, int(kind), C.byref(r), C.byref(mhz)))
+        return (r.value, mhz.value) if with_clock else r.value
 
     def fsmi_probe_mfma(self, A, B):
         D = torch.empty((16, 16), dtype=torch.float32, device=A.device)

@@ -82,6 +82,28 @@ def test_f_fp32_mode_error_bound(ctx):
             assert rel.max() < 1e-9, (d, float(rel.max()))
 
 
+def test_machine_ceilings_are_plausible(ctx):
+    """The library's own microbenchmarks return rates between a floor that only
+    a broken kernel would miss and the chip's published peaks (with 5 % slack):
+    HBM 8 TB/s, FP32 78.6 TFLOP/s unpacked, BF16 MFMA 2.5 PFLOP/s dense, and
+    for the erfc + FMA pair the FP32 issue rate over the erfc's ten
+    non-transcendental instructions."""
+    (copy, c0), (fma, c1), (pair, c2), (mfma, c3) = [
+        ctx.fsmi_peak(k, with_clock=True) for k in
+        (F.FSMI_PEAK_COPY, F.FSMI_PEAK_FMA, F.FSMI_PEAK_PAIR, F.FSMI_PEAK_MFMA_BF16)]
+    print(f"[gpu] ceilings: copy {copy / 1e12:.2f} TB/s, fma {fma / 1e12:.1f} TFLOP/s, "
+          f"pair {pair / 1e12:.3f} T pairs/s, mfma {mfma / 1e12:.0f} TFLOP/s; clocks "
+          f"{c0:.0f} {c1:.0f} {c2:.0f} {c3:.0f} MHz", flush=True)
+    for mhz in (c0, c1, c2, c3):         # the counters ran and the ratio is a clock
+        assert 300.0 < mhz < 3000.0
+    assert 1e12 < copy < 8.0e12 * 1.05
+    assert 2e13 < fma < 78.6e12 * 1.05
+    assert 5e11 < pair < 78.6e12 / 2 / 10 * 1.05
+    assert 2e14 < mfma < 2.5e15 * 1.05
+    with pytest.raises(F.FsmiError):
+        ctx.fsmi_peak(7)
+
+
 # ---------------------------------------------------------------------------
 def _rays_2d(seed, X, Y, n, R_lo=1, R_hi=80):
     rng = np.random.default_rng(seed)
