@@ -29,6 +29,7 @@ def lib():
             "ora_info_gain": (None, [i, p, d, p]),
             "ora_G": (d, [d, d, d, d]),
             "ora_fsmi_exact": (d, [i, p, p, d, d]),
+            "ora_fsmi_exact_ext": (d, [i, p, p, d, d, i, d]),
             "ora_fsmi_approx": (d, [i, p, p, d, d, i]),
             "ora_fsmi_uniform": (d, [i, p, d, i]),
             "ora_kernel_weight": (d, [i, d, i, i]),
@@ -42,9 +43,10 @@ def lib():
             "ora_raycast2d": (i, [p, i64, i64, d, d, d, d, d, i, p, p, p]),
             "ora_virtual3d": (i, [p, i64, i64, i64, p, p, d, d, i, p, p]),
             "ora_rle_runs": (i, [i, p, p, p]),
-            "ora_eval_beams": (i, [i, i, i, d, i64, p, p, p, p, p, i]),
+            "ora_eval_beams": (i, [i, i, i, d, d, i, i64, p, p, p, p, p, i]),
             "ora_rle_eval_beams": (i, [i, i, i, i, d, i64, p, p, p, p, p, i]),
-            "ora_eval_poses_2d": (i, [i, i, i, d, p, i64, i64, i64, p, i64, p, d, d, p, p, i]),
+            "ora_eval_poses_2d": (i, [i, i, i, d, d, i, p, i64, i64, i64, p, i64, p, d, d, p, p,
+                                      i]),
             "ora_eval_poses_3d": (i, [i, i, i, i, d, p, i64, i64, i64, i64, p, i64, p, d, d, d,
                                       p, p, i]),
             "ora_max_threads": (i, []),
@@ -99,6 +101,15 @@ def fsmi_exact(o, l, sigma, delta_occ=1.5):
     o, l = _f64(o), _f64(l)
     assert len(l) == len(o) + 1
     return lib().ora_fsmi_exact(len(o), _pd(o), _pd(l), float(sigma), float(delta_occ))
+
+
+def fsmi_exact_ext(o, l, sigma, slope=0.0, tail=False, delta_occ=1.5):
+    """Thm 1 with range-dependent noise sigma_j = sigma + slope mu_j and, with
+    tail, the max-range return term (ora_fsmi_exact_ext)."""
+    o, l = _f64(o), _f64(l)
+    assert len(l) == len(o) + 1
+    return lib().ora_fsmi_exact_ext(len(o), _pd(o), _pd(l), float(sigma), float(slope),
+                                    int(bool(tail)), float(delta_occ))
 
 
 def fsmi_approx(o, l, sigma, Delta, delta_occ=1.5):
@@ -204,7 +215,8 @@ def rle_runs(occ):
     return ro[:nr].copy(), rl[:nr].copy()
 
 
-def eval_beams(variant, off, occ, sigma, bound=None, Delta=0, H=0, delta_occ=1.5, threads=0):
+def eval_beams(variant, off, occ, sigma, bound=None, Delta=0, H=0, delta_occ=1.5, threads=0,
+               slope=0.0, tail=False):
     off = np.ascontiguousarray(off, dtype=np.int64)
     occ = np.ascontiguousarray(occ, dtype=np.float32)
     sigma = np.ascontiguousarray(sigma, dtype=np.float32)
@@ -212,8 +224,9 @@ def eval_beams(variant, off, occ, sigma, bound=None, Delta=0, H=0, delta_occ=1.5
     mi = np.zeros(nb)
     bnd = None if bound is None else _f64(bound)
     bp = None if bnd is None else _pd(bnd)
-    lib().ora_eval_beams(int(variant), int(Delta), int(H), float(delta_occ), nb, _pd(off),
-                         _pd(occ), bp, _pd(sigma), _pd(mi), int(threads))
+    lib().ora_eval_beams(int(variant), int(Delta), int(H), float(delta_occ), float(slope),
+                         int(bool(tail)), nb, _pd(off), _pd(occ), bp, _pd(sigma), _pd(mi),
+                         int(threads))
     return mi
 
 
@@ -232,7 +245,7 @@ def rle_eval_beams(exact, run_off, run_occ, run_len, sigma_p, kind=K_ERF, Delta=
 
 
 def eval_poses_2d(variant, grid, poses, beam_dir, sigma, R, Delta=0, H=0, delta_occ=1.5,
-                  threads=0, want_beams=True):
+                  threads=0, want_beams=True, slope=0.0, tail=False):
     grid = np.ascontiguousarray(grid, dtype=np.float32)
     Y, X = grid.shape
     poses = _f64(poses).reshape(-1, 4)
@@ -240,9 +253,10 @@ def eval_poses_2d(variant, grid, poses, beam_dir, sigma, R, Delta=0, H=0, delta_
     npo, nb = poses.shape[0], beam_dir.shape[0]
     mp = np.zeros(npo)
     mb = np.zeros((npo, nb)) if want_beams else None
-    rc = lib().ora_eval_poses_2d(int(variant), int(Delta), int(H), float(delta_occ), _pd(grid), X,
-                                 Y, npo, _pd(poses), nb, _pd(beam_dir), float(sigma), float(R),
-                                 _pd(mp), None if mb is None else _pd(mb), int(threads))
+    rc = lib().ora_eval_poses_2d(int(variant), int(Delta), int(H), float(delta_occ), float(slope),
+                                 int(bool(tail)), _pd(grid), X, Y, npo, _pd(poses), nb,
+                                 _pd(beam_dir), float(sigma), float(R), _pd(mp),
+                                 None if mb is None else _pd(mb), int(threads))
     if rc != 0:
         raise ValueError("eval_poses_2d: a pose lies outside the map")
     return mp, mb

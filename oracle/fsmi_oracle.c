@@ -101,6 +101,51 @@ double ora_fsmi_exact(int n, const double* o, const double* l, double sigma, dou
   return nval(&I);
 }
 
+/* Two extensions of Thm 1 (readings the paper leaves open):
+   - range-dependent noise: the reading of event e_j is N(mu_j, sigma_j^2) with
+     sigma_j = sigma + slope * mu_j (the per-event sigma_j of Alg 1), so
+     G_{k,j} uses sigma_j;
+   - max-range returns (tail = 1): a reading at or beyond l_{n+1} is reported
+     as "max range" and updates every cell of the beam as empty, an information
+     gain of q_n = sum_{i=1}^{n} f(delta_emp, r_i).  Its probability is
+     sum_j P(e_j) (1 - Phi((l_{n+1} - mu_j)/sigma_j)) + P(e_0) (e_0 reads max
+     range with certainty), so the term added to Thm 1 is
+     q_n [sum_j P(e_j) (1 - Phi((l_{n+1} - mu_j)/sigma_j)) + P(e_0)].
+   With slope = 0 and tail = 0 this is ora_fsmi_exact. */
+double ora_fsmi_exact_ext(int n, const double* o, const double* l, double sigma, double slope,
+                          int tail, double delta_occ) {
+  if (n <= 0) return 0.0;
+  double* P = (double*)malloc(sizeof(double) * (n + 1));
+  double* C = (double*)malloc(sizeof(double) * n);
+  ora_first_hit(n, o, P);
+  ora_info_gain(n, o, delta_occ, C);
+  nsum I = {0.0, 0.0};
+  for (int j = 1; j <= n; ++j) {
+    double mu = 0.5 * (l[j - 1] + l[j]);
+    double sj = sigma + slope * mu;
+    for (int k = 1; k <= n; ++k) {
+      double G = ora_G(l[k - 1], l[k], mu, sj);
+      nadd(&I, P[j] * C[k - 1] * G);
+    }
+  }
+  if (tail) {
+    const double r2 = 0.70710678118654752440; /* 1/sqrt(2) */
+    double delta_emp = 1.0 / delta_occ;
+    nsum q = {0.0, 0.0}, pmax = {0.0, 0.0};
+    for (int i = 0; i < n; ++i) nadd(&q, ora_f(delta_emp, o[i]));
+    for (int j = 1; j <= n; ++j) {
+      double mu = 0.5 * (l[j - 1] + l[j]);
+      double sj = sigma + slope * mu;
+      nadd(&pmax, P[j] * 0.5 * erfc((l[n] - mu) / sj * r2));
+    }
+    nadd(&pmax, P[0]);
+    nadd(&I, nval(&q) * nval(&pmax));
+  }
+  free(P);
+  free(C);
+  return nval(&I);
+}
+
 /* Eq. fsmi_approx: the k range is cut to [j-Delta, j+Delta] (clipped to 1..n),
    with no renormalisation of the remaining weights. */
 double ora_fsmi_approx(int n, const double* o, const double* l, double sigma, double delta_occ,
@@ -535,16 +580,18 @@ int ora_max_threads(void) {
 #endif
 }
 
-static double eval_one(int variant, int Delta, int H, double delta_occ, int n, const double* o,
-                       const double* l, double sigma) {
+static double eval_one(int variant, int Delta, int H, double delta_occ, double slope, int tail,
+                       int n, const double* o, const double* l, double sigma) {
+  if (variant == ORA_EXACT && (slope != 0.0 || tail))
+    return ora_fsmi_exact_ext(n, o, l, sigma, slope, tail, delta_occ);
   if (variant == ORA_EXACT) return ora_fsmi_exact(n, o, l, sigma, delta_occ);
   if (variant == ORA_APPROX) return ora_fsmi_approx(n, o, l, sigma, delta_occ, Delta);
   return ora_fsmi_uniform(n, o, delta_occ, H);
 }
 
-int ora_eval_beams(int variant, int Delta, int H, double delta_occ, int64_t n_beams,
-                   const int64_t* off, const float* occ, const double* bound, const float* sigma,
-                   double* mi, int threads) {
+int ora_eval_beams(int variant, int Delta, int H, double delta_occ, double slope, int tail,
+                   int64_t n_beams, const int64_t* off, const float* occ, const double* bound,
+                   const float* sigma, double* mi, int threads) {
   if (threads <= 0) threads = ora_max_threads();
 #pragma omp parallel for schedule(dynamic, 4) num_threads(threads)
   for (int64_t b = 0; b < n_beams; ++b) {
@@ -553,7 +600,7 @@ int ora_eval_beams(int variant, int Delta, int H, double delta_occ, int64_t n_be
     double* l = (double*)malloc(sizeof(double) * (n + 1));
     for (int i = 0; i < n; ++i) o[i] = (double)occ[off[b] + i];
     for (int i = 0; i <= n; ++i) l[i] = bound ? bound[off[b] + b + i] : (double)i;
-    mi[b] = eval_one(variant, Delta, H, delta_occ, n, o, l, (double)sigma[b]);
+    mi[b] = eval_one(variant, Delta, H, delta_occ, slope, tail, n, o, l, (double)sigma[b]);
     free(o);
     free(l);
   }
@@ -582,10 +629,10 @@ int ora_rle_eval_beams(int exact, int kind, int Delta, int H, double delta_occ, 
 
 /* Per pose (Sec. 2.4: the scan's MI is the sum over its beams):
    world direction = R(yaw) * sensor direction, each product rounded on its own. */
-int ora_eval_poses_2d(int variant, int Delta, int H, double delta_occ, const float* map,
-                      int64_t X, int64_t Y, int64_t n_poses, const double* poses, int64_t n_beams,
-                      const double* beam_dir, double sigma, double R, double* mi_pose,
-                      double* mi_beam, int threads) {
+int ora_eval_poses_2d(int variant, int Delta, int H, double delta_occ, double slope, int tail,
+                      const float* map, int64_t X, int64_t Y, int64_t n_poses,
+                      const double* poses, int64_t n_beams, const double* beam_dir, double sigma,
+                      double R, double* mi_pose, double* mi_beam, int threads) {
   if (threads <= 0) threads = ora_max_threads();
   int max_cells = (int)floor(1.4142135623730951 * R) + 3;
   int bad = 0;
@@ -608,7 +655,7 @@ int ora_eval_poses_2d(int variant, int Delta, int H, double delta_occ, const flo
         bad = 1;
       } else {
         for (int i = 0; i < n; ++i) o[i] = (double)of[i];
-        v = eval_one(variant, Delta, H, delta_occ, n, o, entry, sigma);
+        v = eval_one(variant, Delta, H, delta_occ, slope, tail, n, o, entry, sigma);
       }
       if (mi_beam) mi_beam[p * n_beams + b] = v;
       nadd(&tot, v);

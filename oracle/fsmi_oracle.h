@@ -35,6 +35,9 @@ double ora_G(double lk, double lk1, double mu, double sigma);
 
 /* ---- single beam, boundaries l[0..n] (l[0] = l_1 = 0) ---- */
 double ora_fsmi_exact(int n, const double* o, const double* l, double sigma, double delta_occ);
+/* Thm 1 with sigma_j = sigma + slope mu_j and, if tail, the max-range term */
+double ora_fsmi_exact_ext(int n, const double* o, const double* l, double sigma, double slope,
+                          int tail, double delta_occ);
 double ora_fsmi_approx(int n, const double* o, const double* l, double sigma, double delta_occ, int Delta);
 double ora_fsmi_uniform(int n, const double* o, double delta_occ, int H);
 
@@ -72,13 +75,14 @@ int ora_rle_runs(int n, const float* occ, float* run_o, int32_t* run_len);
 
 /* ---- batches (OpenMP over beams; threads <= 0 means the OpenMP default) ---- */
 enum { ORA_EXACT = 0, ORA_APPROX = 1, ORA_UNIFORM = 2 };
-int ora_eval_beams(int variant, int Delta, int H, double delta_occ, int64_t n_beams,
-                   const int64_t* off, const float* occ, const double* bound /* or NULL */,
-                   const float* sigma, double* mi, int threads);
+/* slope, tail: the extensions of ora_fsmi_exact_ext (EXACT only; 0, 0 = Thm 1) */
+int ora_eval_beams(int variant, int Delta, int H, double delta_occ, double slope, int tail,
+                   int64_t n_beams, const int64_t* off, const float* occ,
+                   const double* bound /* or NULL */, const float* sigma, double* mi, int threads);
 int ora_rle_eval_beams(int exact, int kind, int Delta, int H, double delta_occ, int64_t n_beams,
                        const int64_t* run_off, const float* run_occ, const int32_t* run_len,
                        const float* sigma_p, double* mi, int threads);
-int ora_eval_poses_2d(int variant, int Delta, int H, double delta_occ,
+int ora_eval_poses_2d(int variant, int Delta, int H, double delta_occ, double slope, int tail,
                       const float* map, int64_t X, int64_t Y,
                       int64_t n_poses, const double* poses /* [n][4] x,y,cos,sin */,
                       int64_t n_beams, const double* beam_dir /* [n][2] */,

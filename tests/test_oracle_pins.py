@@ -166,6 +166,60 @@ def test_exact_equals_bruteforce_quadrature(seed):
     assert abs(got - ref) <= 1e-10 * abs(ref)
 
 
+def brute_force_mi_ext(o, l, sigma, slope=0.0, tail=False, delta=D_OCC):
+    """Eq. mi_sum with per-event noise sigma_j = sigma + slope mu_j.  With tail,
+    a reading at or past l_{n+1} is a max-range return: the quadrature goes on
+    past l_{n+1}, where F(z) counts every cell as passed, and the no-hit event
+    e_0 reads max range with certainty, adding P(e_0) F(max range)."""
+    P = p_first_hit(o)
+    mu = 0.5 * (l[:-1] + l[1:])
+    sj = sigma + slope * mu
+    tot = 0.0
+    for k in range(len(o)):
+        v, _ = integrate.quad(lambda z: np.sum(P * norm.pdf(z, mu, sj)) * f_of_z(z, o, l, delta),
+                              l[k], l[k + 1], epsabs=1e-16, epsrel=1e-13, limit=200)
+        tot += v
+    if tail:
+        fmax = f_of_z(l[-1], o, l, delta)
+        past, _ = integrate.quad(lambda z: np.sum(P * norm.pdf(z, mu, sj)), l[-1], np.inf,
+                                 epsabs=1e-16, epsrel=1e-13, limit=200)
+        tot += (past + np.prod(1.0 - o)) * fmax
+    return tot
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_range_noise_and_max_range_equal_bruteforce(seed):
+    """The two extensions of Thm 1 (range-dependent sigma_j, max-range returns)
+    against quadrature of the definition with the same sensor model."""
+    rng = np.random.default_rng(300 + seed)
+    n = int(rng.integers(1, 9))
+    o = rng.uniform(0.02, 0.98, n)
+    l = np.concatenate([[0.0], np.cumsum(rng.uniform(0.1, 1.5, n))])
+    sigma = float(rng.uniform(0.2, 1.5))
+    slope = float(rng.uniform(0.0, 0.3))
+    for sl, tail in ((slope, False), (0.0, True), (slope, True)):
+        ref = brute_force_mi_ext(o, l, sigma, sl, tail)
+        got = O.fsmi_exact_ext(o, l, sigma, sl, tail, D_OCC)
+        assert abs(got - ref) <= 1e-10 * abs(ref), (sl, tail, got, ref)
+
+
+def test_extensions_reduce_to_thm1_and_vanish_on_known_cells():
+    rng = np.random.default_rng(11)
+    o = rng.uniform(0.05, 0.95, 12)
+    l = np.concatenate([[0.0], np.cumsum(rng.uniform(0.3, 1.2, 12))])
+    assert O.fsmi_exact_ext(o, l, 0.8) == O.fsmi_exact(o, l, 0.8)
+    # the max-range term is q_n times the probability of a max-range reading
+    P = p_first_hit(o)
+    mu = 0.5 * (l[:-1] + l[1:])
+    pmax = float(np.sum(P * norm.sf(l[-1], mu, 0.8))) + float(np.prod(1.0 - o))
+    qn = sum(f_paper(1.0 / D_OCC, v) for v in o)
+    diff = O.fsmi_exact_ext(o, l, 0.8, 0.0, True) - O.fsmi_exact(o, l, 0.8)
+    assert abs(diff - qn * pmax) <= 1e-12 * qn * pmax
+    # known cells carry no information, also as max-range returns
+    k = rng.integers(0, 2, 12).astype(np.float64)
+    assert O.fsmi_exact_ext(k, l, 0.8, 0.2, True) == 0.0
+
+
 def test_exact_equals_smi_riemann_limit():
     rng = np.random.default_rng(7)
     o = rng.uniform(0.05, 0.95, 5)
