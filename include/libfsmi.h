@@ -75,7 +75,15 @@ enum {
      below the smallest normal float, so the result is the dense sum up to
      rounding order.  A separate mode with its own work count; any other
      combination gives FSMI_E_INVAL. */
-  FSMI_F_SKIP_ZERO = 1u
+  FSMI_F_SKIP_ZERO = 1u,
+  /* Max-range returns (EXACT, explicit boundaries, FP32 or FP64): a reading at
+     or past l_{n+1} is reported as max range and updates every cell of the
+     beam as empty, so the term
+       q_n [sum_j P(e_j) (1 - Phi((l_{n+1} - mu_j)/sigma_j)) + P(e_0)],
+     q_n = sum_{i=1}^{n} f(delta_emp, r_i), is added to Thm 1 (the paper's
+     Thm 1 integrates the reading over [0, l_{n+1}) only, Sec. 3.1).  Not with
+     FSMI_F_SKIP_ZERO. */
+  FSMI_F_MAX_RANGE = 2u
 };
 
 typedef struct {
@@ -85,7 +93,14 @@ typedef struct {
   int32_t uniform_h;  /* H >= 0, cells (UNIFORM) */
   int32_t kernel;     /* FSMI_KERNEL_* (equal-width cells and RLE only) */
   int32_t precision;  /* FSMI_FP32 (default) | FSMI_FP64 */
-  uint32_t flags;     /* 0 or FSMI_F_SKIP_ZERO */
+  uint32_t flags;     /* 0, FSMI_F_SKIP_ZERO or FSMI_F_MAX_RANGE */
+  /* Range-dependent noise: the reading of event e_j is N(mu_j, sigma_j^2) with
+     sigma_j = sigma + sigma_slope * mu_j (Alg 1 writes sigma per event; the
+     paper's experiments use one sigma).  >= 0; 0 (default) is one sigma per
+     beam.  Any other value needs EXACT on explicit boundaries (fsmi_eval_beams
+     and fsmi_plan_eval_beams with bound, 2D fsmi_eval_poses), not
+     FSMI_F_SKIP_ZERO. */
+  double sigma_slope;
 } fsmi_params;
 
 typedef struct {

@@ -56,8 +56,17 @@ bool check_params(fsmi_ctx ctx, const fsmi_params* p, fsmi_status* st) {
     *st = fail(ctx, FSMI_E_INVAL, "unknown precision");
     return false;
   }
-  if (p->flags & ~(uint32_t)FSMI_F_SKIP_ZERO) {
+  if (p->flags & ~(uint32_t)(FSMI_F_SKIP_ZERO | FSMI_F_MAX_RANGE)) {
     *st = fail(ctx, FSMI_E_INVAL, "unknown flags");
+    return false;
+  }
+  if (!(p->sigma_slope >= 0.0) || !std::isfinite(p->sigma_slope)) {
+    *st = fail(ctx, FSMI_E_INVAL, "sigma_slope must be finite and >= 0");
+    return false;
+  }
+  if ((p->sigma_slope != 0.0 || (p->flags & FSMI_F_MAX_RANGE)) &&
+      (p->variant != FSMI_EXACT || (p->flags & FSMI_F_SKIP_ZERO))) {
+    *st = fail(ctx, FSMI_E_INVAL, "sigma_slope and FSMI_F_MAX_RANGE are EXACT (not skip-zero) modes");
     return false;
   }
   if ((p->flags & FSMI_F_SKIP_ZERO) && (p->variant != FSMI_EXACT || p->precision != FSMI_FP32)) {
@@ -65,6 +74,10 @@ bool check_params(fsmi_ctx ctx, const fsmi_params* p, fsmi_status* st) {
     return false;
   }
   return true;
+}
+
+bool ext_mode(const fsmi_params* p) {
+  return p->sigma_slope != 0.0 || (p->flags & FSMI_F_MAX_RANGE);
 }
 
 EvalConst to_const(const fsmi_params* p) {
@@ -76,6 +89,7 @@ EvalConst to_const(const fsmi_params* p) {
   ec.precision = p->precision;
   ec.flags = p->flags;
   ec.delta_occ = p->delta_occ;
+  ec.slope = p->sigma_slope;
   return ec;
 }
 
@@ -150,6 +164,7 @@ void fsmi_default_params(fsmi_params* p) {
   p->kernel = FSMI_KERNEL_ERF;
   p->precision = FSMI_FP32;
   p->flags = 0;
+  p->sigma_slope = 0.0;
 }
 
 fsmi_status fsmi_create(fsmi_ctx* out, int device, void* hip_stream) {
@@ -278,6 +293,8 @@ fsmi_status fsmi_eval_beams(fsmi_ctx ctx, const fsmi_params* params, int64_t n_b
   if (!off || !occ || !sigma || !mi) return fail(ctx, FSMI_E_INVAL, "off, occ, sigma, mi are required");
   if ((params->flags & FSMI_F_SKIP_ZERO) && !bound)
     return fail(ctx, FSMI_E_INVAL, "FSMI_F_SKIP_ZERO needs explicit boundaries");
+  if (ext_mode(params) && !bound)
+    return fail(ctx, FSMI_E_INVAL, "sigma_slope and FSMI_F_MAX_RANGE need explicit boundaries");
   (void)hipSetDevice(ctx->device);
   int max_len = 0;
   hipError_t e = launch_max_len(ctx, off, n_beams, &max_len);
@@ -303,6 +320,8 @@ fsmi_status fsmi_rle_eval_beams(fsmi_ctx ctx, const fsmi_params* params, int64_t
     return fail(ctx, FSMI_E_INVAL, "run_off, run_occ, run_len, sigma_prime, mi are required");
   if (params->flags & FSMI_F_SKIP_ZERO)
     return fail(ctx, FSMI_E_INVAL, "FSMI_F_SKIP_ZERO needs explicit boundaries");
+  if (ext_mode(params))
+    return fail(ctx, FSMI_E_INVAL, "sigma_slope and FSMI_F_MAX_RANGE need explicit boundaries");
   (void)hipSetDevice(ctx->device);
   return from_hip(ctx,
                   launch_rle_eval_beams(ctx, to_const(params), n_beams, run_off, run_occ, run_len,
@@ -346,6 +365,8 @@ fsmi_status fsmi_eval_poses(fsmi_ctx ctx, const fsmi_params* params, const fsmi_
   }
   if (params->flags & FSMI_F_SKIP_ZERO)
     return fail(ctx, FSMI_E_INVAL, "FSMI_F_SKIP_ZERO needs explicit boundaries (2D maps)");
+  if (ext_mode(params))
+    return fail(ctx, FSMI_E_INVAL, "sigma_slope and FSMI_F_MAX_RANGE need explicit boundaries (2D maps)");
   if (!(w > 0.0) || !std::isfinite(w)) return fail(ctx, FSMI_E_INVAL, "w must be finite and > 0");
   if (floor(max_range / w) > 4000.0) return fail(ctx, FSMI_E_CAPACITY, "more than 4000 virtual cells per beam");
   return from_hip(ctx,

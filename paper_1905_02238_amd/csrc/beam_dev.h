@@ -129,6 +129,42 @@ FSMI_DEV T tail_E(double L, double M) {
 }
 template <typename T> constexpr double unscale() { return sizeof(T) == 8 ? 1.0 : (double)kInvSqrtL2E; }
 
+// The erfc of a signed scaled distance d, on the tail side.
+template <typename T>
+FSMI_DEV T tail_Ed(double d) {
+  if constexpr (sizeof(T) == 8) {
+    return erfc_pos(tabs(d));
+  } else {
+    return erfc_pos_l2((float)tabs(d));
+  }
+}
+
+// Row j's frame: the scaled distance of a boundary from mu_j.  With one sigma
+// per beam the boundaries are pre-scaled and d(l) = l - M.  With
+// range-dependent noise (sigma_j = sigma + slope mu_j, the per-event sigma_j
+// of Alg 1) the boundaries stay in their own units and d(l) = l a_j + b_j,
+// a_j = 1 / (sigma_j sqrt 2) (times sqrt(log2 e) in FP32), b_j = -mu_j a_j:
+// one FMA in place of the subtraction.
+template <typename T, bool RD>
+struct RowFrame {
+  double M = 0.0, a = 0.0, b = 0.0;
+  FSMI_DEV double d(double l) const {
+    if constexpr (RD) return fma(l, a, b);
+    else return l - M;
+  }
+};
+template <typename T, bool RD>
+FSMI_DEV RowFrame<T, RD> row_frame(const double* sL, int j, double sigma, double slope) {
+  RowFrame<T, RD> f;
+  f.M = 0.5 * (sL[j - 1] + sL[j]);
+  if constexpr (RD) {
+    const double sj = sigma + slope * f.M;
+    f.a = (sizeof(T) == 8 ? 1.0 : (double)kSqrtL2E) / (sj * 1.4142135623730951);
+    f.b = -f.M * f.a;
+  }
+  return f;
+}
+
 // ---------------------------------------------------------------------------
 // Row sums S_j = sum_k C_k G_{k,j} on scaled boundaries sL[0..n].
 // G_{k,j} = (1/2)|E(l_{k+1}) - E(l_k)| for k != j (both boundaries on one side
@@ -193,6 +229,87 @@ FSMI_DEV double exact_rows(const double* sL, const T* sC, const T* sP, int n, in
     if (s < S && b0 <= b1) {
       const int j = full + 1 + r;
       tot += (double)sP[j - 1] * row_exact_seg<T>(sL, sC, j, b0, b1);
+    }
+  }
+  return tot;
+}
+
+// ---------------------------------------------------------------------------
+// The same rows in a row frame (range-dependent noise) and with the
+// max-range return term; kept apart so the one-sigma loop above is unchanged.
+// ---------------------------------------------------------------------------
+template <typename T, bool RD>
+FSMI_DEV double diag_fix_f(Acc<T>& acc, const double* sL, const T* sC, int j,
+                           const RowFrame<T, RD>& f) {
+  // replace the k = j term the loop took by the exact diagonal weight
+  const double dl = f.d(sL[j - 1]), dr = f.d(sL[j]);
+  T Ej = tail_Ed<T>(dl);
+  T Ej1 = tail_Ed<T>(dr);
+  T Cj = sC[j - 1];
+  acc.add(-(Cj * tabs(Ej1 - Ej)));
+  constexpr double u = unscale<T>();
+  T g2 = erf_t<T>((T)(dr * u)) + erf_t<T>((T)(-dl * u));
+  acc.add(Cj * g2);
+  return 0.5 * acc.value();
+}
+
+// Terms b0..b1 (1 <= b0 <= b1 <= n) of row j, halved, with the exact diagonal
+// weight if the segment holds b = j.  Eight pairs per compensated add: the
+// block of eight is an FP32 (or FP64) FMA chain, the blocks are Kahan-summed.
+template <typename T, bool RD>
+FSMI_DEV double row_exact_seg_f(const double* sL, const T* sC, int j, int b0, int b1,
+                                const RowFrame<T, RD>& f) {
+  Acc<T> acc;
+  T Eprev = tail_Ed<T>(f.d(sL[b0 - 1]));
+  int b = b0;
+  for (; b + 7 <= b1; b += 8) {
+    T E[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) E[q] = tail_Ed<T>(f.d(sL[b + q]));
+    T p = sC[b - 1] * tabs(E[0] - Eprev);
+#pragma unroll
+    for (int q = 1; q < 8; ++q) p = fma(sC[b - 1 + q], tabs(E[q] - E[q - 1]), p);
+    acc.add(p);
+    Eprev = E[7];
+  }
+  for (; b <= b1; ++b) {
+    T E = tail_Ed<T>(f.d(sL[b]));
+    acc.add(sC[b - 1] * tabs(E - Eprev));
+    Eprev = E;
+  }
+  if (j >= b0 && j <= b1) return diag_fix_f<T, RD>(acc, sL, sC, j, f);
+  return 0.5 * acc.value();
+}
+
+// sum_j P_j S_j over the n rows of an n x n pair grid, on the G lanes of a
+// group: whole sweeps of G rows (one row per lane), then the last R = n mod G
+// rows, each cut into S = floor(G / R) equal runs of terms, lane l taking row
+// (l mod R), run (l div R), so a partly filled sweep does not leave lanes idle.
+// With tq != 0 each row also adds P_j tq erfc(d(l_{n+1})): the max-range
+// reading's probability under e_j (times 2) weighted by tq = q_n / 2.
+template <int G, typename T, bool RD>
+FSMI_DEV double exact_rows_ext(const double* sL, const T* sC, const T* sP, int n, int tid,
+                               double sigma, double slope, double tq) {
+  double tot = 0.0;
+  const int full = (n / G) * G;
+  for (int j = tid + 1; j <= full; j += G) {
+    const RowFrame<T, RD> f = row_frame<T, RD>(sL, j, sigma, slope);
+    double v = row_exact_seg_f<T, RD>(sL, sC, j, 1, n, f);
+    if (tq != 0.0) v += tq * (double)tail_Ed<T>(f.d(sL[n]));
+    tot += (double)sP[j - 1] * v;
+  }
+  const int R = n - full;
+  if (R > 0) {
+    const int S = G / R;
+    const int r = tid % R, s = tid / R;
+    const int len = (n + S - 1) / S;
+    const int b0 = s * len + 1, b1 = min(n, (s + 1) * len);
+    if (s < S && b0 <= b1) {
+      const int j = full + 1 + r;
+      const RowFrame<T, RD> f = row_frame<T, RD>(sL, j, sigma, slope);
+      double v = row_exact_seg_f<T, RD>(sL, sC, j, b0, b1, f);
+      if (tq != 0.0 && s == 0) v += tq * (double)tail_Ed<T>(f.d(sL[n]));
+      tot += (double)sP[j - 1] * v;
     }
   }
   return tot;
@@ -441,7 +558,9 @@ FSMI_DEV double beam_core(const EvalConst& ec, int n, const float* so, bool has_
   const bool any_bad = group_any<NW, BLOCK>(bad, flag, tid);
   *bad_out = any_bad;
   Grp<NW, BLOCK>::sync();
-  if (has_bound && !uni && !any_bad) {
+  // range-dependent noise keeps the boundaries in their own units (RowFrame)
+  const bool rd = ec.slope != 0.0;
+  if (has_bound && !uni && !any_bad && !rd) {
     // scale the boundaries once: the weight argument becomes |L_b - M_j|
     const double s = sizeof(T) == 8 ? c : c * (double)kSqrtL2E;
     for (int i = tid; i <= n; i += G) sA[i] *= s;
@@ -460,6 +579,12 @@ FSMI_DEV double beam_core(const EvalConst& ec, int n, const float* so, bool has_
     } else if (has_bound) {
       if (ec.variant == FSMI_EXACT && (ec.flags & FSMI_F_SKIP_ZERO)) {
         for (int j = tid + 1; j <= n; j += G) tot += (double)sP[j - 1] * row_exact_band<T>(sA, sC, n, j);
+      } else if (ec.variant == FSMI_EXACT && (rd || (ec.flags & FSMI_F_MAX_RANGE))) {
+        // q_n = carryC (the sum of f_emp over the beam), P(e_0) = carryE
+        const double tq = (ec.flags & FSMI_F_MAX_RANGE) ? 0.5 * carryC : 0.0;
+        if (rd) tot = exact_rows_ext<G, T, true>(sA, sC, sP, n, tid, sigma, ec.slope, tq);
+        else tot = exact_rows_ext<G, T, false>(sA, sC, sP, n, tid, sigma, 0.0, tq);
+        if (tid == 0 && (ec.flags & FSMI_F_MAX_RANGE)) tot += carryC * carryE;
       } else if (ec.variant == FSMI_EXACT) {
         tot = exact_rows<G, T>(sA, sC, sP, n, tid);
       } else {

@@ -33,6 +33,7 @@ struct EvalConst {
   int precision;     // FSMI_FP32 / FSMI_FP64
   uint32_t flags;
   double delta_occ;  // > 1
+  double slope;      // sigma_j = sigma + slope mu_j (EXACT on explicit boundaries); 0 = one sigma
 };
 
 // Grow-only device scratch owned by the context.
@@ -44,6 +45,8 @@ fsmi_status from_hip(fsmi_ctx ctx, hipError_t e, const char* where);
 bool check_params(fsmi_ctx ctx, const fsmi_params* p, fsmi_status* st);
 bool check_map(fsmi_ctx ctx, const fsmi_map* m, fsmi_status* st);
 EvalConst to_const(const fsmi_params* p);
+// sigma_slope != 0 or FSMI_F_MAX_RANGE: the extensions that need explicit boundaries
+bool ext_mode(const fsmi_params* p);
 // The wave/tile threshold for a beam batch: the autotuned one if any, else the default.
 int ctx_wave_max(fsmi_ctx ctx, const fsmi_params* p, bool has_bound);
 

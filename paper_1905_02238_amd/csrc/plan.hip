@@ -152,6 +152,8 @@ fsmi_status fsmi_plan_eval_beams(fsmi_ctx ctx, const fsmi_params* params, int64_
   if (wave_max < 0) return fail(ctx, FSMI_E_INVAL, "wave_max < 0");
   if ((params->flags & FSMI_F_SKIP_ZERO) && !bound)
     return fail(ctx, FSMI_E_INVAL, "FSMI_F_SKIP_ZERO needs explicit boundaries");
+  if (ext_mode(params) && !bound)
+    return fail(ctx, FSMI_E_INVAL, "sigma_slope and FSMI_F_MAX_RANGE need explicit boundaries");
   if (plan_flags & ~(uint32_t)(FSMI_PLAN_AUTOTUNE | FSMI_PLAN_GRAPH))
     return fail(ctx, FSMI_E_INVAL, "unknown plan flags");
   (void)hipSetDevice(ctx->device);

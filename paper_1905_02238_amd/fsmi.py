@@ -25,6 +25,7 @@ FSMI_FP32, FSMI_FP64 = 0, 1
 FSMI_RAY_DDA, FSMI_RAY_VIRTUAL, FSMI_RAY_RLE = 0, 1, 2
 FSMI_PLAN_AUTOTUNE, FSMI_PLAN_GRAPH = 1, 2
 FSMI_F_SKIP_ZERO = 1
+FSMI_F_MAX_RANGE = 2
 FSMI_PEAK_COPY, FSMI_PEAK_FMA, FSMI_PEAK_PAIR, FSMI_PEAK_MFMA_BF16 = 0, 1, 2, 3
 
 EXPORTS = ("fsmi_create", "fsmi_destroy", "fsmi_set_stream", "fsmi_sync", "fsmi_last_error",
@@ -47,7 +48,7 @@ class FsmiError(RuntimeError):
 class fsmi_params(C.Structure):
     _fields_ = [("delta_occ", C.c_double), ("variant", C.c_int32), ("trunc_delta", C.c_int32),
                 ("uniform_h", C.c_int32), ("kernel", C.c_int32), ("precision", C.c_int32),
-                ("flags", C.c_uint32)]
+                ("flags", C.c_uint32), ("sigma_slope", C.c_double)]
 
 
 class fsmi_map(C.Structure):
@@ -131,11 +132,12 @@ def load(path: str = LIB_PATH):
 
 
 def params(variant=FSMI_EXACT, delta_occ=1.5, trunc_delta=3, uniform_h=0, kernel=FSMI_KERNEL_ERF,
-           precision=FSMI_FP32, flags=0) -> fsmi_params:
+           precision=FSMI_FP32, flags=0, sigma_slope=0.0) -> fsmi_params:
     p = fsmi_params()
     load().fsmi_default_params(C.byref(p))
     p.delta_occ, p.variant, p.trunc_delta, p.uniform_h = delta_occ, variant, trunc_delta, uniform_h
     p.kernel, p.precision, p.flags = kernel, precision, flags
+    p.sigma_slope = sigma_slope
     return p
 
 

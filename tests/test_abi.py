@@ -39,7 +39,9 @@ def test_status_strings_and_defaults_without_device():
     p = F.fsmi_params()
     L.fsmi_default_params(ctypes.byref(p))
     assert p.delta_occ == 1.5 and p.variant == F.FSMI_EXACT and p.precision == F.FSMI_FP32
-    assert ctypes.sizeof(F.fsmi_params) == 32
+    assert p.flags == 0 and p.sigma_slope == 0.0
+    # double, 5 x int32, uint32, double: the C layout, no padding before the last double
+    assert ctypes.sizeof(F.fsmi_params) == 40
 
 
 def test_binding_names_match_header():

@@ -416,7 +416,8 @@ def test_skip_zero_rejects_other_modes(ctx):
     bd = dev(np.array([0.0, 1.0, 2.0]))
     for prm in (F.params(variant=F.FSMI_APPROX, flags=F.FSMI_F_SKIP_ZERO),
                 F.params(precision=F.FSMI_FP64, flags=F.FSMI_F_SKIP_ZERO),
-                F.params(flags=2)):
+                F.params(flags=F.FSMI_F_SKIP_ZERO | F.FSMI_F_MAX_RANGE),
+                F.params(flags=4)):
         with pytest.raises(F.FsmiError) as e:
             ctx.fsmi_eval_beams(prm, off, occ, sg, bound=bd)
         assert e.value.status == F.FSMI_E_INVAL
@@ -428,4 +429,87 @@ def test_skip_zero_rejects_other_modes(ctx):
         ctx.fsmi_eval_poses(F.params(flags=F.FSMI_F_SKIP_ZERO), vox, dev(np.array([[4.5, 4.5, 4.5, 1.0, 0.0]])),
                             dev(np.array([[1.0, 0.0, 0.0]])), 1.0, 5.0, 1.0)
     assert e.value.status == F.FSMI_E_INVAL
+    ctx.fsmi_sync()
+
+
+# ---------------------------------------------------------------------------
+# Range-dependent noise (sigma_j = sigma + slope mu_j) and max-range returns
+# ---------------------------------------------------------------------------
+EXT_CASES = [(0.15, False), (0.0, True), (0.15, True)]
+
+
+@pytest.mark.parametrize("slope,tail", EXT_CASES)
+@pytest.mark.parametrize("prec", [F.FSMI_FP32, F.FSMI_FP64])
+def test_range_noise_and_max_range_beams(ctx, slope, tail, prec):
+    """Explicit-boundary batch (empty, one-cell, ragged, wave-per-beam and
+    tile-per-beam lengths) against the oracle's extended Thm 1."""
+    print(f"[gpu] range noise / max range beams slope={slope} tail={tail} prec={prec}", flush=True)
+    off, occ, bound, sigma = _beam_batch(40, len(LENS), LENS, True)
+    prm = F.params(precision=prec, flags=F.FSMI_F_MAX_RANGE if tail else 0, sigma_slope=slope)
+    mi = ctx.fsmi_eval_beams(prm, dev(off), dev(occ), dev(sigma), dev(bound))
+    torch.cuda.synchronize()
+    ctx.fsmi_sync()
+    ref = O.eval_beams(O.EXACT, off, occ, sigma, bound=bound, slope=slope, tail=tail)
+    got = mi.cpu().numpy()
+    assert got[0] == 0.0
+    assert rel_err(got, ref) <= (TOL32 if prec == F.FSMI_FP32 else TOL64)
+    if tail:       # the max-range term is a non-negative addition
+        plain = O.eval_beams(O.EXACT, off, occ, sigma, bound=bound, slope=slope)
+        assert np.all(got >= plain * (1 - 1e-5) - 1e-300)
+
+
+@pytest.mark.parametrize("slope,tail", EXT_CASES)
+@pytest.mark.parametrize("prec,tol", [(F.FSMI_FP64, TOL64), (F.FSMI_FP32, TOL32)])
+def test_range_noise_and_max_range_poses_2d(ctx, slope, tail, prec, tol):
+    print(f"[gpu] range noise / max range poses slope={slope} tail={tail} prec={prec}", flush=True)
+    wl = W.grid_small()
+    prm = F.params(precision=prec, flags=F.FSMI_F_MAX_RANGE if tail else 0, sigma_slope=slope)
+    mp, mb = ctx.fsmi_eval_poses(prm, dev(wl["grid"]), dev(wl["poses"]), dev(wl["beam_dir"]),
+                                 wl["sigma"], wl["R"], want_beams=True)
+    torch.cuda.synchronize()
+    ctx.fsmi_sync()
+    rp, rb = O.eval_poses_2d(O.EXACT, wl["grid"], wl["poses"], wl["beam_dir"], wl["sigma"],
+                             wl["R"], slope=slope, tail=tail)
+    assert rel_err(mb.cpu().numpy(), rb) <= tol
+    assert rel_err(mp.cpu().numpy(), rp) <= tol
+
+
+def test_range_noise_and_max_range_plan_replays_match_eager(ctx):
+    print("[gpu] range noise / max range plan", flush=True)
+    off, occ, bound, sigma = _beam_batch(41, len(LENS), LENS, True)
+    prm = F.params(flags=F.FSMI_F_MAX_RANGE, sigma_slope=0.1)
+    eager = ctx.fsmi_eval_beams(prm, dev(off), dev(occ), dev(sigma), dev(bound))
+    plan = F.Plan(ctx, prm, dev(off), dev(occ), dev(sigma), bound=dev(bound), graph=True)
+    for _ in range(3):
+        plan.launch()
+        torch.cuda.synchronize()
+        assert torch.equal(plan.mi, eager)
+    plan.close()
+    ctx.fsmi_sync()
+
+
+def test_range_noise_and_max_range_reject_other_modes(ctx):
+    off = dev(np.array([0, 2], np.int64))
+    occ = dev(np.array([0.2, 0.3], np.float32))
+    sg = dev(np.array([1.0], np.float32))
+    bd = dev(np.array([0.0, 1.0, 2.0]))
+    for prm in (F.params(sigma_slope=-0.1), F.params(sigma_slope=float("inf")),
+                F.params(variant=F.FSMI_APPROX, sigma_slope=0.1),
+                F.params(variant=F.FSMI_UNIFORM, flags=F.FSMI_F_MAX_RANGE),
+                F.params(flags=F.FSMI_F_SKIP_ZERO, sigma_slope=0.1)):
+        with pytest.raises(F.FsmiError) as e:
+            ctx.fsmi_eval_beams(prm, off, occ, sg, bound=bd)
+        assert e.value.status == F.FSMI_E_INVAL
+    for prm in (F.params(sigma_slope=0.1), F.params(flags=F.FSMI_F_MAX_RANGE)):
+        with pytest.raises(F.FsmiError) as e:      # unit cells: no explicit boundaries
+            ctx.fsmi_eval_beams(prm, off, occ, sg)
+        assert e.value.status == F.FSMI_E_INVAL
+        with pytest.raises(F.FsmiError) as e:
+            ctx.fsmi_rle_eval_beams(prm, off, occ, dev(np.array([1, 1], np.int32)), sg)
+        assert e.value.status == F.FSMI_E_INVAL
+        vox = dev(np.full((8, 8, 8), 0.3, np.float32))
+        with pytest.raises(F.FsmiError) as e:
+            ctx.fsmi_eval_poses(prm, vox, dev(np.array([[4.5, 4.5, 4.5, 1.0, 0.0]])),
+                                dev(np.array([[1.0, 0.0, 0.0]])), 1.0, 5.0, 1.0)
+        assert e.value.status == F.FSMI_E_INVAL
     ctx.fsmi_sync()
