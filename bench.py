@@ -306,6 +306,14 @@ def main():
                                      "pairs_per_step_est": pairs * band / dense_s}
         log(f"[bench] exact skip-zero: {n_total/dt/1e6:.2f} M beams/s, "
             f"{band/dense_s*100:.1f} % of the dense pairs")
+        # range-dependent noise and max-range returns on the same workload
+        # (sigma_j = 3 + 0.005 mu_j: 3 cells near the sensor, 5 at 400)
+        pe = F.params(variant=F.FSMI_EXACT, flags=F.FSMI_F_MAX_RANGE, sigma_slope=0.005)
+        dt = timed(lambda: ctx.fsmi_eval_poses(pe, grid, poses, bdir, sigma, R))
+        gpu["exact_range_noise_max_range"] = ctx.fsmi_eval_poses(pe, grid, poses, bdir, sigma, R)[0]
+        extras["exact_range_noise_max_range"] = {"beams_per_s": n_total / dt, "ms": dt * 1e3,
+                                                 "sigma_slope": 0.005}
+        log(f"[bench] exact, range-dependent sigma + max-range returns: {n_total/dt/1e6:.2f} M beams/s")
         off, occ, sg = W.uneven_beams(100000, seed=W.SEED_BASE + 3)
         o_, oc, s2 = t(off), t(occ), t(sg)
         dt = timed(lambda: ctx.fsmi_eval_beams(prm, o_, oc, s2))
@@ -418,6 +426,10 @@ def oracle_leg(out, gpu, wl, W, args, ctx, F, t):
             rep[name] = _err_stats(_rel(gpu[name][:kp].cpu().numpy(), rp), 1e-5, poses=kp)
         rep["exact_skip_zero"] = _err_stats(_rel(gpu["exact_skip_zero"][:k].cpu().numpy(), ref_pose),
                                             1e-5, poses=k)
+        rp, _ = O.eval_poses_2d(O.EXACT, wl["grid"], wl["poses"][:kp], wl["beam_dir"], sig, R,
+                                threads=thr, want_beams=False, slope=0.005, tail=True)
+        rep["exact_range_noise_max_range"] = _err_stats(
+            _rel(gpu["exact_range_noise_max_range"][:kp].cpu().numpy(), rp), 1e-5, poses=kp)
         off, occ, sg = W.uneven_beams(100000, seed=W.SEED_BASE + 3)
         nb = 2000
         rb = O.eval_beams(O.EXACT, off[:nb + 1], occ[:off[nb]], sg[:nb], threads=thr)
