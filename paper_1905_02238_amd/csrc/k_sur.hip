@@ -307,22 +307,42 @@ constexpr int kA1Px = 40;              // bf16 per conv1 pixel in LDS (32 channe
 constexpr int kW2Elems = 64 * 9 * 32;
 constexpr int kPatchPer = (kTP * kTP + 255) / 256;   // gathers per thread
 
-// Patch window of tile `tile` into registers: all gathers issue before any is
-// used (clamped addresses, selects after the loads).
-FSMI_DEV void gather_window(const PatchSrc& src, int64_t tile, int tid, float (&v)[kPatchPer]) {
-  const int64_t b = tile >> 4;
-  const int oy0 = kT2 * (int)((tile >> 2) & 3), ox0 = kT2 * (int)(tile & 3);
-  const int py0 = 4 * oy0 - 3, px0 = 4 * ox0 - 3;   // patch window origin
-  const int64_t cx0 = src.block(src.poses[4 * b]) - kPatch / 2 + px0;
-  const int64_t cy0 = src.block(src.poses[4 * b + 1]) - kPatch / 2 + py0;
+// A thread's share of a tile's patch window: element e = tid + 256 k at row
+// e / kTP, column e % kTP, the same for every tile (computed once).
+struct WinOffs {
+  int r[kPatchPer], c[kPatchPer];
+  bool v[kPatchPer];
+};
+FSMI_DEV WinOffs win_offsets(int tid) {
+  WinOffs w;
 #pragma unroll
   for (int k = 0; k < kPatchPer; ++k) {
     const int e = tid + 256 * k;
-    const int r = e / kTP, c = e - (e / kTP) * kTP;
-    const int64_t cx = cx0 + c, cy = cy0 + r;
-    const bool on_map = cx >= 0 && cx < src.X && cy >= 0 && cy < src.Y;
-    const float m = src.map[on_map ? cx + src.X * cy : 0];
-    const bool in_patch = py0 + r >= 0 && py0 + r < kPatch && px0 + c >= 0 && px0 + c < kPatch;
+    w.v[k] = e < kTP * kTP;
+    w.r[k] = w.v[k] ? e / kTP : 0;
+    w.c[k] = w.v[k] ? e - (e / kTP) * kTP : 0;
+  }
+  return w;
+}
+
+// Patch window of tile `tile` into registers: all gathers issue before any is
+// used (clamped addresses, selects after the loads).  The map has fewer than
+// 2^31 cells, so cell arithmetic is int32.
+FSMI_DEV void gather_window(const PatchSrc& src, int64_t tile, const WinOffs& w,
+                            float (&v)[kPatchPer]) {
+  const int64_t b = tile >> 4;
+  const int oy0 = kT2 * (int)((tile >> 2) & 3), ox0 = kT2 * (int)(tile & 3);
+  const int py0 = 4 * oy0 - 3, px0 = 4 * ox0 - 3;   // patch window origin
+  const int cx0 = (int)src.block(src.poses[4 * b]) - kPatch / 2 + px0;
+  const int cy0 = (int)src.block(src.poses[4 * b + 1]) - kPatch / 2 + py0;
+  const int X = (int)src.X, Y = (int)src.Y;
+#pragma unroll
+  for (int k = 0; k < kPatchPer; ++k) {
+    const int cx = cx0 + w.c[k], cy = cy0 + w.r[k];
+    const bool on_map = (unsigned)cx < (unsigned)X && (unsigned)cy < (unsigned)Y;
+    const float m = src.map[on_map ? cx + X * cy : 0];
+    const bool in_patch = (unsigned)(py0 + w.r[k]) < (unsigned)kPatch &&
+                          (unsigned)(px0 + w.c[k]) < (unsigned)kPatch;
     v[k] = in_patch ? (on_map ? m : 0.5f) : 0.0f;
   }
 }
@@ -362,8 +382,21 @@ __global__ __launch_bounds__(256) void k_conv12_fwd(int64_t n_tiles, PatchSrc sr
   for (int t = 0; t < 4; ++t)
 #pragma unroll
     for (int r = 0; r < 4; ++r) bias2[t][r] = b2[16 * t + 4 * g + r];
+  const WinOffs woff = win_offsets(tid);
+  // conv1 pixels of this lane (p = 16 m + i, m = wave, wave + 4, ...): their
+  // place in the window and their patch offset, the same for every tile
+  constexpr int kC1 = (19 + 3) / 4;   // column tiles of 16 per wave, at most
+  int c1_pr[kC1], c1_pc[kC1], c1_base[kC1];
+#pragma unroll
+  for (int u = 0; u < kC1; ++u) {
+    const int p = 16 * (wave + 4 * u) + i;
+    const bool pv = p < kT1 * kT1;
+    c1_pr[u] = pv ? p / kT1 : -1000;          // -1000: outside any grid
+    c1_pc[u] = pv ? p - (p / kT1) * kT1 : 0;
+    c1_base[u] = pv ? 2 * c1_pr[u] * kTP + 2 * c1_pc[u] : 0;
+  }
   float v[kPatchPer];
-  if ((int64_t)blockIdx.x < n_tiles) gather_window(src, blockIdx.x, tid, v);
+  if ((int64_t)blockIdx.x < n_tiles) gather_window(src, blockIdx.x, woff, v);
   __syncthreads();
   for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
     const int64_t b = tile >> 4;
@@ -374,13 +407,16 @@ __global__ __launch_bounds__(256) void k_conv12_fwd(int64_t n_tiles, PatchSrc sr
       if (e < kTP * kTP) sP[e] = (bf16)v[k];
     }
     __syncthreads();
-    if (tile + gridDim.x < n_tiles) gather_window(src, tile + gridDim.x, tid, v);
+    if (tile + gridDim.x < n_tiles) gather_window(src, tile + gridDim.x, woff, v);
     // conv1 on the window: 289 pixels in 19 column tiles of 16 (the last padded)
-    for (int m = wave; m < 19; m += 4) {
+#pragma unroll
+    for (int u = 0; u < kC1; ++u) {
+      const int m = wave + 4 * u;
+      if (m >= 19) break;                       // wave-uniform
       const int p = 16 * m + i;
-      const bool pv = p < kT1 * kT1;
-      const int pr = pv ? p / kT1 : 0, pc = pv ? p - (p / kT1) * kT1 : 0;
-      const int base = 2 * pr * kTP + 2 * pc;
+      const bool pv = c1_pr[u] >= 0;
+      const int pr = pv ? c1_pr[u] : 0, pc = c1_pc[u];
+      const int base = c1_base[u];
       bf16x8 x = zero8();   // B operand: taps 8g .. 8g + 7 of pixel p
       if (g == 0) {
         x[0] = sP[base];
