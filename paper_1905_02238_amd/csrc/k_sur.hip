@@ -288,6 +288,101 @@ __global__ __launch_bounds__(256) void k_conv_fwd_m4(int64_t npix, const bf16* _
 }
 
 // ---------------------------------------------------------------------------
+// The same layers with each tap's weights staged in LDS: per tap the
+// workgroup copies W[:, tap, :] (COUT x CIN, rows padded by 16 bytes so the 16
+// rows a fragment reads fall in different banks) once, and its four waves read
+// their weight fragments from LDS instead of each fetching them from L2.  The
+// activation fragments of the tap are issued before the barrier.  Waves past
+// the last pixel still take every barrier.
+// ---------------------------------------------------------------------------
+template <int CIN, int COUT>
+constexpr int conv_lds_row() { return CIN + 8; }
+
+template <int CIN, int COUT, int HIN>
+__global__ __launch_bounds__(256) void k_conv_fwd_lds(int64_t npix, const bf16* __restrict__ in,
+                                                      const bf16* __restrict__ W,
+                                                      const float* __restrict__ bias,
+                                                      bf16* __restrict__ out) {
+  constexpr int HOUT = HIN / 2, NT = COUT / 16, MT = conv_mt<CIN, COUT, HIN>();
+  constexpr int KC = CIN / 32, ROW = conv_lds_row<CIN, COUT>();
+  __shared__ __align__(16) bf16 sW[COUT * ROW];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int64_t base = ((int64_t)blockIdx.x * 4 + wave) * (16 * MT);
+  const int n_mt = base < npix ? (int)min<int64_t>(MT, (npix - base) / 16) : 0;   // wave-uniform
+  const int i = lane & 15, g = lane >> 4;
+  int64_t pb[MT];
+  int poy[MT], pox[MT];
+#pragma unroll
+  for (int m = 0; m < MT; ++m) {
+    const int64_t p = min<int64_t>(base + 16 * m + i, npix - 1);
+    pb[m] = p / (HOUT * HOUT);
+    poy[m] = (int)((p / HOUT) % HOUT);
+    pox[m] = (int)(p % HOUT);
+  }
+  floatx4 acc[MT][NT];
+#pragma unroll
+  for (int m = 0; m < MT; ++m)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[m][t] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 1
+  for (int tap = 0; tap < 9; ++tap) {
+    const int ky = tap / 3, kx = tap % 3;
+    bf16x8 a[MT][KC];
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+      const int iy = 2 * poy[m] + ky - 1, ix = 2 * pox[m] + kx - 1;
+      const bool ok = m < n_mt && iy >= 0 && iy < HIN && ix >= 0 && ix < HIN;
+      const bf16* ip = in + ((pb[m] * HIN + (ok ? iy : 0)) * HIN + (ok ? ix : 0)) * CIN;
+#pragma unroll
+      for (int c = 0; c < KC; ++c) a[m][c] = ok ? load8(ip + 32 * c + 8 * g) : zero8();
+    }
+    for (int e8 = tid; e8 < COUT * CIN / 8; e8 += 256) {
+      const int co = e8 / (CIN / 8), cc = e8 - co * (CIN / 8);
+      *reinterpret_cast<bf16x8*>(sW + co * ROW + 8 * cc) = load8(W + (co * 9 + tap) * CIN + 8 * cc);
+    }
+    __syncthreads();
+    if (n_mt > 0) {
+#pragma unroll
+      for (int c = 0; c < KC; ++c)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          const bf16x8 w = *reinterpret_cast<const bf16x8*>(sW + (16 * t + i) * ROW + 32 * c + 8 * g);
+#pragma unroll
+          for (int m = 0; m < MT; ++m)
+            if (m < n_mt) acc[m][t] = mfma(w, a[m][c], acc[m][t]);
+        }
+    }
+    __syncthreads();
+  }
+  if (n_mt == 0) return;
+  // D[n][p]: channels 16t + 4g + r of pixel base + 16m + i
+  float bv[NT][4];
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) bv[t][r] = bias[16 * t + 4 * g + r];
+#pragma unroll
+  for (int m = 0; m < MT; ++m) {
+    if (m >= n_mt) break;
+    bf16* op = out + (base + 16 * m + i) * COUT + 4 * g;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      float o[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const float v = acc[m][t][r] + bv[t][r];
+        o[r] = v > 0.0f ? v : 0.0f;
+      }
+      uint2 w;
+      w.x = pack2(o[0], o[1]);
+      w.y = pack2(o[2], o[3]);
+      *reinterpret_cast<uint2*>(op + 16 * t) = w;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Inference: conv1 fused into conv2.  A workgroup owns 8 x 8 output pixels of
 // conv2 (all 64 channels) at a time: it gathers the 35 x 35 patch window those
 // pixels depend on, computes the 17 x 17 x 32 conv1 outputs of the window into
@@ -1008,7 +1103,7 @@ static void conv_fwd(fsmi_sur net, int64_t nb, PatchSrc src) {
   } else {
     constexpr int per_block = 4 * 16 * conv_mt<d.cin, d.cout, d.hin>();   // 4 waves
     const int64_t blocks = (npix + per_block - 1) / per_block;
-    hipLaunchKernelGGL((k_conv_fwd_m4<d.cin, d.cout, d.hin>), dim3((unsigned)blocks), dim3(256), 0,
+    hipLaunchKernelGGL((k_conv_fwd_lds<d.cin, d.cout, d.hin>), dim3((unsigned)blocks), dim3(256), 0,
                        net->ctx->stream, npix, net->act[L], net->Wbf + wbf_off(L), net->P + b_off(L),
                        net->act[L + 1]);
   }
