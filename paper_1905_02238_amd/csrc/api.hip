@@ -186,7 +186,7 @@ fsmi_status fsmi_create(fsmi_ctx* out, int device, void* hip_stream) {
   c->stream = (hipStream_t)hip_stream;   // NULL: the device's default stream
   if (hipMalloc(&c->d_status, 256) != hipSuccess || hipMalloc(&c->d_counters, 64 * 4) != hipSuccess) {
     if (c->d_status) (void)hipFree(c->d_status);
-      delete c;
+    delete c;
     return FSMI_E_NOMEM;
   }
   (void)hipMemset(c->d_status, 0, 256);

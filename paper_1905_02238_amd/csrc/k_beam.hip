@@ -186,13 +186,29 @@ __global__ void k_sched_scan(int32_t* hist) {
   }
 }
 
-__global__ void k_sched_scatter(const int64_t* off, int64_t n_beams, int wave_max, int32_t* hist,
-                                int32_t* order) {
-  for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < n_beams;
-       b += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t n = off[b + 1] - off[b];
-    const int pos = atomicAdd(&hist[kBins + len_bin(n, wave_max)], 1);
-    order[pos] = (int32_t)b;
+// Beams into their bins, a block of 256 at a time: ranks within the block
+// from LDS atomics, one global atomic per bin and block for the block's range
+// (order within a bin is arbitrary; every beam's result is independent of it).
+__global__ __launch_bounds__(256) void k_sched_scatter(const int64_t* off, int64_t n_beams,
+                                                       int wave_max, int32_t* hist,
+                                                       int32_t* order) {
+  __shared__ int32_t cnt[kBins], base[kBins];
+  const int tid = threadIdx.x;
+  for (int64_t chunk = (int64_t)blockIdx.x * 256; chunk < n_beams;
+       chunk += (int64_t)gridDim.x * 256) {
+    if (tid < kBins) cnt[tid] = 0;
+    __syncthreads();
+    const int64_t b = chunk + tid;
+    int bin = -1, local = 0;
+    if (b < n_beams) {
+      bin = len_bin(off[b + 1] - off[b], wave_max);
+      local = atomicAdd(&cnt[bin], 1);
+    }
+    __syncthreads();
+    if (tid < kBins && cnt[tid]) base[tid] = atomicAdd(&hist[kBins + tid], cnt[tid]);
+    __syncthreads();
+    if (bin >= 0) order[base[bin] + local] = (int32_t)b;
+    __syncthreads();
   }
 }
 
