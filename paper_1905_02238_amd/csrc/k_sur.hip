@@ -204,97 +204,20 @@ FSMI_DEV uint32_t pack2(float a, float b) {
 
 // ---------------------------------------------------------------------------
 // Forward convolution, layers after the first: one wave = MT column tiles of
-// 16 output pixels x all COUT channels, so every weight fragment it loads
-// feeds MT products (MT = 4, or 2 for 128 channels to keep three waves per
-// SIMD).  Products are taken transposed (weights as the A operand), so a lane
-// ends with four consecutive channels of one pixel and stores 8 bytes at once.
-// npix is a multiple of 16.
-// ---------------------------------------------------------------------------
-template <int CIN, int COUT, int HIN>
-constexpr int conv_mt() { return COUT >= 128 ? 2 : 4; }
-
-template <int CIN, int COUT, int HIN>
-__global__ __launch_bounds__(256) void k_conv_fwd_m4(int64_t npix, const bf16* __restrict__ in,
-                                                     const bf16* __restrict__ W,
-                                                     const float* __restrict__ bias,
-                                                     bf16* __restrict__ out) {
-  constexpr int HOUT = HIN / 2, NT = COUT / 16, MT = conv_mt<CIN, COUT, HIN>();
-  const int lane = threadIdx.x & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int64_t base = ((int64_t)blockIdx.x * 4 + wave) * (16 * MT);
-  if (base >= npix) return;
-  const int n_mt = (int)min<int64_t>(MT, (npix - base) / 16);   // wave-uniform
-  const int i = lane & 15, g = lane >> 4;
-  int64_t pb[MT];
-  int poy[MT], pox[MT];
-#pragma unroll
-  for (int m = 0; m < MT; ++m) {
-    const int64_t p = min<int64_t>(base + 16 * m + i, npix - 1);
-    pb[m] = p / (HOUT * HOUT);
-    poy[m] = (int)((p / HOUT) % HOUT);
-    pox[m] = (int)(p % HOUT);
-  }
-  floatx4 acc[MT][NT];
-#pragma unroll
-  for (int m = 0; m < MT; ++m)
-#pragma unroll
-    for (int t = 0; t < NT; ++t) acc[m][t] = floatx4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 1
-  for (int tap = 0; tap < 9; ++tap) {
-    const int ky = tap / 3, kx = tap % 3;
-#pragma unroll
-    for (int c0 = 0; c0 < CIN; c0 += 32) {
-      bf16x8 a[MT];
-#pragma unroll
-      for (int m = 0; m < MT; ++m) {
-        const int iy = 2 * poy[m] + ky - 1, ix = 2 * pox[m] + kx - 1;
-        const bool ok = iy >= 0 && iy < HIN && ix >= 0 && ix < HIN;
-        const bf16* ip = in + ((pb[m] * HIN + (ok ? iy : 0)) * HIN + (ok ? ix : 0)) * CIN;
-        a[m] = ok ? load8(ip + c0 + 8 * g) : zero8();
-      }
-#pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        const bf16x8 w = load8(W + ((16 * t + i) * 9 + tap) * CIN + c0 + 8 * g);
-#pragma unroll
-        for (int m = 0; m < MT; ++m)
-          if (m < n_mt) acc[m][t] = mfma(w, a[m], acc[m][t]);
-      }
-    }
-  }
-  // D[n][p]: channels 16t + 4g + r of pixel base + 16m + i
-  float bv[NT][4];
-#pragma unroll
-  for (int t = 0; t < NT; ++t)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) bv[t][r] = bias[16 * t + 4 * g + r];
-#pragma unroll
-  for (int m = 0; m < MT; ++m) {
-    if (m >= n_mt) break;
-    bf16* op = out + (base + 16 * m + i) * COUT + 4 * g;
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      float o[4];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const float v = acc[m][t][r] + bv[t][r];
-        o[r] = v > 0.0f ? v : 0.0f;
-      }
-      uint2 w;
-      w.x = pack2(o[0], o[1]);
-      w.y = pack2(o[2], o[3]);
-      *reinterpret_cast<uint2*>(op + 16 * t) = w;
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
-// The same layers with each tap's weights staged in LDS: per tap the
+// 16 output pixels x all COUT channels, so every weight fragment it reads
+// feeds MT products (MT = 4, or 2 for 128 channels; more or fewer measured
+// slower).  Products are taken transposed (weights as the A operand), so a
+// lane ends with four consecutive channels of one pixel and stores 8 bytes at
+// once.  npix is a multiple of 16.  Each tap's weights are staged in LDS: the
 // workgroup copies W[:, tap, :] (COUT x CIN, rows padded by 16 bytes so the 16
 // rows a fragment reads fall in different banks) once, and its four waves read
 // their weight fragments from LDS instead of each fetching them from L2.  The
 // activation fragments of the tap are issued before the barrier.  Waves past
 // the last pixel still take every barrier.
 // ---------------------------------------------------------------------------
+template <int CIN, int COUT, int HIN>
+constexpr int conv_mt() { return COUT >= 128 ? 2 : 4; }
+
 template <int CIN, int COUT>
 constexpr int conv_lds_row() { return CIN + 8; }
 
