@@ -503,146 +503,398 @@ __global__ __launch_bounds__(256) void k_conv12_fwd(int64_t n_tiles, PatchSrc sr
 
 // ---------------------------------------------------------------------------
 // Input-gradient pass: d_in[p][ci] = [act_in[p][ci] > 0] *
-//   sum_{tap, co} W[co][tap][ci] d_out[(p - tap)/2][co], only where p + 1 - tap
-//   is even in both axes and inside the output grid.  Wt is [tap][ci][co].
-// One wave = 16 input pixels x all CIN channels.
+//   sum over taps and co of W[co][tap][ci] d_out[o][co], over the taps whose
+//   output pixel o = ((iy + 1 - ky) / 2, (ix + 1 - kx) / 2) is whole and inside
+//   the output grid.  With stride 2 and padding 1 those taps depend only on
+//   the parity of the input pixel: an even row takes ky = 1 (oy = iy / 2), an
+//   odd row ky = 0 (oy = (iy + 1) / 2) and ky = 2 (oy = (iy - 1) / 2); columns
+//   alike.  So the input pixels fall into four classes of 1, 2, 2 and 4 taps,
+//   and a wave takes pixels of one class only: no product is spent on a tap
+//   that does not reach its pixels.  A workgroup is the four classes (one wave
+//   each) of 16 MT consecutive half-resolution positions q = (b, a, c), pixel
+//   (iy, ix) = (2 a + py, 2 c + px).  Products are taken transposed (weights
+//   as the A operand, Wt is [tap][ci][co]), so a lane ends with four
+//   consecutive channels of one pixel and loads and stores 8 bytes at once.
+//   nq = batch x (HIN / 2)^2 is a multiple of 16.
 // ---------------------------------------------------------------------------
 template <int CIN, int COUT, int HIN>
-__global__ __launch_bounds__(256) void k_conv_dgrad(int64_t npix_in, const bf16* __restrict__ dout,
+constexpr int dgrad_mt() { return CIN >= 128 ? 2 : 4; }
+
+template <int CIN, int COUT, int HIN>
+__global__ __launch_bounds__(256) void k_conv_dgrad(int64_t nq, const bf16* __restrict__ dout,
                                                     const bf16* __restrict__ Wt,
                                                     const bf16* __restrict__ act_in,
                                                     bf16* __restrict__ din) {
-  constexpr int HOUT = HIN / 2, NT = CIN / 16;
+  constexpr int HOUT = HIN / 2, NT = CIN / 16, KC = COUT / 32, MT = dgrad_mt<CIN, COUT, HIN>();
   const int lane = threadIdx.x & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int64_t base = ((int64_t)blockIdx.x * 4 + wave) * 16;
-  if (base >= npix_in) return;
+  const int cls = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int py = cls >> 1, px = cls & 1;
+  const int64_t base = (int64_t)blockIdx.x * (16 * MT);
+  const int n_mt = (int)min<int64_t>(MT, (nq - base) / 16);   // >= 1: the grid covers nq exactly
   const int i = lane & 15, g = lane >> 4;
-  const int64_t p = base + i;
-  const int64_t b = p / (HIN * HIN);
-  const int iy = (int)((p / HIN) % HIN), ix = (int)(p % HIN);
-  floatx4 acc[NT];
+  int64_t qb[MT];
+  int qa[MT], qc[MT];
 #pragma unroll
-  for (int t = 0; t < NT; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+  for (int m = 0; m < MT; ++m) {
+    const int64_t q = min<int64_t>(base + 16 * m + i, nq - 1);
+    qb[m] = q / (HOUT * HOUT);
+    qa[m] = (int)((q / HOUT) % HOUT);
+    qc[m] = (int)(q % HOUT);
+  }
+  floatx4 acc[MT][NT];
+#pragma unroll
+  for (int m = 0; m < MT; ++m)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[m][t] = floatx4{0.f, 0.f, 0.f, 0.f};
+  const int nky = 1 + py, nkx = 1 + px;
 #pragma unroll 1
-  for (int tap = 0; tap < 9; ++tap) {
-    const int ky = tap / 3, kx = tap % 3;
-    const int ty = iy + 1 - ky, tx = ix + 1 - kx;
-    const bool ok = ty >= 0 && tx >= 0 && (ty & 1) == 0 && (tx & 1) == 0 && (ty >> 1) < HOUT &&
-                    (tx >> 1) < HOUT;
-    const bf16* dp = dout + ((b * HOUT + (ok ? ty >> 1 : 0)) * HOUT + (ok ? tx >> 1 : 0)) * COUT;
+  for (int jy = 0; jy < nky; ++jy) {
+#pragma unroll 1
+    for (int jx = 0; jx < nkx; ++jx) {
+      // odd row: ky = 0 reads output row a + 1, ky = 2 row a; even row: ky = 1, row a
+      const int ky = py ? 2 * jy : 1, kx = px ? 2 * jx : 1;
+      const int dy = (py && jy == 0) ? 1 : 0, dx = (px && jx == 0) ? 1 : 0;
+      const int tap = 3 * ky + kx;
+      bf16x8 a[MT][KC];
 #pragma unroll
-    for (int c0 = 0; c0 < COUT; c0 += 32) {
-      const bf16x8 a = ok ? load8(dp + c0 + 8 * g) : zero8();
+      for (int m = 0; m < MT; ++m) {
+        const int oy = qa[m] + dy, ox = qc[m] + dx;
+        const bool ok = m < n_mt && oy < HOUT && ox < HOUT;
+        const bf16* dp = dout + ((qb[m] * HOUT + (ok ? oy : 0)) * HOUT + (ok ? ox : 0)) * COUT;
 #pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        const bf16x8 w = load8(Wt + (tap * CIN + 16 * t + i) * COUT + c0 + 8 * g);
-        acc[t] = mfma(a, w, acc[t]);
+        for (int c = 0; c < KC; ++c) a[m][c] = ok ? load8(dp + 32 * c + 8 * g) : zero8();
       }
+#pragma unroll
+      for (int c = 0; c < KC; ++c)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          const bf16x8 w = load8(Wt + (tap * CIN + 16 * t + i) * COUT + 32 * c + 8 * g);
+#pragma unroll
+          for (int m = 0; m < MT; ++m) acc[m][t] = mfma(w, a[m][c], acc[m][t]);
+        }
     }
   }
+  // D[4 g + r][i]: channel 16 t + 4 g + r of pixel (m, i)
 #pragma unroll
-  for (int t = 0; t < NT; ++t) {
-    const int ci = 16 * t + i;
+  for (int m = 0; m < MT; ++m) {
+    if (m >= n_mt) break;
+    const int iy = 2 * qa[m] + py, ix = 2 * qc[m] + px;
+    const int64_t p = (qb[m] * HIN + iy) * HIN + ix;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int64_t pr = base + 4 * g + r;
-      const float m = (float)act_in[pr * CIN + ci] > 0.0f ? 1.0f : 0.0f;
-      din[pr * CIN + ci] = (bf16)(acc[t][r] * m);
+    for (int t = 0; t < NT; ++t) {
+      const int ci = 16 * t + 4 * g;
+      const uint2 av = *reinterpret_cast<const uint2*>(act_in + p * CIN + ci);
+      const uint32_t aw[2] = {av.x, av.y};
+      uint32_t ow[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        // the two BF16 activations widened to FP32 (the low half is channel ci + 2 h)
+        const float v0 = __builtin_bit_cast(float, aw[h] << 16);
+        const float v1 = __builtin_bit_cast(float, aw[h] & 0xffff0000u);
+        const float m0 = v0 > 0.0f ? 1.0f : 0.0f, m1 = v1 > 0.0f ? 1.0f : 0.0f;
+        ow[h] = pack2(acc[m][t][2 * h] * m0, acc[m][t][2 * h + 1] * m1);
+      }
+      *reinterpret_cast<uint2*>(din + p * CIN + ci) = uint2{ow[0], ow[1]};
     }
   }
 }
 
 // ---------------------------------------------------------------------------
-// Weight-gradient pass: partial[s][co][col] = sum over pixels of split s of
-//   d_out[p][co] * B[p][col], col = tap * CIN + ci (the shifted input) or, in
-//   the extra column block, 1 for the bias.  One wave = a 16 x 16 tile.
+// Weight-gradient pass, layers after the first: partial[s][co][tap CIN + ci] =
+//   sum over the output pixels p of split s of d_out[p][co] x[p, tap][ci],
+//   x[p, tap] the input pixel under tap `tap` of p (0 in the padding), and
+//   partial[s][co][9 CIN] = sum_p d_out[p][co] (the bias).
+// The sum runs over pixels, the K axis of the products, while both operands
+// are stored channel-fastest.  So a workgroup stages 32 pixels at a time in
+// LDS channel-major (the 32 pixels of a channel contiguous): a thread loads 4
+// pixels x 8 channels (four 16-byte loads), transposes them in registers and
+// writes 8 rows of 4 pixels; fragments are then single 16-byte LDS reads.  The
+// next 32 pixels are loaded into registers while the current ones feed the
+// products.  A workgroup owns all COUT x (TPG taps x CIN) outputs of its tap
+// group; its four waves split them 2 x 2 (MW co tiles x NW column tiles each),
+// and the waves of tap group 0 with column half 0 also take the bias (a
+// product with a B fragment of ones).  Pixels past the split read 0.
 // ---------------------------------------------------------------------------
-template <int CIN, int COUT, int HIN, bool FIRST>
-__global__ __launch_bounds__(64) void k_conv_wgrad(int64_t npix_out, int chunk,
-                                                   const bf16* __restrict__ dout,
-                                                   const bf16* __restrict__ in, PatchSrc src,
-                                                   float* __restrict__ part) {
-  constexpr int HOUT = HIN / 2;
-  constexpr int NCOL = FIRST ? 16 : 9 * CIN + 16;
-  const int lane = threadIdx.x;
-  const int i = lane & 15, g = lane >> 4;
-  const int co_tile = blockIdx.x, col_tile = blockIdx.y, s = blockIdx.z;
-  const int co = 16 * co_tile + i;         // A row held by this lane
-  const int col = 16 * col_tile + i;       // B column held by this lane
-  int tap = 0, ci = 0;
-  bool is_bias = false, is_pad = false;
-  if constexpr (FIRST) {
-    tap = col;
-    is_bias = col == 9;
-    is_pad = col > 9;
-  } else {
-    if (col < 9 * CIN) {
-      tap = col / CIN;
-      ci = col % CIN;
-    } else {
-      is_bias = col == 9 * CIN;
-      is_pad = !is_bias;
-    }
+template <int CIN, int COUT, int TPG>
+struct WgradTile {
+  static constexpr int KS = 32;               // pixels per stage
+  static constexpr int ROW = KS + 8;          // LDS row: 80 bytes, 16 fragment rows in distinct banks
+  static constexpr int NMT = COUT / 16, NCT = TPG * CIN / 16;
+  static constexpr int MW = NMT / 2, NW = NCT / 2;
+  static constexpr int UA = (KS / 4) * (COUT / 8);          // staging units of d_out
+  static constexpr int UB = (KS / 4) * TPG * (CIN / 8);     // staging units of the input
+  static constexpr int ROUNDS = (UA + UB + 255) / 256;
+  static constexpr int ROWS = COUT + TPG * CIN;
+  static_assert(NMT % 2 == 0 && NCT % 2 == 0 && 9 % TPG == 0, "tile split");
+};
+
+// Transpose four vectors of 8 BF16 channels (pixels 0..3): row k gets channel
+// k of the four pixels, as two dwords.
+FSMI_DEV void transpose4x8(const bf16x8 (&v)[4], uint2 (&row)[8]) {
+  uint32_t x[4][4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const uint4 u = __builtin_bit_cast(uint4, v[j]);
+    x[j][0] = u.x;
+    x[j][1] = u.y;
+    x[j][2] = u.z;
+    x[j][3] = u.w;
   }
-  const int ky = tap / 3, kx = tap % 3;
-  floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int d = 0; d < 4; ++d) {
+    // low halves hold channel 2 d, high halves channel 2 d + 1
+    row[2 * d] = uint2{__builtin_amdgcn_perm(x[1][d], x[0][d], 0x05040100u),
+                       __builtin_amdgcn_perm(x[3][d], x[2][d], 0x05040100u)};
+    row[2 * d + 1] = uint2{__builtin_amdgcn_perm(x[1][d], x[0][d], 0x07060302u),
+                           __builtin_amdgcn_perm(x[3][d], x[2][d], 0x07060302u)};
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Weight-gradient pass, first layer: partial[s][co][col] = sum over the
+//   output pixels p of split s of d_out[p][co] B[p][col], col = tap (the patch
+//   pixel under the tap), 9 (1: the bias) or 10..15 (0).  A workgroup stages
+//   256 pixels at a time in LDS: d_out channel-major as in the later layers
+//   (transpose4x8), and the nine tap values of every pixel as rows
+//   [tap][pixel]; its four waves take alternate 32-pixel steps, and their sums
+//   are added in wave order at the end.  Pixels past the split read 0.
+// ---------------------------------------------------------------------------
+template <int COUT, int HIN>
+__global__ __launch_bounds__(256) void k_conv_wgrad_first(int64_t npix_out, int chunk,
+                                                          const bf16* __restrict__ dout, PatchSrc src,
+                                                          float* __restrict__ part) {
+  constexpr int HOUT = HIN / 2, NCOL = 16, KS = 256, ROW = KS + 8, NMT = COUT / 16;
+  constexpr int QK = KS / 4, UA = QK * (COUT / 8);
+  __shared__ __align__(16) bf16 sA[COUT * ROW];
+  __shared__ __align__(16) bf16 sB[9 * ROW];
+  __shared__ floatx4 red[4][NMT][64];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int i = lane & 15, g = lane >> 4;
+  const int s = blockIdx.x;
   const int64_t p0 = (int64_t)s * chunk;
   const int64_t p1 = min<int64_t>(p0 + chunk, npix_out);
-  for (int64_t k0 = p0; k0 < p1; k0 += 32) {
-    bf16x8 a, bb;
+  const int nstage = (int)((p1 - p0 + KS - 1) / KS);
+  floatx4 acc[NMT];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int64_t p = k0 + 8 * g + q;
-      const bool in_range = p < p1;
-      a[q] = in_range ? dout[(in_range ? p : p0) * COUT + co] : (bf16)0.0f;
+  for (int ct = 0; ct < NMT; ++ct) acc[ct] = floatx4{0.f, 0.f, 0.f, 0.f};
+  bf16x8 ones;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) ones[q] = (bf16)1.0f;
+#pragma unroll 1
+  for (int st = 0; st < nstage; ++st) {
+    const int64_t k0 = p0 + (int64_t)st * KS;
+    __syncthreads();   // every wave is done reading the previous stage
+    for (int u = tid; u < UA; u += 256) {
+      const int pq = u % QK, o = u / QK;
+      bf16x8 v[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int64_t p = k0 + 4 * pq + j;
+        v[j] = p < p1 ? load8(dout + p * COUT + 8 * o) : zero8();
+      }
+      uint2 rows[8];
+      transpose4x8(v, rows);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) *reinterpret_cast<uint2*>(sA + (8 * o + k) * ROW + 4 * pq) = rows[k];
+    }
+    for (int e = tid; e < 9 * KS; e += 256) {
+      const int tap = e / KS, pl = e % KS;
+      const int64_t p = k0 + pl;
       float v = 0.0f;
-      if (in_range && !is_pad) {
-        if (is_bias) {
-          v = 1.0f;
-        } else {
+      if (p < p1) {
+        const int64_t b = p / (HOUT * HOUT);
+        const int oy = (int)((p / HOUT) % HOUT), ox = (int)(p % HOUT);
+        v = src.at(b, 2 * oy + tap / 3 - 1, 2 * ox + tap % 3 - 1);
+      }
+      sB[tap * ROW + pl] = (bf16)v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = wave; ks < KS / 32; ks += 4) {
+      const bf16x8 fb = i < 9 ? *reinterpret_cast<const bf16x8*>(sB + i * ROW + 32 * ks + 8 * g)
+                              : (i == 9 ? ones : zero8());
+#pragma unroll
+      for (int ct = 0; ct < NMT; ++ct) {
+        const bf16x8 fa = *reinterpret_cast<const bf16x8*>(sA + (16 * ct + i) * ROW + 32 * ks + 8 * g);
+        acc[ct] = mfma(fa, fb, acc[ct]);
+      }
+    }
+  }
+#pragma unroll
+  for (int ct = 0; ct < NMT; ++ct) red[wave][ct][lane] = acc[ct];
+  __syncthreads();
+  if (wave == 0) {
+    // D[4 g + r][i]: co = 16 ct + 4 g + r, column i
+#pragma unroll
+    for (int ct = 0; ct < NMT; ++ct) {
+      const floatx4 d = ((red[0][ct][lane] + red[1][ct][lane]) + red[2][ct][lane]) + red[3][ct][lane];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) part[((int64_t)s * COUT + 16 * ct + 4 * g + r) * NCOL + i] = d[r];
+    }
+  }
+}
+
+template <int CIN, int COUT, int HIN, int TPG>
+__global__ __launch_bounds__(256) void k_conv_wgrad(int64_t npix_out, int chunk,
+                                                    const bf16* __restrict__ dout,
+                                                    const bf16* __restrict__ in,
+                                                    float* __restrict__ part) {
+  using T = WgradTile<CIN, COUT, TPG>;
+  constexpr int HOUT = HIN / 2, NCOL = 9 * CIN + 16;
+  constexpr int KS = T::KS, ROW = T::ROW, MW = T::MW, NW = T::NW, ROUNDS = T::ROUNDS;
+  constexpr int UA = T::UA, UB = T::UB, QK = KS / 4;
+  __shared__ __align__(16) bf16 sL[T::ROWS * ROW];   // rows 0..COUT-1: d_out; then the input
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm = wave >> 1, wn = wave & 1;
+  const int i = lane & 15, g = lane >> 4;
+  const int s = blockIdx.x, tg = blockIdx.y;
+  const int64_t p0 = (int64_t)s * chunk;
+  const int64_t p1 = min<int64_t>(p0 + chunk, npix_out);
+  const int nstep = (int)((p1 - p0 + KS - 1) / KS);
+  const bool bias = tg == 0 && wn == 0;
+  floatx4 acc[MW][NW], accb[MW];
+#pragma unroll
+  for (int mw = 0; mw < MW; ++mw) {
+    accb[mw] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int nw = 0; nw < NW; ++nw) acc[mw][nw] = floatx4{0.f, 0.f, 0.f, 0.f};
+  }
+  bf16x8 ones;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) ones[q] = (bf16)1.0f;
+
+  bf16x8 v[ROUNDS][4];
+  auto load_stage = [&](int64_t k0) {
+#pragma unroll
+    for (int r = 0; r < ROUNDS; ++r) {
+      const int u = tid + 256 * r;
+      if (u < UA) {
+        const int pq = u % QK, o = u / QK;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int64_t p = k0 + 4 * pq + j;
+          v[r][j] = p < p1 ? load8(dout + p * COUT + 8 * o) : zero8();
+        }
+      } else if (u < UA + UB) {
+        const int w = u - UA;
+        const int pq = w % QK, rest = w / QK;
+        const int c8 = rest % (CIN / 8), tap = tg * TPG + rest / (CIN / 8);
+        const int ky = tap / 3, kx = tap % 3;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int64_t p = k0 + 4 * pq + j;
           const int64_t b = p / (HOUT * HOUT);
           const int oy = (int)((p / HOUT) % HOUT), ox = (int)(p % HOUT);
           const int iy = 2 * oy + ky - 1, ix = 2 * ox + kx - 1;
-          if constexpr (FIRST) {
-            v = (float)(bf16)src.at(b, iy, ix);
-          } else {
-            if (iy >= 0 && iy < HIN && ix >= 0 && ix < HIN)
-              v = (float)in[((b * HIN + iy) * HIN + ix) * CIN + ci];
-          }
+          const bool ok = p < p1 && iy >= 0 && iy < HIN && ix >= 0 && ix < HIN;
+          v[r][j] = ok ? load8(in + ((b * HIN + iy) * HIN + ix) * CIN + 8 * c8) : zero8();
         }
       }
-      bb[q] = (bf16)v;
     }
-    acc = mfma(a, bb, acc);
-  }
-  // D[4g + r][i]: row co_tile*16 + 4g + r, column col_tile*16 + i
+  };
+  auto store_stage = [&]() {
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int row = 16 * co_tile + 4 * g + r;
-    part[((int64_t)s * COUT + row) * NCOL + 16 * col_tile + i] = acc[r];
+    for (int r = 0; r < ROUNDS; ++r) {
+      const int u = tid + 256 * r;
+      if (u < UA + UB) {
+        int row0, pq;
+        if (u < UA) {
+          pq = u % QK;
+          row0 = 8 * (u / QK);
+        } else {
+          const int w = u - UA;
+          pq = w % QK;
+          const int rest = w / QK;
+          row0 = COUT + (rest / (CIN / 8)) * CIN + 8 * (rest % (CIN / 8));
+        }
+        uint2 rows[8];
+        transpose4x8(v[r], rows);
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+          *reinterpret_cast<uint2*>(sL + (row0 + k) * ROW + 4 * pq) = rows[k];
+      }
+    }
+  };
+
+  if (nstep > 0) load_stage(p0);
+#pragma unroll 1
+  for (int st = 0; st < nstep; ++st) {
+    __syncthreads();   // every wave is done reading the previous stage
+    store_stage();
+    __syncthreads();
+    if (st + 1 < nstep) load_stage(p0 + (int64_t)(st + 1) * KS);
+    bf16x8 fa[MW];
+#pragma unroll
+    for (int mw = 0; mw < MW; ++mw)
+      fa[mw] = *reinterpret_cast<const bf16x8*>(sL + (16 * (wm * MW + mw) + i) * ROW + 8 * g);
+#pragma unroll
+    for (int nw = 0; nw < NW; ++nw) {
+      const bf16x8 fb =
+          *reinterpret_cast<const bf16x8*>(sL + (COUT + 16 * (wn * NW + nw) + i) * ROW + 8 * g);
+#pragma unroll
+      for (int mw = 0; mw < MW; ++mw) acc[mw][nw] = mfma(fa[mw], fb, acc[mw][nw]);
+    }
+    if (bias) {
+#pragma unroll
+      for (int mw = 0; mw < MW; ++mw) accb[mw] = mfma(fa[mw], ones, accb[mw]);
+    }
+  }
+  // D[4 g + r][i]: co = 16 mt + 4 g + r, column 16 nt + i of the tap group
+#pragma unroll
+  for (int mw = 0; mw < MW; ++mw) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int co = 16 * (wm * MW + mw) + 4 * g + r;
+      float* row = part + ((int64_t)s * COUT + co) * NCOL;
+#pragma unroll
+      for (int nw = 0; nw < NW; ++nw) row[tg * TPG * CIN + 16 * (wn * NW + nw) + i] = acc[mw][nw][r];
+      if (bias && i == 0) row[9 * CIN] = accb[mw][r];
+    }
   }
 }
 
-// grad[W(co, tap, ci)] and grad[b(co)] = sum_s partial[s][co][col], in split order.
+// ---------------------------------------------------------------------------
+// grad[W(co, tap, ci)] and grad[b(co)] = sum over splits of the partials, in a
+// fixed order: pass 1 sums each run of kRedRun consecutive splits (four lanes
+// per output take every fourth split of the run; their four sums are added in
+// lane order), pass 2 sums the runs in order.
+// ---------------------------------------------------------------------------
+constexpr int kRedRun = 32;
+
 template <int CIN, int COUT, bool FIRST>
-__global__ void k_wgrad_reduce(const float* __restrict__ part, int splits, float* __restrict__ gW,
-                               float* __restrict__ gb) {
+__global__ __launch_bounds__(256) void k_wgrad_reduce_runs(const float* __restrict__ part, int splits,
+                                                           float* __restrict__ runs) {
   constexpr int NCOL = FIRST ? 16 : 9 * CIN + 16;
-  constexpr int NW = COUT * 9 * CIN;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < NW) {
-    const int co = t / (9 * CIN), rest = t % (9 * CIN);   // rest = tap * CIN + ci
-    float s = 0.0f;
-    for (int k = 0; k < splits; ++k) s += part[((int64_t)k * COUT + co) * NCOL + rest];
-    gW[t] = s;
-  } else if (t < NW + COUT) {
-    const int co = t - NW;
-    const int bc = FIRST ? 9 : 9 * CIN;
-    float s = 0.0f;
-    for (int k = 0; k < splits; ++k) s += part[((int64_t)k * COUT + co) * NCOL + bc];
-    gb[co] = s;
+  constexpr int NW = COUT * 9 * CIN, NOUT = NW + COUT;
+  __shared__ float red[4][64];
+  const int t = threadIdx.x & 63, sl = threadIdx.x >> 6;
+  const int o = blockIdx.x * 64 + t, run = blockIdx.y;
+  float sum = 0.0f;
+  if (o < NOUT) {
+    const int co = o < NW ? o / (9 * CIN) : o - NW;
+    const int col = o < NW ? o % (9 * CIN) : 9 * CIN;   // rest = tap CIN + ci, or the bias column
+    const int k1 = min(splits, (run + 1) * kRedRun);
+    for (int k = run * kRedRun + sl; k < k1; k += 4) sum += part[((int64_t)k * COUT + co) * NCOL + col];
   }
+  red[sl][t] = sum;
+  __syncthreads();
+  if (sl == 0 && o < NOUT) runs[(int64_t)run * NOUT + o] = (red[0][t] + red[1][t]) + (red[2][t] + red[3][t]);
+}
+
+template <int CIN, int COUT>
+__global__ void k_wgrad_reduce_final(const float* __restrict__ runs, int nrun, float* __restrict__ gW,
+                                     float* __restrict__ gb) {
+  constexpr int NW = COUT * 9 * CIN, NOUT = NW + COUT;
+  const int o = blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= NOUT) return;
+  float sum = 0.0f;
+  for (int r = 0; r < nrun; ++r) sum += runs[(int64_t)r * NOUT + o];
+  if (o < NW)
+    gW[o] = sum;
+  else
+    gb[o - NW] = sum;
 }
 
 // ---------------------------------------------------------------------------
@@ -712,38 +964,99 @@ __global__ __launch_bounds__(256) void k_head_bwd(int64_t n, const float* __rest
   }
 }
 
-// Head weight gradients, each a fixed-order sum over the batch; also the loss.
-__global__ void k_head_wgrad(int64_t n, const float* __restrict__ gsave,
-                             const float* __restrict__ hsave, const float* __restrict__ dysave,
-                             const float* __restrict__ dhsave, const float* __restrict__ ypred,
-                             const double* __restrict__ labels, const double* __restrict__ stats,
-                             float* __restrict__ G, float* __restrict__ loss) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < kHid * kFeat) {   // dF1[k][c] = sum_b dh[b][k] g[b][c]
-    const int k = t / kFeat, c = t % kFeat;
-    float s = 0.0f;
-    for (int64_t b = 0; b < n; ++b) s = fmaf(dhsave[b * kHid + k], gsave[b * kFeat + c], s);
-    G[kF1 + t] = s;
-  } else if (t < kHid * kFeat + kHid) {   // dc1, dF2
-    const int k = t - kHid * kFeat;
-    float s1 = 0.0f, s2 = 0.0f;
-    for (int64_t b = 0; b < n; ++b) {
-      s1 += dhsave[b * kHid + k];
-      s2 = fmaf(dysave[b], hsave[b * kHid + k], s2);
+// Head weight gradients and the loss, each a fixed-order sum over the batch.
+// Pass 1: workgroup (kt, j) sums the poses of chunk j, in order, for the rows
+// k in [32 kt, 32 kt + 32): dF1[k][c] = sum_b dh[b][k] g[b][c], dc1[k] =
+// sum_b dh[b][k], dF2[k] = sum_b dy[b] h[b][k]; the workgroups kt = 0 also
+// take dc2 = sum_b dy[b] and the squared error.  The chunk's poses pass
+// through LDS 64 at a time.  Pass 2 adds the chunks in order.
+constexpr int kHeadOut = kHid * kFeat + 2 * kHid + 2;   // dF1, dc1, dF2, dc2, loss
+constexpr int kHeadMaxChunks = 64;
+
+__global__ __launch_bounds__(256) void k_head_wgrad_part(
+    int64_t n, int64_t chunk, const float* __restrict__ gsave, const float* __restrict__ hsave,
+    const float* __restrict__ dysave, const float* __restrict__ dhsave,
+    const float* __restrict__ ypred, const double* __restrict__ labels,
+    const double* __restrict__ stats, float* __restrict__ part) {
+  __shared__ float sdh[64][32], sh[64][32], sg[64][kFeat], sdy[64], se[64];
+  const int t = threadIdx.x, kt = blockIdx.x, j = blockIdx.y;
+  const int64_t b0 = (int64_t)j * chunk, b1 = min<int64_t>(b0 + chunk, n);
+  const int kp = 2 * (t / 16), c0 = t % 16;   // rows 32 kt + kp + {0, 1}, columns c0 + 16 q
+  float acc[2][8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) acc[0][q] = acc[1][q] = 0.0f;
+  float aux = 0.0f;   // t < 32: dc1; t < 64: dF2; with kt = 0, t = 64: dc2, t = 65: squared error
+  for (int64_t s0 = b0; s0 < b1; s0 += 64) {
+    const int nb = (int)min<int64_t>(64, b1 - s0);
+    __syncthreads();   // the previous poses are consumed
+    for (int e = t; e < 64 * 32; e += 256) {
+      const int bb = e / 32, kk = e % 32;
+      const bool ok = bb < nb;
+      sdh[bb][kk] = ok ? dhsave[(s0 + bb) * kHid + 32 * kt + kk] : 0.0f;
+      sh[bb][kk] = ok ? hsave[(s0 + bb) * kHid + 32 * kt + kk] : 0.0f;
     }
-    G[kC1 + k] = s1;
-    G[kF2 + k] = s2;
-  } else if (t == kHid * kFeat + kHid) {   // dc2 and the loss
-    float s = 0.0f, L = 0.0f;
-    for (int64_t b = 0; b < n; ++b) {
-      s += dysave[b];
-      const float target = (float)((labels[b] - stats[0]) / stats[1]);
-      const float e = ypred[b] - target;
-      L = fmaf(e, e, L);
+    for (int e = t; e < 64 * kFeat; e += 256) {
+      const int bb = e / kFeat, c = e % kFeat;
+      sg[bb][c] = bb < nb ? gsave[(s0 + bb) * kFeat + c] : 0.0f;
     }
-    G[kC2] = s;
-    if (loss) *loss = L / (float)n;
+    if (t < 64) {
+      const bool ok = t < nb;
+      sdy[t] = ok ? dysave[s0 + t] : 0.0f;
+      float ev = 0.0f;
+      if (ok && kt == 0) ev = ypred[s0 + t] - (float)((labels[s0 + t] - stats[0]) / stats[1]);
+      se[t] = ev;
+    }
+    __syncthreads();
+    for (int bb = 0; bb < nb; ++bb) {
+      const float d0 = sdh[bb][kp], d1 = sdh[bb][kp + 1];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const float gv = sg[bb][c0 + 16 * q];
+        acc[0][q] = fmaf(d0, gv, acc[0][q]);
+        acc[1][q] = fmaf(d1, gv, acc[1][q]);
+      }
+      if (t < 32)
+        aux += sdh[bb][t];
+      else if (t < 64)
+        aux = fmaf(sdy[bb], sh[bb][t - 32], aux);
+      else if (t == 64)
+        aux += sdy[bb];
+      else if (t == 65)
+        aux = fmaf(se[bb], se[bb], aux);
+    }
   }
+  float* out = part + (int64_t)j * kHeadOut;
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int q = 0; q < 8; ++q) out[(32 * kt + kp + r) * kFeat + c0 + 16 * q] = acc[r][q];
+  if (t < 32)
+    out[kHid * kFeat + 32 * kt + t] = aux;
+  else if (t < 64)
+    out[kHid * kFeat + kHid + 32 * kt + t - 32] = aux;
+  else if (kt == 0 && t < 66)
+    out[kHid * kFeat + 2 * kHid + (t - 64)] = aux;
+}
+
+__global__ __launch_bounds__(256) void k_head_wgrad_final(int64_t n, int nchunk,
+                                                          const float* __restrict__ part,
+                                                          float* __restrict__ G,
+                                                          float* __restrict__ loss) {
+  const int o = blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= kHeadOut) return;
+  float s = 0.0f;
+  for (int j = 0; j < nchunk; ++j) s += part[(int64_t)j * kHeadOut + o];
+  constexpr int nF1 = kHid * kFeat;
+  if (o < nF1)
+    G[kF1 + o] = s;
+  else if (o < nF1 + kHid)
+    G[kC1 + (o - nF1)] = s;
+  else if (o < nF1 + 2 * kHid)
+    G[kF2 + (o - nF1 - kHid)] = s;
+  else if (o == nF1 + 2 * kHid)
+    G[kC2] = s;
+  else if (loss)
+    *loss = s / (float)n;
 }
 
 // ---------------------------------------------------------------------------
@@ -910,6 +1223,8 @@ struct fsmi_sur_s {
   float* dhsave = nullptr;
   float* ypred = nullptr;
   float* part = nullptr;    // weight-gradient partials
+  float* runs = nullptr;    // their sums over runs of splits
+  float* hpart = nullptr;   // head-gradient partials per chunk of poses
   size_t part_floats = 0;
   float* loss = nullptr;
   int stride = 1;            // cell stride of the patch
@@ -920,7 +1235,10 @@ struct fsmi_sur_s {
 
 namespace fsmi {
 
-static constexpr int kSplitChunk = 4096;   // pixels per weight-gradient split
+// Output pixels per weight-gradient split, and taps per workgroup of the
+// weight-gradient kernel, per layer.
+static constexpr int kWgChunk[5] = {4096, 2048, 2048, 1024, 1024};
+static constexpr int kWgTpg[5] = {0, 9, 3, 3, 1};
 
 static size_t act_elems(int l, int B) {   // elements of act[l] (output of conv l-1... l = 1..5)
   const int h = kL[l - 1].hin / 2;
@@ -951,16 +1269,20 @@ static hipError_t sur_alloc(fsmi_sur net) {
   ALLOC(net->dysave, sizeof(float) * (size_t)B);
   ALLOC(net->dhsave, sizeof(float) * (size_t)B * kHid);
   ALLOC(net->ypred, sizeof(float) * (size_t)B);
-  size_t mx = 0;
+  size_t mx = 0, mr = 0;
   for (int l = 0; l < 5; ++l) {
     const int hout = kL[l].hin / 2;
     const size_t npix = (size_t)B * hout * hout;
-    const size_t splits = (npix + kSplitChunk - 1) / kSplitChunk;
+    const size_t splits = (npix + kWgChunk[l] - 1) / kWgChunk[l];
     const size_t ncol = l == 0 ? 16 : 9 * (size_t)kL[l].cin + 16;
+    const size_t nout = (size_t)kL[l].cout * (9 * kL[l].cin + 1);
     mx = std::max(mx, splits * kL[l].cout * ncol);
+    mr = std::max(mr, (splits + kRedRun - 1) / kRedRun * nout);
   }
   net->part_floats = mx;
   ALLOC(net->part, sizeof(float) * mx);
+  ALLOC(net->runs, sizeof(float) * mr);
+  ALLOC(net->hpart, sizeof(float) * (size_t)kHeadMaxChunks * kHeadOut);
   ALLOC(net->loss, sizeof(float) * 4);
 #undef ALLOC
   return hipSuccess;
@@ -968,7 +1290,7 @@ static hipError_t sur_alloc(fsmi_sur net) {
 
 static void sur_free(fsmi_sur net) {
   void* ps[] = {net->P, net->G, net->M, net->V, net->Wbf, net->Wt, net->stats, net->gsave,
-                net->hsave, net->dysave, net->dhsave, net->ypred, net->part, net->loss};
+                net->hsave, net->dysave, net->dhsave, net->ypred, net->part, net->runs, net->hpart, net->loss};
   for (void* p : ps)
     if (p) (void)hipFree(p);
   if (net->pooled) (void)hipFree(net->pooled);
@@ -1058,25 +1380,34 @@ static hipError_t sur_fwd_batch(fsmi_sur net, int64_t nb, PatchSrc src, bool sav
 template <int L>
 static void conv_dgrad(fsmi_sur net, int64_t nb) {
   constexpr LayerDims d = kL[L];
-  const int64_t npix_in = nb * d.hin * d.hin;
-  hipLaunchKernelGGL((k_conv_dgrad<d.cin, d.cout, d.hin>), dim3((unsigned)((npix_in + 63) / 64)),
-                     dim3(256), 0, net->ctx->stream, npix_in, net->dact[L + 1], net->Wt + wbf_off(L),
-                     net->act[L], net->dact[L]);
+  constexpr int mt = dgrad_mt<d.cin, d.cout, d.hin>();
+  const int64_t nq = nb * (d.hin / 2) * (d.hin / 2);   // a multiple of 16
+  hipLaunchKernelGGL((k_conv_dgrad<d.cin, d.cout, d.hin>),
+                     dim3((unsigned)((nq + 16 * mt - 1) / (16 * mt))), dim3(256), 0, net->ctx->stream,
+                     nq, net->dact[L + 1], net->Wt + wbf_off(L), net->act[L], net->dact[L]);
 }
 
 template <int L, bool FIRST>
 static void conv_wgrad(fsmi_sur net, int64_t nb, PatchSrc src) {
   constexpr LayerDims d = kL[L];
+  hipStream_t st = net->ctx->stream;
   const int64_t npix = nb * (d.hin / 2) * (d.hin / 2);
-  const int splits = (int)((npix + kSplitChunk - 1) / kSplitChunk);
-  constexpr int ncol = FIRST ? 16 : 9 * d.cin + 16;
-  dim3 grid(d.cout / 16, ncol / 16, splits);
-  hipLaunchKernelGGL((k_conv_wgrad<d.cin, d.cout, d.hin, FIRST>), grid, dim3(64), 0, net->ctx->stream,
-                     npix, kSplitChunk, net->dact[L + 1], FIRST ? nullptr : net->act[L], src,
-                     net->part);
-  const int nt = d.cout * 9 * d.cin + d.cout;
-  hipLaunchKernelGGL((k_wgrad_reduce<d.cin, d.cout, FIRST>), dim3((nt + 255) / 256), dim3(256), 0,
-                     net->ctx->stream, net->part, splits, net->G + w_off(L), net->G + b_off(L));
+  const int chunk = kWgChunk[L];
+  const int splits = (int)((npix + chunk - 1) / chunk);
+  if constexpr (FIRST) {
+    hipLaunchKernelGGL((k_conv_wgrad_first<d.cout, d.hin>), dim3(splits), dim3(256), 0, st,
+                       npix, chunk, net->dact[L + 1], src, net->part);
+  } else {
+    constexpr int tpg = kWgTpg[L];
+    hipLaunchKernelGGL((k_conv_wgrad<d.cin, d.cout, d.hin, tpg>), dim3(splits, 9 / tpg), dim3(256), 0,
+                       st, npix, chunk, net->dact[L + 1], net->act[L], net->part);
+  }
+  constexpr int nout = d.cout * 9 * d.cin + d.cout;
+  const int nrun = (splits + kRedRun - 1) / kRedRun;
+  hipLaunchKernelGGL((k_wgrad_reduce_runs<d.cin, d.cout, FIRST>), dim3((nout + 63) / 64, nrun),
+                     dim3(256), 0, st, net->part, splits, net->runs);
+  hipLaunchKernelGGL((k_wgrad_reduce_final<d.cin, d.cout>), dim3((nout + 255) / 256), dim3(256), 0, st,
+                     net->runs, nrun, net->G + w_off(L), net->G + b_off(L));
 }
 
 }  // namespace fsmi
@@ -1176,10 +1507,17 @@ fsmi_status fsmi_sur_backward(fsmi_sur net, const fsmi_map* map, int64_t n, cons
   const int grid = (int)std::min<int64_t>(n, 65535);
   hipLaunchKernelGGL(k_head_bwd, dim3(grid), dim3(256), 0, st, n, net->ypred, labels, net->stats,
                      net->P, net->hsave, net->act[5], net->dysave, net->dhsave, net->dact[5]);
-  const int nt = kHid * kFeat + kHid + 1;
-  hipLaunchKernelGGL(k_head_wgrad, dim3((nt + 255) / 256), dim3(256), 0, st, n, net->gsave,
-                     net->hsave, net->dysave, net->dhsave, net->ypred, labels, net->stats, net->G,
-                     loss ? loss : net->loss);
+  {
+    // chunks of a multiple of 64 poses, at most kHeadMaxChunks of them
+    const int64_t per = (n + kHeadMaxChunks - 1) / kHeadMaxChunks;
+    const int64_t chunk = std::max<int64_t>(64, (per + 63) / 64 * 64);
+    const int nchunk = (int)((n + chunk - 1) / chunk);
+    hipLaunchKernelGGL(k_head_wgrad_part, dim3(kHid / 32, nchunk), dim3(256), 0, st, n, chunk,
+                       net->gsave, net->hsave, net->dysave, net->dhsave, net->ypred, labels,
+                       net->stats, net->hpart);
+    hipLaunchKernelGGL(k_head_wgrad_final, dim3((kHeadOut + 255) / 256), dim3(256), 0, st, n, nchunk,
+                       net->hpart, net->G, loss ? loss : net->loss);
+  }
   conv_wgrad<4, false>(net, n, src);
   conv_dgrad<4>(net, n);
   conv_wgrad<3, false>(net, n, src);
