@@ -101,13 +101,27 @@ struct PatchSrc {
   }
 };
 
-// The patches of n poses as BF16 [n][128][128], the values at() returns.
+// The patches of n poses as BF16 [n][128][128], the values at() returns (src
+// reads the map: src.patch is NULL).  One thread per 8 consecutive pixels of a
+// patch row, stored as 16 bytes; the pose's block coordinates are taken once
+// per 8 pixels.
 __global__ void k_patch_gather(int64_t n, PatchSrc src, bf16* __restrict__ out) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n * kPatch * kPatch;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t b = i / (kPatch * kPatch);
-    const int r = (int)(i % (kPatch * kPatch));
-    out[i] = (bf16)src.at(b, r / kPatch, r % kPatch);
+  constexpr int U = kPatch / 8;   // units per patch row
+  for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < n * kPatch * U;
+       u += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = u / (kPatch * U);
+    const int r = (int)(u % (kPatch * U));
+    const int iy = r / U, ix0 = 8 * (r % U);
+    const int64_t cy = src.block(src.poses[4 * b + 1]) - kPatch / 2 + iy;
+    const int64_t cx0 = src.block(src.poses[4 * b]) - kPatch / 2 + ix0;
+    const bool row_in = cy >= 0 && cy < src.Y;
+    bf16x8 v;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int64_t cx = cx0 + q;
+      v[q] = (bf16)((row_in && cx >= 0 && cx < src.X) ? src.map[cx + src.X * cy] : 0.5f);
+    }
+    *reinterpret_cast<bf16x8*>(out + (b * kPatch + iy) * kPatch + ix0) = v;
   }
 }
 
@@ -126,80 +140,75 @@ __global__ void k_pool_map(const float* __restrict__ map, int64_t X, int64_t Y, 
   }
 }
 
-// ---------------------------------------------------------------------------
-// Forward convolution: out[p][co] = ReLU(b[co] + sum_{tap,ci} W[co][tap][ci] in[p+tap][ci])
-// One wave = 16 output pixels x all COUT channels; 4 waves per workgroup.
-// ---------------------------------------------------------------------------
-template <int CIN, int COUT, int HIN, bool FIRST>
-__global__ __launch_bounds__(256) void k_conv_fwd(int64_t npix, const bf16* __restrict__ in,
-                                                  PatchSrc src, const bf16* __restrict__ W,
-                                                  const float* __restrict__ bias,
-                                                  bf16* __restrict__ out) {
-  constexpr int HOUT = HIN / 2, NT = COUT / 16;
-  const int lane = threadIdx.x & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int64_t base = ((int64_t)blockIdx.x * 4 + wave) * 16;
-  if (base >= npix) return;
-  const int i = lane & 15, g = lane >> 4;
-  const int64_t p = base + i;
-  const int64_t b = p / (HOUT * HOUT);
-  const int oy = (int)((p / HOUT) % HOUT), ox = (int)(p % HOUT);
-  floatx4 acc[NT];
-#pragma unroll
-  for (int t = 0; t < NT; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
-  if constexpr (FIRST) {
-    // K = 9 taps padded to 32; lane group g holds taps 8g .. 8g+7
-    bf16x8 a = zero8();
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int tap = 8 * g + q;
-      if (tap < 9) a[q] = (bf16)src.at(b, 2 * oy + tap / 3 - 1, 2 * ox + tap % 3 - 1);
-    }
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      bf16x8 w = zero8();
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int tap = 8 * g + q;
-        if (tap < 9) w[q] = W[(16 * t + i) * 9 + tap];
-      }
-      acc[t] = mfma(a, w, acc[t]);
-    }
-  } else {
-#pragma unroll 1
-    for (int tap = 0; tap < 9; ++tap) {
-      const int iy = 2 * oy + tap / 3 - 1, ix = 2 * ox + tap % 3 - 1;
-      const bool ok = iy >= 0 && iy < HIN && ix >= 0 && ix < HIN;
-      // the address stays inside the image even where the tap is padding
-      const bf16* ip = in + ((b * HIN + (ok ? iy : 0)) * HIN + (ok ? ix : 0)) * CIN;
-#pragma unroll
-      for (int c0 = 0; c0 < CIN; c0 += 32) {
-        const bf16x8 a = ok ? load8(ip + c0 + 8 * g) : zero8();
-#pragma unroll
-        for (int t = 0; t < NT; ++t) {
-          const bf16x8 w = load8(W + ((16 * t + i) * 9 + tap) * CIN + c0 + 8 * g);
-          acc[t] = mfma(a, w, acc[t]);
-        }
-      }
-    }
-  }
-#pragma unroll
-  for (int t = 0; t < NT; ++t) {
-    const int co = 16 * t + i;
-    const float bv = bias[co];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int64_t pr = base + 4 * g + r;
-      const float v = acc[t][r] + bv;
-      out[pr * COUT + co] = (bf16)(v > 0.0f ? v : 0.0f);
-    }
-  }
-}
-
 // Two floats as packed BF16 (round to nearest even), low half first.
 FSMI_DEV uint32_t pack2(float a, float b) {
   const bf16 x = (bf16)a, y = (bf16)b;
   return (uint32_t)__builtin_bit_cast(uint16_t, x) | ((uint32_t)__builtin_bit_cast(uint16_t, y) << 16);
+}
+
+// ---------------------------------------------------------------------------
+// First convolution when its output is kept (training): out[p][co] =
+// ReLU(b[co] + sum over taps of W[co][tap] x[p, tap]), x[p, tap] the patch
+// pixel under the tap.  A workgroup takes R = 4 output rows of one pose and
+// stages the 2 R + 1 patch rows they read, with a zero column on each side, in
+// LDS.  Each wave computes 16-pixel tiles as W (the A operand; the 9 taps are
+// K, padded to 32 with zeros) times the tap values of the 16 pixels (the B
+// operand), so a lane ends with four consecutive channels of one pixel and
+// stores them as 8 bytes.  The grid is batch x HOUT / R workgroups.
+// ---------------------------------------------------------------------------
+template <int COUT, int HIN>
+__global__ __launch_bounds__(256) void k_conv1_fwd(PatchSrc src, const bf16* __restrict__ W,
+                                                   const float* __restrict__ bias,
+                                                   bf16* __restrict__ out) {
+  constexpr int HOUT = HIN / 2, R = 4, NT = COUT / 16, SROW = HIN + 2, NTILE = R * HOUT / 16;
+  static_assert(HOUT % R == 0 && (R * HOUT) % 16 == 0, "whole 16-pixel tiles per workgroup");
+  __shared__ bf16 sP[(2 * R + 1) * SROW];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int i = lane & 15, g = lane >> 4;
+  const int64_t tile = blockIdx.x;
+  const int64_t b = tile / (HOUT / R);
+  const int oy0 = (int)(tile % (HOUT / R)) * R;
+  // staged row r = patch row 2 oy0 - 1 + r; staged column cx = patch column cx - 1
+  for (int e = tid; e < (2 * R + 1) * SROW; e += 256) {
+    const int r = e / SROW, cx = e % SROW;
+    sP[e] = (bf16)src.at(b, 2 * oy0 - 1 + r, cx - 1);
+  }
+  bf16x8 wa[NT];
+  float bv[NT][4];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int tap = 8 * g + q;
+      wa[t][q] = tap < 9 ? W[(16 * t + i) * 9 + tap] : (bf16)0.0f;
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) bv[t][r] = bias[16 * t + 4 * g + r];
+  }
+  __syncthreads();
+#pragma unroll 1
+  for (int tt = wave; tt < NTILE; tt += 4) {
+    const int pl = 16 * tt + i, oyl = pl / HOUT, ox = pl % HOUT;
+    bf16x8 xb = zero8();
+    if (g < 2) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int tap = 8 * g + q;
+        if (tap < 9) xb[q] = sP[(2 * oyl + tap / 3) * SROW + 2 * ox + tap % 3];
+      }
+    }
+    bf16* op = out + (tile * (R * HOUT) + pl) * COUT;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      // D[4 g + r][i]: channel 16 t + 4 g + r of pixel i
+      const floatx4 d = mfma(wa[t], xb, floatx4{0.f, 0.f, 0.f, 0.f});
+      float v[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) v[r] = fmaxf(d[r] + bv[t][r], 0.0f);
+      *reinterpret_cast<uint2*>(op + 16 * t + 4 * g) = uint2{pack2(v[0], v[1]), pack2(v[2], v[3])};
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -515,7 +524,11 @@ __global__ __launch_bounds__(256) void k_conv12_fwd(int64_t n_tiles, PatchSrc sr
 //   (iy, ix) = (2 a + py, 2 c + px).  Products are taken transposed (weights
 //   as the A operand, Wt is [tap][ci][co]), so a lane ends with four
 //   consecutive channels of one pixel and loads and stores 8 bytes at once.
-//   nq = batch x (HIN / 2)^2 is a multiple of 16.
+//   The d_out pixels a tile reads, (b, a + dy, c + dx) with dy, dx in {0, 1},
+//   are the tile's own positions and the row after them: a contiguous range
+//   of d_out, staged once in LDS for the four waves (each reads it about 2.25
+//   times over).  nq = batch x (HIN / 2)^2 is a multiple of 16, and tiles
+//   start on row boundaries.
 // ---------------------------------------------------------------------------
 template <int CIN, int COUT, int HIN>
 constexpr int dgrad_mt() { return CIN >= 128 ? 2 : 4; }
@@ -526,12 +539,21 @@ __global__ __launch_bounds__(256) void k_conv_dgrad(int64_t nq, const bf16* __re
                                                     const bf16* __restrict__ act_in,
                                                     bf16* __restrict__ din) {
   constexpr int HOUT = HIN / 2, NT = CIN / 16, KC = COUT / 32, MT = dgrad_mt<CIN, COUT, HIN>();
-  const int lane = threadIdx.x & 63;
-  const int cls = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  constexpr int TQ = 16 * MT, ROWD = COUT + 8;   // positions per tile; LDS row (one d_out pixel)
+  static_assert(TQ % HOUT == 0, "tiles hold whole rows");
+  __shared__ __align__(16) bf16 sD[(TQ + HOUT) * ROWD];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int cls = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int py = cls >> 1, px = cls & 1;
-  const int64_t base = (int64_t)blockIdx.x * (16 * MT);
+  const int64_t base = (int64_t)blockIdx.x * TQ;
   const int n_mt = (int)min<int64_t>(MT, (nq - base) / 16);   // >= 1: the grid covers nq exactly
   const int i = lane & 15, g = lane >> 4;
+  for (int e = tid; e < (TQ + HOUT) * (COUT / 8); e += 256) {
+    const int px8 = e / (COUT / 8), c8 = e % (COUT / 8);
+    const int64_t q = base + px8;
+    *reinterpret_cast<bf16x8*>(sD + px8 * ROWD + 8 * c8) = q < nq ? load8(dout + q * COUT + 8 * c8) : zero8();
+  }
+  __syncthreads();
   int64_t qb[MT];
   int qa[MT], qc[MT];
 #pragma unroll
@@ -558,11 +580,12 @@ __global__ __launch_bounds__(256) void k_conv_dgrad(int64_t nq, const bf16* __re
       bf16x8 a[MT][KC];
 #pragma unroll
       for (int m = 0; m < MT; ++m) {
-        const int oy = qa[m] + dy, ox = qc[m] + dx;
-        const bool ok = m < n_mt && oy < HOUT && ox < HOUT;
-        const bf16* dp = dout + ((qb[m] * HOUT + (ok ? oy : 0)) * HOUT + (ok ? ox : 0)) * COUT;
+        // d_out pixel (b, a + dy, c + dx) = position q + dy HOUT + dx
+        const bool ok = m < n_mt && qa[m] + dy < HOUT && qc[m] + dx < HOUT;
+        const bf16* dp = sD + (ok ? 16 * m + i + dy * HOUT + dx : 0) * ROWD;
 #pragma unroll
-        for (int c = 0; c < KC; ++c) a[m][c] = ok ? load8(dp + 32 * c + 8 * g) : zero8();
+        for (int c = 0; c < KC; ++c)
+          a[m][c] = ok ? *reinterpret_cast<const bf16x8*>(dp + 32 * c + 8 * g) : zero8();
       }
 #pragma unroll
       for (int c = 0; c < KC; ++c)
@@ -1341,10 +1364,10 @@ static void conv_fwd(fsmi_sur net, int64_t nb, PatchSrc src) {
   constexpr LayerDims d = kL[L];
   const int64_t npix = nb * (d.hin / 2) * (d.hin / 2);
   if constexpr (FIRST) {
-    const int64_t blocks = (npix + 63) / 64;
-    hipLaunchKernelGGL((k_conv_fwd<d.cin, d.cout, d.hin, true>), dim3((unsigned)blocks), dim3(256),
-                       0, net->ctx->stream, npix, nullptr, src, net->Wbf + wbf_off(L),
-                       net->P + b_off(L), net->act[L + 1]);
+    static_assert(d.cin == 1, "the first convolution reads one channel");
+    hipLaunchKernelGGL((k_conv1_fwd<d.cout, d.hin>), dim3((unsigned)(nb * (d.hin / 2) / 4)), dim3(256),
+                       0, net->ctx->stream, src, net->Wbf + wbf_off(L), net->P + b_off(L),
+                       net->act[L + 1]);
   } else {
     constexpr int per_block = 4 * 16 * conv_mt<d.cin, d.cout, d.hin>();   // 4 waves
     const int64_t blocks = (npix + per_block - 1) / per_block;
@@ -1497,8 +1520,8 @@ fsmi_status fsmi_sur_backward(fsmi_sur net, const fsmi_map* map, int64_t n, cons
     if (e != hipSuccess) return FSMI_E_NOMEM;
   }
   {
-    const int64_t total = n * kPatch * kPatch;
-    const int grid = (int)std::min<int64_t>((total + 255) / 256, 8192);
+    const int64_t units = n * kPatch * (kPatch / 8);
+    const int grid = (int)std::min<int64_t>((units + 255) / 256, 8192);
     hipLaunchKernelGGL(k_patch_gather, dim3(grid), dim3(256), 0, net->ctx->stream, n, src, net->patch);
     src.patch = net->patch;
   }
