@@ -487,6 +487,27 @@ def surrogate_leg(ctx, F, W, t, timed, args):
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t1
     log(f"[bench] surrogate: labels {label_s:.1f} s, {args.sur_steps} steps {train_s:.1f} s")
+    # training throughput: backward + Adam steps of 1024 poses on a fresh net
+    tb = 1024
+    tnet = F.Surrogate(ctx, seed=5, max_batch=tb, patch_stride=args.sur_stride)
+    tnet.fit_label_stats(torch.cat([d[2] for d in train]))
+    g0, p0, mi0 = train[0]
+    sels = [torch.from_numpy(rng.choice(p0.shape[0], tb, replace=False)).to(g0.device)
+            for _ in range(13)]
+    batches = [(p0[s_].contiguous(), mi0[s_].contiguous()) for s_ in sels]
+    for pb, lb in batches[:3]:
+        tnet.backward(g0, pb, lb)
+        tnet.adam_step(1e-3)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for pb, lb in batches[3:]:
+        tnet.backward(g0, pb, lb)
+        tnet.adam_step(1e-3)
+    torch.cuda.synchronize()
+    step_s = (time.perf_counter() - t1) / (len(batches) - 3)
+    tnet.close()
+    log(f"[bench] surrogate training: {step_s * 1e3:.3f} ms per step of {tb} poses "
+        f"({tb / step_s:.0f} poses/s, {3 * tb * SUR_FLOP_PER_POSE / step_s / 1e12:.1f} TFLOP/s)")
     wl = W.grid_large(n_poses=args.sur_candidates)      # held out: not a training map
     g, p = t(wl["grid"]), t(wl["poses"])
     n = p.shape[0]
@@ -507,6 +528,10 @@ def surrogate_leg(ctx, F, W, t, timed, args):
         "forward_poses_per_s": n / fwd,
         "forward_tflops": n * SUR_FLOP_PER_POSE / fwd / 1e12,
         "forward_mfma_frac": n * SUR_FLOP_PER_POSE / fwd / 1e12 / BF16_PEAK_TFLOPS,
+        # one step = forward, backward (about twice the forward's products), Adam
+        "train_batch": tb, "train_ms_per_step": step_s * 1e3,
+        "train_poses_per_s": tb / step_s,
+        "train_tflops": 3 * tb * SUR_FLOP_PER_POSE / step_s / 1e12,
     }
     # accuracy: the mean over the held-out maps (the first is the timed map)
     for key in ("spearman", "recall_at_1pct", "regret", "random_1pct_regret"):

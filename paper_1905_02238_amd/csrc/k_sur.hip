@@ -641,7 +641,9 @@ __global__ __launch_bounds__(256) void k_conv_dgrad(int64_t nq, const bf16* __re
 template <int CIN, int COUT, int TPG>
 struct WgradTile {
   static constexpr int KS = 32;               // pixels per stage
-  static constexpr int ROW = KS + 8;          // LDS row: 80 bytes, 16 fragment rows in distinct banks
+  // LDS row: 72 bytes, so the rows 8 apart that one transposed write touches
+  // fall in different banks; fragments are then 8-byte aligned (two 8-byte reads)
+  static constexpr int ROW = KS + 4;
   static constexpr int NMT = COUT / 16, NCT = TPG * CIN / 16;
   static constexpr int MW = NMT / 2, NW = NCT / 2;
   static constexpr int UA = (KS / 4) * (COUT / 8);          // staging units of d_out
@@ -650,6 +652,12 @@ struct WgradTile {
   static constexpr int ROWS = COUT + TPG * CIN;
   static_assert(NMT % 2 == 0 && NCT % 2 == 0 && 9 % TPG == 0, "tile split");
 };
+
+// Eight BF16 from an 8-byte aligned LDS address.
+FSMI_DEV bf16x8 lds_frag8(const bf16* p) {
+  const uint2 lo = *reinterpret_cast<const uint2*>(p), hi = *reinterpret_cast<const uint2*>(p + 4);
+  return __builtin_bit_cast(bf16x8, uint4{lo.x, lo.y, hi.x, hi.y});
+}
 
 // Transpose four vectors of 8 BF16 channels (pixels 0..3): row k gets channel
 // k of the four pixels, as two dwords.
@@ -851,11 +859,10 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(int64_t npix_out, int chunk,
     bf16x8 fa[MW];
 #pragma unroll
     for (int mw = 0; mw < MW; ++mw)
-      fa[mw] = *reinterpret_cast<const bf16x8*>(sL + (16 * (wm * MW + mw) + i) * ROW + 8 * g);
+      fa[mw] = lds_frag8(sL + (16 * (wm * MW + mw) + i) * ROW + 8 * g);
 #pragma unroll
     for (int nw = 0; nw < NW; ++nw) {
-      const bf16x8 fb =
-          *reinterpret_cast<const bf16x8*>(sL + (COUT + 16 * (wn * NW + nw) + i) * ROW + 8 * g);
+      const bf16x8 fb = lds_frag8(sL + (COUT + 16 * (wn * NW + nw) + i) * ROW + 8 * g);
 #pragma unroll
       for (int mw = 0; mw < MW; ++mw) acc[mw][nw] = mfma(fa[mw], fb, acc[mw][nw]);
     }
