@@ -50,8 +50,8 @@ SLOTS_PER_PAIR = 14.5
 # 131088 KiB for 262144 KiB read, WRITE_SIZE 262144 KiB for 262144 KiB written).
 # They describe the kernel built from the sources hashed here; with any other
 # sources the bench reports traffic as null.
-TRAFFIC = {"fetch_kib": 1.45444e+07, "write_kib": 48795.8,
-           "fetch_scale": 262144.0 / 131088.1, "write_scale": 1.0,
+TRAFFIC = {"fetch_kib": 1.45467e+07, "write_kib": 48762.9,
+           "fetch_scale": 262144.0 / 131087.9, "write_scale": 1.0,
            "sources_sha256": "53041773b712e3ff6c7fea33ccdbf60dde38a1ffd75ac141451f34f47f03c507"}
 TRAFFIC_SOURCES = ("paper_1905_02238_amd/csrc/k_pose.hip", "paper_1905_02238_amd/csrc/beam_dev.h",
                    "paper_1905_02238_amd/csrc/ray_dev.h", "paper_1905_02238_amd/csrc/fsmi_dev.h",
@@ -106,6 +106,10 @@ def parse():
     ap.add_argument("--profile-surrogate", action="store_true",
                     help="for kernel traces: surrogate forward over 65 536 candidates (3 times) "
                          "and one fsmi_rank_poses, random-initialised weights, nothing else")
+    ap.add_argument("--profile-train", action="store_true",
+                    help="for kernel traces: 10 surrogate training steps (backward + Adam) of "
+                         "1024 poses on a rooms map, random-initialised weights and labels, "
+                         "nothing else")
     ap.add_argument("--profile-uneven", action="store_true",
                     help="for kernel traces: the 100k uneven beams through an autotuned, "
                          "graph-captured plan (5 launches), nothing else")
@@ -140,6 +144,23 @@ def main():
         torch.cuda.synchronize()
         ctx.fsmi_sync()
         log("[bench] surrogate profile done")
+        return
+    if args.profile_train:
+        occ, lab = W.room_grid(2048, W.SEED_BASE + 100, split_extent=160, unknown_frac=0.30)
+        g = t(occ)
+        p = t(W.poses_in_free_space_2d(lab, 8192, W.SEED_BASE + 100))
+        mi = t(np.random.default_rng(1).uniform(0.0, 50.0, 8192))
+        net = F.Surrogate(ctx, seed=3, max_batch=1024, patch_stride=args.sur_stride)
+        net.fit_label_stats(mi)
+        rng = np.random.default_rng(0)
+        for _ in range(10):
+            sel = torch.from_numpy(rng.choice(8192, 1024, replace=False)).to(dev)
+            net.backward(g, p[sel].contiguous(), mi[sel].contiguous())
+            net.adam_step(1e-3)
+        torch.cuda.synchronize()
+        ctx.fsmi_sync()
+        log("[bench] training profile done")
+        net.close()
         return
     if args.profile_uneven:
         off, occ, sg = W.uneven_beams(100000, seed=W.SEED_BASE + 3)
