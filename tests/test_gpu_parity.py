@@ -316,6 +316,57 @@ def test_poses_grid_large_sample(ctx, variant):
 
 
 @pytest.mark.parametrize("variant", [F.FSMI_EXACT, F.FSMI_APPROX, F.FSMI_UNIFORM])
+def test_poses_grid_large_timed_launch_sampled(ctx, variant):
+    """The timed 2D workload in the launch the benchmark times (2048 x 2048 rooms,
+    4096 poses x 360 beams in one fsmi_eval_poses call): three poses spread over
+    the batch against the oracle, beam by beam, and every pose's value against
+    the sum of its beams."""
+    print(f"[gpu] grid_large timed launch variant={variant}", flush=True)
+    wl = W.grid_large(n_poses=4096)
+    prm = F.params(variant=variant, trunc_delta=wl["Delta"], uniform_h=wl["H"])
+    mp, mb = ctx.fsmi_eval_poses(prm, dev(wl["grid"]), dev(wl["poses"]), dev(wl["beam_dir"]),
+                                 wl["sigma"], wl["R"], want_beams=True)
+    torch.cuda.synchronize()
+    ctx.fsmi_sync()
+    mp, mb = mp.cpu().numpy(), mb.cpu().numpy()
+    assert np.all(np.isfinite(mb))
+    assert np.allclose(mp, mb.sum(axis=1), rtol=1e-12, atol=0.0)
+    idx = [0, 2047, 4095]
+    rp, rb = O.eval_poses_2d(variant, wl["grid"], wl["poses"][idx], wl["beam_dir"], wl["sigma"],
+                             wl["R"], Delta=wl["Delta"], H=wl["H"])
+    assert rel_err(mb[idx], rb) <= TOL32
+    assert rel_err(mp[idx], rp) <= TOL32
+
+
+@pytest.mark.parametrize("variant", [F.FSMI_EXACT, F.FSMI_APPROX, F.FSMI_UNIFORM])
+def test_poses_voxels_large_timed_launch_sampled(ctx, variant):
+    """The 3D workload in the launch the benchmark times (512 x 512 x 128 voxels,
+    256 poses x 16 384 camera beams, R = 300, sigma = 2): every 32nd beam of the
+    first and last pose against the oracle, and every pose's value against the
+    sum of its beams."""
+    print(f"[gpu] voxels_large timed launch variant={variant}", flush=True)
+    vw = W.voxels_large(n_poses=256)
+    prm = F.params(variant=variant, trunc_delta=vw["Delta"], uniform_h=4)
+    mp, mb = ctx.fsmi_eval_poses(prm, dev(vw["vox"]), dev(vw["poses"]), dev(vw["beam_dir"]),
+                                 vw["sigma"], vw["R"], vw["w"], want_beams=True)
+    torch.cuda.synchronize()
+    ctx.fsmi_sync()
+    mp, mb = mp.cpu().numpy(), mb.cpu().numpy()
+    assert np.all(np.isfinite(mb))
+    assert np.allclose(mp, mb.sum(axis=1), rtol=1e-12, atol=0.0)
+    sel = np.arange(0, vw["beam_dir"].shape[0], 32)
+    for k in (0, 255):
+        if variant == F.FSMI_UNIFORM:
+            _, rb = O.eval_poses_3d(True, vw["vox"], vw["poses"][[k]], vw["beam_dir"][sel],
+                                    vw["sigma"], vw["R"], vw["w"], kind=O.K_UNIFORM, H=4)
+        else:
+            _, rb = O.eval_poses_3d(variant == F.FSMI_EXACT, vw["vox"], vw["poses"][[k]],
+                                    vw["beam_dir"][sel], vw["sigma"], vw["R"], vw["w"],
+                                    Delta=vw["Delta"])
+        assert rel_err(mb[k, sel], rb[0]) <= TOL32
+
+
+@pytest.mark.parametrize("variant", [F.FSMI_EXACT, F.FSMI_APPROX, F.FSMI_UNIFORM])
 def test_poses_voxels_small(ctx, variant):
     print(f"[gpu] voxels variant={variant}", flush=True)
     vox, lab = W.voxel_map(64, 64, 32, seed=9, n_boxes=12, n_pillars=8, block=16, unknown_frac=0.1)
