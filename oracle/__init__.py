@@ -38,6 +38,7 @@ def lib():
             "ora_rle_thm5": (d, [i, p, p, d, d, i, i, i]),
             "ora_rle_thm6": (d, [i, p, p, d, d, i, i, i]),
             "ora_rle_alpha_route": (d, [i, p, p, d, d]),
+            "ora_rle_table": (d, [i, p, p, d, d, i, i]),
             "ora_tab_definition": (None, [d, d, i, i, p, p, p, p]),
             "ora_tab_recurrence": (None, [d, d, i, i, p, p, p, p]),
             "ora_raycast2d": (i, [p, i64, i64, d, d, d, d, d, i, p, p, p]),
@@ -162,6 +163,13 @@ def rle_thm6(ro, L, sigma_p, Delta, kind=K_ERF, H=0, delta_occ=1.5):
 def rle_alpha_route(ro, L, sigma_p, delta_occ=1.5):
     ro, L = _runs(ro, L)
     return lib().ora_rle_alpha_route(len(ro), _pd(ro), _pd(L), float(sigma_p), float(delta_occ))
+
+
+def rle_table(ro, L, sigma_p, Delta, levels, delta_occ=1.5):
+    """Table mode of Approx-FSMI-RLE: tables at 1 - o quantised to i / levels."""
+    ro, L = _runs(ro, L)
+    return lib().ora_rle_table(len(ro), _pd(ro), _pd(L), float(sigma_p), float(delta_occ),
+                               int(Delta), int(levels))
 
 
 def tables(x, sigma_p, Lb, Lmax, route="definition"):

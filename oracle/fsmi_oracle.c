@@ -416,6 +416,103 @@ double ora_rle_alpha_route(int nr, const double* ro, const int* L, double sigma_
   return nval(&I) / (s2pi * sigma_p);
 }
 
+/* ---- table mode of Approx-FSMI-RLE (Alg 11 with the tables of Alg 9 and 10) ----
+   The tables hold the un-normalised Gaussian truncated at |a - b| <= Delta, Thm 6's
+   kernel: alpha_D[x,P,Q] = sum_{a<P} sum_{b<Q, |a-b|<=Delta} x^a g(a-b), beta_D adds a
+   factor b, g(d) = exp(-d^2 / (2 sigma'^2)).  A block cropped by Eqs. su'..Lv' and
+   shifted by t reads entries up to 2 Delta. */
+static double gauss_t(double sp, int Delta, int d) {
+  if (d > Delta || d < -Delta) return 0.0;
+  return exp(-((double)d * (double)d) / (2.0 * sp * sp));
+}
+static double alpha_trunc(double x, int P, int Q, double sp, int Delta) {
+  nsum s = {0.0, 0.0};
+  for (int a = 0; a < P; ++a)
+    for (int b = 0; b < Q; ++b) nadd(&s, pow(x, (double)a) * gauss_t(sp, Delta, a - b));
+  return nval(&s);
+}
+static double beta_trunc(double x, int P, int Q, double sp, int Delta) {
+  nsum s = {0.0, 0.0};
+  for (int a = 0; a < P; ++a)
+    for (int b = 0; b < Q; ++b) nadd(&s, (double)b * pow(x, (double)a) * gauss_t(sp, Delta, a - b));
+  return nval(&s);
+}
+
+/* Table mode: I = (I_{u=v} + I_{u<v} + I_{u>v}) / (sqrt(2 pi) sigma'), with every
+   table read at x_u quantised to the grid i / levels, i = floor(levels (1 - o_u) + 1/2);
+   P_E, D_E and the crop factor (1 - o_u)^(s'_u - s_u) use o itself.  Per pair, with
+   t = s'_u - s'_v of the cropped block:
+     t <= 0 (v after u):  A = alpha_D[L'_u, L'_v - t] - alpha_D[L'_u, -t],
+                          B = beta_D[L'_u, L'_v - t] - beta_D[L'_u, -t] + t A;
+     t >= 1 (v before u): A = x^{-t} (alpha_D[t + L'_u, L'_v] - alpha_D[t, L'_v]),
+                          B = x^{-t} (beta_D[t + L'_u, L'_v] - beta_D[t, L'_v]),
+   the second the algorithm's route whose cancellation Sec. 4.1 warns about.  At x = 0
+   (o within 1/(2 levels) of 1) x^{-t} has no value; the block is then its a = 0 row,
+   A = sum_{b<L'_v} g(t - b), B = sum_b b g(t - b).  theta[x, L] = alpha_D[L, L],
+   gamma[x, L] = beta_D[L, L].  On a grid o (x = x_q) the value is Thm 6's with the
+   density kernel. */
+double ora_rle_table(int nr, const double* ro, const int* L, double sigma_p, double delta_occ,
+                     int Delta, int levels) {
+  if (nr <= 0) return 0.0;
+  double delta_emp = 1.0 / delta_occ;
+  double* PE = (double*)malloc(sizeof(double) * nr);
+  double* DE = (double*)malloc(sizeof(double) * nr);
+  int* s = (int*)malloc(sizeof(int) * nr);
+  rle_prefix(nr, ro, L, delta_occ, PE, DE, s);
+  nsum I = {0.0, 0.0};
+  for (int u = 0; u < nr; ++u) {
+    const double x = 1.0 - ro[u];
+    const int iq = (int)floor(x * (double)levels + 0.5);
+    const double xq = (double)iq / (double)levels;
+    /* u = v */
+    double th = alpha_trunc(xq, L[u], L[u], sigma_p, Delta);
+    double ga = beta_trunc(xq, L[u], L[u], sigma_p, Delta);
+    nadd(&I, PE[u] * ro[u] * ((DE[u] + ora_f(delta_occ, ro[u])) * th + ora_f(delta_emp, ro[u]) * ga));
+    /* v after u */
+    for (int v = u + 1; v < nr; ++v) {
+      if (!(s[v] < s[u] + L[u] + Delta)) continue;
+      int su_p = s[u] > s[v] - Delta ? s[u] : s[v] - Delta;
+      int Lu_p = s[u] + L[u] - su_p;
+      int Lv_p = L[v] < s[u] + L[u] + Delta - s[v] ? L[v] : s[u] + L[u] + Delta - s[v];
+      int t = su_p - s[v];
+      double A = alpha_trunc(xq, Lu_p, Lv_p - t, sigma_p, Delta) - alpha_trunc(xq, Lu_p, -t, sigma_p, Delta);
+      double B = beta_trunc(xq, Lu_p, Lv_p - t, sigma_p, Delta) - beta_trunc(xq, Lu_p, -t, sigma_p, Delta) +
+                 (double)t * A;
+      double Pp = PE[u] * pow(x, (double)(su_p - s[u]));
+      nadd(&I, Pp * ro[u] * ((DE[v] + ora_f(delta_occ, ro[v])) * A + ora_f(delta_emp, ro[v]) * B));
+    }
+    /* v before u */
+    for (int v = 0; v < u; ++v) {
+      if (!(s[u] < s[v] + L[v] + Delta)) continue;
+      int Lu_p = L[u] < s[v] + L[v] + Delta - s[u] ? L[u] : s[v] + L[v] + Delta - s[u];
+      int sv_p = s[v] > s[u] - Delta ? s[v] : s[u] - Delta;
+      int Lv_p = s[v] + L[v] - sv_p;
+      int t = s[u] - sv_p;
+      double A, B;
+      if (iq == 0) {
+        nsum a = {0.0, 0.0}, b = {0.0, 0.0};
+        for (int k = 0; k < Lv_p; ++k) {
+          nadd(&a, gauss_t(sigma_p, Delta, t - k));
+          nadd(&b, (double)k * gauss_t(sigma_p, Delta, t - k));
+        }
+        A = nval(&a);
+        B = nval(&b);
+      } else {
+        double xt = pow(xq, (double)(-t));
+        A = xt * (alpha_trunc(xq, t + Lu_p, Lv_p, sigma_p, Delta) - alpha_trunc(xq, t, Lv_p, sigma_p, Delta));
+        B = xt * (beta_trunc(xq, t + Lu_p, Lv_p, sigma_p, Delta) - beta_trunc(xq, t, Lv_p, sigma_p, Delta));
+      }
+      double Dp = DE[v] + (double)(sv_p - s[v]) * ora_f(delta_emp, ro[v]);
+      nadd(&I, PE[u] * ro[u] * ((Dp + ora_f(delta_occ, ro[v])) * A + ora_f(delta_emp, ro[v]) * B));
+    }
+  }
+  free(PE);
+  free(DE);
+  free(s);
+  const double s2pi = 2.50662827463100050242;
+  return nval(&I) / (s2pi * sigma_p);
+}
+
 /* alpha, beta, theta, gamma straight from their definitions. */
 void ora_tab_definition(double x, double sp, int Lb, int Lmax, double* alpha, double* beta,
                         double* theta, double* gamma) {

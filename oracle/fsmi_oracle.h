@@ -56,6 +56,9 @@ double ora_rle_thm5(int nr, const double* ro, const int* L, double sigma_p, doub
 double ora_rle_thm6(int nr, const double* ro, const int* L, double sigma_p, double delta_occ,
                     int kind, int Delta, int H);
 double ora_rle_alpha_route(int nr, const double* ro, const int* L, double sigma_p, double delta_occ);
+/* table mode of Approx-FSMI-RLE: tables at x = 1 - o quantised to i / levels (see the .c) */
+double ora_rle_table(int nr, const double* ro, const int* L, double sigma_p, double delta_occ,
+                     int Delta, int levels);
 /* alpha/beta/theta/gamma by their definitions and by the (corrected) Alg 9/10 recurrences;
    arrays are [Lb+1][Lb+1] (alpha, beta) and [Lmax+1] (theta, gamma), index 0 unused */
 void ora_tab_definition(double x, double sigma_p, int Lb, int Lmax,

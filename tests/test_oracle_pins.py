@@ -388,6 +388,55 @@ def test_alpha_route_loses_digits_as_the_paper_warns():
     assert abs(a - b) > 1e-5 * b       # FP64 route off by ~3e-4 here
 
 
+# The table mode of Approx-FSMI-RLE (Alg 11 with the tables of Alg 9 and 10):
+# tables read at x = 1 - o quantised to i / levels.
+@pytest.mark.parametrize("Delta", [1, 3, 6])
+@pytest.mark.parametrize("seed", range(3))
+def test_table_mode_on_grid_equals_thm6(Delta, seed):
+    """With every o on the grid (x = i / 64 >= 1/4, so x^{-t} <= 4^Delta) the table
+    route is Thm 6 with the density kernel, itself pinned to the truncated
+    expanded beam."""
+    rng = np.random.default_rng(80 + seed)
+    ro, L = rng.integers(0, 49, 12) / 64.0, rng.integers(1, 9, 12)
+    a = O.rle_table(ro, L, 1.5, Delta, 64)
+    b = O.rle_thm6(ro, L, 1.5, Delta, O.K_DENSITY)
+    assert abs(a - b) <= 1e-14 * abs(b)
+
+
+def test_table_mode_full_occupancy_limit():
+    """o = 1 (x = 0): x^{-t} has no value and the block is its first row; the
+    value is still Thm 6's."""
+    for ro, L in ((np.array([0.25, 1.0, 0.5, 1.0, 0.0]), np.array([3, 2, 4, 1, 5])),
+                  (np.array([0.0, 0.25, 1.0]), np.array([2, 3, 4]))):
+        a = O.rle_table(ro, L, 1.2, 3, 64)
+        b = O.rle_thm6(ro, L, 1.2, 3, O.K_DENSITY)
+        assert abs(a - b) <= 1e-14 * abs(b)
+
+
+def test_table_mode_quantisation_error_falls_with_the_grid():
+    rng = np.random.default_rng(7)
+    ro, L = rng.uniform(0.05, 0.7, 15), rng.integers(1, 9, 15)
+    b = O.rle_thm6(ro, L, 1.5, 3, O.K_DENSITY)
+    err = [abs(O.rle_table(ro, L, 1.5, 3, lv) - b) / b for lv in (16, 64, 256, 1024)]
+    assert all(e1 < e0 for e0, e1 in zip(err, err[1:]))
+    assert err[0] > 1e-2 and err[-1] < 1e-3
+
+
+@pytest.mark.parametrize("Delta,bound", [(3, 1e-11), (6, 1e-5)])
+def test_table_mode_cancellation_grows_as_x_to_the_minus_delta(Delta, bound):
+    """Sec. 4.1's instability in FP64, with o on the grid so that no quantisation
+    error enters: x^{-t} (alpha - alpha) loses about log10(x^{-Delta}) digits."""
+    errs = []
+    for xi in (16, 4, 1):
+        ro = np.array([6, 64 - xi, 6, 64 - xi, 19, 64 - xi]) / 64.0
+        L = np.full(6, 6)
+        a = O.rle_table(ro, L, 1.0, Delta, 64)
+        b = O.rle_thm6(ro, L, 1.0, Delta, O.K_DENSITY)
+        errs.append(abs(a - b) / b)
+    assert errs[0] < errs[1] < errs[2] <= bound
+    assert errs[2] > 1e3 * errs[0] and errs[2] > 1e-13
+
+
 @pytest.mark.parametrize("x", [0.0, 0.3, 0.9])
 def test_table_recurrences_equal_definitions(x):
     a1, b1, t1, g1 = O.tables(x, 1.4, 6, 12, "definition")
