@@ -222,6 +222,29 @@ fsmi_status fsmi_rle_eval_beams(fsmi_ctx ctx, const fsmi_params* params, int64_t
                                 const int64_t* run_off, const float* run_occ,
                                 const int32_t* run_len, const float* sigma_prime, double* mi);
 
+/* ---- the paper's table route for Approx-FSMI-RLE (Alg 11 with the tables of
+   Alg 9 and 10), kept to compare against the run engine above ----
+   Same runs as fsmi_rle_eval_beams, one sigma_prime (> 0) for the batch.  The
+   alpha/beta/theta/gamma tables are built on the device for x = i / levels,
+   i = 0 .. levels, with the Gaussian exp(-d^2 / (2 sigma'^2)) truncated at
+   |d| <= Delta (params.trunc_delta); every table read takes x = 1 - o_u
+   rounded to that grid, i = floor(levels (1 - o_u) + 1/2), while P_E, D_E and
+   the crop factor (1 - o_u)^(s'_u - s_u) use o itself.  Blocks of a run u
+   with an earlier run v use x^{-t} (alpha[t + L'_u, L'_v] - alpha[t, L'_v]),
+   the route Sec. 4.1 calls unstable: with o on the grid the value is
+   Approx-FSMI-RLE's (density kernel) up to a cancellation that grows like
+   x^{-Delta}, about 1e-12 relative at x = 1/64, Delta = 3 and 1e-6 at
+   Delta = 6 in FP64.  Requires variant FSMI_APPROX, precision FSMI_FP64,
+   flags 0, sigma_slope 0, 0 <= trunc_delta <= 8, levels a power of two in
+   [1, 1024]; else FSMI_E_INVAL.  A beam of more than 1024 runs or a run
+   longer than 4096 cells latches FSMI_E_CAPACITY (result NaN); bad runs latch
+   as in fsmi_rle_eval_beams.  Uses the context's work area for the tables.
+   mi [n_beams] FP64, device. */
+fsmi_status fsmi_rle_table_eval_beams(fsmi_ctx ctx, const fsmi_params* params, int64_t n_beams,
+                                      const int64_t* run_off, const float* run_occ,
+                                      const int32_t* run_len, double sigma_prime,
+                                      int32_t levels, double* mi);
+
 /* ---- a12 + fused a1..a11: many poses x many beams ----
    2D map: poses [n_poses][4] = {x, y, cos(yaw), sin(yaw)}; beam_dir [n_beams][2]
    sensor-frame unit vectors.  World direction (c*bx - s*by, s*bx + c*by), each

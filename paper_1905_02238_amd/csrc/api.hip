@@ -329,6 +329,35 @@ fsmi_status fsmi_rle_eval_beams(fsmi_ctx ctx, const fsmi_params* params, int64_t
                   "rle_eval_beams");
 }
 
+fsmi_status fsmi_rle_table_eval_beams(fsmi_ctx ctx, const fsmi_params* params, int64_t n_beams,
+                                      const int64_t* run_off, const float* run_occ,
+                                      const int32_t* run_len, double sigma_prime,
+                                      int32_t levels, double* mi) {
+  if (!ctx) return FSMI_E_INVAL;
+  fsmi_status st;
+  if (!check_params(ctx, params, &st)) return st;
+  if (params->variant != FSMI_APPROX)
+    return fail(ctx, FSMI_E_INVAL, "the table route is Approx-FSMI-RLE: variant FSMI_APPROX");
+  if (params->precision != FSMI_FP64) return fail(ctx, FSMI_E_INVAL, "the table route runs in FP64");
+  if (params->flags != 0 || ext_mode(params))
+    return fail(ctx, FSMI_E_INVAL, "the table route takes no flags and no sigma_slope");
+  if (params->trunc_delta < 0 || params->trunc_delta > 8)
+    return fail(ctx, FSMI_E_INVAL, "the table route needs 0 <= trunc_delta <= 8");
+  if (levels < 1 || levels > 1024 || (levels & (levels - 1)) != 0)
+    return fail(ctx, FSMI_E_INVAL, "levels must be a power of two in [1, 1024]");
+  if (!(sigma_prime > 0.0) || !std::isfinite(sigma_prime))
+    return fail(ctx, FSMI_E_INVAL, "sigma_prime must be finite and > 0");
+  if (n_beams < 0) return fail(ctx, FSMI_E_INVAL, "n_beams < 0");
+  if (n_beams == 0) return FSMI_OK;
+  if (!run_off || !run_occ || !run_len || !mi)
+    return fail(ctx, FSMI_E_INVAL, "run_off, run_occ, run_len, mi are required");
+  (void)hipSetDevice(ctx->device);
+  return from_hip(ctx,
+                  launch_rle_table(ctx, params->delta_occ, params->trunc_delta, levels, sigma_prime,
+                                   n_beams, run_off, run_occ, run_len, mi),
+                  "rle_table_eval_beams");
+}
+
 fsmi_status fsmi_eval_poses(fsmi_ctx ctx, const fsmi_params* params, const fsmi_map* map,
                             int64_t n_poses, const double* poses, int64_t n_beams,
                             const double* beam_dir, double sigma, double max_range, double w,

@@ -36,6 +36,11 @@ struct EvalConst {
   double slope;      // sigma_j = sigma + slope mu_j (EXACT on explicit boundaries); 0 = one sigma
 };
 
+// The table route of Approx-FSMI-RLE (k_rle_table.hip), FP64.
+hipError_t launch_rle_table(fsmi_ctx ctx, double delta_occ, int Delta, int levels,
+                            double sigma_p, int64_t n_beams, const int64_t* run_off,
+                            const float* run_occ, const int32_t* run_len, double* mi);
+
 // Grow-only device scratch owned by the context.
 hipError_t ensure_work(fsmi_ctx ctx, size_t bytes);
 

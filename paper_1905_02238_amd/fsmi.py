@@ -30,7 +30,7 @@ FSMI_PEAK_COPY, FSMI_PEAK_FMA, FSMI_PEAK_PAIR, FSMI_PEAK_MFMA_BF16 = 0, 1, 2, 3
 
 EXPORTS = ("fsmi_create", "fsmi_destroy", "fsmi_set_stream", "fsmi_sync", "fsmi_last_error",
            "fsmi_status_string", "fsmi_default_params", "fsmi_raycast", "fsmi_eval_beams",
-           "fsmi_rle_eval_beams", "fsmi_eval_poses", "fsmi_probe_erfc", "fsmi_probe_f", "fsmi_probe_mfma", "fsmi_peak",
+           "fsmi_rle_eval_beams", "fsmi_rle_table_eval_beams", "fsmi_eval_poses", "fsmi_probe_erfc", "fsmi_probe_f", "fsmi_probe_mfma", "fsmi_peak",
            "fsmi_sur_num_params", "fsmi_sur_create", "fsmi_sur_destroy",
            "fsmi_sur_fit_label_stats", "fsmi_sur_get_label_stats", "fsmi_sur_forward",
            "fsmi_sur_backward", "fsmi_sur_adam_step", "fsmi_sur_get_params",
@@ -89,6 +89,7 @@ def load(path: str = LIB_PATH):
             L.fsmi_raycast.argtypes = [p, C.POINTER(fsmi_map), i32, i64, p, p, d, d, i32, p, p, p, p, p]
             L.fsmi_eval_beams.argtypes = [p, C.POINTER(fsmi_params), i64, p, p, p, p, p]
             L.fsmi_rle_eval_beams.argtypes = [p, C.POINTER(fsmi_params), i64, p, p, p, p, p]
+            L.fsmi_rle_table_eval_beams.argtypes = [p, C.POINTER(fsmi_params), i64, p, p, p, d, i32, p]
             L.fsmi_eval_poses.argtypes = [p, C.POINTER(fsmi_params), C.POINTER(fsmi_map), i64, p,
                                           i64, p, d, d, d, p, p]
             L.fsmi_probe_erfc.argtypes = [p, i64, p, p]
@@ -119,7 +120,8 @@ def load(path: str = LIB_PATH):
             L.fsmi_plan_destroy.argtypes = [p]
             L.fsmi_plan_destroy.restype = None
             for n in ("fsmi_create", "fsmi_set_stream", "fsmi_sync", "fsmi_raycast",
-                      "fsmi_eval_beams", "fsmi_rle_eval_beams", "fsmi_eval_poses",
+                      "fsmi_eval_beams", "fsmi_rle_eval_beams", "fsmi_rle_table_eval_beams",
+                      "fsmi_eval_poses",
                       "fsmi_probe_erfc", "fsmi_probe_f", "fsmi_probe_mfma", "fsmi_peak", "fsmi_sur_create",
                       "fsmi_sur_fit_label_stats", "fsmi_sur_get_label_stats", "fsmi_sur_forward",
                       "fsmi_sur_backward", "fsmi_sur_adam_step", "fsmi_sur_get_params",
@@ -251,6 +253,17 @@ class Context:
             self.handle, C.byref(prm), n, _ptr(run_off, torch.int64, "run_off"),
             _ptr(run_occ, torch.float32, "run_occ"), _ptr(run_len, torch.int32, "run_len"),
             _ptr(sigma_prime, torch.float32, "sigma_prime"), _ptr(mi, torch.float64, "mi")))
+        return mi
+
+    def fsmi_rle_table_eval_beams(self, prm: fsmi_params, run_off, run_occ, run_len, sigma_prime,
+                                  levels, mi=None):
+        n = run_off.shape[0] - 1
+        mi = torch.empty(n, dtype=torch.float64, device=run_occ.device) if mi is None else mi
+        self._stream()
+        self._check(self._lib.fsmi_rle_table_eval_beams(
+            self.handle, C.byref(prm), n, _ptr(run_off, torch.int64, "run_off"),
+            _ptr(run_occ, torch.float32, "run_occ"), _ptr(run_len, torch.int32, "run_len"),
+            float(sigma_prime), int(levels), _ptr(mi, torch.float64, "mi")))
         return mi
 
     def fsmi_eval_poses(self, prm: fsmi_params, map_occ, poses, beam_dir, sigma, max_range, w=1.0,

@@ -285,6 +285,92 @@ def test_rle_eval_beams_parity(ctx, exact, kernel):
 
 
 # ---------------------------------------------------------------------------
+# The paper's table route for Approx-FSMI-RLE (Alg 11, tables of Alg 9 and 10).
+def _grid_runs(seed, n_beams, levels, i_lo, i_hi, run_hi=12, runs_hi=40):
+    """Beams of runs whose o = i / levels lies on the table grid."""
+    rng = np.random.default_rng(seed)
+    nr = rng.integers(0, runs_hi + 1, n_beams)
+    off = np.concatenate([[0], np.cumsum(nr)]).astype(np.int64)
+    ro = (rng.integers(i_lo, i_hi + 1, off[-1]) / levels).astype(np.float32)
+    rl = rng.integers(1, run_hi + 1, off[-1]).astype(np.int32)
+    return off, ro, rl
+
+
+def _oracle_table(off, ro, rl, sigma_p, Delta, levels):
+    return np.array([O.rle_table(ro[off[b]:off[b + 1]], rl[off[b]:off[b + 1]], sigma_p, Delta, levels)
+                     for b in range(len(off) - 1)])
+
+
+@pytest.mark.parametrize("Delta", [1, 3, 6])
+def test_rle_table_route_on_grid(ctx, Delta):
+    """o on the grid with x = 1 - o >= 1/4: x^{-t} <= 4^Delta, so FP64 keeps
+    about 12 digits; the oracle's table route and Thm 6 (density kernel) agree."""
+    print(f"[gpu] rle table route Delta={Delta}", flush=True)
+    levels, sp = 64, 1.5
+    off, ro, rl = _grid_runs(70 + Delta, 80, levels, 0, 48)
+    prm = F.params(variant=F.FSMI_APPROX, trunc_delta=Delta, precision=F.FSMI_FP64)
+    mi = ctx.fsmi_rle_table_eval_beams(prm, dev(off), dev(ro), dev(rl), sp, levels)
+    torch.cuda.synchronize()
+    ctx.fsmi_sync()
+    got = mi.cpu().numpy()
+    ref = _oracle_table(off, ro, rl, sp, Delta, levels)
+    thm6 = np.array([O.rle_thm6(ro[off[b]:off[b + 1]], rl[off[b]:off[b + 1]], sp, Delta, O.K_DENSITY)
+                     for b in range(len(off) - 1)])
+    assert rel_err(got, ref) <= 1e-11
+    assert rel_err(got, thm6) <= 1e-11
+
+
+def test_rle_table_route_any_occupancy(ctx):
+    """o anywhere in [0, 1] (exact 0 and 1 included), off the grid: the table
+    reads and the o = 1 rows follow the oracle's table route.  Here x >= 1/64
+    and Delta = 3, so the cancellation can amplify a rounding difference by up
+    to 64^3; the bar is 2^-52 times that."""
+    print("[gpu] rle table route, any occupancy", flush=True)
+    levels, sp, Delta = 64, 1.2, 3
+    rng = np.random.default_rng(91)
+    nr = rng.integers(0, 30, 60)
+    off = np.concatenate([[0], np.cumsum(nr)]).astype(np.int64)
+    ro = rng.uniform(0.0, 1.0, off[-1]).astype(np.float32)
+    ro[rng.random(off[-1]) < 0.1] = 1.0
+    ro[rng.random(off[-1]) < 0.1] = 0.0
+    rl = rng.integers(1, 10, off[-1]).astype(np.int32)
+    prm = F.params(variant=F.FSMI_APPROX, trunc_delta=Delta, precision=F.FSMI_FP64)
+    mi = ctx.fsmi_rle_table_eval_beams(prm, dev(off), dev(ro), dev(rl), sp, levels)
+    torch.cuda.synchronize()
+    ctx.fsmi_sync()
+    ref = _oracle_table(off, ro, rl, sp, Delta, levels)
+    assert rel_err(mi.cpu().numpy(), ref) <= 2.0 ** -52 * 64.0 ** 3
+
+
+def test_rle_table_route_rejects_and_latches(ctx):
+    off = dev(np.array([0, 2], np.int64))
+    ro = dev(np.array([0.2, 0.3], np.float32))
+    rl = dev(np.array([2, 3], np.int32))
+    ok = F.params(variant=F.FSMI_APPROX, trunc_delta=3, precision=F.FSMI_FP64)
+    for prm, levels, sp in ((F.params(variant=F.FSMI_APPROX, trunc_delta=3), 64, 1.0),   # FP32
+                            (F.params(variant=F.FSMI_EXACT, precision=F.FSMI_FP64), 64, 1.0),
+                            (F.params(variant=F.FSMI_APPROX, trunc_delta=9, precision=F.FSMI_FP64), 64, 1.0),
+                            (ok, 48, 1.0), (ok, 2048, 1.0), (ok, 64, 0.0)):
+        with pytest.raises(F.FsmiError) as e:
+            ctx.fsmi_rle_table_eval_beams(prm, off, ro, rl, sp, levels)
+        assert e.value.status == F.FSMI_E_INVAL
+    # more runs in a beam than the kernel holds, and a run longer than the tables
+    off2 = np.array([0, 1025, 1026, 1027], np.int64)
+    ro2 = np.full(1027, 0.3, np.float32)
+    rl2 = np.ones(1027, np.int32)
+    rl2[1026] = 5000
+    mi = ctx.fsmi_rle_table_eval_beams(ok, dev(off2), dev(ro2), dev(rl2), 1.0, 64)
+    torch.cuda.synchronize()
+    with pytest.raises(F.FsmiError) as e:
+        ctx.fsmi_sync()
+    assert e.value.status == F.FSMI_E_CAPACITY
+    got = mi.cpu().numpy()
+    assert np.isnan(got[0]) and np.isfinite(got[1]) and np.isnan(got[2])
+    assert abs(got[1] - O.rle_table(ro2[1025:1026], rl2[1025:1026], 1.0, 3, 64)) <= 1e-12 * got[1]
+    ctx.fsmi_sync()   # cleared
+
+
+# ---------------------------------------------------------------------------
 @pytest.mark.parametrize("prec,tol", [(F.FSMI_FP64, TOL64), (F.FSMI_FP32, TOL32)])
 def test_poses_grid_small_full(ctx, prec, tol):
     """200 x 200 rooms, pose on a cell vertex at the centre, 60 beams, R = 150, sigma = 2."""
