@@ -375,6 +375,7 @@ def main():
             gpu[name] = ctx.fsmi_eval_poses(p, vx, vp, vb, vw["sigma"], vw["R"], vw["w"],
                                             want_beams=True)
             log(f"[bench] {name}: {nv/dt/1e6:.2f} M beams/s")
+        extras["rle_table_crossover"] = table_route_leg(ctx, F, W, t, timed)
         extras["surrogate_rank"] = surrogate_leg(ctx, F, W, t, timed, args)
         extras["surrogate_rank"]["forward_frac_of_measured_mfma"] = (
             extras["surrogate_rank"]["forward_tflops"] / ceil["bf16_mfma_TFLOPs"])
@@ -475,6 +476,54 @@ def oracle_leg(out, gpu, wl, W, args, ctx, F, t):
     out["error_report"] = rep
     worst = max(v["max_rel"] / v["bar"] for v in rep.values())
     log(f"[bench] error report: {len(rep)} workloads, worst max_rel / bar = {worst:.3f}")
+
+
+def table_route_leg(ctx, F, W, t, timed):
+    """The paper's run-length experiment (Sec. 5.4) on the GPU: beams of 256
+    cells in groups of L, one random o per group.  The table route
+    (fsmi_rle_table_eval_beams: Approx-FSMI-RLE by Alg 11, Delta = 3, a grid of
+    64 levels, FP64) runs on the runs, and Approx-FSMI (Delta = 3) on the
+    expanded cells (fsmi_eval_beams, FP64 and FP32).  The table route's error
+    is taken against the run engine's Approx-FSMI-RLE with the same (density)
+    kernel in FP64, on these random o and on o moved to the grid (where only
+    the cancellation of x^{-t} (alpha - alpha) is left)."""
+    nb, n, Delta, levels, sp = 65536, 256, 3, 64, 1.0
+    p_tab = F.params(variant=F.FSMI_APPROX, trunc_delta=Delta, precision=F.FSMI_FP64)
+    p_run = F.params(variant=F.FSMI_APPROX, trunc_delta=Delta, kernel=F.FSMI_KERNEL_DENSITY,
+                     precision=F.FSMI_FP64)
+    p64 = F.params(variant=F.FSMI_APPROX, trunc_delta=Delta, precision=F.FSMI_FP64)
+    p32 = F.params(variant=F.FSMI_APPROX, trunc_delta=Delta)
+    out = {"beams": nb, "cells": n, "Delta": Delta, "levels": levels, "sigma_prime": sp, "by_L": {}}
+    import torch
+    for L in (1, 2, 4, 8, 16, 32, 64, 128):
+        run_off, ro, rl, off, occ = W.grouped_beams(nb, n, L, seed=W.SEED_BASE + 5 + L)
+        d_ro, d_rl, d_roff = t(ro), t(rl), t(run_off)
+        d_off, d_occ = t(off), t(occ)
+        sig = t(np.full(nb, sp, np.float32))
+        tab = timed(lambda: ctx.fsmi_rle_table_eval_beams(p_tab, d_roff, d_ro, d_rl, sp, levels))
+        pl64 = timed(lambda: ctx.fsmi_eval_beams(p64, d_off, d_occ, sig))
+        pl32 = timed(lambda: ctx.fsmi_eval_beams(p32, d_off, d_occ, sig))
+        errs = {}
+        for name, occs in (("random_o", ro), ("grid_o", (np.floor(ro * levels + 0.5) / levels).astype(np.float32))):
+            d_o = t(occs)
+            a = ctx.fsmi_rle_table_eval_beams(p_tab, d_roff, d_o, d_rl, sp, levels).cpu().numpy()
+            b = ctx.fsmi_rle_eval_beams(p_run, d_roff, d_o, d_rl, sig).cpu().numpy()
+            nz = b != 0.0
+            errs[name] = float(np.max(np.abs(a[nz] - b[nz]) / np.abs(b[nz])))
+        torch.cuda.synchronize()
+        ctx.fsmi_sync()
+        out["by_L"][L] = {"table_us_per_beam": tab / nb * 1e6, "plain_fp64_us_per_beam": pl64 / nb * 1e6,
+                          "plain_fp32_us_per_beam": pl32 / nb * 1e6, "plain_fp64_over_table": pl64 / tab,
+                          "table_max_rel_err_random_o": errs["random_o"],
+                          "table_max_rel_err_grid_o": errs["grid_o"]}
+    log("[bench] table route (runs) vs Approx-FSMI (cells), 256-cell beams in groups of L, "
+        "ns per beam and plain-FP64 / table: "
+        + " ".join(f"L={L}: {v['table_us_per_beam']*1e3:.0f}/{v['plain_fp64_us_per_beam']*1e3:.0f} "
+                   f"(x{v['plain_fp64_over_table']:.2f})" for L, v in out["by_L"].items()))
+    log("[bench] table route max rel err vs the run engine (random o / o on the grid): "
+        + " ".join(f"L={L}: {v['table_max_rel_err_random_o']:.1e}/{v['table_max_rel_err_grid_o']:.1e}"
+                   for L, v in out["by_L"].items()))
+    return out
 
 
 def surrogate_leg(ctx, F, W, t, timed, args):

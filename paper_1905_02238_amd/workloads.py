@@ -264,6 +264,22 @@ def rle_beams(n_beams: int, seed: int, run_lo: int, run_hi: int, n_runs_lo: int,
     return off, occ, ln, sig
 
 
+def grouped_beams(n_beams: int, n_cells: int, L: int, seed: int):
+    """Beams of n_cells equal-width cells in groups of L with one occupancy per
+    group, o ~ U(0, 1) (the synthetic beams of the paper's run-length
+    experiment, Sec. 5.4).  Returns the runs (run_off int64, run_occ float32,
+    run_len int32) and the same beams expanded (off int64, occ float32)."""
+    assert n_cells % L == 0
+    rng = np.random.default_rng(seed)
+    nr = n_cells // L
+    run_off = np.arange(n_beams + 1, dtype=np.int64) * nr
+    run_occ = rng.uniform(0.0, 1.0, n_beams * nr).astype(np.float32)
+    run_len = np.full(n_beams * nr, L, np.int32)
+    off = np.arange(n_beams + 1, dtype=np.int64) * n_cells
+    occ = np.repeat(run_occ, L)
+    return run_off, run_occ, run_len, off, occ
+
+
 # ---------------------------------------------------------------------------
 # The workloads by name
 # ---------------------------------------------------------------------------

@@ -83,3 +83,10 @@ def test_generators_are_deterministic():
     g1, _ = W.room_grid(128, 9, split_extent=60, unknown_frac=0.1)
     g2, _ = W.room_grid(128, 9, split_extent=60, unknown_frac=0.1)
     assert np.array_equal(g1, g2)
+
+
+def test_grouped_beams_structure():
+    run_off, ro, rl, off, occ = W.grouped_beams(5, 256, 8, seed=3)
+    assert run_off.tolist() == [32 * b for b in range(6)] and off[-1] == 5 * 256
+    assert np.all(rl == 8) and ro.dtype == np.float32 and rl.dtype == np.int32
+    assert np.array_equal(occ, np.repeat(ro, 8)) and np.all((ro >= 0) & (ro <= 1))
