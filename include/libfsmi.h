@@ -238,7 +238,8 @@ fsmi_status fsmi_rle_eval_beams(fsmi_ctx ctx, const fsmi_params* params, int64_t
    flags 0, sigma_slope 0, 0 <= trunc_delta <= 8, levels a power of two in
    [1, 1024]; else FSMI_E_INVAL.  A beam of more than 1024 runs or a run
    longer than 4096 cells latches FSMI_E_CAPACITY (result NaN); bad runs latch
-   as in fsmi_rle_eval_beams.  Uses the context's work area for the tables.
+   as in fsmi_rle_eval_beams.  Uses the context's work area for the tables,
+   and waits for the stream once to size them by the batch's longest run.
    mi [n_beams] FP64, device. */
 fsmi_status fsmi_rle_table_eval_beams(fsmi_ctx ctx, const fsmi_params* params, int64_t n_beams,
                                       const int64_t* run_off, const float* run_occ,

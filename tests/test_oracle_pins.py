@@ -422,6 +422,22 @@ def test_table_mode_quantisation_error_falls_with_the_grid():
     assert err[0] > 1e-2 and err[-1] < 1e-3
 
 
+def test_table_mode_runs_of_one_carry_no_quantisation_error():
+    """With every run one cell long, a block's table difference is a single row
+    x^t g(...), which x^{-t} cancels exactly: off-grid o gives Thm 6's value up
+    to the cancellation (x >= 1/64, Delta = 3: at most 64^3 ulps)."""
+    rng = np.random.default_rng(12)
+    ro = rng.uniform(0.0, 0.99, 40)
+    L = np.ones(40, int)
+    a = O.rle_table(ro, L, 1.0, 3, 64)
+    b = O.rle_thm6(ro, L, 1.0, 3, O.K_DENSITY)
+    assert abs(a - b) <= 2.0 ** -52 * 64.0 ** 3 * b
+    ro2, L2 = ro[:20], np.full(20, 3)            # runs of 3: the grid shows
+    c = O.rle_table(ro2, L2, 1.0, 3, 64)
+    d = O.rle_thm6(ro2, L2, 1.0, 3, O.K_DENSITY)
+    assert abs(c - d) > 1e-6 * d
+
+
 @pytest.mark.parametrize("Delta,bound", [(3, 1e-11), (6, 1e-5)])
 def test_table_mode_cancellation_grows_as_x_to_the_minus_delta(Delta, bound):
     """Sec. 4.1's instability in FP64, with o on the grid so that no quantisation
