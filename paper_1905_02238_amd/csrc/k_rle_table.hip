@@ -308,7 +308,10 @@ hipError_t launch_rle_table(fsmi_ctx ctx, double delta_occ, int Delta, int level
   a.levels = levels;
   a.max_run = max_run;
   a.status = ctx->d_status;
-  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(n_beams, (int64_t)ctx->num_cu * 8));
+  // one-wave workgroups: 3 per SIMD fit the registers; the 1024-run kernel's
+  // 45 KB of LDS allows 3 per CU
+  const int per_cu = small ? 12 : 3;
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(n_beams, (int64_t)ctx->num_cu * per_cu));
   if (small)
     hipLaunchKernelGGL(k_rle_table<256>, dim3(grid), dim3(kWave), 0, st, a);
   else
