@@ -393,13 +393,15 @@ FSMI_DEV double row_approx_bound(const double* sL, const T* sC, int n, int j, in
 
 // Unit cells: G_{k,j} = g(|k-j|), g from the per-beam table sG[0..n-1].
 // The weight table of equal-width cells, seen from row j: w(k) = g(|k - j|).
-// FP32 keeps the table mirrored (g(|d|) at n - 1 + d, d = -(n-1)..n-1), so a
+// FP32 keeps the table mirrored (g(|d|) at off + d, d = -(n-1)..n-1), so a
 // row reads consecutive addresses and an unrolled block needs no index
-// arithmetic; FP64 keeps g(d), d = 0..n-1 (a mirror would not fit its LDS).
+// arithmetic; off >= n - 1 puts sG + off on a 16-byte boundary
+// (unit_origin).  FP64 keeps g(d), d = 0..n-1 (a mirror would not fit its
+// LDS).
 template <typename T> struct UnitRow;
 template <> struct UnitRow<float> {
   const float* base;
-  FSMI_DEV UnitRow(const float* sG, int n, int j) : base(sG + (n - 1 - j)) {}
+  FSMI_DEV UnitRow(const float* sG, int off, int j) : base(sG + (off - j)) {}
   FSMI_DEV float operator()(int k) const { return base[k]; }
 };
 template <> struct UnitRow<double> {
@@ -409,10 +411,17 @@ template <> struct UnitRow<double> {
   FSMI_DEV double operator()(int k) const { return g[abs(k - j)]; }
 };
 
+// The mirror's origin: the least off >= n - 1 with sG + off 16-byte aligned
+// (sG is at least 4-byte aligned).
+FSMI_DEV int unit_origin(const float* sG, int n) {
+  const int mis = (int)((reinterpret_cast<uintptr_t>(sG) >> 2) + (uintptr_t)(n - 1)) & 3;
+  return n - 1 + ((4 - mis) & 3);
+}
+
 // Eight pairs per compensated add, as on explicit boundaries.
 template <typename T>
-FSMI_DEV double row_exact_unit(const T* sG, const T* sC, int n, int j) {
-  const UnitRow<T> w(sG, n, j);
+FSMI_DEV double row_exact_unit(const T* sG, const T* sC, int off, int n, int j) {
+  const UnitRow<T> w(sG, off, j);
   Acc<T> acc;
   int k = 1;
   for (; k + 7 <= n; k += 8) {
@@ -425,9 +434,59 @@ FSMI_DEV double row_exact_unit(const T* sG, const T* sC, int n, int j) {
   return acc.value();
 }
 
+// Rows j0 .. j0 + 3 of the FP32 unit-cell sum at once (j0 = 4 b + 1): row
+// j0 + r reads its weight at column k from B[k - r], B = sG + off - j0, so one
+// register window of B slides along k for the four rows.  Per 8 columns a lane
+// loads 8 new weights (two 16-byte reads; B + k is aligned for k = 1 mod 8 by
+// the mirror's origin) and the 8 C_k, for 32 pairs, where one row per lane
+// reads a weight and a C_k per pair.  Each row's arithmetic is
+// row_exact_unit's.
+FSMI_DEV void rows4_exact_unit(const float* sG, const float* sC, int off, int n, int j0,
+                               double (&out)[4]) {
+  const float* B = sG + (off - j0);
+  Acc<float> acc[4];
+  float w[11];   // w[i] = B[k - 3 + i] at the chunk start k
+  w[0] = B[-2];
+  w[1] = B[-1];
+  w[2] = B[0];
+  int k = 1;
+  for (; k + 7 <= n; k += 8) {
+    const float4 lo = *reinterpret_cast<const float4*>(B + k);
+    const float4 hi = *reinterpret_cast<const float4*>(B + k + 4);
+    w[3] = lo.x;
+    w[4] = lo.y;
+    w[5] = lo.z;
+    w[6] = lo.w;
+    w[7] = hi.x;
+    w[8] = hi.y;
+    w[9] = hi.z;
+    w[10] = hi.w;
+    float c[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) c[q] = sC[k - 1 + q];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      float p = c[0] * w[3 - r];
+#pragma unroll
+      for (int q = 1; q < 8; ++q) p = fma(c[q], w[3 + q - r], p);
+      acc[r].add(p);
+    }
+    w[0] = w[8];
+    w[1] = w[9];
+    w[2] = w[10];
+  }
+  for (; k <= n; ++k) {
+    const float c = sC[k - 1];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[r].add(c * B[k - r]);
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) out[r] = acc[r].value();
+}
+
 template <typename T>
-FSMI_DEV double row_approx_unit(const T* sG, const T* sC, int n, int j, int D) {
-  const UnitRow<T> w(sG, n, j);
+FSMI_DEV double row_approx_unit(const T* sG, const T* sC, int off, int n, int j, int D) {
+  const UnitRow<T> w(sG, off, j);
   Acc<T> acc;
   const int k0 = max(1, j - D), k1 = min(n, j + D);
   for (int b = k0; b <= k1; b += 8) {
@@ -536,6 +595,8 @@ FSMI_DEV double beam_core(const EvalConst& ec, int n, const float* so, bool has_
     // g(d) = Phi((d+1/2)/sigma) - Phi((d-1/2)/sigma), d = 0..n-1; FP32 also
     // stores the mirror image (UnitRow), in the 2(n+1) floats of A
     T* sG = reinterpret_cast<T*>(sA);
+    int off = 0;
+    if constexpr (sizeof(T) == 4) off = unit_origin(sG, n);
     for (int d = tid; d < n; d += G) {
       T g;
       if (ec.kernel == FSMI_KERNEL_DENSITY) {
@@ -548,8 +609,8 @@ FSMI_DEV double beam_core(const EvalConst& ec, int n, const float* so, bool has_
         g = T(0.5) * (erfc_pos((T)((d - 0.5) * c)) - erfc_pos((T)((d + 0.5) * c)));
       }
       if constexpr (sizeof(T) == 4) {
-        sG[n - 1 + d] = g;
-        sG[n - 1 - d] = g;
+        sG[off + d] = g;
+        sG[off - d] = g;
       } else {
         sG[d] = g;
       }
@@ -593,11 +654,26 @@ FSMI_DEV double beam_core(const EvalConst& ec, int n, const float* so, bool has_
       }
     } else {
       const T* sG = reinterpret_cast<const T*>(sA);
+      int off = 0;
+      if constexpr (sizeof(T) == 4) off = unit_origin(sG, n);
+      int j1 = 1;   // rows below j1 are done in blocks of four
+      if constexpr (sizeof(T) == 4) {
+        const int nb4 = n / 4;
+        if (ec.variant == FSMI_EXACT && nb4 >= G / 2) {   // enough blocks for the group
+          for (int b = tid; b < nb4; b += G) {
+            double rv[4];
+            rows4_exact_unit(sG, sC, off, n, 4 * b + 1, rv);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) tot += (double)sP[4 * b + r] * rv[r];
+          }
+          j1 = 4 * nb4 + 1;
+        }
+      }
       if (ec.variant == FSMI_EXACT) {
-        for (int j = tid + 1; j <= n; j += G) tot += (double)sP[j - 1] * row_exact_unit<T>(sG, sC, n, j);
+        for (int j = j1 + tid; j <= n; j += G) tot += (double)sP[j - 1] * row_exact_unit<T>(sG, sC, off, n, j);
       } else {
         for (int j = tid + 1; j <= n; j += G)
-          tot += (double)sP[j - 1] * row_approx_unit<T>(sG, sC, n, j, ec.Delta);
+          tot += (double)sP[j - 1] * row_approx_unit<T>(sG, sC, off, n, j, ec.Delta);
       }
     }
   }
