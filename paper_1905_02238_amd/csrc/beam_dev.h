@@ -439,12 +439,13 @@ FSMI_DEV double row_exact_unit(const T* sG, const T* sC, int off, int n, int j) 
 // register window of B slides along k for the four rows.  Per 8 columns a lane
 // loads 8 new weights (two 16-byte reads; B + k is aligned for k = 1 mod 8 by
 // the mirror's origin) and the 8 C_k, for 32 pairs, where one row per lane
-// reads a weight and a C_k per pair.  Each row's arithmetic is
-// row_exact_unit's.
+// reads a weight and a C_k per pair.  Each row sums chunks of eight FMAs as
+// row_exact_unit does, and adds the chunk sums in FP64 (a conversion and an
+// add, where the FP32 compensated add takes four operations).
 FSMI_DEV void rows4_exact_unit(const float* sG, const float* sC, int off, int n, int j0,
                                double (&out)[4]) {
   const float* B = sG + (off - j0);
-  Acc<float> acc[4];
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
   float w[11];   // w[i] = B[k - 3 + i] at the chunk start k
   w[0] = B[-2];
   w[1] = B[-1];
@@ -469,7 +470,7 @@ FSMI_DEV void rows4_exact_unit(const float* sG, const float* sC, int off, int n,
       float p = c[0] * w[3 - r];
 #pragma unroll
       for (int q = 1; q < 8; ++q) p = fma(c[q], w[3 + q - r], p);
-      acc[r].add(p);
+      acc[r] += (double)p;
     }
     w[0] = w[8];
     w[1] = w[9];
@@ -478,10 +479,10 @@ FSMI_DEV void rows4_exact_unit(const float* sG, const float* sC, int off, int n,
   for (; k <= n; ++k) {
     const float c = sC[k - 1];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) acc[r].add(c * B[k - r]);
+    for (int r = 0; r < 4; ++r) acc[r] += (double)(c * B[k - r]);
   }
 #pragma unroll
-  for (int r = 0; r < 4; ++r) out[r] = acc[r].value();
+  for (int r = 0; r < 4; ++r) out[r] = acc[r];
 }
 
 template <typename T>
