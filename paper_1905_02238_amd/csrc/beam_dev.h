@@ -442,16 +442,18 @@ FSMI_DEV double row_exact_unit(const T* sG, const T* sC, int off, int n, int j) 
 // reads a weight and a C_k per pair.  Each row sums chunks of eight FMAs as
 // row_exact_unit does, and adds the chunk sums in FP64 (a conversion and an
 // add, where the FP32 compensated add takes four operations).
-FSMI_DEV void rows4_exact_unit(const float* sG, const float* sC, int off, int n, int j0,
+// Columns k0 .. k1 only (k0 = 1 mod 8), so a block's row can be split over
+// lanes; the partial sums are what a lane adds.
+FSMI_DEV void rows4_exact_unit(const float* sG, const float* sC, int off, int j0, int k0, int k1,
                                double (&out)[4]) {
   const float* B = sG + (off - j0);
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   float w[11];   // w[i] = B[k - 3 + i] at the chunk start k
-  w[0] = B[-2];
-  w[1] = B[-1];
-  w[2] = B[0];
-  int k = 1;
-  for (; k + 7 <= n; k += 8) {
+  w[0] = B[k0 - 3];
+  w[1] = B[k0 - 2];
+  w[2] = B[k0 - 1];
+  int k = k0;
+  for (; k + 7 <= k1; k += 8) {
     const float4 lo = *reinterpret_cast<const float4*>(B + k);
     const float4 hi = *reinterpret_cast<const float4*>(B + k + 4);
     w[3] = lo.x;
@@ -476,7 +478,7 @@ FSMI_DEV void rows4_exact_unit(const float* sG, const float* sC, int off, int n,
     w[1] = w[9];
     w[2] = w[10];
   }
-  for (; k <= n; ++k) {
+  for (; k <= k1; ++k) {
     const float c = sC[k - 1];
 #pragma unroll
     for (int r = 0; r < 4; ++r) acc[r] += (double)(c * B[k - r]);
@@ -661,9 +663,32 @@ FSMI_DEV double beam_core(const EvalConst& ec, int n, const float* so, bool has_
       if constexpr (sizeof(T) == 4) {
         const int nb4 = n / 4;
         if (ec.variant == FSMI_EXACT && nb4 >= G / 2) {   // enough blocks for the group
-          for (int b = tid; b < nb4; b += G) {
+          // Each block's columns are split into S segments (multiples of 8,
+          // at least 64 columns), S <= 8 chosen so that the units nb4 S fill
+          // the group's rounds best (fewer segments unless 2 % better): a
+          // lane adds P_j times its partial row sums.
+          int S = 1;
+          {
+            const int smax = min(8, n / 64);
+            float best = (float)nb4 / (float)(G * ((nb4 + G - 1) / G));
+            for (int sc = 2; sc <= smax; ++sc) {
+              const int U = nb4 * sc;
+              const float e = (float)U / (float)(G * ((U + G - 1) / G));
+              if (e > best + 0.02f) {
+                best = e;
+                S = sc;
+              }
+            }
+          }
+          const int seg = ((n + S - 1) / S + 7) / 8 * 8;
+          // segment-major: neighbouring lanes take neighbouring blocks of the
+          // same columns, so C_k stays a broadcast and the weight windows
+          // stay contiguous
+          for (int u = tid; u < nb4 * S; u += G) {
+            const int sg = u / nb4, b = u - sg * nb4, k0 = 1 + sg * seg;
+            if (k0 > n) continue;
             double rv[4];
-            rows4_exact_unit(sG, sC, off, n, 4 * b + 1, rv);
+            rows4_exact_unit(sG, sC, off, 4 * b + 1, k0, min(n, k0 + seg - 1), rv);
 #pragma unroll
             for (int r = 0; r < 4; ++r) tot += (double)sP[4 * b + r] * rv[r];
           }
