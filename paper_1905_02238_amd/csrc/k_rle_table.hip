@@ -75,21 +75,19 @@ __global__ void k_tab_alpha_beta(int levels, int Delta, double two_var, double* 
   }
 }
 
-// theta and gamma: one thread per level, L = 1 .. max_run, each step adding
-// the new row a = L - 1 (b < L) and the new column b = L - 1 (a < L - 1) of
-// the band |a - b| <= Delta.
-__global__ void k_tab_theta_gamma(int levels, int Delta, double two_var, int max_run, double* tg) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i > levels) return;
-  const double x = (double)i / (double)levels;
-  double* th = tg + (int64_t)i * 2 * (max_run + 1);
-  double* ga = th + (max_run + 1);
-  th[0] = 0.0;
-  ga[0] = 0.0;
-  CSum st, sg;
-  for (int L = 1; L <= max_run; ++L) {
+// theta and gamma.  theta[x, L] - theta[x, L - 1] is the new row a = L - 1
+// (b < L) and the new column b = L - 1 (a < L - 1) of the band
+// |a - b| <= Delta: first every increment, one thread per (i, L), then one
+// thread per level adds them up in order (compensated).
+__global__ void k_tab_tg_steps(int levels, int Delta, double two_var, int max_run, double* tg) {
+  const int64_t total = (int64_t)(levels + 1) * max_run;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e / max_run), L = (int)(e % max_run) + 1;
+    const double x = (double)i / (double)levels;
     const int m = L - 1;
     const double xm = pow(x, (double)m);
+    CSum st, sg;
     for (int b = max(0, m - Delta); b <= m; ++b) {   // row a = m
       const double w = gauss_trunc(two_var, Delta, m - b);
       st.add(xm * w);
@@ -100,6 +98,23 @@ __global__ void k_tab_theta_gamma(int levels, int Delta, double two_var, int max
       st.add(w);
       sg.add((double)m * w);
     }
+    double* th = tg + (int64_t)i * 2 * (max_run + 1);
+    th[L] = st.value();
+    th[max_run + 1 + L] = sg.value();
+  }
+}
+
+__global__ void k_tab_tg_prefix(int levels, int max_run, double* tg) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i > levels) return;
+  double* th = tg + (int64_t)i * 2 * (max_run + 1);
+  double* ga = th + (max_run + 1);
+  th[0] = 0.0;
+  ga[0] = 0.0;
+  CSum st, sg;
+  for (int L = 1; L <= max_run; ++L) {
+    st.add(th[L]);
+    sg.add(ga[L]);
     th[L] = st.value();
     ga[L] = sg.value();
   }
@@ -118,13 +133,76 @@ struct TabArgs {
   uint32_t* status;
 };
 
+// Run u's terms (Alg 11's u = v, v after u and v before u) of a beam whose
+// nr runs sit in the LDS arrays s_*.
+struct RunLds {
+  const float* o;
+  const int *L, *s;
+  const double *P, *D, *fo, *fe;
+};
+FSMI_DEV double table_run_terms(const TabArgs& a, const RunLds& r, int u, int nr) {
+  const int W = 2 * a.Delta + 1, Delta = a.Delta;
+  const float* s_o = r.o;
+  const int *s_L = r.L, *s_s = r.s;
+  const double *s_P = r.P, *s_D = r.D, *s_fo = r.fo, *s_fe = r.fe;
+  double acc = 0.0;
+  const double ou = (double)s_o[u];
+  const double x = 1.0 - ou;
+  const int iq = (int)floor(x * (double)a.levels + 0.5);
+  const double xq = (double)iq / (double)a.levels;
+  const double* al = a.ab + (int64_t)iq * 2 * W * W;
+  const double* be = al + W * W;
+  const double* th = a.tg + (int64_t)iq * 2 * (a.max_run + 1);
+  const double* ga = th + (a.max_run + 1);
+  const int Lu = s_L[u], su = s_s[u];
+  const double PE = s_P[u];
+  acc += PE * ou * ((s_D[u] + s_fo[u]) * th[Lu] + s_fe[u] * ga[Lu]);
+  // v after u: s_v increases with v
+  for (int v = u + 1; v < nr && s_s[v] < su + Lu + Delta; ++v) {
+    const int sv = s_s[v], Lv = s_L[v];
+    const int su_p = max(su, sv - Delta);
+    const int Lu_p = su + Lu - su_p;
+    const int Lv_p = min(Lv, su + Lu + Delta - sv);
+    const int t = su_p - sv;   // <= 0
+    const double A = al[Lu_p * W + Lv_p - t] - al[Lu_p * W - t];
+    const double B = be[Lu_p * W + Lv_p - t] - be[Lu_p * W - t] + (double)t * A;
+    const double Pp = PE * pow(x, (double)(su_p - su));
+    acc += Pp * ou * ((s_D[v] + s_fo[v]) * A + s_fe[v] * B);
+  }
+  // v before u: s_v + L_v decreases as v falls
+  for (int v = u - 1; v >= 0 && su < s_s[v] + s_L[v] + Delta; --v) {
+    const int sv = s_s[v], Lv = s_L[v];
+    const int Lu_p = min(Lu, sv + Lv + Delta - su);
+    const int sv_p = max(sv, su - Delta);
+    const int Lv_p = sv + Lv - sv_p;
+    const int t = su - sv_p;   // >= 1
+    double A, B;
+    if (iq == 0) {
+      double sa = 0.0, sb = 0.0;
+      for (int k = 0; k < Lv_p; ++k) {
+        const double w = gauss_trunc(a.two_var, Delta, t - k);
+        sa += w;
+        sb += (double)k * w;
+      }
+      A = sa;
+      B = sb;
+    } else {
+      const double xt = pow(xq, (double)(-t));
+      A = xt * (al[(t + Lu_p) * W + Lv_p] - al[t * W + Lv_p]);
+      B = xt * (be[(t + Lu_p) * W + Lv_p] - be[t * W + Lv_p]);
+    }
+    const double Dp = s_D[v] + (double)(sv_p - sv) * s_fe[v];
+    acc += PE * ou * ((Dp + s_fo[v]) * A + s_fe[v] * B);
+  }
+  return acc;
+}
+
 template <int RUNS>
 __global__ __launch_bounds__(kWave) void k_rle_table(TabArgs a) {
   __shared__ float s_o[RUNS];
   __shared__ int s_L[RUNS], s_s[RUNS];
   __shared__ double s_P[RUNS], s_D[RUNS], s_fo[RUNS], s_fe[RUNS];
   const int lane = threadIdx.x;
-  const int W = 2 * a.Delta + 1, Delta = a.Delta;
   const double delta_emp = 1.0 / a.delta_occ;
   for (int64_t it = blockIdx.x; it < a.n_beams; it += gridDim.x) {
     const int64_t r0 = a.run_off[it], r1 = a.run_off[it + 1];
@@ -185,60 +263,101 @@ __global__ __launch_bounds__(kWave) void k_rle_table(TabArgs a) {
     }
     wave_sync();
     // pass 2: a lane per run u
+    const RunLds rl{s_o, s_L, s_s, s_P, s_D, s_fo, s_fe};
     double acc = 0.0;
-    for (int u = lane; u < nr; u += kWave) {
-      const double ou = (double)s_o[u];
-      const double x = 1.0 - ou;
-      const int iq = (int)floor(x * (double)a.levels + 0.5);
-      const double xq = (double)iq / (double)a.levels;
-      const double* al = a.ab + (int64_t)iq * 2 * W * W;
-      const double* be = al + W * W;
-      const double* th = a.tg + (int64_t)iq * 2 * (a.max_run + 1);
-      const double* ga = th + (a.max_run + 1);
-      const int Lu = s_L[u], su = s_s[u];
-      const double PE = s_P[u];
-      acc += PE * ou * ((s_D[u] + s_fo[u]) * th[Lu] + s_fe[u] * ga[Lu]);
-      // v after u: s_v increases with v
-      for (int v = u + 1; v < nr && s_s[v] < su + Lu + Delta; ++v) {
-        const int sv = s_s[v], Lv = s_L[v];
-        const int su_p = max(su, sv - Delta);
-        const int Lu_p = su + Lu - su_p;
-        const int Lv_p = min(Lv, su + Lu + Delta - sv);
-        const int t = su_p - sv;   // <= 0
-        const double A = al[Lu_p * W + Lv_p - t] - al[Lu_p * W - t];
-        const double B = be[Lu_p * W + Lv_p - t] - be[Lu_p * W - t] + (double)t * A;
-        const double Pp = PE * pow(x, (double)(su_p - su));
-        acc += Pp * ou * ((s_D[v] + s_fo[v]) * A + s_fe[v] * B);
-      }
-      // v before u: s_v + L_v decreases as v falls
-      for (int v = u - 1; v >= 0 && su < s_s[v] + s_L[v] + Delta; --v) {
-        const int sv = s_s[v], Lv = s_L[v];
-        const int Lu_p = min(Lu, sv + Lv + Delta - su);
-        const int sv_p = max(sv, su - Delta);
-        const int Lv_p = sv + Lv - sv_p;
-        const int t = su - sv_p;   // >= 1
-        double A, B;
-        if (iq == 0) {
-          double sa = 0.0, sb = 0.0;
-          for (int k = 0; k < Lv_p; ++k) {
-            const double w = gauss_trunc(a.two_var, Delta, t - k);
-            sa += w;
-            sb += (double)k * w;
-          }
-          A = sa;
-          B = sb;
-        } else {
-          const double xt = pow(xq, (double)(-t));
-          A = xt * (al[(t + Lu_p) * W + Lv_p] - al[t * W + Lv_p]);
-          B = xt * (be[(t + Lu_p) * W + Lv_p] - be[t * W + Lv_p]);
-        }
-        const double Dp = s_D[v] + (double)(sv_p - sv) * s_fe[v];
-        acc += PE * ou * ((Dp + s_fo[v]) * A + s_fe[v] * B);
-      }
-    }
+    for (int u = lane; u < nr; u += kWave) acc += table_run_terms(a, rl, u, nr);
     const double I = wave_sum(acc);
     if (lane == 0) a.mi[it] = I / (2.50662827463100050242 * a.sigma_p);
     wave_sync();   // the LDS arrays are refilled for the next beam
+  }
+}
+
+// Scans within the 16-lane rows of a wave (DPP row shifts; a row's first
+// lane gets the identity).
+template <typename Op, typename T>
+FSMI_DEV T row_scan_incl(T v) {
+  const T id = Op::template ident<T>();
+  if constexpr (sizeof(T) == 8) {
+    v = Op::apply(v, dpp_f64<dpp::row_shr1, 0xf>(v, id));
+    v = Op::apply(v, dpp_f64<dpp::row_shr2, 0xf>(v, id));
+    v = Op::apply(v, dpp_f64<dpp::row_shr4, 0xf>(v, id));
+    v = Op::apply(v, dpp_f64<dpp::row_shr8, 0xf>(v, id));
+  } else {
+    v = Op::apply(v, dpp_i32<dpp::row_shr1, 0xf>(v, id));
+    v = Op::apply(v, dpp_i32<dpp::row_shr2, 0xf>(v, id));
+    v = Op::apply(v, dpp_i32<dpp::row_shr4, 0xf>(v, id));
+    v = Op::apply(v, dpp_i32<dpp::row_shr8, 0xf>(v, id));
+  }
+  return v;
+}
+template <typename Op>
+FSMI_DEV double row_shift_up(double inc) {
+  return dpp_f64<dpp::row_shr1, 0xf>(inc, Op::template ident<double>());
+}
+
+// Beams of at most 16 runs: four beams per wave, 16 lanes (one DPP row) each,
+// a lane per run.  Beam 4 g + q of the launch's group g sits in row q.
+__global__ __launch_bounds__(kWave) void k_rle_table16(TabArgs a) {
+  __shared__ float s_o[kWave];
+  __shared__ int s_L[kWave], s_s[kWave];
+  __shared__ double s_P[kWave], s_D[kWave], s_fo[kWave], s_fe[kWave];
+  const int lane = threadIdx.x, row = lane >> 4, u = lane & 15;
+  const double delta_emp = 1.0 / a.delta_occ;
+  const RunLds rl{s_o + 16 * row, s_L + 16 * row, s_s + 16 * row, s_P + 16 * row,
+                  s_D + 16 * row, s_fo + 16 * row, s_fe + 16 * row};
+  const int64_t n_groups = (a.n_beams + 3) / 4;
+  for (int64_t gi = blockIdx.x; gi < n_groups; gi += gridDim.x) {
+    const int64_t it = 4 * gi + row;
+    const bool has_beam = it < a.n_beams;
+    const int64_t r0 = has_beam ? a.run_off[it] : 0, r1 = has_beam ? a.run_off[it + 1] : 0;
+    const bool bad_off = has_beam && (r1 < r0 || r1 - r0 > 16);
+    const int nr = (has_beam && !bad_off) ? (int)(r1 - r0) : 0;
+    const bool valid = u < nr;
+    const float o = valid ? a.run_occ[r0 + u] : 0.0f;
+    int L = valid ? a.run_len[r0 + u] : 0;
+    const bool bad_o = valid && !(o >= 0.0f && o <= 1.0f);
+    const bool bad_l = valid && L <= 0;
+    const bool bad_c = valid && L > a.max_run;
+    L = (L > 0 && L <= a.max_run) ? L : 0;
+    const double od = (o >= 0.0f && o <= 1.0f) ? (double)o : 0.0;
+    const double fo = f_cell<double>(a.delta_occ, a.ln_occ, od);
+    const double fe = f_cell<double>(delta_emp, a.ln_emp, od);
+    const double eD = (double)L * fe;
+    const double eP = valid ? pow(1.0 - od, (double)L) : 1.0;
+    // row-local scans: every lane takes part
+    const int incS = row_scan_incl<OpAdd>(L);
+    const double incD = row_scan_incl<OpAdd>(eD);
+    const double incP = row_scan_incl<OpMul>(eP);
+    const double exD = row_shift_up<OpAdd>(incD);
+    const double exP = row_shift_up<OpMul>(incP);
+    if (valid) {
+      s_o[lane] = (float)od;
+      s_L[lane] = L;
+      s_s[lane] = incS - L;
+      s_D[lane] = exD;
+      s_P[lane] = exP;
+      s_fo[lane] = fo;
+      s_fe[lane] = fe;
+    }
+    // this row's flags
+    const uint64_t mo = __ballot(bad_o), ml = __ballot(bad_l || bad_off), mc = __ballot(bad_c);
+    const uint64_t rm = 0xffffull << (16 * row);
+    const bool rbad = ((mo | ml | mc) & rm) != 0;
+    wave_sync();
+    const double acc = (valid && !rbad) ? table_run_terms(a, rl, u, nr) : 0.0;
+    // the row's sum, in lane 15 of the row after the scan
+    const double tot = __shfl(row_scan_incl<OpAdd>(acc), 16 * row + 15);
+    if (u == 0 && has_beam) {
+      if (rbad) {
+        latch(a.status, ((mo & rm) ? kErrOcc : 0u) |
+                            ((ml & rm) ? (bad_off && r1 - r0 > 16 ? kErrCap : kErrLen) : 0u) |
+                            ((mc & rm) ? kErrCap : 0u));
+        a.mi[it] = __builtin_nan("");
+      } else {
+        a.mi[it] = tot / (2.50662827463100050242 * a.sigma_p);
+      }
+    }
+    wave_sync();   // the LDS rows are refilled for the next group
   }
 }
 
@@ -277,7 +396,7 @@ hipError_t launch_rle_table(fsmi_ctx ctx, double delta_occ, int Delta, int level
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) return e;
   const int max_run = std::max(1, std::min(host[0], kTabMaxRun));   // longer runs latch in the kernel
-  const bool small = host[1] <= 256;
+  const bool small = host[1] <= 256, tiny = host[1] <= 16;
   const int W = 2 * Delta + 1;
   const size_t ab_n = (size_t)(levels + 1) * 2 * W * W;
   const size_t tg_n = (size_t)(levels + 1) * 2 * (max_run + 1);
@@ -289,8 +408,10 @@ hipError_t launch_rle_table(fsmi_ctx ctx, double delta_occ, int Delta, int level
   const int g1 = (int)std::min<size_t>((ab_n / 2 + 255) / 256, 4096);
   hipLaunchKernelGGL(k_tab_alpha_beta, dim3(std::max(g1, 1)), dim3(256), 0, st, levels, Delta,
                      two_var, ab);
-  hipLaunchKernelGGL(k_tab_theta_gamma, dim3((levels + 1 + 63) / 64), dim3(64), 0, st, levels, Delta,
-                     two_var, max_run, tg);
+  const int g2 = (int)std::min<int64_t>(((int64_t)(levels + 1) * max_run + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_tab_tg_steps, dim3(std::max(g2, 1)), dim3(256), 0, st, levels, Delta, two_var,
+                     max_run, tg);
+  hipLaunchKernelGGL(k_tab_tg_prefix, dim3((levels + 1 + 63) / 64), dim3(64), 0, st, levels, max_run, tg);
   TabArgs a;
   a.n_beams = n_beams;
   a.run_off = run_off;
@@ -312,7 +433,10 @@ hipError_t launch_rle_table(fsmi_ctx ctx, double delta_occ, int Delta, int level
   // 45 KB of LDS allows 3 per CU
   const int per_cu = small ? 12 : 3;
   const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(n_beams, (int64_t)ctx->num_cu * per_cu));
-  if (small)
+  if (tiny) {
+    const int g16 = (int)std::max<int64_t>(1, std::min<int64_t>((n_beams + 3) / 4, (int64_t)ctx->num_cu * 12));
+    hipLaunchKernelGGL(k_rle_table16, dim3(g16), dim3(kWave), 0, st, a);
+  } else if (small)
     hipLaunchKernelGGL(k_rle_table<256>, dim3(grid), dim3(kWave), 0, st, a);
   else
     hipLaunchKernelGGL(k_rle_table<kTabRuns>, dim3(grid), dim3(kWave), 0, st, a);

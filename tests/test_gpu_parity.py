@@ -301,13 +301,15 @@ def _oracle_table(off, ro, rl, sigma_p, Delta, levels):
                      for b in range(len(off) - 1)])
 
 
+@pytest.mark.parametrize("runs_hi", [16, 40])
 @pytest.mark.parametrize("Delta", [1, 3, 6])
-def test_rle_table_route_on_grid(ctx, Delta):
+def test_rle_table_route_on_grid(ctx, Delta, runs_hi):
     """o on the grid with x = 1 - o >= 1/4: x^{-t} <= 4^Delta, so FP64 keeps
-    about 12 digits; the oracle's table route and Thm 6 (density kernel) agree."""
-    print(f"[gpu] rle table route Delta={Delta}", flush=True)
+    about 12 digits; the oracle's table route and Thm 6 (density kernel) agree.
+    Batches of at most 16 runs per beam run four beams per wave."""
+    print(f"[gpu] rle table route Delta={Delta} runs<={runs_hi}", flush=True)
     levels, sp = 64, 1.5
-    off, ro, rl = _grid_runs(70 + Delta, 80, levels, 0, 48)
+    off, ro, rl = _grid_runs(70 + Delta, 81, levels, 0, 48, runs_hi=runs_hi)
     prm = F.params(variant=F.FSMI_APPROX, trunc_delta=Delta, precision=F.FSMI_FP64)
     mi = ctx.fsmi_rle_table_eval_beams(prm, dev(off), dev(ro), dev(rl), sp, levels)
     torch.cuda.synchronize()
@@ -340,6 +342,26 @@ def test_rle_table_route_any_occupancy(ctx):
     ctx.fsmi_sync()
     ref = _oracle_table(off, ro, rl, sp, Delta, levels)
     assert rel_err(mi.cpu().numpy(), ref) <= 2.0 ** -52 * 64.0 ** 3
+
+
+def test_rle_table_route_four_beams_per_wave_latch_one(ctx):
+    """At most 16 runs per beam: one bad beam of a group of four gives NaN and
+    latches, its neighbours in the same wave keep their values."""
+    off = np.array([0, 3, 5, 9, 10, 12], np.int64)
+    ro = np.array([0.2, 0.5, 0.75, 0.3, np.nan, 0.1, 0.2, 0.3, 0.4, 0.9, 0.25, 1.0], np.float32)
+    rl = np.array([2, 3, 1, 4, 2, 1, 1, 2, 3, 5, 2, 2], np.int32)
+    prm = F.params(variant=F.FSMI_APPROX, trunc_delta=3, precision=F.FSMI_FP64)
+    mi = ctx.fsmi_rle_table_eval_beams(prm, dev(off), dev(ro), dev(rl), 1.3, 64)
+    torch.cuda.synchronize()
+    with pytest.raises(F.FsmiError) as e:
+        ctx.fsmi_sync()
+    assert e.value.status == F.FSMI_E_NUMERIC
+    got = mi.cpu().numpy()
+    assert np.isnan(got[1]) and np.all(np.isfinite(got[[0, 2, 3, 4]]))
+    for b in (0, 2, 3, 4):
+        ref = O.rle_table(ro[off[b]:off[b + 1]], rl[off[b]:off[b + 1]], 1.3, 3, 64)
+        assert abs(got[b] - ref) <= 1e-9 * abs(ref)
+    ctx.fsmi_sync()   # cleared
 
 
 def test_rle_table_route_rejects_and_latches(ctx):
