@@ -233,6 +233,29 @@ def test_eval_beams_uneven_batch(ctx):
     assert torch.equal(mi, mi2)          # deterministic across runs / queue orders
 
 
+def test_eval_beams_unit_cells_row_block_edges(ctx):
+    """Unit-cell exact beams at the lengths where the engine changes shape:
+    below and at two 4-row blocks per lane (127, 128), blocks split into
+    1..8 column segments (129..1100, wave and tile kernels), partial last
+    blocks (n not a multiple of 4) and chunks (n not a multiple of 8)."""
+    print("[gpu] unit cells, row-block edges", flush=True)
+    lens = [127, 128, 129, 130, 131, 200, 255, 256, 300, 333, 511, 512, 513, 700, 767, 768,
+            769, 1023, 1024, 1025, 1100, 1537, 2000]
+    rng = np.random.default_rng(17)
+    off = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    occ = rng.uniform(0.0, 1.0, off[-1]).astype(np.float32)
+    sig = rng.uniform(1.0, 4.0, len(lens)).astype(np.float32)
+    mi = ctx.fsmi_eval_beams(F.params(), dev(off), dev(occ), dev(sig))
+    plan = F.Plan(ctx, F.params(), dev(off), dev(occ), dev(sig), autotune=False, graph=True)
+    plan.launch()
+    torch.cuda.synchronize()
+    ctx.fsmi_sync()
+    ref = O.eval_beams(F.FSMI_EXACT, off, occ, sig)
+    assert rel_err(mi.cpu().numpy(), ref) <= TOL32
+    assert rel_err(plan.mi.cpu().numpy(), ref) <= TOL32
+    plan.close()
+
+
 def test_eval_beams_bad_data_latches(ctx):
     off = np.array([0, 3, 6], np.int64)
     occ = np.array([0.2, np.nan, 0.3, 0.1, 0.2, 0.3], np.float32)
