@@ -124,7 +124,8 @@ def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build measures one GPU; runs on more than one GPU are not "
-              "supported (the path shards by poses, see DESIGN.md)", file=sys.stderr)
+              "supported (the path would shard by poses: each GPU a slice of the poses, the map "
+              "replicated, the per-pose results gathered)", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_1905_02238_amd import fsmi as F
