@@ -123,7 +123,7 @@ def log(*a):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build measures one GPU; runs on more than one GPU are not "
+        print("bench.py measures one GPU; runs on more than one GPU are not "
               "supported (the path would shard by poses: each GPU a slice of the poses, the map "
               "replicated, the per-pose results gathered)", file=sys.stderr)
         sys.exit(2)
