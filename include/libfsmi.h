@@ -52,7 +52,7 @@ typedef enum {
   FSMI_E_NOMEM = 3,       /* device allocation failed */
   FSMI_E_CAPACITY = 4,    /* an output buffer or a beam is larger than allowed */
   FSMI_E_NUMERIC = 5,     /* latched device data error (see above) */
-  FSMI_E_UNSUPPORTED = 6  /* valid request this build does not implement */
+  FSMI_E_UNSUPPORTED = 6  /* valid request the library does not implement */
 } fsmi_status;
 
 /* Variants (Table 1 of the paper). */
