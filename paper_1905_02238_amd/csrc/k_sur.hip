@@ -154,12 +154,17 @@ FSMI_DEV uint32_t pack2(float a, float b) {
 // LDS.  Each wave computes 16-pixel tiles as W (the A operand; the 9 taps are
 // K, padded to 32 with zeros) times the tap values of the 16 pixels (the B
 // operand), so a lane ends with four consecutive channels of one pixel and
-// stores them as 8 bytes.  The grid is batch x HOUT / R workgroups.
+// stores them as 8 bytes.  The grid is batch x HOUT / R workgroups.  It also
+// stores the ReLU signs for the next layer's input-gradient pass: byte g of
+// pixel p (sign[4 p + g]) holds, at bit 4 t + r, whether channel 16 t + 4 g + r
+// is > 0, the channels lane group g holds there too.
 // ---------------------------------------------------------------------------
 template <int COUT, int HIN>
 __global__ __launch_bounds__(256) void k_conv1_fwd(PatchSrc src, const bf16* __restrict__ W,
                                                    const float* __restrict__ bias,
-                                                   bf16* __restrict__ out) {
+                                                   bf16* __restrict__ out,
+                                                   uint8_t* __restrict__ sign) {
+  static_assert(COUT == 32, "one sign byte per lane group: 2 x 4 channels");
   constexpr int HOUT = HIN / 2, R = 4, NT = COUT / 16, SROW = HIN + 2, NTILE = R * HOUT / 16;
   static_assert(HOUT % R == 0 && (R * HOUT) % 16 == 0, "whole 16-pixel tiles per workgroup");
   __shared__ bf16 sP[(2 * R + 1) * SROW];
@@ -198,7 +203,9 @@ __global__ __launch_bounds__(256) void k_conv1_fwd(PatchSrc src, const bf16* __r
         if (tap < 9) xb[q] = sP[(2 * oyl + tap / 3) * SROW + 2 * ox + tap % 3];
       }
     }
-    bf16* op = out + (tile * (R * HOUT) + pl) * COUT;
+    const int64_t pix = tile * (R * HOUT) + pl;
+    bf16* op = out + pix * COUT;
+    uint32_t bits = 0;
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       // D[4 g + r][i]: channel 16 t + 4 g + r of pixel i
@@ -206,8 +213,13 @@ __global__ __launch_bounds__(256) void k_conv1_fwd(PatchSrc src, const bf16* __r
       float v[4];
 #pragma unroll
       for (int r = 0; r < 4; ++r) v[r] = fmaxf(d[r] + bv[t][r], 0.0f);
-      *reinterpret_cast<uint2*>(op + 16 * t + 4 * g) = uint2{pack2(v[0], v[1]), pack2(v[2], v[3])};
+      const uint2 w = uint2{pack2(v[0], v[1]), pack2(v[2], v[3])};
+      *reinterpret_cast<uint2*>(op + 16 * t + 4 * g) = w;
+      // a stored BF16 that is >= 0 is > 0 iff it is not zero
+      bits |= (((w.x & 0xffffu) != 0u ? 1u : 0u) | ((w.x >> 16) != 0u ? 2u : 0u) |
+               ((w.y & 0xffffu) != 0u ? 4u : 0u) | ((w.y >> 16) != 0u ? 8u : 0u)) << (4 * t);
     }
+    sign[4 * pix + g] = (uint8_t)bits;
   }
 }
 
@@ -537,6 +549,7 @@ template <int CIN, int COUT, int HIN>
 __global__ __launch_bounds__(256) void k_conv_dgrad(int64_t nq, const bf16* __restrict__ dout,
                                                     const bf16* __restrict__ Wt,
                                                     const bf16* __restrict__ act_in,
+                                                    const uint8_t* __restrict__ sign,
                                                     bf16* __restrict__ din) {
   constexpr int HOUT = HIN / 2, NT = CIN / 16, KC = COUT / 32, MT = dgrad_mt<CIN, COUT, HIN>();
   constexpr int TQ = 16 * MT, ROWD = COUT + 8;   // positions per tile; LDS row (one d_out pixel)
@@ -603,21 +616,28 @@ __global__ __launch_bounds__(256) void k_conv_dgrad(int64_t nq, const bf16* __re
     if (m >= n_mt) break;
     const int iy = 2 * qa[m] + py, ix = 2 * qc[m] + px;
     const int64_t p = (qb[m] * HIN + iy) * HIN + ix;
+    // with sign bytes (the first layer's output): bit 4 t + r of byte g
+    const uint32_t sb = sign ? (uint32_t)sign[4 * p + g] : 0u;
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       const int ci = 16 * t + 4 * g;
-      const uint2 av = *reinterpret_cast<const uint2*>(act_in + p * CIN + ci);
-      const uint32_t aw[2] = {av.x, av.y};
-      uint32_t ow[2];
+      float mk[4];
+      if (sign) {
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        // the two BF16 activations widened to FP32 (the low half is channel ci + 2 h)
-        const float v0 = __builtin_bit_cast(float, aw[h] << 16);
-        const float v1 = __builtin_bit_cast(float, aw[h] & 0xffff0000u);
-        const float m0 = v0 > 0.0f ? 1.0f : 0.0f, m1 = v1 > 0.0f ? 1.0f : 0.0f;
-        ow[h] = pack2(acc[m][t][2 * h] * m0, acc[m][t][2 * h + 1] * m1);
+        for (int r = 0; r < 4; ++r) mk[r] = (sb >> (4 * t + r)) & 1u ? 1.0f : 0.0f;
+      } else {
+        const uint2 av = *reinterpret_cast<const uint2*>(act_in + p * CIN + ci);
+        // the BF16 activations widened to FP32 (the low half first)
+        const uint32_t aw[2] = {av.x, av.y};
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          mk[2 * h] = __builtin_bit_cast(float, aw[h] << 16) > 0.0f ? 1.0f : 0.0f;
+          mk[2 * h + 1] = __builtin_bit_cast(float, aw[h] & 0xffff0000u) > 0.0f ? 1.0f : 0.0f;
+        }
       }
-      *reinterpret_cast<uint2*>(din + p * CIN + ci) = uint2{ow[0], ow[1]};
+      *reinterpret_cast<uint2*>(din + p * CIN + ci) =
+          uint2{pack2(acc[m][t][0] * mk[0], acc[m][t][1] * mk[1]),
+                pack2(acc[m][t][2] * mk[2], acc[m][t][3] * mk[3])};
     }
   }
 }
@@ -1259,6 +1279,7 @@ struct fsmi_sur_s {
   float* loss = nullptr;
   int stride = 1;            // cell stride of the patch
   fsmi::bf16* patch = nullptr;   // the training batch's patches, allocated on first use
+  uint8_t* sign1 = nullptr;      // ReLU signs of the first layer's output, 4 bytes per pixel
   float* pooled = nullptr;   // block means of the last map (stride > 1)
   size_t pooled_elems = 0;
 };
@@ -1293,6 +1314,7 @@ static hipError_t sur_alloc(fsmi_sur net) {
   for (int l = 1; l <= 5; ++l) {
     ALLOC(net->act[l], sizeof(bf16) * act_elems(l, B));
     ALLOC(net->dact[l], sizeof(bf16) * act_elems(l, B));
+    if (l == 1) ALLOC(net->sign1, act_elems(1, B) / 8);   // 32 channels -> 4 bytes
   }
   ALLOC(net->gsave, sizeof(float) * (size_t)B * kFeat);
   ALLOC(net->hsave, sizeof(float) * (size_t)B * kHid);
@@ -1325,6 +1347,7 @@ static void sur_free(fsmi_sur net) {
     if (p) (void)hipFree(p);
   if (net->pooled) (void)hipFree(net->pooled);
   if (net->patch) (void)hipFree(net->patch);
+  if (net->sign1) (void)hipFree(net->sign1);
   for (int l = 1; l <= 5; ++l) {
     if (net->act[l]) (void)hipFree(net->act[l]);
     if (net->dact[l]) (void)hipFree(net->dact[l]);
@@ -1374,7 +1397,7 @@ static void conv_fwd(fsmi_sur net, int64_t nb, PatchSrc src) {
     static_assert(d.cin == 1, "the first convolution reads one channel");
     hipLaunchKernelGGL((k_conv1_fwd<d.cout, d.hin>), dim3((unsigned)(nb * (d.hin / 2) / 4)), dim3(256),
                        0, net->ctx->stream, src, net->Wbf + wbf_off(L), net->P + b_off(L),
-                       net->act[L + 1]);
+                       net->act[L + 1], net->sign1);
   } else {
     constexpr int per_block = 4 * 16 * conv_mt<d.cin, d.cout, d.hin>();   // 4 waves
     const int64_t blocks = (npix + per_block - 1) / per_block;
@@ -1414,7 +1437,8 @@ static void conv_dgrad(fsmi_sur net, int64_t nb) {
   const int64_t nq = nb * (d.hin / 2) * (d.hin / 2);   // a multiple of 16
   hipLaunchKernelGGL((k_conv_dgrad<d.cin, d.cout, d.hin>),
                      dim3((unsigned)((nq + 16 * mt - 1) / (16 * mt))), dim3(256), 0, net->ctx->stream,
-                     nq, net->dact[L + 1], net->Wt + wbf_off(L), net->act[L], net->dact[L]);
+                     nq, net->dact[L + 1], net->Wt + wbf_off(L), net->act[L],
+                     L == 1 ? net->sign1 : nullptr, net->dact[L]);
 }
 
 template <int L, bool FIRST>
