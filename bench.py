@@ -110,6 +110,14 @@ def parse():
                     help="for kernel traces: 10 surrogate training steps (backward + Adam) of "
                          "1024 poses on a rooms map, random-initialised weights and labels, "
                          "nothing else")
+    ap.add_argument("--profile-3d", action="store_true",
+                    help="for kernel traces: one 3D launch each of FSMI-RLE, Approx-FSMI-RLE "
+                         "(Delta = 6) and Uniform-FSMI-RLE (H = 4), 256 poses x 16 384 beams on "
+                         "the 512 x 512 x 128 voxel map, nothing else")
+    ap.add_argument("--profile-table", action="store_true",
+                    help="for kernel traces: the table route of Approx-FSMI-RLE and Approx-FSMI "
+                         "on the cells, 65 536 beams of 256 cells in runs of 4 and of 32, "
+                         "nothing else")
     ap.add_argument("--profile-uneven", action="store_true",
                     help="for kernel traces: the 100k uneven beams through an autotuned, "
                          "graph-captured plan (5 launches), nothing else")
@@ -162,6 +170,28 @@ def main():
         ctx.fsmi_sync()
         log("[bench] training profile done")
         net.close()
+        return
+    if args.profile_3d:
+        vw = W.voxels_large(n_poses=256)
+        vx, vp, vb = t(vw["vox"]), t(vw["poses"]), t(vw["beam_dir"])
+        for prm in (F.params(), F.params(variant=F.FSMI_APPROX, trunc_delta=6),
+                    F.params(variant=F.FSMI_UNIFORM, uniform_h=4)):
+            ctx.fsmi_eval_poses(prm, vx, vp, vb, vw["sigma"], vw["R"], vw["w"])
+        torch.cuda.synchronize()
+        ctx.fsmi_sync()
+        log("[bench] 3d profile done")
+        return
+    if args.profile_table:
+        nb = 65536
+        p_tab = F.params(variant=F.FSMI_APPROX, trunc_delta=3, precision=F.FSMI_FP64)
+        p64 = F.params(variant=F.FSMI_APPROX, trunc_delta=3, precision=F.FSMI_FP64)
+        for L in (4, 32):
+            run_off, ro, rl, off, occ = W.grouped_beams(nb, 256, L, seed=W.SEED_BASE + 5 + L)
+            ctx.fsmi_rle_table_eval_beams(p_tab, t(run_off), t(ro), t(rl), 1.0, 64)
+            ctx.fsmi_eval_beams(p64, t(off), t(occ), t(np.full(nb, 1.0, np.float32)))
+        torch.cuda.synchronize()
+        ctx.fsmi_sync()
+        log("[bench] table profile done")
         return
     if args.profile_uneven:
         off, occ, sg = W.uneven_beams(100000, seed=W.SEED_BASE + 3)
