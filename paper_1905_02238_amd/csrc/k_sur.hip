@@ -146,6 +146,20 @@ FSMI_DEV uint32_t pack2(float a, float b) {
   return (uint32_t)__builtin_bit_cast(uint16_t, x) | ((uint32_t)__builtin_bit_cast(uint16_t, y) << 16);
 }
 
+// ReLU signs of a stored activation for the next layer's input-gradient pass:
+// word g of pixel p (sign[4 p + g]) holds, at bit 4 t + r, whether channel
+// 16 t + 4 g + r is > 0, the channels lane group g holds in the forward and
+// the input-gradient kernels alike (NT = channels / 16).
+template <int NT> struct SignWord;
+template <> struct SignWord<2> { typedef uint8_t type; };
+template <> struct SignWord<4> { typedef uint16_t type; };
+template <> struct SignWord<8> { typedef uint32_t type; };
+// The 4 sign bits of two packed BF16 pairs (>= 0 values: > 0 iff not zero).
+FSMI_DEV uint32_t sign4(uint2 w) {
+  return ((w.x & 0xffffu) != 0u ? 1u : 0u) | ((w.x >> 16) != 0u ? 2u : 0u) |
+         ((w.y & 0xffffu) != 0u ? 4u : 0u) | ((w.y >> 16) != 0u ? 8u : 0u);
+}
+
 // ---------------------------------------------------------------------------
 // First convolution when its output is kept (training): out[p][co] =
 // ReLU(b[co] + sum over taps of W[co][tap] x[p, tap]), x[p, tap] the patch
@@ -155,9 +169,7 @@ FSMI_DEV uint32_t pack2(float a, float b) {
 // K, padded to 32 with zeros) times the tap values of the 16 pixels (the B
 // operand), so a lane ends with four consecutive channels of one pixel and
 // stores them as 8 bytes.  The grid is batch x HOUT / R workgroups.  It also
-// stores the ReLU signs for the next layer's input-gradient pass: byte g of
-// pixel p (sign[4 p + g]) holds, at bit 4 t + r, whether channel 16 t + 4 g + r
-// is > 0, the channels lane group g holds there too.
+// stores the ReLU sign words (SignWord) for the next layer.
 // ---------------------------------------------------------------------------
 template <int COUT, int HIN>
 __global__ __launch_bounds__(256) void k_conv1_fwd(PatchSrc src, const bf16* __restrict__ W,
@@ -215,9 +227,7 @@ __global__ __launch_bounds__(256) void k_conv1_fwd(PatchSrc src, const bf16* __r
       for (int r = 0; r < 4; ++r) v[r] = fmaxf(d[r] + bv[t][r], 0.0f);
       const uint2 w = uint2{pack2(v[0], v[1]), pack2(v[2], v[3])};
       *reinterpret_cast<uint2*>(op + 16 * t + 4 * g) = w;
-      // a stored BF16 that is >= 0 is > 0 iff it is not zero
-      bits |= (((w.x & 0xffffu) != 0u ? 1u : 0u) | ((w.x >> 16) != 0u ? 2u : 0u) |
-               ((w.y & 0xffffu) != 0u ? 4u : 0u) | ((w.y >> 16) != 0u ? 8u : 0u)) << (4 * t);
+      bits |= sign4(w) << (4 * t);
     }
     sign[4 * pix + g] = (uint8_t)bits;
   }
@@ -246,7 +256,8 @@ template <int CIN, int COUT, int HIN>
 __global__ __launch_bounds__(256) void k_conv_fwd_lds(int64_t npix, const bf16* __restrict__ in,
                                                       const bf16* __restrict__ W,
                                                       const float* __restrict__ bias,
-                                                      bf16* __restrict__ out) {
+                                                      bf16* __restrict__ out,
+                                                      void* __restrict__ sign) {
   constexpr int HOUT = HIN / 2, NT = COUT / 16, MT = conv_mt<CIN, COUT, HIN>();
   constexpr int KC = CIN / 32, ROW = conv_lds_row<CIN, COUT>();
   __shared__ __align__(16) bf16 sW[COUT * ROW];
@@ -309,7 +320,9 @@ __global__ __launch_bounds__(256) void k_conv_fwd_lds(int64_t npix, const bf16* 
 #pragma unroll
   for (int m = 0; m < MT; ++m) {
     if (m >= n_mt) break;
-    bf16* op = out + (base + 16 * m + i) * COUT + 4 * g;
+    const int64_t pix = base + 16 * m + i;
+    bf16* op = out + pix * COUT + 4 * g;
+    uint32_t bits = 0;
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       float o[4];
@@ -322,6 +335,11 @@ __global__ __launch_bounds__(256) void k_conv_fwd_lds(int64_t npix, const bf16* 
       w.x = pack2(o[0], o[1]);
       w.y = pack2(o[2], o[3]);
       *reinterpret_cast<uint2*>(op + 16 * t) = w;
+      bits |= sign4(w) << (4 * t);
+    }
+    if (sign) {   // training: the next layer's input gradient reads these
+      typedef typename SignWord<NT>::type S;
+      reinterpret_cast<S*>(sign)[4 * pix + g] = (S)bits;
     }
   }
 }
@@ -549,7 +567,7 @@ template <int CIN, int COUT, int HIN>
 __global__ __launch_bounds__(256) void k_conv_dgrad(int64_t nq, const bf16* __restrict__ dout,
                                                     const bf16* __restrict__ Wt,
                                                     const bf16* __restrict__ act_in,
-                                                    const uint8_t* __restrict__ sign,
+                                                    const void* __restrict__ sign,
                                                     bf16* __restrict__ din) {
   constexpr int HOUT = HIN / 2, NT = CIN / 16, KC = COUT / 32, MT = dgrad_mt<CIN, COUT, HIN>();
   constexpr int TQ = 16 * MT, ROWD = COUT + 8;   // positions per tile; LDS row (one d_out pixel)
@@ -616,8 +634,9 @@ __global__ __launch_bounds__(256) void k_conv_dgrad(int64_t nq, const bf16* __re
     if (m >= n_mt) break;
     const int iy = 2 * qa[m] + py, ix = 2 * qc[m] + px;
     const int64_t p = (qb[m] * HIN + iy) * HIN + ix;
-    // with sign bytes (the first layer's output): bit 4 t + r of byte g
-    const uint32_t sb = sign ? (uint32_t)sign[4 * p + g] : 0u;
+    // with sign words (SignWord): bit 4 t + r of word g
+    typedef typename SignWord<NT>::type S;
+    const uint32_t sb = sign ? (uint32_t)reinterpret_cast<const S*>(sign)[4 * p + g] : 0u;
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       const int ci = 16 * t + 4 * g;
@@ -1279,7 +1298,7 @@ struct fsmi_sur_s {
   float* loss = nullptr;
   int stride = 1;            // cell stride of the patch
   fsmi::bf16* patch = nullptr;   // the training batch's patches, allocated on first use
-  uint8_t* sign1 = nullptr;      // ReLU signs of the first layer's output, 4 bytes per pixel
+  void* sign[5] = {};            // sign[l]: ReLU sign words of act[l], l = 1..4 (training)
   float* pooled = nullptr;   // block means of the last map (stride > 1)
   size_t pooled_elems = 0;
 };
@@ -1314,7 +1333,7 @@ static hipError_t sur_alloc(fsmi_sur net) {
   for (int l = 1; l <= 5; ++l) {
     ALLOC(net->act[l], sizeof(bf16) * act_elems(l, B));
     ALLOC(net->dact[l], sizeof(bf16) * act_elems(l, B));
-    if (l == 1) ALLOC(net->sign1, act_elems(1, B) / 8);   // 32 channels -> 4 bytes
+    if (l <= 4) ALLOC(net->sign[l], act_elems(l, B) / 8);   // one bit per channel
   }
   ALLOC(net->gsave, sizeof(float) * (size_t)B * kFeat);
   ALLOC(net->hsave, sizeof(float) * (size_t)B * kHid);
@@ -1347,7 +1366,8 @@ static void sur_free(fsmi_sur net) {
     if (p) (void)hipFree(p);
   if (net->pooled) (void)hipFree(net->pooled);
   if (net->patch) (void)hipFree(net->patch);
-  if (net->sign1) (void)hipFree(net->sign1);
+  for (int l = 1; l <= 4; ++l)
+    if (net->sign[l]) (void)hipFree(net->sign[l]);
   for (int l = 1; l <= 5; ++l) {
     if (net->act[l]) (void)hipFree(net->act[l]);
     if (net->dact[l]) (void)hipFree(net->dact[l]);
@@ -1390,28 +1410,28 @@ static hipError_t cast_weights(fsmi_sur net) {
 }
 
 template <int L, bool FIRST>
-static void conv_fwd(fsmi_sur net, int64_t nb, PatchSrc src) {
+static void conv_fwd(fsmi_sur net, int64_t nb, PatchSrc src, bool save) {
   constexpr LayerDims d = kL[L];
   const int64_t npix = nb * (d.hin / 2) * (d.hin / 2);
   if constexpr (FIRST) {
     static_assert(d.cin == 1, "the first convolution reads one channel");
     hipLaunchKernelGGL((k_conv1_fwd<d.cout, d.hin>), dim3((unsigned)(nb * (d.hin / 2) / 4)), dim3(256),
                        0, net->ctx->stream, src, net->Wbf + wbf_off(L), net->P + b_off(L),
-                       net->act[L + 1], net->sign1);
+                       net->act[L + 1], reinterpret_cast<uint8_t*>(net->sign[1]));
   } else {
     constexpr int per_block = 4 * 16 * conv_mt<d.cin, d.cout, d.hin>();   // 4 waves
     const int64_t blocks = (npix + per_block - 1) / per_block;
     hipLaunchKernelGGL((k_conv_fwd_lds<d.cin, d.cout, d.hin>), dim3((unsigned)blocks), dim3(256), 0,
                        net->ctx->stream, npix, net->act[L], net->Wbf + wbf_off(L), net->P + b_off(L),
-                       net->act[L + 1]);
+                       net->act[L + 1], save && L + 1 <= 4 ? net->sign[L + 1] : nullptr);
   }
 }
 
 // Forward of nb (<= max_batch) poses; predictions (standardised) in ypred.
 static hipError_t sur_fwd_batch(fsmi_sur net, int64_t nb, PatchSrc src, bool save) {
   if (save) {   // training keeps conv1's activations for the backward pass
-    conv_fwd<0, true>(net, nb, src);
-    conv_fwd<1, false>(net, nb, src);
+    conv_fwd<0, true>(net, nb, src, save);
+    conv_fwd<1, false>(net, nb, src, save);
   } else {
     static_assert(kL[0].cout == 32 && kL[1].cin == 32 && kL[1].cout == 64 && kL[1].hin == 64,
                   "k_conv12_fwd is written for conv1 1->32 on 128^2 and conv2 32->64");
@@ -1421,9 +1441,9 @@ static hipError_t sur_fwd_batch(fsmi_sur net, int64_t nb, PatchSrc src, bool sav
                        net->Wbf + wbf_off(0), net->P + b_off(0), net->Wbf + wbf_off(1),
                        net->P + b_off(1), net->act[2]);
   }
-  conv_fwd<2, false>(net, nb, src);
-  conv_fwd<3, false>(net, nb, src);
-  conv_fwd<4, false>(net, nb, src);
+  conv_fwd<2, false>(net, nb, src, save);
+  conv_fwd<3, false>(net, nb, src, save);
+  conv_fwd<4, false>(net, nb, src, save);
   const int grid = (int)std::min<int64_t>(nb, 65535);
   hipLaunchKernelGGL(k_head_fwd, dim3(grid), dim3(256), 0, net->ctx->stream, nb, net->act[5], net->P,
                      save ? net->gsave : nullptr, save ? net->hsave : nullptr, net->ypred);
@@ -1438,7 +1458,7 @@ static void conv_dgrad(fsmi_sur net, int64_t nb) {
   hipLaunchKernelGGL((k_conv_dgrad<d.cin, d.cout, d.hin>),
                      dim3((unsigned)((nq + 16 * mt - 1) / (16 * mt))), dim3(256), 0, net->ctx->stream,
                      nq, net->dact[L + 1], net->Wt + wbf_off(L), net->act[L],
-                     L == 1 ? net->sign1 : nullptr, net->dact[L]);
+                     net->sign[L], net->dact[L]);
 }
 
 template <int L, bool FIRST>
