@@ -161,79 +161,6 @@ FSMI_DEV uint32_t sign4(uint2 w) {
 }
 
 // ---------------------------------------------------------------------------
-// First convolution when its output is kept (training): out[p][co] =
-// ReLU(b[co] + sum over taps of W[co][tap] x[p, tap]), x[p, tap] the patch
-// pixel under the tap.  A workgroup takes R = 4 output rows of one pose and
-// stages the 2 R + 1 patch rows they read, with a zero column on each side, in
-// LDS.  Each wave computes 16-pixel tiles as W (the A operand; the 9 taps are
-// K, padded to 32 with zeros) times the tap values of the 16 pixels (the B
-// operand), so a lane ends with four consecutive channels of one pixel and
-// stores them as 8 bytes.  The grid is batch x HOUT / R workgroups.  It also
-// stores the ReLU sign words (SignWord) for the next layer.
-// ---------------------------------------------------------------------------
-template <int COUT, int HIN>
-__global__ __launch_bounds__(256) void k_conv1_fwd(PatchSrc src, const bf16* __restrict__ W,
-                                                   const float* __restrict__ bias,
-                                                   bf16* __restrict__ out,
-                                                   uint8_t* __restrict__ sign) {
-  static_assert(COUT == 32, "one sign byte per lane group: 2 x 4 channels");
-  constexpr int HOUT = HIN / 2, R = 4, NT = COUT / 16, SROW = HIN + 2, NTILE = R * HOUT / 16;
-  static_assert(HOUT % R == 0 && (R * HOUT) % 16 == 0, "whole 16-pixel tiles per workgroup");
-  __shared__ bf16 sP[(2 * R + 1) * SROW];
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int i = lane & 15, g = lane >> 4;
-  const int64_t tile = blockIdx.x;
-  const int64_t b = tile / (HOUT / R);
-  const int oy0 = (int)(tile % (HOUT / R)) * R;
-  // staged row r = patch row 2 oy0 - 1 + r; staged column cx = patch column cx - 1
-  for (int e = tid; e < (2 * R + 1) * SROW; e += 256) {
-    const int r = e / SROW, cx = e % SROW;
-    sP[e] = (bf16)src.at(b, 2 * oy0 - 1 + r, cx - 1);
-  }
-  bf16x8 wa[NT];
-  float bv[NT][4];
-#pragma unroll
-  for (int t = 0; t < NT; ++t) {
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int tap = 8 * g + q;
-      wa[t][q] = tap < 9 ? W[(16 * t + i) * 9 + tap] : (bf16)0.0f;
-    }
-#pragma unroll
-    for (int r = 0; r < 4; ++r) bv[t][r] = bias[16 * t + 4 * g + r];
-  }
-  __syncthreads();
-#pragma unroll 1
-  for (int tt = wave; tt < NTILE; tt += 4) {
-    const int pl = 16 * tt + i, oyl = pl / HOUT, ox = pl % HOUT;
-    bf16x8 xb = zero8();
-    if (g < 2) {
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int tap = 8 * g + q;
-        if (tap < 9) xb[q] = sP[(2 * oyl + tap / 3) * SROW + 2 * ox + tap % 3];
-      }
-    }
-    const int64_t pix = tile * (R * HOUT) + pl;
-    bf16* op = out + pix * COUT;
-    uint32_t bits = 0;
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      // D[4 g + r][i]: channel 16 t + 4 g + r of pixel i
-      const floatx4 d = mfma(wa[t], xb, floatx4{0.f, 0.f, 0.f, 0.f});
-      float v[4];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) v[r] = fmaxf(d[r] + bv[t][r], 0.0f);
-      const uint2 w = uint2{pack2(v[0], v[1]), pack2(v[2], v[3])};
-      *reinterpret_cast<uint2*>(op + 16 * t + 4 * g) = w;
-      bits |= sign4(w) << (4 * t);
-    }
-    sign[4 * pix + g] = (uint8_t)bits;
-  }
-}
-
-// ---------------------------------------------------------------------------
 // Forward convolution, layers after the first: one wave = MT column tiles of
 // 16 output pixels x all COUT channels, so every weight fragment it reads
 // feeds MT products (MT = 4, or 2 for 128 channels; more or fewer measured
@@ -345,7 +272,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd_lds(int64_t npix, const bf16* 
 }
 
 // ---------------------------------------------------------------------------
-// Inference: conv1 fused into conv2.  A workgroup owns 8 x 8 output pixels of
+// conv1 fused into conv2 (inference and training).  A workgroup owns 8 x 8 output pixels of
 // conv2 (all 64 channels) at a time: it gathers the 35 x 35 patch window those
 // pixels depend on, computes the 17 x 17 x 32 conv1 outputs of the window into
 // LDS (zero where conv1's 64 x 64 grid ends: conv2's zero padding), then conv2
@@ -355,7 +282,12 @@ __global__ __launch_bounds__(256) void k_conv_fwd_lds(int64_t npix, const bf16* 
 // Persistent workgroups stage W2 in LDS once (laid out [tap][ci/8][co][8], so
 // the 16 lanes of a fragment read 16 consecutive 16-byte rows) and keep W1 in
 // registers; the next tile's patch gathers are issued before the current tile
-// is computed.
+// is computed.  In training (SAVE) the kernel also stores conv1's activations
+// and both layers' ReLU sign words for the backward pass: a tile owns the
+// conv1 pixels of window rows and columns 1 .. 16 (conv1 rows 2 oy0 .. 2 oy0 +
+// 15; row 0 of the window belongs to the tile above), so each conv1 pixel is
+// stored once.  The products are the same MFMA with the same operands as the
+// stand-alone first convolution, so the values match it.
 // ---------------------------------------------------------------------------
 constexpr int kT2 = 8;                 // conv2 tile edge (output pixels)
 constexpr int kT1 = 2 * kT2 + 1;       // 17: conv1 window edge
@@ -404,12 +336,16 @@ FSMI_DEV void gather_window(const PatchSrc& src, int64_t tile, const WinOffs& w,
   }
 }
 
+template <bool SAVE>
 __global__ __launch_bounds__(256) void k_conv12_fwd(int64_t n_tiles, PatchSrc src,
                                                     const bf16* __restrict__ W1,
                                                     const float* __restrict__ b1,
                                                     const bf16* __restrict__ W2,
                                                     const float* __restrict__ b2,
-                                                    bf16* __restrict__ act2) {
+                                                    bf16* __restrict__ act2,
+                                                    bf16* __restrict__ act1,
+                                                    uint8_t* __restrict__ sign1,
+                                                    uint16_t* __restrict__ sign2) {
   __shared__ __align__(16) bf16 sW2[kW2Elems];
   __shared__ __align__(16) bf16 sP[kTP * kTP + 8];
   __shared__ __align__(16) bf16 sA1[kT1 * kT1 * kA1Px];
@@ -489,6 +425,9 @@ __global__ __launch_bounds__(256) void k_conv12_fwd(int64_t n_tiles, PatchSrc sr
       }
       const int y1 = 2 * oy0 - 1 + pr, x1 = 2 * ox0 - 1 + pc;
       const bool inside = pv && y1 >= 0 && y1 < 64 && x1 >= 0 && x1 < 64;
+      const bool owned = SAVE && pv && pr >= 1 && pc >= 1;   // implies inside
+      const int64_t pix1 = (b * 64 + y1) * 64 + x1;
+      uint32_t bits = 0;
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
         // D[n][p]: channels 16t + 4g + r of pixel p
@@ -504,8 +443,13 @@ __global__ __launch_bounds__(256) void k_conv12_fwd(int64_t n_tiles, PatchSrc sr
           w.x = pack2(o[0], o[1]);
           w.y = pack2(o[2], o[3]);
           *reinterpret_cast<uint2*>(sA1 + p * kA1Px + 16 * t + 4 * g) = w;
+          if (owned) {
+            *reinterpret_cast<uint2*>(act1 + pix1 * 32 + 16 * t + 4 * g) = w;
+            bits |= sign4(w) << (4 * t);
+          }
         }
       }
+      if (owned) sign1[4 * pix1 + g] = (uint8_t)bits;
     }
     __syncthreads();
     // conv2: wave w takes output pixels 16w .. 16w + 15 of the 8 x 8 tile
@@ -522,7 +466,9 @@ __global__ __launch_bounds__(256) void k_conv12_fwd(int64_t n_tiles, PatchSrc sr
         acc[t] = mfma(load8(sW2 + ((tap * 4 + g) * 64 + 16 * t + i) * 8), x, acc[t]);
     }
     const int oy = oy0 + qy, ox = ox0 + qx;
-    bf16* op = act2 + ((b * 32 + oy) * 32 + ox) * 64 + 4 * g;
+    const int64_t pix2 = (b * 32 + oy) * 32 + ox;
+    bf16* op = act2 + pix2 * 64 + 4 * g;
+    uint32_t bits = 0;
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       float o[4];
@@ -535,7 +481,9 @@ __global__ __launch_bounds__(256) void k_conv12_fwd(int64_t n_tiles, PatchSrc sr
       w.x = pack2(o[0], o[1]);
       w.y = pack2(o[2], o[3]);
       *reinterpret_cast<uint2*>(op + 16 * t) = w;
+      bits |= sign4(w) << (4 * t);
     }
+    if (SAVE) sign2[4 * pix2 + g] = (uint16_t)bits;
     __syncthreads();   // sP and sA1 are rewritten by the next tile
   }
 }
@@ -1409,41 +1357,38 @@ static hipError_t cast_weights(fsmi_sur net) {
   return hipGetLastError();
 }
 
-template <int L, bool FIRST>
-static void conv_fwd(fsmi_sur net, int64_t nb, PatchSrc src, bool save) {
+// Layers after the first two (conv1 and conv2 run fused in k_conv12_fwd).
+template <int L>
+static void conv_fwd(fsmi_sur net, int64_t nb, bool save) {
   constexpr LayerDims d = kL[L];
+  static_assert(L >= 2, "conv1 and conv2 run in k_conv12_fwd");
   const int64_t npix = nb * (d.hin / 2) * (d.hin / 2);
-  if constexpr (FIRST) {
-    static_assert(d.cin == 1, "the first convolution reads one channel");
-    hipLaunchKernelGGL((k_conv1_fwd<d.cout, d.hin>), dim3((unsigned)(nb * (d.hin / 2) / 4)), dim3(256),
-                       0, net->ctx->stream, src, net->Wbf + wbf_off(L), net->P + b_off(L),
-                       net->act[L + 1], reinterpret_cast<uint8_t*>(net->sign[1]));
-  } else {
-    constexpr int per_block = 4 * 16 * conv_mt<d.cin, d.cout, d.hin>();   // 4 waves
-    const int64_t blocks = (npix + per_block - 1) / per_block;
-    hipLaunchKernelGGL((k_conv_fwd_lds<d.cin, d.cout, d.hin>), dim3((unsigned)blocks), dim3(256), 0,
-                       net->ctx->stream, npix, net->act[L], net->Wbf + wbf_off(L), net->P + b_off(L),
-                       net->act[L + 1], save && L + 1 <= 4 ? net->sign[L + 1] : nullptr);
-  }
+  constexpr int per_block = 4 * 16 * conv_mt<d.cin, d.cout, d.hin>();   // 4 waves
+  const int64_t blocks = (npix + per_block - 1) / per_block;
+  hipLaunchKernelGGL((k_conv_fwd_lds<d.cin, d.cout, d.hin>), dim3((unsigned)blocks), dim3(256), 0,
+                     net->ctx->stream, npix, net->act[L], net->Wbf + wbf_off(L), net->P + b_off(L),
+                     net->act[L + 1], save && L + 1 <= 4 ? net->sign[L + 1] : nullptr);
 }
 
 // Forward of nb (<= max_batch) poses; predictions (standardised) in ypred.
 static hipError_t sur_fwd_batch(fsmi_sur net, int64_t nb, PatchSrc src, bool save) {
-  if (save) {   // training keeps conv1's activations for the backward pass
-    conv_fwd<0, true>(net, nb, src, save);
-    conv_fwd<1, false>(net, nb, src, save);
-  } else {
-    static_assert(kL[0].cout == 32 && kL[1].cin == 32 && kL[1].cout == 64 && kL[1].hin == 64,
-                  "k_conv12_fwd is written for conv1 1->32 on 128^2 and conv2 32->64");
-    const int64_t n_tiles = nb * 16;
-    const int grid = (int)std::min<int64_t>(n_tiles, (int64_t)net->ctx->num_cu * 2);
-    hipLaunchKernelGGL(k_conv12_fwd, dim3(grid), dim3(256), 0, net->ctx->stream, n_tiles, src,
-                       net->Wbf + wbf_off(0), net->P + b_off(0), net->Wbf + wbf_off(1),
-                       net->P + b_off(1), net->act[2]);
-  }
-  conv_fwd<2, false>(net, nb, src, save);
-  conv_fwd<3, false>(net, nb, src, save);
-  conv_fwd<4, false>(net, nb, src, save);
+  static_assert(kL[0].cout == 32 && kL[1].cin == 32 && kL[1].cout == 64 && kL[1].hin == 64,
+                "k_conv12_fwd is written for conv1 1->32 on 128^2 and conv2 32->64");
+  const int64_t n_tiles = nb * 16;
+  const int grid12 = (int)std::min<int64_t>(n_tiles, (int64_t)net->ctx->num_cu * 2);
+  if (save)   // training keeps conv1's activations and the sign words
+    hipLaunchKernelGGL(k_conv12_fwd<true>, dim3(grid12), dim3(256), 0, net->ctx->stream, n_tiles,
+                       src, net->Wbf + wbf_off(0), net->P + b_off(0), net->Wbf + wbf_off(1),
+                       net->P + b_off(1), net->act[2], net->act[1],
+                       reinterpret_cast<uint8_t*>(net->sign[1]),
+                       reinterpret_cast<uint16_t*>(net->sign[2]));
+  else
+    hipLaunchKernelGGL(k_conv12_fwd<false>, dim3(grid12), dim3(256), 0, net->ctx->stream, n_tiles,
+                       src, net->Wbf + wbf_off(0), net->P + b_off(0), net->Wbf + wbf_off(1),
+                       net->P + b_off(1), net->act[2], nullptr, nullptr, nullptr);
+  conv_fwd<2>(net, nb, save);
+  conv_fwd<3>(net, nb, save);
+  conv_fwd<4>(net, nb, save);
   const int grid = (int)std::min<int64_t>(nb, 65535);
   hipLaunchKernelGGL(k_head_fwd, dim3(grid), dim3(256), 0, net->ctx->stream, nb, net->act[5], net->P,
                      save ? net->gsave : nullptr, save ? net->hsave : nullptr, net->ypred);
