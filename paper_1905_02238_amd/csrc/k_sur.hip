@@ -507,104 +507,214 @@ __global__ __launch_bounds__(256) void k_conv12_fwd(int64_t n_tiles, PatchSrc sr
 //   of d_out, staged once in LDS for the four waves (each reads it about 2.25
 //   times over).  nq = batch x (HIN / 2)^2 is a multiple of 16, and tiles
 //   start on row boundaries.
+// With WG1 (conv2's pass, whose d_in is d_out of conv1) the pass also takes
+//   conv1's weight gradient, so conv1's d_out never reaches HBM: a workgroup
+//   runs tiles_per_wg consecutive tiles, and each tile writes its 256 masked
+//   BF16 gradients (the values d_in would hold) channel-major into LDS, stages
+//   the 9 patch rows under its 4 conv1 rows, and adds to partial[s][co][col] =
+//   sum over the tile's pixels p of d_in[p][co] B[p][col], col = tap (the
+//   patch pixel under the tap), 9 (1: the bias) or 10..15 (0), the layout of
+//   the later layers' weight-gradient partials, s = the workgroup.  Its four
+//   waves take alternate 32-pixel steps; their sums are added in wave order at
+//   the end, so the result is deterministic.
 // ---------------------------------------------------------------------------
 template <int CIN, int COUT, int HIN>
 constexpr int dgrad_mt() { return CIN >= 128 ? 2 : 4; }
+// WG1 workgroups per compute unit: the kernel is held to 4 waves per SIMD, so
+// 4 workgroups of 4 waves fill a compute unit, and one such round of
+// workgroups is the grid (each takes an equal run of tiles)
+constexpr int kWg1PerCu = 4;
 
-template <int CIN, int COUT, int HIN>
-__global__ __launch_bounds__(256) void k_conv_dgrad(int64_t nq, const bf16* __restrict__ dout,
+template <int CIN, int COUT, int HIN, bool WG1>
+__global__ __launch_bounds__(256, WG1 ? 4 : 1) void k_conv_dgrad(int64_t nq, int tiles_per_wg,
+                                                    const bf16* __restrict__ dout,
                                                     const bf16* __restrict__ Wt,
                                                     const bf16* __restrict__ act_in,
                                                     const void* __restrict__ sign,
-                                                    bf16* __restrict__ din) {
+                                                    bf16* __restrict__ din, PatchSrc src,
+                                                    float* __restrict__ part) {
   constexpr int HOUT = HIN / 2, NT = CIN / 16, KC = COUT / 32, MT = dgrad_mt<CIN, COUT, HIN>();
   constexpr int TQ = 16 * MT, ROWD = COUT + 8;   // positions per tile; LDS row (one d_out pixel)
   static_assert(TQ % HOUT == 0, "tiles hold whole rows");
+  static_assert(!WG1 || (CIN == 32 && HIN == 64 && TQ == 2 * HOUT && HIN * 2 == kPatch),
+                "WG1: conv2's pass, tiles of two half-resolution rows (4 conv1 rows)");
+  // WG1: KW = 4 TQ pixels per tile (the K of conv1's weight-gradient products),
+  // stored channel-major with rows of KW + 8; SROW: a patch row with a zero
+  // column on each side
+  constexpr int KW = 4 * TQ, ROWA = KW + 8, SROW = kPatch + 2;
   __shared__ __align__(16) bf16 sD[(TQ + HOUT) * ROWD];
+  __shared__ __align__(16) bf16 sA[WG1 ? CIN * ROWA : 8];
+  __shared__ __align__(16) bf16 sPt[WG1 ? 9 * SROW : 8];
   const int tid = threadIdx.x, lane = tid & 63;
   const int cls = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int py = cls >> 1, px = cls & 1;
-  const int64_t base = (int64_t)blockIdx.x * TQ;
-  const int n_mt = (int)min<int64_t>(MT, (nq - base) / 16);   // >= 1: the grid covers nq exactly
   const int i = lane & 15, g = lane >> 4;
-  for (int e = tid; e < (TQ + HOUT) * (COUT / 8); e += 256) {
-    const int px8 = e / (COUT / 8), c8 = e % (COUT / 8);
-    const int64_t q = base + px8;
-    *reinterpret_cast<bf16x8*>(sD + px8 * ROWD + 8 * c8) = q < nq ? load8(dout + q * COUT + 8 * c8) : zero8();
-  }
-  __syncthreads();
-  int64_t qb[MT];
-  int qa[MT], qc[MT];
+  const int64_t n_tiles = (nq + TQ - 1) / TQ;
+  const int64_t tile0 = (int64_t)blockIdx.x * tiles_per_wg;
+  // without WG1 a workgroup takes one tile (tiles_per_wg is 1 and the grid is n_tiles)
+  const int64_t tile1 = WG1 ? min<int64_t>(tile0 + tiles_per_wg, n_tiles) : tile0 + 1;
+  floatx4 accw[NT];
 #pragma unroll
-  for (int m = 0; m < MT; ++m) {
-    const int64_t q = min<int64_t>(base + 16 * m + i, nq - 1);
-    qb[m] = q / (HOUT * HOUT);
-    qa[m] = (int)((q / HOUT) % HOUT);
-    qc[m] = (int)(q % HOUT);
-  }
-  floatx4 acc[MT][NT];
-#pragma unroll
-  for (int m = 0; m < MT; ++m)
-#pragma unroll
-    for (int t = 0; t < NT; ++t) acc[m][t] = floatx4{0.f, 0.f, 0.f, 0.f};
-  const int nky = 1 + py, nkx = 1 + px;
+  for (int t = 0; t < NT; ++t) accw[t] = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll 1
-  for (int jy = 0; jy < nky; ++jy) {
-#pragma unroll 1
-    for (int jx = 0; jx < nkx; ++jx) {
-      // odd row: ky = 0 reads output row a + 1, ky = 2 row a; even row: ky = 1, row a
-      const int ky = py ? 2 * jy : 1, kx = px ? 2 * jx : 1;
-      const int dy = (py && jy == 0) ? 1 : 0, dx = (px && jx == 0) ? 1 : 0;
-      const int tap = 3 * ky + kx;
-      bf16x8 a[MT][KC];
+  for (int64_t tile = tile0; tile < tile1; ++tile) {
+    const int64_t base = tile * TQ;
+    const int n_mt = (int)min<int64_t>(MT, (nq - base) / 16);   // >= 1: nq is a multiple of 16
+    __syncthreads();   // the previous tile's LDS reads are done
+    for (int e = tid; e < (TQ + HOUT) * (COUT / 8); e += 256) {
+      const int px8 = e / (COUT / 8), c8 = e % (COUT / 8);
+      const int64_t q = base + px8;
+      *reinterpret_cast<bf16x8*>(sD + px8 * ROWD + 8 * c8) = q < nq ? load8(dout + q * COUT + 8 * c8) : zero8();
+    }
+    if constexpr (WG1) {
+      // staged row r = patch row 4 a0 - 1 + r (a0: the tile's first half-row)
+      const int64_t b0 = base / (HOUT * HOUT);
+      const int a0 = (int)((base / HOUT) % HOUT);
+      for (int e = tid; e < 9 * SROW; e += 256) {
+        const int r = e / SROW, cx = e - r * SROW;
+        sPt[e] = (bf16)src.at(b0, 4 * a0 - 1 + r, cx - 1);
+      }
+    }
+    __syncthreads();
+    int64_t qb[MT];
+    int qa[MT], qc[MT];
 #pragma unroll
-      for (int m = 0; m < MT; ++m) {
-        // d_out pixel (b, a + dy, c + dx) = position q + dy HOUT + dx
-        const bool ok = m < n_mt && qa[m] + dy < HOUT && qc[m] + dx < HOUT;
-        const bf16* dp = sD + (ok ? 16 * m + i + dy * HOUT + dx : 0) * ROWD;
+    for (int m = 0; m < MT; ++m) {
+      const int64_t q = min<int64_t>(base + 16 * m + i, nq - 1);
+      qb[m] = q / (HOUT * HOUT);
+      qa[m] = (int)((q / HOUT) % HOUT);
+      qc[m] = (int)(q % HOUT);
+    }
+    floatx4 acc[MT][NT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+      for (int t = 0; t < NT; ++t) acc[m][t] = floatx4{0.f, 0.f, 0.f, 0.f};
+    const int nky = 1 + py, nkx = 1 + px;
+#pragma unroll 1
+    for (int jy = 0; jy < nky; ++jy) {
+#pragma unroll 1
+      for (int jx = 0; jx < nkx; ++jx) {
+        // odd row: ky = 0 reads output row a + 1, ky = 2 row a; even row: ky = 1, row a
+        const int ky = py ? 2 * jy : 1, kx = px ? 2 * jx : 1;
+        const int dy = (py && jy == 0) ? 1 : 0, dx = (px && jx == 0) ? 1 : 0;
+        const int tap = 3 * ky + kx;
+        bf16x8 a[MT][KC];
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+          // d_out pixel (b, a + dy, c + dx) = position q + dy HOUT + dx
+          const bool ok = m < n_mt && qa[m] + dy < HOUT && qc[m] + dx < HOUT;
+          const bf16* dp = sD + (ok ? 16 * m + i + dy * HOUT + dx : 0) * ROWD;
+#pragma unroll
+          for (int c = 0; c < KC; ++c)
+            a[m][c] = ok ? *reinterpret_cast<const bf16x8*>(dp + 32 * c + 8 * g) : zero8();
+        }
 #pragma unroll
         for (int c = 0; c < KC; ++c)
-          a[m][c] = ok ? *reinterpret_cast<const bf16x8*>(dp + 32 * c + 8 * g) : zero8();
-      }
 #pragma unroll
-      for (int c = 0; c < KC; ++c)
+          for (int t = 0; t < NT; ++t) {
+            const bf16x8 w = load8(Wt + (tap * CIN + 16 * t + i) * COUT + 32 * c + 8 * g);
+#pragma unroll
+            for (int m = 0; m < MT; ++m) acc[m][t] = mfma(w, a[m][c], acc[m][t]);
+          }
+      }
+    }
+    // D[4 g + r][i]: channel 16 t + 4 g + r of pixel (m, i)
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+      if (m >= n_mt) {
+        if constexpr (WG1) {   // positions past nq add nothing
+#pragma unroll
+          for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) sA[(16 * t + 4 * g + r) * ROWA + cls * TQ + 16 * m + i] = (bf16)0.0f;
+          continue;
+        } else {
+          break;
+        }
+      }
+      const int iy = 2 * qa[m] + py, ix = 2 * qc[m] + px;
+      const int64_t p = (qb[m] * HIN + iy) * HIN + ix;
+      // with sign words (SignWord): bit 4 t + r of word g
+      typedef typename SignWord<NT>::type S;
+      const uint32_t sb = sign ? (uint32_t)reinterpret_cast<const S*>(sign)[4 * p + g] : 0u;
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const int ci = 16 * t + 4 * g;
+        float mk[4];
+        if (sign) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) mk[r] = (sb >> (4 * t + r)) & 1u ? 1.0f : 0.0f;
+        } else {
+          const uint2 av = *reinterpret_cast<const uint2*>(act_in + p * CIN + ci);
+          // the BF16 activations widened to FP32 (the low half first)
+          const uint32_t aw[2] = {av.x, av.y};
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            mk[2 * h] = __builtin_bit_cast(float, aw[h] << 16) > 0.0f ? 1.0f : 0.0f;
+            mk[2 * h + 1] = __builtin_bit_cast(float, aw[h] & 0xffff0000u) > 0.0f ? 1.0f : 0.0f;
+          }
+        }
+        const uint2 w = uint2{pack2(acc[m][t][0] * mk[0], acc[m][t][1] * mk[1]),
+                              pack2(acc[m][t][2] * mk[2], acc[m][t][3] * mk[3])};
+        if constexpr (WG1) {
+          // channel-major: row = channel, column = class, then position in the tile
+          uint16_t* sa = reinterpret_cast<uint16_t*>(sA) + ci * ROWA + cls * TQ + 16 * m + i;
+          sa[0] = (uint16_t)(w.x & 0xffffu);
+          sa[ROWA] = (uint16_t)(w.x >> 16);
+          sa[2 * ROWA] = (uint16_t)(w.y & 0xffffu);
+          sa[3 * ROWA] = (uint16_t)(w.y >> 16);
+        } else {
+          *reinterpret_cast<uint2*>(din + p * CIN + ci) = w;
+        }
+      }
+    }
+    if constexpr (WG1) {
+      __syncthreads();   // sA holds the tile's 256 pixels
+      bf16x8 ones;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) ones[q] = (bf16)1.0f;
+      const int ky = i / 3, kx = i - 3 * (i / 3);
+#pragma unroll
+      for (int u = 0; u < KW / 128; ++u) {
+        // pixels k = 32 ks + 8 g + j (j < 8): class kc, positions kq0 + j of the
+        // tile, i.e. half-row a0 + da, columns c0 + j of that class
+        const int ks = cls + 4 * u;
+        const int k0 = 32 * ks + 8 * g, kc = k0 / TQ, kq0 = k0 - kc * TQ;
+        const int da = kq0 / HOUT, c0 = kq0 - da * HOUT;
+        bf16x8 fb;
+        if (i < 9) {
+          const bf16* sp = sPt + (4 * da + 2 * (kc >> 1) + ky) * SROW + 4 * c0 + 2 * (kc & 1) + kx;
+#pragma unroll
+          for (int j = 0; j < 8; ++j) fb[j] = sp[4 * j];
+        } else {
+          fb = i == 9 ? ones : zero8();
+        }
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
-          const bf16x8 w = load8(Wt + (tap * CIN + 16 * t + i) * COUT + 32 * c + 8 * g);
-#pragma unroll
-          for (int m = 0; m < MT; ++m) acc[m][t] = mfma(w, a[m][c], acc[m][t]);
-        }
-    }
-  }
-  // D[4 g + r][i]: channel 16 t + 4 g + r of pixel (m, i)
-#pragma unroll
-  for (int m = 0; m < MT; ++m) {
-    if (m >= n_mt) break;
-    const int iy = 2 * qa[m] + py, ix = 2 * qc[m] + px;
-    const int64_t p = (qb[m] * HIN + iy) * HIN + ix;
-    // with sign words (SignWord): bit 4 t + r of word g
-    typedef typename SignWord<NT>::type S;
-    const uint32_t sb = sign ? (uint32_t)reinterpret_cast<const S*>(sign)[4 * p + g] : 0u;
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      const int ci = 16 * t + 4 * g;
-      float mk[4];
-      if (sign) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) mk[r] = (sb >> (4 * t + r)) & 1u ? 1.0f : 0.0f;
-      } else {
-        const uint2 av = *reinterpret_cast<const uint2*>(act_in + p * CIN + ci);
-        // the BF16 activations widened to FP32 (the low half first)
-        const uint32_t aw[2] = {av.x, av.y};
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          mk[2 * h] = __builtin_bit_cast(float, aw[h] << 16) > 0.0f ? 1.0f : 0.0f;
-          mk[2 * h + 1] = __builtin_bit_cast(float, aw[h] & 0xffff0000u) > 0.0f ? 1.0f : 0.0f;
+          const bf16x8 fa = *reinterpret_cast<const bf16x8*>(sA + (16 * t + i) * ROWA + 32 * ks + 8 * g);
+          accw[t] = mfma(fa, fb, accw[t]);
         }
       }
-      *reinterpret_cast<uint2*>(din + p * CIN + ci) =
-          uint2{pack2(acc[m][t][0] * mk[0], acc[m][t][1] * mk[1]),
-                pack2(acc[m][t][2] * mk[2], acc[m][t][3] * mk[3])};
+    }
+  }   // tiles
+  if constexpr (WG1) {
+    __syncthreads();   // every wave is done with sA
+    floatx4* red = reinterpret_cast<floatx4*>(sA);   // [wave][t][lane]
+    static_assert(4 * NT * 64 * sizeof(floatx4) <= sizeof(bf16) * CIN * ROWA, "red fits in sA");
+#pragma unroll
+    for (int t = 0; t < NT; ++t) red[(cls * NT + t) * 64 + lane] = accw[t];
+    __syncthreads();
+    if (cls == 0) {
+      // D[4 g + r][i]: co = 16 t + 4 g + r, column i
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const floatx4 d = ((red[t * 64 + lane] + red[(NT + t) * 64 + lane]) + red[(2 * NT + t) * 64 + lane]) +
+                          red[(3 * NT + t) * 64 + lane];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          part[((int64_t)blockIdx.x * CIN + 16 * t + 4 * g + r) * 16 + i] = d[r];
+      }
     }
   }
 }
@@ -665,91 +775,6 @@ FSMI_DEV void transpose4x8(const bf16x8 (&v)[4], uint2 (&row)[8]) {
                        __builtin_amdgcn_perm(x[3][d], x[2][d], 0x05040100u)};
     row[2 * d + 1] = uint2{__builtin_amdgcn_perm(x[1][d], x[0][d], 0x07060302u),
                            __builtin_amdgcn_perm(x[3][d], x[2][d], 0x07060302u)};
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Weight-gradient pass, first layer: partial[s][co][col] = sum over the
-//   output pixels p of split s of d_out[p][co] B[p][col], col = tap (the patch
-//   pixel under the tap), 9 (1: the bias) or 10..15 (0).  A workgroup stages
-//   256 pixels at a time in LDS: d_out channel-major as in the later layers
-//   (transpose4x8), and the nine tap values of every pixel as rows
-//   [tap][pixel]; its four waves take alternate 32-pixel steps, and their sums
-//   are added in wave order at the end.  Pixels past the split read 0.
-// ---------------------------------------------------------------------------
-template <int COUT, int HIN>
-__global__ __launch_bounds__(256) void k_conv_wgrad_first(int64_t npix_out, int chunk,
-                                                          const bf16* __restrict__ dout, PatchSrc src,
-                                                          float* __restrict__ part) {
-  constexpr int HOUT = HIN / 2, NCOL = 16, KS = 256, ROW = KS + 8, NMT = COUT / 16;
-  constexpr int QK = KS / 4, UA = QK * (COUT / 8);
-  __shared__ __align__(16) bf16 sA[COUT * ROW];
-  __shared__ __align__(16) bf16 sB[9 * ROW];
-  __shared__ floatx4 red[4][NMT][64];
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int i = lane & 15, g = lane >> 4;
-  const int s = blockIdx.x;
-  const int64_t p0 = (int64_t)s * chunk;
-  const int64_t p1 = min<int64_t>(p0 + chunk, npix_out);
-  const int nstage = (int)((p1 - p0 + KS - 1) / KS);
-  floatx4 acc[NMT];
-#pragma unroll
-  for (int ct = 0; ct < NMT; ++ct) acc[ct] = floatx4{0.f, 0.f, 0.f, 0.f};
-  bf16x8 ones;
-#pragma unroll
-  for (int q = 0; q < 8; ++q) ones[q] = (bf16)1.0f;
-#pragma unroll 1
-  for (int st = 0; st < nstage; ++st) {
-    const int64_t k0 = p0 + (int64_t)st * KS;
-    __syncthreads();   // every wave is done reading the previous stage
-    for (int u = tid; u < UA; u += 256) {
-      const int pq = u % QK, o = u / QK;
-      bf16x8 v[4];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int64_t p = k0 + 4 * pq + j;
-        v[j] = p < p1 ? load8(dout + p * COUT + 8 * o) : zero8();
-      }
-      uint2 rows[8];
-      transpose4x8(v, rows);
-#pragma unroll
-      for (int k = 0; k < 8; ++k) *reinterpret_cast<uint2*>(sA + (8 * o + k) * ROW + 4 * pq) = rows[k];
-    }
-    for (int e = tid; e < 9 * KS; e += 256) {
-      const int tap = e / KS, pl = e % KS;
-      const int64_t p = k0 + pl;
-      float v = 0.0f;
-      if (p < p1) {
-        const int64_t b = p / (HOUT * HOUT);
-        const int oy = (int)((p / HOUT) % HOUT), ox = (int)(p % HOUT);
-        v = src.at(b, 2 * oy + tap / 3 - 1, 2 * ox + tap % 3 - 1);
-      }
-      sB[tap * ROW + pl] = (bf16)v;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int ks = wave; ks < KS / 32; ks += 4) {
-      const bf16x8 fb = i < 9 ? *reinterpret_cast<const bf16x8*>(sB + i * ROW + 32 * ks + 8 * g)
-                              : (i == 9 ? ones : zero8());
-#pragma unroll
-      for (int ct = 0; ct < NMT; ++ct) {
-        const bf16x8 fa = *reinterpret_cast<const bf16x8*>(sA + (16 * ct + i) * ROW + 32 * ks + 8 * g);
-        acc[ct] = mfma(fa, fb, acc[ct]);
-      }
-    }
-  }
-#pragma unroll
-  for (int ct = 0; ct < NMT; ++ct) red[wave][ct][lane] = acc[ct];
-  __syncthreads();
-  if (wave == 0) {
-    // D[4 g + r][i]: co = 16 ct + 4 g + r, column i
-#pragma unroll
-    for (int ct = 0; ct < NMT; ++ct) {
-      const floatx4 d = ((red[0][ct][lane] + red[1][ct][lane]) + red[2][ct][lane]) + red[3][ct][lane];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) part[((int64_t)s * COUT + 16 * ct + 4 * g + r) * NCOL + i] = d[r];
-    }
   }
 }
 
@@ -1254,9 +1279,31 @@ struct fsmi_sur_s {
 namespace fsmi {
 
 // Output pixels per weight-gradient split, and taps per workgroup of the
-// weight-gradient kernel, per layer.
-static constexpr int kWgChunk[5] = {4096, 2048, 2048, 1024, 1024};
+// weight-gradient kernel, per layer (conv1's weight gradient is taken inside
+// conv2's input-gradient pass, in wg1_splits(nb) splits).
+static constexpr int kWgChunk[5] = {0, 2048, 2048, 1024, 1024};
 static constexpr int kWgTpg[5] = {0, 9, 3, 3, 1};
+
+// Splits (workgroups) of conv2's input-gradient pass with conv1's weight
+// gradient fused in, for nb poses, and the tiles each takes.  With n tiles
+// and W = kWg1PerCu x num_cu, the splits are ceil(n / ceil(n / W)) <= min(n,
+// W); that count is not monotone in n (n = W gives W, n = W + 1 gives about
+// W / 2), so the partial buffer is sized by wg1_max_splits, min(n, W) at the
+// largest batch.
+static int64_t wg1_tiles(int64_t nb) {
+  constexpr int tq = 16 * dgrad_mt<kL[1].cin, kL[1].cout, kL[1].hin>();
+  return nb * (kL[1].hin / 2) * (kL[1].hin / 2) / tq;
+}
+static int64_t wg1_splits(int64_t nb, int num_cu, int* tiles_per_wg) {
+  const int64_t n_tiles = wg1_tiles(nb);
+  const int64_t w = (int64_t)kWg1PerCu * num_cu;
+  const int64_t per = std::max<int64_t>(1, (n_tiles + w - 1) / w);
+  *tiles_per_wg = (int)per;
+  return (n_tiles + per - 1) / per;
+}
+static int64_t wg1_max_splits(int64_t max_batch, int num_cu) {
+  return std::min<int64_t>(wg1_tiles(max_batch), (int64_t)kWg1PerCu * num_cu);
+}
 
 static size_t act_elems(int l, int B) {   // elements of act[l] (output of conv l-1... l = 1..5)
   const int h = kL[l - 1].hin / 2;
@@ -1280,7 +1327,7 @@ static hipError_t sur_alloc(fsmi_sur net) {
   const int B = net->max_batch;
   for (int l = 1; l <= 5; ++l) {
     ALLOC(net->act[l], sizeof(bf16) * act_elems(l, B));
-    ALLOC(net->dact[l], sizeof(bf16) * act_elems(l, B));
+    if (l >= 2) ALLOC(net->dact[l], sizeof(bf16) * act_elems(l, B));   // conv1's d_out stays on chip
     if (l <= 4) ALLOC(net->sign[l], act_elems(l, B) / 8);   // one bit per channel
   }
   ALLOC(net->gsave, sizeof(float) * (size_t)B * kFeat);
@@ -1292,7 +1339,9 @@ static hipError_t sur_alloc(fsmi_sur net) {
   for (int l = 0; l < 5; ++l) {
     const int hout = kL[l].hin / 2;
     const size_t npix = (size_t)B * hout * hout;
-    const size_t splits = (npix + kWgChunk[l] - 1) / kWgChunk[l];
+    // conv1's weight gradient is taken inside conv2's input-gradient pass
+    const size_t splits =
+        l == 0 ? (size_t)wg1_max_splits(B, net->ctx->num_cu) : (npix + kWgChunk[l] - 1) / kWgChunk[l];
     const size_t ncol = l == 0 ? 16 : 9 * (size_t)kL[l].cin + 16;
     const size_t nout = (size_t)kL[l].cout * (9 * kL[l].cin + 1);
     mx = std::max(mx, splits * kL[l].cout * ncol);
@@ -1398,32 +1447,48 @@ static hipError_t sur_fwd_batch(fsmi_sur net, int64_t nb, PatchSrc src, bool sav
 template <int L>
 static void conv_dgrad(fsmi_sur net, int64_t nb) {
   constexpr LayerDims d = kL[L];
+  static_assert(L >= 2, "conv2's pass runs fused with conv1's weight gradient");
   constexpr int mt = dgrad_mt<d.cin, d.cout, d.hin>();
   const int64_t nq = nb * (d.hin / 2) * (d.hin / 2);   // a multiple of 16
-  hipLaunchKernelGGL((k_conv_dgrad<d.cin, d.cout, d.hin>),
+  hipLaunchKernelGGL((k_conv_dgrad<d.cin, d.cout, d.hin, false>),
                      dim3((unsigned)((nq + 16 * mt - 1) / (16 * mt))), dim3(256), 0, net->ctx->stream,
-                     nq, net->dact[L + 1], net->Wt + wbf_off(L), net->act[L],
-                     net->sign[L], net->dact[L]);
+                     nq, 1, net->dact[L + 1], net->Wt + wbf_off(L), net->act[L],
+                     net->sign[L], net->dact[L], PatchSrc{}, nullptr);
 }
 
-template <int L, bool FIRST>
-static void conv_wgrad(fsmi_sur net, int64_t nb, PatchSrc src) {
+// conv2's input gradient and conv1's weight gradient (k_conv_dgrad with WG1),
+// then conv1's partials summed in fixed order.
+static void conv2_dgrad_conv1_wgrad(fsmi_sur net, int64_t nb, PatchSrc src) {
+  constexpr LayerDims d1 = kL[1], d0 = kL[0];
+  hipStream_t st = net->ctx->stream;
+  const int64_t nq = nb * (d1.hin / 2) * (d1.hin / 2);
+  int per = 1;
+  const int splits = (int)wg1_splits(nb, net->ctx->num_cu, &per);
+  hipLaunchKernelGGL((k_conv_dgrad<d1.cin, d1.cout, d1.hin, true>), dim3(splits), dim3(256), 0, st, nq,
+                     per, net->dact[2], net->Wt + wbf_off(1), net->act[1], net->sign[1], nullptr,
+                     src, net->part);
+  constexpr int nout = d0.cout * 9 * d0.cin + d0.cout;
+  const int nrun = (splits + kRedRun - 1) / kRedRun;
+  hipLaunchKernelGGL((k_wgrad_reduce_runs<d0.cin, d0.cout, true>), dim3((nout + 63) / 64, nrun),
+                     dim3(256), 0, st, net->part, splits, net->runs);
+  hipLaunchKernelGGL((k_wgrad_reduce_final<d0.cin, d0.cout>), dim3((nout + 255) / 256), dim3(256), 0, st,
+                     net->runs, nrun, net->G + w_off(0), net->G + b_off(0));
+}
+
+template <int L>
+static void conv_wgrad(fsmi_sur net, int64_t nb) {
   constexpr LayerDims d = kL[L];
+  static_assert(L >= 1, "conv1's weight gradient is taken in conv2_dgrad_conv1_wgrad");
   hipStream_t st = net->ctx->stream;
   const int64_t npix = nb * (d.hin / 2) * (d.hin / 2);
   const int chunk = kWgChunk[L];
   const int splits = (int)((npix + chunk - 1) / chunk);
-  if constexpr (FIRST) {
-    hipLaunchKernelGGL((k_conv_wgrad_first<d.cout, d.hin>), dim3(splits), dim3(256), 0, st,
-                       npix, chunk, net->dact[L + 1], src, net->part);
-  } else {
-    constexpr int tpg = kWgTpg[L];
-    hipLaunchKernelGGL((k_conv_wgrad<d.cin, d.cout, d.hin, tpg>), dim3(splits, 9 / tpg), dim3(256), 0,
-                       st, npix, chunk, net->dact[L + 1], net->act[L], net->part);
-  }
+  constexpr int tpg = kWgTpg[L];
+  hipLaunchKernelGGL((k_conv_wgrad<d.cin, d.cout, d.hin, tpg>), dim3(splits, 9 / tpg), dim3(256), 0,
+                     st, npix, chunk, net->dact[L + 1], net->act[L], net->part);
   constexpr int nout = d.cout * 9 * d.cin + d.cout;
   const int nrun = (splits + kRedRun - 1) / kRedRun;
-  hipLaunchKernelGGL((k_wgrad_reduce_runs<d.cin, d.cout, FIRST>), dim3((nout + 63) / 64, nrun),
+  hipLaunchKernelGGL((k_wgrad_reduce_runs<d.cin, d.cout, false>), dim3((nout + 63) / 64, nrun),
                      dim3(256), 0, st, net->part, splits, net->runs);
   hipLaunchKernelGGL((k_wgrad_reduce_final<d.cin, d.cout>), dim3((nout + 255) / 256), dim3(256), 0, st,
                      net->runs, nrun, net->G + w_off(L), net->G + b_off(L));
@@ -1537,15 +1602,14 @@ fsmi_status fsmi_sur_backward(fsmi_sur net, const fsmi_map* map, int64_t n, cons
     hipLaunchKernelGGL(k_head_wgrad_final, dim3((kHeadOut + 255) / 256), dim3(256), 0, st, n, nchunk,
                        net->hpart, net->G, loss ? loss : net->loss);
   }
-  conv_wgrad<4, false>(net, n, src);
+  conv_wgrad<4>(net, n);
   conv_dgrad<4>(net, n);
-  conv_wgrad<3, false>(net, n, src);
+  conv_wgrad<3>(net, n);
   conv_dgrad<3>(net, n);
-  conv_wgrad<2, false>(net, n, src);
+  conv_wgrad<2>(net, n);
   conv_dgrad<2>(net, n);
-  conv_wgrad<1, false>(net, n, src);
-  conv_dgrad<1>(net, n);
-  conv_wgrad<0, true>(net, n, src);
+  conv_wgrad<1>(net, n);
+  conv2_dgrad_conv1_wgrad(net, n, src);
   return hipGetLastError() == hipSuccess ? FSMI_OK : FSMI_E_DEVICE;
 }
 
