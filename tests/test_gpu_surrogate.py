@@ -94,6 +94,29 @@ def test_forward_and_gradients_match_fp64_reference(ctx, stride, batch):
         assert cos >= 0.98, (name, cos, rel)
 
 
+def test_gradients_do_not_depend_on_max_batch(ctx):
+    """One batch gives bit-identical loss and gradients whether the network was
+    sized for exactly that batch or for a larger one.  conv1's weight gradient
+    runs in a grid of one resident round of workgroups, and the number of
+    partial sums it writes is not monotone in the batch (a batch of n tiles
+    can write more than a larger batch would), so the partial buffer sized at
+    max_batch must still hold what a smaller batch writes."""
+    wl = W.grid_small()
+    grid, lab = wl["grid"], wl["labels"]
+    poses = _poses_near_and_inside(lab, 64, 9)
+    labels = np.random.default_rng(2).normal(size=64)
+    out = []
+    for mb in (64, 67, 130):
+        print(f"[gpu] max_batch {mb}, batch 64", flush=True)
+        net = F.Surrogate(ctx, seed=7, max_batch=mb)
+        loss = net.backward(dev(grid), dev(poses), dev(labels))
+        out.append((float(loss[0]), net.grads().clone()))
+        net.close()
+    for loss, g in out[1:]:
+        assert loss == out[0][0]
+        assert torch.equal(g, out[0][1])
+
+
 def _labelled(ctx, seeds, n_poses, size=1024):
     """Exact per-pose FSMI labels on rooms maps (360 beams, R = 400, sigma = 3)."""
     out = []
