@@ -560,6 +560,24 @@ __global__ __launch_bounds__(256, WG1 ? 4 : 1) void k_conv_dgrad(int64_t nq, int
   for (int64_t tile = tile0; tile < tile1; ++tile) {
     const int64_t base = tile * TQ;
     const int n_mt = (int)min<int64_t>(MT, (nq - base) / 16);   // >= 1: nq is a multiple of 16
+    int64_t qb[MT];
+    int qa[MT], qc[MT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+      const int64_t q = min<int64_t>(base + 16 * m + i, nq - 1);
+      qb[m] = q / (HOUT * HOUT);
+      qa[m] = (int)((q / HOUT) % HOUT);
+      qc[m] = (int)(q % HOUT);
+    }
+    // the ReLU sign words (SignWord) of this lane's pixels, issued first so
+    // that their latency overlaps the staging and the products
+    typedef typename SignWord<NT>::type S;
+    uint32_t sbm[MT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+      const int64_t p = (qb[m] * HIN + 2 * qa[m] + py) * HIN + 2 * qc[m] + px;
+      sbm[m] = sign ? (uint32_t)reinterpret_cast<const S*>(sign)[4 * p + g] : 0u;
+    }
     __syncthreads();   // the previous tile's LDS reads are done
     for (int e = tid; e < (TQ + HOUT) * (COUT / 8); e += 256) {
       const int px8 = e / (COUT / 8), c8 = e % (COUT / 8);
@@ -576,15 +594,6 @@ __global__ __launch_bounds__(256, WG1 ? 4 : 1) void k_conv_dgrad(int64_t nq, int
       }
     }
     __syncthreads();
-    int64_t qb[MT];
-    int qa[MT], qc[MT];
-#pragma unroll
-    for (int m = 0; m < MT; ++m) {
-      const int64_t q = min<int64_t>(base + 16 * m + i, nq - 1);
-      qb[m] = q / (HOUT * HOUT);
-      qa[m] = (int)((q / HOUT) % HOUT);
-      qc[m] = (int)(q % HOUT);
-    }
     floatx4 acc[MT][NT];
 #pragma unroll
     for (int m = 0; m < MT; ++m)
@@ -635,9 +644,8 @@ __global__ __launch_bounds__(256, WG1 ? 4 : 1) void k_conv_dgrad(int64_t nq, int
       }
       const int iy = 2 * qa[m] + py, ix = 2 * qc[m] + px;
       const int64_t p = (qb[m] * HIN + iy) * HIN + ix;
-      // with sign words (SignWord): bit 4 t + r of word g
-      typedef typename SignWord<NT>::type S;
-      const uint32_t sb = sign ? (uint32_t)reinterpret_cast<const S*>(sign)[4 * p + g] : 0u;
+      // with sign words: bit 4 t + r of word g
+      const uint32_t sb = sbm[m];
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
         const int ci = 16 * t + 4 * g;
