@@ -77,53 +77,21 @@ FSMI_DEV bf16x8 zero8() {
   return z;
 }
 
-// Input of the first layer: patch pixel (iy, ix) of pose b, 0 outside the
-// padded patch, else the map's value (0.5 outside the map).  With cell stride
-// s > 1, `map` is the map of s x s block means and the patch is centred on the
-// block holding the pose's cell; s = 1 reads the map itself.
+// Input of the first layer: patch pixel (iy, ix) of pose b is 0 outside the
+// padded patch (iy or ix outside [0, 128)), else the map's value at cell
+// (block(x) - 64 + ix, block(y) - 64 + iy), 0.5 outside the map.  With cell
+// stride s > 1, `map` is the map of s x s block means and the patch is centred
+// on the block holding the pose's cell; s = 1 reads the map itself.
 struct PatchSrc {
   const float* map;
   int64_t X, Y;          // dims of `map`
   const double* poses;   // [n][4]
   int s;                 // cell stride
-  const bf16* patch = nullptr;   // [n][128][128] once gathered (training), else NULL
   FSMI_DEV int64_t block(double v) const {
     const int64_t c = (int64_t)floor(v);
     return c >= 0 ? c / s : -((-c + s - 1) / s);   // floor(c / s)
   }
-  FSMI_DEV float at(int64_t b, int iy, int ix) const {
-    if (iy < 0 || iy >= kPatch || ix < 0 || ix >= kPatch) return 0.0f;
-    if (patch) return (float)patch[(b * kPatch + iy) * kPatch + ix];
-    const int64_t cx = block(poses[4 * b]) - kPatch / 2 + ix;
-    const int64_t cy = block(poses[4 * b + 1]) - kPatch / 2 + iy;
-    if (cx < 0 || cx >= X || cy < 0 || cy >= Y) return 0.5f;
-    return map[cx + X * cy];
-  }
 };
-
-// The patches of n poses as BF16 [n][128][128], the values at() returns (src
-// reads the map: src.patch is NULL).  One thread per 8 consecutive pixels of a
-// patch row, stored as 16 bytes; the pose's block coordinates are taken once
-// per 8 pixels.
-__global__ void k_patch_gather(int64_t n, PatchSrc src, bf16* __restrict__ out) {
-  constexpr int U = kPatch / 8;   // units per patch row
-  for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < n * kPatch * U;
-       u += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t b = u / (kPatch * U);
-    const int r = (int)(u % (kPatch * U));
-    const int iy = r / U, ix0 = 8 * (r % U);
-    const int64_t cy = src.block(src.poses[4 * b + 1]) - kPatch / 2 + iy;
-    const int64_t cx0 = src.block(src.poses[4 * b]) - kPatch / 2 + ix0;
-    const bool row_in = cy >= 0 && cy < src.Y;
-    bf16x8 v;
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int64_t cx = cx0 + q;
-      v[q] = (bf16)((row_in && cx >= 0 && cx < src.X) ? src.map[cx + src.X * cy] : 0.5f);
-    }
-    *reinterpret_cast<bf16x8*>(out + (b * kPatch + iy) * kPatch + ix0) = v;
-  }
-}
 
 // Block means: out[v][u] = mean of the map's cells x in [s u, s u + s),
 // y in [s v, s v + s) that lie inside the map (FP64 sum, fixed order).
@@ -585,12 +553,21 @@ __global__ __launch_bounds__(256, WG1 ? 4 : 1) void k_conv_dgrad(int64_t nq, int
       *reinterpret_cast<bf16x8*>(sD + px8 * ROWD + 8 * c8) = q < nq ? load8(dout + q * COUT + 8 * c8) : zero8();
     }
     if constexpr (WG1) {
-      // staged row r = patch row 4 a0 - 1 + r (a0: the tile's first half-row)
+      // staged row r = patch row 4 a0 - 1 + r (a0: the tile's first half-row),
+      // staged column c = patch column c - 1, read from the map (PatchSrc)
       const int64_t b0 = base / (HOUT * HOUT);
       const int a0 = (int)((base / HOUT) % HOUT);
+      const int64_t mx0 = src.block(src.poses[4 * b0]) - kPatch / 2;
+      const int64_t my0 = src.block(src.poses[4 * b0 + 1]) - kPatch / 2;
       for (int e = tid; e < 9 * SROW; e += 256) {
-        const int r = e / SROW, cx = e - r * SROW;
-        sPt[e] = (bf16)src.at(b0, 4 * a0 - 1 + r, cx - 1);
+        const int r = e / SROW, c = e - r * SROW;
+        const int iy = 4 * a0 - 1 + r, ix = c - 1;
+        float v = 0.0f;
+        if ((unsigned)iy < (unsigned)kPatch && (unsigned)ix < (unsigned)kPatch) {
+          const int64_t mx = mx0 + ix, my = my0 + iy;
+          v = mx >= 0 && mx < src.X && my >= 0 && my < src.Y ? src.map[mx + src.X * my] : 0.5f;
+        }
+        sPt[e] = (bf16)v;
       }
     }
     __syncthreads();
@@ -1278,7 +1255,6 @@ struct fsmi_sur_s {
   size_t part_floats = 0;
   float* loss = nullptr;
   int stride = 1;            // cell stride of the patch
-  fsmi::bf16* patch = nullptr;   // the training batch's patches, allocated on first use
   void* sign[5] = {};            // sign[l]: ReLU sign words of act[l], l = 1..4 (training)
   float* pooled = nullptr;   // block means of the last map (stride > 1)
   size_t pooled_elems = 0;
@@ -1370,7 +1346,6 @@ static void sur_free(fsmi_sur net) {
   for (void* p : ps)
     if (p) (void)hipFree(p);
   if (net->pooled) (void)hipFree(net->pooled);
-  if (net->patch) (void)hipFree(net->patch);
   for (int l = 1; l <= 4; ++l)
     if (net->sign[l]) (void)hipFree(net->sign[l]);
   for (int l = 1; l <= 5; ++l) {
@@ -1582,18 +1557,6 @@ fsmi_status fsmi_sur_backward(fsmi_sur net, const fsmi_map* map, int64_t n, cons
   PatchSrc src;
   hipError_t e = make_src(net, map, poses, &src);
   if (e != hipSuccess) return e == hipErrorOutOfMemory ? FSMI_E_NOMEM : FSMI_E_DEVICE;
-  // the first layer's forward and weight gradient read the patch from one
-  // gathered copy instead of the map
-  if (!net->patch) {
-    e = hipMalloc((void**)&net->patch, sizeof(bf16) * (size_t)net->max_batch * kPatch * kPatch);
-    if (e != hipSuccess) return FSMI_E_NOMEM;
-  }
-  {
-    const int64_t units = n * kPatch * (kPatch / 8);
-    const int grid = (int)std::min<int64_t>((units + 255) / 256, 8192);
-    hipLaunchKernelGGL(k_patch_gather, dim3(grid), dim3(256), 0, net->ctx->stream, n, src, net->patch);
-    src.patch = net->patch;
-  }
   if (sur_fwd_batch(net, n, src, true) != hipSuccess) return FSMI_E_DEVICE;
   hipStream_t st = net->ctx->stream;
   const int grid = (int)std::min<int64_t>(n, 65535);
