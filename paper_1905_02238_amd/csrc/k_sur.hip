@@ -1262,11 +1262,22 @@ struct fsmi_sur_s {
 
 namespace fsmi {
 
-// Output pixels per weight-gradient split, and taps per workgroup of the
-// weight-gradient kernel, per layer (conv1's weight gradient is taken inside
-// conv2's input-gradient pass, in wg1_splits(nb) splits).
-static constexpr int kWgChunk[5] = {0, 2048, 2048, 1024, 1024};
+// Weight-gradient splits per layer, at most, and taps per workgroup of the
+// weight-gradient kernel (conv1's weight gradient is taken inside conv2's
+// input-gradient pass, in wg1_splits(nb) splits).  A layer's splits are a
+// fixed count rather than a fixed length: the split length follows the batch
+// (wg_chunk), so the grid, kWgSplits[l] x 9 / kWgTpg[l] workgroups, and the
+// partial sums stay the same size at any batch.
+static constexpr int kWgSplits[5] = {0, 512, 256, 128, 32};
 static constexpr int kWgTpg[5] = {0, 9, 3, 3, 1};
+constexpr int kWgStage = 32;   // pixels per stage of k_conv_wgrad (WgradTile::KS)
+
+// Split length for npix output pixels: a multiple of the stage, at least one
+// stage, and long enough for at most kWgSplits[l] splits.
+static int64_t wg_chunk(int l, int64_t npix) {
+  const int64_t per = (npix + kWgSplits[l] - 1) / kWgSplits[l];
+  return std::max<int64_t>(kWgStage, (per + kWgStage - 1) / kWgStage * kWgStage);
+}
 
 // Splits (workgroups) of conv2's input-gradient pass with conv1's weight
 // gradient fused in, for nb poses, and the tiles each takes.  With n tiles
@@ -1325,7 +1336,7 @@ static hipError_t sur_alloc(fsmi_sur net) {
     const size_t npix = (size_t)B * hout * hout;
     // conv1's weight gradient is taken inside conv2's input-gradient pass
     const size_t splits =
-        l == 0 ? (size_t)wg1_max_splits(B, net->ctx->num_cu) : (npix + kWgChunk[l] - 1) / kWgChunk[l];
+        l == 0 ? (size_t)wg1_max_splits(B, net->ctx->num_cu) : (size_t)kWgSplits[l];
     const size_t ncol = l == 0 ? 16 : 9 * (size_t)kL[l].cin + 16;
     const size_t nout = (size_t)kL[l].cout * (9 * kL[l].cin + 1);
     mx = std::max(mx, splits * kL[l].cout * ncol);
@@ -1464,7 +1475,8 @@ static void conv_wgrad(fsmi_sur net, int64_t nb) {
   static_assert(L >= 1, "conv1's weight gradient is taken in conv2_dgrad_conv1_wgrad");
   hipStream_t st = net->ctx->stream;
   const int64_t npix = nb * (d.hin / 2) * (d.hin / 2);
-  const int chunk = kWgChunk[L];
+  static_assert(WgradTile<d.cin, d.cout, kWgTpg[L]>::KS == kWgStage, "split lengths are whole stages");
+  const int chunk = (int)wg_chunk(L, npix);   // <= kWgSplits[L] splits
   const int splits = (int)((npix + chunk - 1) / chunk);
   constexpr int tpg = kWgTpg[L];
   hipLaunchKernelGGL((k_conv_wgrad<d.cin, d.cout, d.hin, tpg>), dim3(splits, 9 / tpg), dim3(256), 0,
