@@ -144,7 +144,7 @@ def main():
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
 
     if args.profile_surrogate:
-        wl = W.grid_large(n_poses=65536)
+        wl = W.grid_large(n_poses=65536, yaw="zero")
         g, p, bd = t(wl["grid"]), t(wl["poses"]), t(wl["beam_dir"])
         net = F.Surrogate(ctx, seed=3, max_batch=8192)
         for _ in range(3):
@@ -512,7 +512,7 @@ def oracle_leg(out, gpu, wl, W, args, ctx, F, t):
 def table_route_leg(ctx, F, W, t, timed):
     """The paper's run-length experiment (Sec. 5.4) on the GPU: beams of 256
     cells in groups of L, one random o per group.  The table route
-    (fsmi_rle_table_eval_beams: Approx-FSMI-RLE by Alg 11, Delta = 3, a grid of
+    (fsmi_rle_table_eval_beams: Approx-FSMI-RLE by Alg 8, Delta = 3, a grid of
     64 levels, FP64) runs on the runs, and Approx-FSMI (Delta = 3) on the
     expanded cells (fsmi_eval_beams, FP64 and FP32).  The table route's error
     is taken against the run engine's Approx-FSMI-RLE with the same (density)
@@ -609,7 +609,7 @@ def surrogate_leg(ctx, F, W, t, timed, args):
     tnet.close()
     log(f"[bench] surrogate training: {step_s * 1e3:.3f} ms per step of {tb} poses "
         f"({tb / step_s:.0f} poses/s, {3 * tb * SUR_FLOP_PER_POSE / step_s / 1e12:.1f} TFLOP/s)")
-    wl = W.grid_large(n_poses=args.sur_candidates)      # held out: not a training map
+    wl = W.grid_large(n_poses=args.sur_candidates, yaw="zero")   # held out: not a training map
     g, p = t(wl["grid"]), t(wl["poses"])
     n = p.shape[0]
     k = max(1, math.ceil(0.01 * n))

@@ -115,7 +115,11 @@ typedef struct {
    status word, queue counters and a grow-only work area on the device. */
 fsmi_status fsmi_create(fsmi_ctx* out, int device, void* hip_stream);
 void fsmi_destroy(fsmi_ctx ctx);
-/* Changes the stream later calls enqueue on (NULL: the default stream). */
+/* Changes the stream later calls enqueue on (NULL: the default stream).  The
+   context's scratch (status word, queue heads, work area) serves every call,
+   so the new stream is first made to wait for all work enqueued so far on the
+   old one (an event recorded there): calls of one context stay ordered across
+   stream changes.  Calls of separate contexts are independent. */
 fsmi_status fsmi_set_stream(fsmi_ctx ctx, void* hip_stream);
 /* Waits for the stream; returns the latched device error (and clears it). */
 fsmi_status fsmi_sync(fsmi_ctx ctx);
@@ -222,7 +226,7 @@ fsmi_status fsmi_rle_eval_beams(fsmi_ctx ctx, const fsmi_params* params, int64_t
                                 const int64_t* run_off, const float* run_occ,
                                 const int32_t* run_len, const float* sigma_prime, double* mi);
 
-/* ---- the paper's table route for Approx-FSMI-RLE (Alg 11 with the tables of
+/* ---- the paper's table route for Approx-FSMI-RLE (Alg 8 with the tables of
    Alg 9 and 10), kept to compare against the run engine above ----
    Same runs as fsmi_rle_eval_beams, one sigma_prime (> 0) for the batch.  The
    alpha/beta/theta/gamma tables are built on the device for x = i / levels,

@@ -416,7 +416,7 @@ double ora_rle_alpha_route(int nr, const double* ro, const int* L, double sigma_
   return nval(&I) / (s2pi * sigma_p);
 }
 
-/* ---- table mode of Approx-FSMI-RLE (Alg 11 with the tables of Alg 9 and 10) ----
+/* ---- table mode of Approx-FSMI-RLE (Alg 8 with the tables of Alg 9 and 10) ----
    The tables hold the un-normalised Gaussian truncated at |a - b| <= Delta, Thm 6's
    kernel: alpha_D[x,P,Q] = sum_{a<P} sum_{b<Q, |a-b|<=Delta} x^a g(a-b), beta_D adds a
    factor b, g(d) = exp(-d^2 / (2 sigma'^2)).  A block cropped by Eqs. su'..Lv' and

@@ -189,6 +189,12 @@ fsmi_status fsmi_create(fsmi_ctx* out, int device, void* hip_stream) {
     delete c;
     return FSMI_E_NOMEM;
   }
+  if (hipEventCreateWithFlags(&c->handoff, hipEventDisableTiming) != hipSuccess) {
+    (void)hipFree(c->d_status);
+    (void)hipFree(c->d_counters);
+    delete c;
+    return FSMI_E_DEVICE;
+  }
   (void)hipMemset(c->d_status, 0, 256);
   (void)hipMemset(c->d_counters, 0, 64 * 4);
   (void)hipDeviceSynchronize();
@@ -203,12 +209,21 @@ void fsmi_destroy(fsmi_ctx ctx) {
   if (ctx->d_work) (void)hipFree(ctx->d_work);
   if (ctx->d_status) (void)hipFree(ctx->d_status);
   if (ctx->d_counters) (void)hipFree(ctx->d_counters);
+  if (ctx->handoff) (void)hipEventDestroy(ctx->handoff);
   delete ctx;
 }
 
 fsmi_status fsmi_set_stream(fsmi_ctx ctx, void* hip_stream) {
   if (!ctx) return FSMI_E_INVAL;
-  ctx->stream = (hipStream_t)hip_stream;   // NULL: the device's default stream
+  const hipStream_t s = (hipStream_t)hip_stream;   // NULL: the device's default stream
+  if (s == ctx->stream) return FSMI_OK;
+  // the new stream waits for everything enqueued so far on the old one, so
+  // calls on the two streams never share the context's scratch at once
+  (void)hipSetDevice(ctx->device);
+  hipError_t e = hipEventRecord(ctx->handoff, ctx->stream);
+  if (e == hipSuccess) e = hipStreamWaitEvent(s, ctx->handoff, 0);
+  if (e != hipSuccess) return from_hip(ctx, e, "fsmi_set_stream");
+  ctx->stream = s;
   return FSMI_OK;
 }
 

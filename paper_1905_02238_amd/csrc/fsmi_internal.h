@@ -11,6 +11,10 @@
 struct fsmi_ctx_s {
   int device = 0;
   hipStream_t stream = nullptr;   // caller's stream; nullptr = the default stream
+  // Orders work across a change of stream: the context's scratch (status word,
+  // queue heads, work area) is shared by every call, so a call on a new stream
+  // must not start before the calls enqueued on the old one have finished.
+  hipEvent_t handoff = nullptr;
   uint32_t* d_status = nullptr;   // latched device error bits
   int32_t* d_counters = nullptr;  // work-queue heads, 64 entries
   void* d_work = nullptr;         // grow-only scratch for schedules / partial results

@@ -1,4 +1,4 @@
-// k_rle_table.hip -- the paper's table route for Approx-FSMI-RLE: Alg 11 with the
+// k_rle_table.hip -- the paper's table route for Approx-FSMI-RLE: Alg 8 with the
 // alpha/beta/theta/gamma tables of Alg 9 and 10, x = 1 - o quantised to a grid.
 // It is kept beside the run engine (k_rle.hip) to reproduce the paper's
 // run-length crossover and to measure the route's cancellation; the run engine
@@ -133,7 +133,7 @@ struct TabArgs {
   uint32_t* status;
 };
 
-// Run u's terms (Alg 11's u = v, v after u and v before u) of a beam whose
+// Run u's terms (Alg 8's u = v, v after u and v before u) of a beam whose
 // nr runs sit in the LDS arrays s_*.
 struct RunLds {
   const float* o;

@@ -106,17 +106,25 @@ def room_grid(size: int, seed: int, split_extent: int, unknown_frac: float = 0.0
     return occupancy_from_labels(lab, seed), lab
 
 
-def poses_in_free_space_2d(lab, n: int, seed: int):
+def poses_in_free_space_2d(lab, n: int, seed: int, yaw: str = "zero"):
     """n poses [x, y, cos(yaw), sin(yaw)] uniform over FREE cells (continuous in
-    the cell), yaw 0."""
+    the cell); yaw 0 (``yaw="zero"``) or U[0, 2 pi) (``yaw="uniform"``, drawn
+    after the positions, so the positions do not depend on it)."""
     rng = np.random.default_rng(seed + 11)
     ys, xs = np.nonzero(lab == FREE)
     pick = rng.integers(0, len(xs), n)
     out = np.zeros((n, 4), np.float64)
     out[:, 0] = xs[pick] + rng.uniform(0.0, 1.0, n)
     out[:, 1] = ys[pick] + rng.uniform(0.0, 1.0, n)
-    out[:, 2] = 1.0
-    out[:, 3] = 0.0
+    if yaw == "uniform":
+        a = rng.uniform(0.0, 2.0 * math.pi, n)
+        out[:, 2] = np.cos(a)
+        out[:, 3] = np.sin(a)
+    elif yaw == "zero":
+        out[:, 2] = 1.0
+        out[:, 3] = 0.0
+    else:
+        raise ValueError(f"unknown yaw mode {yaw!r}")
     return out
 
 
@@ -292,11 +300,12 @@ def grid_small(seed=SEED_BASE + 0):
                 sigma=2.0)
 
 
-def grid_large(n_poses=4096, seed=SEED_BASE + 1):
-    """2048 x 2048 rooms + 30 % unknown frontier blobs, poses uniform in free space,
-    360 beams at 1 deg, R = 400, sigma = 3 (Delta = 9, H = 6)."""
+def grid_large(n_poses=4096, seed=SEED_BASE + 1, yaw="uniform"):
+    """2048 x 2048 rooms + 30 % unknown frontier blobs, poses uniform in free space
+    with yaw U[0, 2 pi) (or 0 with ``yaw="zero"``), 360 beams at 1 deg, R = 400,
+    sigma = 3 (Delta = 9, H = 6)."""
     occ, lab = room_grid(2048, seed, split_extent=160, unknown_frac=0.30)
-    poses = poses_in_free_space_2d(lab, n_poses, seed)
+    poses = poses_in_free_space_2d(lab, n_poses, seed, yaw=yaw)
     return dict(grid=occ, labels=lab, poses=poses, beam_dir=beam_dirs_2d(360), R=400.0,
                 sigma=3.0, Delta=9, H=6)
 

@@ -308,7 +308,7 @@ def test_rle_eval_beams_parity(ctx, exact, kernel):
 
 
 # ---------------------------------------------------------------------------
-# The paper's table route for Approx-FSMI-RLE (Alg 11, tables of Alg 9 and 10).
+# The paper's table route for Approx-FSMI-RLE (Alg 8, tables of Alg 9 and 10).
 def _grid_runs(seed, n_beams, levels, i_lo, i_hi, run_hi=12, runs_hi=40):
     """Beams of runs whose o = i / levels lies on the table grid."""
     rng = np.random.default_rng(seed)
@@ -467,6 +467,94 @@ def test_poses_grid_large_timed_launch_sampled(ctx, variant):
                              wl["R"], Delta=wl["Delta"], H=wl["H"])
     assert rel_err(mb[idx], rb) <= TOL32
     assert rel_err(mp[idx], rp) <= TOL32
+
+
+def _world_dirs_2d(pose, bd):
+    """World directions of a 2D pose's beams by the header's rule: each product
+    rounded on its own, (c bx - s by, s bx + c by)."""
+    c, s = pose[2], pose[3]
+    m1, m2, m3, m4 = c * bd[:, 0], s * bd[:, 1], s * bd[:, 0], c * bd[:, 1]
+    return np.stack([m1 - m2, m3 + m4], 1)
+
+
+@pytest.mark.parametrize("variant", [F.FSMI_EXACT, F.FSMI_APPROX, F.FSMI_UNIFORM])
+def test_poses_2d_turned_timed_launch(ctx, variant):
+    """The timed 2D workload (2048 x 2048 rooms, 4096 poses x 360 beams, R = 400,
+    sigma = 3) with yaw U[0, 2 pi), pose 0 turned by exactly 90 degrees
+    ((cos, sin) = (0, 1)) and pose 1 by exactly 180 ((-1, 0)), in the one launch
+    the benchmark times: five poses beam by beam against the oracle (1e-5), and
+    the cell lists, entries and occupancies of the same turned beams bit-exact
+    through fsmi_raycast."""
+    print(f"[gpu] grid_large turned poses variant={variant}", flush=True)
+    wl = W.grid_large(n_poses=4096)
+    poses = wl["poses"].copy()
+    poses[0, 2:] = (0.0, 1.0)
+    poses[1, 2:] = (-1.0, 0.0)
+    assert np.count_nonzero(np.abs(poses[:, 3]) > 0.1) > 3000
+    prm = F.params(variant=variant, trunc_delta=wl["Delta"], uniform_h=wl["H"])
+    g, bd = dev(wl["grid"]), wl["beam_dir"]
+    mp, mb = ctx.fsmi_eval_poses(prm, g, dev(poses), dev(bd), wl["sigma"], wl["R"], want_beams=True)
+    torch.cuda.synchronize()
+    ctx.fsmi_sync()
+    mp, mb = mp.cpu().numpy(), mb.cpu().numpy()
+    assert np.all(np.isfinite(mb))
+    assert np.allclose(mp, mb.sum(axis=1), rtol=1e-12, atol=0.0)
+    idx = [0, 1, 2, 2047, 4095]
+    rp, rb = O.eval_poses_2d(variant, wl["grid"], poses[idx], bd, wl["sigma"], wl["R"],
+                             Delta=wl["Delta"], H=wl["H"])
+    assert rel_err(mb[idx], rb) <= TOL32
+    assert rel_err(mp[idx], rp) <= TOL32
+    if variant != F.FSMI_EXACT:
+        return
+    org = np.repeat(poses[idx, :2], len(bd), axis=0)
+    dirs = np.concatenate([_world_dirs_2d(poses[p], bd) for p in idx])
+    out = ctx.fsmi_raycast(g, F.FSMI_RAY_DDA, dev(org), dev(dirs), wl["R"])
+    torch.cuda.synchronize()
+    ctx.fsmi_sync()
+    cnt, cells = out["count"].cpu().numpy(), out["cell"].cpu().numpy()
+    ent, occ = out["entry"].cpu().numpy(), out["occ"].cpu().numpy()
+    for r in range(len(org)):
+        c, e, oc = O.raycast2d(wl["grid"], org[r], dirs[r], wl["R"])
+        assert cnt[r] == len(c), r
+        assert np.array_equal(cells[r, : len(c)], c), r
+        assert np.array_equal(ent[r, : len(c) + 1], e), r
+        assert np.array_equal(occ[r, : len(c)], oc), r
+
+
+@pytest.mark.parametrize("deg,cs", [(90, (0.0, 1.0)), (180, (-1.0, 0.0)), (270, (0.0, -1.0))])
+def test_poses_2d_quarter_turn_on_turned_map_is_bit_exact(ctx, deg, cs):
+    """The GPU path on its own: a pose turned by a quarter turn on the map turned
+    the other way reproduces the unturned pose on the original map bit for bit,
+    beam by beam (dyadic origins off the grid lines, see the oracle's pin of the
+    same property)."""
+    print(f"[gpu] quarter turn {deg}", flush=True)
+    X, Y = 301, 233
+    rng = np.random.default_rng(deg)
+    grid = rng.uniform(0.02, 0.98, (Y, X)).astype(np.float32)
+    grid[: Y // 3, : X // 4] = 0.5
+    if deg == 90:
+        rgrid, rot = grid[::-1, :].T, lambda x, y: (Y - y, x)
+    elif deg == 180:
+        rgrid, rot = grid[::-1, ::-1], lambda x, y: (X - x, Y - y)
+    else:
+        rgrid, rot = grid[:, ::-1].T, lambda x, y: (y, X - x)
+    rgrid = np.ascontiguousarray(rgrid)
+    n = 64
+    xs = rng.integers(20, X - 20, n) + (rng.integers(0, 15, n) * 2 + 1) / 32.0
+    ys = rng.integers(20, Y - 20, n) + (rng.integers(0, 15, n) * 2 + 1) / 32.0
+    p0 = np.stack([xs, ys, np.ones(n), np.zeros(n)], 1)
+    rp = np.array([rot(x, y) for x, y in zip(xs, ys)])
+    p1 = np.stack([rp[:, 0], rp[:, 1], np.full(n, cs[0]), np.full(n, cs[1])], 1)
+    bd = dev(W.beam_dirs_2d(360))
+    for variant in (F.FSMI_EXACT, F.FSMI_APPROX, F.FSMI_UNIFORM):
+        prm = F.params(variant=variant, trunc_delta=6, uniform_h=4)
+        _, mb0 = ctx.fsmi_eval_poses(prm, dev(grid), dev(p0), bd, 2.5, 120.0, want_beams=True)
+        _, mb1 = ctx.fsmi_eval_poses(prm, dev(rgrid), dev(p1), bd, 2.5, 120.0, want_beams=True)
+        torch.cuda.synchronize()
+        ctx.fsmi_sync()
+        a, b = mb0.cpu().numpy(), mb1.cpu().numpy()
+        assert np.all(a > 0.0)
+        assert np.array_equal(a, b), (variant, int(np.count_nonzero(a != b)))
 
 
 @pytest.mark.parametrize("variant", [F.FSMI_EXACT, F.FSMI_APPROX, F.FSMI_UNIFORM])
@@ -695,3 +783,27 @@ def test_range_noise_and_max_range_reject_other_modes(ctx):
                                 dev(np.array([[1.0, 0.0, 0.0]])), 1.0, 5.0, 1.0)
         assert e.value.status == F.FSMI_E_INVAL
     ctx.fsmi_sync()
+
+
+def test_context_calls_stay_ordered_across_streams(ctx):
+    """One context used from two torch streams in turn (its queue heads and work
+    area are shared): every call waits for the calls enqueued before it on the
+    other stream, so the results equal the single-stream ones bit for bit."""
+    print("[gpu] calls across two streams", flush=True)
+    wl = W.grid_large(n_poses=512)
+    g, bd = dev(wl["grid"]), dev(wl["beam_dir"])
+    halves = [dev(wl["poses"][:256]), dev(wl["poses"][256:])]
+    prm = F.params(variant=F.FSMI_APPROX, trunc_delta=9)
+    ref = [ctx.fsmi_eval_poses(prm, g, p, bd, 3.0, 400.0)[0] for p in halves]
+    torch.cuda.synchronize()
+    ref = [r.cpu().numpy() for r in ref]
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    outs = []
+    for rep in range(3):
+        for i, s in enumerate((s1, s2)):
+            with torch.cuda.stream(s):
+                outs.append((i, ctx.fsmi_eval_poses(prm, g, halves[i], bd, 3.0, 400.0)[0]))
+    torch.cuda.synchronize()
+    ctx.fsmi_sync()
+    for i, o in outs:
+        assert np.array_equal(o.cpu().numpy(), ref[i])

@@ -388,7 +388,7 @@ def test_alpha_route_loses_digits_as_the_paper_warns():
     assert abs(a - b) > 1e-5 * b       # FP64 route off by ~3e-4 here
 
 
-# The table mode of Approx-FSMI-RLE (Alg 11 with the tables of Alg 9 and 10):
+# The table mode of Approx-FSMI-RLE (Alg 8 with the tables of Alg 9 and 10):
 # tables read at x = 1 - o quantised to i / levels.
 @pytest.mark.parametrize("Delta", [1, 3, 6])
 @pytest.mark.parametrize("seed", range(3))

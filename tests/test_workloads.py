@@ -39,6 +39,19 @@ def test_poses_sit_in_free_cells_with_yaw_zero():
     assert np.all(p[:, 2] == 1.0) and np.all(p[:, 3] == 0.0)
 
 
+def test_uniform_yaw_keeps_positions_and_covers_the_circle():
+    occ, lab = W.room_grid(256, W.SEED_BASE + 51, split_extent=60)
+    p0 = W.poses_in_free_space_2d(lab, 2000, 7)
+    p1 = W.poses_in_free_space_2d(lab, 2000, 7, yaw="uniform")
+    assert np.array_equal(p0[:, :2], p1[:, :2])
+    assert np.allclose(np.hypot(p1[:, 2], p1[:, 3]), 1.0, atol=1e-15)
+    ang = np.mod(np.arctan2(p1[:, 3], p1[:, 2]), 2 * np.pi)
+    hist, _ = np.histogram(ang, bins=8, range=(0, 2 * np.pi))
+    assert hist.min() > 150                       # about 250 per octant
+    large = W.grid_large(n_poses=16)
+    assert np.any(np.abs(large["poses"][:, 3]) > 0.5)   # the timed workload turns its poses
+
+
 def test_beam_directions_are_unit_vectors_at_equal_angles():
     d = W.beam_dirs_2d(360)
     assert np.allclose(np.hypot(d[:, 0], d[:, 1]), 1.0, atol=1e-15)
