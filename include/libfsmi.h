@@ -269,6 +269,27 @@ fsmi_status fsmi_eval_poses(fsmi_ctx ctx, const fsmi_params* params, const fsmi_
                             const double* beam_dir, double sigma, double max_range, double w,
                             double* mi_pose, double* mi_beam);
 
+/* ---- fsmi_eval_poses without device allocation ----
+   For callers that cannot allocate device memory during the call: code under
+   HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+   Same arguments, results and errors as fsmi_eval_poses (the same kernels,
+   bit-identical results), but its scratch -- the per-beam partial results
+   (when mi_beam is NULL) and the work-queue head -- lives in a static device
+   array of the library, 16 MiB + 256 bytes, that each device the library runs
+   on holds until the process ends (its address is resolved per device by
+   fsmi_create).  The call itself allocates nothing (no hipMalloc, hipFree or
+   allocating library routine); the caller passes inputs and outputs.  With
+   mi_beam == NULL, n_poses * n_beams must not exceed 2^21 (2 097 152), else
+   FSMI_E_CAPACITY and nothing is launched; with mi_beam given there is no
+   such limit.  Every call on a device shares that device's array, which keeps
+   the last call's contents (the queue head is cleared by a kernel at the
+   start of each call): calls that overlap on one device, from any context or
+   stream, race and give wrong results -- order them. */
+fsmi_status fsmi_eval_poses_noalloc(fsmi_ctx ctx, const fsmi_params* params, const fsmi_map* map,
+                                    int64_t n_poses, const double* poses, int64_t n_beams,
+                                    const double* beam_dir, double sigma, double max_range,
+                                    double w, double* mi_pose, double* mi_beam);
+
 /* ---- a15..a17: learned surrogate, trained on FSMI's own labels ----
    A small conv net predicts a pose's scan MI from a 128 x 128 patch of o
    around the pose: with cell stride s, patch pixel (iy, ix) is the mean of o

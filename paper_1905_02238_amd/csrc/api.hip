@@ -184,6 +184,11 @@ fsmi_status fsmi_create(fsmi_ctx* out, int device, void* hip_stream) {
   if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
     c->num_cu = prop.multiProcessorCount;
   c->stream = (hipStream_t)hip_stream;   // NULL: the device's default stream
+  // the device address of fsmi_eval_poses_noalloc's static scratch on this device
+  if (noalloc_scratch_init(device) != hipSuccess) {
+    delete c;
+    return FSMI_E_DEVICE;
+  }
   if (hipMalloc(&c->d_status, 256) != hipSuccess || hipMalloc(&c->d_counters, 64 * 4) != hipSuccess) {
     if (c->d_status) (void)hipFree(c->d_status);
     delete c;
@@ -377,6 +382,17 @@ fsmi_status fsmi_eval_poses(fsmi_ctx ctx, const fsmi_params* params, const fsmi_
                             int64_t n_poses, const double* poses, int64_t n_beams,
                             const double* beam_dir, double sigma, double max_range, double w,
                             double* mi_pose, double* mi_beam) {
+  return eval_poses_checked(ctx, params, map, n_poses, poses, n_beams, beam_dir, sigma, max_range,
+                            w, mi_pose, mi_beam, nullptr);
+}
+
+}  // extern "C"
+
+namespace fsmi {
+fsmi_status eval_poses_checked(fsmi_ctx ctx, const fsmi_params* params, const fsmi_map* map,
+                               int64_t n_poses, const double* poses, int64_t n_beams,
+                               const double* beam_dir, double sigma, double max_range, double w,
+                               double* mi_pose, double* mi_beam, const PoseScratch* ws) {
   if (!ctx) return FSMI_E_INVAL;
   fsmi_status st;
   if (!check_params(ctx, params, &st)) return st;
@@ -404,7 +420,7 @@ fsmi_status fsmi_eval_poses(fsmi_ctx ctx, const fsmi_params* params, const fsmi_
     return from_hip(ctx,
                     launch_eval_poses_2d(ctx, to_const(params), map->occ, map->dims[0], map->dims[1],
                                          n_poses, poses, n_beams, beam_dir, sigma, max_range,
-                                         mi_pose, mi_beam),
+                                         mi_pose, mi_beam, ws),
                     "eval_poses_2d");
   }
   if (params->flags & FSMI_F_SKIP_ZERO)
@@ -416,9 +432,12 @@ fsmi_status fsmi_eval_poses(fsmi_ctx ctx, const fsmi_params* params, const fsmi_
   return from_hip(ctx,
                   launch_eval_poses_3d(ctx, to_const(params), map->occ, map->dims[0], map->dims[1],
                                        map->dims[2], n_poses, poses, n_beams, beam_dir, sigma,
-                                       max_range, w, mi_pose, mi_beam),
+                                       max_range, w, mi_pose, mi_beam, ws),
                   "eval_poses_3d");
 }
+}  // namespace fsmi
+
+extern "C" {
 
 fsmi_status fsmi_probe_erfc(fsmi_ctx ctx, int64_t n, const float* z, float* out) {
   if (!ctx) return FSMI_E_INVAL;

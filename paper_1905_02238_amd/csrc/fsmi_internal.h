@@ -91,11 +91,19 @@ hipError_t launch_virtual3d(fsmi_ctx ctx, const float* map, int64_t X, int64_t Y
                             double w, int max_cells, int rle, int32_t* count, int32_t* cell,
                             float* occ_out, int32_t* run_len);
 
+// Caller-provided scratch of the pose launchers (fsmi_eval_poses_noalloc): the
+// per-beam partial results (used when mi_beam is NULL) and the 64-bit queue
+// head.  nullptr: the context's work area and counters.
+struct PoseScratch {
+  double* beams;
+  int32_t* counter;
+};
+
 // ---- launchers (k_pose.hip) ----
 hipError_t launch_eval_poses_2d(fsmi_ctx ctx, const EvalConst& ec, const float* map, int64_t X,
                                 int64_t Y, int64_t n_poses, const double* poses, int64_t n_beams,
                                 const double* beam_dir, double sigma, double R, double* mi_pose,
-                                double* mi_beam);
+                                double* mi_beam, const PoseScratch* ws = nullptr);
 
 // ---- launchers (k_rle.hip) ----
 hipError_t launch_rle_eval_beams(fsmi_ctx ctx, const EvalConst& ec, int64_t n_beams,
@@ -105,7 +113,20 @@ hipError_t launch_rle_eval_beams(fsmi_ctx ctx, const EvalConst& ec, int64_t n_be
 hipError_t launch_eval_poses_3d(fsmi_ctx ctx, const EvalConst& ec, const float* map, int64_t X,
                                 int64_t Y, int64_t Z, int64_t n_poses, const double* poses,
                                 int64_t n_beams, const double* beam_dir, double sigma, double R,
-                                double w, double* mi_pose, double* mi_beam);
+                                double w, double* mi_pose, double* mi_beam,
+                                const PoseScratch* ws = nullptr);
+
+// fsmi_eval_poses after its argument checks (api.hip), with the scratch the
+// call uses: ws == nullptr takes the context's work area and counters.
+fsmi_status eval_poses_checked(fsmi_ctx ctx, const fsmi_params* params, const fsmi_map* map,
+                               int64_t n_poses, const double* poses, int64_t n_beams,
+                               const double* beam_dir, double sigma, double max_range, double w,
+                               double* mi_pose, double* mi_beam, const PoseScratch* ws);
+
+// ---- fsmi_eval_poses_noalloc (noalloc.hip) ----
+// Resolves, once per device and with that device current, the device address
+// of the library's static scratch array; called by fsmi_create.
+hipError_t noalloc_scratch_init(int device);
 
 // ---- machine ceilings (k_peak.hip) ----
 hipError_t run_peak(fsmi_ctx ctx, int kind, double* rate, double* clock_mhz);

@@ -156,11 +156,13 @@ hipError_t launch_pose_reduce(fsmi_ctx ctx, const double* mi_beam, int64_t n_pos
 hipError_t launch_eval_poses_2d(fsmi_ctx ctx, const EvalConst& ec, const float* map, int64_t X,
                                 int64_t Y, int64_t n_poses, const double* poses, int64_t n_beams,
                                 const double* beam_dir, double sigma, double R, double* mi_pose,
-                                double* mi_beam) {
+                                double* mi_beam, const PoseScratch* ws) {
   const int64_t n_items = n_poses * n_beams;
   if (n_items <= 0) return hipSuccess;
   double* mb = mi_beam;
-  if (!mb) {
+  if (!mb && ws) {
+    mb = ws->beams;
+  } else if (!mb) {
     hipError_t e = ensure_work(ctx, (size_t)n_items * 8);
     if (e != hipSuccess) return e;
     mb = reinterpret_cast<double*>(ctx->d_work);
@@ -179,7 +181,7 @@ hipError_t launch_eval_poses_2d(fsmi_ctx ctx, const EvalConst& ec, const float* 
   a.capa = dda2d_axis_cap(R);
   a.ecap = dda2d_event_cap(R);
   a.mi_beam = mb;
-  a.counter = ctx->d_counters + 8;   // 64-bit head at counters[8..9]
+  a.counter = ws ? ws->counter : ctx->d_counters + 8;   // 64-bit head (counters[8..9])
   a.status = ctx->d_status;
   hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, ctx->stream, a.counter);
   const bool fp64 = ec.precision == FSMI_FP64;

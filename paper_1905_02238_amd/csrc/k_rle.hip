@@ -245,11 +245,13 @@ hipError_t launch_rle_eval_beams(fsmi_ctx ctx, const EvalConst& ec, int64_t n_be
 hipError_t launch_eval_poses_3d(fsmi_ctx ctx, const EvalConst& ec, const float* map, int64_t X,
                                 int64_t Y, int64_t Z, int64_t n_poses, const double* poses,
                                 int64_t n_beams, const double* beam_dir, double sigma, double R,
-                                double w, double* mi_pose, double* mi_beam) {
+                                double w, double* mi_pose, double* mi_beam, const PoseScratch* ws) {
   const int64_t n_items = n_poses * n_beams;
   if (n_items <= 0) return hipSuccess;
   double* mb = mi_beam;
-  if (!mb) {
+  if (!mb && ws) {
+    mb = ws->beams;
+  } else if (!mb) {
     hipError_t e = ensure_work(ctx, (size_t)n_items * 8);
     if (e != hipSuccess) return e;
     mb = reinterpret_cast<double*>(ctx->d_work);
@@ -269,7 +271,7 @@ hipError_t launch_eval_poses_3d(fsmi_ctx ctx, const EvalConst& ec, const float* 
   a.w = w;
   a.cap = std::max(1, (int)floor(R / w));
   a.mi_beam = mb;
-  a.counter = ctx->d_counters + 8;
+  a.counter = ws ? ws->counter : ctx->d_counters + 8;
   a.status = ctx->d_status;
   const bool fp64 = ec.precision == FSMI_FP64;
   const size_t lds = fp64 ? rle_lds<double>(a.cap) : rle_lds<float>(a.cap);

@@ -30,7 +30,8 @@ FSMI_PEAK_COPY, FSMI_PEAK_FMA, FSMI_PEAK_PAIR, FSMI_PEAK_MFMA_BF16 = 0, 1, 2, 3
 
 EXPORTS = ("fsmi_create", "fsmi_destroy", "fsmi_set_stream", "fsmi_sync", "fsmi_last_error",
            "fsmi_status_string", "fsmi_default_params", "fsmi_raycast", "fsmi_eval_beams",
-           "fsmi_rle_eval_beams", "fsmi_rle_table_eval_beams", "fsmi_eval_poses", "fsmi_probe_erfc", "fsmi_probe_f", "fsmi_probe_mfma", "fsmi_peak",
+           "fsmi_rle_eval_beams", "fsmi_rle_table_eval_beams", "fsmi_eval_poses",
+           "fsmi_eval_poses_noalloc", "fsmi_probe_erfc", "fsmi_probe_f", "fsmi_probe_mfma", "fsmi_peak",
            "fsmi_sur_num_params", "fsmi_sur_create", "fsmi_sur_destroy",
            "fsmi_sur_fit_label_stats", "fsmi_sur_get_label_stats", "fsmi_sur_forward",
            "fsmi_sur_backward", "fsmi_sur_adam_step", "fsmi_sur_get_params",
@@ -92,6 +93,7 @@ def load(path: str = LIB_PATH):
             L.fsmi_rle_table_eval_beams.argtypes = [p, C.POINTER(fsmi_params), i64, p, p, p, d, i32, p]
             L.fsmi_eval_poses.argtypes = [p, C.POINTER(fsmi_params), C.POINTER(fsmi_map), i64, p,
                                           i64, p, d, d, d, p, p]
+            L.fsmi_eval_poses_noalloc.argtypes = L.fsmi_eval_poses.argtypes
             L.fsmi_probe_erfc.argtypes = [p, i64, p, p]
             L.fsmi_probe_f.argtypes = [p, d, i64, p, p]
             L.fsmi_peak.argtypes = [p, i32, C.POINTER(d), C.POINTER(d)]
@@ -121,7 +123,7 @@ def load(path: str = LIB_PATH):
             L.fsmi_plan_destroy.restype = None
             for n in ("fsmi_create", "fsmi_set_stream", "fsmi_sync", "fsmi_raycast",
                       "fsmi_eval_beams", "fsmi_rle_eval_beams", "fsmi_rle_table_eval_beams",
-                      "fsmi_eval_poses",
+                      "fsmi_eval_poses", "fsmi_eval_poses_noalloc",
                       "fsmi_probe_erfc", "fsmi_probe_f", "fsmi_probe_mfma", "fsmi_peak", "fsmi_sur_create",
                       "fsmi_sur_fit_label_stats", "fsmi_sur_get_label_stats", "fsmi_sur_forward",
                       "fsmi_sur_backward", "fsmi_sur_adam_step", "fsmi_sur_get_params",
@@ -267,7 +269,7 @@ class Context:
         return mi
 
     def fsmi_eval_poses(self, prm: fsmi_params, map_occ, poses, beam_dir, sigma, max_range, w=1.0,
-                        mi_pose=None, mi_beam=None, want_beams=False):
+                        mi_pose=None, mi_beam=None, want_beams=False, _entry="fsmi_eval_poses"):
         npo, nb = poses.shape[0], beam_dir.shape[0]
         dev = map_occ.device
         mi_pose = torch.empty(npo, dtype=torch.float64, device=dev) if mi_pose is None else mi_pose
@@ -275,11 +277,18 @@ class Context:
             mi_beam = torch.empty((npo, nb), dtype=torch.float64, device=dev)
         m = _map(map_occ)
         self._stream()
-        self._check(self._lib.fsmi_eval_poses(
+        self._check(getattr(self._lib, _entry)(
             self.handle, C.byref(prm), C.byref(m), npo, _ptr(poses, torch.float64, "poses"), nb,
             _ptr(beam_dir, torch.float64, "beam_dir"), float(sigma), float(max_range), float(w),
             _ptr(mi_pose, torch.float64, "mi_pose"), _ptr(mi_beam, torch.float64, "mi_beam", True)))
         return mi_pose, mi_beam
+
+    def fsmi_eval_poses_noalloc(self, prm: fsmi_params, map_occ, poses, beam_dir, sigma,
+                                max_range, w=1.0, mi_pose=None, mi_beam=None, want_beams=False):
+        """fsmi_eval_poses with the library's static scratch: no device allocation
+        by the call (outputs are still the caller's; pass them to allocate nothing here)."""
+        return self.fsmi_eval_poses(prm, map_occ, poses, beam_dir, sigma, max_range, w, mi_pose,
+                                    mi_beam, want_beams, _entry="fsmi_eval_poses_noalloc")
 
     def fsmi_probe_erfc(self, z, out=None):
         out = torch.empty_like(z) if out is None else out
