@@ -51,6 +51,10 @@ def lib():
             "ora_eval_poses_3d": (i, [i, i, i, i, d, p, i64, i64, i64, i64, p, i64, p, d, d, d,
                                       p, p, i]),
             "ora_max_threads": (i, []),
+            "ora_csqmi": (d, [i, p, p, d, i]),
+            "ora_fsmi_counted": (d, [i, i, p, p, d, d, i, i, p]),
+            "ora_eval_trajectories_2d": (i, [i, i, i, d, p, i64, i64, i64, p, p, i64, p, d, d, p,
+                                             p, p]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -60,7 +64,7 @@ def lib():
     return _lib
 
 
-EXACT, APPROX, UNIFORM = 0, 1, 2
+EXACT, APPROX, UNIFORM, CSQMI = 0, 1, 2, 3
 K_ERF, K_DENSITY, K_UNIFORM = 0, 1, 2
 
 
@@ -290,3 +294,41 @@ def eval_poses_3d(exact, vox, poses, beam_dir, sigma, R, w=1.0, kind=K_ERF, Delt
 
 def max_threads():
     return lib().ora_max_threads()
+
+
+def csqmi(o, l, sigma, Delta=-1):
+    """Eq. csqmi_exact (Sec. 2.3) on one beam; Delta >= 0 truncates both double
+    sums to |l - j| <= Delta (Approx-CSQMI), Delta < 0 is the exact metric."""
+    o, l = _f64(o), _f64(l)
+    assert len(l) == len(o) + 1
+    return lib().ora_csqmi(len(o), _pd(o), _pd(l), float(sigma), int(Delta))
+
+
+def fsmi_counted(variant, o, l, sigma, counted, Delta=0, H=0, delta_occ=1.5):
+    """One beam's MI over the cells with counted[i] true only (cell marking, Sec. 2.4)."""
+    o, l = _f64(o), _f64(l)
+    assert len(l) == len(o) + 1 and len(counted) == len(o)
+    m = np.ascontiguousarray(counted, dtype=np.uint8)
+    return lib().ora_fsmi_counted(int(variant), len(o), _pd(o), _pd(l), float(sigma),
+                                  float(delta_occ), int(Delta), int(H), _pd(m))
+
+
+def eval_trajectories_2d(variant, grid, traj_off, poses, beam_dir, sigma, R, Delta=0, H=0,
+                         delta_occ=1.5, want_beams=True):
+    """Trajectory MI with cell marking (Sec. 2.4): (mi_traj, mi_state, mi_beam)."""
+    grid = np.ascontiguousarray(grid, dtype=np.float32)
+    Y, X = grid.shape
+    traj_off = np.ascontiguousarray(traj_off, dtype=np.int64)
+    poses = _f64(poses).reshape(-1, 4)
+    beam_dir = _f64(beam_dir).reshape(-1, 2)
+    nt, ns, nb = len(traj_off) - 1, poses.shape[0], beam_dir.shape[0]
+    assert traj_off[0] == 0 and traj_off[-1] == ns
+    mt, ms = np.zeros(nt), np.zeros(ns)
+    mb = np.zeros((ns, nb)) if want_beams else None
+    rc = lib().ora_eval_trajectories_2d(int(variant), int(Delta), int(H), float(delta_occ),
+                                        _pd(grid), X, Y, nt, _pd(traj_off), _pd(poses), nb,
+                                        _pd(beam_dir), float(sigma), float(R), _pd(mt), _pd(ms),
+                                        None if mb is None else _pd(mb))
+    if rc != 0:
+        raise ValueError("eval_trajectories_2d: a state lies outside the map")
+    return mt, ms, mb

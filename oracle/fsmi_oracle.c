@@ -223,17 +223,222 @@ double ora_fsmi_eqwidth(int n, const double* o, double sigma_p, double delta_occ
   if (n <= 0) return 0.0;
   double* P = (double*)malloc(sizeof(double) * (n + 1));
   double* C = (double*)malloc(sizeof(double) * n);
+  /* the weight of each distance d = k - j, evaluated once (w[d + n - 1]) */
+  double* w = (double*)malloc(sizeof(double) * (2 * n - 1));
   ora_first_hit(n, o, P);
   ora_info_gain(n, o, delta_occ, C);
+  for (int d = -(n - 1); d <= n - 1; ++d) w[d + n - 1] = kernel_trunc(kind, sigma_p, H, trunc, d);
   nsum I = {0.0, 0.0};
   for (int j = 1; j <= n; ++j)
     for (int k = 1; k <= n; ++k) {
-      double w = kernel_trunc(kind, sigma_p, H, trunc, k - j);
-      if (w != 0.0) nadd(&I, P[j] * C[k - 1] * w);
+      double wk = w[k - j + n - 1];
+      if (wk != 0.0) nadd(&I, P[j] * C[k - 1] * wk);
     }
   free(P);
   free(C);
+  free(w);
   return nval(&I);
+}
+
+/* ------------------------------------------------------------------ */
+/* CSQMI (Sec. 2.3): the comparison metric, exact and Delta-truncated   */
+/* ------------------------------------------------------------------ */
+/* Density of N(0, 2 sigma^2) at x: the integral over z of the product of
+   two N(z; mu, sigma^2) whose means differ by x. */
+static double n2(double x, double sigma) {
+  const double sqrt_pi = 1.77245385090551602730;
+  return exp(-(x * x) / (4.0 * sigma * sigma)) / (2.0 * sigma * sqrt_pi);
+}
+
+/* Eq. csqmi_exact as printed: I = log B + log C - 2 log A with
+     B = sum_{l=0}^{n} w_l N(0, 2 sigma^2),
+     C = prod_i (o_i^2 + (1-o_i)^2) sum_j sum_l P(e_j) P(e_l) N(mu_l - mu_j, 2 sigma^2),
+     A = sum_j sum_l P(e_j) w_l N(mu_l - mu_j, 2 sigma^2),
+   j, l = 0..n.  Readings:
+   - w_l = P(e_l)^2 prod_{i>l} (o_i^2 + (1-o_i)^2), w_0 = P(e_0)^2: the sum of
+     P(m)^2 over the maps m whose first occupied cell is l (the cells after l
+     are free), which the definition D_CS(P(Z, M), P(Z) P(M)) gives; the
+     printed product runs over j < l;
+   - e_0 (no cell occupied) reads beyond the beam, as in Thm 1: its cross
+     terms with every cell vanish and its self terms carry N(0, 2 sigma^2);
+   - the printed form is log B + log C - 2 log A, twice the -1/2 log of the
+     divergence's definition; it is kept as printed.
+   Delta >= 0 keeps only l in [j - Delta, j + Delta] in both double sums (the
+   truncation of Sec. 2.3 that gives Approx-CSQMI); Delta < 0 is the exact sum.
+   Valid while no sum underflows (returns NaN if one does). */
+double ora_csqmi(int n, const double* o, const double* l, double sigma, int Delta) {
+  if (n <= 0) return 0.0;
+  double* P = (double*)malloc(sizeof(double) * (n + 1));
+  double* S = (double*)malloc(sizeof(double) * (n + 1));
+  double* w = (double*)malloc(sizeof(double) * (n + 1));
+  ora_first_hit(n, o, P);
+  /* S[l] = prod_{i>l} q_i, q_i = o_i^2 + (1-o_i)^2; log prod_i q_i summed */
+  S[n] = 1.0;
+  for (int i = n; i >= 1; --i) {
+    double q = o[i - 1] * o[i - 1] + (1.0 - o[i - 1]) * (1.0 - o[i - 1]);
+    S[i - 1] = S[i] * q;
+  }
+  nsum logQ = {0.0, 0.0};
+  for (int i = 1; i <= n; ++i) {
+    double q = o[i - 1] * o[i - 1] + (1.0 - o[i - 1]) * (1.0 - o[i - 1]);
+    nadd(&logQ, log(q));
+  }
+  w[0] = P[0] * P[0];
+  for (int k = 1; k <= n; ++k) w[k] = P[k] * P[k] * S[k];
+  const double g0 = n2(0.0, sigma);
+  nsum B = {0.0, 0.0}, Cs = {0.0, 0.0}, A = {0.0, 0.0};
+  for (int k = 0; k <= n; ++k) nadd(&B, w[k] * g0);
+  nadd(&Cs, P[0] * P[0] * g0);
+  nadd(&A, P[0] * w[0] * g0);
+  for (int j = 1; j <= n; ++j) {
+    double muj = 0.5 * (l[j - 1] + l[j]);
+    int k0 = 1, k1 = n;
+    if (Delta >= 0) {
+      k0 = j - Delta < 1 ? 1 : j - Delta;
+      k1 = j + Delta > n ? n : j + Delta;
+    }
+    for (int k = k0; k <= k1; ++k) {
+      double muk = 0.5 * (l[k - 1] + l[k]);
+      double g = n2(muk - muj, sigma);
+      nadd(&Cs, P[j] * P[k] * g);
+      nadd(&A, P[j] * w[k] * g);
+    }
+  }
+  double b = nval(&B), c = nval(&Cs), a = nval(&A);
+  free(P);
+  free(S);
+  free(w);
+  if (!(a > 0.0) || !(b > 0.0) || !(c > 0.0)) return NAN;
+  return log(b) + (nval(&logQ) + log(c)) - 2.0 * log(a);
+}
+
+/* ------------------------------------------------------------------ */
+/* Trajectory MI with cell marking (Sec. 2.4)                           */
+/* ------------------------------------------------------------------ */
+/* A beam whose cells i with counted[i-1] == 0 have been counted before: their
+   information is not added again, I = sum over counted cells i of I(M_i; Z).
+   By Lemma 1 (F(z) = sum_i f(delta_i(z), r_i)) this removes the f terms of the
+   uncounted cells from C_k; every cell still shapes P(e_j).  The variants
+   follow Thm 1, Eq. fsmi_approx and Alg 4 with that C. */
+static void info_gain_counted(int n, const double* o, double delta_occ,
+                              const unsigned char* counted, double* C) {
+  double delta_emp = 1.0 / delta_occ;
+  nsum q = {0.0, 0.0};
+  for (int k = 1; k <= n; ++k) {
+    double focc = counted[k - 1] ? ora_f(delta_occ, o[k - 1]) : 0.0;
+    C[k - 1] = nval(&q) + focc;
+    if (counted[k - 1]) nadd(&q, ora_f(delta_emp, o[k - 1]));
+  }
+}
+
+double ora_fsmi_counted(int variant, int n, const double* o, const double* l, double sigma,
+                        double delta_occ, int Delta, int H, const unsigned char* counted) {
+  if (n <= 0) return 0.0;
+  double* P = (double*)malloc(sizeof(double) * (n + 1));
+  double* C = (double*)malloc(sizeof(double) * n);
+  ora_first_hit(n, o, P);
+  info_gain_counted(n, o, delta_occ, counted, C);
+  nsum I = {0.0, 0.0};
+  if (variant == ORA_UNIFORM) {
+    double* D = (double*)malloc(sizeof(double) * (n + 1));
+    nsum acc = {0.0, 0.0};
+    D[0] = 0.0;
+    for (int k = 1; k <= n; ++k) {
+      nadd(&acc, C[k - 1]);
+      D[k] = nval(&acc);
+    }
+    for (int j = 1; j <= n; ++j) {
+      int hi = j + H > n ? n : j + H;
+      int lo = j - H - 1 < 0 ? 0 : j - H - 1;
+      nadd(&I, P[j] * (D[hi] - D[lo]) / (2.0 * H + 1.0));
+    }
+    free(D);
+  } else {
+    for (int j = 1; j <= n; ++j) {
+      double mu = 0.5 * (l[j - 1] + l[j]);
+      int k0 = 1, k1 = n;
+      if (variant == ORA_APPROX) {
+        k0 = j - Delta < 1 ? 1 : j - Delta;
+        k1 = j + Delta > n ? n : j + Delta;
+      }
+      for (int k = k0; k <= k1; ++k) nadd(&I, P[j] * C[k - 1] * ora_G(l[k - 1], l[k], mu, sigma));
+    }
+  }
+  free(P);
+  free(C);
+  return nval(&I);
+}
+
+/* Candidate trajectories in CSR form: trajectory k has the states (2D poses
+   [x, y, cos, sin]) traj_off[k] .. traj_off[k+1]-1, in travel order.  Each
+   state's scan MI is the sum over its beams (Sec. 2.4); a cell's information
+   counts only at the first state of the trajectory whose beams cross it, and
+   there at every beam of that state that crosses it (within one scan beams
+   are summed as they are, as in a single pose).  mi_state[t] = the state's
+   MI, mi_traj[k] = the sum over its states; mi_beam [n_states][n_beams] may
+   be NULL.  Returns -1 if a state lies outside the map. */
+int ora_eval_trajectories_2d(int variant, int Delta, int H, double delta_occ, const float* map,
+                             int64_t X, int64_t Y, int64_t n_traj, const int64_t* traj_off,
+                             const double* poses, int64_t n_beams, const double* beam_dir,
+                             double sigma, double R, double* mi_traj, double* mi_state,
+                             double* mi_beam) {
+  int max_cells = (int)floor(1.4142135623730951 * R) + 3;
+  int32_t* first = (int32_t*)malloc(sizeof(int32_t) * (size_t)(X * Y));
+  int32_t* cell = (int32_t*)malloc(sizeof(int32_t) * max_cells);
+  double* entry = (double*)malloc(sizeof(double) * (max_cells + 1));
+  float* of = (float*)malloc(sizeof(float) * max_cells);
+  double* o = (double*)malloc(sizeof(double) * max_cells);
+  unsigned char* counted = (unsigned char*)malloc((size_t)max_cells);
+  int bad = 0;
+  for (int64_t k = 0; k < n_traj; ++k) {
+    for (int64_t c = 0; c < X * Y; ++c) first[c] = -1;
+    /* the first state of this trajectory whose beams cross each cell */
+    for (int64_t t = traj_off[k]; t < traj_off[k + 1]; ++t) {
+      const double* ps = poses + 4 * t;
+      for (int64_t b = 0; b < n_beams; ++b) {
+        double bx = beam_dir[2 * b], by = beam_dir[2 * b + 1];
+        double m1 = ps[2] * bx, m2 = ps[3] * by, m3 = ps[3] * bx, m4 = ps[2] * by;
+        int n = ora_raycast2d(map, X, Y, ps[0], ps[1], m1 - m2, m3 + m4, R, max_cells, cell,
+                              entry, of);
+        for (int i = 0; i < n; ++i)
+          if (first[cell[i]] < 0) first[cell[i]] = (int32_t)(t - traj_off[k]);
+      }
+    }
+    nsum tk = {0.0, 0.0};
+    for (int64_t t = traj_off[k]; t < traj_off[k + 1]; ++t) {
+      const double* ps = poses + 4 * t;
+      nsum ts = {0.0, 0.0};
+      for (int64_t b = 0; b < n_beams; ++b) {
+        double bx = beam_dir[2 * b], by = beam_dir[2 * b + 1];
+        double m1 = ps[2] * bx, m2 = ps[3] * by, m3 = ps[3] * bx, m4 = ps[2] * by;
+        int n = ora_raycast2d(map, X, Y, ps[0], ps[1], m1 - m2, m3 + m4, R, max_cells, cell,
+                              entry, of);
+        double v;
+        if (n < 0) {
+          v = NAN;
+          bad = 1;
+        } else {
+          for (int i = 0; i < n; ++i) {
+            o[i] = (double)of[i];
+            counted[i] = first[cell[i]] == (int32_t)(t - traj_off[k]);
+          }
+          v = ora_fsmi_counted(variant, n, o, entry, sigma, delta_occ, Delta, H, counted);
+        }
+        if (mi_beam) mi_beam[t * n_beams + b] = v;
+        nadd(&ts, v);
+      }
+      if (mi_state) mi_state[t] = nval(&ts);
+      nadd(&tk, nval(&ts));
+    }
+    mi_traj[k] = nval(&tk);
+  }
+  free(first);
+  free(cell);
+  free(entry);
+  free(of);
+  free(o);
+  free(counted);
+  return bad ? -1 : 0;
 }
 
 /* ------------------------------------------------------------------ */
@@ -683,6 +888,7 @@ static double eval_one(int variant, int Delta, int H, double delta_occ, double s
     return ora_fsmi_exact_ext(n, o, l, sigma, slope, tail, delta_occ);
   if (variant == ORA_EXACT) return ora_fsmi_exact(n, o, l, sigma, delta_occ);
   if (variant == ORA_APPROX) return ora_fsmi_approx(n, o, l, sigma, delta_occ, Delta);
+  if (variant == ORA_CSQMI) return ora_csqmi(n, o, l, sigma, Delta);
   return ora_fsmi_uniform(n, o, delta_occ, H);
 }
 

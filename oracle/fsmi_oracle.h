@@ -66,6 +66,19 @@ void ora_tab_definition(double x, double sigma_p, int Lb, int Lmax,
 void ora_tab_recurrence(double x, double sigma_p, int Lb, int Lmax,
                         double* alpha, double* beta, double* theta, double* gamma);
 
+/* ---- CSQMI (Sec. 2.3): Eq. csqmi_exact, Delta-truncated when Delta >= 0 ---- */
+double ora_csqmi(int n, const double* o, const double* l, double sigma, int Delta);
+
+/* ---- trajectory MI with cell marking (Sec. 2.4) ---- */
+/* one beam, information of the cells with counted[i] != 0 only (variant ORA_*) */
+double ora_fsmi_counted(int variant, int n, const double* o, const double* l, double sigma,
+                        double delta_occ, int Delta, int H, const unsigned char* counted);
+int ora_eval_trajectories_2d(int variant, int Delta, int H, double delta_occ, const float* map,
+                             int64_t X, int64_t Y, int64_t n_traj, const int64_t* traj_off,
+                             const double* poses, int64_t n_beams, const double* beam_dir,
+                             double sigma, double R, double* mi_traj, double* mi_state,
+                             double* mi_beam);
+
 /* ---- ray traversal and virtual sampling ---- */
 /* returns n >= 0 cells, -1 origin outside map / bad direction, -2 capacity */
 int ora_raycast2d(const float* map, int64_t X, int64_t Y, double px, double py,
@@ -77,7 +90,8 @@ int ora_virtual3d(const float* map, int64_t X, int64_t Y, int64_t Z, const doubl
 int ora_rle_runs(int n, const float* occ, float* run_o, int32_t* run_len);
 
 /* ---- batches (OpenMP over beams; threads <= 0 means the OpenMP default) ---- */
-enum { ORA_EXACT = 0, ORA_APPROX = 1, ORA_UNIFORM = 2 };
+/* ORA_CSQMI: the comparison metric of Sec. 2.3 (ora_csqmi), truncated at Delta */
+enum { ORA_EXACT = 0, ORA_APPROX = 1, ORA_UNIFORM = 2, ORA_CSQMI = 3 };
 /* slope, tail: the extensions of ora_fsmi_exact_ext (EXACT only; 0, 0 = Thm 1) */
 int ora_eval_beams(int variant, int Delta, int H, double delta_occ, double slope, int tail,
                    int64_t n_beams, const int64_t* off, const float* occ,
