@@ -59,7 +59,18 @@ typedef enum {
 enum {
   FSMI_EXACT = 0,   /* Thm 1, Eq. fast_exact_mi: full double sum over (j, k) */
   FSMI_APPROX = 1,  /* Eq. fsmi_approx: k restricted to |k - j| <= Delta, no renormalisation */
-  FSMI_UNIFORM = 2  /* Thm 4 / Alg 4: uniform noise of half-width H cells */
+  FSMI_UNIFORM = 2, /* Thm 4 / Alg 4: uniform noise of half-width H cells */
+  /* The comparison metric of Sec. 2.3, not Shannon MI: Approx-CSQMI, Eq.
+     csqmi_exact with both double sums truncated to |l - j| <= Delta
+     (trunc_delta >= 0; trunc_delta >= n - 1 gives the exact CSQMI), in the
+     printed form log B + log C - 2 log A (twice the -1/2 log of the
+     Cauchy-Schwarz divergence's definition).  The weight of a first hit at l
+     is w_l = P(e_l)^2 prod_{i>l} (o_i^2 + (1-o_i)^2), the sum of P(m)^2 over
+     the maps whose first occupied cell is l; the all-free event reads beyond
+     the beam.  Gaussian noise sigma per beam on the cell centres.  2D paths
+     only (fsmi_eval_beams, plans, 2D fsmi_eval_poses); kernel, flags and
+     sigma_slope must be the defaults. */
+  FSMI_CSQMI = 3
 };
 /* Weight between hit cell j and reading cell k on equal-width cells. */
 enum {
@@ -268,6 +279,29 @@ fsmi_status fsmi_eval_poses(fsmi_ctx ctx, const fsmi_params* params, const fsmi_
                             int64_t n_poses, const double* poses, int64_t n_beams,
                             const double* beam_dir, double sigma, double max_range, double w,
                             double* mi_pose, double* mi_beam);
+
+/* ---- trajectory MI with cell marking (Sec. 2.4), 2D maps ----
+   Candidate trajectories in CSR form: trajectory k has the states traj_off[k]
+   .. traj_off[k+1]-1 (device int64 [n_traj + 1], non-decreasing, within
+   [0, n_states]) of poses [n_states][4] = {x, y, cos(yaw), sin(yaw)}, in
+   travel order.  A state's scan MI is the sum over its beams as in
+   fsmi_eval_poses, except that a cell's information counts only at the first
+   state of the trajectory whose beams cross it, and there at every beam of
+   that state crossing it (cells that have contributed are marked and not
+   counted again).  Marked cells still shape the measurement: their f terms
+   leave C_k while P(e_j) uses every cell.  mi_traj[k] = the sum over its
+   states; mi_state [n_states] and mi_beam [n_states][n_beams] (FP64, device)
+   may be NULL.  EXACT, APPROX or UNIFORM, FP32 or FP64, no flags, no
+   sigma_slope (FSMI_E_INVAL otherwise).  Trajectories are evaluated in order
+   on the stream; the context's work area holds 8 bytes per map cell plus the
+   per-beam and per-state sums not kept by the caller.  Bad offsets latch
+   FSMI_E_NUMERIC and give NaN; a state outside the map as in fsmi_eval_poses.
+   Range limits as fsmi_eval_poses on 2D maps. */
+fsmi_status fsmi_eval_trajectories(fsmi_ctx ctx, const fsmi_params* params, const fsmi_map* map,
+                                   int64_t n_traj, const int64_t* traj_off, int64_t n_states,
+                                   const double* poses, int64_t n_beams, const double* beam_dir,
+                                   double sigma, double max_range, double* mi_traj,
+                                   double* mi_state, double* mi_beam);
 
 /* ---- fsmi_eval_poses without device allocation ----
    For callers that cannot allocate device memory during the call: code under

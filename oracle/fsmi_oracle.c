@@ -387,8 +387,7 @@ int ora_eval_trajectories_2d(int variant, int Delta, int H, double delta_occ, co
   int32_t* cell = (int32_t*)malloc(sizeof(int32_t) * max_cells);
   double* entry = (double*)malloc(sizeof(double) * (max_cells + 1));
   float* of = (float*)malloc(sizeof(float) * max_cells);
-  double* o = (double*)malloc(sizeof(double) * max_cells);
-  unsigned char* counted = (unsigned char*)malloc((size_t)max_cells);
+  double* beam_val = (double*)malloc(sizeof(double) * (n_beams > 0 ? n_beams : 1));
   int bad = 0;
   for (int64_t k = 0; k < n_traj; ++k) {
     for (int64_t c = 0; c < X * Y; ++c) first[c] = -1;
@@ -407,25 +406,39 @@ int ora_eval_trajectories_2d(int variant, int Delta, int H, double delta_occ, co
     nsum tk = {0.0, 0.0};
     for (int64_t t = traj_off[k]; t < traj_off[k + 1]; ++t) {
       const double* ps = poses + 4 * t;
-      nsum ts = {0.0, 0.0};
+      /* the state's beams (independent of each other), then their sum in order */
+#pragma omp parallel for schedule(dynamic, 1) reduction(| : bad)
       for (int64_t b = 0; b < n_beams; ++b) {
+        int32_t* bc = (int32_t*)malloc(sizeof(int32_t) * max_cells);
+        double* be = (double*)malloc(sizeof(double) * (max_cells + 1));
+        float* bof = (float*)malloc(sizeof(float) * max_cells);
+        double* bo = (double*)malloc(sizeof(double) * max_cells);
+        unsigned char* bm = (unsigned char*)malloc((size_t)max_cells);
         double bx = beam_dir[2 * b], by = beam_dir[2 * b + 1];
         double m1 = ps[2] * bx, m2 = ps[3] * by, m3 = ps[3] * bx, m4 = ps[2] * by;
-        int n = ora_raycast2d(map, X, Y, ps[0], ps[1], m1 - m2, m3 + m4, R, max_cells, cell,
-                              entry, of);
+        int n = ora_raycast2d(map, X, Y, ps[0], ps[1], m1 - m2, m3 + m4, R, max_cells, bc, be, bof);
         double v;
         if (n < 0) {
           v = NAN;
           bad = 1;
         } else {
           for (int i = 0; i < n; ++i) {
-            o[i] = (double)of[i];
-            counted[i] = first[cell[i]] == (int32_t)(t - traj_off[k]);
+            bo[i] = (double)bof[i];
+            bm[i] = first[bc[i]] == (int32_t)(t - traj_off[k]);
           }
-          v = ora_fsmi_counted(variant, n, o, entry, sigma, delta_occ, Delta, H, counted);
+          v = ora_fsmi_counted(variant, n, bo, be, sigma, delta_occ, Delta, H, bm);
         }
-        if (mi_beam) mi_beam[t * n_beams + b] = v;
-        nadd(&ts, v);
+        beam_val[b] = v;
+        free(bc);
+        free(be);
+        free(bof);
+        free(bo);
+        free(bm);
+      }
+      nsum ts = {0.0, 0.0};
+      for (int64_t b = 0; b < n_beams; ++b) {
+        if (mi_beam) mi_beam[t * n_beams + b] = beam_val[b];
+        nadd(&ts, beam_val[b]);
       }
       if (mi_state) mi_state[t] = nval(&ts);
       nadd(&tk, nval(&ts));
@@ -436,8 +449,7 @@ int ora_eval_trajectories_2d(int variant, int Delta, int H, double delta_occ, co
   free(cell);
   free(entry);
   free(of);
-  free(o);
-  free(counted);
+  free(beam_val);
   return bad ? -1 : 0;
 }
 

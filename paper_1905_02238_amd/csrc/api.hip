@@ -36,11 +36,11 @@ bool check_params(fsmi_ctx ctx, const fsmi_params* p, fsmi_status* st) {
     *st = fail(ctx, FSMI_E_INVAL, "delta_occ must be finite and > 1");
     return false;
   }
-  if (p->variant < FSMI_EXACT || p->variant > FSMI_UNIFORM) {
+  if (p->variant < FSMI_EXACT || p->variant > FSMI_CSQMI) {
     *st = fail(ctx, FSMI_E_INVAL, "unknown variant");
     return false;
   }
-  if (p->variant == FSMI_APPROX && p->trunc_delta < 0) {
+  if ((p->variant == FSMI_APPROX || p->variant == FSMI_CSQMI) && p->trunc_delta < 0) {
     *st = fail(ctx, FSMI_E_INVAL, "trunc_delta must be >= 0");
     return false;
   }
@@ -67,6 +67,10 @@ bool check_params(fsmi_ctx ctx, const fsmi_params* p, fsmi_status* st) {
   if ((p->sigma_slope != 0.0 || (p->flags & FSMI_F_MAX_RANGE)) &&
       (p->variant != FSMI_EXACT || (p->flags & FSMI_F_SKIP_ZERO))) {
     *st = fail(ctx, FSMI_E_INVAL, "sigma_slope and FSMI_F_MAX_RANGE are EXACT (not skip-zero) modes");
+    return false;
+  }
+  if (p->variant == FSMI_CSQMI && (p->flags != 0 || p->sigma_slope != 0.0)) {
+    *st = fail(ctx, FSMI_E_INVAL, "FSMI_CSQMI takes no flags and no sigma_slope");
     return false;
   }
   if ((p->flags & FSMI_F_SKIP_ZERO) && (p->variant != FSMI_EXACT || p->precision != FSMI_FP32)) {
@@ -342,6 +346,8 @@ fsmi_status fsmi_rle_eval_beams(fsmi_ctx ctx, const fsmi_params* params, int64_t
     return fail(ctx, FSMI_E_INVAL, "FSMI_F_SKIP_ZERO needs explicit boundaries");
   if (ext_mode(params))
     return fail(ctx, FSMI_E_INVAL, "sigma_slope and FSMI_F_MAX_RANGE need explicit boundaries");
+  if (params->variant == FSMI_CSQMI)
+    return fail(ctx, FSMI_E_INVAL, "FSMI_CSQMI is a 2D path (fsmi_eval_beams, 2D poses)");
   (void)hipSetDevice(ctx->device);
   return from_hip(ctx,
                   launch_rle_eval_beams(ctx, to_const(params), n_beams, run_off, run_occ, run_len,
@@ -427,6 +433,8 @@ fsmi_status eval_poses_checked(fsmi_ctx ctx, const fsmi_params* params, const fs
     return fail(ctx, FSMI_E_INVAL, "FSMI_F_SKIP_ZERO needs explicit boundaries (2D maps)");
   if (ext_mode(params))
     return fail(ctx, FSMI_E_INVAL, "sigma_slope and FSMI_F_MAX_RANGE need explicit boundaries (2D maps)");
+  if (params->variant == FSMI_CSQMI)
+    return fail(ctx, FSMI_E_INVAL, "FSMI_CSQMI is a 2D path (fsmi_eval_beams, 2D poses)");
   if (!(w > 0.0) || !std::isfinite(w)) return fail(ctx, FSMI_E_INVAL, "w must be finite and > 0");
   if (floor(max_range / w) > 4000.0) return fail(ctx, FSMI_E_CAPACITY, "more than 4000 virtual cells per beam");
   return from_hip(ctx,
@@ -438,6 +446,43 @@ fsmi_status eval_poses_checked(fsmi_ctx ctx, const fsmi_params* params, const fs
 }  // namespace fsmi
 
 extern "C" {
+
+fsmi_status fsmi_eval_trajectories(fsmi_ctx ctx, const fsmi_params* params, const fsmi_map* map,
+                                   int64_t n_traj, const int64_t* traj_off, int64_t n_states,
+                                   const double* poses, int64_t n_beams, const double* beam_dir,
+                                   double sigma, double max_range, double* mi_traj,
+                                   double* mi_state, double* mi_beam) {
+  if (!ctx) return FSMI_E_INVAL;
+  fsmi_status st;
+  if (!check_params(ctx, params, &st)) return st;
+  if (!check_map(ctx, map, &st)) return st;
+  if (map->ndim != 2) return fail(ctx, FSMI_E_INVAL, "trajectories are evaluated on 2D maps");
+  if (params->variant == FSMI_CSQMI)
+    return fail(ctx, FSMI_E_INVAL, "cell marking sums Shannon MI per cell: EXACT, APPROX or UNIFORM");
+  if (params->flags != 0 || params->sigma_slope != 0.0)
+    return fail(ctx, FSMI_E_INVAL, "trajectories take no flags and no sigma_slope");
+  if (n_traj < 0 || n_states < 0 || n_beams < 0) return fail(ctx, FSMI_E_INVAL, "negative count");
+  if (n_traj == 0) return FSMI_OK;
+  if (!traj_off || !mi_traj) return fail(ctx, FSMI_E_INVAL, "traj_off and mi_traj are required");
+  if (n_traj >= ((int64_t)1 << 31)) return fail(ctx, FSMI_E_CAPACITY, "n_traj >= 2^31");
+  if (n_states > 0 && n_beams > 0 && (!poses || !beam_dir))
+    return fail(ctx, FSMI_E_INVAL, "poses and beam_dir are required");
+  if (!(sigma > 0.0) || !std::isfinite(sigma)) return fail(ctx, FSMI_E_INVAL, "sigma must be finite and > 0");
+  if (!(max_range > 0.0) || !std::isfinite(max_range))
+    return fail(ctx, FSMI_E_INVAL, "max_range must be finite and > 0");
+  if (max_range > 4000.0) return fail(ctx, FSMI_E_CAPACITY, "max_range above 4000 cells");
+  if (params->precision == FSMI_FP64 && max_range >= 3873.0)
+    return fail(ctx, FSMI_E_CAPACITY, "max_range above 3872 cells in FP64");
+  if (n_beams > 0 && n_states > ((int64_t)1 << 40) / n_beams)
+    return fail(ctx, FSMI_E_CAPACITY, "too many items");
+  (void)hipSetDevice(ctx->device);
+  return from_hip(ctx,
+                  launch_eval_trajectories_2d(ctx, to_const(params), map->occ, map->dims[0],
+                                              map->dims[1], n_traj, traj_off, n_states, poses,
+                                              n_beams, beam_dir, sigma, max_range, mi_traj,
+                                              mi_state, mi_beam),
+                  "eval_trajectories");
+}
 
 fsmi_status fsmi_probe_erfc(fsmi_ctx ctx, int64_t n, const float* z, float* out) {
   if (!ctx) return FSMI_E_INVAL;

@@ -514,10 +514,13 @@ struct CoreLds {
 // The beam's mutual information, valid in every lane of the group.
 // so[0..n): occupancies; with explicit bounds A[0..n] holds l_1..l_{n+1}.
 // *bad is set (group-uniform) when an input is invalid; the result is then NaN.
-template <int NW, bool BLOCK, typename T>
+// MASK: only the cells i with counted[i] != 0 add their information (cell
+// marking along a trajectory, Sec. 2.4): by Lemma 1 the f terms of the other
+// cells leave C_k, while every cell still shapes P(e_j).
+template <int NW, bool BLOCK, typename T, bool MASK = false>
 FSMI_DEV double beam_core(const EvalConst& ec, int n, const float* so, bool has_bound, double sigma,
                           const CoreLds& L, double* scratch, int* flag, int tid, bool bad_in,
-                          bool* bad_out) {
+                          bool* bad_out, const unsigned char* counted = nullptr) {
   constexpr int G = Grp<NW, BLOCK>::size;
   double* sA = L.A;
   T* sC = reinterpret_cast<T*>(L.C);
@@ -561,6 +564,9 @@ FSMI_DEV double beam_core(const EvalConst& ec, int n, const float* so, bool has_
         fe = f_cell<double>(demp, lde, o);
       }
       if (!v) fo[u] = fe = 0.0;
+      if constexpr (MASK) {
+        if (v && !counted[i0 + u]) fo[u] = fe = 0.0;
+      }
       qin[u] = qs;
       ein[u] = es;
       qs += fe;

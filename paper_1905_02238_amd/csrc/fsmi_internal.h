@@ -23,15 +23,15 @@ struct fsmi_ctx_s {
   std::string last_error;
   // Autotuned wave/tile threshold of the beam-batch schedule, per
   // [precision][variant][explicit boundaries]; 0 = not tuned (use the default).
-  int tuned_wave_max[2][3][2] = {};
+  int tuned_wave_max[2][4][2] = {};
 };
 
 namespace fsmi {
 
 // Scalars of one evaluation, shared by every kernel family.
 struct EvalConst {
-  int variant;       // FSMI_EXACT / FSMI_APPROX / FSMI_UNIFORM
-  int Delta;         // truncation width (cells), APPROX
+  int variant;       // FSMI_EXACT / FSMI_APPROX / FSMI_UNIFORM / FSMI_CSQMI
+  int Delta;         // truncation width (cells), APPROX and CSQMI
   int H;             // uniform half-width (cells), UNIFORM
   int kernel;        // FSMI_KERNEL_ERF / FSMI_KERNEL_DENSITY (equal-width engines)
   int precision;     // FSMI_FP32 / FSMI_FP64
@@ -104,6 +104,14 @@ hipError_t launch_eval_poses_2d(fsmi_ctx ctx, const EvalConst& ec, const float* 
                                 int64_t Y, int64_t n_poses, const double* poses, int64_t n_beams,
                                 const double* beam_dir, double sigma, double R, double* mi_pose,
                                 double* mi_beam, const PoseScratch* ws = nullptr);
+
+// ---- launchers (k_traj.hip) ----
+hipError_t launch_eval_trajectories_2d(fsmi_ctx ctx, const EvalConst& ec, const float* map,
+                                       int64_t X, int64_t Y, int64_t n_traj,
+                                       const int64_t* traj_off, int64_t n_states,
+                                       const double* poses, int64_t n_beams,
+                                       const double* beam_dir, double sigma, double R,
+                                       double* mi_traj, double* mi_state, double* mi_beam);
 
 // ---- launchers (k_rle.hip) ----
 hipError_t launch_rle_eval_beams(fsmi_ctx ctx, const EvalConst& ec, int64_t n_beams,

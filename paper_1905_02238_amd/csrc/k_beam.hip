@@ -11,6 +11,7 @@
 #include <algorithm>
 
 #include "beam_dev.h"
+#include "csqmi_dev.h"
 #include "fsmi_internal.h"
 
 namespace fsmi {
@@ -51,7 +52,7 @@ FSMI_DEV CoreLds carve(char* p, int cap, float** so) {
   return L;
 }
 
-template <bool BLOCK, typename T>
+template <bool BLOCK, typename T, bool CSQ>
 FSMI_DEV void process_beam(const BeamArgs& a, int b, char* lds, int cap, double* scratch,
                            int* flag, int tid) {
   constexpr int G = Grp<kNW, BLOCK>::size;
@@ -72,7 +73,7 @@ FSMI_DEV void process_beam(const BeamArgs& a, int b, char* lds, int cap, double*
     }
     Grp<kNW, BLOCK>::sync();
     bool bad;
-    v = beam_core<kNW, BLOCK, T>(a.ec, n, so, has_bound, (double)a.sigma[b], L, scratch, flag, tid,
+    v = beam_eval<kNW, BLOCK, T, CSQ>(a.ec, n, so, has_bound, (double)a.sigma[b], L, scratch, flag, tid,
                                  false, &bad);
     if (bad) err = kErrOcc;
   } else if (n != 0) {
@@ -89,7 +90,7 @@ FSMI_DEV void process_beam(const BeamArgs& a, int b, char* lds, int cap, double*
 // Every value that steers a branch around a barrier is made wave-uniform
 // (readfirstlane), so those branches are scalar and all waves of the
 // workgroup meet the same barriers.
-template <typename T>
+template <typename T, bool CSQ>
 __global__ __launch_bounds__(kWave* kNW) void k_eval_long(BeamArgs a) {
   extern __shared__ __align__(16) char lds[];
   __shared__ double scratch[kNW];
@@ -104,14 +105,14 @@ __global__ __launch_bounds__(kWave* kNW) void k_eval_long(BeamArgs a) {
     __syncthreads();
     if (it >= n_long) break;
     const int b = __builtin_amdgcn_readfirstlane(a.order[it]);
-    process_beam<true, T>(a, b, lds, a.cap_block, scratch, &s_flag, tid);
+    process_beam<true, T, CSQ>(a, b, lds, a.cap_block, scratch, &s_flag, tid);
     __syncthreads();
   }
 }
 
 // Wave-per-beam: the remaining beams, each wave on its own LDS slice; no
 // workgroup barriers.
-template <typename T>
+template <typename T, bool CSQ>
 __global__ __launch_bounds__(kWave* kNW) void k_eval_short(BeamArgs a) {
   extern __shared__ __align__(16) char lds[];
   const int tid = threadIdx.x;
@@ -130,7 +131,7 @@ __global__ __launch_bounds__(kWave* kNW) void k_eval_short(BeamArgs a) {
     k = (int)run_length(n_short, end, n_waves);
     for (int it = start; it < end; ++it) {
       const int b = __builtin_amdgcn_readfirstlane(a.order[n_long + it]);
-      process_beam<false, T>(a, b, my, a.cap_wave, nullptr, nullptr, lane);
+      process_beam<false, T, CSQ>(a, b, my, a.cap_wave, nullptr, nullptr, lane);
     }
   }
 }
@@ -327,16 +328,19 @@ hipError_t launch_beam_kernels(hipStream_t st, int num_cu, const EvalConst& ec, 
       1, std::min<int64_t>(want, std::min(kMaxGrid, num_cu * std::min(per_cu_s, 8))));
   // queue heads back to zero; the long-beam count written by the schedule stays
   hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, st, a.counters);
+  auto launch = [&](auto klong, auto kshort) {
+    (void)hipFuncSetAttribute((const void*)klong, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_long);
+    (void)hipFuncSetAttribute((const void*)kshort, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_short);
+    if (run_long) hipLaunchKernelGGL(klong, dim3(grid_l), dim3(kWave * kNW), lds_long, st, a);
+    if (run_short) hipLaunchKernelGGL(kshort, dim3(grid_s), dim3(kWave * kNW), lds_short, st, a);
+  };
+  const bool csq = ec.variant == FSMI_CSQMI;
   if (fp64) {
-    (void)hipFuncSetAttribute((const void*)k_eval_long<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_long);
-    (void)hipFuncSetAttribute((const void*)k_eval_short<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_short);
-    if (run_long) hipLaunchKernelGGL(k_eval_long<double>, dim3(grid_l), dim3(kWave * kNW), lds_long, st, a);
-    if (run_short) hipLaunchKernelGGL(k_eval_short<double>, dim3(grid_s), dim3(kWave * kNW), lds_short, st, a);
+    if (csq) launch(k_eval_long<double, true>, k_eval_short<double, true>);
+    else launch(k_eval_long<double, false>, k_eval_short<double, false>);
   } else {
-    (void)hipFuncSetAttribute((const void*)k_eval_long<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_long);
-    (void)hipFuncSetAttribute((const void*)k_eval_short<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_short);
-    if (run_long) hipLaunchKernelGGL(k_eval_long<float>, dim3(grid_l), dim3(kWave * kNW), lds_long, st, a);
-    if (run_short) hipLaunchKernelGGL(k_eval_short<float>, dim3(grid_s), dim3(kWave * kNW), lds_short, st, a);
+    if (csq) launch(k_eval_long<float, true>, k_eval_short<float, true>);
+    else launch(k_eval_long<float, false>, k_eval_short<float, false>);
   }
   return hipGetLastError();
 }

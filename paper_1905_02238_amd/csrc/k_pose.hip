@@ -12,6 +12,7 @@
 #include <algorithm>
 
 #include "beam_dev.h"
+#include "csqmi_dev.h"
 #include "fsmi_internal.h"
 #include "ray_dev.h"
 
@@ -48,7 +49,7 @@ __host__ __device__ inline size_t pose2d_lds(int capa, int ecap) {
   return pose2d_region1<T>(capa, ecap) + 8 * (size_t)(ecap + 1) + 4 * (size_t)ecap + 16;
 }
 
-template <typename T>
+template <typename T, bool CSQ>
 __global__ __launch_bounds__(kWave) void k_poses2d(Pose2dArgs a) {
 #pragma clang fp contract(off)
   extern __shared__ __align__(16) char lds[];
@@ -117,7 +118,7 @@ __global__ __launch_bounds__(kWave) void k_poses2d(Pose2dArgs a) {
         L.P = sizeof(T) == 4 ? reinterpret_cast<void*>(so + res.skip0)
                              : reinterpret_cast<void*>(r1 + sizeof(T) * (size_t)a.ecap);
         bool bad;
-        v = beam_core<1, false, T>(a.ec, res.n, so + res.skip0, true, a.sigma, L, nullptr, nullptr,
+        v = beam_eval<1, false, T, CSQ>(a.ec, res.n, so + res.skip0, true, a.sigma, L, nullptr, nullptr,
                                    lane, false, &bad);
         if (bad && lane == 0) latch(a.status, kErrOcc);
       }
@@ -189,12 +190,17 @@ hipError_t launch_eval_poses_2d(fsmi_ctx ctx, const EvalConst& ec, const float* 
   if (lds > 150 * 1024) return hipErrorInvalidValue;
   const int per_cu = std::max<int>(1, std::min<int>(16, (int)((160 * 1024) / (lds + 256))));
   const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(n_items, (int64_t)ctx->num_cu * per_cu));
+  auto launch = [&](auto kern) {
+    (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kWave), lds, ctx->stream, a);
+  };
+  const bool csq = ec.variant == FSMI_CSQMI;
   if (fp64) {
-    (void)hipFuncSetAttribute((const void*)k_poses2d<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k_poses2d<double>, dim3(grid), dim3(kWave), lds, ctx->stream, a);
+    if (csq) launch(k_poses2d<double, true>);
+    else launch(k_poses2d<double, false>);
   } else {
-    (void)hipFuncSetAttribute((const void*)k_poses2d<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k_poses2d<float>, dim3(grid), dim3(kWave), lds, ctx->stream, a);
+    if (csq) launch(k_poses2d<float, true>);
+    else launch(k_poses2d<float, false>);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

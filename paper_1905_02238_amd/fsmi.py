@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libfsmi.so")
 
 FSMI_OK, FSMI_E_INVAL, FSMI_E_DEVICE, FSMI_E_NOMEM, FSMI_E_CAPACITY, FSMI_E_NUMERIC, \
     FSMI_E_UNSUPPORTED = range(7)
-FSMI_EXACT, FSMI_APPROX, FSMI_UNIFORM = 0, 1, 2
+FSMI_EXACT, FSMI_APPROX, FSMI_UNIFORM, FSMI_CSQMI = 0, 1, 2, 3
 FSMI_KERNEL_ERF, FSMI_KERNEL_DENSITY = 0, 1
 FSMI_FP32, FSMI_FP64 = 0, 1
 FSMI_RAY_DDA, FSMI_RAY_VIRTUAL, FSMI_RAY_RLE = 0, 1, 2
@@ -31,7 +31,7 @@ FSMI_PEAK_COPY, FSMI_PEAK_FMA, FSMI_PEAK_PAIR, FSMI_PEAK_MFMA_BF16 = 0, 1, 2, 3
 EXPORTS = ("fsmi_create", "fsmi_destroy", "fsmi_set_stream", "fsmi_sync", "fsmi_last_error",
            "fsmi_status_string", "fsmi_default_params", "fsmi_raycast", "fsmi_eval_beams",
            "fsmi_rle_eval_beams", "fsmi_rle_table_eval_beams", "fsmi_eval_poses",
-           "fsmi_eval_poses_noalloc", "fsmi_probe_erfc", "fsmi_probe_f", "fsmi_probe_mfma", "fsmi_peak",
+           "fsmi_eval_poses_noalloc", "fsmi_eval_trajectories", "fsmi_probe_erfc", "fsmi_probe_f", "fsmi_probe_mfma", "fsmi_peak",
            "fsmi_sur_num_params", "fsmi_sur_create", "fsmi_sur_destroy",
            "fsmi_sur_fit_label_stats", "fsmi_sur_get_label_stats", "fsmi_sur_forward",
            "fsmi_sur_backward", "fsmi_sur_adam_step", "fsmi_sur_get_params",
@@ -94,6 +94,8 @@ def load(path: str = LIB_PATH):
             L.fsmi_eval_poses.argtypes = [p, C.POINTER(fsmi_params), C.POINTER(fsmi_map), i64, p,
                                           i64, p, d, d, d, p, p]
             L.fsmi_eval_poses_noalloc.argtypes = L.fsmi_eval_poses.argtypes
+            L.fsmi_eval_trajectories.argtypes = [p, C.POINTER(fsmi_params), C.POINTER(fsmi_map),
+                                                 i64, p, i64, p, i64, p, d, d, p, p, p]
             L.fsmi_probe_erfc.argtypes = [p, i64, p, p]
             L.fsmi_probe_f.argtypes = [p, d, i64, p, p]
             L.fsmi_peak.argtypes = [p, i32, C.POINTER(d), C.POINTER(d)]
@@ -124,7 +126,7 @@ def load(path: str = LIB_PATH):
             for n in ("fsmi_create", "fsmi_set_stream", "fsmi_sync", "fsmi_raycast",
                       "fsmi_eval_beams", "fsmi_rle_eval_beams", "fsmi_rle_table_eval_beams",
                       "fsmi_eval_poses", "fsmi_eval_poses_noalloc",
-                      "fsmi_probe_erfc", "fsmi_probe_f", "fsmi_probe_mfma", "fsmi_peak", "fsmi_sur_create",
+                      "fsmi_eval_trajectories", "fsmi_probe_erfc", "fsmi_probe_f", "fsmi_probe_mfma", "fsmi_peak", "fsmi_sur_create",
                       "fsmi_sur_fit_label_stats", "fsmi_sur_get_label_stats", "fsmi_sur_forward",
                       "fsmi_sur_backward", "fsmi_sur_adam_step", "fsmi_sur_get_params",
                       "fsmi_sur_set_params", "fsmi_sur_get_grads", "fsmi_sur_save",
@@ -289,6 +291,23 @@ class Context:
         by the call (outputs are still the caller's; pass them to allocate nothing here)."""
         return self.fsmi_eval_poses(prm, map_occ, poses, beam_dir, sigma, max_range, w, mi_pose,
                                     mi_beam, want_beams, _entry="fsmi_eval_poses_noalloc")
+
+    def fsmi_eval_trajectories(self, prm: fsmi_params, map_occ, traj_off, poses, beam_dir, sigma,
+                               max_range, want_states=True, want_beams=False):
+        """Trajectory MI with cell marking: (mi_traj, mi_state or None, mi_beam or None)."""
+        nt, ns, nb = traj_off.shape[0] - 1, poses.shape[0], beam_dir.shape[0]
+        dev = map_occ.device
+        mt = torch.empty(nt, dtype=torch.float64, device=dev)
+        ms = torch.empty(ns, dtype=torch.float64, device=dev) if want_states else None
+        mb = torch.empty((ns, nb), dtype=torch.float64, device=dev) if want_beams else None
+        m = _map(map_occ)
+        self._stream()
+        self._check(self._lib.fsmi_eval_trajectories(
+            self.handle, C.byref(prm), C.byref(m), nt, _ptr(traj_off, torch.int64, "traj_off"), ns,
+            _ptr(poses, torch.float64, "poses"), nb, _ptr(beam_dir, torch.float64, "beam_dir"),
+            float(sigma), float(max_range), _ptr(mt, torch.float64, "mi_traj"),
+            _ptr(ms, torch.float64, "mi_state", True), _ptr(mb, torch.float64, "mi_beam", True)))
+        return mt, ms, mb
 
     def fsmi_probe_erfc(self, z, out=None):
         out = torch.empty_like(z) if out is None else out

@@ -1,0 +1,143 @@
+"""Trajectory MI with cell marking (Sec. 2.4) on the GPU against the FP64 oracle:
+per beam, per state and per trajectory, for the three FSMI variants in FP32
+(1e-5 relative; an exact zero, a state whose cells were all counted before,
+must stay zero) and FP64 (1e-12); empty trajectories, bad offsets, and the
+one-state trajectory equal to the pose path."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_1905_02238_amd import fsmi as F
+from paper_1905_02238_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    print("[gpu] trajectories: creating libfsmi context on cuda:0", flush=True)
+    return F.context(0)
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def rel_err(got, ref):
+    got, ref = np.asarray(got, np.float64), np.asarray(ref, np.float64)
+    zero = ref == 0.0
+    assert np.all(got[zero] == 0.0), "an exact zero of the oracle is not zero on the GPU"
+    nz = ~zero
+    return float(np.max(np.abs(got[nz] - ref[nz]) / np.abs(ref[nz]))) if np.any(nz) else 0.0
+
+
+def walks(labels, n_traj, steps, seed, step_len=4.0):
+    """n_traj short walks through free cells: CSR offsets and the states [x, y, cos, sin]."""
+    rng = np.random.default_rng(seed)
+    ys, xs = np.nonzero(labels == W.FREE)
+    states, off = [], [0]
+    for _ in range(n_traj):
+        i = rng.integers(0, len(xs))
+        x, y = xs[i] + rng.uniform(0.1, 0.9), ys[i] + rng.uniform(0.1, 0.9)
+        a = rng.uniform(0, 2 * math.pi)
+        for _ in range(steps):
+            states.append([x, y, math.cos(a), math.sin(a)])
+            for _ in range(30):
+                nx, ny = x + step_len * math.cos(a), y + step_len * math.sin(a)
+                if 0 <= nx < labels.shape[1] and 0 <= ny < labels.shape[0] and \
+                        labels[int(ny), int(nx)] == W.FREE:
+                    x, y = nx, ny
+                    break
+                a = rng.uniform(0, 2 * math.pi)
+        off.append(len(states))
+    return np.array(off, np.int64), np.array(states)
+
+
+@pytest.mark.parametrize("variant", [F.FSMI_EXACT, F.FSMI_APPROX, F.FSMI_UNIFORM])
+@pytest.mark.parametrize("prec,tol", [(F.FSMI_FP32, 1e-5), (F.FSMI_FP64, 1e-12)])
+def test_trajectories_small_rooms(ctx, variant, prec, tol):
+    """200 x 200 rooms, 5 walks of 6 states (one repeated, so it counts
+    nothing), 72 beams, R = 60, sigma = 2."""
+    print(f"[gpu] trajectories small variant={variant} prec={prec}", flush=True)
+    wl = W.grid_small()
+    off, poses = walks(wl["labels"], 5, 6, 11)
+    poses = np.concatenate([poses[:3], poses[2:3], poses[3:]])   # state 3 repeats state 2
+    off = np.array([0, 7] + [int(v) + 1 for v in off[2:]], np.int64)
+    bd = W.beam_dirs_2d(72)
+    prm = F.params(variant=variant, trunc_delta=6, uniform_h=4, precision=prec)
+    mt, ms, mb = ctx.fsmi_eval_trajectories(prm, dev(wl["grid"]), dev(off), dev(poses), dev(bd),
+                                            2.0, 60.0, want_beams=True)
+    torch.cuda.synchronize()
+    ctx.fsmi_sync()
+    rt, rs, rb = O.eval_trajectories_2d(variant, wl["grid"], off, poses, bd, 2.0, 60.0,
+                                        Delta=6, H=4)
+    assert rs[3] == 0.0
+    assert rel_err(mb.cpu().numpy(), rb) <= tol
+    assert rel_err(ms.cpu().numpy(), rs) <= tol
+    assert rel_err(mt.cpu().numpy(), rt) <= tol
+
+
+def test_trajectories_large_rooms_and_the_one_state_case(ctx):
+    """2048 x 2048 rooms, 12 walks of 16 states, 360 beams, R = 400, sigma = 3
+    (Approx-FSMI, Delta = 9): two walks state by state against the oracle,
+    every walk's value against the sum of its states, and a walk of one state
+    equal to fsmi_eval_poses on that pose."""
+    print("[gpu] trajectories large", flush=True)
+    wl = W.grid_large(n_poses=1)
+    off, poses = walks(wl["labels"], 12, 16, 5, step_len=6.0)
+    bd = W.beam_dirs_2d(360)
+    prm = F.params(variant=F.FSMI_APPROX, trunc_delta=9)
+    g = dev(wl["grid"])
+    mt, ms, _ = ctx.fsmi_eval_trajectories(prm, g, dev(off), dev(poses), dev(bd), 3.0, 400.0)
+    torch.cuda.synchronize()
+    ctx.fsmi_sync()
+    mt, ms = mt.cpu().numpy(), ms.cpu().numpy()
+    for k in range(12):
+        assert abs(mt[k] - math.fsum(ms[off[k]:off[k + 1]])) <= 1e-12 * mt[k]
+    sel = np.concatenate([np.arange(off[0], off[1]), np.arange(off[7], off[8])])
+    rt, rs, _ = O.eval_trajectories_2d(O.APPROX, wl["grid"], [0, 16, 32], poses[sel], bd, 3.0,
+                                       400.0, Delta=9, want_beams=False)
+    assert rel_err(ms[sel], rs) <= 1e-5
+    assert rel_err(mt[[0, 7]], rt) <= 1e-5
+    # marking only removes information, and the first state counts everything
+    mp, _ = ctx.fsmi_eval_poses(prm, g, dev(poses), dev(bd), 3.0, 400.0)
+    torch.cuda.synchronize()
+    mp = mp.cpu().numpy()
+    assert np.all(ms <= mp * (1 + 1e-6))
+    assert np.array_equal(ms[off[:-1]], mp[off[:-1]])
+    one, _, _ = ctx.fsmi_eval_trajectories(prm, g, dev(np.array([0, 1], np.int64)),
+                                           dev(poses[5:6]), dev(bd), 3.0, 400.0)
+    torch.cuda.synchronize()
+    assert float(one[0]) == float(mp[5])
+
+
+def test_trajectories_empty_and_bad_offsets(ctx):
+    wl = W.grid_small()
+    off, poses = walks(wl["labels"], 2, 3, 2)
+    bd = dev(W.beam_dirs_2d(16))
+    g = dev(wl["grid"])
+    prm = F.params()
+    # an empty trajectory in the middle sums to zero
+    off2 = np.array([0, 3, 3, 6], np.int64)
+    mt, _, _ = ctx.fsmi_eval_trajectories(prm, g, dev(off2), dev(poses), bd, 2.0, 50.0)
+    torch.cuda.synchronize()
+    ctx.fsmi_sync()
+    mt = mt.cpu().numpy()
+    assert mt[1] == 0.0 and mt[0] > 0.0 and mt[2] > 0.0
+    # offsets past the states: that trajectory is NaN and the call latches
+    bad = np.array([0, 3, 9], np.int64)
+    mt, _, _ = ctx.fsmi_eval_trajectories(prm, g, dev(bad), dev(poses), bd, 2.0, 50.0)
+    torch.cuda.synchronize()
+    with pytest.raises(F.FsmiError):
+        ctx.fsmi_sync()
+    mt = mt.cpu().numpy()
+    assert mt[0] > 0.0 and math.isnan(mt[1])
+    with pytest.raises(F.FsmiError):
+        ctx.fsmi_eval_trajectories(F.params(variant=F.FSMI_CSQMI), g, dev(off), dev(poses), bd,
+                                   2.0, 50.0)
+    with pytest.raises(F.FsmiError):
+        ctx.fsmi_eval_trajectories(F.params(flags=F.FSMI_F_MAX_RANGE), g, dev(off), dev(poses),
+                                   bd, 2.0, 50.0)
