@@ -79,6 +79,13 @@ BF16_PEAK_TFLOPS = 2500.0
 # ALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T lane-ops/s
 # (one non-packed FP32 or FP64 VALU instruction per lane per clock).
 ALU_PEAK_TSLOT = 256 * 64 * 2.4e9 / 1e12
+# The exact sum's roof in its own unit, (row, boundary) pairs per second: a
+# pair takes at least one FP32 erfc of the library's form (FMA, reciprocal,
+# degree-7 Horner, exponent FMA, 2^x, product: 12 instructions, two of them on
+# the transcendental unit) and one FMA into the row sum, 13 issue slots, at one
+# instruction per lane per clock: 256 x 64 x 2.4e9 / 13 = 3.02e12 pairs/s.
+PAIR_ISSUE_SLOTS = 13
+PHI_PAIR_PEAK = 256 * 64 * 2.4e9 / PAIR_ISSUE_SLOTS
 
 
 def parse():
@@ -112,7 +119,7 @@ def parse():
                          "nothing else")
     ap.add_argument("--profile-3d", action="store_true",
                     help="for kernel traces: one 3D launch each of FSMI-RLE, Approx-FSMI-RLE "
-                         "(Delta = 6) and Uniform-FSMI-RLE (H = 4), 256 poses x 16 384 beams on "
+                         "(Delta = 6) and Uniform-FSMI-RLE (H = 4), 1024 poses x 16 384 beams on "
                          "the 512 x 512 x 128 voxel map, nothing else")
     ap.add_argument("--profile-table", action="store_true",
                     help="for kernel traces: the table route of Approx-FSMI-RLE and Approx-FSMI "
@@ -172,7 +179,7 @@ def main():
         net.close()
         return
     if args.profile_3d:
-        vw = W.voxels_large(n_poses=256)
+        vw = W.voxels_large(n_poses=1024)
         vx, vp, vb = t(vw["vox"]), t(vw["poses"]), t(vw["beam_dir"])
         for prm in (F.params(), F.params(variant=F.FSMI_APPROX, trunc_delta=6),
                     F.params(variant=F.FSMI_UNIFORM, uniform_h=4)):
@@ -266,7 +273,8 @@ def main():
     ms_step = wall / args.steps * 1e3
     value = n_total / (wall / args.steps)
     kern_ms = float(np.mean(ev_ms))
-    achieved = pairs * SLOTS_PER_PAIR / (kern_ms * 1e-3) / 1e12
+    achieved = pairs / (kern_ms * 1e-3)                      # (row, boundary) pairs per second
+    slots = pairs * SLOTS_PER_PAIR / (kern_ms * 1e-3) / 1e12
     log(f"[bench] exact: {ms_step:.2f} ms/step (events {kern_ms:.2f} ms), {value/1e6:.3f} M beams/s")
 
     out = {
@@ -286,11 +294,17 @@ def main():
                                f"{n_poses} poses x {n_beams} beams, R=400, sigma=3",
                    "poses": n_poses, "beams_per_pose": n_beams, "max_range": R, "sigma": sigma,
                    "mean_cells_per_beam": mean_n, "pairs_per_step": pairs},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TSLOT,
-                     "unit": "TFLOP/s", "frac": achieved / ALU_PEAK_TSLOT,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PHI_PAIR_PEAK,
+                     "unit": "pairs/s", "frac": achieved / PHI_PAIR_PEAK,
                      "traffic": measured_traffic(),
                      "kernel": "k_poses2d<float>", "kernel_ms": kern_ms,
-                     "work": f"{SLOTS_PER_PAIR} VALU slots per (row, boundary) pair"},
+                     "work": "n(n+1) (row, boundary) pairs per beam (Thm 1 with one erfc per "
+                             "pair), counted from the walks; peak: 13 issue slots per pair "
+                             "at 256 CU x 64 lanes x 2.4 GHz",
+                     "slot_accounting": {"charged_slots_per_pair": SLOTS_PER_PAIR,
+                                         "achieved_Tslot_per_s": slots,
+                                         "issue_peak_Tslot_per_s": ALU_PEAK_TSLOT,
+                                         "frac": slots / ALU_PEAK_TSLOT}},
     }
 
     # the chip's ceilings measured by the library's own microbenchmarks, beside
@@ -304,17 +318,16 @@ def main():
         ceil[key.split("_")[0] + "_" + key.split("_")[1] + "_clock_MHz"] = mhz
     out["measured_ceilings"] = ceil
     roof = out["roofline"]
-    roof["measured_peak"] = ceil["fp32_fma_TFLOPs"] / 2      # one FMA per issue slot
-    roof["frac_of_measured"] = achieved / roof["measured_peak"]
-    roof["pairs_per_s"] = pairs / (kern_ms * 1e-3)
-    roof["frac_of_phi_pair_ceiling"] = roof["pairs_per_s"] / (ceil["phi_pair_Tpairs_per_s"] * 1e12)
+    roof["measured_pair_ceiling"] = ceil["phi_pair_Tpairs_per_s"] * 1e12
+    roof["frac_of_measured_pair_ceiling"] = achieved / roof["measured_pair_ceiling"]
+    roof["slot_accounting"]["frac_of_measured_fma_rate"] = slots / (ceil["fp32_fma_TFLOPs"] / 2)
     log(f"[bench] measured ceilings: copy {ceil['hbm_copy_TBps']:.2f} TB/s, FP32 FMA "
         f"{ceil['fp32_fma_TFLOPs']:.1f} TFLOP/s, erfc+FMA pairs {ceil['phi_pair_Tpairs_per_s']:.3f} "
         f"T pairs/s, BF16 MFMA {ceil['bf16_mfma_TFLOPs']:.0f} TFLOP/s (shader clocks "
         f"{ceil['hbm_copy_clock_MHz']:.0f}, {ceil['fp32_fma_clock_MHz']:.0f}, "
         f"{ceil['phi_pair_clock_MHz']:.0f}, {ceil['bf16_mfma_clock_MHz']:.0f} MHz); exact at "
-        f"{roof['frac_of_measured']:.3f} of the measured slot rate, "
-        f"{roof['frac_of_phi_pair_ceiling']:.3f} of the erfc+FMA pair ceiling")
+        f"{roof['frac']:.3f} of the 13-slot pair peak, "
+        f"{roof['frac_of_measured_pair_ceiling']:.3f} of the measured erfc+FMA pair ceiling")
 
     gpu = {"exact": mp}      # results the oracle leg checks, per workload
     # ---- extras: other variants and workloads, one timed run each ----
@@ -332,7 +345,7 @@ def main():
                         ("uniform_h6", F.params(variant=F.FSMI_UNIFORM, uniform_h=6))):
             dt = timed(lambda: ctx.fsmi_eval_poses(p, grid, poses, bdir, sigma, R))
             extras[name] = {"beams_per_s": n_total / dt, "ms": dt * 1e3}
-            gpu[name] = ctx.fsmi_eval_poses(p, grid, poses, bdir, sigma, R)[0]
+            gpu[name] = ctx.fsmi_eval_poses(p, grid, poses, bdir, sigma, R, want_beams=True)
             log(f"[bench] {name}: {n_total/dt/1e6:.2f} M beams/s")
         # skip-zero exact mode: same workload, pairs whose FP32 weight is below
         # the smallest normal float left out; its own work count from the
@@ -394,7 +407,7 @@ def main():
             gpu[name] = ctx.fsmi_eval_poses(pp, gs, ps, bs, small["sigma"], small["R"],
                                             want_beams=True)
         log("[bench] generating the 512x512x128 voxel map")
-        vw = W.voxels_large(n_poses=256)
+        vw = W.voxels_large(n_poses=1024)
         vx, vp, vb = t(vw["vox"]), t(vw["poses"]), t(vw["beam_dir"])
         gpu["voxels"] = vw
         nv = vp.shape[0] * vb.shape[0]
@@ -402,11 +415,17 @@ def main():
                         ("rle_approx_delta6_3d", F.params(variant=F.FSMI_APPROX, trunc_delta=6)),
                         ("rle_uniform_h4_3d", F.params(variant=F.FSMI_UNIFORM, uniform_h=4))):
             dt = timed(lambda: ctx.fsmi_eval_poses(p, vx, vp, vb, vw["sigma"], vw["R"], vw["w"]), reps=2)
-            extras[name] = {"beams_per_s": nv / dt, "ms": dt * 1e3, "poses": vp.shape[0]}
-            gpu[name] = ctx.fsmi_eval_poses(p, vx, vp, vb, vw["sigma"], vw["R"], vw["w"],
-                                            want_beams=True)
+            extras[name] = {"beams_per_s": nv / dt, "ms": dt * 1e3, "poses": vp.shape[0],
+                            "poses_per_s": vp.shape[0] / dt}
+            mp3, mb3 = ctx.fsmi_eval_poses(p, vx, vp, vb, vw["sigma"], vw["R"], vw["w"],
+                                           want_beams=True)
+            gpu[name] = (mp3, mb3[:16].clone())      # the oracle checks the first 16 poses
+            del mb3
             log(f"[bench] {name}: {nv/dt/1e6:.2f} M beams/s")
         extras["rle_table_crossover"] = table_route_leg(ctx, F, W, t, timed)
+        extras["csqmi_comparison"] = csqmi_leg(ctx, F, W, t, timed, grid, poses, bdir, sigma, R,
+                                               n_total, extras, gpu)
+        extras["trajectories"] = trajectory_leg(ctx, F, W, t, timed, wl, gpu)
         extras["surrogate_rank"] = surrogate_leg(ctx, F, W, t, timed, args)
         extras["surrogate_rank"]["forward_frac_of_measured_mfma"] = (
             extras["surrogate_rank"]["forward_tflops"] / ceil["bf16_mfma_TFLOPs"])
@@ -430,6 +449,18 @@ def _err_stats(rel, bar, **kw):
               "p99_rel": float(np.percentile(rel, 99)), "mean_rel": float(rel.mean()),
               "bar": bar, "within_bar": bool(rel.max() <= bar)})
     return d
+
+
+def _log_err_stats(got, ref, **kw):
+    """Error of a value that is a difference of logarithms (CSQMI): the sums'
+    rounding shows up as an absolute error, so the bar is 1e-5 |I| + 2e-6."""
+    got, ref = np.asarray(got, np.float64).ravel(), np.asarray(ref, np.float64).ravel()
+    d = np.abs(got - ref)
+    st = _err_stats(_rel(got, ref), 1e-5, **kw)
+    st["abs_bar"] = 2e-6
+    st["max_abs"] = float(d.max())
+    st["within_bar"] = bool(np.all(d <= 1e-5 * np.abs(ref) + 2e-6))
+    return st
 
 
 def oracle_leg(out, gpu, wl, W, args, ctx, F, t):
@@ -459,6 +490,16 @@ def oracle_leg(out, gpu, wl, W, args, ctx, F, t):
                            "sample": f"first {k} poses x {n_beams} beams of the timed workload, "
                                      f"{cs:.1f} s, FP64, OpenMP over poses"}
     log(f"[bench] cpu oracle: {k} poses in {cs:.1f} s on {thr} threads")
+    # the same oracle on one core (the paper's setting is single-threaded)
+    k1 = int(max(1, min(len(wl["poses"]), round((1.0 if args.quick else 5.0) / max(one, 1e-3)))))
+    t1 = time.perf_counter()
+    O.eval_poses_2d(O.EXACT, wl["grid"], wl["poses"][:k1], wl["beam_dir"], sig, R, threads=1,
+                    want_beams=False)
+    c1 = time.perf_counter() - t1
+    out["cpu_baseline"]["single_core"] = {
+        "value": k1 * n_beams / c1, "unit": "beams/s", "cores": 1,
+        "sample": f"first {k1} poses x {n_beams} beams, {c1:.1f} s, FP64, one thread"}
+    log(f"[bench] cpu oracle, one core: {k1 * n_beams / c1:.0f} beams/s")
 
     rep = {}
     # the timed launch's per-pose results; per-beam results of the same kernel on the sample
@@ -472,11 +513,17 @@ def oracle_leg(out, gpu, wl, W, args, ctx, F, t):
                                              rep["exact_2d"]["max_rel_pose_timed"]))
     if not args.quick:
         kp = min(8, len(wl["poses"]))
+        # Approx and Uniform: every beam and every pose of the timed workload
         for name, v, kw in (("approx_delta9", O.APPROX, {"Delta": wl["Delta"]}),
                             ("uniform_h6", O.UNIFORM, {"H": wl["H"]})):
-            rp, _ = O.eval_poses_2d(v, wl["grid"], wl["poses"][:kp], wl["beam_dir"], sig, R,
-                                    threads=thr, want_beams=False, **kw)
-            rep[name] = _err_stats(_rel(gpu[name][:kp].cpu().numpy(), rp), 1e-5, poses=kp)
+            t1 = time.perf_counter()
+            rp, rb = O.eval_poses_2d(v, wl["grid"], wl["poses"], wl["beam_dir"], sig, R,
+                                     threads=thr, want_beams=True, **kw)
+            gp, gbm = gpu[name]
+            rep[name] = _err_stats(_rel(gbm.cpu().numpy(), rb), 1e-5, poses=len(rp),
+                                   max_rel_pose=float(_rel(gp.cpu().numpy(), rp).max()))
+            log(f"[bench] oracle {name}: every beam of {len(rp)} poses in "
+                f"{time.perf_counter() - t1:.1f} s")
         rep["exact_skip_zero"] = _err_stats(_rel(gpu["exact_skip_zero"][:k].cpu().numpy(), ref_pose),
                                             1e-5, poses=k)
         rp, _ = O.eval_poses_2d(O.EXACT, wl["grid"], wl["poses"][:kp], wl["beam_dir"], sig, R,
@@ -496,17 +543,50 @@ def oracle_leg(out, gpu, wl, W, args, ctx, F, t):
                 _rel(gbm.cpu().numpy(), rb), bar, beams=int(rb.size),
                 max_rel_pose=float(_rel(gp.cpu().numpy(), rp).max()))
         vw = gpu["voxels"]
+        n3 = 16       # the first 16 poses x 16 384 beams of each 3D variant
         for name, exact, kw in (("rle_exact_3d", True, {}),
                                 ("rle_approx_delta6_3d", False, {"Delta": 6}),
                                 ("rle_uniform_h4_3d", True, {"kind": O.K_UNIFORM, "H": 4})):
-            rp, rb = O.eval_poses_3d(exact, vw["vox"], vw["poses"][:1], vw["beam_dir"], vw["sigma"],
+            t1 = time.perf_counter()
+            rp, rb = O.eval_poses_3d(exact, vw["vox"], vw["poses"][:n3], vw["beam_dir"], vw["sigma"],
                                      vw["R"], vw["w"], threads=thr, **kw)
             gp, gbm = gpu[name]
-            rep[name] = _err_stats(_rel(gbm[:1].cpu().numpy(), rb), 1e-5, poses=1,
-                                   max_rel_pose=float(_rel(gp[:1].cpu().numpy(), rp).max()))
+            rep[name] = _err_stats(_rel(gbm[:n3].cpu().numpy(), rb), 1e-5, poses=n3,
+                                   max_rel_pose=float(_rel(gp[:n3].cpu().numpy(), rp).max()))
+            log(f"[bench] oracle {name}: {n3} poses in {time.perf_counter() - t1:.1f} s")
+        # the CSQMI comparator (absolute-plus-relative bar: a difference of logs)
+        kc = min(256, len(wl["poses"]))
+        rp, rb = O.eval_poses_2d(O.CSQMI, wl["grid"], wl["poses"][:kc], wl["beam_dir"], sig, R,
+                                 threads=thr, want_beams=True, Delta=9)
+        gp, gbm = gpu["csqmi_delta9"]
+        rep["approx_csqmi_delta9"] = _log_err_stats(gbm[:kc].cpu().numpy(), rb, poses=kc,
+                                                    max_rel_pose=float(_rel(gp[:kc].cpu().numpy(), rp).max()))
+        eoff, eocc, esg, eH = gpu["e2_inputs"]
+        for kind in ("unit", "explicit"):
+            bnd = None if kind == "unit" else np.tile(np.arange(101, dtype=np.float64), len(esg))
+            for name, v, kw in (("approx_csqmi", O.CSQMI, {"Delta": 3}),
+                                ("approx_fsmi", O.APPROX, {"Delta": 3}),
+                                ("uniform_fsmi", O.UNIFORM, {"H": eH})):
+                rb = O.eval_beams(v, eoff, eocc, esg, bound=bnd, threads=thr, **kw)
+                g_ = gpu[f"e2_{kind}_{name}"].cpu().numpy()
+                rep[f"paper_beam_{kind}_{name}"] = (
+                    _log_err_stats(g_, rb, beams=len(rb)) if v == O.CSQMI
+                    else _err_stats(_rel(g_, rb), 1e-5, beams=len(rb)))
+        # trajectories: the first two walks, every state
+        toff, tst = gpu["traj_inputs"]
+        n2 = int(toff[2])
+        for name, v, kw in (("approx_delta9", O.APPROX, {"Delta": 9}), ("exact", O.EXACT, {})):
+            rt, rs, _ = O.eval_trajectories_2d(v, wl["grid"], toff[:3], tst[:n2], wl["beam_dir"],
+                                               sig, R, want_beams=False, **kw)
+            mt, ms = gpu["traj_" + name]
+            rep["trajectory_" + name] = _err_stats(_rel(ms[:n2].cpu().numpy(), rs), 1e-5,
+                                                   states=n2,
+                                                   max_rel_trajectory=float(_rel(mt[:2].cpu().numpy(), rt).max()))
     out["error_report"] = rep
-    worst = max(v["max_rel"] / v["bar"] for v in rep.values())
-    log(f"[bench] error report: {len(rep)} workloads, worst max_rel / bar = {worst:.3f}")
+    bad = [k for k, v in rep.items() if not v["within_bar"]]
+    worst = max(v["max_rel"] / v["bar"] for v in rep.values() if "abs_bar" not in v)
+    log(f"[bench] error report: {len(rep)} workloads, worst max_rel / bar = {worst:.3f}"
+        f"{', outside the bar: ' + ', '.join(bad) if bad else ', all within their bars'}")
 
 
 def table_route_leg(ctx, F, W, t, timed):
@@ -555,6 +635,89 @@ def table_route_leg(ctx, F, W, t, timed):
         + " ".join(f"L={L}: {v['table_max_rel_err_random_o']:.1e}/{v['table_max_rel_err_grid_o']:.1e}"
                    for L, v in out["by_L"].items()))
     return out
+
+
+def csqmi_leg(ctx, F, W, t, timed, grid, poses, bdir, sigma, R, n_total, extras, gpu):
+    """The comparison metric of Sec. 2.3 beside the FSMI variants, as the paper
+    ranks their speeds (Sec. 5.1, second single-beam experiment: Approx-FSMI
+    1.7x and Uniform-FSMI 3x faster than Approx-CSQMI, Delta = 3, one Xeon
+    core).  (a) That single-beam setting: 100 cells of 0.1 m, o ~ U(0, 1),
+    sigma = 0.05 m = 0.5 cells, as a batch of 2^20 beams through graph-captured
+    plans, on unit cells and on the same cells given as explicit boundaries;
+    Uniform-FSMI with the moment-matched H = round(sqrt(3) sigma - 1/2) = 0.
+    (b) The timed 2D workload's walked beams: Approx-CSQMI (Delta = 9) beside
+    Approx-FSMI (Delta = 9) and Uniform-FSMI (H = 6) measured above."""
+    nb, n = 1 << 20, 100
+    rng = np.random.default_rng(W.SEED_BASE + 9)
+    off = np.arange(nb + 1, dtype=np.int64) * n
+    occ = rng.uniform(0.0, 1.0, nb * n).astype(np.float32)
+    sg = np.full(nb, 0.5, np.float32)
+    d_off, d_occ, d_sg = t(off), t(occ), t(sg)
+    d_bound = t(np.tile(np.arange(n + 1, dtype=np.float64), nb))
+    H = int(round(math.sqrt(3.0) * 0.5 - 0.5))
+    res = {"paper_beam": {"beams": nb, "cells": n, "sigma_cells": 0.5, "Delta": 3, "H": H,
+                          "paper_ratios": {"approx_fsmi_over_approx_csqmi": 1.7,
+                                           "uniform_fsmi_over_approx_csqmi": 3.0,
+                                           "hardware": "one Xeon E5-2695 core"}}}
+    for kind, bnd in (("unit", None), ("explicit", d_bound)):
+        row = {}
+        for name, p in (("approx_csqmi", F.params(variant=F.FSMI_CSQMI, trunc_delta=3)),
+                        ("approx_fsmi", F.params(variant=F.FSMI_APPROX, trunc_delta=3)),
+                        ("uniform_fsmi", F.params(variant=F.FSMI_UNIFORM, uniform_h=H))):
+            plan = F.Plan(ctx, p, d_off, d_occ, d_sg, bound=bnd, graph=True)
+            dt = timed(plan.launch, reps=5)
+            gpu[f"e2_{kind}_{name}"] = plan.launch()[:20000].clone()
+            plan.close()
+            row[name] = {"beams_per_s": nb / dt, "ns_per_beam": dt / nb * 1e9}
+        row["approx_fsmi_over_approx_csqmi"] = (row["approx_fsmi"]["beams_per_s"]
+                                                / row["approx_csqmi"]["beams_per_s"])
+        row["uniform_fsmi_over_approx_csqmi"] = (row["uniform_fsmi"]["beams_per_s"]
+                                                 / row["approx_csqmi"]["beams_per_s"])
+        res["paper_beam"][kind] = row
+        log(f"[bench] paper beam ({kind} cells), ns per beam: Approx-CSQMI "
+            f"{row['approx_csqmi']['ns_per_beam']:.2f}, Approx-FSMI {row['approx_fsmi']['ns_per_beam']:.2f}, "
+            f"Uniform-FSMI {row['uniform_fsmi']['ns_per_beam']:.2f} (Approx-FSMI x"
+            f"{row['approx_fsmi_over_approx_csqmi']:.2f}, Uniform-FSMI "
+            f"x{row['uniform_fsmi_over_approx_csqmi']:.2f} of Approx-CSQMI; paper 1.7, 3)")
+    del d_occ, d_bound
+    gpu["e2_inputs"] = (off[:20001], occ[:20000 * n], sg[:20000], H)
+    pc = F.params(variant=F.FSMI_CSQMI, trunc_delta=9)
+    dt = timed(lambda: ctx.fsmi_eval_poses(pc, grid, poses, bdir, sigma, R))
+    gpu["csqmi_delta9"] = ctx.fsmi_eval_poses(pc, grid, poses, bdir, sigma, R, want_beams=True)
+    cs = n_total / dt
+    res["timed_workload"] = {
+        "approx_csqmi_delta9": {"beams_per_s": cs, "ms": dt * 1e3},
+        "approx_fsmi_over_approx_csqmi": extras["approx_delta9"]["beams_per_s"] / cs,
+        "uniform_fsmi_over_approx_csqmi": extras["uniform_h6"]["beams_per_s"] / cs}
+    log(f"[bench] Approx-CSQMI (Delta 9) on the timed workload: {cs/1e6:.2f} M beams/s "
+        f"(Approx-FSMI x{res['timed_workload']['approx_fsmi_over_approx_csqmi']:.2f}, "
+        f"Uniform-FSMI x{res['timed_workload']['uniform_fsmi_over_approx_csqmi']:.2f})")
+    return res
+
+
+def trajectory_leg(ctx, F, W, t, timed, wl, gpu):
+    """Trajectory MI with cell marking (Sec. 2.4) on the timed map: 64 candidate
+    walks of 16 states 6 cells apart, 360 beams, R = 400, sigma = 3; Approx-FSMI
+    (Delta = 9) and exact FSMI.  Candidate trajectories per second, and the
+    states per second beside the pose path on the same states (no marking)."""
+    n_traj, steps = 64, 16
+    off, st = W.walks_2d(wl["labels"], n_traj, steps, W.SEED_BASE + 21, step_len=6.0)
+    g, d_off, d_st, bd = t(wl["grid"]), t(off), t(st), t(wl["beam_dir"])
+    ns = st.shape[0]
+    res = {"trajectories": n_traj, "states_per_trajectory": steps, "step_cells": 6.0,
+           "beams_per_state": int(bd.shape[0])}
+    for name, p in (("approx_delta9", F.params(variant=F.FSMI_APPROX, trunc_delta=9)),
+                    ("exact", F.params(variant=F.FSMI_EXACT))):
+        dt = timed(lambda: ctx.fsmi_eval_trajectories(p, g, d_off, d_st, bd, 3.0, 400.0), reps=2)
+        mt, ms, _ = ctx.fsmi_eval_trajectories(p, g, d_off, d_st, bd, 3.0, 400.0)
+        dtp = timed(lambda: ctx.fsmi_eval_poses(p, g, d_st, bd, 3.0, 400.0), reps=2)
+        res[name] = {"trajectories_per_s": n_traj / dt, "ms": dt * 1e3, "states_per_s": ns / dt,
+                     "pose_path_states_per_s": ns / dtp, "time_over_pose_path": dt / dtp}
+        gpu["traj_" + name] = (mt, ms)
+        log(f"[bench] trajectories ({name}): {n_traj / dt:.0f} trajectories/s, {ns / dt:.0f} "
+            f"states/s ({dt / dtp:.2f}x the pose path's time)")
+    gpu["traj_inputs"] = (off, st)
+    return res
 
 
 def surrogate_leg(ctx, F, W, t, timed, args):

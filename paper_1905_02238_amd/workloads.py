@@ -128,6 +128,34 @@ def poses_in_free_space_2d(lab, n: int, seed: int, yaw: str = "zero"):
     return out
 
 
+def walks_2d(lab, n_traj: int, steps: int, seed: int, step_len: float = 4.0):
+    """Candidate trajectories for the planner-level sum (Sec. 2.4): n_traj walks
+    of `steps` states through FREE cells, each starting at a random free cell
+    (continuous within it) with a random heading, stepping step_len cells along
+    the heading and turning to a fresh random heading whenever the next state
+    would leave free space.  Returns (traj_off int64 [n_traj + 1], states
+    float64 [n_traj * steps][4] = x, y, cos(yaw), sin(yaw)), the yaw being the
+    heading of travel."""
+    rng = np.random.default_rng(seed + 17)
+    ys, xs = np.nonzero(lab == FREE)
+    H, Wd = lab.shape
+    states, off = [], [0]
+    for _ in range(n_traj):
+        i = rng.integers(0, len(xs))
+        x, y = xs[i] + rng.uniform(0.1, 0.9), ys[i] + rng.uniform(0.1, 0.9)
+        a = rng.uniform(0.0, 2.0 * math.pi)
+        for _ in range(steps):
+            states.append([x, y, math.cos(a), math.sin(a)])
+            for _ in range(30):
+                nx, ny = x + step_len * math.cos(a), y + step_len * math.sin(a)
+                if 0 <= nx < Wd and 0 <= ny < H and lab[int(ny), int(nx)] == FREE:
+                    x, y = nx, ny
+                    break
+                a = rng.uniform(0.0, 2.0 * math.pi)
+        off.append(len(states))
+    return np.array(off, np.int64), np.array(states, np.float64)
+
+
 def beam_dirs_2d(n_beams: int):
     """Sensor-frame unit vectors, angle 2*pi*b/B from +x (host libm)."""
     th = 2.0 * math.pi * np.arange(n_beams, dtype=np.float64) / n_beams

@@ -34,28 +34,6 @@ def rel_err(got, ref):
     return float(np.max(np.abs(got[nz] - ref[nz]) / np.abs(ref[nz]))) if np.any(nz) else 0.0
 
 
-def walks(labels, n_traj, steps, seed, step_len=4.0):
-    """n_traj short walks through free cells: CSR offsets and the states [x, y, cos, sin]."""
-    rng = np.random.default_rng(seed)
-    ys, xs = np.nonzero(labels == W.FREE)
-    states, off = [], [0]
-    for _ in range(n_traj):
-        i = rng.integers(0, len(xs))
-        x, y = xs[i] + rng.uniform(0.1, 0.9), ys[i] + rng.uniform(0.1, 0.9)
-        a = rng.uniform(0, 2 * math.pi)
-        for _ in range(steps):
-            states.append([x, y, math.cos(a), math.sin(a)])
-            for _ in range(30):
-                nx, ny = x + step_len * math.cos(a), y + step_len * math.sin(a)
-                if 0 <= nx < labels.shape[1] and 0 <= ny < labels.shape[0] and \
-                        labels[int(ny), int(nx)] == W.FREE:
-                    x, y = nx, ny
-                    break
-                a = rng.uniform(0, 2 * math.pi)
-        off.append(len(states))
-    return np.array(off, np.int64), np.array(states)
-
-
 @pytest.mark.parametrize("variant", [F.FSMI_EXACT, F.FSMI_APPROX, F.FSMI_UNIFORM])
 @pytest.mark.parametrize("prec,tol", [(F.FSMI_FP32, 1e-5), (F.FSMI_FP64, 1e-12)])
 def test_trajectories_small_rooms(ctx, variant, prec, tol):
@@ -63,7 +41,7 @@ def test_trajectories_small_rooms(ctx, variant, prec, tol):
     nothing), 72 beams, R = 60, sigma = 2."""
     print(f"[gpu] trajectories small variant={variant} prec={prec}", flush=True)
     wl = W.grid_small()
-    off, poses = walks(wl["labels"], 5, 6, 11)
+    off, poses = W.walks_2d(wl["labels"], 5, 6, 11)
     poses = np.concatenate([poses[:3], poses[2:3], poses[3:]])   # state 3 repeats state 2
     off = np.array([0, 7] + [int(v) + 1 for v in off[2:]], np.int64)
     bd = W.beam_dirs_2d(72)
@@ -87,7 +65,7 @@ def test_trajectories_large_rooms_and_the_one_state_case(ctx):
     equal to fsmi_eval_poses on that pose."""
     print("[gpu] trajectories large", flush=True)
     wl = W.grid_large(n_poses=1)
-    off, poses = walks(wl["labels"], 12, 16, 5, step_len=6.0)
+    off, poses = W.walks_2d(wl["labels"], 12, 16, 5, step_len=6.0)
     bd = W.beam_dirs_2d(360)
     prm = F.params(variant=F.FSMI_APPROX, trunc_delta=9)
     g = dev(wl["grid"])
@@ -116,7 +94,7 @@ def test_trajectories_large_rooms_and_the_one_state_case(ctx):
 
 def test_trajectories_empty_and_bad_offsets(ctx):
     wl = W.grid_small()
-    off, poses = walks(wl["labels"], 2, 3, 2)
+    off, poses = W.walks_2d(wl["labels"], 2, 3, 2)
     bd = dev(W.beam_dirs_2d(16))
     g = dev(wl["grid"])
     prm = F.params()

@@ -52,6 +52,24 @@ def test_uniform_yaw_keeps_positions_and_covers_the_circle():
     assert np.any(np.abs(large["poses"][:, 3]) > 0.5)   # the timed workload turns its poses
 
 
+def test_walks_stay_in_free_cells_and_head_where_they_go():
+    occ, lab = W.room_grid(256, W.SEED_BASE + 51, split_extent=60)
+    off, st = W.walks_2d(lab, 20, 10, 3, step_len=4.0)
+    assert off.tolist() == list(range(0, 201, 10))
+    cells = lab[np.floor(st[:, 1]).astype(int), np.floor(st[:, 0]).astype(int)]
+    assert np.all(cells == W.FREE)
+    assert np.allclose(np.hypot(st[:, 2], st[:, 3]), 1.0, atol=1e-15)
+    moved = 0
+    for k in range(20):
+        for t in range(off[k], off[k + 1] - 1):
+            d = st[t + 1, :2] - st[t, :2]
+            if np.any(d != 0):
+                moved += 1
+                assert abs(np.hypot(*d) - 4.0) < 1e-9
+                assert np.allclose(d / 4.0, st[t + 1, 2:], atol=1e-12)   # moved along its heading
+    assert moved > 100
+
+
 def test_beam_directions_are_unit_vectors_at_equal_angles():
     d = W.beam_dirs_2d(360)
     assert np.allclose(np.hypot(d[:, 0], d[:, 1]), 1.0, atol=1e-15)
