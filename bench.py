@@ -422,7 +422,20 @@ def main():
             gpu[name] = (mp3, mb3[:16].clone())      # the oracle checks the first 16 poses
             del mb3
             log(f"[bench] {name}: {nv/dt/1e6:.2f} M beams/s")
+        # the same beams through the run engine (FSMI_F_RLE_RUNS): same value,
+        # the run-domain evaluation of Thm 5 / Thm 6 timed
+        for name, p in (("rle_exact_3d_run_engine", F.params(flags=F.FSMI_F_RLE_RUNS)),
+                        ("rle_approx_delta6_3d_run_engine",
+                         F.params(variant=F.FSMI_APPROX, trunc_delta=6, flags=F.FSMI_F_RLE_RUNS))):
+            dt = timed(lambda: ctx.fsmi_eval_poses(p, vx, vp, vb, vw["sigma"], vw["R"], vw["w"]), reps=2)
+            mp3 = ctx.fsmi_eval_poses(p, vx, vp, vb, vw["sigma"], vw["R"], vw["w"])[0].cpu().numpy()
+            base = gpu[name.replace("_run_engine", "")][0].cpu().numpy()
+            extras[name] = {"beams_per_s": nv / dt, "ms": dt * 1e3, "poses": vp.shape[0],
+                            "max_rel_vs_expanded": float(np.max(np.abs(mp3 - base) / np.abs(base)))}
+            log(f"[bench] {name}: {nv/dt/1e6:.2f} M beams/s (pose values within "
+                f"{extras[name]['max_rel_vs_expanded']:.1e} of the expanded engine's)")
         extras["rle_table_crossover"] = table_route_leg(ctx, F, W, t, timed)
+        extras["rle_engine_crossover"] = rle_engine_leg(ctx, F, W, t, timed)
         extras["csqmi_comparison"] = csqmi_leg(ctx, F, W, t, timed, grid, poses, bdir, sigma, R,
                                                n_total, extras, gpu)
         extras["trajectories"] = trajectory_leg(ctx, F, W, t, timed, wl, gpu)
@@ -633,6 +646,34 @@ def table_route_leg(ctx, F, W, t, timed):
                    f"(x{v['plain_fp64_over_table']:.2f})" for L, v in out["by_L"].items()))
     log("[bench] table route max rel err vs the run engine (random o / o on the grid): "
         + " ".join(f"L={L}: {v['table_max_rel_err_random_o']:.1e}/{v['table_max_rel_err_grid_o']:.1e}"
+                   for L, v in out["by_L"].items()))
+    return out
+
+
+def rle_engine_leg(ctx, F, W, t, timed):
+    """The run-length experiment of Sec. 5.4 with this library's two engines for
+    the same FSMI-RLE / Approx-FSMI-RLE value: 65 536 beams of 256 cells in
+    groups of L, one random o per group, sigma' = 2 (the 3D workload's),
+    Approx Delta = 6; the run engine (FSMI_F_RLE_RUNS) against the expanded
+    engine (FSMI_F_RLE_CELLS).  The default switch follows this crossover."""
+    nb, n, sp = 65536, 256, 2.0
+    out = {"beams": nb, "cells": n, "sigma_prime": sp, "Delta": 6, "by_L": {}}
+    for L in (2, 4, 8, 16, 32, 64, 128):
+        run_off, ro, rl, _, _ = W.grouped_beams(nb, n, L, seed=W.SEED_BASE + 40 + L)
+        d = (t(run_off), t(ro), t(rl), t(np.full(nb, sp, np.float32)))
+        row = {}
+        for vname, variant in (("exact", F.FSMI_EXACT), ("approx", F.FSMI_APPROX)):
+            for ename, fl in (("runs", F.FSMI_F_RLE_RUNS), ("cells", F.FSMI_F_RLE_CELLS)):
+                p = F.params(variant=variant, trunc_delta=6, flags=fl)
+                dt = timed(lambda: ctx.fsmi_rle_eval_beams(p, *d), reps=5)
+                row[f"{vname}_{ename}_ns_per_beam"] = dt / nb * 1e9
+            row[f"{vname}_cells_over_runs"] = (row[f"{vname}_cells_ns_per_beam"]
+                                               / row[f"{vname}_runs_ns_per_beam"])
+        out["by_L"][L] = row
+    log("[bench] run engine vs expanded engine, 256-cell beams in runs of L, ns per beam "
+        "(exact runs/cells, approx runs/cells): "
+        + " ".join(f"L={L}: {v['exact_runs_ns_per_beam']:.2f}/{v['exact_cells_ns_per_beam']:.2f} "
+                   f"{v['approx_runs_ns_per_beam']:.2f}/{v['approx_cells_ns_per_beam']:.2f}"
                    for L, v in out["by_L"].items()))
     return out
 

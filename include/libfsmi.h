@@ -94,7 +94,23 @@ enum {
      q_n = sum_{i=1}^{n} f(delta_emp, r_i), is added to Thm 1 (the paper's
      Thm 1 integrates the reading over [0, l_{n+1}) only, Sec. 3.1).  Not with
      FSMI_F_SKIP_ZERO. */
-  FSMI_F_MAX_RANGE = 2u
+  FSMI_F_MAX_RANGE = 2u,
+  /* Engine of FSMI-RLE / Approx-FSMI-RLE (fsmi_rle_eval_beams, 3D
+     fsmi_eval_poses; not with UNIFORM).  The run engine sums each row over the
+     runs within the kernel's reach from tail tables of the kernel, O(n x runs);
+     the expanded engine takes the double sum over the cells.  They give the
+     same value up to rounding.  By default fsmi_rle_eval_beams takes the run
+     engine for an EXACT beam of at most 64 runs averaging at least 32 cells and
+     the expanded engine otherwise (the paper switches at runs of 4 cells, Sec.
+     5.4; 32 is the measured crossover of these kernels, and Approx's expanded
+     sum of 2 Delta + 1 terms a row stays cheaper); the fused 3D fsmi_eval_poses
+     evaluates every beam on its cells by default (the sampled beams' runs fall
+     below the crossover, and the fused kernel would carry the run engine's
+     registers).  FSMI_F_RLE_RUNS takes the run engine for every beam of at most
+     64 runs, FSMI_F_RLE_CELLS the expanded engine for every beam.  At most one
+     of them; no other flag with them. */
+  FSMI_F_RLE_RUNS = 4u,
+  FSMI_F_RLE_CELLS = 8u
 };
 
 typedef struct {
@@ -104,7 +120,7 @@ typedef struct {
   int32_t uniform_h;  /* H >= 0, cells (UNIFORM) */
   int32_t kernel;     /* FSMI_KERNEL_* (equal-width cells and RLE only) */
   int32_t precision;  /* FSMI_FP32 (default) | FSMI_FP64 */
-  uint32_t flags;     /* 0, FSMI_F_SKIP_ZERO or FSMI_F_MAX_RANGE */
+  uint32_t flags;     /* 0, FSMI_F_SKIP_ZERO, FSMI_F_MAX_RANGE or an FSMI_F_RLE_* engine */
   /* Range-dependent noise: the reading of event e_j is N(mu_j, sigma_j^2) with
      sigma_j = sigma + sigma_slope * mu_j (Alg 1 writes sigma per event; the
      paper's experiments use one sigma).  >= 0; 0 (default) is one sigma per
@@ -268,9 +284,11 @@ fsmi_status fsmi_rle_table_eval_beams(fsmi_ctx ctx, const fsmi_params* params, i
    max_range and evaluated with sigma and the variant.
    3D map: poses [n_poses][5] = {x, y, z, cos(yaw), sin(yaw)}; beam_dir
    [n_beams][3]; world direction (c*bx - s*by, s*bx + c*by, bz).  Each beam is
-   sampled as FSMI_RAY_RLE with cell width w and evaluated by the run engine
-   with sigma' = sigma / w (EXACT: FSMI-RLE, APPROX: Approx-FSMI-RLE,
-   UNIFORM: Uniform-FSMI-RLE with half-width H virtual cells).
+   sampled onto virtual cells of width w as FSMI_RAY_VIRTUAL, and evaluated
+   with sigma' = sigma / w as FSMI-RLE (EXACT), Approx-FSMI-RLE (APPROX) or
+   Uniform-FSMI-RLE (UNIFORM, half-width H virtual cells): on its expanded
+   cells by default, or in the run domain over its maximal runs of
+   bit-identical o with FSMI_F_RLE_RUNS (see the flag); the value is the same.
    mi_pose[p] = sum over the pose's beams (Sec. 2.4; FP64, fixed order).
    mi_beam [n_poses][n_beams] (FP64) may be NULL.  One wave keeps a beam in
    LDS: 2D max_range <= 4000 cells (FP32) or < 3873 (FP64), 3D

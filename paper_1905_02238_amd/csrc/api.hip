@@ -56,8 +56,13 @@ bool check_params(fsmi_ctx ctx, const fsmi_params* p, fsmi_status* st) {
     *st = fail(ctx, FSMI_E_INVAL, "unknown precision");
     return false;
   }
-  if (p->flags & ~(uint32_t)(FSMI_F_SKIP_ZERO | FSMI_F_MAX_RANGE)) {
+  if (p->flags & ~(uint32_t)(FSMI_F_SKIP_ZERO | FSMI_F_MAX_RANGE | FSMI_F_RLE_RUNS | FSMI_F_RLE_CELLS)) {
     *st = fail(ctx, FSMI_E_INVAL, "unknown flags");
+    return false;
+  }
+  if ((p->flags & (FSMI_F_RLE_RUNS | FSMI_F_RLE_CELLS)) &&
+      (p->flags != FSMI_F_RLE_RUNS && p->flags != FSMI_F_RLE_CELLS)) {
+    *st = fail(ctx, FSMI_E_INVAL, "FSMI_F_RLE_RUNS and FSMI_F_RLE_CELLS go alone");
     return false;
   }
   if (!(p->sigma_slope >= 0.0) || !std::isfinite(p->sigma_slope)) {
@@ -71,6 +76,10 @@ bool check_params(fsmi_ctx ctx, const fsmi_params* p, fsmi_status* st) {
   }
   if (p->variant == FSMI_CSQMI && (p->flags != 0 || p->sigma_slope != 0.0)) {
     *st = fail(ctx, FSMI_E_INVAL, "FSMI_CSQMI takes no flags and no sigma_slope");
+    return false;
+  }
+  if ((p->flags & (FSMI_F_RLE_RUNS | FSMI_F_RLE_CELLS)) && p->variant == FSMI_UNIFORM) {
+    *st = fail(ctx, FSMI_E_INVAL, "Uniform-FSMI-RLE has one engine (the expanded cells)");
     return false;
   }
   if ((p->flags & FSMI_F_SKIP_ZERO) && (p->variant != FSMI_EXACT || p->precision != FSMI_FP32)) {
@@ -317,6 +326,8 @@ fsmi_status fsmi_eval_beams(fsmi_ctx ctx, const fsmi_params* params, int64_t n_b
   if (!off || !occ || !sigma || !mi) return fail(ctx, FSMI_E_INVAL, "off, occ, sigma, mi are required");
   if ((params->flags & FSMI_F_SKIP_ZERO) && !bound)
     return fail(ctx, FSMI_E_INVAL, "FSMI_F_SKIP_ZERO needs explicit boundaries");
+  if (params->flags & (FSMI_F_RLE_RUNS | FSMI_F_RLE_CELLS))
+    return fail(ctx, FSMI_E_INVAL, "FSMI_F_RLE_* select the engine of the RLE paths");
   if (ext_mode(params) && !bound)
     return fail(ctx, FSMI_E_INVAL, "sigma_slope and FSMI_F_MAX_RANGE need explicit boundaries");
   (void)hipSetDevice(ctx->device);
@@ -423,6 +434,8 @@ fsmi_status eval_poses_checked(fsmi_ctx ctx, const fsmi_params* params, const fs
     if (max_range > 4000.0) return fail(ctx, FSMI_E_CAPACITY, "max_range above 4000 cells");
     if (params->precision == FSMI_FP64 && max_range >= 3873.0)
       return fail(ctx, FSMI_E_CAPACITY, "max_range above 3872 cells in FP64");
+    if (params->flags & (FSMI_F_RLE_RUNS | FSMI_F_RLE_CELLS))
+      return fail(ctx, FSMI_E_INVAL, "FSMI_F_RLE_* select the engine of the RLE paths (3D maps)");
     return from_hip(ctx,
                     launch_eval_poses_2d(ctx, to_const(params), map->occ, map->dims[0], map->dims[1],
                                          n_poses, poses, n_beams, beam_dir, sigma, max_range,

@@ -1,12 +1,18 @@
 // k_rle.hip -- FSMI on run-length-encoded beams (fsmi_rle_eval_beams) and the
 // fused 3D pose path (fsmi_eval_poses on voxel maps).
 //
-// FSMI-RLE (Thm 5) and Approx-FSMI-RLE (Thm 6) are, by their proofs, the plain
-// double sum over the expanded beam of equal-width virtual cells with the
-// weight g(k - j) (exactly so once the kernel is truncated inside the blocks
-// too).  This engine expands the runs in LDS and evaluates that sum with the
-// per-beam kernel table; the paper itself evaluates short runs this way
-// (Sec. 5.4: decompress when runs are shorter than 4).
+// FSMI-RLE (Thm 5) and Approx-FSMI-RLE (Thm 6) are evaluated per beam by one
+// of two engines, chosen as the paper chooses (Sec. 5.4: decompress when runs
+// are shorter than 4 cells on average):
+//   - the run engine (rle_dev.h): per-run f and D_E, each row's sum over the
+//     runs within the kernel's reach from two tail tables, O(n x runs in reach),
+//     for beams of at most kRunCap runs with a mean run length of at least 4;
+//   - the expanded engine: the runs expanded to their cells and the plain
+//     double sum with the per-beam kernel table (beam_dev.h), which equals
+//     the RLE formulas by the proofs of Thm 5 and Thm 6 (with the kernel
+//     truncated inside the blocks too).
+// Uniform-FSMI-RLE always takes the expanded engine: Alg 4 on the cells is
+// already O(n).
 #include <math.h>
 
 #include <algorithm>
@@ -14,6 +20,7 @@
 #include "beam_dev.h"
 #include "fsmi_internal.h"
 #include "ray_dev.h"
+#include "rle_dev.h"
 
 namespace fsmi {
 hipError_t launch_pose_reduce(fsmi_ctx ctx, const double* mi_beam, int64_t n_poses,
@@ -33,9 +40,31 @@ struct RleArgs {
   uint32_t* status;
 };
 
+// LDS of one wave: A, C, P of the expanded engine and the occupancies, then the
+// run region (rle_dev.h); in the run engine C's slots hold the run of each cell.
 template <typename T>
-__host__ __device__ inline size_t rle_lds(int cap) {
-  return (size_t)core_bytes_per_cell<T>() * cap + 8 + 4 * (size_t)cap + 16;
+__host__ __device__ inline size_t rle_lds(int cap, bool with_runs = true) {
+  return (size_t)core_bytes_per_cell<T>() * cap + 8 + 4 * (size_t)cap + 16 +
+         (with_runs ? run_region_bytes<T>(cap) : 0);
+}
+
+// The run region starts on the first 16-byte boundary after the occupancies
+// (rle_lds leaves 16 bytes for it).
+FSMI_DEV char* run_region(float* so, int cap) {
+  return reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(so + cap) + 15) & ~(uintptr_t)15);
+}
+
+// The engine of a beam of nr runs over n cells.  The paper decompresses when
+// runs are shorter than 4 cells (Sec. 5.4); on this chip the measured crossover
+// (256-cell beams in runs of L, sigma' = 2) lies at about 32 cells for FSMI-RLE
+// and beyond 128 for Approx-FSMI-RLE, whose expanded sum is only 2 Delta + 1
+// terms a row: the run engine takes EXACT beams of at most kRunCap runs
+// averaging 32 cells or more.  FSMI_F_RLE_RUNS / FSMI_F_RLE_CELLS force one.
+constexpr int kRunEngineMeanLen = 32;
+FSMI_DEV bool use_run_engine(const EvalConst& ec, int n, int nr) {
+  if (ec.variant == FSMI_UNIFORM || nr > kRunCap || (ec.flags & FSMI_F_RLE_CELLS)) return false;
+  if (ec.flags & FSMI_F_RLE_RUNS) return true;
+  return ec.variant == FSMI_EXACT && n >= kRunEngineMeanLen * nr;
 }
 
 template <typename T>
@@ -80,6 +109,7 @@ __global__ __launch_bounds__(kWave) void k_rle_beams(RleArgs a) {
   extern __shared__ __align__(16) char lds[];
   float* so;
   const CoreLds L = carve_rle<T>(lds, a.cap, &so);
+  const RunLds R = carve_runs<T>(run_region(so, a.cap), a.cap, reinterpret_cast<int*>(L.C));
   const int lane = threadIdx.x;
   // runs of beams from the queue (guided self-scheduling)
   const int64_t n_waves = gridDim.x;
@@ -95,7 +125,10 @@ __global__ __launch_bounds__(kWave) void k_rle_beams(RleArgs a) {
         v = __builtin_nan("");
         if (lane == 0) latch(a.status, kErrLen);
       } else {
-        const int n = expand_runs(a.run_occ, a.run_len, r0, r1, a.cap, so, nullptr, lane);
+        const int nr = (int)min<int64_t>(r1 - r0, (int64_t)kRunCap + 1);
+        const int n = nr <= kRunCap
+                          ? runs_from_csr(a.run_occ, a.run_len, r0, r1, a.cap, so, R, lane)
+                          : expand_runs(a.run_occ, a.run_len, r0, r1, a.cap, so, nullptr, lane);
         if (n < 0) {
           v = __builtin_nan("");
           if (lane == 0) latch(a.status, kErrLen);
@@ -103,8 +136,11 @@ __global__ __launch_bounds__(kWave) void k_rle_beams(RleArgs a) {
           v = 0.0;
         } else {
           bool bad;
-          v = beam_core<1, false, T>(a.ec, n, so, false, (double)a.sigma_p[it], L, nullptr, nullptr,
-                                     lane, false, &bad);
+          if (use_run_engine(a.ec, n, nr))
+            v = rle_core<T>(a.ec, n, so, nr, R, (double)a.sigma_p[it], L, lane, &bad);
+          else
+            v = beam_core<1, false, T>(a.ec, n, so, false, (double)a.sigma_p[it], L, nullptr,
+                                       nullptr, lane, false, &bad);
           if (bad && lane == 0) latch(a.status, kErrOcc);
         }
       }
@@ -132,12 +168,17 @@ struct Pose3dArgs {
   uint32_t* status;
 };
 
-template <typename T>
-__global__ __launch_bounds__(kWave) void k_poses3d(Pose3dArgs a) {
+// RUNS: the instantiation that carries the run engine (FSMI_F_RLE_RUNS); the
+// default one evaluates every beam on its expanded cells.  At the 3D
+// workload's run lengths (15.6 cells on average) the run engine does not
+// reach its measured crossover, and carrying it costs registers.
+template <typename T, bool RUNS>
+FSMI_DEV void poses3d_body(const Pose3dArgs& a) {
 #pragma clang fp contract(off)
   extern __shared__ __align__(16) char lds[];
   float* so;
   const CoreLds L = carve_rle<T>(lds, a.cap, &so);
+  const RunLds R = carve_runs<T>(run_region(so, a.cap), a.cap, reinterpret_cast<int*>(L.C));
   const int lane = threadIdx.x;
   const int64_t n_items = a.n_poses * a.n_beams;
   // runs of items from the queue (guided self-scheduling); k, start and the
@@ -165,13 +206,39 @@ __global__ __launch_bounds__(kWave) void k_poses3d(Pose3dArgs a) {
       } else {
         wave_sync();
         bool bad;
-        v = beam_core<1, false, T>(a.ec, n, so, false, a.sigma_p, L, nullptr, nullptr, lane, false, &bad);
+        if constexpr (RUNS) {
+          const int nr = runs_of_cells(so, n, R, lane);
+          if (nr <= kRunCap)
+            v = rle_core<T>(a.ec, n, so, nr, R, a.sigma_p, L, lane, &bad);
+          else
+            v = beam_core<1, false, T>(a.ec, n, so, false, a.sigma_p, L, nullptr, nullptr, lane,
+                                       false, &bad);
+        } else {
+          v = beam_core<1, false, T>(a.ec, n, so, false, a.sigma_p, L, nullptr, nullptr, lane, false,
+                                     &bad);
+        }
         if (bad && lane == 0) latch(a.status, kErrOcc);
       }
       if (lane == 0) a.mi_beam[it] = v;
       wave_sync();
     }
   }
+}
+
+__global__ __launch_bounds__(kWave) void k_poses3d_f32(Pose3dArgs a) {
+  poses3d_body<float, false>(a);
+}
+__global__ __launch_bounds__(kWave) void k_poses3d_f64(Pose3dArgs a) {
+  poses3d_body<double, false>(a);
+}
+// With the run engine: FP32 held to 128 VGPRs (4 waves per SIMD, which the
+// sampler's gathers need to hide their latency; two spilled registers).
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(4)))
+void k_poses3d_runs_f32(Pose3dArgs a) {
+  poses3d_body<float, true>(a);
+}
+__global__ __launch_bounds__(kWave) void k_poses3d_runs_f64(Pose3dArgs a) {
+  poses3d_body<double, true>(a);
 }
 
 __global__ void k_reset_counter64(int32_t* c) {
@@ -274,17 +341,23 @@ hipError_t launch_eval_poses_3d(fsmi_ctx ctx, const EvalConst& ec, const float* 
   a.counter = ws ? ws->counter : ctx->d_counters + 8;
   a.status = ctx->d_status;
   const bool fp64 = ec.precision == FSMI_FP64;
-  const size_t lds = fp64 ? rle_lds<double>(a.cap) : rle_lds<float>(a.cap);
+  const bool with_runs = (ec.flags & FSMI_F_RLE_RUNS) != 0;
+  const size_t lds = fp64 ? rle_lds<double>(a.cap, with_runs) : rle_lds<float>(a.cap, with_runs);
   if (lds > 150 * 1024) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_reset_counter64, dim3(1), dim3(64), 0, ctx->stream, a.counter);
   const int per_cu = std::max<int>(1, std::min<int>(16, (int)((160 * 1024) / (lds + 256))));
   const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(n_items, (int64_t)ctx->num_cu * per_cu));
+  auto launch = [&](auto kern) {
+    (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kWave), lds, ctx->stream, a);
+  };
+  const bool runs = (ec.flags & FSMI_F_RLE_RUNS) != 0;
   if (fp64) {
-    (void)hipFuncSetAttribute((const void*)k_poses3d<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k_poses3d<double>, dim3(grid), dim3(kWave), lds, ctx->stream, a);
+    if (runs) launch(k_poses3d_runs_f64);
+    else launch(k_poses3d_f64);
   } else {
-    (void)hipFuncSetAttribute((const void*)k_poses3d<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k_poses3d<float>, dim3(grid), dim3(kWave), lds, ctx->stream, a);
+    if (runs) launch(k_poses3d_runs_f32);
+    else launch(k_poses3d_f32);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
