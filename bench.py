@@ -86,6 +86,22 @@ ALU_PEAK_TSLOT = 256 * 64 * 2.4e9 / 1e12
 # instruction per lane per clock: 256 x 64 x 2.4e9 / 13 = 3.02e12 pairs/s.
 PAIR_ISSUE_SLOTS = 13
 PHI_PAIR_PEAK = 256 * 64 * 2.4e9 / PAIR_ISSUE_SLOTS
+# FP32 matrix cores: v_mfma_f32_16x16x4f32 is 1024 multiply-adds per 32 cycles
+# per SIMD, 256 x 4 x 32 x 2.4e9 = 7.86e13 MAC/s (157.3 TFLOP/s).
+MFMA_F32_MAC_PEAK = 256 * 4 * 32 * 2.4e9
+
+
+def unit_mfma_macs(lens):
+    """Matrix-core multiply-adds of the FP32 exact unit-cell sum for beams of
+    these lengths: blocks of 16 cells, four block offsets per pass, two
+    16x16x4 products per (offset, step) whose rows reach into the beam, i.e.
+    2 * sum_{m < nb} (floor(m / 4) + 1) instructions for nb = ceil(n / 16)."""
+    nb = (np.asarray(lens, np.int64) + 15) // 16
+    if nb.size == 0:
+        return 0.0
+    m = np.arange(int(nb.max()) + 1)
+    S = np.concatenate([[0], np.cumsum(m // 4 + 1)])
+    return float(2 * 1024 * S[nb].sum())
 
 
 def parse():
@@ -390,8 +406,11 @@ def main():
         dtp = timed(plan.launch, reps=5)
         info = plan.info()
         gpu["uneven"] = plan.launch().clone()
+        macs = unit_mfma_macs(lens)
         extras["uneven_100k_exact"] = {
             "beams_per_s": 1e5 / dtp, "ms": dtp * 1e3, "pairs": float(np.sum(lens * lens)),
+            "matrix_macs": macs, "matrix_mac_per_s": macs / dtp,
+            "matrix_frac_of_peak": macs / dtp / MFMA_F32_MAC_PEAK,
             "eager_ms": dt * 1e3, "eager_wave_max": 512, "tuned_wave_max": info["wave_max"],
             "tiles": info["n_tile"], "autotune_and_capture_s": plan_s,
             "tried": {str(w): round(m, 4) for w, m in info["tried"]}}

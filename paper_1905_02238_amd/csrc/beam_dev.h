@@ -7,11 +7,13 @@
 // uniform-noise form (Thm 4 / Alg 4).
 //
 // Numerics (FP32 mode): f is evaluated in FP64 (f_cell_series); the prefix
-// product of (1 - o) and the C_k prefix are scanned in FP64; the O(n^2) loop
-// is FP32 with one erfc per (row j, boundary), evaluated on the tail side of
-// mu_j so that no digits cancel, and a Kahan-compensated sum over blocks of
-// eight terms; each row's P_j S_j is accumulated in FP64 and the group total
-// is a fixed-order tree.
+// product of (1 - o) and the C_k prefix are scanned in FP64; on explicit
+// boundaries the O(n^2) loop is FP32 with one erfc per (row j, boundary),
+// evaluated on the tail side of mu_j so that no digits cancel, and a
+// Kahan-compensated sum over blocks of eight terms; each row's P_j S_j is
+// accumulated in FP64 and the group total is a fixed-order tree.  On unit
+// cells exact FSMI runs on the matrix cores (exact_unit_mfma): FP32 products
+// accumulated in FP32 per 16 x 16 block offset, weighted and added in FP64.
 #pragma once
 #include <math.h>
 
@@ -434,57 +436,123 @@ FSMI_DEV double row_exact_unit(const T* sG, const T* sC, int off, int n, int j) 
   return acc.value();
 }
 
-// Rows j0 .. j0 + 3 of the FP32 unit-cell sum at once (j0 = 4 b + 1): row
-// j0 + r reads its weight at column k from B[k - r], B = sG + off - j0, so one
-// register window of B slides along k for the four rows.  Per 8 columns a lane
-// loads 8 new weights (two 16-byte reads; B + k is aligned for k = 1 mod 8 by
-// the mirror's origin) and the 8 C_k, for 32 pairs, where one row per lane
-// reads a weight and a C_k per pair.  Each row sums chunks of eight FMAs as
-// row_exact_unit does, and adds the chunk sums in FP64 (a conversion and an
-// add, where the FP32 compensated add takes four operations).
-// Columns k0 .. k1 only (k0 = 1 mod 8), so a block's row can be split over
-// lanes; the partial sums are what a lane adds.
-FSMI_DEV void rows4_exact_unit(const float* sG, const float* sC, int off, int j0, int k0, int k1,
-                               double (&out)[4]) {
-  const float* B = sG + (off - j0);
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  float w[11];   // w[i] = B[k - 3 + i] at the chunk start k
-  w[0] = B[k0 - 3];
-  w[1] = B[k0 - 2];
-  w[2] = B[k0 - 1];
-  int k = k0;
-  for (; k + 7 <= k1; k += 8) {
-    const float4 lo = *reinterpret_cast<const float4*>(B + k);
-    const float4 hi = *reinterpret_cast<const float4*>(B + k + 4);
-    w[3] = lo.x;
-    w[4] = lo.y;
-    w[5] = lo.z;
-    w[6] = lo.w;
-    w[7] = hi.x;
-    w[8] = hi.y;
-    w[9] = hi.z;
-    w[10] = hi.w;
-    float c[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) c[q] = sC[k - 1 + q];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      float p = c[0] * w[3 - r];
-#pragma unroll
-      for (int q = 1; q < 8; ++q) p = fma(c[q], w[3 + q - r], p);
-      acc[r] += (double)p;
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// The FP32 unit-cell double sum of Thm 1, sum_j P_j sum_k C_k g(|j - k|), on
+// the matrix cores.  With the cells in blocks of 16, the weight between a cell
+// of row block r and one of column block s depends only on t = r - s and on
+// the two offsets a, b within the blocks, so for each t >= 0
+//   M_t[a][b] = sum_s P[16(s + t) + a] C[16 s + b]  (+ C[16(s + t) + a] P[16 s + b], t > 0)
+// is a 16 x 16 product over the blocks s (the second term holds the pairs below
+// the diagonal, which meet the same weight g(|16 t + a - b|)), and the sum is
+// sum_t sum_{a,b} g(|16 t + a - b|) M_t[a][b]: every pair (j, k) once.
+// v_mfma_f32_16x16x4f32 takes four blocks s per step: lane l gives the A
+// value of row l % 16 and the B value of column l % 16 for block l / 16 of the
+// step, so both operands are 64 consecutive floats, and it returns rows
+// 4 (l / 16) .. + 3 of column l % 16.  Values past the beam read as zero.
+// Four offsets t0 .. t0 + 3 go together: they share the column operands of a
+// step (C and P at block s), and their eight products are independent chains.
+// A group deals the sets of four to its waves in a snake order; a wave
+// accumulates M_t in FP32 over the blocks, weights its four entries in FP32
+// and adds that in FP64.  sG is the mirrored FP32 weight table (unit_origin).
+template <int NW, bool BLOCK>
+FSMI_DEV double exact_unit_mfma(const float* sG, const float* sC, const float* sP, int off, int n,
+                                int tid) {
+  const int lane = tid & 63;
+  const int wv = BLOCK ? __builtin_amdgcn_readfirstlane(tid >> 6) : 0;
+  const int nb = (n + 15) >> 4;
+  const int ng = (nb + 3) >> 2;
+  const int ra = 4 * (lane >> 4) - (lane & 15);   // row - column of this lane's first output
+  double tot = 0.0;
+  for (int g = 0; g < ng; ++g) {
+    if constexpr (BLOCK) {
+      const int r = g % (2 * NW);
+      if ((r < NW ? r : 2 * NW - 1 - r) != wv) continue;
     }
-    w[0] = w[8];
-    w[1] = w[9];
-    w[2] = w[10];
-  }
-  for (; k <= k1; ++k) {
-    const float c = sC[k - 1];
+    const int t0 = 4 * g;
+    const int steps = (nb - t0 + 3) >> 2;
+    // steps q < qf read only cells below n: 16 (t0 + 3) + 64 q + 63 < n
+    const int rem = n - 16 * t0 - 112;
+    const int qf = rem >= 0 ? min(steps, (rem >> 6) + 1) : 0;
+    f32x4 a[4], b[4];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) acc[r] += (double)(c * B[k - r]);
-  }
+    for (int u = 0; u < 4; ++u) {
+      a[u] = f32x4{0.f, 0.f, 0.f, 0.f};
+      b[u] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+    const float* pr = sP + 16 * t0 + lane;
+    const float* cr = sC + 16 * t0 + lane;
+    // full steps in pairs, software-pipelined: the operands of one step (ten
+    // reads) are in flight while the other step's eight products run
+    int q = 0;
+    float ac = 0.f, ap = 0.f, ax[4], ay[4];
+    auto load = [&](int qq, float& c0, float& p0, float (&x)[4], float (&y)[4]) {
+      const int o = 64 * qq;
+      c0 = sC[o + lane];
+      p0 = sP[o + lane];
 #pragma unroll
-  for (int r = 0; r < 4; ++r) out[r] = acc[r];
+      for (int u = 0; u < 4; ++u) {
+        x[u] = pr[o + 16 * u];
+        y[u] = cr[o + 16 * u];
+      }
+    };
+    auto step = [&](float c0, float p0, const float (&x)[4], const float (&y)[4]) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        a[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(x[u], c0, a[u], 0, 0, 0);
+        b[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(y[u], p0, b[u], 0, 0, 0);
+      }
+    };
+    if (qf > 0) load(0, ac, ap, ax, ay);
+    for (; q + 1 < qf; q += 2) {
+      float bc, bp, bx[4], by[4];
+      load(q + 1, bc, bp, bx, by);
+      step(ac, ap, ax, ay);
+      if (q + 2 < qf) load(q + 2, ac, ap, ax, ay);
+      step(bc, bp, bx, by);
+    }
+    if (q < qf) {
+      step(ac, ap, ax, ay);
+      ++q;
+    }
+    for (; q < steps; ++q) {   // the last steps: cells at n and beyond are zero
+      const int ib = 64 * q + lane, jb = min(ib, n - 1);
+      const float c0 = ib < n ? sC[jb] : 0.f, p0 = ib < n ? sP[jb] : 0.f;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (16 * (t0 + u) + 64 * q >= n) break;   // this offset's rows are all past the beam
+        const int ia = 16 * (t0 + u) + ib, ja = min(ia, n - 1);
+        const float x = ia < n ? sP[ja] : 0.f, y = ia < n ? sC[ja] : 0.f;
+        a[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(x, c0, a[u], 0, 0, 0);
+        b[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(y, p0, b[u], 0, 0, 0);
+      }
+    }
+    // weights g(|16 t + a - b|); offsets of n or more meet products of zero
+    // (weight zero); at t = 0 the second product repeats the first
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int t = t0 + u;
+      if (t >= nb) break;
+      float w[4];
+      if (16 * t + 15 < n && n >= 16) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) w[r] = sG[off + 16 * t + ra + r];
+      } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int dd = 16 * t + ra + r;
+          const int dc = max(-(n - 1), min(dd, n - 1));
+          w[r] = (dd < n && dd > -n) ? sG[off + dc] : 0.f;
+        }
+      }
+      const float k2 = t > 0 ? 1.f : 0.f;
+      float acc = fmaf(k2, b[u][0], a[u][0]) * w[0];
+#pragma unroll
+      for (int r = 1; r < 4; ++r) acc = fmaf(fmaf(k2, b[u][r], a[u][r]), w[r], acc);
+      tot += (double)acc;
+    }
+  }
+  return tot;
 }
 
 template <typename T>
@@ -665,44 +733,12 @@ FSMI_DEV double beam_core(const EvalConst& ec, int n, const float* so, bool has_
       const T* sG = reinterpret_cast<const T*>(sA);
       int off = 0;
       if constexpr (sizeof(T) == 4) off = unit_origin(sG, n);
-      int j1 = 1;   // rows below j1 are done in blocks of four
-      if constexpr (sizeof(T) == 4) {
-        const int nb4 = n / 4;
-        if (ec.variant == FSMI_EXACT && nb4 >= G / 2) {   // enough blocks for the group
-          // Each block's columns are split into S segments (multiples of 8,
-          // at least 64 columns), S <= 8 chosen so that the units nb4 S fill
-          // the group's rounds best (fewer segments unless 2 % better): a
-          // lane adds P_j times its partial row sums.
-          int S = 1;
-          {
-            const int smax = min(8, n / 64);
-            float best = (float)nb4 / (float)(G * ((nb4 + G - 1) / G));
-            for (int sc = 2; sc <= smax; ++sc) {
-              const int U = nb4 * sc;
-              const float e = (float)U / (float)(G * ((U + G - 1) / G));
-              if (e > best + 0.02f) {
-                best = e;
-                S = sc;
-              }
-            }
-          }
-          const int seg = ((n + S - 1) / S + 7) / 8 * 8;
-          // segment-major: neighbouring lanes take neighbouring blocks of the
-          // same columns, so C_k stays a broadcast and the weight windows
-          // stay contiguous
-          for (int u = tid; u < nb4 * S; u += G) {
-            const int sg = u / nb4, b = u - sg * nb4, k0 = 1 + sg * seg;
-            if (k0 > n) continue;
-            double rv[4];
-            rows4_exact_unit(sG, sC, off, 4 * b + 1, k0, min(n, k0 + seg - 1), rv);
-#pragma unroll
-            for (int r = 0; r < 4; ++r) tot += (double)sP[4 * b + r] * rv[r];
-          }
-          j1 = 4 * nb4 + 1;
-        }
-      }
       if (ec.variant == FSMI_EXACT) {
-        for (int j = j1 + tid; j <= n; j += G) tot += (double)sP[j - 1] * row_exact_unit<T>(sG, sC, off, n, j);
+        if constexpr (sizeof(T) == 4) {
+          tot = exact_unit_mfma<NW, BLOCK>(sG, sC, sP, off, n, tid);
+        } else {
+          for (int j = tid + 1; j <= n; j += G) tot += (double)sP[j - 1] * row_exact_unit<T>(sG, sC, off, n, j);
+        }
       } else {
         for (int j = tid + 1; j <= n; j += G)
           tot += (double)sP[j - 1] * row_approx_unit<T>(sG, sC, off, n, j, ec.Delta);

@@ -75,8 +75,7 @@ hipError_t launch_beam_schedule(hipStream_t st, const int64_t* off, int64_t n_be
 hipError_t launch_beam_kernels(hipStream_t st, int num_cu, const EvalConst& ec, int64_t n_beams,
                                const int64_t* off, const float* occ, const double* bound,
                                const float* sigma, double* mi, const int32_t* sched,
-                               uint32_t* status, int wave_max, int max_len, bool run_long,
-                               bool run_short);
+                               uint32_t* status, int wave_max, int max_len);
 hipError_t launch_eval_beams(fsmi_ctx ctx, const EvalConst& ec, int64_t n_beams, const int64_t* off,
                              const float* occ, const double* bound, const float* sigma,
                              double* mi, int max_len, int wave_max);

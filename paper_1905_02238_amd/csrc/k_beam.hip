@@ -4,8 +4,9 @@
 // descending length bins, with every beam above the wave threshold ahead of
 // every beam at or below it; beams above the threshold are taken by a whole
 // workgroup (rows j split over all its lanes: tile-per-beam), the rest by
-// single waves (wave-per-beam).  Both pop items from atomic queue heads, so
-// every wave exits once the queues are drained.
+// single waves (wave-per-beam), in the same kernel (k_eval_fused).  Both pop
+// items from atomic queue heads, so every wave exits once the queues are
+// drained.
 #include <math.h>
 
 #include <algorithm>
@@ -86,17 +87,23 @@ FSMI_DEV void process_beam(const BeamArgs& a, int b, char* lds, int cap, double*
   }
 }
 
-// Tile-per-beam: the beams above the wave threshold, one workgroup per beam.
-// Every value that steers a branch around a barrier is made wave-uniform
-// (readfirstlane), so those branches are scalar and all waves of the
-// workgroup meet the same barriers.
+// Both schedules in one persistent launch: every workgroup first takes beams
+// above the wave threshold from the tile queue (all four waves on one beam),
+// and once that queue is empty each of its waves takes beams from the wave
+// queue on its own LDS slice.  A workgroup that finishes the long beams starts
+// on the short ones at once, so no compute unit waits at a kernel boundary for
+// the last long beams.  The LDS is the larger of the two phases' needs; the
+// phases share it, and all waves leave the first phase together (its exit test
+// is on a value read between two barriers), after the barrier that ends the
+// last beam's use of the LDS.
 template <typename T, bool CSQ>
-__global__ __launch_bounds__(kWave* kNW) void k_eval_long(BeamArgs a) {
+__global__ __launch_bounds__(kWave* kNW) void k_eval_fused(BeamArgs a) {
   extern __shared__ __align__(16) char lds[];
   __shared__ double scratch[kNW];
   __shared__ int s_item, s_flag;
   const int tid = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int lane = tid & 63;
   const int n_long = __builtin_amdgcn_readfirstlane(a.counters[2]);
   for (;;) {
     if (wave == 0) s_item = wave_pop(&a.counters[0]);   // every lane of wave 0 writes the same value
@@ -108,21 +115,8 @@ __global__ __launch_bounds__(kWave* kNW) void k_eval_long(BeamArgs a) {
     process_beam<true, T, CSQ>(a, b, lds, a.cap_block, scratch, &s_flag, tid);
     __syncthreads();
   }
-}
-
-// Wave-per-beam: the remaining beams, each wave on its own LDS slice; no
-// workgroup barriers.
-template <typename T, bool CSQ>
-__global__ __launch_bounds__(kWave* kNW) void k_eval_short(BeamArgs a) {
-  extern __shared__ __align__(16) char lds[];
-  const int tid = threadIdx.x;
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int lane = tid & 63;
-  const int n_long = __builtin_amdgcn_readfirstlane(a.counters[2]);
   const int n_short = (int)a.n_beams - n_long;
   char* my = lds + (size_t)wave * ((size_t)a.cap_wave * bytes_per_cell<T>() + 16);
-  // runs of beams (guided self-scheduling): neighbours in the order have
-  // similar lengths, and the queue head is touched once per run
   const int64_t n_waves = (int64_t)gridDim.x * kNW;
   int k = (int)run_length(n_short, 0, n_waves);
   for (int start = wave_take(&a.counters[1], k); start < n_short;
@@ -300,8 +294,7 @@ int64_t beam_sched_n_long_index(int64_t n_beams) { return n_beams + 2 * kBins + 
 hipError_t launch_beam_kernels(hipStream_t st, int num_cu, const EvalConst& ec, int64_t n_beams,
                                const int64_t* off, const float* occ, const double* bound,
                                const float* sigma, double* mi, const int32_t* sched,
-                               uint32_t* status, int wave_max, int max_len, bool run_long,
-                               bool run_short) {
+                               uint32_t* status, int wave_max, int max_len) {
   BeamArgs a;
   a.ec = ec;
   a.n_beams = n_beams;
@@ -320,27 +313,23 @@ hipError_t launch_beam_kernels(hipStream_t st, int num_cu, const EvalConst& ec, 
   const size_t lds_long = bpc * a.cap_block + 16;
   const size_t lds_short = (size_t)kNW * (bpc * a.cap_wave + 16);
   if (lds_long > kLdsLimit || lds_short > kLdsLimit) return hipErrorInvalidValue;
-  const int64_t want = (n_beams + kNW - 1) / kNW;
-  const int per_cu_l = std::max<int>(1, (int)((160 * 1024) / (lds_long + 512)));
-  const int per_cu_s = std::max<int>(1, (int)((160 * 1024) / (lds_short + 512)));
-  const int grid_l = std::max(1, std::min(kMaxGrid, num_cu * std::min(per_cu_l, 8)));
-  const int grid_s = (int)std::max<int64_t>(
-      1, std::min<int64_t>(want, std::min(kMaxGrid, num_cu * std::min(per_cu_s, 8))));
+  // one persistent launch over both queues, sized for the larger phase
+  const size_t lds = std::max(lds_long, lds_short);
+  const int per_cu = std::max<int>(1, (int)((160 * 1024) / (lds + 512)));
+  const int grid = std::max(1, std::min(kMaxGrid, num_cu * std::min(per_cu, 8)));
   // queue heads back to zero; the long-beam count written by the schedule stays
   hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, st, a.counters);
-  auto launch = [&](auto klong, auto kshort) {
-    (void)hipFuncSetAttribute((const void*)klong, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_long);
-    (void)hipFuncSetAttribute((const void*)kshort, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_short);
-    if (run_long) hipLaunchKernelGGL(klong, dim3(grid_l), dim3(kWave * kNW), lds_long, st, a);
-    if (run_short) hipLaunchKernelGGL(kshort, dim3(grid_s), dim3(kWave * kNW), lds_short, st, a);
+  auto launch = [&](auto kern) {
+    (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kWave * kNW), lds, st, a);
   };
   const bool csq = ec.variant == FSMI_CSQMI;
   if (fp64) {
-    if (csq) launch(k_eval_long<double, true>, k_eval_short<double, true>);
-    else launch(k_eval_long<double, false>, k_eval_short<double, false>);
+    if (csq) launch(k_eval_fused<double, true>);
+    else launch(k_eval_fused<double, false>);
   } else {
-    if (csq) launch(k_eval_long<float, true>, k_eval_short<float, true>);
-    else launch(k_eval_long<float, false>, k_eval_short<float, false>);
+    if (csq) launch(k_eval_fused<float, true>);
+    else launch(k_eval_fused<float, false>);
   }
   return hipGetLastError();
 }
@@ -355,7 +344,7 @@ hipError_t launch_eval_beams(fsmi_ctx ctx, const EvalConst& ec, int64_t n_beams,
   e = launch_beam_schedule(ctx->stream, off, n_beams, wave_max, sched);
   if (e != hipSuccess) return e;
   return launch_beam_kernels(ctx->stream, ctx->num_cu, ec, n_beams, off, occ, bound, sigma, mi, sched,
-                             ctx->d_status, wave_max, max_len, true, true);
+                             ctx->d_status, wave_max, max_len);
 }
 
 __global__ void k_fill_f64(int64_t n, double v, double* p) {

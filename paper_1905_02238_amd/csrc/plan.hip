@@ -54,7 +54,7 @@ hipError_t plan_schedule(fsmi_plan p, int wave_max) {
 hipError_t plan_enqueue(fsmi_plan p, hipStream_t st) {
   return launch_beam_kernels(st, p->ctx->num_cu, p->ec, p->n_beams, p->off, p->occ, p->bound,
                              p->sigma, p->mi, p->d_sched, p->ctx->d_status, p->wave_max,
-                             p->max_len, p->n_long > 0, p->n_long < p->n_beams);
+                             p->max_len);
 }
 
 // Time each candidate threshold (one warm launch, then the mean of three) and

@@ -35,3 +35,26 @@ def test_slot_accounting_is_the_documented_one():
     assert bench.SLOTS_PER_PAIR == 14.5
     assert abs(bench.ALU_PEAK_TSLOT - 39.3216) < 1e-9
     assert bench.SUR_FLOP_PER_POSE == 73204224
+
+
+def test_matrix_core_work_counts_the_kernel_loop():
+    """The closed form of unit_mfma_macs against a walk over the kernel's
+    loop: sets of four block offsets t0 = 4 g, steps q < ceil((nb - t0) / 4),
+    two products per offset whose first row 16 (t0 + u) + 64 q lies in the
+    beam."""
+    def walk(n):
+        nb = (n + 15) // 16
+        cnt = 0
+        for g in range((nb + 3) // 4):
+            t0 = 4 * g
+            for q in range((nb - t0 + 3) // 4):
+                for u in range(4):
+                    if 16 * (t0 + u) + 64 * q < n:
+                        cnt += 2
+        return cnt * 1024
+    lens = [1, 15, 16, 17, 63, 64, 65, 127, 128, 129, 300, 511, 512, 513, 1999, 2000]
+    assert bench.unit_mfma_macs(lens) == float(sum(walk(n) for n in lens))
+    assert bench.unit_mfma_macs([]) == 0.0
+    # every pair is covered: at least n^2 multiply-adds
+    assert all(bench.unit_mfma_macs([n]) >= n * n for n in lens)
+    assert abs(bench.MFMA_F32_MAC_PEAK - 7.86432e13) < 1e6
