@@ -86,6 +86,11 @@ ALU_PEAK_TSLOT = 256 * 64 * 2.4e9 / 1e12
 # instruction per lane per clock: 256 x 64 x 2.4e9 / 13 = 3.02e12 pairs/s.
 PAIR_ISSUE_SLOTS = 13
 PHI_PAIR_PEAK = 256 * 64 * 2.4e9 / PAIR_ISSUE_SLOTS
+# Error bar reported for the look-up-table mode (FSMI_F_LUT): an approximation
+# of its own, not held to the analytic FP32 mode's 1e-5.  Its tail table is
+# within 6e-6 of erfc and its f table within 5e-7 of f; 1e-4 relative is the
+# bar this build reports it against.
+LUT_BAR = 1e-4
 # FP32 matrix cores: v_mfma_f32_16x16x4f32 is 1024 multiply-adds per 32 cycles
 # per SIMD, 256 x 4 x 32 x 2.4e9 = 7.86e13 MAC/s (157.3 TFLOP/s).
 MFMA_F32_MAC_PEAK = 256 * 4 * 32 * 2.4e9
@@ -363,6 +368,18 @@ def main():
             extras[name] = {"beams_per_s": n_total / dt, "ms": dt * 1e3}
             gpu[name] = ctx.fsmi_eval_poses(p, grid, poses, bdir, sigma, R, want_beams=True)
             log(f"[bench] {name}: {n_total/dt/1e6:.2f} M beams/s")
+        # the look-up-table mode of Sec. 3.3 (opt-in): the tail of the normal
+        # distribution and f read from tables, beside the analytic path
+        for name, p, ref in (("exact_lut", F.params(flags=F.FSMI_F_LUT), None),
+                             ("approx_delta9_lut", F.params(variant=F.FSMI_APPROX, trunc_delta=9,
+                                                            flags=F.FSMI_F_LUT), "approx_delta9")):
+            dt = timed(lambda: ctx.fsmi_eval_poses(p, grid, poses, bdir, sigma, R))
+            base = extras[ref]["beams_per_s"] if ref else value
+            extras[name] = {"beams_per_s": n_total / dt, "ms": dt * 1e3,
+                            "speed_over_analytic": (n_total / dt) / base,
+                            "pairs_per_s": pairs / dt if not ref else None}
+            gpu[name] = ctx.fsmi_eval_poses(p, grid, poses, bdir, sigma, R, want_beams=True)
+            log(f"[bench] {name}: {n_total/dt/1e6:.2f} M beams/s")
         # skip-zero exact mode: same workload, pairs whose FP32 weight is below
         # the smallest normal float left out; its own work count from the
         # walks of the first 16 poses
@@ -556,6 +573,15 @@ def oracle_leg(out, gpu, wl, W, args, ctx, F, t):
                                    max_rel_pose=float(_rel(gp.cpu().numpy(), rp).max()))
             log(f"[bench] oracle {name}: every beam of {len(rp)} poses in "
                 f"{time.perf_counter() - t1:.1f} s")
+            if name == "approx_delta9":
+                gp, gbm = gpu["approx_delta9_lut"]
+                rep["approx_delta9_lut"] = _err_stats(
+                    _rel(gbm.cpu().numpy(), rb), LUT_BAR, poses=len(rp), mode="FSMI_F_LUT",
+                    max_rel_pose=float(_rel(gp.cpu().numpy(), rp).max()))
+        gp, gbm = gpu["exact_lut"]
+        rep["exact_lut"] = _err_stats(_rel(gbm[:k].cpu().numpy(), ref_beam), LUT_BAR, poses=k,
+                                      mode="FSMI_F_LUT",
+                                      max_rel_pose=float(_rel(gp[:k].cpu().numpy(), ref_pose).max()))
         rep["exact_skip_zero"] = _err_stats(_rel(gpu["exact_skip_zero"][:k].cpu().numpy(), ref_pose),
                                             1e-5, poses=k)
         rp, _ = O.eval_poses_2d(O.EXACT, wl["grid"], wl["poses"][:kp], wl["beam_dir"], sig, R,

@@ -110,7 +110,19 @@ enum {
      64 runs, FSMI_F_RLE_CELLS the expanded engine for every beam.  At most one
      of them; no other flag with them. */
   FSMI_F_RLE_RUNS = 4u,
-  FSMI_F_RLE_CELLS = 8u
+  FSMI_F_RLE_CELLS = 8u,
+  /* Look-up-table mode (Sec. 3.3, opt-in; 2D fsmi_eval_poses and
+     fsmi_eval_poses_noalloc, FP32, EXACT or APPROX, one sigma): the tail of the
+     normal distribution (the Phi differences of Eq. G_jk) and f(delta_occ, .)
+     are read from tables with linear interpolation instead of being evaluated:
+     1536 tail entries at 1/128 of the FP32 mode's scaled argument
+     |l - mu| sqrt(log2 e) / (sigma sqrt 2), within 6e-6 of erfc, and 512 f
+     entries over o in [0, 1]; f(delta_emp, o) = f(delta_occ, 1 - o).  The
+     tables are built on the device at each call (16 KiB, held by the context)
+     and staged into LDS.  An approximation with its own error (not the 1e-5
+     bar of the analytic FP32 mode).  Alone: no other flag, no sigma_slope.
+     Other entry points return FSMI_E_UNSUPPORTED. */
+  FSMI_F_LUT = 16u
 };
 
 typedef struct {
@@ -120,7 +132,7 @@ typedef struct {
   int32_t uniform_h;  /* H >= 0, cells (UNIFORM) */
   int32_t kernel;     /* FSMI_KERNEL_* (equal-width cells and RLE only) */
   int32_t precision;  /* FSMI_FP32 (default) | FSMI_FP64 */
-  uint32_t flags;     /* 0, FSMI_F_SKIP_ZERO, FSMI_F_MAX_RANGE or an FSMI_F_RLE_* engine */
+  uint32_t flags;     /* 0, FSMI_F_SKIP_ZERO, FSMI_F_MAX_RANGE, an FSMI_F_RLE_* engine or FSMI_F_LUT */
   /* Range-dependent noise: the reading of event e_j is N(mu_j, sigma_j^2) with
      sigma_j = sigma + sigma_slope * mu_j (Alg 1 writes sigma per event; the
      paper's experiments use one sigma).  >= 0; 0 (default) is one sigma per

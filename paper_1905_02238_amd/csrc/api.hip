@@ -56,8 +56,15 @@ bool check_params(fsmi_ctx ctx, const fsmi_params* p, fsmi_status* st) {
     *st = fail(ctx, FSMI_E_INVAL, "unknown precision");
     return false;
   }
-  if (p->flags & ~(uint32_t)(FSMI_F_SKIP_ZERO | FSMI_F_MAX_RANGE | FSMI_F_RLE_RUNS | FSMI_F_RLE_CELLS)) {
+  if (p->flags & ~(uint32_t)(FSMI_F_SKIP_ZERO | FSMI_F_MAX_RANGE | FSMI_F_RLE_RUNS | FSMI_F_RLE_CELLS |
+                             FSMI_F_LUT)) {
     *st = fail(ctx, FSMI_E_INVAL, "unknown flags");
+    return false;
+  }
+  if ((p->flags & FSMI_F_LUT) &&
+      (p->flags != FSMI_F_LUT || p->precision != FSMI_FP32 || p->sigma_slope != 0.0 ||
+       (p->variant != FSMI_EXACT && p->variant != FSMI_APPROX))) {
+    *st = fail(ctx, FSMI_E_INVAL, "FSMI_F_LUT goes alone, with FP32 EXACT or APPROX and one sigma");
     return false;
   }
   if ((p->flags & (FSMI_F_RLE_RUNS | FSMI_F_RLE_CELLS)) &&
@@ -202,14 +209,17 @@ fsmi_status fsmi_create(fsmi_ctx* out, int device, void* hip_stream) {
     delete c;
     return FSMI_E_DEVICE;
   }
-  if (hipMalloc(&c->d_status, 256) != hipSuccess || hipMalloc(&c->d_counters, 64 * 4) != hipSuccess) {
+  if (hipMalloc(&c->d_status, 256) != hipSuccess || hipMalloc(&c->d_counters, 64 * 4) != hipSuccess ||
+      hipMalloc(&c->d_lut, lut_bytes()) != hipSuccess) {
     if (c->d_status) (void)hipFree(c->d_status);
+    if (c->d_counters) (void)hipFree(c->d_counters);
     delete c;
     return FSMI_E_NOMEM;
   }
   if (hipEventCreateWithFlags(&c->handoff, hipEventDisableTiming) != hipSuccess) {
     (void)hipFree(c->d_status);
     (void)hipFree(c->d_counters);
+    (void)hipFree(c->d_lut);
     delete c;
     return FSMI_E_DEVICE;
   }
@@ -225,6 +235,7 @@ void fsmi_destroy(fsmi_ctx ctx) {
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
   if (ctx->d_work) (void)hipFree(ctx->d_work);
+  if (ctx->d_lut) (void)hipFree(ctx->d_lut);
   if (ctx->d_status) (void)hipFree(ctx->d_status);
   if (ctx->d_counters) (void)hipFree(ctx->d_counters);
   if (ctx->handoff) (void)hipEventDestroy(ctx->handoff);
@@ -328,6 +339,8 @@ fsmi_status fsmi_eval_beams(fsmi_ctx ctx, const fsmi_params* params, int64_t n_b
     return fail(ctx, FSMI_E_INVAL, "FSMI_F_SKIP_ZERO needs explicit boundaries");
   if (params->flags & (FSMI_F_RLE_RUNS | FSMI_F_RLE_CELLS))
     return fail(ctx, FSMI_E_INVAL, "FSMI_F_RLE_* select the engine of the RLE paths");
+  if (params->flags & FSMI_F_LUT)
+    return fail(ctx, FSMI_E_UNSUPPORTED, "FSMI_F_LUT is implemented on 2D fsmi_eval_poses");
   if (ext_mode(params) && !bound)
     return fail(ctx, FSMI_E_INVAL, "sigma_slope and FSMI_F_MAX_RANGE need explicit boundaries");
   (void)hipSetDevice(ctx->device);
@@ -359,6 +372,8 @@ fsmi_status fsmi_rle_eval_beams(fsmi_ctx ctx, const fsmi_params* params, int64_t
     return fail(ctx, FSMI_E_INVAL, "sigma_slope and FSMI_F_MAX_RANGE need explicit boundaries");
   if (params->variant == FSMI_CSQMI)
     return fail(ctx, FSMI_E_INVAL, "FSMI_CSQMI is a 2D path (fsmi_eval_beams, 2D poses)");
+  if (params->flags & FSMI_F_LUT)
+    return fail(ctx, FSMI_E_UNSUPPORTED, "FSMI_F_LUT is implemented on 2D fsmi_eval_poses");
   (void)hipSetDevice(ctx->device);
   return from_hip(ctx,
                   launch_rle_eval_beams(ctx, to_const(params), n_beams, run_off, run_occ, run_len,
@@ -448,6 +463,8 @@ fsmi_status eval_poses_checked(fsmi_ctx ctx, const fsmi_params* params, const fs
     return fail(ctx, FSMI_E_INVAL, "sigma_slope and FSMI_F_MAX_RANGE need explicit boundaries (2D maps)");
   if (params->variant == FSMI_CSQMI)
     return fail(ctx, FSMI_E_INVAL, "FSMI_CSQMI is a 2D path (fsmi_eval_beams, 2D poses)");
+  if (params->flags & FSMI_F_LUT)
+    return fail(ctx, FSMI_E_UNSUPPORTED, "FSMI_F_LUT is implemented on 2D fsmi_eval_poses");
   if (!(w > 0.0) || !std::isfinite(w)) return fail(ctx, FSMI_E_INVAL, "w must be finite and > 0");
   if (floor(max_range / w) > 4000.0) return fail(ctx, FSMI_E_CAPACITY, "more than 4000 virtual cells per beam");
   return from_hip(ctx,

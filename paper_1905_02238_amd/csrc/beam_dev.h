@@ -19,6 +19,7 @@
 
 #include "fsmi_dev.h"
 #include "fsmi_internal.h"
+#include "lut_dev.h"
 
 namespace fsmi {
 
@@ -121,15 +122,21 @@ template <> struct Acc<double> {
 //   FP64: L = l c;
 // with c = 1/(sigma sqrt 2), so the weight argument of a boundary is |L - M|
 // (M the scaled mid-point of the hit cell) with no multiply per pair.
-template <typename T>
-FSMI_DEV T tail_E(double L, double M) {
+// LUT (FP32 only): the boundaries are scaled by kLutInvH too and the tail is
+// read from the table (lut_dev.h).
+template <typename T, bool LUT = false>
+FSMI_DEV T tail_E(double L, double M, const float2* lut = nullptr) {
   if constexpr (sizeof(T) == 8) {
     return erfc_pos(tabs(L - M));
+  } else if constexpr (LUT) {
+    return lut_tail(lut, (float)tabs(L - M));
   } else {
     return erfc_pos_l2((float)tabs(L - M));
   }
 }
-template <typename T> constexpr double unscale() { return sizeof(T) == 8 ? 1.0 : (double)kInvSqrtL2E; }
+template <typename T, bool LUT = false> constexpr double unscale() {
+  return sizeof(T) == 8 ? 1.0 : (LUT ? (double)kInvSqrtL2E / (double)kLutInvH : (double)kInvSqrtL2E);
+}
 
 // The erfc of a signed scaled distance d, on the tail side.
 template <typename T>
@@ -172,14 +179,15 @@ FSMI_DEV RowFrame<T, RD> row_frame(const double* sL, int j, double sigma, double
 // G_{k,j} = (1/2)|E(l_{k+1}) - E(l_k)| for k != j (both boundaries on one side
 // of mu_j), G_{j,j} = (1/2)(erf((l_{j+1}-mu)c) + erf((mu-l_j)c)).
 // ---------------------------------------------------------------------------
-template <typename T>
-FSMI_DEV double diag_fix(Acc<T>& acc, const double* sL, const T* sC, int j, double M) {
+template <typename T, bool LUT = false>
+FSMI_DEV double diag_fix(Acc<T>& acc, const double* sL, const T* sC, int j, double M,
+                         const float2* lut = nullptr) {
   // replace the k = j term the loop took by the exact diagonal weight
-  T Ej = tail_E<T>(sL[j - 1], M);
-  T Ej1 = tail_E<T>(sL[j], M);
+  T Ej = tail_E<T, LUT>(sL[j - 1], M, lut);
+  T Ej1 = tail_E<T, LUT>(sL[j], M, lut);
   T Cj = sC[j - 1];
   acc.add(-(Cj * tabs(Ej1 - Ej)));
-  constexpr double u = unscale<T>();
+  constexpr double u = unscale<T, LUT>();
   T g2 = erf_t<T>((T)((sL[j] - M) * u)) + erf_t<T>((T)((M - sL[j - 1]) * u));
   acc.add(Cj * g2);
   return 0.5 * acc.value();
@@ -188,16 +196,17 @@ FSMI_DEV double diag_fix(Acc<T>& acc, const double* sL, const T* sC, int j, doub
 // Terms b0..b1 (1 <= b0 <= b1 <= n) of row j, halved, with the exact diagonal
 // weight if the segment holds b = j.  Eight pairs per compensated add: the
 // block of eight is an FP32 (or FP64) FMA chain, the blocks are Kahan-summed.
-template <typename T>
-FSMI_DEV double row_exact_seg(const double* sL, const T* sC, int j, int b0, int b1) {
+template <typename T, bool LUT = false>
+FSMI_DEV double row_exact_seg(const double* sL, const T* sC, int j, int b0, int b1,
+                              const float2* lut = nullptr) {
   const double M = 0.5 * (sL[j - 1] + sL[j]);
   Acc<T> acc;
-  T Eprev = tail_E<T>(sL[b0 - 1], M);
+  T Eprev = tail_E<T, LUT>(sL[b0 - 1], M, lut);
   int b = b0;
   for (; b + 7 <= b1; b += 8) {
     T E[8];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) E[q] = tail_E<T>(sL[b + q], M);
+    for (int q = 0; q < 8; ++q) E[q] = tail_E<T, LUT>(sL[b + q], M, lut);
     T p = sC[b - 1] * tabs(E[0] - Eprev);
 #pragma unroll
     for (int q = 1; q < 8; ++q) p = fma(sC[b - 1 + q], tabs(E[q] - E[q - 1]), p);
@@ -205,11 +214,11 @@ FSMI_DEV double row_exact_seg(const double* sL, const T* sC, int j, int b0, int 
     Eprev = E[7];
   }
   for (; b <= b1; ++b) {
-    T E = tail_E<T>(sL[b], M);
+    T E = tail_E<T, LUT>(sL[b], M, lut);
     acc.add(sC[b - 1] * tabs(E - Eprev));
     Eprev = E;
   }
-  if (j >= b0 && j <= b1) return diag_fix<T>(acc, sL, sC, j, M);
+  if (j >= b0 && j <= b1) return diag_fix<T, LUT>(acc, sL, sC, j, M, lut);
   return 0.5 * acc.value();
 }
 
@@ -217,11 +226,13 @@ FSMI_DEV double row_exact_seg(const double* sL, const T* sC, int j, int b0, int 
 // group: whole sweeps of G rows (one row per lane), then the last R = n mod G
 // rows, each cut into S = floor(G / R) equal runs of terms, lane l taking row
 // (l mod R), run (l div R), so a partly filled sweep does not leave lanes idle.
-template <int G, typename T>
-FSMI_DEV double exact_rows(const double* sL, const T* sC, const T* sP, int n, int tid) {
+template <int G, typename T, bool LUT = false>
+FSMI_DEV double exact_rows(const double* sL, const T* sC, const T* sP, int n, int tid,
+                           const float2* lut = nullptr) {
   double tot = 0.0;
   const int full = (n / G) * G;
-  for (int j = tid + 1; j <= full; j += G) tot += (double)sP[j - 1] * row_exact_seg<T>(sL, sC, j, 1, n);
+  for (int j = tid + 1; j <= full; j += G)
+    tot += (double)sP[j - 1] * row_exact_seg<T, LUT>(sL, sC, j, 1, n, lut);
   const int R = n - full;
   if (R > 0) {
     const int S = G / R;
@@ -230,7 +241,7 @@ FSMI_DEV double exact_rows(const double* sL, const T* sC, const T* sP, int n, in
     const int b0 = s * len + 1, b1 = min(n, (s + 1) * len);
     if (s < S && b0 <= b1) {
       const int j = full + 1 + r;
-      tot += (double)sP[j - 1] * row_exact_seg<T>(sL, sC, j, b0, b1);
+      tot += (double)sP[j - 1] * row_exact_seg<T, LUT>(sL, sC, j, b0, b1, lut);
     }
   }
   return tot;
@@ -363,14 +374,14 @@ FSMI_DEV double row_exact_band(const double* sL, const T* sC, int n, int j) {
 // Cells k in [k0, k1) of row j on the tail side given by Eprev (the tail
 // value at boundary k0 - 1): sum of C_k |E_k - E_{k-1}| in FMA chains of up
 // to eight terms, each chain Kahan-added to acc.
-template <typename T>
+template <typename T, bool LUT = false>
 FSMI_DEV void row_side(const double* sL, const T* sC, double M, int k0, int k1, T Eprev,
-                       Acc<T>& acc) {
+                       Acc<T>& acc, const float2* lut = nullptr) {
   for (int b = k0; b < k1; b += 8) {
     const int e = min(b + 8, k1);
     T p = T(0);
     for (int k = b; k < e; ++k) {
-      const T E = tail_E<T>(sL[k], M);
+      const T E = tail_E<T, LUT>(sL[k], M, lut);
       p = fma(sC[k - 1], tabs(E - Eprev), p);
       Eprev = E;
     }
@@ -378,16 +389,17 @@ FSMI_DEV void row_side(const double* sL, const T* sC, double M, int k0, int k1, 
   }
 }
 
-template <typename T>
-FSMI_DEV double row_approx_bound(const double* sL, const T* sC, int n, int j, int D) {
+template <typename T, bool LUT = false>
+FSMI_DEV double row_approx_bound(const double* sL, const T* sC, int n, int j, int D,
+                                 const float2* lut = nullptr) {
   const double M = 0.5 * (sL[j - 1] + sL[j]);
   // cells k = j-D..j+D inside the beam; the hit cell k = j takes the exact
   // weight of its two half widths, the others their tail differences
   const int k0 = max(1, j - D), k1 = min(n, j + D);
   Acc<T> acc;
-  row_side<T>(sL, sC, M, k0, j, tail_E<T>(sL[k0 - 1], M), acc);
-  row_side<T>(sL, sC, M, j + 1, k1 + 1, tail_E<T>(sL[j], M), acc);
-  constexpr double u = unscale<T>();
+  row_side<T, LUT>(sL, sC, M, k0, j, tail_E<T, LUT>(sL[k0 - 1], M, lut), acc, lut);
+  row_side<T, LUT>(sL, sC, M, j + 1, k1 + 1, tail_E<T, LUT>(sL[j], M, lut), acc, lut);
+  constexpr double u = unscale<T, LUT>();
   const T g2 = erf_t<T>((T)((sL[j] - M) * u)) + erf_t<T>((T)((M - sL[j - 1]) * u));
   acc.add(sC[j - 1] * g2);
   return 0.5 * acc.value();
@@ -577,6 +589,7 @@ struct CoreLds {
   double* A;   // boundaries l_1..l_{n+1} on entry (explicit bounds); D prefix; kernel table
   void* C;     // C_k
   void* P;     // P(e_j)
+  const float2* lut = nullptr;   // the look-up tables in LDS (LUT mode)
 };
 
 // The beam's mutual information, valid in every lane of the group.
@@ -585,7 +598,7 @@ struct CoreLds {
 // MASK: only the cells i with counted[i] != 0 add their information (cell
 // marking along a trajectory, Sec. 2.4): by Lemma 1 the f terms of the other
 // cells leave C_k, while every cell still shapes P(e_j).
-template <int NW, bool BLOCK, typename T, bool MASK = false>
+template <int NW, bool BLOCK, typename T, bool MASK = false, bool LUT = false>
 FSMI_DEV double beam_core(const EvalConst& ec, int n, const float* so, bool has_bound, double sigma,
                           const CoreLds& L, double* scratch, int* flag, int tid, bool bad_in,
                           bool* bad_out, const unsigned char* counted = nullptr) {
@@ -624,7 +637,10 @@ FSMI_DEV double beam_core(const EvalConst& ec, int n, const float* so, bool has_
       if (v && !(of[u] >= 0.0f && of[u] <= 1.0f)) bad = true;
       const double o = (double)of[u];
       double fe;
-      if constexpr (sizeof(T) == 4) {
+      if constexpr (LUT) {
+        fo[u] = lut_f(L.lut, o);
+        fe = lut_f(L.lut, 1.0 - o);
+      } else if constexpr (sizeof(T) == 4) {
         fo[u] = f_cell_series(ko, o);
         fe = f_cell_series(ke, o);
       } else {
@@ -700,7 +716,7 @@ FSMI_DEV double beam_core(const EvalConst& ec, int n, const float* so, bool has_
   const bool rd = ec.slope != 0.0;
   if (has_bound && !uni && !any_bad && !rd) {
     // scale the boundaries once: the weight argument becomes |L_b - M_j|
-    const double s = sizeof(T) == 8 ? c : c * (double)kSqrtL2E;
+    const double s = sizeof(T) == 8 ? c : c * (double)kSqrtL2E * (LUT ? (double)kLutInvH : 1.0);
     for (int i = tid; i <= n; i += G) sA[i] *= s;
     Grp<NW, BLOCK>::sync();
   }
@@ -724,10 +740,10 @@ FSMI_DEV double beam_core(const EvalConst& ec, int n, const float* so, bool has_
         else tot = exact_rows_ext<G, T, false>(sA, sC, sP, n, tid, sigma, 0.0, tq);
         if (tid == 0 && (ec.flags & FSMI_F_MAX_RANGE)) tot += carryC * carryE;
       } else if (ec.variant == FSMI_EXACT) {
-        tot = exact_rows<G, T>(sA, sC, sP, n, tid);
+        tot = exact_rows<G, T, LUT>(sA, sC, sP, n, tid, L.lut);
       } else {
         for (int j = tid + 1; j <= n; j += G)
-          tot += (double)sP[j - 1] * row_approx_bound<T>(sA, sC, n, j, ec.Delta);
+          tot += (double)sP[j - 1] * row_approx_bound<T, LUT>(sA, sC, n, j, ec.Delta, L.lut);
       }
     } else {
       const T* sG = reinterpret_cast<const T*>(sA);

@@ -150,7 +150,7 @@ namespace fsmi {
 // The per-beam evaluation of the 2D paths: FSMI's variants (beam_core) or, in
 // kernels instantiated for it (CSQ), the CSQMI comparator, so the FSMI kernels
 // compile without the comparator's code.
-template <int NW, bool BLOCK, typename T, bool CSQ>
+template <int NW, bool BLOCK, typename T, bool CSQ, bool LUT = false>
 FSMI_DEV double beam_eval(const EvalConst& ec, int n, const float* so, bool has_bound,
                           double sigma, const CoreLds& L, double* scratch, int* flag, int tid,
                           bool bad_in, bool* bad_out) {
@@ -158,7 +158,7 @@ FSMI_DEV double beam_eval(const EvalConst& ec, int n, const float* so, bool has_
     return csqmi_core<NW, BLOCK, T>(ec, n, so, has_bound, sigma, L, scratch, flag, tid, bad_in,
                                     bad_out);
   else
-    return beam_core<NW, BLOCK, T>(ec, n, so, has_bound, sigma, L, scratch, flag, tid, bad_in,
-                                   bad_out);
+    return beam_core<NW, BLOCK, T, false, LUT>(ec, n, so, has_bound, sigma, L, scratch, flag, tid,
+                                               bad_in, bad_out);
 }
 }  // namespace fsmi

@@ -18,6 +18,7 @@ struct fsmi_ctx_s {
   uint32_t* d_status = nullptr;   // latched device error bits
   int32_t* d_counters = nullptr;  // work-queue heads, 64 entries
   void* d_work = nullptr;         // grow-only scratch for schedules / partial results
+  void* d_lut = nullptr;          // the look-up tables of FSMI_F_LUT (built per call)
   size_t work_bytes = 0;
   int num_cu = 256;
   std::string last_error;
@@ -76,6 +77,8 @@ hipError_t launch_beam_kernels(hipStream_t st, int num_cu, const EvalConst& ec, 
                                const int64_t* off, const float* occ, const double* bound,
                                const float* sigma, double* mi, const int32_t* sched,
                                uint32_t* status, int wave_max, int max_len);
+hipError_t launch_build_lut(hipStream_t st, double delta_occ, void* out);   // kLutBytes at out
+size_t lut_bytes();
 hipError_t launch_eval_beams(fsmi_ctx ctx, const EvalConst& ec, int64_t n_beams, const int64_t* off,
                              const float* occ, const double* bound, const float* sigma,
                              double* mi, int max_len, int wave_max);

@@ -14,6 +14,7 @@
 #include "beam_dev.h"
 #include "csqmi_dev.h"
 #include "fsmi_internal.h"
+#include "lut_dev.h"
 #include "ray_dev.h"
 
 namespace fsmi {
@@ -31,6 +32,7 @@ struct Pose2dArgs {
   double* mi_beam;         // [n_poses][n_beams]
   int32_t* counter;        // item queue head
   uint32_t* status;
+  const float2* lut;       // the look-up tables in global memory (LUT mode)
 };
 
 // LDS of one wave: region 1 = the walk's tie counts, reused for C (and, in
@@ -49,19 +51,33 @@ __host__ __device__ inline size_t pose2d_lds(int capa, int ecap) {
   return pose2d_region1<T>(capa, ecap) + 8 * (size_t)(ecap + 1) + 4 * (size_t)ecap + 16;
 }
 
-template <typename T, bool CSQ>
-__global__ __launch_bounds__(kWave) void k_poses2d(Pose2dArgs a) {
+// Waves per workgroup: one, or in the look-up-table mode four, which share one
+// copy of the tables in LDS ahead of their own regions.
+template <bool LUT> constexpr int pose2d_waves() { return LUT ? 4 : 1; }
+template <bool LUT> constexpr size_t pose2d_shared() { return LUT ? kLutBytes : 0; }
+template <typename T>
+__host__ __device__ inline size_t pose2d_wave_bytes(int capa, int ecap) {
+  return (pose2d_lds<T>(capa, ecap) + 15) / 16 * 16;
+}
+
+template <typename T, bool CSQ, bool LUT>
+__global__ __launch_bounds__(kWave* pose2d_waves<LUT>()) void k_poses2d(Pose2dArgs a) {
 #pragma clang fp contract(off)
   extern __shared__ __align__(16) char lds[];
-  const int lane = threadIdx.x;
-  char* r1 = lds;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+  if constexpr (LUT) {
+    lut_stage(reinterpret_cast<float2*>(lds), a.lut, threadIdx.x, blockDim.x);
+    __syncthreads();
+  }
+  char* r1 = lds + pose2d_shared<LUT>() + (size_t)wave * pose2d_wave_bytes<T>(a.capa, a.ecap);
   int* tie = reinterpret_cast<int*>(r1);
-  double* sL = reinterpret_cast<double*>(lds + pose2d_region1<T>(a.capa, a.ecap));
+  double* sL = reinterpret_cast<double*>(r1 + pose2d_region1<T>(a.capa, a.ecap));
   float* so = reinterpret_cast<float*>(sL + a.ecap + 1);
   const int64_t n_items = a.n_poses * a.n_beams;
   // runs of items from the queue (guided self-scheduling); k, start and the
   // loop bounds are wave-uniform
-  const int64_t n_waves = gridDim.x;
+  const int64_t n_waves = (int64_t)gridDim.x * pose2d_waves<LUT>();
   int64_t k = run_length(n_items, 0, n_waves);
   for (int64_t start = wave_take64(a.counter, k); start < n_items;
        start = wave_take64(a.counter, k)) {
@@ -117,14 +133,35 @@ __global__ __launch_bounds__(kWave) void k_poses2d(Pose2dArgs a) {
         L.C = r1;
         L.P = sizeof(T) == 4 ? reinterpret_cast<void*>(so + res.skip0)
                              : reinterpret_cast<void*>(r1 + sizeof(T) * (size_t)a.ecap);
+        if constexpr (LUT) L.lut = reinterpret_cast<const float2*>(lds);
         bool bad;
-        v = beam_eval<1, false, T, CSQ>(a.ec, res.n, so + res.skip0, true, a.sigma, L, nullptr, nullptr,
-                                   lane, false, &bad);
+        v = beam_eval<1, false, T, CSQ, LUT>(a.ec, res.n, so + res.skip0, true, a.sigma, L, nullptr,
+                                             nullptr, lane, false, &bad);
         if (bad && lane == 0) latch(a.status, kErrOcc);
       }
       if (lane == 0) a.mi_beam[it] = v;
       wave_sync();
     }
+  }
+}
+
+// The look-up tables of lut_dev.h, computed in FP64 and rounded to FP32.
+__global__ __launch_bounds__(256) void k_build_lut(double delta_occ, float2* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < kLutPhiN) {
+    const double s = (double)kInvSqrtL2E / (double)kLutInvH;   // table step in erfc's argument
+    const double e0 = erfc(i * s);
+    const double e1 = i + 1 < kLutPhiN ? erfc((i + 1) * s) : 0.0;
+    out[i] = make_float2((float)e0, (float)(e1 - e0));
+  } else if (i == kLutPhiN) {
+    out[i] = make_float2(0.0f, 0.0f);
+  } else if (i < kLutEntries) {
+    const int k = i - kLutPhiN - 1;
+    const double ld = log(delta_occ);
+    const double h = 1.0 / (kLutFN - 1);
+    const double f0 = f_cell<double>(delta_occ, ld, k * h);
+    const double f1 = k + 1 < kLutFN ? f_cell<double>(delta_occ, ld, fmin(1.0, (k + 1) * h)) : f0;
+    out[i] = make_float2((float)f0, (float)(f1 - f0));
   }
 }
 
@@ -145,6 +182,15 @@ __global__ void k_reset_counter(int32_t* c) {
 }
 
 }  // namespace
+
+size_t lut_bytes() { return kLutBytes; }
+
+hipError_t launch_build_lut(hipStream_t st, double delta_occ, void* out) {
+  const int n = kLutEntries;
+  hipLaunchKernelGGL(k_build_lut, dim3((n + 255) / 256), dim3(256), 0, st, delta_occ,
+                     reinterpret_cast<float2*>(out));
+  return hipGetLastError();
+}
 
 hipError_t launch_pose_reduce(fsmi_ctx ctx, const double* mi_beam, int64_t n_poses,
                               int64_t n_beams, double* mi_pose) {
@@ -184,23 +230,36 @@ hipError_t launch_eval_poses_2d(fsmi_ctx ctx, const EvalConst& ec, const float* 
   a.mi_beam = mb;
   a.counter = ws ? ws->counter : ctx->d_counters + 8;   // 64-bit head (counters[8..9])
   a.status = ctx->d_status;
-  hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, ctx->stream, a.counter);
+  a.lut = reinterpret_cast<const float2*>(ctx->d_lut);
   const bool fp64 = ec.precision == FSMI_FP64;
-  const size_t lds = fp64 ? pose2d_lds<double>(a.capa, a.ecap) : pose2d_lds<float>(a.capa, a.ecap);
+  const bool lut = (ec.flags & FSMI_F_LUT) != 0;
+  if (lut && (fp64 || ec.variant == FSMI_CSQMI)) return hipErrorInvalidValue;
+  if (lut) {
+    hipError_t e = launch_build_lut(ctx->stream, ec.delta_occ, ctx->d_lut);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, ctx->stream, a.counter);
+  const size_t wb = fp64 ? pose2d_wave_bytes<double>(a.capa, a.ecap)
+                         : pose2d_wave_bytes<float>(a.capa, a.ecap);
+  const int waves = lut ? pose2d_waves<true>() : pose2d_waves<false>();
+  const size_t lds = (lut ? pose2d_shared<true>() : 0) + (size_t)waves * wb;
   if (lds > 150 * 1024) return hipErrorInvalidValue;
-  const int per_cu = std::max<int>(1, std::min<int>(16, (int)((160 * 1024) / (lds + 256))));
-  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(n_items, (int64_t)ctx->num_cu * per_cu));
+  const int per_cu = std::max<int>(1, std::min<int>(16 / waves, (int)((160 * 1024) / (lds + 256))));
+  const int64_t groups = (n_items + waves - 1) / waves;
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(groups, (int64_t)ctx->num_cu * per_cu));
   auto launch = [&](auto kern) {
     (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(kWave), lds, ctx->stream, a);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kWave * waves), lds, ctx->stream, a);
   };
   const bool csq = ec.variant == FSMI_CSQMI;
   if (fp64) {
-    if (csq) launch(k_poses2d<double, true>);
-    else launch(k_poses2d<double, false>);
+    if (csq) launch(k_poses2d<double, true, false>);
+    else launch(k_poses2d<double, false, false>);
+  } else if (lut) {
+    launch(k_poses2d<float, false, true>);
   } else {
-    if (csq) launch(k_poses2d<float, true>);
-    else launch(k_poses2d<float, false>);
+    if (csq) launch(k_poses2d<float, true, false>);
+    else launch(k_poses2d<float, false, false>);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

@@ -150,6 +150,8 @@ fsmi_status fsmi_plan_eval_beams(fsmi_ctx ctx, const fsmi_params* params, int64_
   if (n_beams >= ((int64_t)1 << 31)) return fail(ctx, FSMI_E_CAPACITY, "n_beams >= 2^31");
   if (!off || !occ || !sigma || !mi) return fail(ctx, FSMI_E_INVAL, "off, occ, sigma, mi are required");
   if (wave_max < 0) return fail(ctx, FSMI_E_INVAL, "wave_max < 0");
+  if (params->flags & FSMI_F_LUT)
+    return fail(ctx, FSMI_E_UNSUPPORTED, "FSMI_F_LUT is implemented on 2D fsmi_eval_poses");
   if ((params->flags & FSMI_F_SKIP_ZERO) && !bound)
     return fail(ctx, FSMI_E_INVAL, "FSMI_F_SKIP_ZERO needs explicit boundaries");
   if (ext_mode(params) && !bound)

@@ -27,6 +27,7 @@ FSMI_PLAN_AUTOTUNE, FSMI_PLAN_GRAPH = 1, 2
 FSMI_F_SKIP_ZERO = 1
 FSMI_F_MAX_RANGE = 2
 FSMI_F_RLE_RUNS, FSMI_F_RLE_CELLS = 4, 8
+FSMI_F_LUT = 16
 FSMI_PEAK_COPY, FSMI_PEAK_FMA, FSMI_PEAK_PAIR, FSMI_PEAK_MFMA_BF16 = 0, 1, 2, 3
 
 EXPORTS = ("fsmi_create", "fsmi_destroy", "fsmi_set_stream", "fsmi_sync", "fsmi_last_error",
