@@ -118,9 +118,9 @@ def parse():
     ap.add_argument("--quick", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--sur-maps", type=int, default=32)
-    ap.add_argument("--sur-poses", type=int, default=8192)
-    ap.add_argument("--sur-steps", type=int, default=8000)
+    ap.add_argument("--sur-maps", type=int, default=64)
+    ap.add_argument("--sur-poses", type=int, default=16384)
+    ap.add_argument("--sur-steps", type=int, default=16000)
     ap.add_argument("--sur-stride", type=int, default=2, help="patch cell stride")
     ap.add_argument("--sur-candidates", type=int, default=65536)
     ap.add_argument("--sur-eval-maps", type=int, default=4,

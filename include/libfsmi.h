@@ -356,16 +356,19 @@ fsmi_status fsmi_eval_poses_noalloc(fsmi_ctx ctx, const fsmi_params* params, con
 
 /* ---- a15..a17: learned surrogate, trained on FSMI's own labels ----
    A small conv net predicts a pose's scan MI from a 128 x 128 patch of o
-   around the pose: with cell stride s, patch pixel (iy, ix) is the mean of o
-   over the s x s block (bx - 64 + ix, by - 64 + iy) of cells, where (bx, by) =
-   (floor(floor(x) / s), floor(floor(y) / s)) is the block holding the pose's
-   cell (blocks cut by the map edge average their inside cells; blocks outside
-   the map read 0.5); s = 1 is the plain local patch.  Five 3x3 convs,
+   around the pose, resampled at the pose's continuous position: with cell
+   stride s the map is taken as its s x s block means (blocks cut by the map
+   edge average their inside cells; blocks outside the map read 0.5; s = 1 is
+   the cells themselves), and with (u, v) = (x / s, y / s) the pose in block
+   units, patch pixel (iy, ix) is the bilinear interpolation of the blocks at
+   (u - 64 + ix + 1/2, v - 64 + iy + 1/2), block k centred at k + 1/2: blocks
+   bx - 64 + ix + {0, 1}, by - 64 + iy + {0, 1} with (bx, by) = (floor(floor(x)
+   / s), floor(floor(y) / s)) weighted by (u - bx, v - by).  Five 3x3 convs,
    stride 2, padding 1, ReLU (1-32-64-64-128-128 channels), global average pool,
    FC 128->256, ReLU, FC 256->1, 310465 parameters.  BF16 activations and
    weights on the matrix cores with FP32 accumulation, FP32 master weights and
-   Adam moments.  Labels are standardised with fsmi_sur_fit_label_stats and the
-   loss is the batch-mean squared error.  Surrogate calls take 2D maps and 2D
+   Adam moments.  Labels become regression targets through
+   fsmi_sur_fit_label_stats and the loss is the batch-mean squared error.  Surrogate calls take 2D maps and 2D
    poses ([n][4]); they enqueue on the stream of the context the net was created
    with.  The network is not in the paper: it ranks candidate poses cheaply, and
    fsmi_rank_poses always re-scores its top k with exact FSMI (Thm 1). */
@@ -377,15 +380,22 @@ int64_t fsmi_sur_num_params(void);
 fsmi_status fsmi_sur_create(fsmi_ctx ctx, fsmi_sur* out, uint64_t seed, int32_t max_batch,
                             int32_t patch_stride);
 void fsmi_sur_destroy(fsmi_sur net);
-/* Mean and standard deviation of n device FP64 labels (nats), kept in the net. */
+/* Statistics of n device FP64 labels (nats), kept in the net: their mean and
+   standard deviation, then the mean and standard deviation of
+   e = exp((label - mean) / scale).  A label's regression target is
+   (e - emean) / escale: monotone in the label, with the squared error weighting
+   the upper tail, where a ranking keeps its candidates.  A prediction y reads
+   mean + scale ln(max(y escale + emean, 1e-6)) nats.  A new net holds
+   {0, 1, 0, 1}. */
 fsmi_status fsmi_sur_fit_label_stats(fsmi_sur net, int64_t n, const double* labels);
-fsmi_status fsmi_sur_get_label_stats(fsmi_sur net, double* host_mean_scale /* [2], host */);
+fsmi_status fsmi_sur_get_label_stats(fsmi_sur net,
+                                     double* host_stats /* [4] host: mean, scale, emean, escale */);
 /* pred[n] (device FP32) = predicted MI in nats; any n (processed in batches). */
 fsmi_status fsmi_sur_forward(fsmi_sur net, const fsmi_map* map, int64_t n, const double* poses,
                              float* pred);
 /* Forward and backward of one batch (n <= max_batch) against labels[n] (device
    FP64, nats): gradients are kept in the net; *loss (device FP32, or NULL) gets
-   the standardised MSE.  Deterministic (fixed-order reductions). */
+   the MSE against the targets.  Deterministic (fixed-order reductions). */
 fsmi_status fsmi_sur_backward(fsmi_sur net, const fsmi_map* map, int64_t n, const double* poses,
                               const double* labels, float* loss);
 fsmi_status fsmi_sur_adam_step(fsmi_sur net, float lr, float beta1, float beta2, float eps);

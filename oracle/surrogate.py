@@ -4,14 +4,16 @@ Only the tests and the benchmark's baseline leg use this module.  It shares no
 code with the HIP kernels.  The network (not from the paper; it ranks candidate
 poses before exact FSMI re-scores the best ones):
 
-  patch 128 x 128 of o around the pose (cells, or s x s block means), 0.5
-  outside the map
+  patch 128 x 128 of o around the pose (cells, or s x s block means, 0.5
+  outside the map), bilinearly resampled at the pose's continuous position
   -> 5 x [3x3 conv, stride 2, zero padding 1, ReLU], channels 1-32-64-64-128-128
   -> global average pool -> FC 128->256 -> ReLU -> FC 256->1.
 
 Parameters are one flat FP64 vector in the order
 W1 b1 W2 b2 ... W5 b5 F1 c1 F2 c2, conv weights [co][tap = 3 ky + kx][ci],
-F1 [256][128].  Loss: mean over the batch of (y - (label - mean)/scale)^2.
+F1 [256][128].  Loss: mean over the batch of (y - target(label))^2 with
+target = (exp((label - mean)/scale) - emean)/escale (label_stats); a
+prediction y reads mean + scale ln(y escale + emean) nats.
 
 `q` (identity unless given) is applied to every tensor a reduced-precision
 implementation stores between steps: the input patch, the conv weights, each
@@ -63,21 +65,31 @@ def block_means(grid, s):
 
 
 def patches(grid, poses, stride=1):
-    """[B][128][128][1] patches.  With cell stride s, pixel (iy, ix) is block
-    (bx - 64 + ix, by - 64 + iy) of the s x s block means, (bx, by) = the block
-    holding the pose's cell (floor(floor(x) / s), floor(floor(y) / s)); 0.5
-    outside the map.  s = 1 reads the cells themselves."""
+    """[B][128][128][1] patches, resampled at the pose's continuous position.
+    With cell stride s the map is taken as its s x s block means (s = 1: the
+    cells themselves), block k centred at k + 1/2 in block units, 0.5 outside
+    the map.  With (u, v) = (x / s, y / s) the pose in block units, pixel
+    (iy, ix) is the bilinear interpolation of the blocks at
+    (u - 64 + ix + 1/2, v - 64 + iy + 1/2): blocks bx - 64 + ix + {0, 1},
+    by - 64 + iy + {0, 1}, (bx, by) = (floor(floor(x) / s), floor(floor(y) / s))
+    the block holding the pose's cell, weighted by fx = u - bx, fy = v - by."""
     src = np.asarray(grid, np.float64) if stride == 1 else block_means(grid, stride)
     Y, X = src.shape
-    out = np.full((len(poses), PATCH, PATCH, 1), 0.5)
+    out = np.empty((len(poses), PATCH, PATCH, 1))
     for b, p in enumerate(poses):
-        cx0 = int(np.floor(p[0])) // stride - PATCH // 2
-        cy0 = int(np.floor(p[1])) // stride - PATCH // 2
-        ys = np.arange(cy0, cy0 + PATCH)
-        xs = np.arange(cx0, cx0 + PATCH)
+        bx = int(np.floor(p[0])) // stride
+        by = int(np.floor(p[1])) // stride
+        fx = p[0] / stride - bx
+        fy = p[1] / stride - by
+        ys = np.arange(by - PATCH // 2, by - PATCH // 2 + PATCH + 1)
+        xs = np.arange(bx - PATCH // 2, bx - PATCH // 2 + PATCH + 1)
         vy = (ys >= 0) & (ys < Y)
         vx = (xs >= 0) & (xs < X)
-        out[b][np.ix_(vy, vx)] = src[np.ix_(ys[vy], xs[vx])][..., None]
+        win = np.full((PATCH + 1, PATCH + 1), 0.5)      # blocks, one more row and column
+        win[np.ix_(vy, vx)] = src[np.ix_(ys[vy], xs[vx])]
+        top = (1.0 - fx) * win[:-1, :-1] + fx * win[:-1, 1:]
+        bot = (1.0 - fx) * win[1:, :-1] + fx * win[1:, 1:]
+        out[b, ..., 0] = (1.0 - fy) * top + fy * bot
     return out
 
 
@@ -129,11 +141,36 @@ def forward(flat, x, q=_ident):
     return y, (acts, g, h)
 
 
-def loss_and_grads(flat, x, labels, mean=0.0, scale=1.0, q=_ident):
-    """Batch-mean squared error against standardised labels and its gradient."""
+def label_stats(labels):
+    """(mean, scale, emean, escale): the labels' mean and standard deviation,
+    then those of e = exp((label - mean) / scale)."""
+    lab = np.asarray(labels, np.float64)
+    mean = lab.mean()
+    scale = lab.std() or 1.0
+    e = np.exp((lab - mean) / scale)
+    return mean, scale, e.mean(), (e.std() or 1.0)
+
+
+def target(labels, stats=(0.0, 1.0, 0.0, 1.0)):
+    """Regression target of labels (nats): exp of the standardised label,
+    standardised again."""
+    mean, scale, emean, escale = stats
+    return (np.exp((np.asarray(labels, np.float64) - mean) / scale) - emean) / escale
+
+
+def prediction_nats(y, stats=(0.0, 1.0, 0.0, 1.0)):
+    """The target's inverse: mean + scale ln(y escale + emean), the logarithm's
+    argument clamped to 1e-6 from below."""
+    mean, scale, emean, escale = stats
+    e = np.asarray(y, np.float64) * escale + emean
+    return mean + scale * np.log(np.maximum(e, 1e-6))
+
+
+def loss_and_grads(flat, x, labels, stats=(0.0, 1.0, 0.0, 1.0), q=_ident):
+    """Batch-mean squared error against the labels' targets and its gradient."""
     P = unpack(flat)
     y, (acts, g, h) = forward(flat, x, q)
-    t = (np.asarray(labels, np.float64) - mean) / scale
+    t = target(labels, stats)
     n = len(y)
     L = float(np.mean((y - t) ** 2))
     dy = 2.0 * (y - t) / n

@@ -6,8 +6,10 @@
 // Network (per pose): 128 x 128 patch of o around the pose (cells outside the
 // map read 0.5) -> five 3x3 convolutions, stride 2, padding 1, ReLU
 // (1->32->64->64->128->128 channels; 128 -> 64 -> 32 -> 16 -> 8 -> 4 pixels) ->
-// global average pool -> FC 128->256 -> ReLU -> FC 256->1.  Labels are
-// standardised ((MI - mean)/scale); the loss is the batch-mean squared error.
+// global average pool -> FC 128->256 -> ReLU -> FC 256->1.  The regression
+// target of a label is exp((MI - mean)/scale), standardised (sur_target); the
+// loss is the batch-mean squared error, and predictions are mapped back to
+// nats.
 //
 // Layout: activations NHWC in BF16, conv weights [co][tap][ci] (and a copy
 // [tap][ci][co] for the input-gradient pass) in BF16, FP32 master weights,
@@ -78,10 +80,15 @@ FSMI_DEV bf16x8 zero8() {
 }
 
 // Input of the first layer: patch pixel (iy, ix) of pose b is 0 outside the
-// padded patch (iy or ix outside [0, 128)), else the map's value at cell
-// (block(x) - 64 + ix, block(y) - 64 + iy), 0.5 outside the map.  With cell
-// stride s > 1, `map` is the map of s x s block means and the patch is centred
-// on the block holding the pose's cell; s = 1 reads the map itself.
+// padded patch (iy or ix outside [0, 128)), else the map resampled at the
+// pose's continuous position: with (u, v) = (x / s, y / s) the pose in block
+// units, the bilinear interpolation of the map's blocks (block k centred at
+// k + 1/2, 0.5 outside the map) at (u - 64 + ix + 1/2, v - 64 + iy + 1/2),
+// i.e. blocks (floor(u) - 64 + ix + {0, 1}, floor(v) - 64 + iy + {0, 1})
+// weighted by the pose's fraction (u - floor(u), v - floor(v)) inside its
+// block, the same for every pixel.  So the patch moves with the pose's
+// sub-block position.  With cell stride s > 1, `map` is the map of s x s
+// block means; s = 1 reads the map itself.
 struct PatchSrc {
   const float* map;
   int64_t X, Y;          // dims of `map`
@@ -90,6 +97,23 @@ struct PatchSrc {
   FSMI_DEV int64_t block(double v) const {
     const int64_t c = (int64_t)floor(v);
     return c >= 0 ? c / s : -((-c + s - 1) / s);   // floor(c / s)
+  }
+  // the pose's fraction inside its block along one axis, in [0, 1)
+  FSMI_DEV float frac(double v) const {
+    const double q = v / (double)s;
+    return (float)(q - floor(q));
+  }
+  // block (bx, by) of the map, 0.5 outside (int32: the map has < 2^31 cells)
+  FSMI_DEV float at(int bx, int by) const {
+    const bool on = (unsigned)bx < (unsigned)X && (unsigned)by < (unsigned)Y;
+    const float m = map[on ? bx + (int)X * by : 0];
+    return on ? m : 0.5f;
+  }
+  // the resampled pixel from the four blocks around it (bx, by = the lower ones)
+  FSMI_DEV float bilinear(int bx, int by, float fx, float fy) const {
+    const float a = at(bx, by), b = at(bx + 1, by), c = at(bx, by + 1), d = at(bx + 1, by + 1);
+    const float top = fmaf(fx, b - a, a), bot = fmaf(fx, d - c, c);
+    return fmaf(fy, bot - top, top);
   }
 };
 
@@ -290,17 +314,16 @@ FSMI_DEV void gather_window(const PatchSrc& src, int64_t tile, const WinOffs& w,
   const int64_t b = tile >> 4;
   const int oy0 = kT2 * (int)((tile >> 2) & 3), ox0 = kT2 * (int)(tile & 3);
   const int py0 = 4 * oy0 - 3, px0 = 4 * ox0 - 3;   // patch window origin
-  const int cx0 = (int)src.block(src.poses[4 * b]) - kPatch / 2 + px0;
-  const int cy0 = (int)src.block(src.poses[4 * b + 1]) - kPatch / 2 + py0;
-  const int X = (int)src.X, Y = (int)src.Y;
+  const double x = src.poses[4 * b], y = src.poses[4 * b + 1];
+  const int cx0 = (int)src.block(x) - kPatch / 2 + px0;
+  const int cy0 = (int)src.block(y) - kPatch / 2 + py0;
+  const float fx = src.frac(x), fy = src.frac(y);
 #pragma unroll
   for (int k = 0; k < kPatchPer; ++k) {
-    const int cx = cx0 + w.c[k], cy = cy0 + w.r[k];
-    const bool on_map = (unsigned)cx < (unsigned)X && (unsigned)cy < (unsigned)Y;
-    const float m = src.map[on_map ? cx + X * cy : 0];
+    const float m = src.bilinear(cx0 + w.c[k], cy0 + w.r[k], fx, fy);
     const bool in_patch = (unsigned)(py0 + w.r[k]) < (unsigned)kPatch &&
                           (unsigned)(px0 + w.c[k]) < (unsigned)kPatch;
-    v[k] = in_patch ? (on_map ? m : 0.5f) : 0.0f;
+    v[k] = in_patch ? m : 0.0f;
   }
 }
 
@@ -557,16 +580,16 @@ __global__ __launch_bounds__(256, WG1 ? 4 : 1) void k_conv_dgrad(int64_t nq, int
       // staged column c = patch column c - 1, read from the map (PatchSrc)
       const int64_t b0 = base / (HOUT * HOUT);
       const int a0 = (int)((base / HOUT) % HOUT);
-      const int64_t mx0 = src.block(src.poses[4 * b0]) - kPatch / 2;
-      const int64_t my0 = src.block(src.poses[4 * b0 + 1]) - kPatch / 2;
+      const double x = src.poses[4 * b0], y = src.poses[4 * b0 + 1];
+      const int mx0 = (int)src.block(x) - kPatch / 2;
+      const int my0 = (int)src.block(y) - kPatch / 2;
+      const float fx = src.frac(x), fy = src.frac(y);
       for (int e = tid; e < 9 * SROW; e += 256) {
         const int r = e / SROW, c = e - r * SROW;
         const int iy = 4 * a0 - 1 + r, ix = c - 1;
         float v = 0.0f;
-        if ((unsigned)iy < (unsigned)kPatch && (unsigned)ix < (unsigned)kPatch) {
-          const int64_t mx = mx0 + ix, my = my0 + iy;
-          v = mx >= 0 && mx < src.X && my >= 0 && my < src.Y ? src.map[mx + src.X * my] : 0.5f;
-        }
+        if ((unsigned)iy < (unsigned)kPatch && (unsigned)ix < (unsigned)kPatch)
+          v = src.bilinear(mx0 + ix, my0 + iy, fx, fy);
         sPt[e] = (bf16)v;
       }
     }
@@ -956,6 +979,15 @@ __global__ __launch_bounds__(256) void k_head_fwd(int64_t n, const bf16* __restr
   }
 }
 
+// The regression target of a label (nats): e = exp((label - mean) / scale),
+// the standardised label passed through exp so that the squared error weights
+// the upper tail (the candidates a ranking keeps) more than the bulk, then
+// standardised again, (e - emean) / escale.  Monotone, so the ranking it
+// learns is the labels' ranking.  stats = {mean, scale, emean, escale}.
+FSMI_DEV float sur_target(double label, const double* stats) {
+  return (float)((exp((label - stats[0]) / stats[1]) - stats[2]) / stats[3]);
+}
+
 // Head backward for one pose: dy = 2 (y - target) / n; dh = dy F2 [h > 0];
 // dg = F1^T dh; d_act5[p][c] = dg[c] / 16 [act5 > 0].
 __global__ __launch_bounds__(256) void k_head_bwd(int64_t n, const float* __restrict__ ypred,
@@ -970,7 +1002,7 @@ __global__ __launch_bounds__(256) void k_head_bwd(int64_t n, const float* __rest
   __shared__ float dh[kHid];
   const int t = threadIdx.x;
   for (int64_t b = blockIdx.x; b < n; b += gridDim.x) {
-    const float target = (float)((labels[b] - stats[0]) / stats[1]);
+    const float target = sur_target(labels[b], stats);
     const float dy = 2.0f * (ypred[b] - target) / (float)n;
     if (t == 0) dysave[b] = dy;
     const float h = hsave[b * kHid + t];
@@ -1030,7 +1062,7 @@ __global__ __launch_bounds__(256) void k_head_wgrad_part(
       const bool ok = t < nb;
       sdy[t] = ok ? dysave[s0 + t] : 0.0f;
       float ev = 0.0f;
-      if (ok && kt == 0) ev = ypred[s0 + t] - (float)((labels[s0 + t] - stats[0]) / stats[1]);
+      if (ok && kt == 0) ev = ypred[s0 + t] - sur_target(labels[s0 + t], stats);
       se[t] = ev;
     }
     __syncthreads();
@@ -1159,19 +1191,49 @@ __global__ void k_label_stats(int64_t n, const double* labels, double* stats) {
   q = wave_sum(q);
   if ((t & 63) == 0) red[t >> 6] = q;
   __syncthreads();
+  double v = 0.0;
+  for (int k = 0; k < (int)(blockDim.x >> 6); ++k) v += red[k];
+  v = sqrt(v / (double)n);
+  const double scale = v > 0.0 ? v : 1.0;
+  __syncthreads();
+  // mean and standard deviation of e = exp((label - mean) / scale)
+  double se = 0.0;
+  for (int64_t i = t; i < n; i += blockDim.x) se += exp((labels[i] - mean) / scale);
+  se = wave_sum(se);
+  if ((t & 63) == 0) red[t >> 6] = se;
+  __syncthreads();
+  double emean = 0.0;
+  for (int k = 0; k < (int)(blockDim.x >> 6); ++k) emean += red[k];
+  emean /= (double)n;
+  __syncthreads();
+  double qe = 0.0;
+  for (int64_t i = t; i < n; i += blockDim.x) {
+    const double d = exp((labels[i] - mean) / scale) - emean;
+    qe += d * d;
+  }
+  qe = wave_sum(qe);
+  if ((t & 63) == 0) red[t >> 6] = qe;
+  __syncthreads();
   if (t == 0) {
-    double v = 0.0;
-    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) v += red[k];
-    v = sqrt(v / (double)n);
+    double ve = 0.0;
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) ve += red[k];
+    ve = sqrt(ve / (double)n);
     stats[0] = mean;
-    stats[1] = v > 0.0 ? v : 1.0;
+    stats[1] = scale;
+    stats[2] = emean;
+    stats[3] = ve > 0.0 ? ve : 1.0;
   }
 }
 
-// Predictions in nats: y * scale + mean.
+// Predictions in nats, the target's inverse: mean + scale ln(y escale + emean)
+// (the logarithm's argument clamped to 1e-6 from below: a prediction at or
+// under the exponential's range reads as 13.8 scales under the mean).
 __global__ void k_destandardise(int64_t n, const float* y, const double* stats, float* out) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i < n) out[i] = (float)((double)y[i] * stats[1] + stats[0]);
+  if (i < n) {
+    const double e = (double)y[i] * stats[3] + stats[2];
+    out[i] = (float)(log(fmax(e, 1e-6)) * stats[1] + stats[0]);
+  }
 }
 
 // One 16x16x32 product through the matrix core, A and B row-major (diagnostic).
@@ -1514,7 +1576,7 @@ fsmi_status fsmi_sur_create(fsmi_ctx ctx, fsmi_sur* out, uint64_t seed, int32_t 
   }
   hipLaunchKernelGGL(k_sur_init, dim3((kNumParams + 255) / 256), dim3(256), 0, ctx->stream, seed,
                      net->P, net->M, net->V);
-  const double st[2] = {0.0, 1.0};
+  const double st[4] = {0.0, 1.0, 0.0, 1.0};
   (void)hipMemcpy(net->stats, st, sizeof(st), hipMemcpyHostToDevice);
   if (cast_weights(net) != hipSuccess || hipStreamSynchronize(ctx->stream) != hipSuccess) {
     sur_free(net);
@@ -1626,9 +1688,9 @@ fsmi_status fsmi_sur_get_grads(fsmi_sur net, float* dst) {
                         net->ctx->stream) == hipSuccess ? FSMI_OK : FSMI_E_DEVICE;
 }
 
-fsmi_status fsmi_sur_get_label_stats(fsmi_sur net, double* host_mean_scale) {
-  if (!net || !host_mean_scale) return FSMI_E_INVAL;
-  return hipMemcpy(host_mean_scale, net->stats, 2 * sizeof(double), hipMemcpyDeviceToHost) ==
+fsmi_status fsmi_sur_get_label_stats(fsmi_sur net, double* host_stats) {
+  if (!net || !host_stats) return FSMI_E_INVAL;
+  return hipMemcpy(host_stats, net->stats, 4 * sizeof(double), hipMemcpyDeviceToHost) ==
                  hipSuccess ? FSMI_OK : FSMI_E_DEVICE;
 }
 
@@ -1637,7 +1699,7 @@ fsmi_status fsmi_sur_save(fsmi_sur net, const char* path) {
   if (!net || !path) return FSMI_E_INVAL;
   if (hipStreamSynchronize(net->ctx->stream) != hipSuccess) return FSMI_E_DEVICE;
   std::vector<float> buf(3 * (size_t)kNumParams);
-  double st[2];
+  double st[4];
   if (hipMemcpy(buf.data(), net->P, sizeof(float) * kNumParams, hipMemcpyDeviceToHost) != hipSuccess ||
       hipMemcpy(buf.data() + kNumParams, net->M, sizeof(float) * kNumParams, hipMemcpyDeviceToHost) != hipSuccess ||
       hipMemcpy(buf.data() + 2 * kNumParams, net->V, sizeof(float) * kNumParams, hipMemcpyDeviceToHost) != hipSuccess ||
@@ -1645,7 +1707,7 @@ fsmi_status fsmi_sur_save(fsmi_sur net, const char* path) {
     return FSMI_E_DEVICE;
   FILE* f = fopen(path, "wb");
   if (!f) return FSMI_E_INVAL;
-  const uint32_t hdr[5] = {0x46534D49u, 2u, (uint32_t)net->step, (uint32_t)kNumParams,
+  const uint32_t hdr[5] = {0x46534D49u, 3u, (uint32_t)net->step, (uint32_t)kNumParams,
                            (uint32_t)net->stride};
   bool ok = fwrite(hdr, sizeof(hdr), 1, f) == 1 && fwrite(st, sizeof(st), 1, f) == 1 &&
             fwrite(buf.data(), sizeof(float), buf.size(), f) == buf.size();
@@ -1658,9 +1720,9 @@ fsmi_status fsmi_sur_load(fsmi_sur net, const char* path) {
   FILE* f = fopen(path, "rb");
   if (!f) return FSMI_E_INVAL;
   uint32_t hdr[5];
-  double st[2];
+  double st[4];
   std::vector<float> buf(3 * (size_t)kNumParams);
-  bool ok = fread(hdr, sizeof(hdr), 1, f) == 1 && hdr[0] == 0x46534D49u && hdr[1] == 2u &&
+  bool ok = fread(hdr, sizeof(hdr), 1, f) == 1 && hdr[0] == 0x46534D49u && hdr[1] == 3u &&
             hdr[3] == (uint32_t)kNumParams && hdr[4] >= 1u && hdr[4] <= 64u &&
             fread(st, sizeof(st), 1, f) == 1 &&
             fread(buf.data(), sizeof(float), buf.size(), f) == buf.size();

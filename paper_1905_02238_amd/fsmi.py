@@ -439,9 +439,10 @@ class Surrogate:
                                                      _ptr(labels, torch.float64, "labels")))
 
     def label_stats(self):
-        out = (C.c_double * 2)()
+        """(mean, scale, emean, escale) of the fitted labels."""
+        out = (C.c_double * 4)()
         self._chk(self._lib.fsmi_sur_get_label_stats(self.handle, C.cast(out, C.c_void_p)))
-        return float(out[0]), float(out[1])
+        return tuple(float(v) for v in out)
 
     def forward(self, map_occ, poses, pred=None):
         self.ctx._stream()

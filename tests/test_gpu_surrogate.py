@@ -1,6 +1,8 @@
 """The learned surrogate on the GPU: matrix-core layout, forward and gradients
 against the FP64 reference, deterministic training, checkpoints, and what the
 network gains in the exact-rescore ranking path."""
+import math
+
 import numpy as np
 import pytest
 import torch
@@ -64,16 +66,30 @@ def test_forward_and_gradients_match_fp64_reference(ctx, stride, batch):
     grid, lab = wl["grid"], wl["labels"]
     poses = _poses_near_and_inside(lab, batch, 5)
     net = F.Surrogate(ctx, seed=7, max_batch=batch, patch_stride=stride)
+    # the output bias lifted so every output is positive: with the label
+    # statistics at (0, 1) a prediction is ln y nats, so exp gives y back
+    c2 = [o for name, o, _ in S.layout() if name == "c2"][0]
     flat = net.params().double().cpu().numpy()
+    flat[c2] = 3.0
+    net.set_params(torch.from_numpy(flat.astype(np.float32)).cuda())
     x = S.patches(grid, poses, stride=stride)
     y_ref, _ = S.forward(flat, x)
     y_bf, _ = S.forward(flat, x, q=_bf16)
+    assert np.min(y_ref) > 0.1
     pred = net.forward(dev(grid), dev(poses))
     torch.cuda.synchronize()
-    y = pred.double().cpu().numpy()
-    # FP32 vs FP64 summation order can move a stored BF16 activation by one
-    # ulp (2^-8 relative), which shows up at ~1e-4 of the output scale.
-    assert np.max(np.abs(y - y_bf)) <= 1e-3 * np.max(np.abs(y_bf)) + 1e-6
+    y = np.exp(pred.double().cpu().numpy())
+    # FP32 vs FP64 summation order can move a stored BF16 value by one ulp
+    # (2^-8 relative) wherever it sits near a rounding boundary.  How far that
+    # moves the output depends on the inputs, so the bar is the reference's
+    # own spread: the same BF16 reference with every stored tensor perturbed
+    # by up to 1e-7 relative (FP32 rounding) before it is rounded.
+    spread = 0.0
+    for sd in (1, 2):
+        rr = np.random.default_rng(sd)
+        y_p, _ = S.forward(flat, x, q=lambda a: _bf16(np.asarray(a) * (1 + rr.uniform(-1e-7, 1e-7, np.shape(a)))))
+        spread = max(spread, float(np.max(np.abs(y_p - y_bf))))
+    assert np.max(np.abs(y - y_bf)) <= 2.0 * spread + 1e-4 * np.max(np.abs(y_bf)) + 1e-6
     assert np.max(np.abs(y - y_ref)) <= 2e-2 * np.max(np.abs(y_ref)) + 1e-6
     labels = np.random.default_rng(1).normal(size=batch)
     loss = net.backward(dev(grid), dev(poses), dev(labels))
@@ -130,8 +146,9 @@ def _labelled(ctx, seeds, n_poses, size=1024):
     return out
 
 
-def _train(ctx, data, seed, steps, batch=128, lr=1e-3):
-    net = F.Surrogate(ctx, seed=seed, max_batch=batch)
+def _train(ctx, data, seed, steps, batch=128, lr=1e-3, stride=1, cosine=False):
+    net = F.Surrogate(ctx, seed=seed, max_batch=max(batch, 8192) if cosine else batch,
+                      patch_stride=stride)
     net.fit_label_stats(torch.cat([d[2] for d in data]))
     losses = []
     rng = np.random.default_rng(seed)
@@ -140,7 +157,7 @@ def _train(ctx, data, seed, steps, batch=128, lr=1e-3):
         sel = torch.from_numpy(rng.choice(p.shape[0], batch, replace=False)).cuda()
         pb, lb = p[sel].contiguous(), mi[sel].contiguous()
         loss = net.backward(g, pb, lb)
-        net.adam_step(lr)
+        net.adam_step(float(lr * 0.5 * (1.0 + math.cos(math.pi * it / steps))) if cosine else lr)
         losses.append(loss)
     torch.cuda.synchronize()
     return net, [float(l[0]) for l in losses]
@@ -174,20 +191,29 @@ def test_checkpoint_resume_is_exact(ctx, tmp_path):
 
 
 def test_surrogate_gain_over_random_candidates(ctx):
-    """Trained on FSMI labels of other maps, on each held-out map the network
-    ranks the candidates with a clearly positive rank correlation, and its top
-    prediction, re-scored exactly, loses less MI to the true best pose than a
-    random candidate does (the ablation).  The regret of its top 1 % against a
-    random 1 % is printed; on these flat MI landscapes it is close to random
-    and not asserted.  The top 1 % are the k largest predictions, re-scored
-    exactly."""
+    """The benchmark's recipe (1M labels: 64 maps x 16 384 poses, patch stride
+    2, 16 000 Adam steps of 128 with a cosine learning rate) and its four
+    held-out maps of 65 536 candidates (the timed map and three more): on each,
+    the network ranks the candidates with a clearly positive rank correlation,
+    and its top 1 % (the k largest predictions, re-scored exactly) loses less
+    MI to the true best pose than a random 1 % re-scored the same way (the
+    ablation, mean of 200 draws); so does its top prediction against a random
+    candidate.  Training is deterministic, so these are the benchmark's own
+    figures."""
     print("[gpu] surrogate gain test", flush=True)
-    train = _labelled(ctx, [W.SEED_BASE + 110 + i for i in range(16)], 4096)
-    net, losses = _train(ctx, train, seed=3, steps=2000, batch=128)
+    train = _labelled(ctx, [W.SEED_BASE + 100 + i for i in range(64)], 16384, size=2048)
+    net, losses = _train(ctx, train, seed=3, steps=16000, batch=128, stride=2, cosine=True)
+    del train
     from scipy.stats import spearmanr
     bd = dev(W.beam_dirs_2d(360))
-    k = 41
-    for (g, p, mi) in _labelled(ctx, [W.SEED_BASE + 198, W.SEED_BASE + 199], 4096):
+    n = 65536
+    k = n // 100 + 1
+    wl = W.grid_large(n_poses=n, yaw="zero")
+    g0, p0 = dev(wl["grid"]), dev(wl["poses"])
+    mi0, _ = ctx.fsmi_eval_poses(F.params(), g0, p0, bd, 3.0, 400.0)
+    held = [(g0, p0, mi0)] + _labelled(ctx, [W.SEED_BASE + 200 + i for i in range(3)], n,
+                                       size=2048)
+    for (g, p, mi) in held:
         idx, mi_top, pred = ctx.fsmi_rank_poses(F.params(), net, g, p, bd, 3.0, 400.0, k,
                                                 want_pred=True)
         torch.cuda.synchronize()
@@ -212,3 +238,4 @@ def test_surrogate_gain_over_random_candidates(ctx):
               f"final loss {np.mean(losses[-100:]):.3f}", flush=True)
         assert rho > 0.4
         assert top1 < rand1
+        assert ours_k < rand_k
