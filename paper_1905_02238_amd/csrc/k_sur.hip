@@ -31,6 +31,7 @@ namespace fsmi {
 
 typedef __bf16 bf16;
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 // ---------------------------------------------------------------------------
@@ -70,6 +71,13 @@ int64_t sur_num_params() { return kNumParams; }
 // ---------------------------------------------------------------------------
 FSMI_DEV floatx4 mfma(bf16x8 a, bf16x8 b, floatx4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+// v_mfma_f32_16x16x16_bf16: as above with K = 16, lane l holding A[l % 16][4 (l / 16) + 0..3]
+// and B[4 (l / 16) + 0..3][l % 16].
+typedef short shortx4 __attribute__((ext_vector_type(4)));
+FSMI_DEV floatx4 mfma16(bf16x4 a, bf16x4 b, floatx4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(shortx4, a),
+                                                   __builtin_bit_cast(shortx4, b), c, 0, 0, 0);
 }
 FSMI_DEV bf16x8 load8(const bf16* p) { return *reinterpret_cast<const bf16x8*>(p); }
 FSMI_DEV bf16x8 zero8() {
@@ -278,8 +286,9 @@ __global__ __launch_bounds__(256) void k_conv_fwd_lds(int64_t npix, const bf16* 
 // and both layers' ReLU sign words for the backward pass: a tile owns the
 // conv1 pixels of window rows and columns 1 .. 16 (conv1 rows 2 oy0 .. 2 oy0 +
 // 15; row 0 of the window belongs to the tile above), so each conv1 pixel is
-// stored once.  The products are the same MFMA with the same operands as the
-// stand-alone first convolution, so the values match it.
+// stored once.  conv1's nine taps take one v_mfma_f32_16x16x16_bf16 per
+// channel tile (K = 16: lane group g holds taps 4 g .. 4 g + 3, read from the
+// patch window with one 2-byte LDS read each).
 // ---------------------------------------------------------------------------
 constexpr int kT2 = 8;                 // conv2 tile edge (output pixels)
 constexpr int kT1 = 2 * kT2 + 1;       // 17: conv1 window edge
@@ -348,16 +357,22 @@ __global__ __launch_bounds__(256) void k_conv12_fwd(int64_t n_tiles, PatchSrc sr
     const int co = e8 / 36, rem = e8 - co * 36, tap = rem >> 2, gg = rem & 3;
     *reinterpret_cast<bf16x8*>(sW2 + ((tap * 4 + gg) * 64 + co) * 8) = load8(W2 + e8 * 8);
   }
-  // A operand of conv1: A[n][k] = W1[16t + n][k], k = tap 8g + q (< 9)
-  bf16x8 w1[2];
+  // A operand of conv1 (16 x 16 x 16): A[n][k] = W1[16t + n][k], k = tap 4g + q
+  // (< 9); the lane's taps sit at window offsets toff[q] from a pixel's base
+  bf16x4 w1[2];
+  int toff[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int tap = 4 * g + q;
+    toff[q] = tap < 9 ? (tap / 3) * kTP + tap % 3 : -1;
+  }
   float bias1[2][4], bias2[4][4];
 #pragma unroll
   for (int t = 0; t < 2; ++t) {
-    w1[t] = zero8();
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int tap = 8 * g + q;
-      if (tap < 9) w1[t][q] = W1[(16 * t + i) * 9 + tap];
+    for (int q = 0; q < 4; ++q) {
+      const int tap = 4 * g + q;
+      w1[t][q] = tap < 9 ? W1[(16 * t + i) * 9 + tap] : (bf16)0.0f;
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) bias1[t][r] = b1[16 * t + 4 * g + r];
@@ -401,19 +416,9 @@ __global__ __launch_bounds__(256) void k_conv12_fwd(int64_t n_tiles, PatchSrc sr
       const bool pv = c1_pr[u] >= 0;
       const int pr = pv ? c1_pr[u] : 0, pc = c1_pc[u];
       const int base = c1_base[u];
-      bf16x8 x = zero8();   // B operand: taps 8g .. 8g + 7 of pixel p
-      if (g == 0) {
-        x[0] = sP[base];
-        x[1] = sP[base + 1];
-        x[2] = sP[base + 2];
-        x[3] = sP[base + kTP];
-        x[4] = sP[base + kTP + 1];
-        x[5] = sP[base + kTP + 2];
-        x[6] = sP[base + 2 * kTP];
-        x[7] = sP[base + 2 * kTP + 1];
-      } else if (g == 1) {
-        x[0] = sP[base + 2 * kTP + 2];
-      }
+      bf16x4 x;   // B operand: taps 4g .. 4g + 3 of pixel p
+#pragma unroll
+      for (int q = 0; q < 4; ++q) x[q] = toff[q] >= 0 ? sP[base + toff[q]] : (bf16)0.0f;
       const int y1 = 2 * oy0 - 1 + pr, x1 = 2 * ox0 - 1 + pc;
       const bool inside = pv && y1 >= 0 && y1 < 64 && x1 >= 0 && x1 < 64;
       const bool owned = SAVE && pv && pr >= 1 && pc >= 1;   // implies inside
@@ -422,7 +427,7 @@ __global__ __launch_bounds__(256) void k_conv12_fwd(int64_t n_tiles, PatchSrc sr
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
         // D[n][p]: channels 16t + 4g + r of pixel p
-        const floatx4 d = mfma(w1[t], x, floatx4{0.f, 0.f, 0.f, 0.f});
+        const floatx4 d = mfma16(w1[t], x, floatx4{0.f, 0.f, 0.f, 0.f});
         float o[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
