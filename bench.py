@@ -50,25 +50,97 @@ SLOTS_PER_PAIR = 14.5
 # 131087 KiB for 262144 KiB read, WRITE_SIZE 262144 KiB for 262144 KiB written).
 # They describe the kernel built from the sources hashed here; with any other
 # sources the bench reports traffic as null.
-TRAFFIC = {"fetch_kib": 1.45403e+07, "write_kib": 48734.5,
-           "fetch_scale": 262144.0 / 131087.3, "write_scale": 1.0,
-           "sources_sha256": "b842b1c6c865b7b24d369f072d9735672a71d6bbab6a92dab3d83126a8239d09"}
+TRAFFIC = {"fetch_kib": 14473762.25, "write_kib": 48776.125,
+           "fetch_scale": 262144.0 / 131087.8125, "write_scale": 1.0,
+           "sources_sha256": "2ee2a730d606972c2f23490515820eefb38516ec533f8f6c07112c9b279d6f75"}
 TRAFFIC_SOURCES = ("paper_1905_02238_amd/csrc/k_pose.hip", "paper_1905_02238_amd/csrc/beam_dev.h",
                    "paper_1905_02238_amd/csrc/ray_dev.h", "paper_1905_02238_amd/csrc/fsmi_dev.h",
-                   "paper_1905_02238_amd/csrc/fsmi_internal.h", "paper_1905_02238_amd/build.py")
+                   "paper_1905_02238_amd/csrc/fsmi_internal.h", "paper_1905_02238_amd/csrc/lut_dev.h",
+                   "paper_1905_02238_amd/csrc/csqmi_dev.h", "paper_1905_02238_amd/build.py")
+
+
+def sources_sha256(files):
+    import hashlib
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 
 
 def measured_traffic():
     """Bytes per launch from the counters, or None if the kernel sources changed."""
-    import hashlib
-    h = hashlib.sha256()
-    for f in TRAFFIC_SOURCES:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
-    if h.hexdigest() != TRAFFIC["sources_sha256"]:
+    if sources_sha256(TRAFFIC_SOURCES) != TRAFFIC["sources_sha256"]:
         return None
     return 1024.0 * (TRAFFIC["fetch_kib"] * TRAFFIC["fetch_scale"]
                      + TRAFFIC["write_kib"] * TRAFFIC["write_scale"])
+
+
+# Counter figures of every path, from the summaries under profiles/ (each file
+# gives the rocprofv3 commands): kernel time from --kernel-trace --stats, VALU
+# busy = SQ_ACTIVE_INST_VALU / (256 CUs x GRBM_GUI_ACTIVE of one XCD), MFMA
+# busy = SQ_VALU_MFMA_BUSY_CYCLES / (1024 SIMDs x the same cycles), HBM-side
+# traffic = FETCH_SIZE + WRITE_SIZE scaled by a plain copy's readings, and
+# each path's fraction of the roof that binds it.  They describe the library
+# built from the sources hashed here; with other sources the bench reports
+# them as stale.
+COUNTER_SOURCES = tuple(sorted(
+    os.path.relpath(os.path.join(dp, f), ROOT)
+    for dp, _, fs in os.walk(os.path.join(ROOT, "paper_1905_02238_amd", "csrc"))
+    for f in fs if f.endswith((".hip", ".h")))) + ("paper_1905_02238_amd/build.py",)
+COUNTER_PROFILES = {
+    "sources_sha256": "4f7cc79c3d5c7433121f3b440d9c603f514ffcd556a4ba50c24b1ac66ab96c36",
+    "paths": {
+        "2d_exact": {"profile": "profiles/k_poses2d_exact_grid2048_4096x360.md",
+                     "kernel_ms": 135.19, "valu_busy": 1.291, "mfma_busy": 0.0,
+                     "fetch_write_GBps": 225, "bound": "alu",
+                     "frac": 0.81, "frac_of": "13-slot pair peak 3.02e12 pairs/s"},
+        "2d_approx_delta9": {"profile": "profiles/k_poses2d_approx_delta9_grid2048_4096x360.md",
+                             "kernel_ms": 14.59, "valu_busy": 1.246, "mfma_busy": 0.0,
+                             "fetch_write_GBps": 2185, "bound": "alu",
+                             "frac": 0.30, "frac_of": "13-slot pair peak, tail evaluations"},
+        "2d_uniform_h6": {"profile": "profiles/k_poses2d_uniform_h6_grid2048_4096x360.md",
+                          "kernel_ms": 7.06, "valu_busy": 0.959, "mfma_busy": 0.0,
+                          "fetch_write_GBps": 4525, "bound": "alu",
+                          "frac": 0.959, "frac_of": "VALU busy"},
+        "2d_exact_lut": {"profile": "profiles/k_poses2d_exact_lut_grid2048_4096x360.md",
+                         "kernel_ms": 91.14, "valu_busy": 1.023, "mfma_busy": 0.0,
+                         "fetch_write_GBps": 335, "bound": "alu",
+                         "frac": 1.023, "frac_of": "VALU busy"},
+        "3d_exact": {"profile": "profiles/k_poses3d_voxels512_1024x16384.md",
+                     "kernel_ms": 45.43, "valu_busy": 0.765, "mfma_busy": 0.218,
+                     "fetch_write_GBps": 3809, "bound": "alu", "frac": 0.765,
+                     "frac_of": "VALU busy"},
+        "3d_approx_delta6": {"profile": "profiles/k_poses3d_voxels512_1024x16384.md",
+                             "kernel_ms": 34.22, "valu_busy": 0.985, "mfma_busy": 0.0,
+                             "fetch_write_GBps": 5139, "bound": "alu", "frac": 0.985,
+                             "frac_of": "VALU busy"},
+        "3d_uniform_h4": {"profile": "profiles/k_poses3d_voxels512_1024x16384.md",
+                          "kernel_ms": 26.70, "valu_busy": 0.857, "mfma_busy": 0.0,
+                          "fetch_write_GBps": 6510, "bound": "alu", "frac": 0.857,
+                          "frac_of": "VALU busy"},
+        "uneven_100k_exact": {"profile": "profiles/k_eval_fused_uneven_100k.md",
+                              "kernel_ms": 1.45, "valu_busy": 0.34, "mfma_busy": 0.34,
+                              "fetch_write_GBps": 116, "bound": "mfma", "frac": 0.34,
+                              "frac_of": "FP32 matrix peak 7.86e13 MAC/s over the launch "
+                                         "(0.50 ms of matrix work in 1.45 ms)"},
+        "surrogate_forward": {"profile": "profiles/surrogate_forward_rank_65536.md",
+                              "kernel_ms": 1.94, "valu_busy": 0.53, "mfma_busy": 0.147,
+                              "fetch_write_GBps": 5765, "bound": "mfma", "frac": 0.124,
+                              "frac_of": "2.5 PFLOP/s BF16 dense (per batch of 8192; conv3 "
+                                         "at 72 % of HBM peak)"},
+        "surrogate_training": {"profile": "profiles/surrogate_training_step_1024.md",
+                               "kernel_ms": 1.164, "valu_busy": 0.46, "mfma_busy": 0.09,
+                               "fetch_write_GBps": None, "bound": "mfma", "frac": 0.077,
+                               "frac_of": "2.5 PFLOP/s BF16 dense (per step of 1024)"},
+    }}
+
+
+def counter_profiles():
+    """The committed counter figures, or a note that the library changed since."""
+    if sources_sha256(COUNTER_SOURCES) != COUNTER_PROFILES["sources_sha256"]:
+        return {"stale": True, "note": "library sources changed since the counters were taken"}
+    return COUNTER_PROFILES["paths"]
 
 
 # Surrogate forward, multiply-adds x 2 per pose: five 3x3 stride-2 convolutions
@@ -128,7 +200,8 @@ def parse():
     ap.add_argument("--profile-step", action="store_true",
                     help="for counter runs: one plain 256 MiB device copy (the traffic "
                          "calibration), then exactly one timed-workload step, nothing else")
-    ap.add_argument("--profile-variant", choices=("exact", "approx", "uniform"), default="exact",
+    ap.add_argument("--profile-variant", choices=("exact", "approx", "uniform", "exact_lut"),
+                    default="exact",
                     help="with --profile-step: the FSMI variant of that one step (Approx "
                          "Delta = 9, Uniform H = 6)")
     ap.add_argument("--profile-surrogate", action="store_true",
@@ -156,6 +229,16 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def calibration_copy(torch, dev):
+    """A plain device copy of 256 MiB (reads 256 MiB, writes 256 MiB): under
+    rocprofv3 --pmc its FETCH_SIZE and WRITE_SIZE give the counters' scale."""
+    src = torch.empty(64 << 20, dtype=torch.float32, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -172,6 +255,7 @@ def main():
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
 
     if args.profile_surrogate:
+        calibration_copy(torch, dev)
         wl = W.grid_large(n_poses=65536, yaw="zero")
         g, p, bd = t(wl["grid"]), t(wl["poses"]), t(wl["beam_dir"])
         net = F.Surrogate(ctx, seed=3, max_batch=8192)
@@ -183,6 +267,7 @@ def main():
         log("[bench] surrogate profile done")
         return
     if args.profile_train:
+        calibration_copy(torch, dev)
         occ, lab = W.room_grid(2048, W.SEED_BASE + 100, split_extent=160, unknown_frac=0.30)
         g = t(occ)
         p = t(W.poses_in_free_space_2d(lab, 8192, W.SEED_BASE + 100))
@@ -200,8 +285,10 @@ def main():
         net.close()
         return
     if args.profile_3d:
+        calibration_copy(torch, dev)
         vw = W.voxels_large(n_poses=1024)
         vx, vp, vb = t(vw["vox"]), t(vw["poses"]), t(vw["beam_dir"])
+        # one launch each of exact, Approx (Delta 6) and Uniform (H 4), in that order
         for prm in (F.params(), F.params(variant=F.FSMI_APPROX, trunc_delta=6),
                     F.params(variant=F.FSMI_UNIFORM, uniform_h=4)):
             ctx.fsmi_eval_poses(prm, vx, vp, vb, vw["sigma"], vw["R"], vw["w"])
@@ -222,6 +309,7 @@ def main():
         log("[bench] table profile done")
         return
     if args.profile_uneven:
+        calibration_copy(torch, dev)
         off, occ, sg = W.uneven_beams(100000, seed=W.SEED_BASE + 3)
         plan = F.Plan(ctx, F.params(), t(off), t(occ), t(sg), autotune=True, graph=True)
         for _ in range(5):
@@ -241,13 +329,10 @@ def main():
     prm = F.params(variant=F.FSMI_EXACT)
 
     if args.profile_step:
-        src = torch.empty(64 << 20, dtype=torch.float32, device=dev).fill_(1.0)
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)                      # reads 256 MiB, writes 256 MiB
-        torch.cuda.synchronize()
+        calibration_copy(torch, dev)
         pv = {"exact": prm, "approx": F.params(variant=F.FSMI_APPROX, trunc_delta=wl["Delta"]),
-              "uniform": F.params(variant=F.FSMI_UNIFORM, uniform_h=wl["H"])}[args.profile_variant]
+              "uniform": F.params(variant=F.FSMI_UNIFORM, uniform_h=wl["H"]),
+              "exact_lut": F.params(flags=F.FSMI_F_LUT)}[args.profile_variant]
         ctx.fsmi_eval_poses(pv, grid, poses, bdir, sigma, R)
         torch.cuda.synchronize()
         ctx.fsmi_sync()
@@ -338,6 +423,7 @@ def main():
         ceil[key] = rate / 1e12
         ceil[key.split("_")[0] + "_" + key.split("_")[1] + "_clock_MHz"] = mhz
     out["measured_ceilings"] = ceil
+    out["counter_profiles"] = counter_profiles()
     roof = out["roofline"]
     roof["measured_pair_ceiling"] = ceil["phi_pair_Tpairs_per_s"] * 1e12
     roof["frac_of_measured_pair_ceiling"] = achieved / roof["measured_pair_ceiling"]

@@ -58,3 +58,14 @@ def test_matrix_core_work_counts_the_kernel_loop():
     # every pair is covered: at least n^2 multiply-adds
     assert all(bench.unit_mfma_macs([n]) >= n * n for n in lens)
     assert abs(bench.MFMA_F32_MAC_PEAK - 7.86432e13) < 1e6
+
+
+def test_counter_figures_name_their_profiles_and_go_stale(monkeypatch):
+    """Each committed counter figure names a profile summary that exists, and
+    the figures are withheld once the library's sources differ from the ones
+    they were taken on."""
+    for name, d in bench.COUNTER_PROFILES["paths"].items():
+        assert os.path.exists(os.path.join(ROOT, d["profile"])), name
+        assert d["bound"] in ("alu", "mfma", "hbm")
+    monkeypatch.setitem(bench.COUNTER_PROFILES, "sources_sha256", "0" * 64)
+    assert bench.counter_profiles()["stale"] is True
