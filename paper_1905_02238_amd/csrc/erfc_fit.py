@@ -2,7 +2,7 @@
 
 Form: erfc(x) = t * exp(h(t) - x^2) with t = 1 / (1 + a x), x >= 0, where
 h(t) = ln(erfc(x) / t) + x^2 is smooth on t in (0, 1] (it tends to
-ln(a / sqrt(pi)) - ln(1 - t) as x grows).  A polynomial P of degree 7 in t
+ln(a / sqrt(pi)) - ln(1 - t) as x grows).  A polynomial P of degree 6 in t
 is fitted to h by iteratively reweighted least squares (Lawson's algorithm,
 which converges to the minimax fit) on x in [0, 10]; erfc(10) = 2e-45 is
 already below the smallest FP32 denormal.  An absolute error e in P is a
@@ -21,7 +21,7 @@ adds a few ulp of the exponent on top).
 import numpy as np
 from scipy.special import erfcx
 
-DEG = 7
+DEG = 6
 X_MAX = 10.0
 L2E = 1.4426950408889634
 
@@ -61,7 +61,7 @@ def max_rel_err(a, c):
 
 def main():
     best = None
-    for a in np.round(np.arange(0.25, 0.40, 0.002), 3):
+    for a in np.round(np.arange(0.30, 0.50, 0.002), 3):
         c = lawson(a)
         c32 = c.astype(np.float32).astype(np.float64)
         e = max_rel_err(a, c32)
@@ -72,7 +72,7 @@ def main():
     c2 = (c * L2E).astype(np.float32)
     print(f"// degree {DEG}, a = {a}, max relative error {e:.3g} on [0, {X_MAX}]")
     print(f"constexpr float kErfcA = {float(a2)!r}f;")
-    print("constexpr float kErfcP[8] = {" + ", ".join(f"{float(v)!r}f" for v in c2) + "};")
+    print(f"constexpr float kErfcP[{DEG + 1}] = {{" + ", ".join(f"{float(v)!r}f" for v in c2) + "};")
 
 
 if __name__ == "__main__":

@@ -32,7 +32,8 @@ def test_traffic_is_dropped_when_sources_change(monkeypatch):
 
 
 def test_slot_accounting_is_the_documented_one():
-    assert bench.SLOTS_PER_PAIR == 14.5
+    assert bench.SLOTS_PER_PAIR == 13.5
+    assert bench.PAIR_ISSUE_SLOTS == 12
     assert abs(bench.ALU_PEAK_TSLOT - 39.3216) < 1e-9
     assert bench.SUR_FLOP_PER_POSE == 73204224
 
