@@ -322,11 +322,15 @@ fsmi_status fsmi_eval_poses(fsmi_ctx ctx, const fsmi_params* params, const fsmi_
    leave C_k while P(e_j) uses every cell.  mi_traj[k] = the sum over its
    states; mi_state [n_states] and mi_beam [n_states][n_beams] (FP64, device)
    may be NULL.  EXACT, APPROX or UNIFORM, FP32 or FP64, no flags, no
-   sigma_slope (FSMI_E_INVAL otherwise).  Trajectories are evaluated in order
-   on the stream; the context's work area holds 8 bytes per map cell plus the
-   per-beam and per-state sums not kept by the caller.  Bad offsets latch
-   FSMI_E_NUMERIC and give NaN; a state outside the map as in fsmi_eval_poses.
-   Range limits as fsmi_eval_poses on 2D maps. */
+   sigma_slope (FSMI_E_INVAL otherwise).  The call reads traj_off back to the
+   host once (it waits for the work before it on the stream) and evaluates the
+   trajectories in groups of up to 64, one stamp map of 8 bytes per map cell
+   each, within 1 GiB (at least one map); the context's work area holds those
+   maps plus the per-beam and per-state sums not kept by the caller.  A
+   trajectory whose offsets are invalid gives NaN and the call latches
+   FSMI_E_NUMERIC (states that no valid trajectory covers keep MI 0); a state
+   outside the map as in fsmi_eval_poses.  Range limits as fsmi_eval_poses on
+   2D maps. */
 fsmi_status fsmi_eval_trajectories(fsmi_ctx ctx, const fsmi_params* params, const fsmi_map* map,
                                    int64_t n_traj, const int64_t* traj_off, int64_t n_states,
                                    const double* poses, int64_t n_beams, const double* beam_dir,

@@ -3,14 +3,17 @@
 //
 // A candidate trajectory is a sequence of states (2D poses) in travel order;
 // its MI is the sum of its states' scan MI, with each cell's information
-// counted only at the first state whose beams cross it.  Trajectories are
-// evaluated one after another on the stream, each in two persistent passes of
-// one wave per (state, beam):
-//   1. stamp: walk every beam and raise a per-cell 64-bit stamp to
-//      (k << 32) | (2^32 - 1 - t) with an atomic max, so after the pass a cell
-//      crossed by trajectory k holds k and the first state t that crosses it
-//      (later trajectories' stamps exceed every earlier one, so the map-sized
-//      stamp array is cleared once per call, not per trajectory);
+// counted only at the first state whose beams cross it.  The host reads the
+// CSR offsets once, sets aside trajectories whose offsets are invalid (their
+// MI is NaN and the call latches), and evaluates the rest in groups of up to
+// G trajectories, G stamp maps side by side (G from a 1 GiB budget, at most
+// 64).  Each group takes two persistent passes of one wave per (state, beam)
+// item of all its trajectories:
+//   1. stamp: walk every beam and raise the cell's 64-bit stamp in its
+//      trajectory's map to (k << 32) | (2^32 - 1 - t) with an atomic max, so
+//      after the pass a cell crossed by trajectory k holds k and the first
+//      state t that crosses it (a later trajectory in the same slot has a
+//      larger k, so the maps are cleared once per call, not per group);
 //   2. evaluate: walk again, gather o and mark cell i counted iff its stamp
 //      names this state, and run the beam engine with that mask (the f terms
 //      of uncounted cells leave C_k; every cell still shapes P(e_j)).
@@ -19,28 +22,36 @@
 #include <math.h>
 
 #include <algorithm>
+#include <vector>
 
 #include "beam_dev.h"
 #include "fsmi_internal.h"
 #include "ray_dev.h"
 
 namespace fsmi {
+// Stamp maps side by side: at most kTrajSlots trajectories per group, within
+// kStampBudget bytes of maps.
+constexpr int64_t kTrajSlots = 64;
+constexpr int64_t kStampBudget = (int64_t)1 << 30;
 hipError_t launch_pose_reduce(fsmi_ctx ctx, const double* mi_beam, int64_t n_poses,
                               int64_t n_beams, double* mi_pose);
 namespace {
 
+// A group's table: record j < ng = {trajectory k, first state s0, states,
+// items before slot j}; record ng holds the group's item count in its last
+// field.
 struct TrajArgs {
   EvalConst ec;
   const float* map;
   int64_t X, Y;
-  const int64_t* traj_off;   // [n_traj + 1], device
-  int64_t k;                 // the trajectory of this launch
+  const int64_t* gtab;       // [(ng + 1) * 4], device
+  int ng;
   int64_t n_states, n_beams;
   const double* poses;       // [n_states][4] x, y, cos, sin
   const double* beam_dir;    // [n_beams][2]
   double sigma, R;
   int capa, ecap;
-  unsigned long long* stamp; // [X * Y]
+  unsigned long long* stamp; // [G][X * Y]: slot j of the group uses map j
   double* mi_beam;           // [n_states][n_beams]
   int32_t* counter;          // 64-bit queue head
   uint32_t* status;
@@ -81,13 +92,7 @@ __global__ __launch_bounds__(kWave) void k_traj2d(TrajArgs a) {
   double* sL = reinterpret_cast<double*>(lds + traj_region1<T>(a.capa, a.ecap));
   float* so = reinterpret_cast<float*>(sL + a.ecap + 1);
   unsigned char* sm = reinterpret_cast<unsigned char*>(so + a.ecap);
-  const int64_t s0 = uniform_i64(a.traj_off[a.k]);
-  const int64_t s1 = uniform_i64(a.traj_off[a.k + 1]);
-  if (s0 < 0 || s1 < s0 || s1 > a.n_states) {
-    if (STAMP && blockIdx.x == 0 && lane == 0) latch(a.status, kErrLen);
-    return;
-  }
-  const int64_t n_items = (s1 - s0) * a.n_beams;
+  const int64_t n_items = uniform_i64(a.gtab[4 * a.ng + 3]);
   const int64_t n_waves = gridDim.x;
   int64_t kr = run_length(n_items, 0, n_waves);
   for (int64_t start = wave_take64(a.counter, kr); start < n_items;
@@ -95,7 +100,18 @@ __global__ __launch_bounds__(kWave) void k_traj2d(TrajArgs a) {
     const int64_t it_end = min<int64_t>(start + kr, n_items);
     kr = run_length(n_items, it_end, n_waves);
     for (int64_t it = start; it < it_end; ++it) {
-      const int64_t t = it / a.n_beams, b = it - t * a.n_beams;
+      // the item's slot: the last record whose item prefix is <= it
+      int lo = 0, hi = a.ng;
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (uniform_i64(a.gtab[4 * mid + 3]) <= it) lo = mid;
+        else hi = mid;
+      }
+      const int64_t k = uniform_i64(a.gtab[4 * lo]);
+      const int64_t s0 = uniform_i64(a.gtab[4 * lo + 1]);
+      const int64_t local = it - uniform_i64(a.gtab[4 * lo + 3]);
+      const int64_t t = local / a.n_beams, b = local - t * a.n_beams;
+      unsigned long long* stamp = a.stamp + (int64_t)lo * a.X * a.Y;
       const double* ps = a.poses + 4 * (s0 + t);
       const double bx = a.beam_dir[2 * b], by = a.beam_dir[2 * b + 1];
       const double m1 = ps[2] * bx, m2 = ps[3] * by, m3 = ps[3] * bx, m4 = ps[2] * by;
@@ -107,7 +123,7 @@ __global__ __launch_bounds__(kWave) void k_traj2d(TrajArgs a) {
       };
       const Dda2dResult res =
           dda2d_wave(a.X, a.Y, ps[0], ps[1], dx, dy, a.R, a.capa, a.ecap, tie, emit, lane);
-      const unsigned long long key = traj_key(a.k, t);
+      const unsigned long long key = traj_key(k, t);
       if constexpr (STAMP) {
         if (res.n < 0) {
           if (lane == 0) latch(a.status, res.n == -1 ? kErrPose : kErrCap);
@@ -117,7 +133,7 @@ __global__ __launch_bounds__(kWave) void k_traj2d(TrajArgs a) {
           const int hi = res.skip0 + res.n;
           for (int i = res.skip0 + lane; i < hi; i += kWave) {
             const int64_t c = i == 0 ? res.cell0 : (int64_t)sc[i];
-            if (c >= 0) atomicMax(&a.stamp[c], key);
+            if (c >= 0) atomicMax(&stamp[c], key);
           }
         }
         wave_sync();
@@ -139,7 +155,7 @@ __global__ __launch_bounds__(kWave) void k_traj2d(TrajArgs a) {
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
               o[u] = a.map[c[u] >= 0 ? c[u] : 0];
-              st[u] = a.stamp[c[u] >= 0 ? c[u] : 0];
+              st[u] = stamp[c[u] >= 0 ? c[u] : 0];
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
@@ -153,7 +169,7 @@ __global__ __launch_bounds__(kWave) void k_traj2d(TrajArgs a) {
           if (lane == 0) {
             sL[0] = 0.0;
             so[0] = a.map[res.cell0];
-            sm[0] = a.stamp[res.cell0] == key ? 1 : 0;
+            sm[0] = stamp[res.cell0] == key ? 1 : 0;
             sL[res.skip0 + res.n] = res.lend;
           }
           wave_sync();
@@ -172,6 +188,10 @@ __global__ __launch_bounds__(kWave) void k_traj2d(TrajArgs a) {
       }
     }
   }
+}
+
+__global__ void k_latch(uint32_t* status, uint32_t bits) {
+  if (threadIdx.x == 0) latch(status, bits);
 }
 
 __global__ void k_traj_reset64(int32_t* c) {
@@ -212,21 +232,58 @@ hipError_t launch_eval_trajectories_2d(fsmi_ctx ctx, const EvalConst& ec, const 
                                        const double* beam_dir, double sigma, double R,
                                        double* mi_traj, double* mi_state, double* mi_beam) {
   if (n_traj <= 0) return hipSuccess;
-  // work area: the stamp map, then the per-beam and per-state sums the caller
-  // does not keep, each on a 256-byte boundary
+  // the offsets, read once: the groups are laid out on the host
+  std::vector<int64_t> off((size_t)n_traj + 1);
+  hipError_t e = hipMemcpyAsync(off.data(), traj_off, sizeof(int64_t) * off.size(),
+                                hipMemcpyDeviceToHost, ctx->stream);
+  if (e != hipSuccess) return e;
+  e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return e;
+  std::vector<int64_t> valid;
+  bool any_bad = false;
+  for (int64_t k = 0; k < n_traj; ++k) {
+    if (off[k] >= 0 && off[k + 1] >= off[k] && off[k + 1] <= n_states) valid.push_back(k);
+    else any_bad = true;
+  }
+  const int64_t cells = X * Y;
+  const int64_t G = std::max<int64_t>(1, std::min<int64_t>({kTrajSlots, (kStampBudget / 8) / cells,
+                                                            (int64_t)valid.size()}));
+  const int64_t n_groups = ((int64_t)valid.size() + G - 1) / G;
+  // group tables: (G + 1) records of 4 per group
+  std::vector<int64_t> tab((size_t)std::max<int64_t>(n_groups, 1) * (G + 1) * 4, 0);
+  for (int64_t gi = 0; gi < n_groups; ++gi) {
+    int64_t* rec = tab.data() + gi * (G + 1) * 4;
+    const int64_t j0 = gi * G, j1 = std::min<int64_t>(j0 + G, (int64_t)valid.size());
+    int64_t items = 0;
+    for (int64_t j = j0; j < j1; ++j) {
+      const int64_t k = valid[(size_t)j];
+      int64_t* r = rec + (j - j0) * 4;
+      r[0] = k;
+      r[1] = off[k];
+      r[2] = off[k + 1] - off[k];
+      r[3] = items;
+      items += r[2] * n_beams;
+    }
+    rec[(j1 - j0) * 4 + 3] = items;
+  }
+  // work area: G stamp maps, the per-beam and per-state sums the caller does
+  // not keep, the group tables; each on a 256-byte boundary
   auto up = [](size_t b) { return (b + 255) / 256 * 256; };
-  const size_t stamp_b = up((size_t)X * (size_t)Y * 8);
+  const size_t stamp_b = up((size_t)G * (size_t)cells * 8);
   const size_t beam_b = mi_beam ? 0 : up((size_t)n_states * (size_t)n_beams * 8);
   const size_t state_b = mi_state ? 0 : up((size_t)n_states * 8);
-  hipError_t e = ensure_work(ctx, stamp_b + beam_b + state_b + 256);
+  const size_t tab_b = up(tab.size() * 8);
+  e = ensure_work(ctx, stamp_b + beam_b + state_b + tab_b + 256);
   if (e != hipSuccess) return e;
   char* w = reinterpret_cast<char*>(ctx->d_work);
+  int64_t* d_tab = reinterpret_cast<int64_t*>(w + stamp_b + beam_b + state_b);
+  e = hipMemcpyAsync(d_tab, tab.data(), tab.size() * 8, hipMemcpyHostToDevice, ctx->stream);
+  if (e != hipSuccess) return e;
   TrajArgs a;
   a.ec = ec;
   a.map = map;
   a.X = X;
   a.Y = Y;
-  a.traj_off = traj_off;
   a.n_states = n_states;
   a.n_beams = n_beams;
   a.poses = poses;
@@ -245,8 +302,14 @@ hipError_t launch_eval_trajectories_2d(fsmi_ctx ctx, const EvalConst& ec, const 
   if (lds > 150 * 1024) return hipErrorInvalidValue;
   const int per_cu = std::max<int>(1, std::min<int>(16, (int)((160 * 1024) / (lds + 256))));
   const int grid = std::max(1, ctx->num_cu * per_cu);
+  if (any_bad) hipLaunchKernelGGL(k_latch, dim3(1), dim3(64), 0, ctx->stream, a.status, kErrLen);
+  // per-state sums of states no valid trajectory reaches stay zero
+  if (n_states > 0) {
+    e = launch_fill_f64(ctx->stream, n_states * n_beams, 0.0, a.mi_beam);
+    if (e != hipSuccess) return e;
+  }
   {
-    const int64_t n = X * Y;
+    const int64_t n = G * cells;
     const int g = (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 4096));
     hipLaunchKernelGGL(k_fill_u64, dim3(g), dim3(256), 0, ctx->stream, n, a.stamp);
   }
@@ -255,8 +318,9 @@ hipError_t launch_eval_trajectories_2d(fsmi_ctx ctx, const EvalConst& ec, const 
     hipLaunchKernelGGL(k_traj_reset64, dim3(1), dim3(64), 0, ctx->stream, a.counter);
     hipLaunchKernelGGL(kern, dim3(grid), dim3(kWave), lds, ctx->stream, a);
   };
-  for (int64_t k = 0; k < n_traj; ++k) {
-    a.k = k;
+  for (int64_t gi = 0; gi < n_groups; ++gi) {
+    a.gtab = d_tab + gi * (G + 1) * 4;
+    a.ng = (int)(std::min<int64_t>((gi + 1) * G, (int64_t)valid.size()) - gi * G);
     if (fp64) {
       launch(k_traj2d<double, true>);
       launch(k_traj2d<double, false>);
@@ -267,8 +331,10 @@ hipError_t launch_eval_trajectories_2d(fsmi_ctx ctx, const EvalConst& ec, const 
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  e = launch_pose_reduce(ctx, a.mi_beam, n_states, n_beams, ms);
-  if (e != hipSuccess) return e;
+  if (n_states > 0) {
+    e = launch_pose_reduce(ctx, a.mi_beam, n_states, n_beams, ms);
+    if (e != hipSuccess) return e;
+  }
   const int g = (int)std::max<int64_t>(1, std::min<int64_t>(n_traj, 8192));
   hipLaunchKernelGGL(k_traj_reduce, dim3(g), dim3(kWave), 0, ctx->stream, ms, traj_off, n_traj,
                      n_states, mi_traj);
