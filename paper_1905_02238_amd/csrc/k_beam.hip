@@ -67,10 +67,37 @@ FSMI_DEV void process_beam(const BeamArgs& a, int b, char* lds, int cap, double*
     float* so;
     const CoreLds L = carve<T>(lds, cap, &so);
     const bool has_bound = a.bound != nullptr && a.ec.variant != FSMI_UNIFORM;
-    for (int i = tid; i < n; i += G) so[i] = a.occ[o0 + i];
+    // eight loads in flight per lane before any is stored: the beam's
+    // occupancies come from HBM, and one round trip per element would
+    // serialise a short beam's whole load
+    for (int base = 0; base < n; base += 8 * G) {
+      float v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int i = base + u * G + tid;
+        v[u] = a.occ[o0 + min(i, n - 1)];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int i = base + u * G + tid;
+        if (i < n) so[i] = v[u];
+      }
+    }
     if (has_bound) {
       const double* bp = a.bound + o0 + b;
-      for (int i = tid; i <= n; i += G) L.A[i] = bp[i];
+      for (int base = 0; base <= n; base += 4 * G) {
+        double v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int i = base + u * G + tid;
+          v[u] = bp[min(i, n)];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int i = base + u * G + tid;
+          if (i <= n) L.A[i] = v[u];
+        }
+      }
     }
     Grp<kNW, BLOCK>::sync();
     bool bad;
