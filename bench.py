@@ -580,6 +580,11 @@ def _rel(got, ref):
     return np.abs(got - ref) / np.maximum(np.abs(ref), 1e-30)
 
 
+def _cpu_rate(n, seconds, threads, sample):
+    return {"beams_per_s": n / max(seconds, 1e-9), "seconds": seconds, "threads": threads,
+            "sample": sample}
+
+
 def _err_stats(rel, bar, **kw):
     d = dict(kw)
     d.update({"results": int(rel.size), "max_rel": float(rel.max()),
@@ -639,6 +644,11 @@ def oracle_leg(out, gpu, wl, W, args, ctx, F, t):
     log(f"[bench] cpu oracle, one core: {k1 * n_beams / c1:.0f} beams/s")
 
     rep = {}
+    # the oracle's rate on each workload it checks, beside the timed one's
+    cpu_cfg = {"exact_2d": {"beams_per_s": out["cpu_baseline"]["value"], "threads": thr},
+               "exact_2d_one_core": {"beams_per_s": out["cpu_baseline"]["single_core"]["value"],
+                                     "threads": 1}}
+    out["cpu_oracle_per_workload"] = cpu_cfg
     # the timed launch's per-pose results; per-beam results of the same kernel on the sample
     got_pose = gpu["exact"][:k].cpu().numpy()
     grid, bdir = t(wl["grid"]), t(wl["beam_dir"])
@@ -656,6 +666,8 @@ def oracle_leg(out, gpu, wl, W, args, ctx, F, t):
             t1 = time.perf_counter()
             rp, rb = O.eval_poses_2d(v, wl["grid"], wl["poses"], wl["beam_dir"], sig, R,
                                      threads=thr, want_beams=True, **kw)
+            cpu_cfg[name] = _cpu_rate(int(rb.size), time.perf_counter() - t1, thr,
+                                      "every beam of the timed workload")
             gp, gbm = gpu[name]
             rep[name] = _err_stats(_rel(gbm.cpu().numpy(), rb), 1e-5, poses=len(rp),
                                    max_rel_pose=float(_rel(gp.cpu().numpy(), rp).max()))
@@ -678,11 +690,16 @@ def oracle_leg(out, gpu, wl, W, args, ctx, F, t):
             _rel(gpu["exact_range_noise_max_range"][:kp].cpu().numpy(), rp), 1e-5, poses=kp)
         off, occ, sg = W.uneven_beams(100000, seed=W.SEED_BASE + 3)
         nb = 2000
+        t1 = time.perf_counter()
         rb = O.eval_beams(O.EXACT, off[:nb + 1], occ[:off[nb]], sg[:nb], threads=thr)
+        cpu_cfg["uneven_100k_exact"] = _cpu_rate(nb, time.perf_counter() - t1, thr, "first 2000 beams")
         rep["uneven_exact"] = _err_stats(_rel(gpu["uneven"][:nb].cpu().numpy(), rb), 1e-5, beams=nb)
         small = W.grid_small()
+        t1 = time.perf_counter()
         rp, rb = O.eval_poses_2d(O.EXACT, small["grid"], small["poses"], small["beam_dir"],
-                                 small["sigma"], small["R"], threads=thr)
+                                 small["sigma"], small["R"], threads=1)
+        cpu_cfg["grid_small_exact"] = _cpu_rate(int(rb.size), time.perf_counter() - t1, 1,
+                                                "the 200 x 200 pose, 60 beams, one thread")
         for name, bar in (("grid_small_fp64_us", 1e-12), ("grid_small_fp32_us", 1e-5)):
             gp, gbm = gpu[name]
             rep[name.replace("_us", "")] = _err_stats(
@@ -696,6 +713,8 @@ def oracle_leg(out, gpu, wl, W, args, ctx, F, t):
             t1 = time.perf_counter()
             rp, rb = O.eval_poses_3d(exact, vw["vox"], vw["poses"][:n3], vw["beam_dir"], vw["sigma"],
                                      vw["R"], vw["w"], threads=thr, **kw)
+            cpu_cfg[name] = _cpu_rate(int(rb.size), time.perf_counter() - t1, thr,
+                                      f"first {n3} poses x {rb.shape[1]} beams")
             gp, gbm = gpu[name]
             rep[name] = _err_stats(_rel(gbm[:n3].cpu().numpy(), rb), 1e-5, poses=n3,
                                    max_rel_pose=float(_rel(gp[:n3].cpu().numpy(), rp).max()))
@@ -713,7 +732,10 @@ def oracle_leg(out, gpu, wl, W, args, ctx, F, t):
             for name, v, kw in (("approx_csqmi", O.CSQMI, {"Delta": 3}),
                                 ("approx_fsmi", O.APPROX, {"Delta": 3}),
                                 ("uniform_fsmi", O.UNIFORM, {"H": eH})):
+                t1 = time.perf_counter()
                 rb = O.eval_beams(v, eoff, eocc, esg, bound=bnd, threads=thr, **kw)
+                cpu_cfg[f"paper_beam_{kind}_{name}"] = _cpu_rate(
+                    len(rb), time.perf_counter() - t1, thr, "20 000 beams of 100 cells")
                 g_ = gpu[f"e2_{kind}_{name}"].cpu().numpy()
                 rep[f"paper_beam_{kind}_{name}"] = (
                     _log_err_stats(g_, rb, beams=len(rb)) if v == O.CSQMI
@@ -1000,6 +1022,16 @@ def surrogate_leg(ctx, F, W, t, timed, args):
                                                          for a in acc)),
                       "per_map": [[a["regret"], a["random_1pct_regret"]] for a in acc]})
     res["seed_study"] = study
+    if not args.no_cpu:
+        # the FP64 reference forward (oracle/surrogate.py) on the host, for scale
+        from oracle import surrogate as S
+        flat = net.params().double().cpu().numpy()
+        ph = wl["poses"][:64]
+        t1 = time.perf_counter()
+        S.forward(flat, S.patches(wl["grid"], ph, stride=args.sur_stride))
+        dt_cpu = time.perf_counter() - t1
+        res["cpu_fp64_forward"] = {"poses_per_s": len(ph) / dt_cpu, "poses": len(ph),
+                                   "seconds": dt_cpu, "kind": "oracle (numpy FP64)"}
     log("[bench] surrogate seed study (seed: mean top-1% regret vs random, maps better): "
         + ", ".join(f"{d['seed']}: {d['regret']:.4f} vs {d['random_1pct_regret']:.4f}, "
                     f"{d['maps_better_than_random']}/4" for d in study))

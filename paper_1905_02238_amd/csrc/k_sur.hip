@@ -954,32 +954,54 @@ __global__ void k_wgrad_reduce_final(const float* __restrict__ runs, int nrun, f
 
 // ---------------------------------------------------------------------------
 // Head: global average pool, FC 128->256, ReLU, FC 256->1 (FP32 VALU).
-// One workgroup (256 threads) per pose.
+// kHeadPoses poses per workgroup of 256 threads: thread t is hidden unit t and
+// reads its FC1 weight row once for all the workgroup's poses.  Per pose the
+// sums run in the same order as one pose at a time would take them.
 // ---------------------------------------------------------------------------
+constexpr int kHeadPoses = 16;
 __global__ __launch_bounds__(256) void k_head_fwd(int64_t n, const bf16* __restrict__ act5,
                                                   const float* __restrict__ P, float* __restrict__ gsave,
                                                   float* __restrict__ hsave, float* __restrict__ ypred) {
-  __shared__ float g[kFeat];
-  __shared__ float red[4];
+  __shared__ float g[kHeadPoses][kFeat];
+  __shared__ float red[kHeadPoses][4];
   const int t = threadIdx.x;
-  for (int64_t b = blockIdx.x; b < n; b += gridDim.x) {
-    if (t < kFeat) {
+  for (int64_t b0 = (int64_t)blockIdx.x * kHeadPoses; b0 < n; b0 += (int64_t)gridDim.x * kHeadPoses) {
+    const int nb = (int)min<int64_t>(kHeadPoses, n - b0);
+    for (int e = t; e < nb * kFeat; e += 256) {
+      const int pb = e / kFeat, c = e - pb * kFeat;
+      const int64_t b = b0 + pb;
       float s = 0.0f;
-      for (int q = 0; q < 16; ++q) s += (float)act5[(b * 16 + q) * kFeat + t];
-      g[t] = s * (1.0f / 16.0f);
-      if (gsave) gsave[b * kFeat + t] = g[t];
+      for (int q = 0; q < 16; ++q) s += (float)act5[(b * 16 + q) * kFeat + c];
+      g[pb][c] = s * (1.0f / 16.0f);
+      if (gsave) gsave[b * kFeat + c] = g[pb][c];
     }
     __syncthreads();
-    float h = P[kC1 + t];
+    float h[kHeadPoses];
+    const float bias = P[kC1 + t];
+#pragma unroll
+    for (int pb = 0; pb < kHeadPoses; ++pb) h[pb] = bias;
     const float* w = P + kF1 + t * kFeat;
-    for (int c = 0; c < kFeat; ++c) h = fmaf(w[c], g[c], h);
-    h = h > 0.0f ? h : 0.0f;
-    if (hsave) hsave[b * kHid + t] = h;
-    float y = P[kF2 + t] * h;
-    y = wave_sum(y);
-    if ((t & 63) == 0) red[t >> 6] = y;
+    for (int c = 0; c < kFeat; c += 4) {
+      const float4 w4 = *reinterpret_cast<const float4*>(w + c);
+#pragma unroll
+      for (int pb = 0; pb < kHeadPoses; ++pb) {
+        h[pb] = fmaf(w4.x, g[pb][c], h[pb]);
+        h[pb] = fmaf(w4.y, g[pb][c + 1], h[pb]);
+        h[pb] = fmaf(w4.z, g[pb][c + 2], h[pb]);
+        h[pb] = fmaf(w4.w, g[pb][c + 3], h[pb]);
+      }
+    }
+    const float f2 = P[kF2 + t];
+#pragma unroll
+    for (int pb = 0; pb < kHeadPoses; ++pb) {
+      const float hp = h[pb] > 0.0f ? h[pb] : 0.0f;
+      if (pb < nb && hsave) hsave[(b0 + pb) * kHid + t] = hp;
+      float y = f2 * hp;
+      y = wave_sum(y);
+      if ((t & 63) == 0) red[pb][t >> 6] = y;
+    }
     __syncthreads();
-    if (t == 0) ypred[b] = ((red[0] + red[1]) + (red[2] + red[3])) + P[kC2];
+    if (t < nb) ypred[b0 + t] = ((red[t][0] + red[t][1]) + (red[t][2] + red[t][3])) + P[kC2];
     __syncthreads();
   }
 }
@@ -1499,7 +1521,7 @@ static hipError_t sur_fwd_batch(fsmi_sur net, int64_t nb, PatchSrc src, bool sav
   conv_fwd<2>(net, nb, save);
   conv_fwd<3>(net, nb, save);
   conv_fwd<4>(net, nb, save);
-  const int grid = (int)std::min<int64_t>(nb, 65535);
+  const int grid = (int)std::min<int64_t>((nb + kHeadPoses - 1) / kHeadPoses, 65535);
   hipLaunchKernelGGL(k_head_fwd, dim3(grid), dim3(256), 0, net->ctx->stream, nb, net->act[5], net->P,
                      save ? net->gsave : nullptr, save ? net->hsave : nullptr, net->ypred);
   return hipGetLastError();
