@@ -102,9 +102,13 @@ struct PatchSrc {
   int64_t X, Y;          // dims of `map`
   const double* poses;   // [n][4]
   int s;                 // cell stride
-  FSMI_DEV int64_t block(double v) const {
-    const int64_t c = (int64_t)floor(v);
-    return c >= 0 ? c / s : -((-c + s - 1) / s);   // floor(c / s)
+  // floor(floor(v) / s), exact in FP64 for |v| < 2^53 (a quotient of
+  // integers below 2^53 that is not whole lies at least 1/s from the next
+  // whole number, more than its rounding error), held within +-(2^31 - 2^10)
+  // so that window arithmetic stays in int32
+  FSMI_DEV int block(double v) const {
+    const double q = floor(floor(v) / (double)s);
+    return (int)fmin(fmax(q, -2147482624.0), 2147482624.0);
   }
   // the pose's fraction inside its block along one axis, in [0, 1)
   FSMI_DEV float frac(double v) const {
@@ -119,7 +123,10 @@ struct PatchSrc {
   }
   // the resampled pixel from the four blocks around it (bx, by = the lower ones)
   FSMI_DEV float bilinear(int bx, int by, float fx, float fy) const {
-    const float a = at(bx, by), b = at(bx + 1, by), c = at(bx, by + 1), d = at(bx + 1, by + 1);
+    return lerp2(at(bx, by), at(bx + 1, by), at(bx, by + 1), at(bx + 1, by + 1), fx, fy);
+  }
+  // a, b: blocks (bx, by), (bx + 1, by); c, d: the row below
+  static FSMI_DEV float lerp2(float a, float b, float c, float d, float fx, float fy) {
     const float top = fmaf(fx, b - a, a), bot = fmaf(fx, d - c, c);
     return fmaf(fy, bot - top, top);
   }
@@ -140,10 +147,19 @@ __global__ void k_pool_map(const float* __restrict__ map, int64_t X, int64_t Y, 
   }
 }
 
-// Two floats as packed BF16 (round to nearest even), low half first.
+// Two floats as packed BF16 (round to nearest even), low half first: one
+// two-lane conversion instruction.
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float floatx2 __attribute__((ext_vector_type(2)));
 FSMI_DEV uint32_t pack2(float a, float b) {
-  const bf16 x = (bf16)a, y = (bf16)b;
-  return (uint32_t)__builtin_bit_cast(uint16_t, x) | ((uint32_t)__builtin_bit_cast(uint16_t, y) << 16);
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector((floatx2{a, b}), bf16x2));
+}
+
+// ReLU as an integer max on the bits (one instruction): a float with its sign
+// bit set, -0 included, is a negative int and becomes +0.
+FSMI_DEV float relu(float v) {
+  const int b = __builtin_bit_cast(int, v);
+  return __builtin_bit_cast(float, b > 0 ? b : 0);
 }
 
 // ReLU signs of a stored activation for the next layer's input-gradient pass:
@@ -202,11 +218,14 @@ __global__ __launch_bounds__(256) void k_conv_fwd_lds(int64_t npix, const bf16* 
     poy[m] = (int)((p / HOUT) % HOUT);
     pox[m] = (int)(p % HOUT);
   }
-  floatx4 acc[MT][NT];
+  floatx4 acc[MT][NT];   // D[n][p]: channels 16t + 4g + r of pixel base + 16m + i; the bias as the start
 #pragma unroll
-  for (int m = 0; m < MT; ++m)
+  for (int t = 0; t < NT; ++t) {
+    const floatx4 bv = floatx4{bias[16 * t + 4 * g], bias[16 * t + 4 * g + 1], bias[16 * t + 4 * g + 2],
+                               bias[16 * t + 4 * g + 3]};
 #pragma unroll
-    for (int t = 0; t < NT; ++t) acc[m][t] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int m = 0; m < MT; ++m) acc[m][t] = bv;
+  }
 #pragma unroll 1
   for (int tap = 0; tap < 9; ++tap) {
     const int ky = tap / 3, kx = tap % 3;
@@ -238,12 +257,6 @@ __global__ __launch_bounds__(256) void k_conv_fwd_lds(int64_t npix, const bf16* 
     __syncthreads();
   }
   if (n_mt == 0) return;
-  // D[n][p]: channels 16t + 4g + r of pixel base + 16m + i
-  float bv[NT][4];
-#pragma unroll
-  for (int t = 0; t < NT; ++t)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) bv[t][r] = bias[16 * t + 4 * g + r];
 #pragma unroll
   for (int m = 0; m < MT; ++m) {
     if (m >= n_mt) break;
@@ -254,10 +267,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd_lds(int64_t npix, const bf16* 
     for (int t = 0; t < NT; ++t) {
       float o[4];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const float v = acc[m][t][r] + bv[t][r];
-        o[r] = v > 0.0f ? v : 0.0f;
-      }
+      for (int r = 0; r < 4; ++r) o[r] = relu(acc[m][t][r]);
       uint2 w;
       w.x = pack2(o[0], o[1]);
       w.y = pack2(o[2], o[3]);
@@ -324,15 +334,28 @@ FSMI_DEV void gather_window(const PatchSrc& src, int64_t tile, const WinOffs& w,
   const int oy0 = kT2 * (int)((tile >> 2) & 3), ox0 = kT2 * (int)(tile & 3);
   const int py0 = 4 * oy0 - 3, px0 = 4 * ox0 - 3;   // patch window origin
   const double x = src.poses[4 * b], y = src.poses[4 * b + 1];
-  const int cx0 = (int)src.block(x) - kPatch / 2 + px0;
-  const int cy0 = (int)src.block(y) - kPatch / 2 + py0;
+  const int cx0 = src.block(x) - kPatch / 2 + px0;
+  const int cy0 = src.block(y) - kPatch / 2 + py0;
   const float fx = src.frac(x), fy = src.frac(y);
+  // window rows and columns before the patch's first (the window never
+  // reaches past its last: py0, px0 <= 93 and 93 + 34 < 128)
+  const int rmin = py0 < 0 ? -py0 : 0, cmin = px0 < 0 ? -px0 : 0;
+  if (cx0 >= 0 && cy0 >= 0 && cx0 + kTP < src.X && cy0 + kTP < src.Y) {
+    // every block the window reads lies inside the map: no per-block checks
+    const float* base = src.map + (cx0 + src.X * (int64_t)cy0);
+    const uint32_t X = (uint32_t)src.X;
+#pragma unroll
+    for (int k = 0; k < kPatchPer; ++k) {
+      const uint32_t o = (uint32_t)w.r[k] * X + (uint32_t)w.c[k];
+      const float m = PatchSrc::lerp2(base[o], base[o + 1], base[o + X], base[o + X + 1], fx, fy);
+      v[k] = w.r[k] >= rmin && w.c[k] >= cmin ? m : 0.0f;
+    }
+    return;
+  }
 #pragma unroll
   for (int k = 0; k < kPatchPer; ++k) {
     const float m = src.bilinear(cx0 + w.c[k], cy0 + w.r[k], fx, fy);
-    const bool in_patch = (unsigned)(py0 + w.r[k]) < (unsigned)kPatch &&
-                          (unsigned)(px0 + w.c[k]) < (unsigned)kPatch;
-    v[k] = in_patch ? m : 0.0f;
+    v[k] = w.r[k] >= rmin && w.c[k] >= cmin ? m : 0.0f;
   }
 }
 
@@ -358,13 +381,15 @@ __global__ __launch_bounds__(256) void k_conv12_fwd(int64_t n_tiles, PatchSrc sr
     *reinterpret_cast<bf16x8*>(sW2 + ((tap * 4 + gg) * 64 + co) * 8) = load8(W2 + e8 * 8);
   }
   // A operand of conv1 (16 x 16 x 16): A[n][k] = W1[16t + n][k], k = tap 4g + q
-  // (< 9); the lane's taps sit at window offsets toff[q] from a pixel's base
+  // (< 9, else 0); the lane's taps sit at window offsets toff[q] from a
+  // pixel's base (the slots past the ninth tap read tap 0's pixel, which their
+  // zero weight cancels: the sum is the same as with a zero there)
   bf16x4 w1[2];
   int toff[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int tap = 4 * g + q;
-    toff[q] = tap < 9 ? (tap / 3) * kTP + tap % 3 : -1;
+    toff[q] = tap < 9 ? (tap / 3) * kTP + tap % 3 : 0;
   }
   float bias1[2][4], bias2[4][4];
 #pragma unroll
@@ -418,7 +443,7 @@ __global__ __launch_bounds__(256) void k_conv12_fwd(int64_t n_tiles, PatchSrc sr
       const int base = c1_base[u];
       bf16x4 x;   // B operand: taps 4g .. 4g + 3 of pixel p
 #pragma unroll
-      for (int q = 0; q < 4; ++q) x[q] = toff[q] >= 0 ? sP[base + toff[q]] : (bf16)0.0f;
+      for (int q = 0; q < 4; ++q) x[q] = sP[base + toff[q]];
       const int y1 = 2 * oy0 - 1 + pr, x1 = 2 * ox0 - 1 + pc;
       const bool inside = pv && y1 >= 0 && y1 < 64 && x1 >= 0 && x1 < 64;
       const bool owned = SAVE && pv && pr >= 1 && pc >= 1;   // implies inside
@@ -426,18 +451,15 @@ __global__ __launch_bounds__(256) void k_conv12_fwd(int64_t n_tiles, PatchSrc sr
       uint32_t bits = 0;
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
-        // D[n][p]: channels 16t + 4g + r of pixel p
-        const floatx4 d = mfma16(w1[t], x, floatx4{0.f, 0.f, 0.f, 0.f});
+        // D[n][p]: channels 16t + 4g + r of pixel p, the bias as the accumulator's start
+        const floatx4 d = mfma16(w1[t], x, floatx4{bias1[t][0], bias1[t][1], bias1[t][2], bias1[t][3]});
         float o[4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const float val = d[r] + bias1[t][r];
-          o[r] = inside && val > 0.0f ? val : 0.0f;
-        }
+        for (int r = 0; r < 4; ++r) o[r] = relu(d[r]);
         if (pv) {
           uint2 w;
-          w.x = pack2(o[0], o[1]);
-          w.y = pack2(o[2], o[3]);
+          w.x = inside ? pack2(o[0], o[1]) : 0u;
+          w.y = inside ? pack2(o[2], o[3]) : 0u;
           *reinterpret_cast<uint2*>(sA1 + p * kA1Px + 16 * t + 4 * g) = w;
           if (owned) {
             *reinterpret_cast<uint2*>(act1 + pix1 * 32 + 16 * t + 4 * g) = w;
@@ -449,9 +471,9 @@ __global__ __launch_bounds__(256) void k_conv12_fwd(int64_t n_tiles, PatchSrc sr
     }
     __syncthreads();
     // conv2: wave w takes output pixels 16w .. 16w + 15 of the 8 x 8 tile
-    floatx4 acc[4];
+    floatx4 acc[4];   // the bias as the accumulators' start
 #pragma unroll
-    for (int t = 0; t < 4; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int t = 0; t < 4; ++t) acc[t] = floatx4{bias2[t][0], bias2[t][1], bias2[t][2], bias2[t][3]};
     const int qy = (16 * wave + i) >> 3, qx = (16 * wave + i) & 7;
 #pragma unroll
     for (int tap = 0; tap < 9; ++tap) {
@@ -469,10 +491,7 @@ __global__ __launch_bounds__(256) void k_conv12_fwd(int64_t n_tiles, PatchSrc sr
     for (int t = 0; t < 4; ++t) {
       float o[4];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const float val = acc[t][r] + bias2[t][r];
-        o[r] = val > 0.0f ? val : 0.0f;
-      }
+      for (int r = 0; r < 4; ++r) o[r] = relu(acc[t][r]);
       uint2 w;
       w.x = pack2(o[0], o[1]);
       w.y = pack2(o[2], o[3]);
@@ -586,8 +605,8 @@ __global__ __launch_bounds__(256, WG1 ? 4 : 1) void k_conv_dgrad(int64_t nq, int
       const int64_t b0 = base / (HOUT * HOUT);
       const int a0 = (int)((base / HOUT) % HOUT);
       const double x = src.poses[4 * b0], y = src.poses[4 * b0 + 1];
-      const int mx0 = (int)src.block(x) - kPatch / 2;
-      const int my0 = (int)src.block(y) - kPatch / 2;
+      const int mx0 = src.block(x) - kPatch / 2;
+      const int my0 = src.block(y) - kPatch / 2;
       const float fx = src.frac(x), fy = src.frac(y);
       for (int e = tid; e < 9 * SROW; e += 256) {
         const int r = e / SROW, c = e - r * SROW;
