@@ -282,6 +282,164 @@ __global__ __launch_bounds__(256) void k_conv_fwd_lds(int64_t npix, const bf16* 
 }
 
 // ---------------------------------------------------------------------------
+// conv3 (64 -> 64 channels, 32^2 -> 16^2) by input rows.  An output row is 16
+// pixels, one per lane i of a lane group, so a wave takes four output rows oy0
+// .. oy0 + 3 of one pose (a unit; four units per pose) and reads the nine
+// input rows under them once each, in order: lane (i, g) loads the even
+// column 2i and the odd column 2i + 1 of a row (channels 32c + 8g .. + 7, c =
+// 0, 1), and the odd column left of 2i, 2i - 1, is the odd load of lane i - 1,
+// one lane shift within the 16-lane row (lane 0 gets 0: the zero padding left
+// of column 0).  Input row 2(oy0 + m) + ky is tap row ky of output row m, so a
+// row feeds one or two output rows as it arrives, and no input byte is read
+// twice by a wave (the k_conv_fwd_lds form reads each 2.25 times, from all
+// over the pose, and its concurrent workgroups' poses exceed the L2).  All
+// nine taps' weights sit in LDS as 72 fragments of 1 KiB (fragment (tap, c, t)
+// = lane l's W[16t + l % 16][tap][32c + 8(l / 16) .. + 7] at 16 l), staged
+// once by each persistent workgroup; the waves then run their units without
+// barriers.  Products are taken transposed (weights as the A operand), as in
+// k_conv_fwd_lds, whose output and sign layouts this kernel keeps.
+// ---------------------------------------------------------------------------
+constexpr int kC3Waves = 4;                           // waves per workgroup
+constexpr int kC3Frag = 512;                          // bf16 per weight fragment
+constexpr int kC3WElems = 9 * 2 * 4 * kC3Frag;        // 72 KiB
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+// lane i of each 16-lane row takes lane i - 1's value, lane 0 takes 0
+FSMI_DEV bf16x8 shift_right1(bf16x8 v) {
+  u32x4 u = __builtin_bit_cast(u32x4, v), r;
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    r[q] = (unsigned)__builtin_amdgcn_update_dpp(0, (int)u[q], 0x111, 0xf, 0xf, false);   // row_shr:1
+  return __builtin_bit_cast(bf16x8, r);
+}
+
+// The unit's 72 product groups in input-row order: group k is tap (ky, kx),
+// channel half c, output row m (= (rr - ky) / 2) of input row rr, four
+// products (one per 16-channel output tile).
+struct Conv3Plan {
+  int8_t rr[72], ky[72], kx[72], c[72];
+  constexpr Conv3Plan() : rr(), ky(), kx(), c() {
+    int k = 0;
+    for (int r = 0; r < 9; ++r)
+      for (int y = 0; y < 3; ++y) {
+        if (r - y < 0 || ((r - y) & 1) || (r - y) / 2 >= 4) continue;
+        for (int x = 0; x < 3; ++x)
+          for (int h = 0; h < 2; ++h) {
+            rr[k] = (int8_t)r;
+            ky[k] = (int8_t)y;
+            kx[k] = (int8_t)x;
+            c[k] = (int8_t)h;
+            ++k;
+          }
+      }
+  }
+};
+constexpr Conv3Plan kC3Plan{};
+constexpr int kC3Ahead = 3;   // input rows in flight beyond the one in use
+
+__global__ __launch_bounds__(64 * kC3Waves, 2) void k_conv3_rows(int64_t n_units,
+                                                                const bf16* __restrict__ in,
+                                                                const bf16* __restrict__ W,
+                                                                const float* __restrict__ bias,
+                                                                bf16* __restrict__ out,
+                                                                uint16_t* __restrict__ sign) {
+  constexpr int HIN = 32, HOUT = 16, CIN = 64, COUT = 64, MT = 4, NR = 2 * MT + 1;
+  __shared__ __align__(16) bf16 sW[kC3WElems];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int i = lane & 15, g = lane >> 4;
+  // fragment (tap, c, t), lane l: 16 bytes of W[co = 16t + l % 16][tap][32c + 8(l / 16) ..]
+  for (int e = tid; e < kC3WElems / 8; e += 64 * kC3Waves) {
+    const int l = e & 63, f = e >> 6, t = f & 3, c = (f >> 2) & 1, tap = f >> 3;
+    *reinterpret_cast<bf16x8*>(sW + 8 * e) =
+        load8(W + ((16 * t + (l & 15)) * 9 + tap) * CIN + 32 * c + 8 * (l >> 4));
+  }
+  __syncthreads();
+  const int64_t wave0 = (int64_t)blockIdx.x * kC3Waves + (tid >> 6);
+  const int64_t n_waves = (int64_t)gridDim.x * kC3Waves;
+  for (int64_t u = wave0; u < n_units; u += n_waves) {
+    const int64_t b = u >> 2;
+    const int oy0 = MT * (int)(u & 3);
+    // the weight reads' base, opaque to the compiler: keeps it from hoisting
+    // the 72 fragment reads out of the unit loop (288 registers)
+    int wofs = 8 * lane;
+    asm volatile("" : "+v"(wofs));
+    floatx4 acc[MT][4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const floatx4 bv = *reinterpret_cast<const floatx4*>(bias + 16 * t + 4 * g);
+#pragma unroll
+      for (int m = 0; m < MT; ++m) acc[m][t] = bv;
+    }
+    // input row rr = 0 .. 8 is image row 2 oy0 - 1 + rr (<= 31; only rr = 0
+    // of the top unit lies outside: zeros).  x[rr] = even column c = 0, 1,
+    // then odd column c = 0, 1.
+    bf16x8 x[NR][4];
+    auto fetch = [&](int rr) {
+      const int row = 2 * oy0 - 1 + rr;
+      const bool ok = row >= 0;
+      const bf16* p = in + ((b * HIN + (ok ? row : 0)) * HIN + 2 * i) * CIN + 8 * g;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) x[rr][q] = load8(p + (q >> 1) * CIN + 32 * (q & 1));
+      if (!ok) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) x[rr][q] = zero8();
+      }
+    };
+    bf16x8 ol[2];   // odd column left of 2i, of the row in use
+    auto begin_row = [&](int k) {
+      const int rr = kC3Plan.rr[k];
+      if (k > 0 && kC3Plan.rr[k - 1] == rr) return;
+      if (rr + kC3Ahead < NR) fetch(rr + kC3Ahead);
+#pragma unroll
+      for (int c = 0; c < 2; ++c) ol[c] = shift_right1(x[rr][2 + c]);
+    };
+    bf16x8 wa[4], wb[4];
+    auto wload = [&](int k, bf16x8 (&w)[4]) {
+      const int f = ((3 * kC3Plan.ky[k] + kC3Plan.kx[k]) * 2 + kC3Plan.c[k]) * 4;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) w[t] = *reinterpret_cast<const bf16x8*>(sW + (f + t) * kC3Frag + wofs);
+    };
+    auto products = [&](int k, const bf16x8 (&w)[4]) {
+      const int rr = kC3Plan.rr[k], kx = kC3Plan.kx[k], c = kC3Plan.c[k];
+      const int m = (rr - kC3Plan.ky[k]) >> 1;
+      const bf16x8 xv = kx == 0 ? ol[c] : kx == 1 ? x[rr][c] : x[rr][2 + c];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) acc[m][t] = mfma(w[t], xv, acc[m][t]);
+    };
+#pragma unroll
+    for (int rr = 0; rr < kC3Ahead; ++rr) fetch(rr);
+    wload(0, wa);
+#pragma unroll
+    for (int k = 0; k < 72; k += 2) {
+      begin_row(k);
+      wload(k + 1, wb);
+      products(k, wa);
+      __builtin_amdgcn_sched_barrier(0);
+      begin_row(k + 1);
+      if (k + 2 < 72) wload(k + 2, wa);
+      products(k + 1, wb);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    // D[n][p]: channels 16t + 4g + r of pixel (oy0 + m, i)
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+      const int64_t pix = (b * HOUT + oy0 + m) * HOUT + i;
+      bf16* op = out + pix * COUT + 4 * g;
+      uint32_t bits = 0;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        uint2 w;
+        w.x = pack2(relu(acc[m][t][0]), relu(acc[m][t][1]));
+        w.y = pack2(relu(acc[m][t][2]), relu(acc[m][t][3]));
+        *reinterpret_cast<uint2*>(op + 16 * t) = w;
+        bits |= sign4(w) << (4 * t);
+      }
+      if (sign) sign[4 * pix + g] = (uint16_t)bits;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // conv1 fused into conv2 (inference and training).  A workgroup owns 8 x 8 output pixels of
 // conv2 (all 64 channels) at a time: it gathers the 35 x 35 patch window those
 // pixels depend on, computes the 17 x 17 x 32 conv1 outputs of the window into
@@ -1513,6 +1671,15 @@ template <int L>
 static void conv_fwd(fsmi_sur net, int64_t nb, bool save) {
   constexpr LayerDims d = kL[L];
   static_assert(L >= 2, "conv1 and conv2 run in k_conv12_fwd");
+  if constexpr (L == 2) {
+    static_assert(d.cin == 64 && d.cout == 64 && d.hin == 32, "k_conv3_rows is written for conv3");
+    const int64_t units = nb * 4;
+    const int grid = (int)std::min<int64_t>((units + kC3Waves - 1) / kC3Waves, (int64_t)net->ctx->num_cu * 2);
+    hipLaunchKernelGGL(k_conv3_rows, dim3(grid), dim3(64 * kC3Waves), 0, net->ctx->stream, units,
+                       net->act[L], net->Wbf + wbf_off(L), net->P + b_off(L), net->act[L + 1],
+                       save ? (uint16_t*)net->sign[L + 1] : nullptr);
+    return;
+  }
   const int64_t npix = nb * (d.hin / 2) * (d.hin / 2);
   constexpr int per_block = 4 * 16 * conv_mt<d.cin, d.cout, d.hin>();   // 4 waves
   const int64_t blocks = (npix + per_block - 1) / per_block;
