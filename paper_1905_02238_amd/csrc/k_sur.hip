@@ -354,10 +354,34 @@ __global__ __launch_bounds__(64 * kC3Waves, 2) void k_conv3_rows(int64_t n_units
         load8(W + ((16 * t + (l & 15)) * 9 + tap) * CIN + 32 * c + 8 * (l >> 4));
   }
   __syncthreads();
+  floatx4 bv[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) bv[t] = *reinterpret_cast<const floatx4*>(bias + 16 * t + 4 * g);
+  // input row rr = 0 .. 8 of unit u is image row 2 oy0 - 1 + rr (<= 31; only
+  // rr = 0 of a pose's top unit lies outside: zeros).  x[rr] = even column
+  // c = 0, 1, then odd column c = 0, 1.  The last kC3Ahead rows' loads are
+  // followed by the next unit's first rows, into the registers of the rows
+  // already used, so no unit starts by waiting for memory.
+  bf16x8 x[NR][4];
+  auto fetch = [&](int64_t un, int rr, int slot) {
+    const int row = 2 * (MT * (int)(un & 3)) - 1 + rr;
+    const bool ok = row >= 0;
+    const bf16* p = in + (((un >> 2) * HIN + (ok ? row : 0)) * HIN + 2 * i) * CIN + 8 * g;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) x[slot][q] = load8(p + (q >> 1) * CIN + 32 * (q & 1));
+    if (!ok) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) x[slot][q] = zero8();
+    }
+  };
   const int64_t wave0 = (int64_t)blockIdx.x * kC3Waves + (tid >> 6);
   const int64_t n_waves = (int64_t)gridDim.x * kC3Waves;
+  if (wave0 < n_units) {
+#pragma unroll
+    for (int rr = 0; rr < kC3Ahead; ++rr) fetch(wave0, rr, rr);
+  }
   for (int64_t u = wave0; u < n_units; u += n_waves) {
-    const int64_t b = u >> 2;
+    const int64_t b = u >> 2, un = u + n_waves;
     const int oy0 = MT * (int)(u & 3);
     // the weight reads' base, opaque to the compiler: keeps it from hoisting
     // the 72 fragment reads out of the unit loop (288 registers)
@@ -365,31 +389,15 @@ __global__ __launch_bounds__(64 * kC3Waves, 2) void k_conv3_rows(int64_t n_units
     asm volatile("" : "+v"(wofs));
     floatx4 acc[MT][4];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const floatx4 bv = *reinterpret_cast<const floatx4*>(bias + 16 * t + 4 * g);
+    for (int t = 0; t < 4; ++t)
 #pragma unroll
-      for (int m = 0; m < MT; ++m) acc[m][t] = bv;
-    }
-    // input row rr = 0 .. 8 is image row 2 oy0 - 1 + rr (<= 31; only rr = 0
-    // of the top unit lies outside: zeros).  x[rr] = even column c = 0, 1,
-    // then odd column c = 0, 1.
-    bf16x8 x[NR][4];
-    auto fetch = [&](int rr) {
-      const int row = 2 * oy0 - 1 + rr;
-      const bool ok = row >= 0;
-      const bf16* p = in + ((b * HIN + (ok ? row : 0)) * HIN + 2 * i) * CIN + 8 * g;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) x[rr][q] = load8(p + (q >> 1) * CIN + 32 * (q & 1));
-      if (!ok) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) x[rr][q] = zero8();
-      }
-    };
+      for (int m = 0; m < MT; ++m) acc[m][t] = bv[t];
     bf16x8 ol[2];   // odd column left of 2i, of the row in use
     auto begin_row = [&](int k) {
       const int rr = kC3Plan.rr[k];
       if (k > 0 && kC3Plan.rr[k - 1] == rr) return;
-      if (rr + kC3Ahead < NR) fetch(rr + kC3Ahead);
+      if (rr + kC3Ahead < NR) fetch(u, rr + kC3Ahead, rr + kC3Ahead);
+      else if (un < n_units) fetch(un, rr + kC3Ahead - NR, rr + kC3Ahead - NR);
 #pragma unroll
       for (int c = 0; c < 2; ++c) ol[c] = shift_right1(x[rr][2 + c]);
     };
@@ -406,8 +414,6 @@ __global__ __launch_bounds__(64 * kC3Waves, 2) void k_conv3_rows(int64_t n_units
 #pragma unroll
       for (int t = 0; t < 4; ++t) acc[m][t] = mfma(w[t], xv, acc[m][t]);
     };
-#pragma unroll
-    for (int rr = 0; rr < kC3Ahead; ++rr) fetch(rr);
     wload(0, wa);
 #pragma unroll
     for (int k = 0; k < 72; k += 2) {
@@ -462,7 +468,12 @@ constexpr int kT2 = 8;                 // conv2 tile edge (output pixels)
 constexpr int kT1 = 2 * kT2 + 1;       // 17: conv1 window edge
 constexpr int kTP = 2 * kT1 + 1;       // 35: patch window edge
 constexpr int kA1Px = 40;              // bf16 per conv1 pixel in LDS (32 channels + 8 pad)
-constexpr int kW2Elems = 64 * 9 * 32;
+// LDS slot of conv1 window pixel (y, x): each row holds its even columns, then
+// its odd ones.  conv2 reads 16 pixels two columns apart per fragment, which
+// this makes neighbouring slots, 80 bytes apart: the 8 lanes that one LDS
+// cycle serves then fall on distinct banks (at a 160-byte stride lanes i and
+// i + 4 share them).
+FSMI_DEV int a1_slot(int y, int x) { return y * kT1 + ((x & 1) ? (kT1 + 1) / 2 + (x >> 1) : x >> 1); }
 constexpr int kPatchPer = (kTP * kTP + 255) / 256;   // gathers per thread
 
 // A thread's share of a tile's patch window: element e = tid + 256 k at row
@@ -527,17 +538,21 @@ __global__ __launch_bounds__(256) void k_conv12_fwd(int64_t n_tiles, PatchSrc sr
                                                     bf16* __restrict__ act1,
                                                     uint8_t* __restrict__ sign1,
                                                     uint16_t* __restrict__ sign2) {
-  __shared__ __align__(16) bf16 sW2[kW2Elems];
-  __shared__ __align__(16) bf16 sP[kTP * kTP + 8];
-  __shared__ __align__(16) bf16 sA1[kT1 * kT1 * kA1Px];
+  __shared__ __align__(16) bf16 sP[2][kTP * kTP + 8];
+  __shared__ __align__(16) bf16 sA1[2][kT1 * kT1 * kA1Px];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int i = lane & 15, g = lane >> 4;
-  // W2 [co][tap][ci] -> LDS [tap][ci/8][co][8]
-  for (int e8 = tid; e8 < kW2Elems / 8; e8 += 256) {
-    const int co = e8 / 36, rem = e8 - co * 36, tap = rem >> 2, gg = rem & 3;
-    *reinterpret_cast<bf16x8*>(sW2 + ((tap * 4 + gg) * 64 + co) * 8) = load8(W2 + e8 * 8);
-  }
+  // conv2: wave w takes column tiles 2 ph, 2 ph + 1 of the tile's 64 pixels and
+  // output channel tiles 2 chh, 2 chh + 1 (ph = w % 2, chh = w / 2).  Its A
+  // operands, W2[16 (2 chh + tt) + i][tap][8g .. 8g + 7], stay in registers for
+  // the whole launch (W2 is [co][tap][ci], 32 input channels).
+  const int ph = wave & 1, chh = wave >> 1;
+  bf16x8 w2r[9][2];
+#pragma unroll
+  for (int tap = 0; tap < 9; ++tap)
+#pragma unroll
+    for (int tt = 0; tt < 2; ++tt) w2r[tap][tt] = load8(W2 + ((16 * (2 * chh + tt) + i) * 9 + tap) * 32 + 8 * g);
   // A operand of conv1 (16 x 16 x 16): A[n][k] = W1[16t + n][k], k = tap 4g + q
   // (< 9, else 0); the lane's taps sit at window offsets toff[q] from a
   // pixel's base (the slots past the ninth tap read tap 0's pixel, which their
@@ -549,7 +564,7 @@ __global__ __launch_bounds__(256) void k_conv12_fwd(int64_t n_tiles, PatchSrc sr
     const int tap = 4 * g + q;
     toff[q] = tap < 9 ? (tap / 3) * kTP + tap % 3 : 0;
   }
-  float bias1[2][4], bias2[4][4];
+  float bias1[2][4], bias2[2][4];
 #pragma unroll
   for (int t = 0; t < 2; ++t) {
 #pragma unroll
@@ -561,14 +576,14 @@ __global__ __launch_bounds__(256) void k_conv12_fwd(int64_t n_tiles, PatchSrc sr
     for (int r = 0; r < 4; ++r) bias1[t][r] = b1[16 * t + 4 * g + r];
   }
 #pragma unroll
-  for (int t = 0; t < 4; ++t)
+  for (int tt = 0; tt < 2; ++tt)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) bias2[t][r] = b2[16 * t + 4 * g + r];
+    for (int r = 0; r < 4; ++r) bias2[tt][r] = b2[16 * (2 * chh + tt) + 4 * g + r];
   const WinOffs woff = win_offsets(tid);
   // conv1 pixels of this lane (p = 16 m + i, m = wave, wave + 4, ...): their
   // place in the window and their patch offset, the same for every tile
   constexpr int kC1 = (19 + 3) / 4;   // column tiles of 16 per wave, at most
-  int c1_pr[kC1], c1_pc[kC1], c1_base[kC1];
+  int c1_pr[kC1], c1_pc[kC1], c1_base[kC1], c1_slot[kC1];
 #pragma unroll
   for (int u = 0; u < kC1; ++u) {
     const int p = 16 * (wave + 4 * u) + i;
@@ -576,88 +591,126 @@ __global__ __launch_bounds__(256) void k_conv12_fwd(int64_t n_tiles, PatchSrc sr
     c1_pr[u] = pv ? p / kT1 : -1000;          // -1000: outside any grid
     c1_pc[u] = pv ? p - (p / kT1) * kT1 : 0;
     c1_base[u] = pv ? 2 * c1_pr[u] * kTP + 2 * c1_pc[u] : 0;
+    c1_slot[u] = pv ? a1_slot(c1_pr[u], c1_pc[u]) : 0;
   }
+  // Two-stage pipeline over the workgroup's tiles j = 0, 1, ...: step j runs
+  // conv1 of tile j (patch buffer j % 2 -> conv1 buffer j % 2) beside conv2
+  // of tile j - 1 (conv1 buffer (j - 1) % 2), stores tile j + 1's patch
+  // window, gathered during step j - 1, into patch buffer (j + 1) % 2 and
+  // issues the gathers of tile j + 2; one barrier ends the step.  Each buffer
+  // is written in one step and read in the next only.
+  const int64_t n_my = (int64_t)blockIdx.x < n_tiles ? (n_tiles - 1 - blockIdx.x) / gridDim.x + 1 : 0;
+  auto tile_of = [&](int64_t j) { return (int64_t)blockIdx.x + j * (int64_t)gridDim.x; };
   float v[kPatchPer];
-  if ((int64_t)blockIdx.x < n_tiles) gather_window(src, blockIdx.x, woff, v);
-  __syncthreads();
-  for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-    const int64_t b = tile >> 4;
-    const int oy0 = kT2 * (int)((tile >> 2) & 3), ox0 = kT2 * (int)(tile & 3);
+  auto stage_patch = [&](int buf) {
 #pragma unroll
     for (int k = 0; k < kPatchPer; ++k) {
       const int e = tid + 256 * k;
-      if (e < kTP * kTP) sP[e] = (bf16)v[k];
+      if (e < kTP * kTP) sP[buf][e] = (bf16)v[k];
     }
-    __syncthreads();
-    if (tile + gridDim.x < n_tiles) gather_window(src, tile + gridDim.x, woff, v);
-    // conv1 on the window: 289 pixels in 19 column tiles of 16 (the last padded)
+  };
+  if (n_my > 0) {
+    gather_window(src, tile_of(0), woff, v);
+    stage_patch(0);
+    if (n_my > 1) gather_window(src, tile_of(1), woff, v);
+  }
+  __syncthreads();
+  for (int64_t j = 0; j <= n_my; ++j) {
+    if (j < n_my) {
+      // conv1 on the window of tile j: 289 pixels in 19 column tiles of 16 (the last padded)
+      const int64_t tile = tile_of(j);
+      const int64_t b = tile >> 4;
+      const int oy0 = kT2 * (int)((tile >> 2) & 3), ox0 = kT2 * (int)(tile & 3);
+      const bf16* P = sP[j & 1];
+      bf16* A1 = sA1[j & 1];
 #pragma unroll
-    for (int u = 0; u < kC1; ++u) {
-      const int m = wave + 4 * u;
-      if (m >= 19) break;                       // wave-uniform
-      const int p = 16 * m + i;
-      const bool pv = c1_pr[u] >= 0;
-      const int pr = pv ? c1_pr[u] : 0, pc = c1_pc[u];
-      const int base = c1_base[u];
-      bf16x4 x;   // B operand: taps 4g .. 4g + 3 of pixel p
+      for (int u = 0; u < kC1; ++u) {
+        const int m = wave + 4 * u;
+        if (m >= 19) break;                       // wave-uniform
+        const bool pv = c1_pr[u] >= 0;            // pixel 16 m + i of the window
+        const int pr = pv ? c1_pr[u] : 0, pc = c1_pc[u];
+        const int base = c1_base[u];
+        bf16x4 x;   // B operand: taps 4g .. 4g + 3 of the pixel
 #pragma unroll
-      for (int q = 0; q < 4; ++q) x[q] = sP[base + toff[q]];
-      const int y1 = 2 * oy0 - 1 + pr, x1 = 2 * ox0 - 1 + pc;
-      const bool inside = pv && y1 >= 0 && y1 < 64 && x1 >= 0 && x1 < 64;
-      const bool owned = SAVE && pv && pr >= 1 && pc >= 1;   // implies inside
-      const int64_t pix1 = (b * 64 + y1) * 64 + x1;
-      uint32_t bits = 0;
+        for (int q = 0; q < 4; ++q) x[q] = P[base + toff[q]];
+        const int y1 = 2 * oy0 - 1 + pr, x1 = 2 * ox0 - 1 + pc;
+        const bool inside = pv && y1 >= 0 && y1 < 64 && x1 >= 0 && x1 < 64;
+        const bool owned = SAVE && pv && pr >= 1 && pc >= 1;   // implies inside
+        const int64_t pix1 = (b * 64 + y1) * 64 + x1;
+        uint32_t bits = 0;
 #pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        // D[n][p]: channels 16t + 4g + r of pixel p, the bias as the accumulator's start
-        const floatx4 d = mfma16(w1[t], x, floatx4{bias1[t][0], bias1[t][1], bias1[t][2], bias1[t][3]});
-        float o[4];
+        for (int t = 0; t < 2; ++t) {
+          // D[n][p]: channels 16t + 4g + r of the pixel, the bias as the accumulator's start
+          const floatx4 d = mfma16(w1[t], x, floatx4{bias1[t][0], bias1[t][1], bias1[t][2], bias1[t][3]});
+          float o[4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) o[r] = relu(d[r]);
-        if (pv) {
-          uint2 w;
-          w.x = inside ? pack2(o[0], o[1]) : 0u;
-          w.y = inside ? pack2(o[2], o[3]) : 0u;
-          *reinterpret_cast<uint2*>(sA1 + p * kA1Px + 16 * t + 4 * g) = w;
-          if (owned) {
-            *reinterpret_cast<uint2*>(act1 + pix1 * 32 + 16 * t + 4 * g) = w;
-            bits |= sign4(w) << (4 * t);
+          for (int r = 0; r < 4; ++r) o[r] = relu(d[r]);
+          if (pv) {
+            uint2 w;
+            w.x = inside ? pack2(o[0], o[1]) : 0u;
+            w.y = inside ? pack2(o[2], o[3]) : 0u;
+            *reinterpret_cast<uint2*>(A1 + c1_slot[u] * kA1Px + 16 * t + 4 * g) = w;
+            if (owned) {
+              *reinterpret_cast<uint2*>(act1 + pix1 * 32 + 16 * t + 4 * g) = w;
+              bits |= sign4(w) << (4 * t);
+            }
           }
         }
+        if (owned) sign1[4 * pix1 + g] = (uint8_t)bits;
       }
-      if (owned) sign1[4 * pix1 + g] = (uint8_t)bits;
+    }
+    if (j > 0) {
+      // conv2 of tile j - 1: pixels 16 (2 ph + mm) + i of the 8 x 8 tile, channel tiles 2 chh + tt
+      const int64_t tile = tile_of(j - 1);
+      const int64_t b = tile >> 4;
+      const int oy0 = kT2 * (int)((tile >> 2) & 3), ox0 = kT2 * (int)(tile & 3);
+      const bf16* A1 = sA1[(j - 1) & 1];
+      floatx4 acc[2][2];   // the bias as the accumulators' start
+      int qy[2], qx[2];
+#pragma unroll
+      for (int mm = 0; mm < 2; ++mm) {
+        const int p = 16 * (2 * ph + mm) + i;
+        qy[mm] = p >> 3;
+        qx[mm] = p & 7;
+#pragma unroll
+        for (int tt = 0; tt < 2; ++tt)
+          acc[mm][tt] = floatx4{bias2[tt][0], bias2[tt][1], bias2[tt][2], bias2[tt][3]};
+      }
+#pragma unroll
+      for (int tap = 0; tap < 9; ++tap) {
+        const int ky = tap / 3, kx = tap % 3;
+#pragma unroll
+        for (int mm = 0; mm < 2; ++mm) {
+          const bf16x8 x = load8(A1 + a1_slot(2 * qy[mm] + ky, 2 * qx[mm] + kx) * kA1Px + 8 * g);
+#pragma unroll
+          for (int tt = 0; tt < 2; ++tt) acc[mm][tt] = mfma(w2r[tap][tt], x, acc[mm][tt]);
+        }
+      }
+#pragma unroll
+      for (int mm = 0; mm < 2; ++mm) {
+        const int64_t pix2 = (b * 32 + oy0 + qy[mm]) * 32 + ox0 + qx[mm];
+        bf16* op = act2 + pix2 * 64 + 4 * g;
+        uint32_t bits = 0;
+#pragma unroll
+        for (int tt = 0; tt < 2; ++tt) {
+          float o[4];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) o[r] = relu(acc[mm][tt][r]);
+          uint2 w;
+          w.x = pack2(o[0], o[1]);
+          w.y = pack2(o[2], o[3]);
+          *reinterpret_cast<uint2*>(op + 16 * (2 * chh + tt)) = w;
+          bits |= sign4(w) << (4 * tt);
+        }
+        // byte chh of the pixel's 16-bit sign word g: channel tiles 2 chh, 2 chh + 1
+        if (SAVE) reinterpret_cast<uint8_t*>(sign2)[2 * (4 * pix2 + g) + chh] = (uint8_t)bits;
+      }
+    }
+    if (j + 1 < n_my) {
+      stage_patch((j + 1) & 1);
+      if (j + 2 < n_my) gather_window(src, tile_of(j + 2), woff, v);
     }
     __syncthreads();
-    // conv2: wave w takes output pixels 16w .. 16w + 15 of the 8 x 8 tile
-    floatx4 acc[4];   // the bias as the accumulators' start
-#pragma unroll
-    for (int t = 0; t < 4; ++t) acc[t] = floatx4{bias2[t][0], bias2[t][1], bias2[t][2], bias2[t][3]};
-    const int qy = (16 * wave + i) >> 3, qx = (16 * wave + i) & 7;
-#pragma unroll
-    for (int tap = 0; tap < 9; ++tap) {
-      const int ky = tap / 3, kx = tap % 3;
-      const bf16x8 x = load8(sA1 + ((2 * qy + ky) * kT1 + 2 * qx + kx) * kA1Px + 8 * g);
-#pragma unroll
-      for (int t = 0; t < 4; ++t)
-        acc[t] = mfma(load8(sW2 + ((tap * 4 + g) * 64 + 16 * t + i) * 8), x, acc[t]);
-    }
-    const int oy = oy0 + qy, ox = ox0 + qx;
-    const int64_t pix2 = (b * 32 + oy) * 32 + ox;
-    bf16* op = act2 + pix2 * 64 + 4 * g;
-    uint32_t bits = 0;
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      float o[4];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) o[r] = relu(acc[t][r]);
-      uint2 w;
-      w.x = pack2(o[0], o[1]);
-      w.y = pack2(o[2], o[3]);
-      *reinterpret_cast<uint2*>(op + 16 * t) = w;
-      bits |= sign4(w) << (4 * t);
-    }
-    if (SAVE) sign2[4 * pix2 + g] = (uint16_t)bits;
-    __syncthreads();   // sP and sA1 are rewritten by the next tile
   }
 }
 
