@@ -446,6 +446,123 @@ __global__ __launch_bounds__(64 * kC3Waves, 2) void k_conv3_rows(int64_t n_units
 }
 
 // ---------------------------------------------------------------------------
+// conv4 (64 -> 128 channels, 16^2 -> 8^2) in the same manner: a unit is
+// output rows oy0, oy0 + 1 of one pose (four units per pose), lane (i, g) of
+// a fragment pixel (oy0 + i / 8, i % 8), so tap row ky of the fragment reads
+// input row 2 (oy0 + i / 8) + ky - 1 per lane, the even and odd columns
+// 2 (i % 8) and 2 (i % 8) + 1, and the odd column to the left is a one-lane
+// shift that leaves lanes i % 8 = 0 at 0 (the zero padding).  All nine
+// taps' weights, 144 fragments of 1 KiB, fill one persistent workgroup's LDS
+// (one workgroup of eight waves per compute unit); each wave loads its next
+// unit's three tap rows while it computes the current one.  Output and sign
+// layouts are those of k_conv_fwd_lds.
+// ---------------------------------------------------------------------------
+constexpr int kC4Waves = 8;
+constexpr int kC4WElems = 9 * 2 * 8 * kC3Frag;       // 144 KiB
+
+// lane i of each 16-lane row takes lane i - 1's value; lanes i % 8 = 0 take 0
+FSMI_DEV bf16x8 shift_right1_seg8(bf16x8 v, bool first) {
+  const bf16x8 r = shift_right1(v);
+  return first ? zero8() : r;
+}
+
+__global__ __launch_bounds__(64 * kC4Waves, 2) void k_conv4_rows(int64_t n_units,
+                                                                const bf16* __restrict__ in,
+                                                                const bf16* __restrict__ W,
+                                                                const float* __restrict__ bias,
+                                                                bf16* __restrict__ out,
+                                                                uint32_t* __restrict__ sign) {
+  constexpr int HIN = 16, HOUT = 8, CIN = 64, COUT = 128, NT = 8;
+  __shared__ __align__(16) bf16 sW4[kC4WElems];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int i = lane & 15, g = lane >> 4, h = i >> 3, ox = i & 7;
+  // fragment (tap, c, t), lane l: 16 bytes of W[co = 16t + l % 16][tap][32c + 8(l / 16) ..]
+  for (int e = tid; e < kC4WElems / 8; e += 64 * kC4Waves) {
+    const int l = e & 63, f = e >> 6, t = f & 7, c = (f >> 3) & 1, tap = f >> 4;
+    *reinterpret_cast<bf16x8*>(sW4 + 8 * e) =
+        load8(W + ((16 * t + (l & 15)) * 9 + tap) * CIN + 32 * c + 8 * (l >> 4));
+  }
+  __syncthreads();
+  floatx4 bv[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) bv[t] = *reinterpret_cast<const floatx4*>(bias + 16 * t + 4 * g);
+  // x[ky] = even column c = 0, 1, then odd column c = 0, 1 of input row
+  // 2 (oy0 + h) + ky - 1 (<= 15; < 0 only for h = 0, ky = 0 of a pose's top unit: zeros)
+  bf16x8 x[3][4], nx[3][4];
+  auto fetch = [&](int64_t un, bf16x8 (&d)[3][4]) {
+    const int oy = 2 * (int)(un & 3) + h;
+#pragma unroll
+    for (int ky = 0; ky < 3; ++ky) {
+      const int row = 2 * oy + ky - 1;
+      const bool ok = row >= 0;
+      const bf16* p = in + (((un >> 2) * HIN + (ok ? row : 0)) * HIN + 2 * ox) * CIN + 8 * g;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const bf16x8 val = load8(p + (q >> 1) * CIN + 32 * (q & 1));
+        d[ky][q] = ok ? val : zero8();
+      }
+    }
+  };
+  const int64_t wave0 = (int64_t)blockIdx.x * kC4Waves + (tid >> 6);
+  const int64_t n_waves = (int64_t)gridDim.x * kC4Waves;
+  if (wave0 < n_units) fetch(wave0, x);
+  for (int64_t u = wave0; u < n_units; u += n_waves) {
+    const int64_t un = u + n_waves;
+    if (un < n_units) fetch(un, nx);
+    int wofs = 8 * lane;   // opaque to the compiler: no hoisting of the fragment reads
+    asm volatile("" : "+v"(wofs));
+    floatx4 acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = bv[t];
+    bf16x8 wa[NT], wb[NT];
+    // group k = (ky, kx, c) in that order, 18 groups of NT products sharing one B operand
+    auto wload = [&](int k, bf16x8 (&w)[NT]) {
+      const int f = k * NT;   // (tap * 2 + c) * NT with tap = 3 ky + kx
+#pragma unroll
+      for (int t = 0; t < NT; ++t) w[t] = *reinterpret_cast<const bf16x8*>(sW4 + (f + t) * kC3Frag + wofs);
+    };
+    bf16x8 ol[3][2];
+#pragma unroll
+    for (int ky = 0; ky < 3; ++ky)
+#pragma unroll
+      for (int c = 0; c < 2; ++c) ol[ky][c] = shift_right1_seg8(x[ky][2 + c], ox == 0);
+    auto products = [&](int k, const bf16x8 (&w)[NT]) {
+      const int c = k & 1, tap = k >> 1, ky = tap / 3, kx = tap % 3;
+      const bf16x8 xv = kx == 0 ? ol[ky][c] : kx == 1 ? x[ky][c] : x[ky][2 + c];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) acc[t] = mfma(w[t], xv, acc[t]);
+    };
+    wload(0, wa);
+#pragma unroll
+    for (int k = 0; k < 18; k += 2) {
+      wload(k + 1, wb);
+      products(k, wa);
+      __builtin_amdgcn_sched_barrier(0);
+      if (k + 2 < 18) wload(k + 2, wa);
+      products(k + 1, wb);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    // D[n][p]: channels 16t + 4g + r of pixel (oy0 + h, ox)
+    const int64_t pix = ((u >> 2) * HOUT + 2 * (int)(u & 3) + h) * HOUT + ox;
+    bf16* op = out + pix * COUT + 4 * g;
+    uint32_t bits = 0;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      uint2 w;
+      w.x = pack2(relu(acc[t][0]), relu(acc[t][1]));
+      w.y = pack2(relu(acc[t][2]), relu(acc[t][3]));
+      *reinterpret_cast<uint2*>(op + 16 * t) = w;
+      bits |= sign4(w) << (4 * t);
+    }
+    if (sign) sign[4 * pix + g] = bits;
+#pragma unroll
+    for (int ky = 0; ky < 3; ++ky)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) x[ky][q] = nx[ky][q];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // conv1 fused into conv2 (inference and training).  A workgroup owns 8 x 8 output pixels of
 // conv2 (all 64 channels) at a time: it gathers the 35 x 35 patch window those
 // pixels depend on, computes the 17 x 17 x 32 conv1 outputs of the window into
@@ -1731,6 +1848,15 @@ static void conv_fwd(fsmi_sur net, int64_t nb, bool save) {
     hipLaunchKernelGGL(k_conv3_rows, dim3(grid), dim3(64 * kC3Waves), 0, net->ctx->stream, units,
                        net->act[L], net->Wbf + wbf_off(L), net->P + b_off(L), net->act[L + 1],
                        save ? (uint16_t*)net->sign[L + 1] : nullptr);
+    return;
+  }
+  if constexpr (L == 3) {
+    static_assert(d.cin == 64 && d.cout == 128 && d.hin == 16, "k_conv4_rows is written for conv4");
+    const int64_t units = nb * 4;
+    const int grid = (int)std::min<int64_t>((units + kC4Waves - 1) / kC4Waves, (int64_t)net->ctx->num_cu);
+    hipLaunchKernelGGL(k_conv4_rows, dim3(grid), dim3(64 * kC4Waves), 0,
+                       net->ctx->stream, units, net->act[L], net->Wbf + wbf_off(L), net->P + b_off(L),
+                       net->act[L + 1], save ? (uint32_t*)net->sign[L + 1] : nullptr);
     return;
   }
   const int64_t npix = nb * (d.hin / 2) * (d.hin / 2);
