@@ -374,7 +374,7 @@ __global__ __launch_bounds__(64 * kC3Waves, 2) void k_conv3_rows(int64_t n_units
       for (int q = 0; q < 4; ++q) x[slot][q] = zero8();
     }
   };
-  const int64_t wave0 = (int64_t)blockIdx.x * kC3Waves + (tid >> 6);
+  const int64_t wave0 = (int64_t)blockIdx.x * kC3Waves + __builtin_amdgcn_readfirstlane(tid >> 6);
   const int64_t n_waves = (int64_t)gridDim.x * kC3Waves;
   if (wave0 < n_units) {
 #pragma unroll
@@ -460,10 +460,16 @@ __global__ __launch_bounds__(64 * kC3Waves, 2) void k_conv3_rows(int64_t n_units
 constexpr int kC4Waves = 8;
 constexpr int kC4WElems = 9 * 2 * 8 * kC3Frag;       // 144 KiB
 
-// lane i of each 16-lane row takes lane i - 1's value; lanes i % 8 = 0 take 0
-FSMI_DEV bf16x8 shift_right1_seg8(bf16x8 v, bool first) {
-  const bf16x8 r = shift_right1(v);
-  return first ? zero8() : r;
+// lane i of each 16-lane row takes lane i - 1's value, ANDed with keep (all
+// ones, or 0 for the first lane of a segment).  The lane shift must run with
+// every lane active (a lane reads its neighbour's register, and an inactive
+// neighbour gives 0), so the segment's first lane is cleared by the mask after
+// it, never by a branch around it, which the compiler could form from a select.
+FSMI_DEV bf16x8 shift_right1_masked(bf16x8 v, unsigned keep) {
+  u32x4 u = __builtin_bit_cast(u32x4, shift_right1(v));
+#pragma unroll
+  for (int q = 0; q < 4; ++q) u[q] &= keep;
+  return __builtin_bit_cast(bf16x8, u);
 }
 
 __global__ __launch_bounds__(64 * kC4Waves, 2) void k_conv4_rows(int64_t n_units,
@@ -476,6 +482,7 @@ __global__ __launch_bounds__(64 * kC4Waves, 2) void k_conv4_rows(int64_t n_units
   __shared__ __align__(16) bf16 sW4[kC4WElems];
   const int tid = threadIdx.x, lane = tid & 63;
   const int i = lane & 15, g = lane >> 4, h = i >> 3, ox = i & 7;
+  const unsigned keep = 0u - (unsigned)(ox != 0);   // 0 for the first lane of an 8-lane segment
   // fragment (tap, c, t), lane l: 16 bytes of W[co = 16t + l % 16][tap][32c + 8(l / 16) ..]
   for (int e = tid; e < kC4WElems / 8; e += 64 * kC4Waves) {
     const int l = e & 63, f = e >> 6, t = f & 7, c = (f >> 3) & 1, tap = f >> 4;
@@ -503,7 +510,7 @@ __global__ __launch_bounds__(64 * kC4Waves, 2) void k_conv4_rows(int64_t n_units
       }
     }
   };
-  const int64_t wave0 = (int64_t)blockIdx.x * kC4Waves + (tid >> 6);
+  const int64_t wave0 = (int64_t)blockIdx.x * kC4Waves + __builtin_amdgcn_readfirstlane(tid >> 6);
   const int64_t n_waves = (int64_t)gridDim.x * kC4Waves;
   if (wave0 < n_units) fetch(wave0, x);
   for (int64_t u = wave0; u < n_units; u += n_waves) {
@@ -525,7 +532,7 @@ __global__ __launch_bounds__(64 * kC4Waves, 2) void k_conv4_rows(int64_t n_units
 #pragma unroll
     for (int ky = 0; ky < 3; ++ky)
 #pragma unroll
-      for (int c = 0; c < 2; ++c) ol[ky][c] = shift_right1_seg8(x[ky][2 + c], ox == 0);
+      for (int c = 0; c < 2; ++c) ol[ky][c] = shift_right1_masked(x[ky][2 + c], keep);
     auto products = [&](int k, const bf16x8 (&w)[NT]) {
       const int c = k & 1, tap = k >> 1, ky = tap / 3, kx = tap % 3;
       const bf16x8 xv = kx == 0 ? ol[ky][c] : kx == 1 ? x[ky][c] : x[ky][2 + c];
@@ -563,6 +570,103 @@ __global__ __launch_bounds__(64 * kC4Waves, 2) void k_conv4_rows(int64_t n_units
 }
 
 // ---------------------------------------------------------------------------
+// conv5 (128 -> 128 channels, 8^2 -> 4^2) in the same manner.  A pose's 16
+// output pixels are one fragment (lane i: pixel (i / 4, i % 4)), and the
+// weights of all 128 output channels (288 KiB) exceed one workgroup's LDS, so
+// a workgroup holds those of one half, output channels 64 chh .. 64 chh + 63
+// (chh = its index % 2), and a unit is (pose, half).  Tap row ky of lane i
+// reads input row 2 (i / 4) + ky - 1, columns 2 (i % 4) and 2 (i % 4) + 1,
+// channels 32c + 8g .. + 7 (c = 0 .. 3); the odd column to the left is a
+// lane shift that leaves lanes i % 4 = 0 at 0.  The output layout is that of
+// k_conv_fwd_lds; no sign words (the head's backward reads act5 itself).
+// ---------------------------------------------------------------------------
+constexpr int kC5Waves = 8;
+constexpr int kC5WElems = 9 * 4 * 4 * kC3Frag;       // 144 KiB: one half's weights
+
+__global__ __launch_bounds__(64 * kC5Waves, 2) void k_conv5_rows(int64_t n_poses,
+                                                                const bf16* __restrict__ in,
+                                                                const bf16* __restrict__ W,
+                                                                const float* __restrict__ bias,
+                                                                bf16* __restrict__ out) {
+  constexpr int HIN = 8, CIN = 128, COUT = 128, KC = 4, NT = 4;
+  __shared__ __align__(16) bf16 sW5[kC5WElems];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int i = lane & 15, g = lane >> 4, oy = i >> 2, ox = i & 3;
+  const unsigned keep = 0u - (unsigned)(ox != 0);   // 0 for the first lane of a 4-lane segment
+  const int chh = (int)(blockIdx.x & 1);
+  // fragment (tap, c, t), lane l: 16 bytes of W[co = 64 chh + 16t + l % 16][tap][32c + 8(l / 16) ..]
+  for (int e = tid; e < kC5WElems / 8; e += 64 * kC5Waves) {
+    const int l = e & 63, f = e >> 6, t = f & 3, c = (f >> 2) & 3, tap = f >> 4;
+    *reinterpret_cast<bf16x8*>(sW5 + 8 * e) =
+        load8(W + ((64 * chh + 16 * t + (l & 15)) * 9 + tap) * CIN + 32 * c + 8 * (l >> 4));
+  }
+  __syncthreads();
+  floatx4 bv[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) bv[t] = *reinterpret_cast<const floatx4*>(bias + 64 * chh + 16 * t + 4 * g);
+  // x[ky] = even column c = 0 .. 3, then odd column c = 0 .. 3 of input row
+  // 2 oy + ky - 1 (<= 7; < 0 only for oy = 0, ky = 0: zeros)
+  bf16x8 x[3][2 * KC];
+  auto fetch = [&](int64_t b) {
+#pragma unroll
+    for (int ky = 0; ky < 3; ++ky) {
+      const int row = 2 * oy + ky - 1;
+      const bool ok = row >= 0;
+      const bf16* p = in + ((b * HIN + (ok ? row : 0)) * HIN + 2 * ox) * CIN + 8 * g;
+#pragma unroll
+      for (int q = 0; q < 2 * KC; ++q) {
+        const bf16x8 val = load8(p + (q / KC) * CIN + 32 * (q % KC));
+        x[ky][q] = ok ? val : zero8();
+      }
+    }
+  };
+  // workgroups 2w and 2w + 1 take the two halves of the same poses
+  const int64_t wave0 = (int64_t)(blockIdx.x >> 1) * kC5Waves + __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int64_t n_waves = (int64_t)(gridDim.x >> 1) * kC5Waves;
+  for (int64_t b = wave0; b < n_poses; b += n_waves) {
+    fetch(b);
+    int wofs = 8 * lane;   // opaque to the compiler: no hoisting of the fragment reads
+    asm volatile("" : "+v"(wofs));
+    floatx4 acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = bv[t];
+    bf16x8 wa[NT], wb[NT];
+    // group k = (tap, c), 36 groups of NT products sharing one B operand
+    auto wload = [&](int k, bf16x8 (&w)[NT]) {
+#pragma unroll
+      for (int t = 0; t < NT; ++t) w[t] = *reinterpret_cast<const bf16x8*>(sW5 + (k * NT + t) * kC3Frag + wofs);
+    };
+    auto products = [&](int k, const bf16x8 (&w)[NT]) {
+      const int c = k % KC, tap = k / KC, ky = tap / 3, kx = tap % 3;
+      const bf16x8 xo = x[ky][KC + c];
+      const bf16x8 xv = kx == 1 ? x[ky][c] : kx == 2 ? xo : shift_right1_masked(xo, keep);
+#pragma unroll
+      for (int t = 0; t < NT; ++t) acc[t] = mfma(w[t], xv, acc[t]);
+    };
+    wload(0, wa);
+#pragma unroll
+    for (int k = 0; k < 9 * KC; k += 2) {
+      wload(k + 1, wb);
+      products(k, wa);
+      __builtin_amdgcn_sched_barrier(0);
+      if (k + 2 < 9 * KC) wload(k + 2, wa);
+      products(k + 1, wb);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    // D[n][p]: channels 64 chh + 16t + 4g + r of pixel (oy, ox)
+    const int64_t pix = (b * 4 + oy) * 4 + ox;
+    bf16* op = out + pix * COUT + 64 * chh + 4 * g;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      uint2 w;
+      w.x = pack2(relu(acc[t][0]), relu(acc[t][1]));
+      w.y = pack2(relu(acc[t][2]), relu(acc[t][3]));
+      *reinterpret_cast<uint2*>(op + 16 * t) = w;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // conv1 fused into conv2 (inference and training).  A workgroup owns 8 x 8 output pixels of
 // conv2 (all 64 channels) at a time: it gathers the 35 x 35 patch window those
 // pixels depend on, computes the 17 x 17 x 32 conv1 outputs of the window into
@@ -585,12 +689,6 @@ constexpr int kT2 = 8;                 // conv2 tile edge (output pixels)
 constexpr int kT1 = 2 * kT2 + 1;       // 17: conv1 window edge
 constexpr int kTP = 2 * kT1 + 1;       // 35: patch window edge
 constexpr int kA1Px = 40;              // bf16 per conv1 pixel in LDS (32 channels + 8 pad)
-// LDS slot of conv1 window pixel (y, x): each row holds its even columns, then
-// its odd ones.  conv2 reads 16 pixels two columns apart per fragment, which
-// this makes neighbouring slots, 80 bytes apart: the 8 lanes that one LDS
-// cycle serves then fall on distinct banks (at a 160-byte stride lanes i and
-// i + 4 share them).
-FSMI_DEV int a1_slot(int y, int x) { return y * kT1 + ((x & 1) ? (kT1 + 1) / 2 + (x >> 1) : x >> 1); }
 constexpr int kPatchPer = (kTP * kTP + 255) / 256;   // gathers per thread
 
 // A thread's share of a tile's patch window: element e = tid + 256 k at row
@@ -700,7 +798,7 @@ __global__ __launch_bounds__(256) void k_conv12_fwd(int64_t n_tiles, PatchSrc sr
   // conv1 pixels of this lane (p = 16 m + i, m = wave, wave + 4, ...): their
   // place in the window and their patch offset, the same for every tile
   constexpr int kC1 = (19 + 3) / 4;   // column tiles of 16 per wave, at most
-  int c1_pr[kC1], c1_pc[kC1], c1_base[kC1], c1_slot[kC1];
+  int c1_pr[kC1], c1_pc[kC1], c1_base[kC1];
 #pragma unroll
   for (int u = 0; u < kC1; ++u) {
     const int p = 16 * (wave + 4 * u) + i;
@@ -708,7 +806,6 @@ __global__ __launch_bounds__(256) void k_conv12_fwd(int64_t n_tiles, PatchSrc sr
     c1_pr[u] = pv ? p / kT1 : -1000;          // -1000: outside any grid
     c1_pc[u] = pv ? p - (p / kT1) * kT1 : 0;
     c1_base[u] = pv ? 2 * c1_pr[u] * kTP + 2 * c1_pc[u] : 0;
-    c1_slot[u] = pv ? a1_slot(c1_pr[u], c1_pc[u]) : 0;
   }
   // Two-stage pipeline over the workgroup's tiles j = 0, 1, ...: step j runs
   // conv1 of tile j (patch buffer j % 2 -> conv1 buffer j % 2) beside conv2
@@ -744,10 +841,11 @@ __global__ __launch_bounds__(256) void k_conv12_fwd(int64_t n_tiles, PatchSrc sr
       for (int u = 0; u < kC1; ++u) {
         const int m = wave + 4 * u;
         if (m >= 19) break;                       // wave-uniform
-        const bool pv = c1_pr[u] >= 0;            // pixel 16 m + i of the window
+        const int p = 16 * m + i;
+        const bool pv = c1_pr[u] >= 0;
         const int pr = pv ? c1_pr[u] : 0, pc = c1_pc[u];
         const int base = c1_base[u];
-        bf16x4 x;   // B operand: taps 4g .. 4g + 3 of the pixel
+        bf16x4 x;   // B operand: taps 4g .. 4g + 3 of pixel p
 #pragma unroll
         for (int q = 0; q < 4; ++q) x[q] = P[base + toff[q]];
         const int y1 = 2 * oy0 - 1 + pr, x1 = 2 * ox0 - 1 + pc;
@@ -757,7 +855,7 @@ __global__ __launch_bounds__(256) void k_conv12_fwd(int64_t n_tiles, PatchSrc sr
         uint32_t bits = 0;
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
-          // D[n][p]: channels 16t + 4g + r of the pixel, the bias as the accumulator's start
+          // D[n][p]: channels 16t + 4g + r of pixel p, the bias as the accumulator's start
           const floatx4 d = mfma16(w1[t], x, floatx4{bias1[t][0], bias1[t][1], bias1[t][2], bias1[t][3]});
           float o[4];
 #pragma unroll
@@ -766,7 +864,7 @@ __global__ __launch_bounds__(256) void k_conv12_fwd(int64_t n_tiles, PatchSrc sr
             uint2 w;
             w.x = inside ? pack2(o[0], o[1]) : 0u;
             w.y = inside ? pack2(o[2], o[3]) : 0u;
-            *reinterpret_cast<uint2*>(A1 + c1_slot[u] * kA1Px + 16 * t + 4 * g) = w;
+            *reinterpret_cast<uint2*>(A1 + p * kA1Px + 16 * t + 4 * g) = w;
             if (owned) {
               *reinterpret_cast<uint2*>(act1 + pix1 * 32 + 16 * t + 4 * g) = w;
               bits |= sign4(w) << (4 * t);
@@ -798,7 +896,7 @@ __global__ __launch_bounds__(256) void k_conv12_fwd(int64_t n_tiles, PatchSrc sr
         const int ky = tap / 3, kx = tap % 3;
 #pragma unroll
         for (int mm = 0; mm < 2; ++mm) {
-          const bf16x8 x = load8(A1 + a1_slot(2 * qy[mm] + ky, 2 * qx[mm] + kx) * kA1Px + 8 * g);
+          const bf16x8 x = load8(A1 + ((2 * qy[mm] + ky) * kT1 + 2 * qx[mm] + kx) * kA1Px + 8 * g);
 #pragma unroll
           for (int tt = 0; tt < 2; ++tt) acc[mm][tt] = mfma(w2r[tap][tt], x, acc[mm][tt]);
         }
@@ -1857,6 +1955,14 @@ static void conv_fwd(fsmi_sur net, int64_t nb, bool save) {
     hipLaunchKernelGGL(k_conv4_rows, dim3(grid), dim3(64 * kC4Waves), 0,
                        net->ctx->stream, units, net->act[L], net->Wbf + wbf_off(L), net->P + b_off(L),
                        net->act[L + 1], save ? (uint32_t*)net->sign[L + 1] : nullptr);
+    return;
+  }
+  if constexpr (L == 4) {
+    static_assert(d.cin == 128 && d.cout == 128 && d.hin == 8, "k_conv5_rows is written for conv5");
+    const int grid = 2 * (int)std::min<int64_t>((nb + kC5Waves - 1) / kC5Waves, (int64_t)net->ctx->num_cu / 2);
+    (void)save;   // act5 has no sign words
+    hipLaunchKernelGGL(k_conv5_rows, dim3(grid), dim3(64 * kC5Waves), 0, net->ctx->stream, nb,
+                       net->act[L], net->Wbf + wbf_off(L), net->P + b_off(L), net->act[L + 1]);
     return;
   }
   const int64_t npix = nb * (d.hin / 2) * (d.hin / 2);
