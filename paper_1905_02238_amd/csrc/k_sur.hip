@@ -177,110 +177,16 @@ FSMI_DEV uint32_t sign4(uint2 w) {
 }
 
 // ---------------------------------------------------------------------------
-// Forward convolution, layers after the first: one wave = MT column tiles of
-// 16 output pixels x all COUT channels, so every weight fragment it reads
-// feeds MT products (MT = 4, or 2 for 128 channels; more or fewer measured
-// slower).  Products are taken transposed (weights as the A operand), so a
-// lane ends with four consecutive channels of one pixel and stores 8 bytes at
-// once.  npix is a multiple of 16.  Each tap's weights are staged in LDS: the
-// workgroup copies W[:, tap, :] (COUT x CIN, rows padded by 16 bytes so the 16
-// rows a fragment reads fall in different banks) once, and its four waves read
-// their weight fragments from LDS instead of each fetching them from L2.  The
-// activation fragments of the tap are issued before the barrier.  Waves past
-// the last pixel still take every barrier.
+// Forward convolutions after conv2 (k_conv3_rows, k_conv4_rows, k_conv5_rows)
+// share these conventions.  Activations are BF16, pixel-major with the
+// channels of a pixel contiguous (act[pixel][channel], pixels row-major per
+// pose).  Products are taken transposed: the weights W[co][tap][ci] are the A
+// operand (16 output channels x 32 input channels) and 16 output pixels' input
+// channels the B operand, so D[n][p] leaves lane (i, g) with channels
+// 16t + 4g .. + 3 of pixel i, stored as one 8-byte word, and the bias starts
+// the accumulator.  In training the kernels also write the ReLU sign words of
+// their output (SignWord layout above).
 // ---------------------------------------------------------------------------
-template <int CIN, int COUT, int HIN>
-constexpr int conv_mt() { return COUT >= 128 ? 2 : 4; }
-
-template <int CIN, int COUT>
-constexpr int conv_lds_row() { return CIN + 8; }
-
-template <int CIN, int COUT, int HIN>
-__global__ __launch_bounds__(256) void k_conv_fwd_lds(int64_t npix, const bf16* __restrict__ in,
-                                                      const bf16* __restrict__ W,
-                                                      const float* __restrict__ bias,
-                                                      bf16* __restrict__ out,
-                                                      void* __restrict__ sign) {
-  constexpr int HOUT = HIN / 2, NT = COUT / 16, MT = conv_mt<CIN, COUT, HIN>();
-  constexpr int KC = CIN / 32, ROW = conv_lds_row<CIN, COUT>();
-  __shared__ __align__(16) bf16 sW[COUT * ROW];
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int64_t base = ((int64_t)blockIdx.x * 4 + wave) * (16 * MT);
-  const int n_mt = base < npix ? (int)min<int64_t>(MT, (npix - base) / 16) : 0;   // wave-uniform
-  const int i = lane & 15, g = lane >> 4;
-  int64_t pb[MT];
-  int poy[MT], pox[MT];
-#pragma unroll
-  for (int m = 0; m < MT; ++m) {
-    const int64_t p = min<int64_t>(base + 16 * m + i, npix - 1);
-    pb[m] = p / (HOUT * HOUT);
-    poy[m] = (int)((p / HOUT) % HOUT);
-    pox[m] = (int)(p % HOUT);
-  }
-  floatx4 acc[MT][NT];   // D[n][p]: channels 16t + 4g + r of pixel base + 16m + i; the bias as the start
-#pragma unroll
-  for (int t = 0; t < NT; ++t) {
-    const floatx4 bv = floatx4{bias[16 * t + 4 * g], bias[16 * t + 4 * g + 1], bias[16 * t + 4 * g + 2],
-                               bias[16 * t + 4 * g + 3]};
-#pragma unroll
-    for (int m = 0; m < MT; ++m) acc[m][t] = bv;
-  }
-#pragma unroll 1
-  for (int tap = 0; tap < 9; ++tap) {
-    const int ky = tap / 3, kx = tap % 3;
-    bf16x8 a[MT][KC];
-#pragma unroll
-    for (int m = 0; m < MT; ++m) {
-      const int iy = 2 * poy[m] + ky - 1, ix = 2 * pox[m] + kx - 1;
-      const bool ok = m < n_mt && iy >= 0 && iy < HIN && ix >= 0 && ix < HIN;
-      const bf16* ip = in + ((pb[m] * HIN + (ok ? iy : 0)) * HIN + (ok ? ix : 0)) * CIN;
-#pragma unroll
-      for (int c = 0; c < KC; ++c) a[m][c] = ok ? load8(ip + 32 * c + 8 * g) : zero8();
-    }
-    for (int e8 = tid; e8 < COUT * CIN / 8; e8 += 256) {
-      const int co = e8 / (CIN / 8), cc = e8 - co * (CIN / 8);
-      *reinterpret_cast<bf16x8*>(sW + co * ROW + 8 * cc) = load8(W + (co * 9 + tap) * CIN + 8 * cc);
-    }
-    __syncthreads();
-    if (n_mt > 0) {
-#pragma unroll
-      for (int c = 0; c < KC; ++c)
-#pragma unroll
-        for (int t = 0; t < NT; ++t) {
-          const bf16x8 w = *reinterpret_cast<const bf16x8*>(sW + (16 * t + i) * ROW + 32 * c + 8 * g);
-#pragma unroll
-          for (int m = 0; m < MT; ++m)
-            if (m < n_mt) acc[m][t] = mfma(w, a[m][c], acc[m][t]);
-        }
-    }
-    __syncthreads();
-  }
-  if (n_mt == 0) return;
-#pragma unroll
-  for (int m = 0; m < MT; ++m) {
-    if (m >= n_mt) break;
-    const int64_t pix = base + 16 * m + i;
-    bf16* op = out + pix * COUT + 4 * g;
-    uint32_t bits = 0;
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      float o[4];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) o[r] = relu(acc[m][t][r]);
-      uint2 w;
-      w.x = pack2(o[0], o[1]);
-      w.y = pack2(o[2], o[3]);
-      *reinterpret_cast<uint2*>(op + 16 * t) = w;
-      bits |= sign4(w) << (4 * t);
-    }
-    if (sign) {   // training: the next layer's input gradient reads these
-      typedef typename SignWord<NT>::type S;
-      reinterpret_cast<S*>(sign)[4 * pix + g] = (S)bits;
-    }
-  }
-}
-
 // ---------------------------------------------------------------------------
 // conv3 (64 -> 64 channels, 32^2 -> 16^2) by input rows.  An output row is 16
 // pixels, one per lane i of a lane group, so a wave takes four output rows oy0
@@ -291,13 +197,13 @@ __global__ __launch_bounds__(256) void k_conv_fwd_lds(int64_t npix, const bf16* 
 // one lane shift within the 16-lane row (lane 0 gets 0: the zero padding left
 // of column 0).  Input row 2(oy0 + m) + ky is tap row ky of output row m, so a
 // row feeds one or two output rows as it arrives, and no input byte is read
-// twice by a wave (the k_conv_fwd_lds form reads each 2.25 times, from all
-// over the pose, and its concurrent workgroups' poses exceed the L2).  All
+// twice by a wave (a tap-by-tap loop reads each 2.25 times, from all
+// over the pose: 9 taps x 256 pixels x 128 bytes, and concurrent workgroups'
+// poses exceed the L2, so most of it comes from HBM again).  All
 // nine taps' weights sit in LDS as 72 fragments of 1 KiB (fragment (tap, c, t)
 // = lane l's W[16t + l % 16][tap][32c + 8(l / 16) .. + 7] at 16 l), staged
 // once by each persistent workgroup; the waves then run their units without
-// barriers.  Products are taken transposed (weights as the A operand), as in
-// k_conv_fwd_lds, whose output and sign layouts this kernel keeps.
+// barriers.
 // ---------------------------------------------------------------------------
 constexpr int kC3Waves = 4;                           // waves per workgroup
 constexpr int kC3Frag = 512;                          // bf16 per weight fragment
@@ -454,8 +360,7 @@ __global__ __launch_bounds__(64 * kC3Waves, 2) void k_conv3_rows(int64_t n_units
 // shift that leaves lanes i % 8 = 0 at 0 (the zero padding).  All nine
 // taps' weights, 144 fragments of 1 KiB, fill one persistent workgroup's LDS
 // (one workgroup of eight waves per compute unit); each wave loads its next
-// unit's three tap rows while it computes the current one.  Output and sign
-// layouts are those of k_conv_fwd_lds.
+// unit's three tap rows while it computes the current one.
 // ---------------------------------------------------------------------------
 constexpr int kC4Waves = 8;
 constexpr int kC4WElems = 9 * 2 * 8 * kC3Frag;       // 144 KiB
@@ -577,8 +482,8 @@ __global__ __launch_bounds__(64 * kC4Waves, 2) void k_conv4_rows(int64_t n_units
 // (chh = its index % 2), and a unit is (pose, half).  Tap row ky of lane i
 // reads input row 2 (i / 4) + ky - 1, columns 2 (i % 4) and 2 (i % 4) + 1,
 // channels 32c + 8g .. + 7 (c = 0 .. 3); the odd column to the left is a
-// lane shift that leaves lanes i % 4 = 0 at 0.  The output layout is that of
-// k_conv_fwd_lds; no sign words (the head's backward reads act5 itself).
+// lane shift that leaves lanes i % 4 = 0 at 0.  No sign words: the head's
+// backward reads act5 itself.
 // ---------------------------------------------------------------------------
 constexpr int kC5Waves = 8;
 constexpr int kC5WElems = 9 * 4 * 4 * kC3Frag;       // 144 KiB: one half's weights
@@ -1965,12 +1870,7 @@ static void conv_fwd(fsmi_sur net, int64_t nb, bool save) {
                        net->act[L], net->Wbf + wbf_off(L), net->P + b_off(L), net->act[L + 1]);
     return;
   }
-  const int64_t npix = nb * (d.hin / 2) * (d.hin / 2);
-  constexpr int per_block = 4 * 16 * conv_mt<d.cin, d.cout, d.hin>();   // 4 waves
-  const int64_t blocks = (npix + per_block - 1) / per_block;
-  hipLaunchKernelGGL((k_conv_fwd_lds<d.cin, d.cout, d.hin>), dim3((unsigned)blocks), dim3(256), 0,
-                     net->ctx->stream, npix, net->act[L], net->Wbf + wbf_off(L), net->P + b_off(L),
-                     net->act[L + 1], save && L + 1 <= 4 ? net->sign[L + 1] : nullptr);
+  static_assert(L <= 4, "five conv layers");
 }
 
 // Forward of nb (<= max_batch) poses; predictions (standardised) in ypred.
