@@ -50,9 +50,9 @@ SLOTS_PER_PAIR = 13.5
 # 131087 KiB for 262144 KiB read, WRITE_SIZE 262144 KiB for 262144 KiB written).
 # They describe the kernel built from the sources hashed here; with any other
 # sources the bench reports traffic as null.
-TRAFFIC = {"fetch_kib": 14473762.25, "write_kib": 48776.125,
-           "fetch_scale": 262144.0 / 131087.8125, "write_scale": 1.0,
-           "sources_sha256": "2ee2a730d606972c2f23490515820eefb38516ec533f8f6c07112c9b279d6f75"}
+TRAFFIC = {"fetch_kib": 14442139.5, "write_kib": 48907.15625,
+           "fetch_scale": 262144.0 / 131088.125, "write_scale": 1.0,
+           "sources_sha256": "0296ee517ea6aef35a2cec810b18771a030cb6e247a647807e5f4c9c48559d99"}
 TRAFFIC_SOURCES = ("paper_1905_02238_amd/csrc/k_pose.hip", "paper_1905_02238_amd/csrc/beam_dev.h",
                    "paper_1905_02238_amd/csrc/ray_dev.h", "paper_1905_02238_amd/csrc/fsmi_dev.h",
                    "paper_1905_02238_amd/csrc/fsmi_internal.h", "paper_1905_02238_amd/csrc/lut_dev.h",
@@ -89,49 +89,49 @@ COUNTER_SOURCES = tuple(sorted(
     for dp, _, fs in os.walk(os.path.join(ROOT, "paper_1905_02238_amd", "csrc"))
     for f in fs if f.endswith((".hip", ".h")))) + ("paper_1905_02238_amd/build.py",)
 COUNTER_PROFILES = {
-    "sources_sha256": "4f7cc79c3d5c7433121f3b440d9c603f514ffcd556a4ba50c24b1ac66ab96c36",
+    "sources_sha256": "f5dd68028aa05098ef923efe6aca6c3857ad43d4a3d17391f51d6e5741979bb2",
     "paths": {
         "2d_exact": {"profile": "profiles/k_poses2d_exact_grid2048_4096x360.md",
-                     "kernel_ms": 135.19, "valu_busy": 1.291, "mfma_busy": 0.0,
-                     "fetch_write_GBps": 225, "bound": "alu",
-                     "frac": 0.81, "frac_of": "13-slot pair peak 3.02e12 pairs/s"},
+                     "kernel_ms": 132.12, "valu_busy": 1.259, "mfma_busy": 0.0,
+                     "fetch_write_GBps": 224, "bound": "alu",
+                     "frac": 0.76, "frac_of": "12-slot pair peak 3.28e12 pairs/s"},
         "2d_approx_delta9": {"profile": "profiles/k_poses2d_approx_delta9_grid2048_4096x360.md",
-                             "kernel_ms": 14.59, "valu_busy": 1.246, "mfma_busy": 0.0,
-                             "fetch_write_GBps": 2185, "bound": "alu",
-                             "frac": 0.30, "frac_of": "13-slot pair peak, tail evaluations"},
+                             "kernel_ms": 14.20, "valu_busy": 1.237, "mfma_busy": 0.0,
+                             "fetch_write_GBps": 2246, "bound": "alu",
+                             "frac": 0.29, "frac_of": "12-slot pair peak, tail evaluations"},
         "2d_uniform_h6": {"profile": "profiles/k_poses2d_uniform_h6_grid2048_4096x360.md",
-                          "kernel_ms": 7.06, "valu_busy": 0.959, "mfma_busy": 0.0,
-                          "fetch_write_GBps": 4525, "bound": "alu",
-                          "frac": 0.959, "frac_of": "VALU busy"},
+                          "kernel_ms": 6.97, "valu_busy": 0.958, "mfma_busy": 0.0,
+                          "fetch_write_GBps": 4581, "bound": "alu",
+                          "frac": 0.958, "frac_of": "VALU busy"},
         "2d_exact_lut": {"profile": "profiles/k_poses2d_exact_lut_grid2048_4096x360.md",
-                         "kernel_ms": 91.14, "valu_busy": 1.023, "mfma_busy": 0.0,
-                         "fetch_write_GBps": 335, "bound": "alu",
-                         "frac": 1.023, "frac_of": "VALU busy"},
+                         "kernel_ms": 90.74, "valu_busy": 1.024, "mfma_busy": 0.0,
+                         "fetch_write_GBps": 337, "bound": "alu",
+                         "frac": 1.024, "frac_of": "VALU busy"},
         "3d_exact": {"profile": "profiles/k_poses3d_voxels512_1024x16384.md",
-                     "kernel_ms": 45.43, "valu_busy": 0.765, "mfma_busy": 0.218,
-                     "fetch_write_GBps": 3809, "bound": "alu", "frac": 0.765,
+                     "kernel_ms": 45.41, "valu_busy": 0.762, "mfma_busy": 0.218,
+                     "fetch_write_GBps": 3813, "bound": "alu", "frac": 0.762,
                      "frac_of": "VALU busy"},
         "3d_approx_delta6": {"profile": "profiles/k_poses3d_voxels512_1024x16384.md",
-                             "kernel_ms": 34.22, "valu_busy": 0.985, "mfma_busy": 0.0,
-                             "fetch_write_GBps": 5139, "bound": "alu", "frac": 0.985,
+                             "kernel_ms": 34.19, "valu_busy": 0.981, "mfma_busy": 0.0,
+                             "fetch_write_GBps": 5145, "bound": "alu", "frac": 0.981,
                              "frac_of": "VALU busy"},
         "3d_uniform_h4": {"profile": "profiles/k_poses3d_voxels512_1024x16384.md",
-                          "kernel_ms": 26.70, "valu_busy": 0.857, "mfma_busy": 0.0,
-                          "fetch_write_GBps": 6510, "bound": "alu", "frac": 0.857,
+                          "kernel_ms": 26.75, "valu_busy": 0.856, "mfma_busy": 0.0,
+                          "fetch_write_GBps": 6504, "bound": "alu", "frac": 0.856,
                           "frac_of": "VALU busy"},
         "uneven_100k_exact": {"profile": "profiles/k_eval_fused_uneven_100k.md",
-                              "kernel_ms": 1.45, "valu_busy": 0.34, "mfma_busy": 0.34,
-                              "fetch_write_GBps": 116, "bound": "mfma", "frac": 0.34,
+                              "kernel_ms": 1.43, "valu_busy": 0.352, "mfma_busy": 0.347,
+                              "fetch_write_GBps": 123, "bound": "mfma", "frac": 0.35,
                               "frac_of": "FP32 matrix peak 7.86e13 MAC/s over the launch "
-                                         "(0.50 ms of matrix work in 1.45 ms)"},
+                                         "(0.50 ms of matrix work in 1.43 ms)"},
         "surrogate_forward": {"profile": "profiles/surrogate_forward_rank_65536.md",
-                              "kernel_ms": 1.94, "valu_busy": 0.53, "mfma_busy": 0.147,
-                              "fetch_write_GBps": 5765, "bound": "mfma", "frac": 0.124,
-                              "frac_of": "2.5 PFLOP/s BF16 dense (per batch of 8192; conv3 "
-                                         "at 72 % of HBM peak)"},
+                              "kernel_ms": 1.329, "valu_busy": 0.474, "mfma_busy": 0.198,
+                              "fetch_write_GBps": 4773, "bound": "mfma", "frac": 0.18,
+                              "frac_of": "2.5 PFLOP/s BF16 dense (per batch of 8192; the five "
+                                         "kernels' MFMA busy 20-27 %, conv3 at 60 % of HBM peak)"},
         "surrogate_training": {"profile": "profiles/surrogate_training_step_1024.md",
-                               "kernel_ms": 1.164, "valu_busy": 0.46, "mfma_busy": 0.09,
-                               "fetch_write_GBps": None, "bound": "mfma", "frac": 0.077,
+                               "kernel_ms": 1.072, "valu_busy": 0.47, "mfma_busy": 0.13,
+                               "fetch_write_GBps": None, "bound": "mfma", "frac": 0.084,
                                "frac_of": "2.5 PFLOP/s BF16 dense (per step of 1024)"},
     }}
 
