@@ -956,6 +956,7 @@ def surrogate_leg(ctx, F, W, t, timed, args):
     tnet = F.Surrogate(ctx, seed=5, max_batch=tb, patch_stride=args.sur_stride)
     tnet.fit_label_stats(torch.cat([d[2] for d in train]))
     g0, p0, mi0 = train[0]
+    rng = np.random.default_rng(11)
     sels = [torch.from_numpy(rng.choice(p0.shape[0], tb, replace=False)).to(g0.device)
             for _ in range(13)]
     batches = [(p0[s_].contiguous(), mi0[s_].contiguous()) for s_ in sels]
