@@ -97,11 +97,20 @@ FSMI_DEV bf16x8 zero8() {
 // block, the same for every pixel.  So the patch moves with the pose's
 // sub-block position.  With cell stride s > 1, `map` is the map of s x s
 // block means; s = 1 reads the map itself.
+// A pose's block (bx, by) and its fraction (fx, fy) inside that block: what
+// every tile of its patch needs from the pose, computed once per pose of a
+// batch (k_patch_origin) instead of once per tile (four FP64 divisions).
+struct PatchOrigin {
+  int bx, by;
+  float fx, fy;
+};
+
 struct PatchSrc {
   const float* map;
   int64_t X, Y;          // dims of `map`
   const double* poses;   // [n][4]
   int s;                 // cell stride
+  const PatchOrigin* org = nullptr;   // per pose of the batch (k_patch_origin)
   // floor(floor(v) / s), exact in FP64 for |v| < 2^53 (a quotient of
   // integers below 2^53 that is not whole lies at least 1/s from the next
   // whole number, more than its rounding error), held within +-(2^31 - 2^10)
@@ -125,6 +134,13 @@ struct PatchSrc {
   FSMI_DEV float bilinear(int bx, int by, float fx, float fy) const {
     return lerp2(at(bx, by), at(bx + 1, by), at(bx, by + 1), at(bx + 1, by + 1), fx, fy);
   }
+  // block and fraction of pose b, from the pose
+  FSMI_DEV PatchOrigin origin_of_pose(int64_t b) const {
+    const double x = poses[4 * b], y = poses[4 * b + 1];
+    return PatchOrigin{block(x), block(y), frac(x), frac(y)};
+  }
+  // the same, from the batch's table (the patch kernels run after k_patch_origin)
+  FSMI_DEV PatchOrigin origin(int64_t b) const { return org[b]; }
   // a, b: blocks (bx, by), (bx + 1, by); c, d: the row below
   static FSMI_DEV float lerp2(float a, float b, float c, float d, float fx, float fy) {
     const float top = fmaf(fx, b - a, a), bot = fmaf(fx, d - c, c);
@@ -145,6 +161,13 @@ __global__ void k_pool_map(const float* __restrict__ map, int64_t X, int64_t Y, 
       for (int64_t x = s * u; x < x1; ++x) acc += (double)map[x + X * y];
     out[i] = (float)(acc / (double)((x1 - s * u) * (y1 - s * v)));
   }
+}
+
+// PatchOrigin of each of the batch's n poses.
+__global__ void k_patch_origin(int64_t n, PatchSrc src, PatchOrigin* __restrict__ out) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = src.origin_of_pose(i);
 }
 
 // Two floats as packed BF16 (round to nearest even), low half first: one
@@ -622,10 +645,10 @@ FSMI_DEV void gather_window(const PatchSrc& src, int64_t tile, const WinOffs& w,
   const int64_t b = tile >> 4;
   const int oy0 = kT2 * (int)((tile >> 2) & 3), ox0 = kT2 * (int)(tile & 3);
   const int py0 = 4 * oy0 - 3, px0 = 4 * ox0 - 3;   // patch window origin
-  const double x = src.poses[4 * b], y = src.poses[4 * b + 1];
-  const int cx0 = src.block(x) - kPatch / 2 + px0;
-  const int cy0 = src.block(y) - kPatch / 2 + py0;
-  const float fx = src.frac(x), fy = src.frac(y);
+  const PatchOrigin og = src.origin(b);
+  const int cx0 = og.bx - kPatch / 2 + px0;
+  const int cy0 = og.by - kPatch / 2 + py0;
+  const float fx = og.fx, fy = og.fy;
   // window rows and columns before the patch's first (the window never
   // reaches past its last: py0, px0 <= 93 and 93 + 34 < 128)
   const int rmin = py0 < 0 ? -py0 : 0, cmin = px0 < 0 ? -px0 : 0;
@@ -935,10 +958,10 @@ __global__ __launch_bounds__(256, WG1 ? 4 : 1) void k_conv_dgrad(int64_t nq, int
       // staged column c = patch column c - 1, read from the map (PatchSrc)
       const int64_t b0 = base / (HOUT * HOUT);
       const int a0 = (int)((base / HOUT) % HOUT);
-      const double x = src.poses[4 * b0], y = src.poses[4 * b0 + 1];
-      const int mx0 = src.block(x) - kPatch / 2;
-      const int my0 = src.block(y) - kPatch / 2;
-      const float fx = src.frac(x), fy = src.frac(y);
+      const PatchOrigin og = src.origin(b0);
+      const int mx0 = og.bx - kPatch / 2;
+      const int my0 = og.by - kPatch / 2;
+      const float fx = og.fx, fy = og.fy;
       for (int e = tid; e < 9 * SROW; e += 256) {
         const int r = e / SROW, c = e - r * SROW;
         const int iy = 4 * a0 - 1 + r, ix = c - 1;
@@ -1697,6 +1720,7 @@ struct fsmi_sur_s {
   void* sign[5] = {};            // sign[l]: ReLU sign words of act[l], l = 1..4 (training)
   float* pooled = nullptr;   // block means of the last map (stride > 1)
   size_t pooled_elems = 0;
+  fsmi::PatchOrigin* porg = nullptr;   // patch origins of the batch's poses
 };
 
 namespace fsmi {
@@ -1769,6 +1793,7 @@ static hipError_t sur_alloc(fsmi_sur net) {
   ALLOC(net->dysave, sizeof(float) * (size_t)B);
   ALLOC(net->dhsave, sizeof(float) * (size_t)B * kHid);
   ALLOC(net->ypred, sizeof(float) * (size_t)B);
+  ALLOC(net->porg, sizeof(PatchOrigin) * (size_t)B);
   size_t mx = 0, mr = 0;
   for (int l = 0; l < 5; ++l) {
     const int hout = kL[l].hin / 2;
@@ -1792,7 +1817,8 @@ static hipError_t sur_alloc(fsmi_sur net) {
 
 static void sur_free(fsmi_sur net) {
   void* ps[] = {net->P, net->G, net->M, net->V, net->Wbf, net->Wt, net->stats, net->gsave,
-                net->hsave, net->dysave, net->dhsave, net->ypred, net->part, net->runs, net->hpart, net->loss};
+                net->hsave, net->dysave, net->dhsave, net->ypred, net->part, net->runs, net->hpart, net->loss,
+                net->porg};
   for (void* p : ps)
     if (p) (void)hipFree(p);
   if (net->pooled) (void)hipFree(net->pooled);
@@ -1874,9 +1900,13 @@ static void conv_fwd(fsmi_sur net, int64_t nb, bool save) {
 }
 
 // Forward of nb (<= max_batch) poses; predictions (standardised) in ypred.
-static hipError_t sur_fwd_batch(fsmi_sur net, int64_t nb, PatchSrc src, bool save) {
+// Sets src.org to the batch's patch origins, computed here.
+static hipError_t sur_fwd_batch(fsmi_sur net, int64_t nb, PatchSrc& src, bool save) {
   static_assert(kL[0].cout == 32 && kL[1].cin == 32 && kL[1].cout == 64 && kL[1].hin == 64,
                 "k_conv12_fwd is written for conv1 1->32 on 128^2 and conv2 32->64");
+  hipLaunchKernelGGL(k_patch_origin, dim3((unsigned)std::min<int64_t>((nb + 255) / 256, 1024)), dim3(256),
+                     0, net->ctx->stream, nb, src, net->porg);
+  src.org = net->porg;
   const int64_t n_tiles = nb * 16;
   const int grid12 = (int)std::min<int64_t>(n_tiles, (int64_t)net->ctx->num_cu * 2);
   if (save)   // training keeps conv1's activations and the sign words
