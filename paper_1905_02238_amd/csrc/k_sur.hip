@@ -617,6 +617,7 @@ constexpr int kT2 = 8;                 // conv2 tile edge (output pixels)
 constexpr int kT1 = 2 * kT2 + 1;       // 17: conv1 window edge
 constexpr int kTP = 2 * kT1 + 1;       // 35: patch window edge
 constexpr int kA1Px = 40;              // bf16 per conv1 pixel in LDS (32 channels + 8 pad)
+constexpr int kC1Tiles = 20;           // conv1 column tiles of 16 pixels per window (19 needed)
 constexpr int kPatchPer = (kTP * kTP + 255) / 256;   // gathers per thread
 
 // A thread's share of a tile's patch window: element e = tid + 256 k at row
@@ -682,7 +683,9 @@ __global__ __launch_bounds__(256) void k_conv12_fwd(int64_t n_tiles, PatchSrc sr
                                                     uint8_t* __restrict__ sign1,
                                                     uint16_t* __restrict__ sign2) {
   __shared__ __align__(16) bf16 sP[2][kTP * kTP + 8];
-  __shared__ __align__(16) bf16 sA1[2][kT1 * kT1 * kA1Px];
+  // conv1 buffers hold 20 column tiles of 16 pixels: the window's 289 and
+  // padding that the waves' fifth column tiles write without a branch
+  __shared__ __align__(16) bf16 sA1[2][kC1Tiles * 16 * kA1Px];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int i = lane & 15, g = lane >> 4;
@@ -724,8 +727,10 @@ __global__ __launch_bounds__(256) void k_conv12_fwd(int64_t n_tiles, PatchSrc sr
     for (int r = 0; r < 4; ++r) bias2[tt][r] = b2[16 * (2 * chh + tt) + 4 * g + r];
   const WinOffs woff = win_offsets(tid);
   // conv1 pixels of this lane (p = 16 m + i, m = wave, wave + 4, ...): their
-  // place in the window and their patch offset, the same for every tile
-  constexpr int kC1 = (19 + 3) / 4;   // column tiles of 16 per wave, at most
+  // place in the window and their patch offset, the same for every tile.
+  // Every wave takes five column tiles; pixels past the window's 289 (the
+  // last tile and a half) read the patch at 0 and write padding slots.
+  constexpr int kC1 = kC1Tiles / 4;
   int c1_pr[kC1], c1_pc[kC1], c1_base[kC1];
 #pragma unroll
   for (int u = 0; u < kC1; ++u) {
@@ -759,7 +764,7 @@ __global__ __launch_bounds__(256) void k_conv12_fwd(int64_t n_tiles, PatchSrc sr
   __syncthreads();
   for (int64_t j = 0; j <= n_my; ++j) {
     if (j < n_my) {
-      // conv1 on the window of tile j: 289 pixels in 19 column tiles of 16 (the last padded)
+      // conv1 on the window of tile j: 289 pixels in 20 column tiles of 16, five per wave
       const int64_t tile = tile_of(j);
       const int64_t b = tile >> 4;
       const int oy0 = kT2 * (int)((tile >> 2) & 3), ox0 = kT2 * (int)(tile & 3);
@@ -767,9 +772,7 @@ __global__ __launch_bounds__(256) void k_conv12_fwd(int64_t n_tiles, PatchSrc sr
       bf16* A1 = sA1[j & 1];
 #pragma unroll
       for (int u = 0; u < kC1; ++u) {
-        const int m = wave + 4 * u;
-        if (m >= 19) break;                       // wave-uniform
-        const int p = 16 * m + i;
+        const int p = 16 * (wave + 4 * u) + i;
         const bool pv = c1_pr[u] >= 0;
         const int pr = pv ? c1_pr[u] : 0, pc = c1_pc[u];
         const int base = c1_base[u];
@@ -788,15 +791,13 @@ __global__ __launch_bounds__(256) void k_conv12_fwd(int64_t n_tiles, PatchSrc sr
           float o[4];
 #pragma unroll
           for (int r = 0; r < 4; ++r) o[r] = relu(d[r]);
-          if (pv) {
-            uint2 w;
-            w.x = inside ? pack2(o[0], o[1]) : 0u;
-            w.y = inside ? pack2(o[2], o[3]) : 0u;
-            *reinterpret_cast<uint2*>(A1 + p * kA1Px + 16 * t + 4 * g) = w;
-            if (owned) {
-              *reinterpret_cast<uint2*>(act1 + pix1 * 32 + 16 * t + 4 * g) = w;
-              bits |= sign4(w) << (4 * t);
-            }
+          uint2 w;
+          w.x = inside ? pack2(o[0], o[1]) : 0u;
+          w.y = inside ? pack2(o[2], o[3]) : 0u;
+          *reinterpret_cast<uint2*>(A1 + p * kA1Px + 16 * t + 4 * g) = w;
+          if (owned) {
+            *reinterpret_cast<uint2*>(act1 + pix1 * 32 + 16 * t + 4 * g) = w;
+            bits |= sign4(w) << (4 * t);
           }
         }
         if (owned) sign1[4 * pix1 + g] = (uint8_t)bits;
