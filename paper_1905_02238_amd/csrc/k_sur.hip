@@ -618,6 +618,7 @@ constexpr int kT1 = 2 * kT2 + 1;       // 17: conv1 window edge
 constexpr int kTP = 2 * kT1 + 1;       // 35: patch window edge
 constexpr int kA1Px = 40;              // bf16 per conv1 pixel in LDS (32 channels + 8 pad)
 constexpr int kC1Tiles = 20;           // conv1 column tiles of 16 pixels per window (19 needed)
+constexpr int kPWin = kTP * kTP + 11;   // patch window in LDS: 1225 pixels, zero padding, 8-byte rows
 constexpr int kPatchPer = (kTP * kTP + 255) / 256;   // gathers per thread
 
 // A thread's share of a tile's patch window: element e = tid + 256 k at row
@@ -682,7 +683,7 @@ __global__ __launch_bounds__(256) void k_conv12_fwd(int64_t n_tiles, PatchSrc sr
                                                     bf16* __restrict__ act1,
                                                     uint8_t* __restrict__ sign1,
                                                     uint16_t* __restrict__ sign2) {
-  __shared__ __align__(16) bf16 sP[2][kTP * kTP + 8];
+  __shared__ __align__(16) bf16 sP[2][kPWin];
   // conv1 buffers hold 20 column tiles of 16 pixels: the window's 289 and
   // padding that the waves' fifth column tiles write without a branch
   __shared__ __align__(16) bf16 sA1[2][kC1Tiles * 16 * kA1Px];
@@ -699,25 +700,30 @@ __global__ __launch_bounds__(256) void k_conv12_fwd(int64_t n_tiles, PatchSrc sr
   for (int tap = 0; tap < 9; ++tap)
 #pragma unroll
     for (int tt = 0; tt < 2; ++tt) w2r[tap][tt] = load8(W2 + ((16 * (2 * chh + tt) + i) * 9 + tap) * 32 + 8 * g);
-  // A operand of conv1 (16 x 16 x 16): A[n][k] = W1[16t + n][k], k = tap 4g + q
-  // (< 9, else 0); the lane's taps sit at window offsets toff[q] from a
-  // pixel's base (the slots past the ninth tap read tap 0's pixel, which their
-  // zero weight cancels: the sum is the same as with a zero there)
+  // conv1 as a 16 x 16 x 16 product: A[n][k] = W1[16t + n][tap(k)], B[k][p] =
+  // the window pixel under tap(k) of conv1 pixel p.  The K slots are laid out
+  // so that lane group g reads its four B values as two aligned pairs of
+  // window pixels (two 4-byte LDS reads at offsets off0, off1 from the
+  // pixel's base, which is even): g = 0 takes taps (0,0) (0,1) | (0,2) -,
+  // g = 1 (1,1) (1,2) | - (1,0), g = 2 (2,0) (2,1) | (2,2) -, g = 3 nothing.
+  // A "-" slot has weight 0 and reads a neighbouring window pixel or the
+  // zeroed padding after the window: finite values, so the sum is the one
+  // over the nine taps.
   bf16x4 w1[2];
-  int toff[4];
+  int slot_tap[4];   // tap (3 ky + kx) of slot 4g + q, -1 for none
+  {
+    constexpr int kSlotTap[4][4] = {{0, 1, 2, -1}, {4, 5, -1, 3}, {6, 7, 8, -1}, {-1, -1, -1, -1}};
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int tap = 4 * g + q;
-    toff[q] = tap < 9 ? (tap / 3) * kTP + tap % 3 : 0;
+    for (int q = 0; q < 4; ++q) slot_tap[q] = kSlotTap[g][q];
   }
+  const int off0 = g == 1 ? kTP + 1 : g == 2 ? 2 * kTP : 0;
+  const int off1 = g == 0 ? 2 : g == 1 ? kTP - 1 : g == 2 ? 2 * kTP + 2 : 0;
   float bias1[2][4], bias2[2][4];
 #pragma unroll
   for (int t = 0; t < 2; ++t) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int tap = 4 * g + q;
-      w1[t][q] = tap < 9 ? W1[(16 * t + i) * 9 + tap] : (bf16)0.0f;
-    }
+    for (int q = 0; q < 4; ++q)
+      w1[t][q] = slot_tap[q] >= 0 ? W1[(16 * t + i) * 9 + slot_tap[q]] : (bf16)0.0f;
 #pragma unroll
     for (int r = 0; r < 4; ++r) bias1[t][r] = b1[16 * t + 4 * g + r];
   }
@@ -756,6 +762,7 @@ __global__ __launch_bounds__(256) void k_conv12_fwd(int64_t n_tiles, PatchSrc sr
       if (e < kTP * kTP) sP[buf][e] = (bf16)v[k];
     }
   };
+  if (tid < 2 * (kPWin - kTP * kTP)) sP[tid & 1][kTP * kTP + (tid >> 1)] = (bf16)0.0f;   // padding
   if (n_my > 0) {
     gather_window(src, tile_of(0), woff, v);
     stage_patch(0);
@@ -776,9 +783,11 @@ __global__ __launch_bounds__(256) void k_conv12_fwd(int64_t n_tiles, PatchSrc sr
         const bool pv = c1_pr[u] >= 0;
         const int pr = pv ? c1_pr[u] : 0, pc = c1_pc[u];
         const int base = c1_base[u];
-        bf16x4 x;   // B operand: taps 4g .. 4g + 3 of pixel p
-#pragma unroll
-        for (int q = 0; q < 4; ++q) x[q] = P[base + toff[q]];
+        // B operand: the window pixels of slots 4g .. 4g + 3 of pixel p
+        uint2 xw;
+        xw.x = *reinterpret_cast<const uint32_t*>(P + base + off0);
+        xw.y = *reinterpret_cast<const uint32_t*>(P + base + off1);
+        const bf16x4 x = __builtin_bit_cast(bf16x4, xw);
         const int y1 = 2 * oy0 - 1 + pr, x1 = 2 * ox0 - 1 + pc;
         const bool inside = pv && y1 >= 0 && y1 < 64 && x1 >= 0 && x1 < 64;
         const bool owned = SAVE && pv && pr >= 1 && pc >= 1;   // implies inside
