@@ -769,102 +769,115 @@ __global__ __launch_bounds__(256) void k_conv12_fwd(int64_t n_tiles, PatchSrc sr
     if (n_my > 1) gather_window(src, tile_of(1), woff, v);
   }
   __syncthreads();
-  for (int64_t j = 0; j <= n_my; ++j) {
-    if (j < n_my) {
-      // conv1 on the window of tile j: 289 pixels in 20 column tiles of 16, five per wave
-      const int64_t tile = tile_of(j);
-      const int64_t b = tile >> 4;
-      const int oy0 = kT2 * (int)((tile >> 2) & 3), ox0 = kT2 * (int)(tile & 3);
-      const bf16* P = sP[j & 1];
-      bf16* A1 = sA1[j & 1];
+  // conv1 on the window of tile j: 289 pixels in 20 column tiles of 16, five per wave
+  auto conv1_tile = [&](int64_t j) {
+    const int64_t tile = tile_of(j);
+    const int64_t b = tile >> 4;
+    const int oy0 = kT2 * (int)((tile >> 2) & 3), ox0 = kT2 * (int)(tile & 3);
+    const bf16* P = sP[j & 1];
+    bf16* A1 = sA1[j & 1];
 #pragma unroll
-      for (int u = 0; u < kC1; ++u) {
-        const int p = 16 * (wave + 4 * u) + i;
-        const bool pv = c1_pr[u] >= 0;
-        const int pr = pv ? c1_pr[u] : 0, pc = c1_pc[u];
-        const int base = c1_base[u];
-        // B operand: the window pixels of slots 4g .. 4g + 3 of pixel p
-        uint2 xw;
-        xw.x = *reinterpret_cast<const uint32_t*>(P + base + off0);
-        xw.y = *reinterpret_cast<const uint32_t*>(P + base + off1);
-        const bf16x4 x = __builtin_bit_cast(bf16x4, xw);
-        const int y1 = 2 * oy0 - 1 + pr, x1 = 2 * ox0 - 1 + pc;
-        const bool inside = pv && y1 >= 0 && y1 < 64 && x1 >= 0 && x1 < 64;
-        const bool owned = SAVE && pv && pr >= 1 && pc >= 1;   // implies inside
-        const int64_t pix1 = (b * 64 + y1) * 64 + x1;
-        uint32_t bits = 0;
+    for (int u = 0; u < kC1; ++u) {
+      const int p = 16 * (wave + 4 * u) + i;
+      const bool pv = c1_pr[u] >= 0;
+      const int pr = pv ? c1_pr[u] : 0, pc = c1_pc[u];
+      const int base = c1_base[u];
+      // B operand: the window pixels of slots 4g .. 4g + 3 of pixel p
+      uint2 xw;
+      xw.x = *reinterpret_cast<const uint32_t*>(P + base + off0);
+      xw.y = *reinterpret_cast<const uint32_t*>(P + base + off1);
+      const bf16x4 x = __builtin_bit_cast(bf16x4, xw);
+      const int y1 = 2 * oy0 - 1 + pr, x1 = 2 * ox0 - 1 + pc;
+      const bool inside = pv && y1 >= 0 && y1 < 64 && x1 >= 0 && x1 < 64;
+      const bool owned = SAVE && pv && pr >= 1 && pc >= 1;   // implies inside
+      const int64_t pix1 = (b * 64 + y1) * 64 + x1;
+      uint32_t bits = 0;
 #pragma unroll
-        for (int t = 0; t < 2; ++t) {
-          // D[n][p]: channels 16t + 4g + r of pixel p, the bias as the accumulator's start
-          const floatx4 d = mfma16(w1[t], x, floatx4{bias1[t][0], bias1[t][1], bias1[t][2], bias1[t][3]});
-          float o[4];
+      for (int t = 0; t < 2; ++t) {
+        // D[n][p]: channels 16t + 4g + r of pixel p, the bias as the accumulator's start
+        const floatx4 d = mfma16(w1[t], x, floatx4{bias1[t][0], bias1[t][1], bias1[t][2], bias1[t][3]});
+        float o[4];
 #pragma unroll
-          for (int r = 0; r < 4; ++r) o[r] = relu(d[r]);
-          uint2 w;
-          w.x = inside ? pack2(o[0], o[1]) : 0u;
-          w.y = inside ? pack2(o[2], o[3]) : 0u;
-          *reinterpret_cast<uint2*>(A1 + p * kA1Px + 16 * t + 4 * g) = w;
-          if (owned) {
-            *reinterpret_cast<uint2*>(act1 + pix1 * 32 + 16 * t + 4 * g) = w;
-            bits |= sign4(w) << (4 * t);
-          }
+        for (int r = 0; r < 4; ++r) o[r] = relu(d[r]);
+        uint2 w;
+        w.x = inside ? pack2(o[0], o[1]) : 0u;
+        w.y = inside ? pack2(o[2], o[3]) : 0u;
+        *reinterpret_cast<uint2*>(A1 + p * kA1Px + 16 * t + 4 * g) = w;
+        if (owned) {
+          *reinterpret_cast<uint2*>(act1 + pix1 * 32 + 16 * t + 4 * g) = w;
+          bits |= sign4(w) << (4 * t);
         }
-        if (owned) sign1[4 * pix1 + g] = (uint8_t)bits;
       }
+      if (owned) sign1[4 * pix1 + g] = (uint8_t)bits;
     }
-    if (j > 0) {
-      // conv2 of tile j - 1: pixels 16 (2 ph + mm) + i of the 8 x 8 tile, channel tiles 2 chh + tt
-      const int64_t tile = tile_of(j - 1);
-      const int64_t b = tile >> 4;
-      const int oy0 = kT2 * (int)((tile >> 2) & 3), ox0 = kT2 * (int)(tile & 3);
-      const bf16* A1 = sA1[(j - 1) & 1];
-      floatx4 acc[2][2];   // the bias as the accumulators' start
-      int qy[2], qx[2];
+  };
+  // conv2 of tile j: pixels 16 (2 ph + mm) + i of the 8 x 8 tile, channel tiles 2 chh + tt
+  auto conv2_tile = [&](int64_t j) {
+    const int64_t tile = tile_of(j);
+    const int64_t b = tile >> 4;
+    const int oy0 = kT2 * (int)((tile >> 2) & 3), ox0 = kT2 * (int)(tile & 3);
+    const bf16* A1 = sA1[j & 1];
+    floatx4 acc[2][2];   // the bias as the accumulators' start
+    int qy[2], qx[2];
+#pragma unroll
+    for (int mm = 0; mm < 2; ++mm) {
+      const int p = 16 * (2 * ph + mm) + i;
+      qy[mm] = p >> 3;
+      qx[mm] = p & 7;
+#pragma unroll
+      for (int tt = 0; tt < 2; ++tt)
+        acc[mm][tt] = floatx4{bias2[tt][0], bias2[tt][1], bias2[tt][2], bias2[tt][3]};
+    }
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+      const int ky = tap / 3, kx = tap % 3;
 #pragma unroll
       for (int mm = 0; mm < 2; ++mm) {
-        const int p = 16 * (2 * ph + mm) + i;
-        qy[mm] = p >> 3;
-        qx[mm] = p & 7;
+        const bf16x8 x = load8(A1 + ((2 * qy[mm] + ky) * kT1 + 2 * qx[mm] + kx) * kA1Px + 8 * g);
 #pragma unroll
-        for (int tt = 0; tt < 2; ++tt)
-          acc[mm][tt] = floatx4{bias2[tt][0], bias2[tt][1], bias2[tt][2], bias2[tt][3]};
-      }
-#pragma unroll
-      for (int tap = 0; tap < 9; ++tap) {
-        const int ky = tap / 3, kx = tap % 3;
-#pragma unroll
-        for (int mm = 0; mm < 2; ++mm) {
-          const bf16x8 x = load8(A1 + ((2 * qy[mm] + ky) * kT1 + 2 * qx[mm] + kx) * kA1Px + 8 * g);
-#pragma unroll
-          for (int tt = 0; tt < 2; ++tt) acc[mm][tt] = mfma(w2r[tap][tt], x, acc[mm][tt]);
-        }
-      }
-#pragma unroll
-      for (int mm = 0; mm < 2; ++mm) {
-        const int64_t pix2 = (b * 32 + oy0 + qy[mm]) * 32 + ox0 + qx[mm];
-        bf16* op = act2 + pix2 * 64 + 4 * g;
-        uint32_t bits = 0;
-#pragma unroll
-        for (int tt = 0; tt < 2; ++tt) {
-          float o[4];
-#pragma unroll
-          for (int r = 0; r < 4; ++r) o[r] = relu(acc[mm][tt][r]);
-          uint2 w;
-          w.x = pack2(o[0], o[1]);
-          w.y = pack2(o[2], o[3]);
-          *reinterpret_cast<uint2*>(op + 16 * (2 * chh + tt)) = w;
-          bits |= sign4(w) << (4 * tt);
-        }
-        // byte chh of the pixel's 16-bit sign word g: channel tiles 2 chh, 2 chh + 1
-        if (SAVE) reinterpret_cast<uint8_t*>(sign2)[2 * (4 * pix2 + g) + chh] = (uint8_t)bits;
+        for (int tt = 0; tt < 2; ++tt) acc[mm][tt] = mfma(w2r[tap][tt], x, acc[mm][tt]);
       }
     }
-    if (j + 1 < n_my) {
-      stage_patch((j + 1) & 1);
-      if (j + 2 < n_my) gather_window(src, tile_of(j + 2), woff, v);
+#pragma unroll
+    for (int mm = 0; mm < 2; ++mm) {
+      const int64_t pix2 = (b * 32 + oy0 + qy[mm]) * 32 + ox0 + qx[mm];
+      bf16* op = act2 + pix2 * 64 + 4 * g;
+      uint32_t bits = 0;
+#pragma unroll
+      for (int tt = 0; tt < 2; ++tt) {
+        float o[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) o[r] = relu(acc[mm][tt][r]);
+        uint2 w;
+        w.x = pack2(o[0], o[1]);
+        w.y = pack2(o[2], o[3]);
+        *reinterpret_cast<uint2*>(op + 16 * (2 * chh + tt)) = w;
+        bits |= sign4(w) << (4 * tt);
+      }
+      // byte chh of the pixel's 16-bit sign word g: channel tiles 2 chh, 2 chh + 1
+      if (SAVE) reinterpret_cast<uint8_t*>(sign2)[2 * (4 * pix2 + g) + chh] = (uint8_t)bits;
     }
+  };
+  // The steps between the first and the last hold both stages in one basic
+  // block, so the compiler interleaves conv1's VALU work with conv2's
+  // products; their gathers are clamped to the last tile (a step past it
+  // gathers and stages a window that nothing reads).
+  if (n_my > 0) {
+    conv1_tile(0);
+    if (n_my > 1) {
+      stage_patch(1);
+      gather_window(src, tile_of(min<int64_t>(2, n_my - 1)), woff, v);
+    }
+  }
+  __syncthreads();
+  for (int64_t j = 1; j < n_my; ++j) {
+    conv1_tile(j);
+    conv2_tile(j - 1);
+    stage_patch((j + 1) & 1);
+    gather_window(src, tile_of(min<int64_t>(j + 2, n_my - 1)), woff, v);
     __syncthreads();
   }
+  if (n_my > 0) conv2_tile(n_my - 1);
 }
 
 // ---------------------------------------------------------------------------
