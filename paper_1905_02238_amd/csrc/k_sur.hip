@@ -178,11 +178,15 @@ FSMI_DEV uint32_t pack2(float a, float b) {
   return __builtin_bit_cast(uint32_t, __builtin_convertvector((floatx2{a, b}), bf16x2));
 }
 
-// ReLU as an integer max on the bits (one instruction): a float with its sign
-// bit set, -0 included, is a negative int and becomes +0.
-FSMI_DEV float relu(float v) {
-  const int b = __builtin_bit_cast(int, v);
-  return __builtin_bit_cast(float, b > 0 ? b : 0);
+// ReLU of two floats, packed as BF16 (low half first): the two-lane
+// conversion, then a two-lane 16-bit integer max with 0 on the bits.  A BF16
+// value with its sign bit set, -0 included, is a negative int16 and becomes
+// +0; rounding commutes with the max, so this is the packed ReLU of the
+// floats.
+typedef short shortx2 __attribute__((ext_vector_type(2)));
+FSMI_DEV uint32_t pack2_relu(float a, float b) {
+  const shortx2 v = __builtin_bit_cast(shortx2, __builtin_convertvector((floatx2{a, b}), bf16x2));
+  return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(v, (shortx2){0, 0}));
 }
 
 // ReLU signs of a stored activation for the next layer's input-gradient pass:
@@ -364,8 +368,8 @@ __global__ __launch_bounds__(64 * kC3Waves, 2) void k_conv3_rows(int64_t n_units
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         uint2 w;
-        w.x = pack2(relu(acc[m][t][0]), relu(acc[m][t][1]));
-        w.y = pack2(relu(acc[m][t][2]), relu(acc[m][t][3]));
+        w.x = pack2_relu(acc[m][t][0], acc[m][t][1]);
+        w.y = pack2_relu(acc[m][t][2], acc[m][t][3]);
         *reinterpret_cast<uint2*>(op + 16 * t) = w;
         bits |= sign4(w) << (4 * t);
       }
@@ -484,8 +488,8 @@ __global__ __launch_bounds__(64 * kC4Waves, 2) void k_conv4_rows(int64_t n_units
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       uint2 w;
-      w.x = pack2(relu(acc[t][0]), relu(acc[t][1]));
-      w.y = pack2(relu(acc[t][2]), relu(acc[t][3]));
+      w.x = pack2_relu(acc[t][0], acc[t][1]);
+      w.y = pack2_relu(acc[t][2], acc[t][3]);
       *reinterpret_cast<uint2*>(op + 16 * t) = w;
       bits |= sign4(w) << (4 * t);
     }
@@ -587,8 +591,8 @@ __global__ __launch_bounds__(64 * kC5Waves, 2) void k_conv5_rows(int64_t n_poses
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       uint2 w;
-      w.x = pack2(relu(acc[t][0]), relu(acc[t][1]));
-      w.y = pack2(relu(acc[t][2]), relu(acc[t][3]));
+      w.x = pack2_relu(acc[t][0], acc[t][1]);
+      w.y = pack2_relu(acc[t][2], acc[t][3]);
       *reinterpret_cast<uint2*>(op + 16 * t) = w;
     }
   }
@@ -796,12 +800,9 @@ __global__ __launch_bounds__(256) void k_conv12_fwd(int64_t n_tiles, PatchSrc sr
       for (int t = 0; t < 2; ++t) {
         // D[n][p]: channels 16t + 4g + r of pixel p, the bias as the accumulator's start
         const floatx4 d = mfma16(w1[t], x, floatx4{bias1[t][0], bias1[t][1], bias1[t][2], bias1[t][3]});
-        float o[4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) o[r] = relu(d[r]);
         uint2 w;
-        w.x = inside ? pack2(o[0], o[1]) : 0u;
-        w.y = inside ? pack2(o[2], o[3]) : 0u;
+        w.x = inside ? pack2_relu(d[0], d[1]) : 0u;
+        w.y = inside ? pack2_relu(d[2], d[3]) : 0u;
         *reinterpret_cast<uint2*>(A1 + p * kA1Px + 16 * t + 4 * g) = w;
         if (owned) {
           *reinterpret_cast<uint2*>(act1 + pix1 * 32 + 16 * t + 4 * g) = w;
@@ -845,12 +846,9 @@ __global__ __launch_bounds__(256) void k_conv12_fwd(int64_t n_tiles, PatchSrc sr
       uint32_t bits = 0;
 #pragma unroll
       for (int tt = 0; tt < 2; ++tt) {
-        float o[4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) o[r] = relu(acc[mm][tt][r]);
         uint2 w;
-        w.x = pack2(o[0], o[1]);
-        w.y = pack2(o[2], o[3]);
+        w.x = pack2_relu(acc[mm][tt][0], acc[mm][tt][1]);
+        w.y = pack2_relu(acc[mm][tt][2], acc[mm][tt][3]);
         *reinterpret_cast<uint2*>(op + 16 * (2 * chh + tt)) = w;
         bits |= sign4(w) << (4 * tt);
       }
