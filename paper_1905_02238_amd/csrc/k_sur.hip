@@ -983,13 +983,28 @@ __global__ __launch_bounds__(256, WG1 ? 4 : 1) void k_conv_dgrad(int64_t nq, int
       const int mx0 = og.bx - kPatch / 2;
       const int my0 = og.by - kPatch / 2;
       const float fx = og.fx, fy = og.fy;
-      for (int e = tid; e < 9 * SROW; e += 256) {
-        const int r = e / SROW, c = e - r * SROW;
-        const int iy = 4 * a0 - 1 + r, ix = c - 1;
-        float v = 0.0f;
-        if ((unsigned)iy < (unsigned)kPatch && (unsigned)ix < (unsigned)kPatch)
-          v = src.bilinear(mx0 + ix, my0 + iy, fx, fy);
-        sPt[e] = (bf16)v;
+      // blocks mx0 - 1 .. mx0 + kPatch + 1 and my0 + 4 a0 - 1 .. my0 + 4 a0 + 8
+      // inside the map: no per-block checks
+      const int ry0 = my0 + 4 * a0 - 1;
+      if (mx0 >= 1 && ry0 >= 0 && mx0 + kPatch + 1 < src.X && ry0 + 9 < src.Y) {
+        const float* mp = src.map + ((mx0 - 1) + src.X * (int64_t)ry0);   // staged (0, 0)
+        const uint32_t X = (uint32_t)src.X;
+        for (int e = tid; e < 9 * SROW; e += 256) {
+          const int r = e / SROW, c = e - r * SROW;
+          const int iy = 4 * a0 - 1 + r, ix = c - 1;
+          const uint32_t o = (uint32_t)r * X + (uint32_t)c;
+          const float m = PatchSrc::lerp2(mp[o], mp[o + 1], mp[o + X], mp[o + X + 1], fx, fy);
+          sPt[e] = (bf16)((unsigned)iy < (unsigned)kPatch && (unsigned)ix < (unsigned)kPatch ? m : 0.0f);
+        }
+      } else {
+        for (int e = tid; e < 9 * SROW; e += 256) {
+          const int r = e / SROW, c = e - r * SROW;
+          const int iy = 4 * a0 - 1 + r, ix = c - 1;
+          float v = 0.0f;
+          if ((unsigned)iy < (unsigned)kPatch && (unsigned)ix < (unsigned)kPatch)
+            v = src.bilinear(mx0 + ix, my0 + iy, fx, fy);
+          sPt[e] = (bf16)v;
+        }
       }
     }
     __syncthreads();
