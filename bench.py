@@ -89,7 +89,7 @@ COUNTER_SOURCES = tuple(sorted(
     for dp, _, fs in os.walk(os.path.join(ROOT, "paper_1905_02238_amd", "csrc"))
     for f in fs if f.endswith((".hip", ".h")))) + ("paper_1905_02238_amd/build.py",)
 COUNTER_PROFILES = {
-    "sources_sha256": "7dd805b8390e8a923fc6e271d5ae671b0f1416a27842a0d1b95ebea1281484cc",
+    "sources_sha256": "561341428ea5ffbbb2f3acf388b2d1b3c95e16a253dc84ec21c8ab1be715dfe2",
     "paths": {
         "2d_exact": {"profile": "profiles/k_poses2d_exact_grid2048_4096x360.md",
                      "kernel_ms": 131.63, "valu_busy": 1.260, "mfma_busy": 0.0,

@@ -606,16 +606,15 @@ __global__ __launch_bounds__(64 * kC5Waves, 2) void k_conv5_rows(int64_t n_poses
 // from LDS, so conv1's activations never reach HBM.  The products are taken
 // transposed (weights as the A operand, activations as B), so a lane ends with
 // four consecutive channels of one pixel and stores them as one 8-byte word.
-// Persistent workgroups stage W2 in LDS once (laid out [tap][ci/8][co][8], so
-// the 16 lanes of a fragment read 16 consecutive 16-byte rows) and keep W1 in
-// registers; the next tile's patch gathers are issued before the current tile
-// is computed.  In training (SAVE) the kernel also stores conv1's activations
-// and both layers' ReLU sign words for the backward pass: a tile owns the
-// conv1 pixels of window rows and columns 1 .. 16 (conv1 rows 2 oy0 .. 2 oy0 +
-// 15; row 0 of the window belongs to the tile above), so each conv1 pixel is
-// stored once.  conv1's nine taps take one v_mfma_f32_16x16x16_bf16 per
-// channel tile (K = 16: lane group g holds taps 4 g .. 4 g + 3, read from the
-// patch window with one 2-byte LDS read each).
+// Persistent workgroups keep W1 in registers, and each wave the W2 fragments
+// of its 32 output channels; the tiles run as a two-stage pipeline over
+// double-buffered LDS (described at the loop).  In training (SAVE) the kernel
+// also stores conv1's activations and both layers' ReLU sign words for the
+// backward pass: a tile owns the conv1 pixels of window rows and columns
+// 1 .. 16 (conv1 rows 2 oy0 .. 2 oy0 + 15; row 0 of the window belongs to the
+// tile above), so each conv1 pixel is stored once.  conv1's nine taps take one
+// v_mfma_f32_16x16x16_bf16 per channel tile (K = 16, the slot layout given
+// where W1 is loaded).
 // ---------------------------------------------------------------------------
 constexpr int kT2 = 8;                 // conv2 tile edge (output pixels)
 constexpr int kT1 = 2 * kT2 + 1;       // 17: conv1 window edge
