@@ -779,17 +779,24 @@ __global__ __launch_bounds__(256) void k_conv12_fwd(int64_t n_tiles, PatchSrc sr
     const int oy0 = kT2 * (int)((tile >> 2) & 3), ox0 = kT2 * (int)(tile & 3);
     const bf16* P = sP[j & 1];
     bf16* A1 = sA1[j & 1];
+    // B operands of all five column tiles first (the window pixels of slots
+    // 4g .. 4g + 3 of each pixel): the compiler cannot tell the patch buffer
+    // from the conv1 buffer written below, so reads placed after a write
+    // would wait for it
+    bf16x4 xs[kC1];
+#pragma unroll
+    for (int u = 0; u < kC1; ++u) {
+      uint2 xw;
+      xw.x = *reinterpret_cast<const uint32_t*>(P + c1_base[u] + off0);
+      xw.y = *reinterpret_cast<const uint32_t*>(P + c1_base[u] + off1);
+      xs[u] = __builtin_bit_cast(bf16x4, xw);
+    }
 #pragma unroll
     for (int u = 0; u < kC1; ++u) {
       const int p = 16 * (wave + 4 * u) + i;
       const bool pv = c1_pr[u] >= 0;
       const int pr = pv ? c1_pr[u] : 0, pc = c1_pc[u];
-      const int base = c1_base[u];
-      // B operand: the window pixels of slots 4g .. 4g + 3 of pixel p
-      uint2 xw;
-      xw.x = *reinterpret_cast<const uint32_t*>(P + base + off0);
-      xw.y = *reinterpret_cast<const uint32_t*>(P + base + off1);
-      const bf16x4 x = __builtin_bit_cast(bf16x4, xw);
+      const bf16x4 x = xs[u];
       const int y1 = 2 * oy0 - 1 + pr, x1 = 2 * ox0 - 1 + pc;
       const bool inside = pv && y1 >= 0 && y1 < 64 && x1 >= 0 && x1 < 64;
       const bool owned = SAVE && pv && pr >= 1 && pc >= 1;   // implies inside
@@ -868,8 +875,8 @@ __global__ __launch_bounds__(256) void k_conv12_fwd(int64_t n_tiles, PatchSrc sr
   }
   __syncthreads();
   for (int64_t j = 1; j < n_my; ++j) {
+    conv2_tile(j - 1);   // its LDS reads ahead of conv1's writes (another buffer)
     conv1_tile(j);
-    conv2_tile(j - 1);
     stage_patch((j + 1) & 1);
     gather_window(src, tile_of(min<int64_t>(j + 2, n_my - 1)), woff, v);
     __syncthreads();
