@@ -89,35 +89,35 @@ COUNTER_SOURCES = tuple(sorted(
     for dp, _, fs in os.walk(os.path.join(ROOT, "paper_1905_02238_amd", "csrc"))
     for f in fs if f.endswith((".hip", ".h")))) + ("paper_1905_02238_amd/build.py",)
 COUNTER_PROFILES = {
-    "sources_sha256": "561341428ea5ffbbb2f3acf388b2d1b3c95e16a253dc84ec21c8ab1be715dfe2",
+    "sources_sha256": "db65ad05b44363419973fe03042c9ca0a256cad2d4af69d4b7eb7e667586b809",
     "paths": {
         "2d_exact": {"profile": "profiles/k_poses2d_exact_grid2048_4096x360.md",
-                     "kernel_ms": 131.63, "valu_busy": 1.260, "mfma_busy": 0.0,
-                     "fetch_write_GBps": 225, "bound": "alu",
-                     "frac": 0.76, "frac_of": "12-slot pair peak 3.28e12 pairs/s"},
+                     "kernel_ms": 130.94, "valu_busy": 1.259, "mfma_busy": 0.0,
+                     "fetch_write_GBps": 226, "bound": "alu",
+                     "frac": 0.77, "frac_of": "12-slot pair peak 3.28e12 pairs/s"},
         "2d_approx_delta9": {"profile": "profiles/k_poses2d_approx_delta9_grid2048_4096x360.md",
-                             "kernel_ms": 14.13, "valu_busy": 1.236, "mfma_busy": 0.0,
-                             "fetch_write_GBps": 2254, "bound": "alu",
-                             "frac": 0.29, "frac_of": "12-slot pair peak, tail evaluations"},
+                             "kernel_ms": 14.37, "valu_busy": 1.238, "mfma_busy": 0.0,
+                             "fetch_write_GBps": 2216, "bound": "alu",
+                             "frac": 0.28, "frac_of": "12-slot pair peak, tail evaluations"},
         "2d_uniform_h6": {"profile": "profiles/k_poses2d_uniform_h6_grid2048_4096x360.md",
-                          "kernel_ms": 7.04, "valu_busy": 0.962, "mfma_busy": 0.0,
-                          "fetch_write_GBps": 4540, "bound": "alu",
-                          "frac": 0.962, "frac_of": "VALU busy"},
+                          "kernel_ms": 7.08, "valu_busy": 0.958, "mfma_busy": 0.0,
+                          "fetch_write_GBps": 4512, "bound": "alu",
+                          "frac": 0.958, "frac_of": "VALU busy"},
         "2d_exact_lut": {"profile": "profiles/k_poses2d_exact_lut_grid2048_4096x360.md",
-                         "kernel_ms": 90.36, "valu_busy": 1.024, "mfma_busy": 0.0,
-                         "fetch_write_GBps": 338, "bound": "alu",
+                         "kernel_ms": 91.07, "valu_busy": 1.024, "mfma_busy": 0.0,
+                         "fetch_write_GBps": 336, "bound": "alu",
                          "frac": 1.024, "frac_of": "VALU busy"},
         "3d_exact": {"profile": "profiles/k_poses3d_voxels512_1024x16384.md",
-                     "kernel_ms": 45.43, "valu_busy": 0.762, "mfma_busy": 0.218,
+                     "kernel_ms": 45.41, "valu_busy": 0.762, "mfma_busy": 0.218,
                      "fetch_write_GBps": 3812, "bound": "alu", "frac": 0.762,
                      "frac_of": "VALU busy"},
         "3d_approx_delta6": {"profile": "profiles/k_poses3d_voxels512_1024x16384.md",
-                             "kernel_ms": 34.20, "valu_busy": 0.981, "mfma_busy": 0.0,
-                             "fetch_write_GBps": 5144, "bound": "alu", "frac": 0.981,
+                             "kernel_ms": 34.19, "valu_busy": 0.981, "mfma_busy": 0.0,
+                             "fetch_write_GBps": 5142, "bound": "alu", "frac": 0.981,
                              "frac_of": "VALU busy"},
         "3d_uniform_h4": {"profile": "profiles/k_poses3d_voxels512_1024x16384.md",
-                          "kernel_ms": 26.81, "valu_busy": 0.854, "mfma_busy": 0.0,
-                          "fetch_write_GBps": 6488, "bound": "alu", "frac": 0.854,
+                          "kernel_ms": 26.75, "valu_busy": 0.856, "mfma_busy": 0.0,
+                          "fetch_write_GBps": 6502, "bound": "alu", "frac": 0.856,
                           "frac_of": "VALU busy"},
         "uneven_100k_exact": {"profile": "profiles/k_eval_fused_uneven_100k.md",
                               "kernel_ms": 1.43, "valu_busy": 0.352, "mfma_busy": 0.347,
@@ -125,12 +125,12 @@ COUNTER_PROFILES = {
                               "frac_of": "FP32 matrix peak 7.86e13 MAC/s over the launch "
                                          "(0.50 ms of matrix work in 1.43 ms)"},
         "surrogate_forward": {"profile": "profiles/surrogate_forward_rank_65536.md",
-                              "kernel_ms": 1.225, "valu_busy": 0.377, "mfma_busy": 0.234,
-                              "fetch_write_GBps": 4721, "bound": "mfma", "frac": 0.197,
+                              "kernel_ms": 1.188, "valu_busy": 0.404, "mfma_busy": 0.251,
+                              "fetch_write_GBps": 4844, "bound": "mfma", "frac": 0.202,
                               "frac_of": "2.5 PFLOP/s BF16 dense (per batch of 8192; the five "
-                                         "kernels' MFMA busy 20-27 %, conv3 at 59 % of HBM peak)"},
+                                         "kernels' MFMA busy 21-27 %, conv3 at 61 % of HBM peak)"},
         "surrogate_training": {"profile": "profiles/surrogate_training_step_1024.md",
-                               "kernel_ms": 1.052, "valu_busy": 0.43, "mfma_busy": 0.13,
+                               "kernel_ms": 1.053, "valu_busy": 0.43, "mfma_busy": 0.13,
                                "fetch_write_GBps": None, "bound": "mfma", "frac": 0.086,
                                "frac_of": "2.5 PFLOP/s BF16 dense (per step of 1024)"},
     }}
