@@ -89,7 +89,7 @@ COUNTER_SOURCES = tuple(sorted(
     for dp, _, fs in os.walk(os.path.join(ROOT, "paper_1905_02238_amd", "csrc"))
     for f in fs if f.endswith((".hip", ".h")))) + ("paper_1905_02238_amd/build.py",)
 COUNTER_PROFILES = {
-    "sources_sha256": "db65ad05b44363419973fe03042c9ca0a256cad2d4af69d4b7eb7e667586b809",
+    "sources_sha256": "dc3a20860ed857605cce2bfd94490804961b27e7f889e6e2df62f19afbe150ba",
     "paths": {
         "2d_exact": {"profile": "profiles/k_poses2d_exact_grid2048_4096x360.md",
                      "kernel_ms": 130.94, "valu_busy": 1.259, "mfma_busy": 0.0,

@@ -739,10 +739,10 @@ __global__ __launch_bounds__(256) void k_conv12_fwd(int64_t n_tiles, PatchSrc sr
   // place in the window and their patch offset, the same for every tile.
   // Every wave takes five column tiles; pixels past the window's 289 (the
   // last tile and a half) read the patch at 0 and write padding slots.
-  constexpr int kC1 = kC1Tiles / 4;
-  int c1_pr[kC1], c1_pc[kC1], c1_base[kC1];
+  constexpr int kUPerWave = kC1Tiles / 4;   // conv1 column tiles per wave
+  int c1_pr[kUPerWave], c1_pc[kUPerWave], c1_base[kUPerWave];
 #pragma unroll
-  for (int u = 0; u < kC1; ++u) {
+  for (int u = 0; u < kUPerWave; ++u) {
     const int p = 16 * (wave + 4 * u) + i;
     const bool pv = p < kT1 * kT1;
     c1_pr[u] = pv ? p / kT1 : -1000;          // -1000: outside any grid
@@ -783,16 +783,16 @@ __global__ __launch_bounds__(256) void k_conv12_fwd(int64_t n_tiles, PatchSrc sr
     // 4g .. 4g + 3 of each pixel): the compiler cannot tell the patch buffer
     // from the conv1 buffer written below, so reads placed after a write
     // would wait for it
-    bf16x4 xs[kC1];
+    bf16x4 xs[kUPerWave];
 #pragma unroll
-    for (int u = 0; u < kC1; ++u) {
+    for (int u = 0; u < kUPerWave; ++u) {
       uint2 xw;
       xw.x = *reinterpret_cast<const uint32_t*>(P + c1_base[u] + off0);
       xw.y = *reinterpret_cast<const uint32_t*>(P + c1_base[u] + off1);
       xs[u] = __builtin_bit_cast(bf16x4, xw);
     }
 #pragma unroll
-    for (int u = 0; u < kC1; ++u) {
+    for (int u = 0; u < kUPerWave; ++u) {
       const int p = 16 * (wave + 4 * u) + i;
       const bool pv = c1_pr[u] >= 0;
       const int pr = pv ? c1_pr[u] : 0, pc = c1_pc[u];
