@@ -367,9 +367,8 @@ fsmi_status fsmi_eval_poses_noalloc(fsmi_ctx ctx, const fsmi_params* params, con
    units, patch pixel (iy, ix) is the bilinear interpolation of the blocks at
    (u - 64 + ix + 1/2, v - 64 + iy + 1/2), block k centred at k + 1/2: blocks
    bx - 64 + ix + {0, 1}, by - 64 + iy + {0, 1} with (bx, by) = (floor(floor(x)
-   / s), floor(floor(y) / s)) weighted by (u - bx, v - by) (bx and by held
-   within +-(2^31 - 2^10), where every block of the patch is outside any
-   map).  Five 3x3 convs,
+   / s), floor(floor(y) / s)) weighted by (u - bx, v - by), bx and by held
+   within +-(2^31 - 2^10).  Five 3x3 convs,
    stride 2, padding 1, ReLU (1-32-64-64-128-128 channels), global average pool,
    FC 128->256, ReLU, FC 256->1, 310465 parameters.  BF16 activations and
    weights on the matrix cores with FP32 accumulation, FP32 master weights and
