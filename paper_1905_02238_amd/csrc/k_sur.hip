@@ -754,9 +754,13 @@ __global__ __launch_bounds__(256) void k_conv12_fwd(int64_t n_tiles, PatchSrc sr
   // of tile j - 1 (conv1 buffer (j - 1) % 2), stores tile j + 1's patch
   // window, gathered during step j - 1, into patch buffer (j + 1) % 2 and
   // issues the gathers of tile j + 2; one barrier ends the step.  Each buffer
-  // is written in one step and read in the next only.
-  const int64_t n_my = (int64_t)blockIdx.x < n_tiles ? (n_tiles - 1 - blockIdx.x) / gridDim.x + 1 : 0;
-  auto tile_of = [&](int64_t j) { return (int64_t)blockIdx.x + j * (int64_t)gridDim.x; };
+  // is written in one step and read in the next only.  A workgroup's tiles
+  // are one contiguous run, so a pose's 16 tiles follow each other and their
+  // overlapping windows meet the same map blocks in the caches.
+  const int64_t per = (n_tiles + gridDim.x - 1) / gridDim.x;
+  const int64_t first = (int64_t)blockIdx.x * per;
+  const int64_t n_my = first < n_tiles ? min<int64_t>(per, n_tiles - first) : 0;
+  auto tile_of = [&](int64_t j) { return first + j; };
   float v[kPatchPer];
   auto stage_patch = [&](int buf) {
 #pragma unroll
