@@ -89,35 +89,35 @@ COUNTER_SOURCES = tuple(sorted(
     for dp, _, fs in os.walk(os.path.join(ROOT, "paper_1905_02238_amd", "csrc"))
     for f in fs if f.endswith((".hip", ".h")))) + ("paper_1905_02238_amd/build.py",)
 COUNTER_PROFILES = {
-    "sources_sha256": "dc3a20860ed857605cce2bfd94490804961b27e7f889e6e2df62f19afbe150ba",
+    "sources_sha256": "f63e9393e62773ec362159c05e0ca786c64b6af36795d99c685a0f39a242832d",
     "paths": {
         "2d_exact": {"profile": "profiles/k_poses2d_exact_grid2048_4096x360.md",
-                     "kernel_ms": 130.94, "valu_busy": 1.259, "mfma_busy": 0.0,
-                     "fetch_write_GBps": 226, "bound": "alu",
-                     "frac": 0.77, "frac_of": "12-slot pair peak 3.28e12 pairs/s"},
+                     "kernel_ms": 131.74, "valu_busy": 1.259, "mfma_busy": 0.0,
+                     "fetch_write_GBps": 225, "bound": "alu",
+                     "frac": 0.76, "frac_of": "12-slot pair peak 3.28e12 pairs/s"},
         "2d_approx_delta9": {"profile": "profiles/k_poses2d_approx_delta9_grid2048_4096x360.md",
-                             "kernel_ms": 14.37, "valu_busy": 1.238, "mfma_busy": 0.0,
-                             "fetch_write_GBps": 2216, "bound": "alu",
+                             "kernel_ms": 14.26, "valu_busy": 1.236, "mfma_busy": 0.0,
+                             "fetch_write_GBps": 2233, "bound": "alu",
                              "frac": 0.28, "frac_of": "12-slot pair peak, tail evaluations"},
         "2d_uniform_h6": {"profile": "profiles/k_poses2d_uniform_h6_grid2048_4096x360.md",
-                          "kernel_ms": 7.08, "valu_busy": 0.958, "mfma_busy": 0.0,
-                          "fetch_write_GBps": 4512, "bound": "alu",
-                          "frac": 0.958, "frac_of": "VALU busy"},
+                          "kernel_ms": 6.9, "valu_busy": 0.957, "mfma_busy": 0.0,
+                          "fetch_write_GBps": 4626, "bound": "alu",
+                          "frac": 0.957, "frac_of": "VALU busy"},
         "2d_exact_lut": {"profile": "profiles/k_poses2d_exact_lut_grid2048_4096x360.md",
-                         "kernel_ms": 91.07, "valu_busy": 1.024, "mfma_busy": 0.0,
-                         "fetch_write_GBps": 336, "bound": "alu",
+                         "kernel_ms": 90.73, "valu_busy": 1.024, "mfma_busy": 0.0,
+                         "fetch_write_GBps": 337, "bound": "alu",
                          "frac": 1.024, "frac_of": "VALU busy"},
         "3d_exact": {"profile": "profiles/k_poses3d_voxels512_1024x16384.md",
                      "kernel_ms": 45.41, "valu_busy": 0.762, "mfma_busy": 0.218,
-                     "fetch_write_GBps": 3812, "bound": "alu", "frac": 0.762,
+                     "fetch_write_GBps": 3813, "bound": "alu", "frac": 0.762,
                      "frac_of": "VALU busy"},
         "3d_approx_delta6": {"profile": "profiles/k_poses3d_voxels512_1024x16384.md",
                              "kernel_ms": 34.19, "valu_busy": 0.981, "mfma_busy": 0.0,
-                             "fetch_write_GBps": 5142, "bound": "alu", "frac": 0.981,
+                             "fetch_write_GBps": 5143, "bound": "alu", "frac": 0.981,
                              "frac_of": "VALU busy"},
         "3d_uniform_h4": {"profile": "profiles/k_poses3d_voxels512_1024x16384.md",
-                          "kernel_ms": 26.75, "valu_busy": 0.856, "mfma_busy": 0.0,
-                          "fetch_write_GBps": 6502, "bound": "alu", "frac": 0.856,
+                          "kernel_ms": 26.79, "valu_busy": 0.854, "mfma_busy": 0.0,
+                          "fetch_write_GBps": 6492, "bound": "alu", "frac": 0.854,
                           "frac_of": "VALU busy"},
         "uneven_100k_exact": {"profile": "profiles/k_eval_fused_uneven_100k.md",
                               "kernel_ms": 1.43, "valu_busy": 0.352, "mfma_busy": 0.347,
@@ -125,10 +125,10 @@ COUNTER_PROFILES = {
                               "frac_of": "FP32 matrix peak 7.86e13 MAC/s over the launch "
                                          "(0.50 ms of matrix work in 1.43 ms)"},
         "surrogate_forward": {"profile": "profiles/surrogate_forward_rank_65536.md",
-                              "kernel_ms": 1.188, "valu_busy": 0.404, "mfma_busy": 0.251,
-                              "fetch_write_GBps": 4844, "bound": "mfma", "frac": 0.202,
+                              "kernel_ms": 1.165, "valu_busy": 0.427, "mfma_busy": 0.267,
+                              "fetch_write_GBps": 4677, "bound": "mfma", "frac": 0.206,
                               "frac_of": "2.5 PFLOP/s BF16 dense (per batch of 8192; the five "
-                                         "kernels' MFMA busy 21-27 %, conv3 at 61 % of HBM peak)"},
+                                         "kernels' MFMA busy 20-27 %, conv3 at 58 % of HBM peak)"},
         "surrogate_training": {"profile": "profiles/surrogate_training_step_1024.md",
                                "kernel_ms": 1.053, "valu_busy": 0.43, "mfma_busy": 0.13,
                                "fetch_write_GBps": None, "bound": "mfma", "frac": 0.086,
