@@ -125,10 +125,10 @@ COUNTER_PROFILES = {
                               "frac_of": "FP32 matrix peak 7.86e13 MAC/s over the launch "
                                          "(0.50 ms of matrix work in 1.43 ms)"},
         "surrogate_forward": {"profile": "profiles/surrogate_forward_rank_65536.md",
-                              "kernel_ms": 1.165, "valu_busy": 0.427, "mfma_busy": 0.267,
-                              "fetch_write_GBps": 4677, "bound": "mfma", "frac": 0.206,
-                              "frac_of": "2.5 PFLOP/s BF16 dense (per batch of 8192; the five "
-                                         "kernels' MFMA busy 20-27 %, conv3 at 58 % of HBM peak)"},
+                              "kernel_ms": 2.29, "valu_busy": 0.444, "mfma_busy": 0.272,
+                              "fetch_write_GBps": 4828, "bound": "mfma", "frac": 0.209,
+                              "frac_of": "2.5 PFLOP/s BF16 dense (per batch of 16 384; the five "
+                                         "kernels' MFMA busy 22-31 %, conv3 at 60 % of HBM peak)"},
         "surrogate_training": {"profile": "profiles/surrogate_training_step_1024.md",
                                "kernel_ms": 1.053, "valu_busy": 0.43, "mfma_busy": 0.13,
                                "fetch_write_GBps": None, "bound": "mfma", "frac": 0.086,
@@ -148,6 +148,10 @@ def counter_profiles():
 SUR_FLOP_PER_POSE = 2 * (64 * 64 * 32 * 9 * 1 + 32 * 32 * 64 * 9 * 32 + 16 * 16 * 64 * 9 * 64
                          + 8 * 8 * 128 * 9 * 64 + 4 * 4 * 128 * 9 * 128 + 128 * 256 + 256)
 BF16_PEAK_TFLOPS = 2500.0
+# Poses per surrogate forward batch in the rank path (about 13 GiB of
+# activations and training buffers per net; 16 384 measured 3 % faster than
+# 8192, 6 % faster than 4096)
+SUR_BATCH = 16384
 # ALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T lane-ops/s
 # (one non-packed FP32 or FP64 VALU instruction per lane per clock).
 ALU_PEAK_TSLOT = 256 * 64 * 2.4e9 / 1e12
@@ -207,8 +211,9 @@ def parse():
                     help="with --profile-step: the FSMI variant of that one step (Approx "
                          "Delta = 9, Uniform H = 6)")
     ap.add_argument("--profile-surrogate", action="store_true",
-                    help="for kernel traces: surrogate forward over 65 536 candidates (3 times) "
-                         "and one fsmi_rank_poses, random-initialised weights, nothing else")
+                    help="for kernel traces: surrogate forward over 65 536 candidates (3 times, "
+                         "the rank path's batch and patch stride 2) and one fsmi_rank_poses, "
+                         "random-initialised weights, nothing else")
     ap.add_argument("--profile-train", action="store_true",
                     help="for kernel traces: 10 surrogate training steps (backward + Adam) of "
                          "1024 poses on a rooms map, random-initialised weights and labels, "
@@ -260,7 +265,7 @@ def main():
         calibration_copy(torch, dev)
         wl = W.grid_large(n_poses=65536, yaw="zero")
         g, p, bd = t(wl["grid"]), t(wl["poses"]), t(wl["beam_dir"])
-        net = F.Surrogate(ctx, seed=3, max_batch=8192)
+        net = F.Surrogate(ctx, seed=3, max_batch=SUR_BATCH, patch_stride=2)
         for _ in range(3):
             net.forward(g, p)
         ctx.fsmi_rank_poses(F.params(), net, g, p, bd, wl["sigma"], wl["R"], 656)
@@ -936,7 +941,7 @@ def surrogate_leg(ctx, F, W, t, timed, args):
     torch.cuda.synchronize()
     label_s = time.perf_counter() - t1
     def train_net(seed):
-        net = F.Surrogate(ctx, seed=seed, max_batch=8192, patch_stride=args.sur_stride)
+        net = F.Surrogate(ctx, seed=seed, max_batch=SUR_BATCH, patch_stride=args.sur_stride)
         net.fit_label_stats(torch.cat([d[2] for d in train]))
         rng = np.random.default_rng(seed)
         for it in range(args.sur_steps):
