@@ -113,6 +113,36 @@ def test_forward_and_gradients_match_fp64_reference(ctx, stride, batch):
         assert cos >= 0.98, (name, cos, rel)
 
 
+def test_forward_at_block_boundaries(ctx):
+    """Poses on and next to the edges of the s x s blocks (s = 3) and of the
+    cells: the patch origin (the block holding the pose's cell, an FP64 floor
+    division) and the fraction inside it must match the FP64 reference's, so
+    a pose a hair below a block edge samples the block before it at fraction
+    ~1 and a pose on the edge the next block at fraction 0."""
+    wl = W.grid_small()
+    grid = wl["grid"]
+    xs = [96.0, 96.0 - 1e-9, 95.0, 95.5, 97.0, 98.999999, 99.0, 100.25]
+    ys = [60.0, 60.0 - 1e-9, 61.0, 62.5, 63.0, 59.999999, 57.0, 120.75]
+    poses = np.array([[x, y, 1.0, 0.0] for x in xs for y in ys[:4]] +
+                     [[x, y, 1.0, 0.0] for x in xs[:4] for y in ys[4:]])
+    net = F.Surrogate(ctx, seed=11, max_batch=len(poses), patch_stride=3)
+    c2 = [o for name, o, _ in S.layout() if name == "c2"][0]
+    flat = net.params().double().cpu().numpy()
+    flat[c2] = 3.0
+    net.set_params(torch.from_numpy(flat.astype(np.float32)).cuda())
+    x = S.patches(grid, poses, stride=3)
+    y_bf, _ = S.forward(flat, x, q=_bf16)
+    pred = net.forward(dev(grid), dev(poses))
+    torch.cuda.synchronize()
+    y = np.exp(pred.double().cpu().numpy())
+    spread = 0.0
+    for sd in (1, 2):
+        rr = np.random.default_rng(sd)
+        y_p, _ = S.forward(flat, x, q=lambda a: _bf16(np.asarray(a) * (1 + rr.uniform(-1e-7, 1e-7, np.shape(a)))))
+        spread = max(spread, float(np.max(np.abs(y_p - y_bf))))
+    assert np.max(np.abs(y - y_bf)) <= 2.0 * spread + 1e-4 * np.max(np.abs(y_bf)) + 1e-6
+
+
 def test_gradients_do_not_depend_on_max_batch(ctx):
     """One batch gives bit-identical loss and gradients whether the network was
     sized for exactly that batch or for a larger one.  conv1's weight gradient
