@@ -199,7 +199,7 @@ def parse():
     ap.add_argument("--sur-steps", type=int, default=16000)
     ap.add_argument("--sur-stride", type=int, default=2, help="patch cell stride")
     ap.add_argument("--sur-candidates", type=int, default=65536)
-    ap.add_argument("--sur-seeds", type=int, nargs="*", default=[4, 5],
+    ap.add_argument("--sur-seeds", type=int, nargs="*", default=[4, 5, 6, 7, 8, 9, 10],
                     help="further training seeds of the surrogate's seed study")
     ap.add_argument("--sur-eval-maps", type=int, default=4,
                     help="held-out maps the ranking accuracy is averaged over (the timed one first)")
